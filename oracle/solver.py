@@ -1,0 +1,125 @@
+"""Oracle sparse-recovery solvers (test infrastructure only).
+
+Problem (Sec. IV-A, l1 relaxation, taken in its penalised LASSO form):
+
+    F(a) = 1/2 ||A a - y||_2^2 + lam ||a||_1,   lam = mu ||A^H y||_inf  (Sec. VII).
+
+FISTA follows Algorithm 1 (Sec. IV-A) with these readings of its garbles:
+  * step: the printed "2 s beta(.)" with s = 1/sigma_max^2 is the step for
+    ||.||^2; on the 1/2 ||.||^2 objective the step is 1/L, L = sigma_max^2;
+  * threshold lam / L;
+  * momentum is applied to the newest iterate (Beck & Teboulle 2009):
+    gamma_{k+1} = a_k + ((t_k - 1) / t_{k+1}) (a_k - a_{k-1});
+  * the complex soft threshold is z max(0, 1 - alpha/|z|) (sgn z = z/|z|, 0 at 0).
+ISTA is the same iteration with gamma_{k+1} = a_k.
+
+With this reading a = 0 is optimal exactly when mu >= 1, matching the lambda rule.
+
+The Lipschitz constant L = sigma_max(A)^2 (Sec. IV-C) is computed exactly with
+``numpy.linalg.eigvalsh`` on a dense A, or by power iteration on A^H A (the
+paper uses ARPACK; it warns that under-estimates make FISTA diverge).
+"""
+import math
+
+import numpy as np
+
+
+def soft(z, alpha):
+    """Complex soft threshold z * max(0, 1 - alpha/|z|), with soft(0) = 0."""
+    z = np.asarray(z, dtype=np.complex128)
+    mag = np.abs(z)
+    scale = np.where(mag > alpha, 1.0 - alpha / np.where(mag > 0, mag, 1.0), 0.0)
+    return z * scale
+
+
+def objective(A, y, a, lam):
+    r = A(a) - y
+    return 0.5 * float(np.vdot(r, r).real) + lam * float(np.abs(a).sum())
+
+
+def lambda_rule(AH, y, mu):
+    """lam = mu * ||A^H y||_inf (Sec. VII)."""
+    return mu * float(np.abs(AH(y)).max())
+
+
+def momentum_weights(iters, t1=1.0):
+    """t_k and beta_k = (t_k - 1)/t_{k+1} for k = 1..iters (t_1 = 1)."""
+    t = [t1]
+    for _ in range(iters):
+        t.append((1.0 + math.sqrt(1.0 + 4.0 * t[-1] * t[-1])) / 2.0)
+    beta = [(t[i] - 1.0) / t[i + 1] for i in range(iters)]
+    return t, beta
+
+
+def fista(A, AH, y, lam, L, iters, a0=None, accel=True, a_ref=None, state=None):
+    """Run ``iters`` FISTA (or ISTA) iterations in complex128.
+
+    A, AH    callables for x -> A x and y -> A^H y
+    a0       start value (zeros if None)
+    state    optional dict {"a", "gamma", "t", "k"} to resume; updated on return
+    Returns (a_K, stats) where stats holds, per iteration k, the objective at
+    gamma_k, ||A gamma_k - y||, ||a_k - a_{k-1}|| / ||a_k|| and, if a_ref is
+    given, ||a_k - a_ref|| / ||a_ref||.
+    """
+    y = np.asarray(y, dtype=np.complex128)
+    if state is not None and state.get("k", 0) > 0:
+        a = np.array(state["a"], dtype=np.complex128)
+        gamma = np.array(state["gamma"], dtype=np.complex128)
+        t = float(state["t"])
+        k0 = int(state["k"])
+    else:
+        shape = AH(y).shape if a0 is None else np.shape(a0)
+        a = np.zeros(shape, np.complex128) if a0 is None else np.array(a0, np.complex128)
+        gamma = a.copy()
+        t, k0 = 1.0, 0
+    ref_norm = None if a_ref is None else float(np.linalg.norm(a_ref))
+    stats = {"obj": [], "res": [], "rel_change": [], "err_ref": []}
+    for _ in range(iters):
+        r = A(gamma) - y
+        res = float(np.linalg.norm(r))
+        stats["obj"].append(0.5 * res * res + lam * float(np.abs(gamma).sum()))
+        grad = AH(r)
+        a_new = soft(gamma - grad / L, lam / L)
+        t_new = (1.0 + math.sqrt(1.0 + 4.0 * t * t)) / 2.0
+        if accel:
+            gamma = a_new + ((t - 1.0) / t_new) * (a_new - a)
+        else:
+            gamma = a_new
+        stats["res"].append(res)
+        nrm = float(np.linalg.norm(a_new))
+        stats["rel_change"].append(float(np.linalg.norm(a_new - a)) / nrm if nrm > 0 else 0.0)
+        if a_ref is not None:
+            stats["err_ref"].append(float(np.linalg.norm(a_new - a_ref)) / ref_norm)
+        a, t = a_new, t_new
+    if state is not None:
+        state.update({"a": a.copy(), "gamma": gamma.copy(), "t": t, "k": k0 + iters})
+    return a, stats
+
+
+def lipschitz_dense(Amat):
+    """L = lambda_max(A^H A) by a dense Hermitian eigensolver.
+
+    A^H A and A A^H share their non-zero eigenvalues, so the smaller Gram
+    matrix is decomposed.
+    """
+    G = Amat.conj().T @ Amat if Amat.shape[1] <= Amat.shape[0] else Amat @ Amat.conj().T
+    return float(np.linalg.eigvalsh(G)[-1])
+
+
+def power_iteration(A, AH, v0, max_iters=200, rtol=1e-6):
+    """Rayleigh quotient rho = ||A v||^2/||v||^2 of A^H A by power iteration.
+
+    Returns (rho, iterations used).  rho never exceeds lambda_max(A^H A).
+    """
+    v = np.array(v0, dtype=np.complex128)
+    v /= np.linalg.norm(v)
+    rho_old = 0.0
+    for it in range(1, max_iters + 1):
+        Av = A(v)
+        rho = float(np.vdot(Av, Av).real)
+        w = AH(Av)
+        v = w / np.linalg.norm(w)
+        if rho_old > 0 and abs(rho - rho_old) <= rtol * rho:
+            return rho, it
+        rho_old = rho
+    return rho, max_iters

@@ -1,0 +1,109 @@
+"""Synthetic workloads: geometry parameters and seeded input generators.
+
+This module holds numbers and random draws only -- none of the method's
+arithmetic (no pulse spectrum, no delays, no operator).  Both the HIP path and
+the FP64 oracle take their inputs from here.
+
+Geometry parameters follow the simulation setup of the paper (Sec. VII and
+its Table III) where it gives them, with these choices where it does not:
+  * c = 5900 m/s, f_s = 40 MHz, f_c = 4 MHz, -6 dB fractional bandwidth 0.5;
+  * lateral pitch 0.5 mm; depth pitch c / (2 f_s) = 73.75 um (whole samples);
+  * first voxel at 29.6 mm depth (the imaging region of Sec. VII);
+  * t0 = NaN asks for the window that centres the aperture's delay span;
+  * pulse band: bins within 40 dB of the spectral peak.
+
+Workloads (one per measured configuration):
+  bscan32   B-scan, 32 positions, 32 x 128 voxels, N_t = 256, 32 shared bins
+  cscan32   C-scan, 32 x 32 positions, 32 x 32 x 256 voxels, N_t = 512,
+            64 bins drawn per position, full aperture
+  cscan64   C-scan, 64 x 64 positions, 64 x 64 x 512 voxels, N_t = 1024,
+            128 shared bins, aperture window of +-16 voxels
+Scenes are distinct on-grid point scatterers; noise is circular complex
+Gaussian scaled to a target SNR over all measured values (the scaling needs
+||A x||, which the caller computes with its own operator).
+"""
+import math
+
+import numpy as np
+
+C_SOUND = 5900.0
+FS = 40e6
+FC = 4e6
+FRAC_BW = 0.5
+BAND_DB = 40.0
+PITCH = 0.5e-3
+DZ = 73.75e-6          # c / (2 f_s) for the values above
+Z_START = 29.6e-3
+
+DTYPE_F32 = 0
+DTYPE_BF16 = 1
+
+
+def geometry(nx, ny, nz, nt, win_x=-1, win_y=-1, t0=float("nan"), **over):
+    """Geometry dict (SI units) with the common physical constants."""
+    g = dict(nx=nx, ny=ny, nz=nz, nt=nt, dx=PITCH, dy=PITCH, dz=DZ,
+             z_start=Z_START, t0=t0, c=C_SOUND, fs=FS, fc=FC,
+             frac_bw=FRAC_BW, band_db=BAND_DB, win_x=win_x, win_y=win_y)
+    g.update(over)
+    return g
+
+
+WORKLOADS = {
+    "bscan32": dict(
+        geom=geometry(32, 1, 128, 256), m=32, per_position=False, seed=1001,
+        n_scat=3, amp=(1.0, 1.0), snr_db=20.0, iters=200, mu=0.1, back_wall=None),
+    "cscan32": dict(
+        geom=geometry(32, 32, 256, 512), m=64, per_position=True, seed=1002,
+        n_scat=20, amp=(0.5, 1.0), snr_db=10.0, iters=100, mu=0.1, back_wall=240),
+    "cscan64": dict(
+        geom=geometry(64, 64, 512, 1024, win_x=16, win_y=16), m=128,
+        per_position=False, seed=1003, n_scat=50, amp=(0.5, 1.0), snr_db=15.0,
+        iters=100, mu=0.1, back_wall=None),
+}
+
+
+def workload(name):
+    w = dict(WORKLOADS[name])
+    w["geom"] = dict(w["geom"])
+    return w
+
+
+def subvolume(g, nx, ny, nz):
+    """Smaller grid with the same physics; t0 is pinned by the caller."""
+    s = dict(g)
+    s.update(nx=nx, ny=ny, nz=nz)
+    return s
+
+
+def scene(g, n_scat, amp=(1.0, 1.0), seed=0, back_wall=None, phase=0.0,
+          max_depth=None):
+    """Sparse reflectivity [ny, nx, nz] complex128 with distinct voxels.
+
+    Scatterer depths are drawn below ``max_depth`` (default: all depths, or
+    24 samples above a back wall).  A back wall sets every lateral voxel at
+    depth index ``back_wall`` to amplitude 1.
+    """
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = g["nx"], g["ny"], g["nz"]
+    if max_depth is None:
+        max_depth = nz if back_wall is None else back_wall - 8
+    x = np.zeros((ny, nx, nz), dtype=np.complex128)
+    flat = rng.choice(ny * nx * max_depth, size=n_scat, replace=False)
+    iy, rem = np.divmod(flat, nx * max_depth)
+    ix, iz = np.divmod(rem, max_depth)
+    a = rng.uniform(amp[0], amp[1], size=n_scat) if amp[0] != amp[1] else np.full(n_scat, amp[0])
+    x[iy, ix, iz] = a * np.exp(1j * phase)
+    if back_wall is not None:
+        x[:, :, back_wall] = 1.0
+    return x
+
+
+def cn(shape, seed):
+    """Circular complex Gaussian CN(0, 1) array (complex128)."""
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / math.sqrt(2.0)
+
+
+def noise_sigma(signal_energy, count, snr_db):
+    """Noise std so that E||n||^2 = ||A x||^2 / 10^(snr/10) over ``count`` values."""
+    return math.sqrt(signal_energy / (count * 10.0 ** (snr_db / 10.0)))

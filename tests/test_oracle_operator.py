@@ -1,0 +1,170 @@
+"""Pins of the oracle operator A / A^H (CPU only).
+
+Each check is independent of the closed form the oracle evaluates:
+adjointness, the DFT of the time-domain pulse-echo model, the DFT-matrix
+special case, the SAFT special case, the Frobenius count, shift invariance and
+the 2-level Toeplitz index map of the paper's worked example.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import geometry as G
+from oracle import operator as O
+from oracle import select as S
+from oracle import timedomain as T
+from paper_2012_04534_amd import workloads as W
+
+
+def tiny(nx=6, ny=5, nz=24, nt=64, win=-1):
+    return W.geometry(nx, ny, nz, nt, win_x=win, win_y=win)
+
+
+def tiny_cases():
+    out = []
+    for win in (-1, 2):
+        for per_pos in (False, True):
+            g = tiny(win=win)
+            bins = S.select_freqs(g, 6, per_pos, 11 + win)
+            out.append((g, bins))
+    g2 = W.geometry(9, 1, 20, 64, win_x=3)      # B-scan, windowed
+    out.append((g2, S.select_freqs(g2, 5, True, 5)))
+    return out
+
+
+@pytest.mark.parametrize("case", range(5))
+def test_adjointness_dense_and_direct(case):
+    """P1: <A x, y> = <x, A^H y> to 1e-12 (dense and direct-sum modes)."""
+    g, bins = tiny_cases()[case]
+    m = bins.shape[-1]
+    x = W.cn((g["ny"], g["nx"], g["nz"]), 1)
+    y = W.cn((g["ny"], g["nx"], m), 2)
+    Ax = O.apply_A(g, bins, x)
+    AHy = O.apply_AH(g, bins, y)
+    lhs = np.vdot(y, Ax)
+    rhs = np.vdot(AHy, x)
+    assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(Ax) * np.linalg.norm(y)
+    A = O.dense_A(g, bins)
+    np.testing.assert_allclose(A @ x.reshape(-1), Ax.reshape(-1), rtol=0, atol=1e-12 * np.abs(Ax).max())
+    np.testing.assert_allclose(A.conj().T @ y.reshape(-1), AHy.reshape(-1), rtol=0,
+                               atol=1e-12 * np.abs(AHy).max())
+
+
+@pytest.mark.parametrize("win", [-1, 2])
+def test_full_spectrum_equals_dft_of_time_domain_model(win):
+    """P3 (check c): with every non-negative bin selected, A x at each position
+    equals numpy.fft of the periodised sampled pulse-echo A-scan."""
+    g = tiny(nx=5, ny=4, nz=16, nt=64, win=win)
+    x = W.scene(g, 6, amp=(0.5, 1.0), seed=3, phase=0.7)
+    x[1, 2, 5] = 0.3 - 0.8j
+    bins = np.arange(0, g["nt"] // 2 + 1)
+    y = O.apply_A(g, bins, x)
+    b = T.ascans(g, x)
+    ref = np.fft.fft(b, axis=-1)[..., : g["nt"] // 2 + 1]
+    assert np.abs(y - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def test_single_ascan_reduces_to_dft_columns():
+    """P4: one A-scan, aperture 0, delays on whole samples -> A's columns are
+    the selected rows of the DFT matrix times H_k."""
+    g = W.geometry(1, 1, 32, 64, win_x=0, win_y=0)
+    # start the window at the first voxel's delay: tau_j - t0 = j / fs
+    g["t0"] = float(G.tau(g, 0.0, 0.0, G.depth(g, 0)))
+    bins = np.array([3, 4, 6, 9])
+    A = O.dense_A(g, bins)
+    n = np.arange(g["nz"])
+    F = np.fft.fft(np.eye(g["nt"]))[bins][:, : g["nz"]]
+    H = G.pulse_spectrum(g, bins)
+    np.testing.assert_allclose(A, H[:, None] * F, rtol=0, atol=1e-13 * H.max())
+    assert n.size == g["nz"]
+
+
+def test_saft_special_case():
+    """P5 (Remark on SAFT): unit spectrum, all N_t bins, whole-sample delays ->
+    A^H of the DFT of an A-scan is N_t times the delay-and-sum image."""
+    g = W.geometry(1, 1, 40, 64, win_x=0, win_y=0)
+    g["t0"] = float(G.tau(g, 0.0, 0.0, G.depth(g, 0))) - 5 / g["fs"]
+    bins = np.arange(g["nt"])
+    rng = np.random.default_rng(0)
+    b = rng.standard_normal(g["nt"]) + 1j * rng.standard_normal(g["nt"])
+    y = np.fft.fft(b)[None, None, :]
+    img = O.apply_AH(g, bins, y, unit_spectrum=True)[0, 0]
+    # voxel j sits at sample n = 5 + j of the record
+    np.testing.assert_allclose(img, g["nt"] * b[5:5 + g["nz"]], rtol=0, atol=1e-10)
+
+
+@pytest.mark.parametrize("case", range(5))
+def test_frobenius_count_and_norm_bounds(case):
+    """P6: ||A||_F^2 equals the structural count; L lies in [||A||_F^2/N, ||A||_F^2]."""
+    g, bins = tiny_cases()[case]
+    A = O.dense_A(g, bins)
+    fro = float(np.sum(np.abs(A) ** 2))
+    assert fro == pytest.approx(O.frobenius_sq(g, bins), rel=1e-12)
+    L = float(np.linalg.eigvalsh(A.conj().T @ A)[-1])
+    N = A.shape[1]
+    assert fro / N <= L * (1 + 1e-12) and L <= fro * (1 + 1e-12)
+
+
+def test_shift_invariance():
+    """P11 (Theorem on block 2-level Toeplitz structure): translating an
+    interior scene laterally translates A x, for shared bins."""
+    g = tiny(nx=12, ny=10, nz=16, nt=64, win=2)
+    bins = S.select_freqs(g, 6, False, 4)
+    x = np.zeros((g["ny"], g["nx"], g["nz"]), complex)
+    x[4, 4, 3] = 1.0
+    x[5, 3, 9] = 0.5j
+    xs = np.roll(np.roll(x, 2, axis=0), 3, axis=1)
+    y = O.apply_A(g, bins, x)
+    ys = O.apply_A(g, bins, xs)
+    np.testing.assert_allclose(ys[2:, 3:], y[:-2, :-3], rtol=0, atol=1e-12 * np.abs(y).max())
+
+
+def test_two_level_toeplitz_index_map(golden):
+    """P11: on a 2 x 2 scan, A (one bin, one depth) equals the paper's worked
+    2-level Toeplitz example with t indexed by the lateral offset
+    (outer level y, inner level x; offset 0 -> 1, +1 -> 2, -1 -> 3)."""
+    g = W.geometry(2, 2, 1, 64)
+    A = O.dense_A(g, np.array([5]))
+    assert A.shape == (4, 4)
+    idx = {0: 1, 1: 2, -1: 3}
+    t = {}
+    for p in range(4):
+        for v in range(4):
+            key = (idx[p // 2 - v // 2], idx[p % 2 - v % 2])
+            t.setdefault(key, A[p, v])
+    rows = [r.split() for r in golden("toeplitz_2level_example.txt")]
+    T2 = np.array([[t[tuple(int(s) for s in e.split(","))] for e in r] for r in rows])
+    np.testing.assert_array_equal(A, T2)
+    # lateral offsets 0 and +-1 give distinct generators
+    assert abs(t[(1, 1)] - t[(1, 2)]) > 1e-3 * abs(t[(1, 1)])
+
+
+def test_sampled_rows_and_columns_match_dense():
+    """apply_A_at / apply_AH_at (window-restricted sums used for full-size
+    sampling) agree with the dense matrix."""
+    g = tiny(nx=7, ny=6, nz=12, nt=64, win=2)
+    bins = S.select_freqs(g, 5, True, 9)
+    x = W.cn((g["ny"], g["nx"], g["nz"]), 5)
+    y = W.cn((g["ny"], g["nx"], 5), 6)
+    Ax = O.apply_A(g, bins, x)
+    AHy = O.apply_AH(g, bins, y)
+    for (py, px) in [(0, 0), (3, 4), (5, 6)]:
+        np.testing.assert_allclose(O.apply_A_at(g, bins, x, py, px, chunk=50), Ax[py, px],
+                                   rtol=0, atol=1e-12 * np.abs(Ax).max())
+        np.testing.assert_allclose(O.apply_AH_at(g, bins, y, py, px), AHy[py, px],
+                                   rtol=0, atol=1e-12 * np.abs(AHy).max())
+
+
+def test_phase_sign_single_scatterer():
+    """P2: a lone scatterer deeper in the record has a later echo, i.e. the
+    phase decreases with frequency at rate -2 pi (tau - t0)."""
+    g = W.geometry(1, 1, 64, 256)
+    bins = np.array([20, 21])
+    x = np.zeros((1, 1, 64), complex)
+    x[0, 0, 40] = 1.0
+    y = O.apply_A(g, bins, x)[0, 0]
+    ratio = (y[1] / G.pulse_spectrum(g, 21)) / (y[0] / G.pulse_spectrum(g, 20))
+    delay = G.tau(g, 0, 0, G.depth(g, 40)) - G.t0(g)
+    want = np.exp(-2j * math.pi * (g["fs"] / g["nt"]) * delay)
+    assert abs(ratio - want) < 1e-12

@@ -1,0 +1,159 @@
+"""Pins of the oracle solvers (CPU only): Lipschitz constant, lambda rule,
+ISTA monotonicity, the FISTA convergence bound, optimality (KKT) conditions,
+support recovery, the single-atom LASSO closed form, resume and divergence."""
+import numpy as np
+import pytest
+
+from oracle import operator as O
+from oracle import select as S
+from oracle import solver as V
+from paper_2012_04534_amd import workloads as W
+
+
+def problem(nx=10, ny=1, nz=32, nt=128, m=10, per_pos=False, win=-1, n_scat=3,
+            seed=1, snr_db=None):
+    g = W.geometry(nx, ny, nz, nt, win_x=win, win_y=win)
+    bins = S.select_freqs(g, m, per_pos, 100 + seed)
+    Amat = O.dense_A(g, bins)
+    x = W.scene(g, n_scat, amp=(0.5, 1.0), seed=seed).reshape(-1)
+    y = Amat @ x
+    if snr_db is not None:
+        sig = W.noise_sigma(float(np.vdot(y, y).real), y.size, snr_db)
+        y = y + sig * W.cn(y.shape, seed + 7).reshape(-1)
+    A = lambda v: Amat @ v
+    AH = lambda v: Amat.conj().T @ v
+    return g, bins, Amat, A, AH, x, y
+
+
+def test_power_iteration_vs_eigvalsh():
+    """P7: the Rayleigh quotient never exceeds lambda_max and converges to it."""
+    _, _, Amat, A, AH, _, _ = problem(nx=8, ny=6, nz=12, nt=64, m=5, win=2, per_pos=True)
+    L = V.lipschitz_dense(Amat)
+    s = np.linalg.svd(Amat, compute_uv=False)[0]
+    assert L == pytest.approx(s * s, rel=1e-10)
+    rho, _ = V.power_iteration(A, AH, W.cn(Amat.shape[1], 3), max_iters=2000, rtol=1e-13)
+    assert rho <= L * (1 + 1e-12)
+    assert rho >= L * (1 - 1e-4)
+
+
+def test_mu_at_least_one_gives_zero():
+    """P8: lam = mu ||A^H y||_inf with mu >= 1 makes the first iterate exactly 0."""
+    _, _, Amat, A, AH, _, y = problem()
+    L = V.lipschitz_dense(Amat)
+    for mu in (1.0, 1.5):
+        lam = V.lambda_rule(AH, y, mu)
+        a, _ = V.fista(A, AH, y, lam, L, 5)
+        assert np.count_nonzero(a) == 0
+
+
+def test_unitary_operator_one_step():
+    """With A = I the LASSO optimum is soft(y, lam); FISTA with L = 1 reaches
+    it in one step (checks the 1/L step and lam/L threshold readings)."""
+    rng = np.random.default_rng(0)
+    y = rng.standard_normal(50) + 1j * rng.standard_normal(50)
+    I = lambda v: v
+    a, _ = V.fista(I, I, y, 0.8, 1.0, 1)
+    np.testing.assert_array_equal(a, V.soft(y, 0.8))
+    a3, _ = V.fista(I, I, y, 0.8, 1.0, 3)
+    np.testing.assert_allclose(a3, V.soft(y, 0.8), atol=1e-15)
+
+
+def test_soft_threshold_definition():
+    z = np.array([0.0, 3 + 4j, 0.3j, -2.0])
+    out = V.soft(z, 1.0)
+    np.testing.assert_allclose(out, [0.0, (3 + 4j) * 0.8, 0.0, -1.0])
+
+
+def test_ista_monotone_and_fista_bound():
+    """P9: ISTA never increases F; FISTA obeys F(a_k) - F* <= 2 L ||a0 - a*||^2 / (k+1)^2."""
+    _, _, Amat, A, AH, _, y = problem(nx=12, nz=32, m=8, n_scat=3, snr_db=30.0)
+    L = V.lipschitz_dense(Amat)
+    lam = V.lambda_rule(AH, y, 0.1)
+    a_star, _ = V.fista(A, AH, y, lam, L, 6000)
+    F_star = V.objective(A, y, a_star, lam)
+    a, st = V.fista(A, AH, y, lam, L, 300, accel=False)
+    F_ista = st["obj"]                 # objective at gamma_k = a_{k-1}
+    assert all(F_ista[i + 1] <= F_ista[i] * (1 + 1e-13) for i in range(len(F_ista) - 1))
+    bound_c = 2 * L * float(np.vdot(a_star, a_star).real)
+    for k in (1, 2, 5, 10, 20, 50, 100, 200):
+        ak, _ = V.fista(A, AH, y, lam, L, k)
+        gap = V.objective(A, y, ak, lam) - F_star
+        assert gap <= bound_c / (k + 1) ** 2 + 1e-12 * F_star
+
+
+def test_kkt_certificate_at_convergence():
+    """P10: near the optimum (20000 iterations, 1e-5 lam slack), A^H (y - A a) = lam a/|a| on the support and has
+    modulus <= lam elsewhere."""
+    _, _, Amat, A, AH, _, y = problem(nx=10, nz=24, m=10, n_scat=2, snr_db=40.0)
+    L = V.lipschitz_dense(Amat)
+    lam = V.lambda_rule(AH, y, 0.3)
+    a, _ = V.fista(A, AH, y, lam, L, 20000)
+    c = AH(y - A(a))
+    on = np.abs(a) > 0
+    assert on.any()
+    np.testing.assert_allclose(c[on], lam * a[on] / np.abs(a[on]), rtol=0, atol=1e-5 * lam)
+    assert np.all(np.abs(c[~on]) <= lam * (1 + 1e-5))
+
+
+def test_single_atom_lasso_closed_form():
+    """P12: one isolated scatterer, no noise -> the solution is a single atom
+    with modulus |a| - lam / ||A_v||^2 and the scatterer's phase."""
+    g, bins, Amat, A, AH, _, _ = problem(nx=10, nz=24, m=10, n_scat=1)
+    x = np.zeros(Amat.shape[1], complex)
+    v = 5 * g["nz"] + 12
+    x[v] = 0.8 * np.exp(0.4j)
+    y = Amat @ x
+    L = V.lipschitz_dense(Amat)
+    lam = V.lambda_rule(AH, y, 0.5)
+    a, _ = V.fista(A, AH, y, lam, L, 20000)
+    nv = float(np.vdot(Amat[:, v], Amat[:, v]).real)
+    want = (0.8 - lam / nv) * np.exp(0.4j)
+    assert abs(a[v] - want) < 1e-8
+    others = np.delete(a, v)
+    assert np.abs(others).max() < 1e-8
+
+
+def test_support_recovery_bscan_workload():
+    """P12 / check (d): on the 32-position B-scan workload (32 shared bins,
+    3 unit scatterers, 20 dB SNR, mu = 0.1, 200 FISTA iterations) the three
+    largest |a| sit exactly on the true support, for several scene seeds."""
+    w = W.workload("bscan32")
+    g = w["geom"]
+    bins = S.select_freqs(g, w["m"], False, w["seed"])
+    Amat = O.dense_A(g, bins)
+    A = lambda v: Amat @ v
+    AH = lambda v: Amat.conj().T @ v
+    L = V.lipschitz_dense(Amat)
+    for seed in range(3):
+        x = W.scene(g, 3, seed=seed).reshape(-1)
+        y = A(x)
+        sig = W.noise_sigma(float(np.vdot(y, y).real), y.size, w["snr_db"])
+        y = y + sig * W.cn(y.shape, seed + 100).reshape(-1)
+        lam = V.lambda_rule(AH, y, w["mu"])
+        a, _ = V.fista(A, AH, y, lam, L, w["iters"])
+        top = set(np.argsort(np.abs(a))[-3:])
+        assert top == set(np.flatnonzero(x))
+
+
+def test_resume_equals_uninterrupted():
+    """50 + 50 iterations with saved state equal 100 iterations exactly."""
+    _, _, Amat, A, AH, _, y = problem(snr_db=20.0)
+    L = V.lipschitz_dense(Amat)
+    lam = V.lambda_rule(AH, y, 0.1)
+    a100, _ = V.fista(A, AH, y, lam, L, 100)
+    st = {}
+    V.fista(A, AH, y, lam, L, 50, state=st)
+    a_res, _ = V.fista(A, AH, y, lam, L, 50, state=st)
+    np.testing.assert_array_equal(a_res, a100)
+    assert st["k"] == 100
+
+
+def test_underestimated_lipschitz_diverges():
+    """With L/4 the step exceeds 2/L and the iterates blow up (Sec. IV-C warning)."""
+    _, _, Amat, A, AH, _, y = problem(snr_db=20.0)
+    L = V.lipschitz_dense(Amat)
+    lam = V.lambda_rule(AH, y, 0.1)
+    with np.errstate(all="ignore"):
+        _, st = V.fista(A, AH, y, lam, L / 4, 200)
+    res = np.array(st["res"])
+    assert not np.all(np.isfinite(res)) or res[-1] > 1e6 * res[0]
