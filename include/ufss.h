@@ -1,0 +1,205 @@
+/*
+ * ufss.h -- C ABI of libufss: the matrix-free Fourier-subsampled pulse-echo
+ * operator A, its adjoint A^H and the FISTA / ISTA l1 solver on MI355X (gfx950).
+ *
+ * The operator (paper Sec. II, eq. of the frequency-domain A-scan model,
+ * discretised on the G2D / G3D grids; Sec. II-B compression Phi = S F Sigma with
+ * Sigma = I):
+ *
+ *   A[(p, m), v] = H_k * 1[|p_x - v_x| <= W_x, |p_y - v_y| <= W_y]
+ *                      * exp(-j 2 pi f_k (tau(p - v, z_v) - t0)),
+ *   k = k_m(p) (the m-th selected DFT bin of scan position p), f_k = k f_s / N_t,
+ *   tau(d, z) = (2 / c) sqrt((d_x dx)^2 + (d_y dy)^2 + z^2),  z_v = z_start + j_z dz,
+ *   H_k = f_s sqrt(2 pi) sigma_t exp(-(f_k - f_c)^2 / (2 sigma_f^2)),
+ *   sigma_f = frac_bw f_c / (2 sqrt(2 ln 2)), sigma_t = 1 / (2 pi sigma_f).
+ *
+ * Conventions shared by every call:
+ *   - Every call returns UFSS_OK (0) or a negative UFSS_ERR_* code and never
+ *     throws; ufss_last_error() then describes the failure (thread-local).
+ *   - Pointers are DEVICE pointers unless the comment says "host".
+ *   - Complex buffers are interleaved float pairs (re, im), i.e. complex64.
+ *   - x (reflectivity) is laid out [ny][nx][nz] (depth fastest);
+ *     y (measurements) is [ny][nx][m] (bin fastest).
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
+ *     is asynchronous unless the comment says the call synchronises.
+ *   - The caller owns x, y and every buffer it passes; a plan owns its own
+ *     device tables and workspace.  A plan is not thread-safe: use one plan per
+ *     host thread / stream.
+ */
+#ifndef UFSS_H
+#define UFSS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define UFSS_OK                  0
+#define UFSS_ERR_INVALID_ARG    -1  /* bad size, pointer or option            */
+#define UFSS_ERR_BAND_TOO_SMALL -2  /* m exceeds the number of band bins      */
+#define UFSS_ERR_HIP            -3  /* a HIP runtime call failed              */
+#define UFSS_ERR_OOM            -4  /* device allocation failed               */
+#define UFSS_ERR_UNSUPPORTED    -5  /* valid request this build cannot serve  */
+#define UFSS_ERR_DIVERGED       -6  /* non-finite or exploding FISTA iterates */
+
+/* ---- operator precision ------------------------------------------------ */
+#define UFSS_F32  0   /* FP32 phasors and operands, FP32 accumulation           */
+#define UFSS_BF16 1   /* BF16 phasors and operands, FP32 accumulation           */
+
+/* ---- operator algorithm -------------------------------------------------- */
+#define UFSS_ALGO_AUTO   0  /* GEMM for shared bins; per-position: fastest     */
+#define UFSS_ALGO_GEMM   1  /* windowed complex GEMM over (offset, depth) on MFMA;
+                               per-position subsets run over their union of bins
+                               and are gathered / scattered                    */
+#define UFSS_ALGO_PHASOR 2  /* per-position on-the-fly phasors (VALU); FP32 only */
+
+/* Scan and pulse geometry (SI units).  Paper Sec. II-A (grids, delay, pulse),
+ * Sec. VI (Gabor pulse).  t0 = NaN selects the window that centres the delay
+ * span of the aperture: t0 = (tau_min + tau_max)/2 - nt/(2 fs).  ny = 1 is a
+ * B-scan.  win_x / win_y < 0 means the full grid. */
+typedef struct ufss_geom {
+    int32_t nx, ny, nz, nt;
+    double dx, dy, dz, z_start, t0, c, fs, fc, frac_bw, band_db;
+    int32_t win_x, win_y;
+    int32_t dtype;      /* UFSS_F32 or UFSS_BF16 */
+    int32_t algo;       /* UFSS_ALGO_* */
+} ufss_geom;
+
+typedef struct ufss_plan_s* ufss_plan_t;
+typedef void* ufss_stream_t;
+
+/* Derived plan quantities (host struct filled by ufss_plan_info). */
+typedef struct ufss_plan_info {
+    double t0;            /* window start actually used (s)                    */
+    double lipschitz;     /* cached L from ufss_lipschitz, 0 if not computed   */
+    int32_t band_lo, band_hi, band_size;  /* pulse band [lo, hi] and its size   */
+    int32_t win_x, win_y; /* effective aperture half-widths                    */
+    int32_t m, per_position, dtype, algo; /* algo actually used                */
+    int32_t union_size;   /* bins in the union of per-position subsets         */
+    int64_t workspace_bytes;              /* device memory owned by the plan    */
+} ufss_plan_info;
+
+/* Per-iteration FISTA statistics, FP64, written to HOST arrays of length
+ * `iters` (each pointer may be NULL).  obj[k] = 1/2 ||A gamma_k - y||^2 +
+ * lambda ||gamma_k||_1 (objective at the extrapolated point), res[k] =
+ * ||A gamma_k - y||, rel_change[k] = ||a_k - a_{k-1}|| / ||a_k||, err_ref[k] =
+ * ||a_k - a_ref|| / ||a_ref|| (only if a_ref was given). */
+typedef struct ufss_fista_stats {
+    double* obj;
+    double* res;
+    double* rel_change;
+    double* err_ref;
+    int32_t iters_done;   /* out: iterations executed                           */
+    double lambda;        /* out: lambda used                                   */
+} ufss_fista_stats;
+
+/* Resumable FISTA state.  gamma is a caller-owned DEVICE buffer [ny][nx][nz]
+ * complex64 holding the extrapolated point; k_done counts completed
+ * iterations (0 = start from x).  The momentum sequence t_k depends on k only,
+ * so (x = a_k, gamma, k_done) is the whole state. */
+typedef struct ufss_fista_state {
+    void* gamma;
+    int32_t k_done;
+} ufss_fista_state;
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* ufss_last_error(void);
+
+/* Select m DFT bins inside the pulse band from a seeded random draw.
+ * Paper Sec. III-A (random sampling, and the per-A-scan variants of Table I).
+ * The band is {k in [0, nt/2] : exp(-(f_k - f_c)^2 / (2 sigma_f^2)) >=
+ * 10^(-band_db/20)}.  Generator: SplitMix64; key = seed for a shared subset,
+ * seed XOR mix64(p + 1) for position p = ix + nx*iy; partial Fisher-Yates over
+ * the ascending band with multiply-high bounds; each subset sorted ascending.
+ *   bins_out      HOST int32 [m] (shared) or [ny][nx][m] (per_position != 0)
+ *   band_size_out HOST, optional (may be NULL)
+ * Errors: INVALID_ARG, BAND_TOO_SMALL (m > band size). */
+int ufss_select_freqs(const ufss_geom* g, int32_t m, int32_t per_position,
+                      uint64_t seed, int32_t* bins_out, int32_t* band_size_out);
+
+/* Build a plan: derived geometry (FP64 on the host), the integer-turn delay
+ * table, H_k and the device workspace.  Paper Sec. IV-B: the operator is block
+ * 2-level Toeplitz in the lateral offset, which the kernels exploit.
+ *   bins  HOST int32 [m] or [ny][nx][m]; each subset strictly ascending and in
+ *         [0, nt/2] (normally from ufss_select_freqs)
+ *   out   HOST, receives the plan handle
+ * Errors: INVALID_ARG, UNSUPPORTED (e.g. BF16 with ALGO_PHASOR), OOM, HIP. */
+int ufss_plan_create(const ufss_geom* g, int32_t m, int32_t per_position,
+                     const int32_t* bins, ufss_plan_t* out);
+
+/* Release a plan and its device memory (synchronises the device). */
+int ufss_plan_destroy(ufss_plan_t plan);
+
+/* Fill a HOST ufss_plan_info. */
+int ufss_plan_info_get(ufss_plan_t plan, ufss_plan_info* info);
+
+/* Forward projection y = A x (paper Sec. IV-A, phi mapping).
+ *   x  DEVICE complex64 [ny][nx][nz], read only
+ *   y  DEVICE complex64 [ny][nx][m], overwritten
+ * Asynchronous on `stream`.  x and y must not overlap. */
+int ufss_forward(ufss_plan_t plan, const void* x, void* y, ufss_stream_t stream);
+
+/* Backward projection x = A^H y (paper Sec. IV-A, beta mapping; with a delta
+ * pulse and no compression it is the SAFT image of the Remark on SAFT).
+ *   y  DEVICE complex64 [ny][nx][m], read only
+ *   x  DEVICE complex64 [ny][nx][nz], overwritten
+ * Asynchronous on `stream`. */
+int ufss_adjoint(ufss_plan_t plan, const void* y, void* x, ufss_stream_t stream);
+
+/* Lipschitz constant L = margin_factor * rho of grad 1/2||Ax - y||^2, where rho
+ * is the power-iteration Rayleigh quotient ||A v||^2 / ||v||^2 of A^H A
+ * (paper Sec. IV-C: sigma_max^2, estimated iteratively; an under-estimate makes
+ * FISTA diverge, so L = (1 + margin) rho).  Vectors in the plan's operator
+ * precision, norms and quotient in FP64.  Start vector CN(0, I) from SplitMix64
+ * keyed by `seed`.  Stops when |rho_k - rho_{k-1}| <= rtol rho_k or after
+ * max_iters.  Synchronises `stream`; caches L in the plan.
+ *   L_out  HOST double */
+int ufss_lipschitz(ufss_plan_t plan, int32_t max_iters, double rtol,
+                   double margin, uint64_t seed, double* L_out,
+                   ufss_stream_t stream);
+
+/* FISTA (accel = 1) or ISTA (accel = 0) for min 1/2||A a - y||^2 + lambda||a||_1
+ * (paper Alg. 1 with step 1/L, threshold lambda/L, complex soft threshold
+ * z max(0, 1 - alpha/|z|), Beck-Teboulle momentum; lambda rule of Sec. VII).
+ *   y       DEVICE complex64 [ny][nx][m]
+ *   lambda  > 0: used as is; < 0: lambda = (-lambda) * max|A^H y|
+ *   L       > 0: Lipschitz constant; <= 0: the plan's cached value (error if none)
+ *   iters   number of iterations (>= 0)
+ *   tol     > 0: stop early once ||a_k - a_{k-1}|| <= tol ||a_k|| (checked every
+ *           8 iterations); 0: run exactly `iters`
+ *   x       DEVICE complex64 [ny][nx][nz]: in = a_0 (ignored when resuming), out = a_K
+ *   a_ref   DEVICE complex64 [ny][nx][nz] or NULL (enables stats->err_ref)
+ *   stats   HOST or NULL; state HOST or NULL (see the struct comments)
+ * Synchronises `stream` before returning.  Returns UFSS_ERR_DIVERGED if an
+ * iterate or residual becomes non-finite or the residual exceeds 1e6 times its
+ * first value; x then holds the last iterate. */
+int ufss_fista(ufss_plan_t plan, const void* y, double lambda, double L,
+               int32_t iters, double tol, int32_t accel, void* x,
+               const void* a_ref, ufss_fista_stats* stats,
+               ufss_fista_state* state, ufss_stream_t stream);
+
+/* Fused proximal-gradient update, standalone (paper Alg. 1, threshold and
+ * momentum lines; ISTA is beta = 0).  For each of n complex entries:
+ *   a_new = soft(gamma - step * g, thresh),  gamma <- a_new + beta (a_new - a),
+ *   a <- a_new.
+ *   gamma, a  DEVICE complex64 [n], updated in place;  g DEVICE complex64 [n]
+ *   a_ref     DEVICE complex64 [n] or NULL
+ *   norms_out HOST double [5] or NULL: ||a_new||_1, ||gamma_new||_1,
+ *             ||a_new - a||^2, ||a_new||^2, ||a_new - a_ref||^2 (FP64, fixed-order
+ *             reduction, bitwise reproducible).  Synchronises only if norms_out. */
+int ufss_shrink_update(int64_t n, void* gamma, const void* g, void* a,
+                       double step, double thresh, double beta,
+                       const void* a_ref, double* norms_out,
+                       ufss_stream_t stream);
+
+/* max_v |x_v| over n complex entries (FP32 values, exact max), for the lambda
+ * rule.  out HOST double.  Synchronises `stream`. */
+int ufss_absmax(int64_t n, const void* x, double* out, ufss_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UFSS_H */

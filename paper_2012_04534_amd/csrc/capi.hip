@@ -1,0 +1,345 @@
+// Operator drivers, solvers and the C ABI entry points of libufss.
+//
+// FISTA (paper Alg. 1, Sec. IV-A) with step 1/L, threshold lambda/L and
+// Beck-Teboulle momentum; lambda rule of Sec. VII; Lipschitz constant by power
+// iteration on A^H A with FP64 norms (Sec. IV-C, iterative approximation).
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace ufss {
+
+Plan* plan_create(const ufss_geom* g, int m, int per_position, const int32_t* bins);
+void plan_destroy(Plan* P);
+void plan_info(const Plan* P, ufss_plan_info* info);
+void select_freqs(const ufss_geom* g, int m, int per_position, uint64_t seed, int32_t* out,
+                  int32_t* band_size);
+const char* last_error();
+int phasor_forward_blocks(const Plan& P);
+void launch_forward_gemm_bf16(const Plan& P, hipStream_t s);
+void launch_adjoint_gemm_bf16(const Plan& P, cf32* out, hipStream_t s);
+
+// y = A x (ymeas == NULL) or y = A x - ymeas.  If res2_out != NULL it receives
+// ||y||^2 (FP64, device scalar).
+void op_forward(Plan& P, const cf32* x, cf32* y, const cf32* ymeas, double* res2_out,
+                hipStream_t s) {
+    if (P.algo == UFSS_ALGO_PHASOR) {
+        launch_forward_phasor(P, x, y, ymeas, P.d_part, s);
+        if (res2_out) launch_reduce(P.d_part, phasor_forward_blocks(P), 1, res2_out, s);
+        return;
+    }
+    if (P.dtype == UFSS_BF16) {
+        launch_to_bf16(x, P.d_xop, P.nvox, s);
+        launch_forward_gemm_bf16(P, s);
+    } else {
+        launch_forward_gemm(P, x, s);
+    }
+    int nb = launch_forward_post(P, y, ymeas, P.d_part, s);
+    if (res2_out) launch_reduce(P.d_part, nb, 1, res2_out, s);
+}
+
+void op_adjoint(Plan& P, const cf32* y, cf32* x, hipStream_t s) {
+    launch_adjoint_pre(P, y, s);
+    if (P.algo == UFSS_ALGO_PHASOR)
+        launch_adjoint_phasor(P, x, s);
+    else if (P.dtype == UFSS_BF16)
+        launch_adjoint_gemm_bf16(P, x, s);
+    else
+        launch_adjoint_gemm(P, x, s);
+}
+
+static void sync(hipStream_t s) { UFSS_HIP(hipStreamSynchronize(s)); }
+
+static double read_scalar(const double* d, hipStream_t s) {
+    double h = 0.0;
+    UFSS_HIP(hipMemcpyAsync(&h, d, sizeof(double), hipMemcpyDeviceToHost, s));
+    sync(s);
+    return h;
+}
+
+static uint64_t sm_next(uint64_t& st) {
+    st += 0x9E3779B97F4A7C15ull;
+    uint64_t z = st;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+double lipschitz(Plan& P, int max_iters, double rtol, double margin, uint64_t seed, hipStream_t s) {
+    if (max_iters < 1) fail(UFSS_ERR_INVALID_ARG, "max_iters must be >= 1");
+    if (!(rtol >= 0) || !(margin >= 0)) fail(UFSS_ERR_INVALID_ARG, "rtol and margin must be >= 0");
+    // CN(0, I) start vector by Box-Muller on SplitMix64 uniforms
+    std::vector<cf32> v0(P.nvox);
+    uint64_t st = seed;
+    for (int64_t i = 0; i < P.nvox; ++i) {
+        double u1 = ((sm_next(st) >> 11) + 1.0) * 0x1.0p-53;
+        double u2 = (sm_next(st) >> 11) * 0x1.0p-53;
+        double rad = std::sqrt(-std::log(u1));
+        v0[i] = cf32{(float)(rad * std::cos(2 * M_PI * u2)), (float)(rad * std::sin(2 * M_PI * u2))};
+    }
+    UFSS_HIP(hipMemcpyAsync(P.d_v, v0.data(), P.nvox * sizeof(cf32), hipMemcpyHostToDevice, s));
+    double* nrm = P.d_scalars + 32;
+    int nb = launch_norm2(P.nvox, P.d_v, P.d_part, s);
+    launch_reduce(P.d_part, nb, 2, nrm, s);
+    launch_scale(P.nvox, P.d_v, nrm, s);
+    double rho = 0.0, rho_old = 0.0;
+    for (int it = 1; it <= max_iters; ++it) {
+        op_forward(P, P.d_v, P.d_r, nullptr, P.d_scalars + 34, s);   // rho = ||A v||^2
+        op_adjoint(P, P.d_r, P.d_g, s);
+        nb = launch_norm2(P.nvox, P.d_g, P.d_part, s);
+        launch_reduce(P.d_part, nb, 2, nrm, s);
+        launch_copy(P.nvox, P.d_g, P.d_v, s);
+        launch_scale(P.nvox, P.d_v, nrm, s);
+        rho = read_scalar(P.d_scalars + 34, s);
+        if (!std::isfinite(rho)) fail(UFSS_ERR_DIVERGED, "non-finite Rayleigh quotient");
+        if (rho_old > 0 && std::fabs(rho - rho_old) <= rtol * rho) break;
+        rho_old = rho;
+    }
+    P.lipschitz = (1.0 + margin) * rho;
+    return P.lipschitz;
+}
+
+static double absmax_dev(int64_t n, const cf32* x, double* part, double* out, hipStream_t s) {
+    int nb = launch_absmax(n, x, part, s);
+    launch_reduce_max(part, nb, out, s);
+    return read_scalar(out, s);
+}
+
+int fista(Plan& P, const cf32* y, double lambda, double L, int iters, double tol, int accel,
+          cf32* x, const cf32* aref, ufss_fista_stats* stats, ufss_fista_state* state,
+          hipStream_t s) {
+    if (!y || !x) fail(UFSS_ERR_INVALID_ARG, "y and x must be device pointers");
+    if (iters < 0) fail(UFSS_ERR_INVALID_ARG, "iters must be >= 0");
+    if (!(tol >= 0)) fail(UFSS_ERR_INVALID_ARG, "tol must be >= 0");
+    if (!(L > 0)) L = P.lipschitz;
+    if (!(L > 0)) fail(UFSS_ERR_INVALID_ARG, "no Lipschitz constant given or cached");
+    if (lambda == 0 || std::isnan(lambda)) fail(UFSS_ERR_INVALID_ARG, "lambda must be non-zero");
+    if (lambda < 0) {
+        op_adjoint(P, y, P.d_g, s);
+        lambda = -lambda * absmax_dev(P.nvox, P.d_g, P.d_part, P.d_scalars + 40, s);
+    }
+    cf32* gamma = (state && state->gamma) ? static_cast<cf32*>(state->gamma) : P.d_gamma;
+    const int k0 = state ? state->k_done : 0;
+    if (k0 < 0) fail(UFSS_ERR_INVALID_ARG, "state->k_done must be >= 0");
+    if (k0 > 0 && !(state && state->gamma))
+        fail(UFSS_ERR_INVALID_ARG, "resuming needs state->gamma");
+    if (k0 == 0) launch_copy(P.nvox, x, gamma, s);
+    double tk = 1.0;
+    for (int i = 0; i < k0; ++i) tk = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * tk * tk));
+    double ref2 = 0.0;
+    if (aref) {
+        int nb = launch_norm2(P.nvox, aref, P.d_part, s);
+        launch_reduce(P.d_part, nb, 2, P.d_scalars + 44, s);
+        ref2 = read_scalar(P.d_scalars + 44, s);
+        if (!(ref2 > 0)) fail(UFSS_ERR_INVALID_ARG, "a_ref is zero");
+    }
+    if (P.stats_cap < iters) {
+        if (P.d_stats) UFSS_HIP(hipFree(P.d_stats));
+        P.d_stats = nullptr;
+        P.stats_cap = 0;
+        UFSS_HIP(hipMalloc(&P.d_stats, (size_t)std::max(iters, 1) * 4 * sizeof(double)));
+        P.stats_cap = std::max(iters, 1);
+    }
+    // ||gamma_k0||_1 for the first objective value
+    double* g1 = P.d_scalars + 16;
+    {
+        int nb = launch_norm2(P.nvox, gamma, P.d_part, s);
+        double* tmp = P.d_scalars + 20;
+        launch_reduce(P.d_part, nb, 2, tmp, s);
+        UFSS_HIP(hipMemcpyAsync(g1, tmp + 1, sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    const float step = (float)(1.0 / L), thresh = (float)(lambda / L);
+    int done = 0;
+    for (int k = 0; k < iters; ++k) {
+        op_forward(P, gamma, P.d_r, y, P.d_scalars + 0, s);
+        op_adjoint(P, P.d_r, P.d_g, s);
+        const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * tk * tk));
+        const double beta = accel ? (tk - 1.0) / tn : 0.0;
+        int nb = launch_update(P.nvox, gamma, P.d_g, x, step, thresh, (float)beta, aref, P.d_part, s);
+        launch_reduce(P.d_part, nb, 5, P.d_scalars + 8, s);
+        launch_fista_stats(P.d_stats, k, P.d_scalars + 8, P.d_scalars + 0, g1, lambda,
+                           aref ? 1 : 0, ref2, s);
+        tk = tn;
+        done = k + 1;
+        if (tol > 0 && (done % 8 == 0)) {
+            double rc = read_scalar(P.d_stats + 4 * (int64_t)k + 2, s);
+            if (rc <= tol) break;
+        }
+    }
+    std::vector<double> h((size_t)std::max(done, 1) * 4);
+    if (done > 0)
+        UFSS_HIP(hipMemcpyAsync(h.data(), P.d_stats, (size_t)done * 4 * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+    sync(s);
+    if (state) state->k_done = k0 + done;
+    if (stats) {
+        stats->iters_done = done;
+        stats->lambda = lambda;
+        for (int k = 0; k < done; ++k) {
+            if (stats->obj) stats->obj[k] = h[4 * k + 0];
+            if (stats->res) stats->res[k] = h[4 * k + 1];
+            if (stats->rel_change) stats->rel_change[k] = h[4 * k + 2];
+            if (stats->err_ref) stats->err_ref[k] = h[4 * k + 3];
+        }
+    }
+    for (int k = 0; k < done; ++k) {
+        if (!std::isfinite(h[4 * k + 0]) || !std::isfinite(h[4 * k + 1]) ||
+            !std::isfinite(h[4 * k + 2]) || h[4 * k + 1] > 1e6 * h[1] + 1e-300)
+            fail(UFSS_ERR_DIVERGED, "FISTA diverged at iteration " + std::to_string(k0 + k) +
+                                        " (non-finite or exploding residual); check L");
+    }
+    return UFSS_OK;
+}
+
+}  // namespace ufss
+
+// ---------------------------------------------------------------------------
+// C ABI.
+// ---------------------------------------------------------------------------
+using ufss::Error;
+using ufss::Plan;
+
+#define UFSS_GUARD_BEGIN \
+    try {                \
+        ufss::set_last_error("");
+#define UFSS_GUARD_END                                   \
+    }                                                    \
+    catch (const Error& e) {                             \
+        ufss::set_last_error(e.msg);                     \
+        return e.code;                                   \
+    }                                                    \
+    catch (const std::bad_alloc&) {                      \
+        ufss::set_last_error("host allocation failed");  \
+        return UFSS_ERR_OOM;                             \
+    }                                                    \
+    catch (...) {                                        \
+        ufss::set_last_error("unexpected exception");    \
+        return UFSS_ERR_INVALID_ARG;                     \
+    }                                                    \
+    return UFSS_OK;
+
+static Plan* as_plan(ufss_plan_t p) {
+    if (!p) ufss::fail(UFSS_ERR_INVALID_ARG, "plan is NULL");
+    return reinterpret_cast<Plan*>(p);
+}
+
+extern "C" {
+
+const char* ufss_last_error(void) { return ufss::last_error(); }
+
+int ufss_select_freqs(const ufss_geom* g, int32_t m, int32_t per_position, uint64_t seed,
+                      int32_t* bins_out, int32_t* band_size_out) {
+    UFSS_GUARD_BEGIN
+    ufss::select_freqs(g, m, per_position, seed, bins_out, band_size_out);
+    UFSS_GUARD_END
+}
+
+int ufss_plan_create(const ufss_geom* g, int32_t m, int32_t per_position, const int32_t* bins,
+                     ufss_plan_t* out) {
+    UFSS_GUARD_BEGIN
+    if (!out) ufss::fail(UFSS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    *out = reinterpret_cast<ufss_plan_t>(ufss::plan_create(g, m, per_position, bins));
+    UFSS_GUARD_END
+}
+
+int ufss_plan_destroy(ufss_plan_t plan) {
+    UFSS_GUARD_BEGIN
+    ufss::plan_destroy(as_plan(plan));
+    UFSS_GUARD_END
+}
+
+int ufss_plan_info_get(ufss_plan_t plan, ufss_plan_info* info) {
+    UFSS_GUARD_BEGIN
+    ufss::plan_info(as_plan(plan), info);
+    UFSS_GUARD_END
+}
+
+int ufss_forward(ufss_plan_t plan, const void* x, void* y, ufss_stream_t stream) {
+    UFSS_GUARD_BEGIN
+    if (!x || !y) ufss::fail(UFSS_ERR_INVALID_ARG, "x and y must be device pointers");
+    Plan* P = as_plan(plan);
+    ufss::op_forward(*P, static_cast<const ufss::cf32*>(x), static_cast<ufss::cf32*>(y), nullptr,
+                     nullptr, static_cast<hipStream_t>(stream));
+    UFSS_GUARD_END
+}
+
+int ufss_adjoint(ufss_plan_t plan, const void* y, void* x, ufss_stream_t stream) {
+    UFSS_GUARD_BEGIN
+    if (!x || !y) ufss::fail(UFSS_ERR_INVALID_ARG, "x and y must be device pointers");
+    Plan* P = as_plan(plan);
+    ufss::op_adjoint(*P, static_cast<const ufss::cf32*>(y), static_cast<ufss::cf32*>(x),
+                     static_cast<hipStream_t>(stream));
+    UFSS_GUARD_END
+}
+
+int ufss_lipschitz(ufss_plan_t plan, int32_t max_iters, double rtol, double margin, uint64_t seed,
+                   double* L_out, ufss_stream_t stream) {
+    UFSS_GUARD_BEGIN
+    Plan* P = as_plan(plan);
+    double L = ufss::lipschitz(*P, max_iters, rtol, margin, seed, static_cast<hipStream_t>(stream));
+    if (L_out) *L_out = L;
+    UFSS_GUARD_END
+}
+
+int ufss_fista(ufss_plan_t plan, const void* y, double lambda, double L, int32_t iters,
+               double tol, int32_t accel, void* x, const void* a_ref, ufss_fista_stats* stats,
+               ufss_fista_state* state, ufss_stream_t stream) {
+    UFSS_GUARD_BEGIN
+    Plan* P = as_plan(plan);
+    return ufss::fista(*P, static_cast<const ufss::cf32*>(y), lambda, L, iters, tol, accel,
+                       static_cast<ufss::cf32*>(x), static_cast<const ufss::cf32*>(a_ref), stats,
+                       state, static_cast<hipStream_t>(stream));
+    UFSS_GUARD_END
+}
+
+int ufss_shrink_update(int64_t n, void* gamma, const void* g, void* a, double step, double thresh,
+                       double beta, const void* a_ref, double* norms_out, ufss_stream_t stream) {
+    UFSS_GUARD_BEGIN
+    if (n < 0 || (n > 0 && (!gamma || !g || !a)))
+        ufss::fail(UFSS_ERR_INVALID_ARG, "bad size or NULL buffer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* part = nullptr;
+    double* out = nullptr;
+    UFSS_HIP(hipMalloc(&part, (size_t)ufss::max_blocks_vec() * 5 * sizeof(double) + 64));
+    UFSS_HIP(hipMalloc(&out, 8 * sizeof(double)));
+    try {
+        int nb = ufss::launch_update(n, static_cast<ufss::cf32*>(gamma),
+                                     static_cast<const ufss::cf32*>(g), static_cast<ufss::cf32*>(a),
+                                     (float)step, (float)thresh, (float)beta,
+                                     static_cast<const ufss::cf32*>(a_ref), part, s);
+        ufss::launch_reduce(part, nb, 5, out, s);
+        if (norms_out) {
+            UFSS_HIP(hipMemcpyAsync(norms_out, out, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
+        }
+        UFSS_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+        (void)hipFree(part);
+        (void)hipFree(out);
+        throw;
+    }
+    UFSS_HIP(hipFree(part));
+    UFSS_HIP(hipFree(out));
+    UFSS_GUARD_END
+}
+
+int ufss_absmax(int64_t n, const void* x, double* out, ufss_stream_t stream) {
+    UFSS_GUARD_BEGIN
+    if (n < 1 || !x || !out) ufss::fail(UFSS_ERR_INVALID_ARG, "bad size or NULL buffer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* part = nullptr;
+    UFSS_HIP(hipMalloc(&part, (size_t)(ufss::max_blocks_vec() + 8) * sizeof(double)));
+    try {
+        *out = ufss::absmax_dev(n, static_cast<const ufss::cf32*>(x), part,
+                                part + ufss::max_blocks_vec(), s);
+    } catch (...) {
+        (void)hipFree(part);
+        throw;
+    }
+    UFSS_HIP(hipFree(part));
+    UFSS_GUARD_END
+}
+
+}  // extern "C"

@@ -1,0 +1,375 @@
+// Windowed complex GEMM kernels for shared frequency subsets, FP32 on MFMA.
+//
+// The operator is block 2-level Toeplitz in the lateral offset d = p - v
+// (paper Sec. IV-B, theorem on the structure of H): for one offset d it is a
+// dense complex product between the phase matrix P_d[k, z] and the depth
+// profiles of the voxels at p - d.  Instead of the paper's FFT-based
+// correlation (Alg. 2) the window is summed directly, one small GEMM per
+// offset, which puts the work on the matrix cores:
+//
+//   forward  Y[p, k] = sum_{d in W} sum_z  P_d[k, z] x[p - d, z]
+//   adjoint  G[v, z] = sum_{d in W} sum_k  conj(P_d[k, z]) R[v + d, k]
+//
+// with P_d[k, z] = exp(-j 2 pi (k * u(|d|, z) mod 2^32) / 2^32), u the
+// integer-turn delay table built by the plan.  H_k scaling, gathers for
+// per-position subsets and residuals live in the small pre/post kernels.
+//
+// MFMA: v_mfma_f32_16x16x4_f32.  Lane l holds A[i = l%16][k = l/16],
+// B[k = l/16][j = l%16] and D[i = 4(l/16) + r][j = l%16] for r = 0..3.
+// Complex products use four real MFMAs on split real / imaginary parts.
+//
+// Tiling (both kernels): a workgroup of 4 waves owns one lateral tile of
+// NP sub-tiles of 16 positions (sw x 16/sw each, sw = 4 for C-scans, 16 for
+// B-scans).  Forward: each wave owns 16 bins, the 4 waves cover 64 bins.
+// Adjoint: each wave owns NZ x 16 depths.  The shifted input rows for one d_y
+// and one chunk of the reduction axis are staged in LDS (zero outside the
+// grid); phasors are generated per lane in registers.  Accumulation is two
+// level (per d_y in MFMA registers, then into an outer FP32 sum) to keep the
+// FP32 error of ~1e5-term sums near 1e-6.
+#include "internal.h"
+
+namespace ufss {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+static constexpr float kTwoM32 = 2.3283064365386963e-10f;   // 2^-32
+
+// exp(-j 2 pi phi) components for the integer phase k*u (mod 2^32) in turns.
+__device__ __forceinline__ void phasor(uint32_t ku, float& c, float& s) {
+    float ph = (float)(int32_t)ku * kTwoM32;     // [-0.5, 0.5) turns
+    c = __builtin_amdgcn_cosf(ph);              // cos(2 pi ph)
+    s = __builtin_amdgcn_sinf(ph);              // sin(2 pi ph)
+}
+
+struct FwdArgs {
+    const cf32* x;
+    cf32* yraw;            // [split][npos][mu]
+    const uint32_t* u;     // [wy+1][wx+1][nz]
+    const int* kb;         // [mu]
+    int nx, ny, nz, wx, wy, mu;
+    int sw;                // sub-tile width (4 or 16)
+    int ntx, nty;          // lateral tiles
+    int nbt;               // bin tiles of 64
+    int zc;                // depth chunk (multiple of 4)
+    int split;             // split of the d_y range
+    int64_t npos;
+};
+
+template <int NP>
+__global__ __launch_bounds__(256) void fwd_gemm_f32_kernel(FwdArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int sw = a.sw, sh = 16 / sw;
+    const int tpx = sw * NP, tpy = sh;
+    const int hc = tpx + 2 * a.wx;            // halo columns
+    const int cs = a.zc + 1;                  // padded cell stride (complex)
+    cf32* halo = reinterpret_cast<cf32*>(smem);
+    uint32_t* ulds = reinterpret_cast<uint32_t*>(halo + (size_t)tpy * hc * cs);
+
+    // block -> (split, bin tile, lateral tile); consecutive tiles of one split
+    // and bin tile stay on one XCD (blocks are dealt round-robin to 8 XCDs).
+    const int nblk = gridDim.x;
+    int b = blockIdx.x;
+    int per_xcd = nblk / 8;
+    if (per_xcd * 8 == nblk) b = (b % 8) * per_xcd + b / 8;
+    const int ntile = a.ntx * a.nty;
+    const int tile = b % ntile;
+    const int bt = (b / ntile) % a.nbt;
+    const int sp = b / (ntile * a.nbt);
+    const int px0 = (tile % a.ntx) * tpx, py0 = (tile / a.ntx) * tpy;
+
+    // d_y range of this split (rows that hit the grid for some tile row)
+    int dy_lo = max(-a.wy, py0 - (a.ny - 1));
+    int dy_hi = min(a.wy, py0 + tpy - 1);
+    const int ndy = dy_hi - dy_lo + 1;
+    const int chunk = (ndy + a.split - 1) / a.split;
+    dy_lo += sp * chunk;
+    dy_hi = min(dy_hi, dy_lo + chunk - 1);
+    const int dx_lo = max(-a.wx, px0 - (a.nx - 1));
+    const int dx_hi = min(a.wx, px0 + tpx - 1);
+
+    const int mb = bt * 64 + wave * 16 + (lane & 15);   // this lane's bin column
+    const bool wave_active = bt * 64 + wave * 16 < a.mu;
+    const uint32_t kbin = (mb < a.mu) ? (uint32_t)a.kb[mb] : 0u;
+    const int i = lane & 15, ix = i % sw, iy = i / sw;
+    const int kq = lane >> 4;
+
+    f4 out_re[NP], out_im[NP];
+#pragma unroll
+    for (int s = 0; s < NP; ++s) out_re[s] = out_im[s] = f4{0.f, 0.f, 0.f, 0.f};
+
+    const int ncell = tpy * hc;
+    for (int z0 = 0; z0 < a.nz; z0 += a.zc) {
+        for (int dy = dy_lo; dy <= dy_hi; ++dy) {
+            __syncthreads();
+            // stage x rows (py0 + r - dy), columns (px0 - wx + c), depths z0..z0+zc
+            for (int t = threadIdx.x; t < ncell * a.zc; t += 256) {
+                int cell = t / a.zc, zz = t - cell * a.zc;
+                int r = cell / hc, c = cell - r * hc;
+                int gy = py0 + r - dy, gx = px0 - a.wx + c, z = z0 + zz;
+                cf32 v{0.f, 0.f};
+                if (gy >= 0 && gy < a.ny && gx >= 0 && gx < a.nx && z < a.nz)
+                    v = a.x[((int64_t)gy * a.nx + gx) * a.nz + z];
+                halo[cell * cs + zz] = v;
+            }
+            const int ady = dy < 0 ? -dy : dy;
+            for (int t = threadIdx.x; t < (a.wx + 1) * a.zc; t += 256) {
+                int adx = t / a.zc, zz = t - adx * a.zc;
+                int z = z0 + zz;
+                ulds[t] = z < a.nz ? a.u[((int64_t)ady * (a.wx + 1) + adx) * a.nz + z] : 0u;
+            }
+            __syncthreads();
+            if (!wave_active) continue;
+            f4 in_re[NP], in_im[NP];
+#pragma unroll
+            for (int s = 0; s < NP; ++s) in_re[s] = in_im[s] = f4{0.f, 0.f, 0.f, 0.f};
+            for (int dx = dx_lo; dx <= dx_hi; ++dx) {
+                const int adx = dx < 0 ? -dx : dx;
+                const uint32_t* urow = ulds + adx * a.zc;
+                const cf32* hrow = halo + (iy * hc + ix + a.wx - dx) * cs;
+                for (int zz = 0; zz < a.zc; zz += 4) {
+                    float c, sn;
+                    phasor(kbin * urow[zz + kq], c, sn);
+#pragma unroll
+                    for (int s = 0; s < NP; ++s) {
+                        cf32 xv = hrow[s * sw * cs + zz + kq];
+                        in_re[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.re, c, in_re[s], 0, 0, 0);
+                        in_re[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.im, sn, in_re[s], 0, 0, 0);
+                        in_im[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.im, c, in_im[s], 0, 0, 0);
+                        in_im[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.re, -sn, in_im[s], 0, 0, 0);
+                    }
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < NP; ++s) {
+                out_re[s] += in_re[s];
+                out_im[s] += in_im[s];
+            }
+        }
+    }
+    if (!wave_active || mb >= a.mu) return;
+    cf32* yo = a.yraw + (int64_t)sp * a.npos * a.mu;
+#pragma unroll
+    for (int s = 0; s < NP; ++s) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            int irow = 4 * kq + r;
+            int px = px0 + s * sw + irow % sw, py = py0 + irow / sw;
+            if (px < a.nx && py < a.ny)
+                yo[((int64_t)py * a.nx + px) * a.mu + mb] = cf32{out_re[s][r], out_im[s][r]};
+        }
+    }
+}
+
+struct AdjArgs {
+    const cf32* r;         // H-scaled operand [npos][mu]
+    cf32* out;             // [ny][nx][nz]
+    const uint32_t* u;
+    const int* kb;
+    int nx, ny, nz, wx, wy, mu;
+    int sw, ntx, nty, nzt; // lateral tiles, depth tiles (of 64 * NZ)
+    int kc;                // bin chunk (multiple of 4)
+};
+
+template <int NP, int NZ>
+__global__ __launch_bounds__(256) void adj_gemm_f32_kernel(AdjArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int sw = a.sw, sh = 16 / sw;
+    const int tpx = sw * NP, tpy = sh;
+    const int hc = tpx + 2 * a.wx;
+    const int cs = a.kc + 1;
+    const int zspan = 64 * NZ;                       // depths per workgroup
+    cf32* halo = reinterpret_cast<cf32*>(smem);
+    uint32_t* ulds = reinterpret_cast<uint32_t*>(halo + (size_t)tpy * hc * cs);
+    int* klds = reinterpret_cast<int*>(ulds + (size_t)(a.wx + 1) * zspan);
+
+    const int nblk = gridDim.x;
+    int b = blockIdx.x;
+    int per_xcd = nblk / 8;
+    if (per_xcd * 8 == nblk) b = (b % 8) * per_xcd + b / 8;
+    const int ntile = a.ntx * a.nty;
+    const int tile = b % ntile;
+    const int zt = b / ntile;
+    const int vx0 = (tile % a.ntx) * tpx, vy0 = (tile / a.ntx) * tpy;
+    const int zw0 = zt * zspan;                      // first depth of the workgroup
+
+    // d with v + d inside the grid for some voxel of the tile
+    const int dy_lo = max(-a.wy, -(vy0 + tpy - 1)), dy_hi = min(a.wy, a.ny - 1 - vy0);
+    const int dx_lo = max(-a.wx, -(vx0 + tpx - 1)), dx_hi = min(a.wx, a.nx - 1 - vx0);
+
+    const int i = lane & 15, ix = i % sw, iy = i / sw;
+    const int kq = lane >> 4;
+    const bool wave_active = zw0 + wave * NZ * 16 < a.nz;
+
+    f4 out_re[NP][NZ], out_im[NP][NZ];
+#pragma unroll
+    for (int s = 0; s < NP; ++s)
+#pragma unroll
+        for (int q = 0; q < NZ; ++q) out_re[s][q] = out_im[s][q] = f4{0.f, 0.f, 0.f, 0.f};
+
+    const int ncell = tpy * hc;
+    for (int k0 = 0; k0 < a.mu; k0 += a.kc) {
+        for (int dy = dy_lo; dy <= dy_hi; ++dy) {
+            __syncthreads();
+            for (int t = threadIdx.x; t < ncell * a.kc; t += 256) {
+                int cell = t / a.kc, kk = t - cell * a.kc;
+                int rr = cell / hc, c = cell - rr * hc;
+                int gy = vy0 + rr + dy, gx = vx0 - a.wx + c, k = k0 + kk;
+                cf32 v{0.f, 0.f};
+                if (gy >= 0 && gy < a.ny && gx >= 0 && gx < a.nx && k < a.mu)
+                    v = a.r[((int64_t)gy * a.nx + gx) * a.mu + k];
+                halo[cell * cs + kk] = v;
+            }
+            const int ady = dy < 0 ? -dy : dy;
+            for (int t = threadIdx.x; t < (a.wx + 1) * zspan; t += 256) {
+                int adx = t / zspan, zz = t - adx * zspan;
+                int z = zw0 + zz;
+                ulds[t] = z < a.nz ? a.u[((int64_t)ady * (a.wx + 1) + adx) * a.nz + z] : 0u;
+            }
+            for (int t = threadIdx.x; t < a.kc; t += 256)
+                klds[t] = (k0 + t < a.mu) ? a.kb[k0 + t] : 0;
+            __syncthreads();
+            if (!wave_active) continue;
+            f4 in_re[NP][NZ], in_im[NP][NZ];
+#pragma unroll
+            for (int s = 0; s < NP; ++s)
+#pragma unroll
+                for (int q = 0; q < NZ; ++q) in_re[s][q] = in_im[s][q] = f4{0.f, 0.f, 0.f, 0.f};
+            for (int dx = dx_lo; dx <= dx_hi; ++dx) {
+                const int adx = dx < 0 ? -dx : dx;
+                uint32_t uz[NZ];
+#pragma unroll
+                for (int q = 0; q < NZ; ++q) uz[q] = ulds[adx * zspan + wave * NZ * 16 + q * 16 + i];
+                const cf32* hrow = halo + (iy * hc + ix + a.wx + dx) * cs;
+                for (int kk = 0; kk < a.kc; kk += 4) {
+                    const uint32_t k = (uint32_t)klds[kk + kq];
+                    cf32 rv[NP];
+#pragma unroll
+                    for (int s = 0; s < NP; ++s) rv[s] = hrow[s * sw * cs + kk + kq];
+#pragma unroll
+                    for (int q = 0; q < NZ; ++q) {
+                        float c, sn;
+                        phasor(k * uz[q], c, sn);
+#pragma unroll
+                        for (int s = 0; s < NP; ++s) {
+                            // (rr + j ri)(c + j s) = rr c - ri s + j (rr s + ri c)
+                            in_re[s][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(rv[s].re, c, in_re[s][q], 0, 0, 0);
+                            in_re[s][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(rv[s].im, -sn, in_re[s][q], 0, 0, 0);
+                            in_im[s][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(rv[s].re, sn, in_im[s][q], 0, 0, 0);
+                            in_im[s][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(rv[s].im, c, in_im[s][q], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < NP; ++s)
+#pragma unroll
+                for (int q = 0; q < NZ; ++q) {
+                    out_re[s][q] += in_re[s][q];
+                    out_im[s][q] += in_im[s][q];
+                }
+        }
+    }
+    if (!wave_active) return;
+#pragma unroll
+    for (int s = 0; s < NP; ++s)
+#pragma unroll
+        for (int q = 0; q < NZ; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int irow = 4 * kq + r;
+                int vx = vx0 + s * sw + irow % sw, vy = vy0 + irow / sw;
+                int z = zw0 + wave * NZ * 16 + q * 16 + i;
+                if (vx < a.nx && vy < a.ny && z < a.nz)
+                    a.out[((int64_t)vy * a.nx + vx) * a.nz + z] = cf32{out_re[s][q][r], out_im[s][q][r]};
+            }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+// ---------------------------------------------------------------------------
+static constexpr int kFwdNP = 2;
+static constexpr int kAdjNP = 2;
+static constexpr int kAdjNZ = 1;
+static constexpr size_t kLdsMax = 64 * 1024;
+
+static int sub_width(const Plan& P) { return P.g.ny == 1 ? 16 : 4; }
+
+int gemm_split(const Plan& P) {
+    const int sw = sub_width(P), tpx = sw * kFwdNP, tpy = 16 / sw;
+    const int ntx = (P.g.nx + tpx - 1) / tpx, nty = (P.g.ny + tpy - 1) / tpy;
+    const int mu = (int)P.ubins_h.size();
+    const int nbt = (mu + 63) / 64;
+    const int active_waves = ntx * nty * ((mu + 15) / 16);
+    const int ndy_max = std::min(2 * P.d.wy + 1, P.g.ny + tpy - 1);
+    int split = (4096 + active_waves - 1) / active_waves;
+    split = std::max(1, std::min(split, std::min(ndy_max, 16)));
+    (void)nbt;
+    return split;
+}
+
+void launch_forward_gemm(const Plan& P, const cf32* x, hipStream_t s) {
+    FwdArgs a{};
+    a.x = x;
+    a.yraw = P.d_yraw;
+    a.u = P.d_u;
+    a.kb = P.d_ubins;
+    a.nx = P.g.nx;
+    a.ny = P.g.ny;
+    a.nz = P.g.nz;
+    a.wx = P.d.wx;
+    a.wy = P.d.wy;
+    a.mu = (int)P.ubins_h.size();
+    a.sw = sub_width(P);
+    const int tpx = a.sw * kFwdNP, tpy = 16 / a.sw;
+    a.ntx = (a.nx + tpx - 1) / tpx;
+    a.nty = (a.ny + tpy - 1) / tpy;
+    a.nbt = (a.mu + 63) / 64;
+    a.split = P.fwd_split;
+    a.npos = P.npos;
+    const int hc = tpx + 2 * a.wx;
+    int zc = 16;
+    while (zc > 4 && (size_t)tpy * hc * (zc + 1) * sizeof(cf32) + (size_t)(a.wx + 1) * zc * 4 > kLdsMax)
+        zc -= 4;
+    size_t lds = (size_t)tpy * hc * (zc + 1) * sizeof(cf32) + (size_t)(a.wx + 1) * zc * 4;
+    if (lds > kLdsMax) fail(UFSS_ERR_UNSUPPORTED, "aperture window too wide for the GEMM path");
+    a.zc = zc;
+    const int nblk = a.ntx * a.nty * a.nbt * a.split;
+    hipLaunchKernelGGL(fwd_gemm_f32_kernel<kFwdNP>, dim3(nblk), dim3(256), lds, s, a);
+    UFSS_HIP(hipGetLastError());
+}
+
+void launch_adjoint_gemm(const Plan& P, cf32* out, hipStream_t s) {
+    AdjArgs a{};
+    a.r = static_cast<const cf32*>(P.d_rop);
+    a.out = out;
+    a.u = P.d_u;
+    a.kb = P.d_ubins;
+    a.nx = P.g.nx;
+    a.ny = P.g.ny;
+    a.nz = P.g.nz;
+    a.wx = P.d.wx;
+    a.wy = P.d.wy;
+    a.mu = (int)P.ubins_h.size();
+    a.sw = sub_width(P);
+    const int tpx = a.sw * kAdjNP, tpy = 16 / a.sw;
+    a.ntx = (a.nx + tpx - 1) / tpx;
+    a.nty = (a.ny + tpy - 1) / tpy;
+    const int zspan = 64 * kAdjNZ;
+    a.nzt = (a.nz + zspan - 1) / zspan;
+    const int hc = tpx + 2 * a.wx;
+    int kc = 16;
+    auto lds_of = [&](int k) {
+        return (size_t)tpy * hc * (k + 1) * sizeof(cf32) + (size_t)(a.wx + 1) * zspan * 4 +
+               (size_t)k * 4;
+    };
+    while (kc > 4 && lds_of(kc) > kLdsMax) kc -= 4;
+    if (lds_of(kc) > kLdsMax) fail(UFSS_ERR_UNSUPPORTED, "aperture window too wide for the GEMM path");
+    a.kc = kc;
+    const int nblk = a.ntx * a.nty * a.nzt;
+    hipLaunchKernelGGL((adj_gemm_f32_kernel<kAdjNP, kAdjNZ>), dim3(nblk), dim3(256), lds_of(kc), s, a);
+    UFSS_HIP(hipGetLastError());
+}
+
+}  // namespace ufss

@@ -1,0 +1,123 @@
+// Internal declarations of libufss (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ufss.h"
+
+namespace ufss {
+
+// Error handling: C-ABI entry points catch ufss::Error and return its code.
+struct Error {
+    int code;
+    std::string msg;
+};
+[[noreturn]] void fail(int code, const std::string& msg);
+void check_hip(hipError_t e, const char* what);
+#define UFSS_HIP(call) ::ufss::check_hip((call), #call)
+void set_last_error(const std::string& msg);
+
+// Complex value as stored in device memory (interleaved re, im).
+struct cf32 {
+    float re, im;
+};
+
+// Complex BF16 (round-to-nearest-even from FP32), used by BF16 plans.
+struct cbf16 {
+    __bf16 re, im;
+};
+__host__ __device__ inline cbf16 to_cbf16(float re, float im) {
+    return cbf16{(__bf16)re, (__bf16)im};
+}
+
+// Host-side derived geometry, computed in FP64.
+struct Derived {
+    int wx = 0, wy = 0;                 // effective aperture half-widths
+    double t0 = 0, sigma_f = 0, sigma_t = 0;
+    int band_lo = 0, band_hi = -1;      // inclusive bin range of the band
+    std::vector<int> band;              // ascending band bins
+};
+Derived derive(const ufss_geom& g);
+double pulse_spectrum(const ufss_geom& g, const Derived& d, int k);
+
+// Launch description of the operator kernels.  Everything a kernel needs is in
+// these POD structs, passed by value.
+struct OpDims {
+    int nx, ny, nz;
+    int wx, wy;         // window half-widths
+    int mu;             // number of bins the GEMM runs over (M or union size)
+};
+
+// Plan: owns device tables and workspace.
+struct Plan {
+    ufss_geom g{};
+    Derived d;
+    int m = 0, per_position = 0, algo = 0, dtype = 0;
+    int npos = 0;
+    int64_t nvox = 0;
+    int fwd_split = 1;             // split of the forward GEMM's d_y range
+    std::vector<int> bins_h;       // [m] or [npos*m]
+    std::vector<int> ubins_h;      // union of bins (GEMM path), ascending
+    // device tables
+    int* d_bins = nullptr;         // selected bins [m] or [npos*m]
+    int* d_ubins = nullptr;        // union bins [mu]
+    int* d_map = nullptr;          // per (p, m): index into the union list
+    float* d_hsel = nullptr;       // H_k per selection entry [m] or [npos*m]
+    uint32_t* d_u = nullptr;       // integer-turn delay table [wy+1][wx+1][nz]
+    // device workspace
+    cf32* d_yraw = nullptr;        // GEMM output over union bins [npos][mu]
+    void* d_rop = nullptr;         // adjoint operand (H-scaled), [npos][mu] f32 or bf16
+    void* d_xop = nullptr;         // forward operand in BF16 [nvox] (BF16 plans)
+    double* d_part = nullptr;      // FP64 block partials
+    int part_cap = 0;
+    double* d_scalars = nullptr;   // small FP64 results
+    cf32* d_r = nullptr;           // residual [npos*m]
+    cf32* d_g = nullptr;           // gradient [nvox]
+    cf32* d_gamma = nullptr;       // FISTA extrapolated point [nvox]
+    cf32* d_v = nullptr;           // power-iteration vector [nvox]
+    double* d_stats = nullptr;     // FISTA per-iteration statistics
+    int stats_cap = 0;
+    double lipschitz = 0.0;
+    int64_t ws_bytes = 0;
+    hipStream_t cap_stream = nullptr;
+};
+
+// Kernel launchers (kernels_*.hip).  All asynchronous on `s`.
+void launch_forward_gemm(const Plan& P, const cf32* x, hipStream_t s);   // -> P.d_yraw
+void launch_adjoint_gemm(const Plan& P, cf32* out, hipStream_t s);       // P.d_rop -> out
+void launch_forward_phasor(const Plan& P, const cf32* x, cf32* y, const cf32* ymeas,
+                           double* part, hipStream_t s);
+void launch_adjoint_phasor(const Plan& P, cf32* out, hipStream_t s);     // P.d_rop -> out
+// y[p][m] = H * yraw[p][map(p,m)] (- ymeas), FP64 partial sums of |y|^2 per block.
+int launch_forward_post(const Plan& P, cf32* y, const cf32* ymeas, double* part, hipStream_t s);
+// rop[p][j] = sum over m with map(p,m) = j of H * r[p][m] (zero elsewhere).
+void launch_adjoint_pre(const Plan& P, const cf32* r, hipStream_t s);
+void launch_to_bf16(const cf32* x, void* out, int64_t n, hipStream_t s);
+int gemm_split(const Plan& P);
+
+// Vector kernels.
+int launch_update(int64_t n, cf32* gamma, const cf32* g, cf32* a, float step, float thresh,
+                  float beta, const cf32* aref, double* part, hipStream_t s);
+// Sums nblk partial blocks of `width` doubles in fixed order into out[width].
+void launch_reduce(const double* part, int nblk, int width, double* out, hipStream_t s);
+int launch_absmax(int64_t n, const cf32* x, double* part, hipStream_t s);
+void launch_reduce_max(const double* part, int nblk, double* out, hipStream_t s);
+int launch_norm2(int64_t n, const cf32* x, double* part, hipStream_t s);
+void launch_scale(int64_t n, cf32* x, const double* norm2, hipStream_t s);   // x /= sqrt(norm2)
+void launch_copy(int64_t n, const cf32* src, cf32* dst, hipStream_t s);
+void launch_fista_stats(double* stats, int k, const double* upd, const double* res2,
+                        const double* g1_prev, double lam, int have_ref, double ref2,
+                        hipStream_t s);
+
+int max_blocks_vec();
+
+// Operator drivers (operator.cpp).
+void op_forward(Plan& P, const cf32* x, cf32* y, const cf32* ymeas, double* res2_out,
+                hipStream_t s);
+void op_adjoint(Plan& P, const cf32* y, cf32* x, hipStream_t s);
+
+}  // namespace ufss

@@ -1,0 +1,171 @@
+// Per-position frequency subsets: on-the-fly phasor path (FP32, VALU).
+//
+// When every A-scan keeps its own bins (the "f" strategies of the paper's
+// Table I, Sec. III-A) the phase matrix differs per position, so the GEMM
+// structure is lost; each term is generated where it is used:
+//
+//   forward  y[p, m] = H_{k_m(p)} sum_{v in W(p)} sum_z exp(-j 2 pi k_m(p) u(p - v, z)) x[v, z]
+//   adjoint  x[v, z] = sum_{p in W(v)} sum_m exp(+j 2 pi k_m(p) u(p - v, z)) R[p, m]
+//
+// with R = H r prepared by the adjoint pre pass.  Forward: one workgroup per
+// (position, group of 32 bins); lanes stride the (voxel, depth) terms of the
+// window with depth-contiguous, coalesced loads of x and of the delay table,
+// the 32 bins are wave-uniform scalars, and the per-lane sums are reduced
+// across the wavefront with shuffles and across waves in LDS.  Adjoint: one
+// workgroup per (voxel column, 256 depths); each lane owns one depth, so no
+// cross-lane reduction is needed, and the bins and operands of each position
+// are wave-uniform scalar loads.
+#include "internal.h"
+
+namespace ufss {
+
+static constexpr float kTwoM32 = 2.3283064365386963e-10f;
+
+__device__ __forceinline__ void phasor_p(uint32_t ku, float& c, float& s) {
+    float ph = (float)(int32_t)ku * kTwoM32;
+    c = __builtin_amdgcn_cosf(ph);
+    s = __builtin_amdgcn_sinf(ph);
+}
+
+static constexpr int kMB = 32;   // bins per forward workgroup
+
+__global__ __launch_bounds__(256) void fwd_phasor_kernel(
+    const cf32* __restrict__ x, const uint32_t* __restrict__ ut, const int* __restrict__ bins,
+    const float* __restrict__ hsel, const cf32* __restrict__ ymeas, cf32* __restrict__ y,
+    double* __restrict__ part, int nx, int ny, int nz, int wx, int wy, int m, int ngroups) {
+    __shared__ float red[2 * kMB][4];
+    const int p = blockIdx.x / ngroups, grp = blockIdx.x - p * ngroups;
+    const int px = p % nx, py = p / nx;
+    const int mb0 = grp * kMB;
+    uint32_t kb[kMB];
+#pragma unroll
+    for (int j = 0; j < kMB; ++j) kb[j] = (mb0 + j < m) ? (uint32_t)bins[(int64_t)p * m + mb0 + j] : 0u;
+
+    const int vx_lo = max(px - wx, 0), vx_hi = min(px + wx, nx - 1);
+    const int vy_lo = max(py - wy, 0), vy_hi = min(py + wy, ny - 1);
+    const int nvx = vx_hi - vx_lo + 1;
+    const int64_t total = (int64_t)nvx * (vy_hi - vy_lo + 1) * nz;
+
+    float acc_re[kMB], acc_im[kMB];
+#pragma unroll
+    for (int j = 0; j < kMB; ++j) acc_re[j] = acc_im[j] = 0.f;
+
+    // walk t = w * nz + z with w the window column index; update (w, z) incrementally
+    int64_t t = threadIdx.x;
+    int w = (int)(t / nz), z = (int)(t - (int64_t)w * nz);
+    for (; t < total; t += 256) {
+        const int vx = vx_lo + w % nvx, vy = vy_lo + w / nvx;
+        const cf32 xv = x[((int64_t)vy * nx + vx) * nz + z];
+        const int adx = px > vx ? px - vx : vx - px, ady = py > vy ? py - vy : vy - py;
+        const uint32_t u = ut[((int64_t)ady * (wx + 1) + adx) * nz + z];
+#pragma unroll
+        for (int j = 0; j < kMB; ++j) {
+            float c, s;
+            phasor_p(kb[j] * u, c, s);
+            // (xr + j xi)(c - j s)
+            acc_re[j] += xv.re * c + xv.im * s;
+            acc_im[j] += xv.im * c - xv.re * s;
+        }
+        z += 256;
+        while (z >= nz) {
+            z -= nz;
+            ++w;
+        }
+    }
+    // reduce over the block
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < kMB; ++j) {
+        float a = acc_re[j], b = acc_im[j];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            a += __shfl_xor(a, off, 64);
+            b += __shfl_xor(b, off, 64);
+        }
+        if (lane == 0) {
+            red[2 * j][wave] = a;
+            red[2 * j + 1][wave] = b;
+        }
+    }
+    __syncthreads();
+    double r2 = 0.0;
+    if (threadIdx.x < kMB) {
+        const int j = threadIdx.x, mi = mb0 + j;
+        if (mi < m) {
+            float re = (red[2 * j][0] + red[2 * j][1]) + (red[2 * j][2] + red[2 * j][3]);
+            float im = (red[2 * j + 1][0] + red[2 * j + 1][1]) + (red[2 * j + 1][2] + red[2 * j + 1][3]);
+            const int64_t o = (int64_t)p * m + mi;
+            const float h = hsel[o];
+            re *= h;
+            im *= h;
+            if (ymeas) {
+                re -= ymeas[o].re;
+                im -= ymeas[o].im;
+            }
+            y[o] = cf32{re, im};
+            r2 = (double)re * re + (double)im * im;
+        }
+    }
+    // partial |y|^2 of this block (threads >= kMB contribute 0); fixed order
+    if (threadIdx.x < 64) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) r2 += __shfl_xor(r2, off, 64);
+        if (threadIdx.x == 0) part[blockIdx.x] = r2;
+    }
+}
+
+void launch_forward_phasor(const Plan& P, const cf32* x, cf32* y, const cf32* ymeas,
+                           double* part, hipStream_t s) {
+    const int ngroups = (P.m + kMB - 1) / kMB;
+    const int nblk = P.npos * ngroups;
+    if (nblk > P.part_cap) fail(UFSS_ERR_UNSUPPORTED, "too many positions for the phasor path");
+    hipLaunchKernelGGL(fwd_phasor_kernel, dim3(nblk), dim3(256), 0, s, x, P.d_u, P.d_bins,
+                       P.d_hsel, ymeas, y, part, P.g.nx, P.g.ny, P.g.nz, P.d.wx, P.d.wy, P.m,
+                       ngroups);
+    UFSS_HIP(hipGetLastError());
+}
+
+int phasor_forward_blocks(const Plan& P) { return P.npos * ((P.m + kMB - 1) / kMB); }
+
+__global__ __launch_bounds__(256) void adj_phasor_kernel(
+    const cf32* __restrict__ rop, const uint32_t* __restrict__ ut, const int* __restrict__ bins,
+    cf32* __restrict__ out, int nx, int ny, int nz, int wx, int wy, int m, int nzc) {
+    const int v = blockIdx.x / nzc, zc = blockIdx.x - v * nzc;
+    const int vx = v % nx, vy = v / nx;
+    const int z = zc * 256 + threadIdx.x;
+    const int zl = z < nz ? z : nz - 1;      // clamp for loads; store is guarded
+    const int px_lo = max(vx - wx, 0), px_hi = min(vx + wx, nx - 1);
+    const int py_lo = max(vy - wy, 0), py_hi = min(vy + wy, ny - 1);
+    float acc_re = 0.f, acc_im = 0.f;
+    for (int py = py_lo; py <= py_hi; ++py) {
+        const int ady = py > vy ? py - vy : vy - py;
+        for (int px = px_lo; px <= px_hi; ++px) {
+            const int adx = px > vx ? px - vx : vx - px;
+            const uint32_t u = ut[((int64_t)ady * (wx + 1) + adx) * nz + zl];
+            const int64_t prow = ((int64_t)py * nx + px) * m;
+            float in_re = 0.f, in_im = 0.f;
+            for (int mi = 0; mi < m; ++mi) {
+                const uint32_t k = (uint32_t)bins[prow + mi];
+                const cf32 rv = rop[prow + mi];
+                float c, s;
+                phasor_p(k * u, c, s);
+                // (rr + j ri)(c + j s)
+                in_re += rv.re * c - rv.im * s;
+                in_im += rv.re * s + rv.im * c;
+            }
+            acc_re += in_re;
+            acc_im += in_im;
+        }
+    }
+    if (z < nz) out[(int64_t)v * nz + z] = cf32{acc_re, acc_im};
+}
+
+void launch_adjoint_phasor(const Plan& P, cf32* out, hipStream_t s) {
+    const int nzc = (P.g.nz + 255) / 256;
+    hipLaunchKernelGGL(adj_phasor_kernel, dim3(P.npos * nzc), dim3(256), 0, s,
+                       static_cast<const cf32*>(P.d_rop), P.d_u, P.d_bins, out, P.g.nx, P.g.ny,
+                       P.g.nz, P.d.wx, P.d.wy, P.m, nzc);
+    UFSS_HIP(hipGetLastError());
+}
+
+}  // namespace ufss

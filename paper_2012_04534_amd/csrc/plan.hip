@@ -1,0 +1,287 @@
+// Plan construction: derived geometry (FP64, host), bin selection, the
+// integer-turn delay table and device workspace.
+//
+// Paper sources: Sec. II-A (delay tau, grids, frequency-domain A-scan model),
+// Sec. III-A (random bin subsets, shared or per A-scan), Sec. IV-B (block
+// 2-level Toeplitz structure: A depends on the lateral offset p - v only, so one
+// table indexed by (|d_x|, |d_y|, z) serves every position).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace ufss {
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+const char* last_error() { return g_last_error.c_str(); }
+
+void fail(int code, const std::string& msg) { throw Error{code, msg}; }
+
+void check_hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return;
+    int code = (e == hipErrorOutOfMemory) ? UFSS_ERR_OOM : UFSS_ERR_HIP;
+    fail(code, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// Derived geometry.  Pulse: complex Gabor with -6 dB fractional bandwidth
+// frac_bw, so sigma_f = frac_bw f_c / (2 sqrt(2 ln 2)) and sigma_t = 1/(2 pi
+// sigma_f); its sampled echo has DFT H_k exp(-j 2 pi f_k (tau - t0)) with H_k as
+// in ufss.h.  Band: bins 0..nt/2 whose Gaussian envelope is within band_db of
+// the peak.  Window start: centre of the aperture's delay span.
+// ---------------------------------------------------------------------------
+static double delay(const ufss_geom& g, double ddx, double ddy, double z) {
+    return (2.0 / g.c) * std::sqrt(ddx * ddx + ddy * ddy + z * z);
+}
+
+Derived derive(const ufss_geom& g) {
+    Derived d;
+    d.wx = g.win_x < 0 ? g.nx - 1 : std::min(g.win_x, g.nx - 1);
+    d.wy = g.win_y < 0 ? g.ny - 1 : std::min(g.win_y, g.ny - 1);
+    d.sigma_f = g.frac_bw * g.fc / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+    d.sigma_t = 1.0 / (2.0 * M_PI * d.sigma_f);
+    if (std::isnan(g.t0)) {
+        double tmin = delay(g, 0.0, 0.0, g.z_start);
+        double tmax = delay(g, d.wx * g.dx, d.wy * g.dy, g.z_start + (g.nz - 1) * g.dz);
+        d.t0 = 0.5 * (tmin + tmax) - g.nt / (2.0 * g.fs);
+    } else {
+        d.t0 = g.t0;
+    }
+    double floor_amp = std::pow(10.0, -g.band_db / 20.0);
+    for (int k = 0; k <= g.nt / 2; ++k) {
+        double f = (double)k * g.fs / g.nt;
+        double env = std::exp(-(f - g.fc) * (f - g.fc) / (2.0 * d.sigma_f * d.sigma_f));
+        if (env >= floor_amp) d.band.push_back(k);
+    }
+    if (!d.band.empty()) {
+        d.band_lo = d.band.front();
+        d.band_hi = d.band.back();
+    }
+    return d;
+}
+
+double pulse_spectrum(const ufss_geom& g, const Derived& d, int k) {
+    double f = (double)k * g.fs / g.nt;
+    return g.fs * std::sqrt(2.0 * M_PI) * d.sigma_t *
+           std::exp(-(f - g.fc) * (f - g.fc) / (2.0 * d.sigma_f * d.sigma_f));
+}
+
+static void validate_geom(const ufss_geom* g) {
+    if (!g) fail(UFSS_ERR_INVALID_ARG, "geometry pointer is NULL");
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1 || g->nt < 2)
+        fail(UFSS_ERR_INVALID_ARG, "grid sizes must be positive (nt >= 2)");
+    if ((int64_t)g->nx * g->ny > (1 << 24) || g->nz > (1 << 16) || g->nt > (1 << 20))
+        fail(UFSS_ERR_INVALID_ARG, "grid too large");
+    if (!(g->dx > 0) || !(g->dy > 0) || !(g->dz > 0) || !(g->c > 0) || !(g->fs > 0) ||
+        !(g->fc > 0) || !(g->frac_bw > 0) || !(g->band_db > 0) || !(g->z_start >= 0))
+        fail(UFSS_ERR_INVALID_ARG, "physical parameters must be positive");
+    if (g->dtype != UFSS_F32 && g->dtype != UFSS_BF16)
+        fail(UFSS_ERR_INVALID_ARG, "dtype must be UFSS_F32 or UFSS_BF16");
+    if (g->algo < UFSS_ALGO_AUTO || g->algo > UFSS_ALGO_PHASOR)
+        fail(UFSS_ERR_INVALID_ARG, "unknown algo");
+}
+
+// ---------------------------------------------------------------------------
+// SplitMix64 (Steele, Lea & Flood 2014) and the seeded subset draw.
+// ---------------------------------------------------------------------------
+static inline uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+struct SplitMix64 {
+    uint64_t s;
+    explicit SplitMix64(uint64_t seed) : s(seed) {}
+    uint64_t next() {
+        s += 0x9E3779B97F4A7C15ull;
+        return mix64(s);
+    }
+};
+
+static void draw(const std::vector<int>& band, int m, uint64_t key, int32_t* out) {
+    std::vector<int> pool(band);
+    const uint64_t n = pool.size();
+    SplitMix64 rng(key);
+    for (int i = 0; i < m; ++i) {
+        uint64_t span = n - (uint64_t)i;
+        uint64_t j = (uint64_t)i + (uint64_t)(((unsigned __int128)rng.next() * span) >> 64);
+        std::swap(pool[i], pool[j]);
+    }
+    std::sort(pool.begin(), pool.begin() + m);
+    for (int i = 0; i < m; ++i) out[i] = pool[i];
+}
+
+void select_freqs(const ufss_geom* g, int m, int per_position, uint64_t seed, int32_t* out,
+                  int32_t* band_size) {
+    validate_geom(g);
+    if (!out) fail(UFSS_ERR_INVALID_ARG, "bins_out is NULL");
+    if (m < 1) fail(UFSS_ERR_INVALID_ARG, "m must be >= 1");
+    Derived d = derive(*g);
+    if (band_size) *band_size = (int32_t)d.band.size();
+    if ((size_t)m > d.band.size())
+        fail(UFSS_ERR_BAND_TOO_SMALL, "m = " + std::to_string(m) + " exceeds the band size " +
+                                          std::to_string(d.band.size()));
+    if (!per_position) {
+        draw(d.band, m, seed, out);
+        return;
+    }
+    for (int iy = 0; iy < g->ny; ++iy)
+        for (int ix = 0; ix < g->nx; ++ix) {
+            int64_t p = ix + (int64_t)g->nx * iy;
+            draw(d.band, m, seed ^ mix64((uint64_t)p + 1), out + p * m);
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Plan.
+// ---------------------------------------------------------------------------
+template <class T>
+static T* dalloc(Plan& P, size_t count) {
+    if (count == 0) count = 1;
+    void* p = nullptr;
+    UFSS_HIP(hipMalloc(&p, count * sizeof(T)));
+    P.ws_bytes += count * sizeof(T);
+    return static_cast<T*>(p);
+}
+
+template <class T>
+static void upload(T* dst, const T* src, size_t count) {
+    UFSS_HIP(hipMemcpy(dst, src, count * sizeof(T), hipMemcpyHostToDevice));
+}
+
+static void free_plan(Plan* P) {
+    if (!P) return;
+    void* ptrs[] = {P->d_bins, P->d_ubins, P->d_map, P->d_hsel, P->d_u, P->d_yraw,
+                    P->d_rop, P->d_xop, P->d_part, P->d_scalars, P->d_r, P->d_g,
+                    P->d_gamma, P->d_v, P->d_stats};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
+    delete P;
+}
+
+Plan* plan_create(const ufss_geom* g, int m, int per_position, const int32_t* bins) {
+    validate_geom(g);
+    if (!bins) fail(UFSS_ERR_INVALID_ARG, "bins is NULL");
+    if (m < 1 || m > 4096) fail(UFSS_ERR_INVALID_ARG, "m must be in [1, 4096]");
+    Derived d = derive(*g);
+    const int npos = g->nx * g->ny;
+    const int64_t nsel = per_position ? (int64_t)npos * m : m;
+    // validate bins: strictly ascending inside [0, nt/2]
+    const int nrows = per_position ? npos : 1;
+    for (int r = 0; r < nrows; ++r) {
+        const int32_t* b = bins + (int64_t)r * m;
+        for (int i = 0; i < m; ++i) {
+            if (b[i] < 0 || b[i] > g->nt / 2)
+                fail(UFSS_ERR_INVALID_ARG, "bin index outside [0, nt/2]");
+            if (i > 0 && b[i] <= b[i - 1])
+                fail(UFSS_ERR_INVALID_ARG, "bins of a position must be strictly ascending");
+        }
+    }
+    int algo = g->algo;
+    if (algo == UFSS_ALGO_AUTO) algo = UFSS_ALGO_GEMM;
+    if (algo == UFSS_ALGO_PHASOR && g->dtype == UFSS_BF16)
+        fail(UFSS_ERR_UNSUPPORTED, "the phasor path is FP32 only");
+    if (algo == UFSS_ALGO_PHASOR && !per_position) algo = UFSS_ALGO_GEMM;
+
+    Plan* P = new (std::nothrow) Plan();
+    if (!P) fail(UFSS_ERR_OOM, "host allocation failed");
+    try {
+        P->g = *g;
+        P->d = d;
+        P->m = m;
+        P->per_position = per_position ? 1 : 0;
+        P->algo = algo;
+        P->dtype = g->dtype;
+        P->npos = npos;
+        P->nvox = (int64_t)npos * g->nz;
+        P->bins_h.assign(bins, bins + nsel);
+        // union of bins (GEMM path over per-position subsets)
+        std::vector<int> u(P->bins_h);
+        std::sort(u.begin(), u.end());
+        u.erase(std::unique(u.begin(), u.end()), u.end());
+        P->ubins_h = u;
+        const int mu = (int)u.size();
+        const int opw = (algo == UFSS_ALGO_PHASOR) ? m : mu;   // operand row width
+        std::vector<int> map(nsel);
+        std::vector<float> hsel(nsel);
+        for (int64_t i = 0; i < nsel; ++i) {
+            int k = P->bins_h[i];
+            map[i] = (algo == UFSS_ALGO_PHASOR)
+                         ? (int)(i % m)
+                         : (int)(std::lower_bound(u.begin(), u.end(), k) - u.begin());
+            hsel[i] = (float)pulse_spectrum(*g, d, k);
+        }
+        // integer-turn delay table: u(|dx|, |dy|, z) = round(2^32 frac((tau - t0) fs / nt))
+        const int wx = d.wx, wy = d.wy;
+        std::vector<uint32_t> ut((size_t)(wy + 1) * (wx + 1) * g->nz);
+        for (int j = 0; j <= wy; ++j)
+            for (int i = 0; i <= wx; ++i)
+                for (int z = 0; z < g->nz; ++z) {
+                    double t = delay(*g, i * g->dx, j * g->dy, g->z_start + z * g->dz);
+                    double ph = (t - d.t0) * g->fs / g->nt;
+                    double fr = ph - std::floor(ph);
+                    double q = std::nearbyint(fr * 4294967296.0);
+                    uint64_t qi = (uint64_t)q & 0xFFFFFFFFull;
+                    ut[((size_t)j * (wx + 1) + i) * g->nz + z] = (uint32_t)qi;
+                }
+        P->d_bins = dalloc<int>(*P, nsel);
+        upload(P->d_bins, P->bins_h.data(), nsel);
+        P->d_ubins = dalloc<int>(*P, mu);
+        upload(P->d_ubins, u.data(), mu);
+        P->d_map = dalloc<int>(*P, nsel);
+        upload(P->d_map, map.data(), nsel);
+        P->d_hsel = dalloc<float>(*P, nsel);
+        upload(P->d_hsel, hsel.data(), nsel);
+        P->d_u = dalloc<uint32_t>(*P, ut.size());
+        upload(P->d_u, ut.data(), ut.size());
+        P->fwd_split = (algo == UFSS_ALGO_GEMM) ? gemm_split(*P) : 1;
+        P->d_yraw = dalloc<cf32>(*P, (size_t)P->fwd_split * npos * mu);
+        P->d_rop = dalloc<cf32>(*P, (size_t)npos * opw);
+        if (P->dtype == UFSS_BF16) P->d_xop = dalloc<cf32>(*P, (size_t)(P->nvox + 1) / 2 + 1);
+        P->part_cap = 65536;
+        P->d_part = dalloc<double>(*P, P->part_cap);
+        P->d_scalars = dalloc<double>(*P, 64);
+        P->d_r = dalloc<cf32>(*P, (size_t)npos * m);
+        P->d_g = dalloc<cf32>(*P, P->nvox);
+        P->d_gamma = dalloc<cf32>(*P, P->nvox);
+        P->d_v = dalloc<cf32>(*P, P->nvox);
+        UFSS_HIP(hipMemset(P->d_scalars, 0, 64 * sizeof(double)));
+        UFSS_HIP(hipDeviceSynchronize());
+    } catch (...) {
+        free_plan(P);
+        throw;
+    }
+    return P;
+}
+
+void plan_destroy(Plan* P) {
+    if (!P) fail(UFSS_ERR_INVALID_ARG, "plan is NULL");
+    UFSS_HIP(hipDeviceSynchronize());
+    free_plan(P);
+}
+
+void plan_info(const Plan* P, ufss_plan_info* info) {
+    if (!P || !info) fail(UFSS_ERR_INVALID_ARG, "NULL argument");
+    std::memset(info, 0, sizeof(*info));
+    info->t0 = P->d.t0;
+    info->lipschitz = P->lipschitz;
+    info->band_lo = P->d.band_lo;
+    info->band_hi = P->d.band_hi;
+    info->band_size = (int32_t)P->d.band.size();
+    info->win_x = P->d.wx;
+    info->win_y = P->d.wy;
+    info->m = P->m;
+    info->per_position = P->per_position;
+    info->dtype = P->dtype;
+    info->algo = P->algo;
+    info->union_size = (int32_t)P->ubins_h.size();
+    info->workspace_bytes = P->ws_bytes;
+}
+
+}  // namespace ufss

@@ -1,0 +1,340 @@
+// Elementwise and reduction kernels: the operator's pre/post passes, the fused
+// FISTA update, and FP64 block reductions.
+//
+// All reductions are deterministic: a fixed grid of at most kMaxBlocks blocks
+// walks the data in a fixed order, each block writes FP64 partials to its own
+// slot, and a single-block kernel sums the slots in a fixed order.  No float
+// atomics anywhere, so results are bitwise reproducible run to run.
+#include "internal.h"
+
+namespace ufss {
+
+static constexpr int kThreads = 256;
+static constexpr int kMaxBlocks = 1024;
+
+int max_blocks_vec() { return kMaxBlocks; }
+
+static int blocks_for(int64_t n) {
+    int64_t b = (n + kThreads - 1) / kThreads;
+    if (b < 1) b = 1;
+    return (int)(b > kMaxBlocks ? kMaxBlocks : b);
+}
+
+// Block-wide FP64 sum of W values per thread; thread 0 writes part[blk*W + w].
+template <int W>
+__device__ void block_sum_write(double (&v)[W], double* part) {
+    __shared__ double red[W][kThreads / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        double x = v[w];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) red[w][wave] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            double s = 0.0;
+            for (int i = 0; i < kThreads / 64; ++i) s += red[w][i];
+            part[(int64_t)blockIdx.x * W + w] = s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Forward post pass: y[p][m] = H_sel * sum_s yraw[s][p][map(p, m)] (- ymeas),
+// plus FP64 partials of ||y||^2.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void fwd_post_kernel(
+    const cf32* __restrict__ yraw, int split, int64_t npos, int mu, int m, int per_pos,
+    const int* __restrict__ map, const float* __restrict__ hsel, const cf32* __restrict__ ymeas,
+    cf32* __restrict__ y, double* __restrict__ part) {
+    double acc[1] = {0.0};
+    const int64_t n = npos * m;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads) {
+        int64_t p = i / m;
+        int mi = (int)(i - p * m);
+        int64_t sel = per_pos ? i : mi;
+        int j = map[sel];
+        float h = hsel[sel];
+        float re = 0.f, im = 0.f;
+        for (int s = 0; s < split; ++s) {
+            cf32 v = yraw[((int64_t)s * npos + p) * mu + j];
+            re += v.re;
+            im += v.im;
+        }
+        re *= h;
+        im *= h;
+        if (ymeas) {
+            cf32 q = ymeas[i];
+            re -= q.re;
+            im -= q.im;
+        }
+        y[i] = cf32{re, im};
+        acc[0] += (double)re * re + (double)im * im;
+    }
+    block_sum_write<1>(acc, part);
+}
+
+int launch_forward_post(const Plan& P, cf32* y, const cf32* ymeas, double* part, hipStream_t s) {
+    const int64_t n = (int64_t)P.npos * P.m;
+    const int nb = blocks_for(n);
+    hipLaunchKernelGGL(fwd_post_kernel, dim3(nb), dim3(kThreads), 0, s, P.d_yraw, P.fwd_split,
+                       (int64_t)P.npos, (int)P.ubins_h.size(), P.m, P.per_position, P.d_map,
+                       P.d_hsel, ymeas, y, part);
+    UFSS_HIP(hipGetLastError());
+    return nb;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint pre pass: one block per scan position writes the row
+// rop[p][0..w) = 0 except rop[p][map(p, m)] = H_sel * r[p][m].
+// ---------------------------------------------------------------------------
+template <bool BF16>
+__global__ __launch_bounds__(128) void adj_pre_kernel(const cf32* __restrict__ r, int m, int w,
+                                                      int per_pos, const int* __restrict__ map,
+                                                      const float* __restrict__ hsel,
+                                                      void* __restrict__ rop) {
+    const int64_t p = blockIdx.x;
+    if (BF16) {
+        cbf16* row = static_cast<cbf16*>(rop) + p * w;
+        for (int j = threadIdx.x; j < w; j += blockDim.x) row[j] = to_cbf16(0.f, 0.f);
+        __syncthreads();
+        for (int mi = threadIdx.x; mi < m; mi += blockDim.x) {
+            int64_t sel = per_pos ? p * m + mi : mi;
+            cf32 v = r[p * m + mi];
+            float h = hsel[sel];
+            row[map[sel]] = to_cbf16(h * v.re, h * v.im);
+        }
+    } else {
+        cf32* row = static_cast<cf32*>(rop) + p * w;
+        for (int j = threadIdx.x; j < w; j += blockDim.x) row[j] = cf32{0.f, 0.f};
+        __syncthreads();
+        for (int mi = threadIdx.x; mi < m; mi += blockDim.x) {
+            int64_t sel = per_pos ? p * m + mi : mi;
+            cf32 v = r[p * m + mi];
+            float h = hsel[sel];
+            row[map[sel]] = cf32{h * v.re, h * v.im};
+        }
+    }
+}
+
+void launch_adjoint_pre(const Plan& P, const cf32* r, hipStream_t s) {
+    const int w = (P.algo == UFSS_ALGO_PHASOR) ? P.m : (int)P.ubins_h.size();
+    if (P.dtype == UFSS_BF16)
+        hipLaunchKernelGGL(adj_pre_kernel<true>, dim3(P.npos), dim3(128), 0, s, r, P.m, w,
+                           P.per_position, P.d_map, P.d_hsel, P.d_rop);
+    else
+        hipLaunchKernelGGL(adj_pre_kernel<false>, dim3(P.npos), dim3(128), 0, s, r, P.m, w,
+                           P.per_position, P.d_map, P.d_hsel, P.d_rop);
+    UFSS_HIP(hipGetLastError());
+}
+
+__global__ __launch_bounds__(kThreads) void to_bf16_kernel(const cf32* __restrict__ x,
+                                                           cbf16* __restrict__ out,
+                                                           int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads) {
+        cf32 v = x[i];
+        out[i] = to_cbf16(v.re, v.im);
+    }
+}
+
+void launch_to_bf16(const cf32* x, void* out, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks_for(n)), dim3(kThreads), 0, s, x,
+                       static_cast<cbf16*>(out), n);
+    UFSS_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Fused proximal-gradient update (FISTA / ISTA step), in place:
+//   z = gamma - step g;  a_new = z max(0, 1 - thresh/|z|);
+//   gamma <- a_new + beta (a_new - a);  a <- a_new.
+// Partials: ||a_new||_1, ||gamma_new||_1, ||a_new - a||^2, ||a_new||^2,
+// ||a_new - a_ref||^2.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void update_kernel(int64_t n, cf32* __restrict__ gamma,
+                                                          const cf32* __restrict__ g,
+                                                          cf32* __restrict__ a, float step,
+                                                          float thresh, float beta,
+                                                          const cf32* __restrict__ aref,
+                                                          double* __restrict__ part) {
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads) {
+        cf32 gm = gamma[i], gg = g[i], aa = a[i];
+        float zr = gm.re - step * gg.re, zi = gm.im - step * gg.im;
+        float mag = sqrtf(zr * zr + zi * zi);
+        float sc = mag > thresh ? 1.0f - thresh / mag : 0.0f;
+        float ar = zr * sc, ai = zi * sc;
+        float gr = ar + beta * (ar - aa.re), gi = ai + beta * (ai - aa.im);
+        a[i] = cf32{ar, ai};
+        gamma[i] = cf32{gr, gi};
+        double dr = (double)ar - aa.re, di = (double)ai - aa.im;
+        acc[0] += sqrt((double)ar * ar + (double)ai * ai);
+        acc[1] += sqrt((double)gr * gr + (double)gi * gi);
+        acc[2] += dr * dr + di * di;
+        acc[3] += (double)ar * ar + (double)ai * ai;
+        if (aref) {
+            cf32 q = aref[i];
+            double er = (double)ar - q.re, ei = (double)ai - q.im;
+            acc[4] += er * er + ei * ei;
+        }
+    }
+    block_sum_write<5>(acc, part);
+}
+
+int launch_update(int64_t n, cf32* gamma, const cf32* g, cf32* a, float step, float thresh,
+                  float beta, const cf32* aref, double* part, hipStream_t s) {
+    const int nb = blocks_for(n);
+    hipLaunchKernelGGL(update_kernel, dim3(nb), dim3(kThreads), 0, s, n, gamma, g, a, step,
+                       thresh, beta, aref, part);
+    UFSS_HIP(hipGetLastError());
+    return nb;
+}
+
+// ---------------------------------------------------------------------------
+// Fixed-order reductions.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void reduce_kernel(const double* __restrict__ part,
+                                                          int nblk, int width,
+                                                          double* __restrict__ out) {
+    __shared__ double red[kThreads];
+    for (int w = 0; w < width; ++w) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += kThreads) s += part[(int64_t)b * width + w];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int off = kThreads / 2; off > 0; off >>= 1) {
+            if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[w] = red[0];
+        __syncthreads();
+    }
+}
+
+void launch_reduce(const double* part, int nblk, int width, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, s, part, nblk, width, out);
+    UFSS_HIP(hipGetLastError());
+}
+
+__global__ __launch_bounds__(kThreads) void absmax_kernel(int64_t n, const cf32* __restrict__ x,
+                                                          double* __restrict__ part) {
+    __shared__ double red[kThreads];
+    double mx = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads) {
+        cf32 v = x[i];
+        mx = fmax(mx, sqrt((double)v.re * v.re + (double)v.im * v.im));
+    }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int off = kThreads / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+int launch_absmax(int64_t n, const cf32* x, double* part, hipStream_t s) {
+    const int nb = blocks_for(n);
+    hipLaunchKernelGGL(absmax_kernel, dim3(nb), dim3(kThreads), 0, s, n, x, part);
+    UFSS_HIP(hipGetLastError());
+    return nb;
+}
+
+__global__ __launch_bounds__(kThreads) void reduce_max_kernel(const double* __restrict__ part,
+                                                              int nblk, double* __restrict__ out) {
+    __shared__ double red[kThreads];
+    double mx = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kThreads) mx = fmax(mx, part[b]);
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int off = kThreads / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+void launch_reduce_max(const double* part, int nblk, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_max_kernel, dim3(1), dim3(kThreads), 0, s, part, nblk, out);
+    UFSS_HIP(hipGetLastError());
+}
+
+// Partials of ||x||^2 and ||x||_1.
+__global__ __launch_bounds__(kThreads) void norm2_kernel(int64_t n, const cf32* __restrict__ x,
+                                                         double* __restrict__ part) {
+    double acc[2] = {0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads) {
+        cf32 v = x[i];
+        double q = (double)v.re * v.re + (double)v.im * v.im;
+        acc[0] += q;
+        acc[1] += sqrt(q);
+    }
+    block_sum_write<2>(acc, part);
+}
+
+int launch_norm2(int64_t n, const cf32* x, double* part, hipStream_t s) {
+    const int nb = blocks_for(n);
+    hipLaunchKernelGGL(norm2_kernel, dim3(nb), dim3(kThreads), 0, s, n, x, part);
+    UFSS_HIP(hipGetLastError());
+    return nb;
+}
+
+__global__ __launch_bounds__(kThreads) void scale_kernel(int64_t n, cf32* __restrict__ x,
+                                                         const double* __restrict__ norm2) {
+    const float inv = (float)(1.0 / sqrt(norm2[0]));
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads) {
+        cf32 v = x[i];
+        x[i] = cf32{v.re * inv, v.im * inv};
+    }
+}
+
+void launch_scale(int64_t n, cf32* x, const double* norm2, hipStream_t s) {
+    hipLaunchKernelGGL(scale_kernel, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, x, norm2);
+    UFSS_HIP(hipGetLastError());
+}
+
+__global__ __launch_bounds__(kThreads) void copy_kernel(int64_t n, const cf32* __restrict__ src,
+                                                        cf32* __restrict__ dst) {
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads)
+        dst[i] = src[i];
+}
+
+void launch_copy(int64_t n, const cf32* src, cf32* dst, hipStream_t s) {
+    hipLaunchKernelGGL(copy_kernel, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, src, dst);
+    UFSS_HIP(hipGetLastError());
+}
+
+// stats[k] = {1/2 res2 + lam g1, sqrt(res2), sqrt(dA2 / a2), sqrt(ref2diff / ref2)};
+// then g1 <- ||gamma_new||_1 for the next iteration.
+// upd = {l1a, l1g, dA2, a2, ref2diff}; res2 = ||A gamma_k - y||^2; g1 = ||gamma_k||_1.
+__global__ void fista_stats_kernel(double* stats, int k, const double* upd, const double* res2,
+                                   double* g1, double lam, int have_ref, double ref2) {
+    if (threadIdx.x != 0) return;
+    double r2 = res2[0];
+    double* s = stats + 4 * (int64_t)k;
+    s[0] = 0.5 * r2 + lam * g1[0];
+    s[1] = sqrt(r2);
+    s[2] = upd[3] > 0.0 ? sqrt(upd[2] / upd[3]) : 0.0;
+    s[3] = have_ref ? sqrt(upd[4] / ref2) : 0.0;
+    g1[0] = upd[1];
+}
+
+void launch_fista_stats(double* stats, int k, const double* upd, const double* res2,
+                        const double* g1_prev, double lam, int have_ref, double ref2,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(fista_stats_kernel, dim3(1), dim3(64), 0, s, stats, k, upd, res2,
+                       const_cast<double*>(g1_prev), lam, have_ref, ref2);
+    UFSS_HIP(hipGetLastError());
+}
+
+}  // namespace ufss

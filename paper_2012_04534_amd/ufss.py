@@ -1,0 +1,265 @@
+"""Thin ctypes binding of libufss (argument marshalling only).
+
+Every function forwards to the C ABI entry point of the same name declared in
+``include/ufss.h``; all computation happens in the HIP library.  Device
+buffers are torch tensors (complex64, contiguous, on the GPU): the binding
+passes their ``data_ptr()`` and the current HIP stream.  If the library is
+missing or fails to load, every call raises -- there is no fallback.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libufss.so")
+
+UFSS_OK = 0
+ERRORS = {
+    -1: "INVALID_ARG", -2: "BAND_TOO_SMALL", -3: "HIP", -4: "OOM",
+    -5: "UNSUPPORTED", -6: "DIVERGED",
+}
+F32, BF16 = 0, 1
+ALGO_AUTO, ALGO_GEMM, ALGO_PHASOR = 0, 1, 2
+
+EXPORTED = [
+    "ufss_last_error", "ufss_select_freqs", "ufss_plan_create", "ufss_plan_destroy",
+    "ufss_plan_info_get", "ufss_forward", "ufss_adjoint", "ufss_lipschitz", "ufss_fista",
+    "ufss_shrink_update", "ufss_absmax",
+]
+
+
+class UfssError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "?"), code, msg))
+        self.code = code
+        self.name = ERRORS.get(code, "?")
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("nt", ctypes.c_int32),
+        ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+        ("z_start", ctypes.c_double), ("t0", ctypes.c_double), ("c", ctypes.c_double),
+        ("fs", ctypes.c_double), ("fc", ctypes.c_double), ("frac_bw", ctypes.c_double),
+        ("band_db", ctypes.c_double),
+        ("win_x", ctypes.c_int32), ("win_y", ctypes.c_int32),
+        ("dtype", ctypes.c_int32), ("algo", ctypes.c_int32),
+    ]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("t0", ctypes.c_double), ("lipschitz", ctypes.c_double),
+        ("band_lo", ctypes.c_int32), ("band_hi", ctypes.c_int32), ("band_size", ctypes.c_int32),
+        ("win_x", ctypes.c_int32), ("win_y", ctypes.c_int32),
+        ("m", ctypes.c_int32), ("per_position", ctypes.c_int32), ("dtype", ctypes.c_int32),
+        ("algo", ctypes.c_int32), ("union_size", ctypes.c_int32),
+        ("workspace_bytes", ctypes.c_int64),
+    ]
+
+
+class FistaStats(ctypes.Structure):
+    _fields_ = [
+        ("obj", ctypes.POINTER(ctypes.c_double)), ("res", ctypes.POINTER(ctypes.c_double)),
+        ("rel_change", ctypes.POINTER(ctypes.c_double)),
+        ("err_ref", ctypes.POINTER(ctypes.c_double)),
+        ("iters_done", ctypes.c_int32), ("lambda_", ctypes.c_double),
+    ]
+
+
+class FistaState(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_void_p), ("k_done", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libufss (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libufss.so is not built (run __graft_entry__.build()); "
+                               "there is no fallback path")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, D, U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64
+        sig = {
+            "ufss_last_error": ([], ctypes.c_char_p),
+            "ufss_select_freqs": ([ctypes.POINTER(Geom), I32, I32, U64, P, P], ctypes.c_int),
+            "ufss_plan_create": ([ctypes.POINTER(Geom), I32, I32, P, ctypes.POINTER(P)], ctypes.c_int),
+            "ufss_plan_destroy": ([P], ctypes.c_int),
+            "ufss_plan_info_get": ([P, ctypes.POINTER(PlanInfo)], ctypes.c_int),
+            "ufss_forward": ([P, P, P, P], ctypes.c_int),
+            "ufss_adjoint": ([P, P, P, P], ctypes.c_int),
+            "ufss_lipschitz": ([P, I32, D, D, U64, ctypes.POINTER(D), P], ctypes.c_int),
+            "ufss_fista": ([P, P, D, D, I32, D, I32, P, P, ctypes.POINTER(FistaStats),
+                            ctypes.POINTER(FistaState), P], ctypes.c_int),
+            "ufss_shrink_update": ([I64, P, P, P, D, D, D, P, P, P], ctypes.c_int),
+            "ufss_absmax": ([I64, P, ctypes.POINTER(D), P], ctypes.c_int),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != UFSS_OK:
+        raise UfssError(code, lib().ufss_last_error().decode())
+
+
+def make_geom(g, dtype=F32, algo=ALGO_AUTO):
+    """ctypes geometry from a geometry dict (see workloads.geometry)."""
+    return Geom(int(g["nx"]), int(g["ny"]), int(g["nz"]), int(g["nt"]), g["dx"], g["dy"], g["dz"],
+                g["z_start"], g["t0"], g["c"], g["fs"], g["fc"], g["frac_bw"], g["band_db"],
+                int(g["win_x"]), int(g["win_y"]), int(dtype), int(algo))
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, name, dtype="complex64"):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous() or str(t.dtype) != "torch." + dtype:
+        raise ValueError("%s must be a contiguous %s CUDA tensor" % (name, dtype))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _numel_check(t, n, name):
+    if t.numel() != n:
+        raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), n))
+
+
+def ufss_select_freqs(g, m, per_position, seed):
+    """Seeded bins (int32 [m] or [ny, nx, m]) and the band size."""
+    geom = make_geom(g)
+    shape = (g["ny"], g["nx"], m) if per_position else (m,)
+    out = np.zeros(shape, dtype=np.int32)
+    band = ctypes.c_int32(0)
+    _check(lib().ufss_select_freqs(ctypes.byref(geom), int(m), int(bool(per_position)),
+                                   ctypes.c_uint64(seed & (2 ** 64 - 1)),
+                                   out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(band)))
+    return out, band.value
+
+
+class Plan:
+    """Owning handle of a ufss plan (ufss_plan_create / ufss_plan_destroy)."""
+
+    def __init__(self, g, m, per_position, bins, dtype=F32, algo=ALGO_AUTO):
+        self.g = dict(g)
+        self.m = int(m)
+        self.per_position = bool(per_position)
+        geom = make_geom(g, dtype, algo)
+        b = np.ascontiguousarray(bins, dtype=np.int32)
+        want = g["nx"] * g["ny"] * m if per_position else m
+        if b.size != want:
+            raise ValueError("bins has %d entries, expected %d" % (b.size, want))
+        h = ctypes.c_void_p()
+        _check(lib().ufss_plan_create(ctypes.byref(geom), self.m, int(self.per_position),
+                                      b.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)))
+        self.handle = h
+        self.nvox = g["nx"] * g["ny"] * g["nz"]
+        self.nmeas = g["nx"] * g["ny"] * m
+
+    def info(self):
+        i = PlanInfo()
+        _check(lib().ufss_plan_info_get(self.handle, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in PlanInfo._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(lib().ufss_plan_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ufss_forward(plan, x, y, stream=None):
+    _numel_check(x, plan.nvox, "x")
+    _numel_check(y, plan.nmeas, "y")
+    _check(lib().ufss_forward(plan.handle, _ptr(x, "x"), _ptr(y, "y"), _stream(stream)))
+
+
+def ufss_adjoint(plan, y, x, stream=None):
+    _numel_check(x, plan.nvox, "x")
+    _numel_check(y, plan.nmeas, "y")
+    _check(lib().ufss_adjoint(plan.handle, _ptr(y, "y"), _ptr(x, "x"), _stream(stream)))
+
+
+def ufss_lipschitz(plan, max_iters=200, rtol=1e-6, margin=0.01, seed=4, stream=None):
+    L = ctypes.c_double(0.0)
+    _check(lib().ufss_lipschitz(plan.handle, int(max_iters), float(rtol), float(margin),
+                                ctypes.c_uint64(seed), ctypes.byref(L), _stream(stream)))
+    return L.value
+
+
+def ufss_fista(plan, y, lam, L, iters, x, tol=0.0, accel=True, a_ref=None, state=None,
+               stream=None):
+    """Run FISTA/ISTA; returns a dict of per-iteration FP64 statistics.
+
+    ``state`` may be a dict {"gamma": tensor, "k_done": int}; it is updated.
+    """
+    _numel_check(x, plan.nvox, "x")
+    _numel_check(y, plan.nmeas, "y")
+    n = max(int(iters), 1)
+    arrs = {k: np.zeros(n) for k in ("obj", "res", "rel_change", "err_ref")}
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    st = FistaStats(dp(arrs["obj"]), dp(arrs["res"]), dp(arrs["rel_change"]),
+                    dp(arrs["err_ref"]), 0, 0.0)
+    cst = None
+    if state is not None:
+        _numel_check(state["gamma"], plan.nvox, "state gamma")
+        cst = FistaState(_ptr(state["gamma"], "gamma"), int(state.get("k_done", 0)))
+    code = lib().ufss_fista(plan.handle, _ptr(y, "y"), float(lam), float(L), int(iters),
+                            float(tol), int(bool(accel)), _ptr(x, "x"),
+                            _ptr(a_ref, "a_ref") if a_ref is not None else None,
+                            ctypes.byref(st), ctypes.byref(cst) if cst is not None else None,
+                            _stream(stream))
+    if cst is not None:
+        state["k_done"] = cst.k_done
+    _check(code)
+    k = st.iters_done
+    out = {key: v[:k].copy() for key, v in arrs.items()}
+    out["iters_done"] = k
+    out["lambda"] = st.lambda_
+    return out
+
+
+def ufss_shrink_update(gamma, g, a, step, thresh, beta, a_ref=None, stream=None):
+    """Fused update in place; returns the 5 FP64 norms (see ufss.h)."""
+    n = a.numel()
+    for t, nm in ((gamma, "gamma"), (g, "g")):
+        _numel_check(t, n, nm)
+    out = np.zeros(5)
+    _check(lib().ufss_shrink_update(n, _ptr(gamma, "gamma"), _ptr(g, "g"), _ptr(a, "a"),
+                                    float(step), float(thresh), float(beta),
+                                    _ptr(a_ref, "a_ref") if a_ref is not None else None,
+                                    out.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+    return out
+
+
+def ufss_absmax(x, stream=None):
+    out = ctypes.c_double(0.0)
+    _check(lib().ufss_absmax(x.numel(), _ptr(x, "x"), ctypes.byref(out), _stream(stream)))
+    return out.value
+
+
+def lambda_from_mu(mu):
+    """ufss_fista's lambda argument asking for lambda = mu * max|A^H y|."""
+    if not (mu > 0) or math.isnan(mu):
+        raise ValueError("mu must be positive")
+    return -float(mu)

@@ -1,0 +1,75 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol that
+include/ufss.h declares, and its host-only logic (bin selection, argument
+validation) matches the oracle bit for bit.  No GPU call is made."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import select as S
+from paper_2012_04534_amd import ufss
+from paper_2012_04534_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for f in os.listdir(inc):
+        if f.endswith(".h"):
+            text = open(os.path.join(inc, f)).read()
+            names |= set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(ufss_\w+)\s*\(", text, re.M))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ufss.lib()
+    names = declared_symbols()
+    assert len(names) >= 11
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    assert set(ufss.EXPORTED) <= names
+
+
+@pytest.mark.parametrize("name", ["bscan32", "cscan32", "cscan64"])
+def test_select_freqs_bit_identical_to_oracle(name):
+    w = W.workload(name)
+    g = w["geom"]
+    for seed in (w["seed"], 0, 2 ** 64 - 1):
+        b, band = ufss.ufss_select_freqs(g, w["m"], w["per_position"], seed)
+        o = S.select_freqs(g, w["m"], w["per_position"], seed)
+        assert np.array_equal(b, o)
+        assert band == {256: 33, 512: 66, 1024: 132}[g["nt"]]
+
+
+def test_select_freqs_errors():
+    g = W.workload("bscan32")["geom"]
+    with pytest.raises(ufss.UfssError) as e:
+        ufss.ufss_select_freqs(g, 34, False, 1)
+    assert e.value.name == "BAND_TOO_SMALL"
+    with pytest.raises(ufss.UfssError) as e:
+        ufss.ufss_select_freqs(g, 0, False, 1)
+    assert e.value.name == "INVALID_ARG"
+    bad = dict(g)
+    bad["c"] = -1.0
+    with pytest.raises(ufss.UfssError) as e:
+        ufss.ufss_select_freqs(bad, 4, False, 1)
+    assert e.value.name == "INVALID_ARG"
+    full, _ = ufss.ufss_select_freqs(g, 33, False, 9)
+    assert list(full) == list(range(10, 43))
+
+
+def test_plan_rejects_bad_bins_before_touching_the_gpu():
+    g = W.geometry(8, 4, 16, 64)
+    with pytest.raises(ufss.UfssError) as e:
+        ufss.Plan(g, 3, False, np.array([5, 4, 6]))
+    assert e.value.name == "INVALID_ARG"
+    with pytest.raises(ufss.UfssError) as e:
+        ufss.Plan(g, 2, False, np.array([5, 40]))
+    assert e.value.name == "INVALID_ARG"
+    bad = dict(g)
+    with pytest.raises(ufss.UfssError) as e:
+        ufss.Plan(bad, 2, False, np.array([4, 5]), dtype=ufss.BF16, algo=ufss.ALGO_PHASOR)
+    assert e.value.name in ("UNSUPPORTED", "INVALID_ARG")

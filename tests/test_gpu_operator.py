@@ -1,0 +1,186 @@
+"""GPU parity of the operator A / A^H (C ABI) against the FP64 oracle.
+
+Tolerance: FP32 operator, relative error <= 1e-5 measured both norm-wise and
+element by element against the largest output (max |gpu - ref| / max |ref|).
+Cases: tiny grids for every mode, ragged sizes spanning several tiles, edge
+cases, the full B-scan workload (dense oracle), and the full C-scan workloads
+on outputs the oracle computes one position / one voxel column at a time.
+"""
+import numpy as np
+import pytest
+
+from oracle import operator as O
+from oracle import select as S
+from paper_2012_04534_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+
+
+def ufss():
+    from paper_2012_04534_amd import ufss as u
+    return u
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def errs(got, ref):
+    got = np.asarray(got).astype(np.complex128)
+    d = got - ref
+    return (np.linalg.norm(d) / np.linalg.norm(ref), np.abs(d).max() / np.abs(ref).max())
+
+
+def run_op(plan, x, y_shape, dev):
+    u = ufss()
+    xt = torch.from_numpy(x.astype(np.complex64)).to(dev)
+    yt = torch.empty(y_shape, dtype=torch.complex64, device=dev)
+    u.ufss_forward(plan, xt, yt)
+    return yt
+
+
+def case_list():
+    cases = []
+    for win in (-1, 2):
+        for per_pos in (False, True):
+            cases.append(("tiny", dict(nx=6, ny=5, nz=24, nt=64, win=win), 6, per_pos))
+    cases.append(("bscan", dict(nx=9, ny=1, nz=20, nt=64, win=3), 5, True))
+    cases.append(("bscan-shared", dict(nx=40, ny=1, nz=37, nt=128, win=-1), 11, False))
+    cases.append(("ragged", dict(nx=13, ny=7, nz=45, nt=128, win=3), 11, False))
+    cases.append(("ragged-pp", dict(nx=13, ny=7, nz=45, nt=128, win=3), 11, True))
+    cases.append(("one-bin", dict(nx=5, ny=3, nz=9, nt=64, win=1), 1, False))
+    cases.append(("one-depth", dict(nx=6, ny=6, nz=1, nt=64, win=-1), 4, True))
+    cases.append(("one-pos", dict(nx=1, ny=1, nz=30, nt=64, win=-1), 7, False))
+    cases.append(("win0", dict(nx=7, ny=4, nz=17, nt=64, win=0), 8, False))
+    cases.append(("tall", dict(nx=3, ny=21, nz=16, nt=64, win=5), 6, True))
+    return cases
+
+
+CASES = case_list()
+
+
+def algos(per_pos):
+    u = ufss()
+    return [u.ALGO_GEMM, u.ALGO_PHASOR] if per_pos else [u.ALGO_GEMM]
+
+
+@pytest.mark.parametrize("ci", range(len(CASES)), ids=[c[0] + str(i) for i, c in enumerate(CASES)])
+def test_forward_adjoint_small(ci, dev):
+    u = ufss()
+    name, gs, m, per_pos = CASES[ci]
+    g = W.geometry(gs["nx"], gs["ny"], gs["nz"], gs["nt"], win_x=gs["win"], win_y=gs["win"])
+    bins, _ = u.ufss_select_freqs(g, m, per_pos, 31 + ci)
+    x = W.cn((g["ny"], g["nx"], g["nz"]), 100 + ci).astype(np.complex64)
+    y = W.cn((g["ny"], g["nx"], m), 200 + ci).astype(np.complex64)
+    A = O.dense_A(g, bins)
+    y_ref = (A @ x.reshape(-1).astype(np.complex128)).reshape(g["ny"], g["nx"], m)
+    x_ref = (A.conj().T @ y.reshape(-1).astype(np.complex128)).reshape(x.shape)
+    for algo in algos(per_pos):
+        plan = u.Plan(g, m, per_pos, bins, algo=algo)
+        yt = run_op(plan, x, y.shape, dev)
+        xt = torch.empty(x.shape, dtype=torch.complex64, device=dev)
+        u.ufss_adjoint(plan, torch.from_numpy(y).to(dev), xt)
+        torch.cuda.synchronize()
+        ey = errs(yt.cpu().numpy(), y_ref)
+        ex = errs(xt.cpu().numpy(), x_ref)
+        assert max(ey) < TOL32, (name, algo, "forward", ey)
+        assert max(ex) < TOL32, (name, algo, "adjoint", ex)
+        plan.close()
+
+
+@pytest.mark.parametrize("per_pos", [False, True])
+def test_gpu_adjointness_and_determinism(per_pos, dev):
+    u = ufss()
+    g = W.geometry(20, 12, 64, 256, win_x=6, win_y=6)
+    bins, _ = u.ufss_select_freqs(g, 24, per_pos, 5)
+    for algo in algos(per_pos):
+        plan = u.Plan(g, 24, per_pos, bins, algo=algo)
+        x = torch.from_numpy(W.cn((12, 20, 64), 1).astype(np.complex64)).to(dev)
+        y = torch.from_numpy(W.cn((12, 20, 24), 2).astype(np.complex64)).to(dev)
+        Ax = torch.empty_like(y)
+        AHy = torch.empty_like(x)
+        u.ufss_forward(plan, x, Ax)
+        u.ufss_adjoint(plan, y, AHy)
+        Ax2 = torch.empty_like(y)
+        AHy2 = torch.empty_like(x)
+        u.ufss_forward(plan, x, Ax2)
+        u.ufss_adjoint(plan, y, AHy2)
+        torch.cuda.synchronize()
+        assert torch.equal(Ax, Ax2) and torch.equal(AHy, AHy2)
+        lhs = np.vdot(y.cpu().numpy().astype(np.complex128), Ax.cpu().numpy().astype(np.complex128))
+        rhs = np.vdot(AHy.cpu().numpy().astype(np.complex128), x.cpu().numpy().astype(np.complex128))
+        scale = np.linalg.norm(Ax.cpu().numpy()) * np.linalg.norm(y.cpu().numpy())
+        assert abs(lhs - rhs) < 1e-6 * scale
+        plan.close()
+
+
+def test_bscan_workload_full(dev):
+    """Full 32-position B-scan workload against the dense FP64 oracle."""
+    u = ufss()
+    w = W.workload("bscan32")
+    g = w["geom"]
+    bins, _ = u.ufss_select_freqs(g, w["m"], False, w["seed"])
+    A = O.dense_A(g, bins)
+    plan = u.Plan(g, w["m"], False, bins)
+    x = W.cn((g["ny"], g["nx"], g["nz"]), 3).astype(np.complex64)
+    y = W.cn((g["ny"], g["nx"], w["m"]), 4).astype(np.complex64)
+    yt = run_op(plan, x, y.shape, dev)
+    xt = torch.empty(x.shape, dtype=torch.complex64, device=dev)
+    u.ufss_adjoint(plan, torch.from_numpy(y).to(dev), xt)
+    torch.cuda.synchronize()
+    assert max(errs(yt.cpu().numpy().reshape(-1), A @ x.reshape(-1).astype(np.complex128))) < TOL32
+    assert max(errs(xt.cpu().numpy().reshape(-1), A.conj().T @ y.reshape(-1).astype(np.complex128))) < TOL32
+    plan.close()
+
+
+@pytest.mark.parametrize("name", ["cscan32", "cscan64"])
+def test_cscan_workloads_full_sampled(name, dev):
+    """Full-size C-scan workloads, in the bench's launch configuration, checked
+    on positions / voxel columns the oracle evaluates one at a time (corners,
+    edges and the centre)."""
+    u = ufss()
+    w = W.workload(name)
+    g = w["geom"]
+    m = w["m"]
+    bins, _ = u.ufss_select_freqs(g, m, w["per_position"], w["seed"])
+    x = W.cn((g["ny"], g["nx"], g["nz"]), 5).astype(np.complex64)
+    y = W.cn((g["ny"], g["nx"], m), 6).astype(np.complex64)
+    nx, ny = g["nx"], g["ny"]
+    pos = [(0, 0), (ny - 1, nx - 1), (ny // 2, nx // 2), (3, nx - 5)]
+    cols = [(0, nx - 1), (ny // 2 + 1, nx // 2 - 2)]
+    y_ref = np.stack([O.apply_A_at(g, bins, x, py, px) for (py, px) in pos])
+    x_ref = np.stack([O.apply_AH_at(g, bins, y, vy, vx) for (vy, vx) in cols])
+    for algo in algos(w["per_position"]):
+        plan = u.Plan(g, m, w["per_position"], bins, algo=algo)
+        yt = run_op(plan, x, y.shape, dev)
+        xt = torch.empty(x.shape, dtype=torch.complex64, device=dev)
+        u.ufss_adjoint(plan, torch.from_numpy(y).to(dev), xt)
+        torch.cuda.synchronize()
+        yg = yt.cpu().numpy()
+        xg = xt.cpu().numpy()
+        ey = errs(np.stack([yg[py, px] for (py, px) in pos]), y_ref)
+        ex = errs(np.stack([xg[vy, vx] for (vy, vx) in cols]), x_ref)
+        assert max(ey) < TOL32, (name, algo, ey)
+        assert max(ex) < TOL32, (name, algo, ex)
+        plan.close()
+
+
+def test_plan_info_and_errors(dev):
+    u = ufss()
+    g = W.workload("cscan32")["geom"]
+    bins, _ = u.ufss_select_freqs(g, 64, True, 1002)
+    plan = u.Plan(g, 64, True, bins)
+    info = plan.info()
+    assert info["band_size"] == 66 and info["union_size"] <= 66 and info["per_position"] == 1
+    assert abs(info["t0"] - 7.6234185e-6) < 1e-12
+    x = torch.zeros(10, dtype=torch.complex64, device=dev)
+    y = torch.zeros(32 * 32 * 64, dtype=torch.complex64, device=dev)
+    with pytest.raises(ValueError):
+        u.ufss_forward(plan, x, y)
+    plan.close()
