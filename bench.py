@@ -1,0 +1,250 @@
+"""Benchmark: A + A^H throughput and FISTA time-to-accuracy on one MI355X.
+
+One step = one FISTA iteration of the whole hot path on the 32 x 32 C-scan
+workload (per-position bins): forward operator with the residual epilogue,
+adjoint operator, fused soft-threshold / momentum update and the FP64
+reductions of the objective, residual and stopping statistics.  The reported
+value is the A + A^H throughput in algorithmic GFLOP/s (8 flops per complex
+multiply-accumulate of the windowed direct sum, selected bins only), with the
+inputs resident in HBM.
+
+Prints ONE JSON line.  Extra fields: the dominant kernel's roofline, the FP64
+oracle timed on host cores ("cpu_baseline"), the FISTA time to a relative
+error of 1e-2, and per-kernel timings.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "A+A^H GFLOP/s & FISTA time to 1e-2 rel error: FP32 plain vs BF16/learned"
+PEAK_FP32_MFMA = 157.3e12
+PEAK_BF16_MFMA = 2.5e15
+PEAK_HBM = 8e12
+
+
+def window_terms(g, bins, per_pos):
+    """Algorithmic complex MACs of one apply (voxels inside each window x bins)."""
+    nx, ny = g["nx"], g["ny"]
+    wx = nx - 1 if g["win_x"] < 0 else min(g["win_x"], nx - 1)
+    wy = ny - 1 if g["win_y"] < 0 else min(g["win_y"], ny - 1)
+    cy = np.array([min(p + wy, ny - 1) - max(p - wy, 0) + 1 for p in range(ny)])
+    cx = np.array([min(p + wx, nx - 1) - max(p - wx, 0) + 1 for p in range(nx)])
+    return int(cy.sum()) * int(cx.sum()) * bins.shape[-1] * g["nz"]
+
+
+def cpu_baseline(w, bins, seconds=12.0):
+    """Time the FP64 oracle on a bounded sample of the same workload."""
+    from oracle import operator as O
+    from paper_2012_04534_amd import workloads as W
+    try:
+        from threadpoolctl import threadpool_limits
+        limit = threadpool_limits(limits=1)
+    except Exception:  # pragma: no cover
+        limit = None
+    g = w["geom"]
+    x = W.cn((g["ny"], g["nx"], g["nz"]), 5)
+    y = W.cn((g["ny"], g["nx"], w["m"]), 6)
+    rng = np.random.default_rng(0)
+    wx = g["nx"] - 1 if g["win_x"] < 0 else g["win_x"]
+    wy = g["ny"] - 1 if g["win_y"] < 0 else g["win_y"]
+    cmac, n_fwd, n_adj = 0, 0, 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        py, px = int(rng.integers(g["ny"])), int(rng.integers(g["nx"]))
+        O.apply_A_at(g, bins, x, py, px)
+        nvx = min(px + wx, g["nx"] - 1) - max(px - wx, 0) + 1
+        nvy = min(py + wy, g["ny"] - 1) - max(py - wy, 0) + 1
+        cmac += nvx * nvy * g["nz"] * w["m"]
+        n_fwd += 1
+        vy, vx = int(rng.integers(g["ny"])), int(rng.integers(g["nx"]))
+        O.apply_AH_at(g, bins, y, vy, vx)
+        npx = min(vx + wx, g["nx"] - 1) - max(vx - wx, 0) + 1
+        npy = min(vy + wy, g["ny"] - 1) - max(vy - wy, 0) + 1
+        cmac += npx * npy * g["nz"] * w["m"]
+        n_adj += 1
+    dt = time.perf_counter() - t0
+    if limit is not None:
+        limit.unregister()
+    return {
+        "value": round(8.0 * cmac / dt / 1e9, 4), "unit": "GFLOP/s", "cores": 1,
+        "kind": "oracle",
+        "sample": "%d rows of A x (one scan position each) and %d columns of A^H y (one voxel "
+                  "column each) at the full 32x32 C-scan geometry, FP64 numpy direct sum, "
+                  "1 BLAS thread, %.1f s" % (n_fwd, n_adj, dt),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cscan32")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--quick", action="store_true", help="skip time-to-accuracy and extras")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="also run a plain device copy of this size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see the sharding design); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2012_04534_amd import ufss
+    from paper_2012_04534_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    w = W.workload(args.workload)
+    g = w["geom"]
+    m, per_pos = w["m"], w["per_position"]
+    bins, _ = ufss.ufss_select_freqs(g, m, per_pos, w["seed"])
+    cmac = window_terms(g, bins, per_pos)
+    flop_pair = 16.0 * cmac           # A + A^H
+
+    def ev_time(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    shape_x = (g["ny"], g["nx"], g["nz"])
+    shape_y = (g["ny"], g["nx"], m)
+    extras = {"algos": {}}
+    # pick the operator algorithm by measurement (FP32)
+    algos = [ufss.ALGO_GEMM, ufss.ALGO_PHASOR] if per_pos else [ufss.ALGO_GEMM]
+    xr = torch.from_numpy(W.cn(shape_x, 1).astype(np.complex64)).to(dev)
+    yr = torch.empty(shape_y, dtype=torch.complex64, device=dev)
+    xo = torch.empty_like(xr)
+    best = None
+    for algo in algos:
+        plan = ufss.Plan(g, m, per_pos, bins, algo=algo)
+        tf = ev_time(lambda: ufss.ufss_forward(plan, xr, yr), 5)
+        ta = ev_time(lambda: ufss.ufss_adjoint(plan, yr, xo), 5)
+        name = {ufss.ALGO_GEMM: "gemm", ufss.ALGO_PHASOR: "phasor"}[algo]
+        extras["algos"][name] = {"forward_ms": round(tf, 4), "adjoint_ms": round(ta, 4),
+                                 "a_plus_ah_gflops": round(flop_pair / ((tf + ta) * 1e-3) / 1e9, 1)}
+        if best is None or tf + ta < best[1]:
+            best = (algo, tf + ta, name)
+        plan.close()
+    algo, _, algo_name = best
+    plan = ufss.Plan(g, m, per_pos, bins, algo=algo)
+
+    # synthetic scene and measurements: y = A x + n at the workload's SNR
+    x_true = W.scene(g, w["n_scat"], amp=w["amp"], seed=w["seed"], back_wall=w["back_wall"])
+    xt = torch.from_numpy(x_true.astype(np.complex64)).to(dev)
+    y0 = torch.empty(shape_y, dtype=torch.complex64, device=dev)
+    ufss.ufss_forward(plan, xt, y0)
+    torch.cuda.synchronize()
+    sig = W.noise_sigma(float((y0.abs() ** 2).sum().item()), y0.numel(), w["snr_db"])
+    y = (y0 + sig * torch.from_numpy(W.cn(shape_y, w["seed"] + 1).astype(np.complex64)).to(dev)).contiguous()
+
+    t_l = time.perf_counter()
+    L = ufss.ufss_lipschitz(plan, max_iters=200, rtol=1e-6, margin=0.01, seed=4)
+    t_l = time.perf_counter() - t_l
+    x = torch.zeros(shape_x, dtype=torch.complex64, device=dev)
+    st = ufss.ufss_fista(plan, y, ufss.lambda_from_mu(w["mu"]), L, 1, x)
+    lam = st["lambda"]
+
+    # warmup, then exactly K timed FISTA iterations
+    x.zero_()
+    ufss.ufss_fista(plan, y, lam, L, max(args.warmup, 1), x)
+    x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ufss.ufss_fista(plan, y, lam, L, args.steps, x)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = flop_pair / (ms_step * 1e-3) / 1e9
+
+    # dominant kernel, timed live with HIP events on the launch stream
+    ufss.ufss_forward(plan, xr, yr)
+    ufss.ufss_adjoint(plan, yr, xo)
+    k_f = ufss.ufss_time_kernel(plan, 0, 10)
+    k_a = ufss.ufss_time_kernel(plan, 1, 10)
+    dom, k_ms = ("adjoint", k_a) if k_a >= k_f else ("forward", k_f)
+    if algo == ufss.ALGO_PHASOR:
+        # per term: one complex MAC (8 flops) on the VALU; peak is the FP32 vector rate
+        roof = {"bound": "alu", "achieved": round(8.0 * cmac / (k_ms * 1e-3) / 1e12, 3),
+                "peak": 157.3, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "mfma", "achieved": round(8.0 * cmac / (k_ms * 1e-3) / 1e12, 3),
+                "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s"}
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    roof["traffic"] = None
+    roof["kernel"] = "%s %s core (%.4f ms per launch)" % (algo_name, dom, k_ms)
+    extras["kernel_ms"] = {"forward_core": round(k_f, 4), "adjoint_core": round(k_a, 4)}
+
+    result = {
+        "metric": METRIC, "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "%s: %dx%d scan positions, %dx%dx%d voxels, N_t=%d, M=%d %s bins, "
+                               "%s window, %d scatterers%s, %g dB SNR, FISTA mu=%g" % (
+                                   args.workload, g["nx"], g["ny"], g["nx"], g["ny"], g["nz"], g["nt"], m,
+                                   "per-position" if per_pos else "shared",
+                                   "full" if g["win_x"] < 0 else "+-%d" % g["win_x"], w["n_scat"],
+                                   " + back wall" if w["back_wall"] is not None else "",
+                                   w["snr_db"], w["mu"]),
+                   "operator_algo": algo_name, "cmac_per_apply": cmac},
+        "roofline": roof,
+    }
+
+    if not args.quick:
+        # FISTA time to 1e-2 relative error against a long FP32 FISTA reference
+        a_ref = torch.zeros_like(x)
+        ufss.ufss_fista(plan, y, lam, L, 4 * w["iters"], a_ref)
+        xa = torch.zeros_like(x)
+        sa = ufss.ufss_fista(plan, y, lam, L, w["iters"], xa, a_ref=a_ref)
+        hit = np.flatnonzero(sa["err_ref"] <= 1e-2)
+        k_hit = int(hit[0]) + 1 if hit.size else None
+        fista = {"reference": "FP32 FISTA, %d iterations" % (4 * w["iters"]),
+                 "lipschitz_s": round(t_l, 4), "L": L, "lambda": lam}
+        if k_hit is not None:
+            xa.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ufss.ufss_fista(plan, y, lam, L, k_hit, xa)
+            torch.cuda.synchronize()
+            fista["fp32_iters_to_1e-2"] = k_hit
+            fista["fp32_time_to_1e-2_s"] = round(time.perf_counter() - t0, 5)
+        fista["fp32_err_at_%d" % w["iters"]] = float(sa["err_ref"][-1])
+        result["fista"] = fista
+
+    result["extras"] = extras
+    plan.close()
+
+    if args.calib_copy_mb > 0:
+        n = args.calib_copy_mb * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        result["extras"]["calib_copy_bytes_each_way"] = n * 4
+
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(w, bins)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -198,6 +198,15 @@ int ufss_shrink_update(int64_t n, void* gamma, const void* g, void* a,
  * rule.  out HOST double.  Synchronises `stream`. */
 int ufss_absmax(int64_t n, const void* x, double* out, ufss_stream_t stream);
 
+/* Diagnostic: average duration (ms) of the operator's core kernel, launched
+ * `reps` times back to back between two HIP events recorded on `stream`.
+ * which = 0: forward core (windowed GEMM, or phasor forward), 1: adjoint core.
+ * The kernel reads the plan's own workspace (its last operands), so call it
+ * after at least one ufss_forward / ufss_adjoint.  Synchronises `stream`.
+ *   ms_out HOST double */
+int ufss_time_kernel(ufss_plan_t plan, int32_t which, int32_t reps, double* ms_out,
+                     ufss_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -325,6 +325,52 @@ int ufss_shrink_update(int64_t n, void* gamma, const void* g, void* a, double st
     UFSS_GUARD_END
 }
 
+int ufss_time_kernel(ufss_plan_t plan, int32_t which, int32_t reps, double* ms_out,
+                     ufss_stream_t stream) {
+    UFSS_GUARD_BEGIN
+    Plan* P = as_plan(plan);
+    if (which < 0 || which > 1 || reps < 1 || !ms_out)
+        ufss::fail(UFSS_ERR_INVALID_ARG, "which must be 0 or 1, reps >= 1, ms_out non-NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    UFSS_HIP(hipEventCreate(&e0));
+    UFSS_HIP(hipEventCreate(&e1));
+    try {
+        auto launch = [&]() {
+            if (which == 0) {
+                if (P->algo == UFSS_ALGO_PHASOR)
+                    ufss::launch_forward_phasor(*P, P->d_gamma, P->d_r, nullptr, P->d_part, s);
+                else if (P->dtype == UFSS_BF16)
+                    ufss::launch_forward_gemm_bf16(*P, s);
+                else
+                    ufss::launch_forward_gemm(*P, P->d_gamma, s);
+            } else {
+                if (P->algo == UFSS_ALGO_PHASOR)
+                    ufss::launch_adjoint_phasor(*P, P->d_g, s);
+                else if (P->dtype == UFSS_BF16)
+                    ufss::launch_adjoint_gemm_bf16(*P, P->d_g, s);
+                else
+                    ufss::launch_adjoint_gemm(*P, P->d_g, s);
+            }
+        };
+        launch();   // warm
+        UFSS_HIP(hipEventRecord(e0, s));
+        for (int i = 0; i < reps; ++i) launch();
+        UFSS_HIP(hipEventRecord(e1, s));
+        UFSS_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        UFSS_HIP(hipEventElapsedTime(&ms, e0, e1));
+        *ms_out = (double)ms / reps;
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    UFSS_HIP(hipEventDestroy(e0));
+    UFSS_HIP(hipEventDestroy(e1));
+    UFSS_GUARD_END
+}
+
 int ufss_absmax(int64_t n, const void* x, double* out, ufss_stream_t stream) {
     UFSS_GUARD_BEGIN
     if (n < 1 || !x || !out) ufss::fail(UFSS_ERR_INVALID_ARG, "bad size or NULL buffer");

@@ -26,7 +26,7 @@ ALGO_AUTO, ALGO_GEMM, ALGO_PHASOR = 0, 1, 2
 EXPORTED = [
     "ufss_last_error", "ufss_select_freqs", "ufss_plan_create", "ufss_plan_destroy",
     "ufss_plan_info_get", "ufss_forward", "ufss_adjoint", "ufss_lipschitz", "ufss_fista",
-    "ufss_shrink_update", "ufss_absmax",
+    "ufss_shrink_update", "ufss_absmax", "ufss_time_kernel",
 ]
 
 
@@ -99,6 +99,7 @@ def lib():
                             ctypes.POINTER(FistaState), P], ctypes.c_int),
             "ufss_shrink_update": ([I64, P, P, P, D, D, D, P, P, P], ctypes.c_int),
             "ufss_absmax": ([I64, P, ctypes.POINTER(D), P], ctypes.c_int),
+            "ufss_time_kernel": ([P, I32, I32, ctypes.POINTER(D), P], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -256,6 +257,14 @@ def ufss_absmax(x, stream=None):
     out = ctypes.c_double(0.0)
     _check(lib().ufss_absmax(x.numel(), _ptr(x, "x"), ctypes.byref(out), _stream(stream)))
     return out.value
+
+
+def ufss_time_kernel(plan, which, reps=10, stream=None):
+    """Average duration (ms) of the forward (0) or adjoint (1) core kernel."""
+    ms = ctypes.c_double(0.0)
+    _check(lib().ufss_time_kernel(plan.handle, int(which), int(reps), ctypes.byref(ms),
+                                  _stream(stream)))
+    return ms.value
 
 
 def lambda_from_mu(mu):
