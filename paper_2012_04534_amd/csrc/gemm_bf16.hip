@@ -1,14 +1,497 @@
-// BF16 variants of the windowed GEMM kernels (placeholder until implemented).
+// Windowed complex GEMM kernels, BF16 operands with FP32 accumulation.
+//
+// Same products as the FP32 kernels (paper Sec. IV-B: one small complex GEMM
+// per lateral offset d of the block 2-level Toeplitz operator):
+//
+//   forward  Y[p, k] = sum_d sum_z  P_d[k, z] x[p - d, z]
+//   adjoint  G[v, z] = sum_d sum_k  conj(P_d[k, z]) R[v + d, k]
+//
+// with the phasors P and the operands x (forward) and R = H r (adjoint) rounded
+// to BF16 (round to nearest even); accumulation and everything in HBM stay FP32.
+//
+// MFMA: v_mfma_f32_16x16x32_bf16.  Lane l holds A[i = l%16][k = 8(l/16) + e],
+// B[k = 8(l/16) + e][j = l%16] for e = 0..7, D[i = 4(l/16) + r][j = l%16].
+//
+// At BF16 rates a phasor costs far more VALU time than the MFMA work one wave
+// does with it, so the four waves of a workgroup share one phasor tile: it is
+// generated cooperatively in LDS for each offset d (double buffered, the next
+// offset's tile is written while the current one is consumed) and each wave
+// applies it to its own positions.  Along the bin axis the phasors of
+// consecutive bins are produced by one complex multiplication (angle addition)
+// from the previous one; non-consecutive bins take a fresh sin/cos.  Operand
+// halos are stored planar (8 real then 8 imaginary values contiguous) so one
+// 16-byte LDS read fills a BF16 MFMA operand; columns outside the grid map to a
+// single zero cell.
 #include "internal.h"
 
 namespace ufss {
 
-void launch_forward_gemm_bf16(const Plan&, hipStream_t) {
-    fail(UFSS_ERR_UNSUPPORTED, "BF16 operator not built yet");
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+static constexpr float kTwoM32b = 2.3283064365386963e-10f;
+static constexpr int ZCB = 32;             // reduction chunk = one MFMA K
+static constexpr int CELL = 2 * ZCB + 8;   // bf16 per halo cell (re, im, pad)
+static constexpr int PROW = ZCB + 8;       // bf16 per phasor-tile row
+
+__device__ __forceinline__ void sincos_turns(uint32_t ku, float& c, float& s) {
+    float ph = (float)(int32_t)ku * kTwoM32b;
+    c = __builtin_amdgcn_cosf(ph);
+    s = __builtin_amdgcn_sinf(ph);
 }
 
-void launch_adjoint_gemm_bf16(const Plan&, cf32*, hipStream_t) {
-    fail(UFSS_ERR_UNSUPPORTED, "BF16 operator not built yet");
+__device__ __forceinline__ bf8 lds_bf8(const __bf16* p) {
+    return *reinterpret_cast<const bf8*>(p);
+}
+
+__device__ __forceinline__ bf8 neg_bf8(bf8 v) {
+    u4 w = __builtin_bit_cast(u4, v);
+    w ^= u4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+    return __builtin_bit_cast(bf8, w);
+}
+
+// Cooperative phasor generation: `rows` x ZCB entries of cos / sin(2 pi k u)
+// for the tile rows' bins.  Thread t takes one reduction index and a run of
+// `run` consecutive rows.  kidx(row) gives the bin, uval(col) the delay.
+//   layout: pc[row * PROW + col], ps[row * PROW + col]
+template <class KF, class UF>
+__device__ __forceinline__ void gen_tile(__bf16* pc, __bf16* ps, int rows, int ncol, int run,
+                                         KF kidx, UF uval) {
+    const int groups = (rows + run - 1) / run;
+    for (int t = threadIdx.x; t < groups * ncol; t += blockDim.x) {
+        const int col = t % ncol, g = t / ncol;
+        const uint32_t u = uval(col);
+        float wc, ws;
+        sincos_turns(u, wc, ws);
+        int kprev = -2;
+        float c = 0.f, s = 0.f;
+        const int r_end = min(rows, (g + 1) * run);
+        for (int r = g * run; r < r_end; ++r) {
+            const int k = kidx(r);
+            if (k == kprev + 1) {
+                // angle addition: e^{j 2 pi (k-1) u} e^{j 2 pi u}
+                float c2 = c * wc - s * ws;
+                s = s * wc + c * ws;
+                c = c2;
+            } else {
+                sincos_turns((uint32_t)k * u, c, s);
+            }
+            kprev = k;
+            pc[r * PROW + col] = (__bf16)c;
+            ps[r * PROW + col] = (__bf16)s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Forward.
+// ---------------------------------------------------------------------------
+struct FwdB {
+    const cbf16* x;        // [ny][nx][nz] bf16 complex
+    cf32* yraw;            // [split][npos][mu]
+    const uint32_t* u;
+    const int* kb;
+    int nx, ny, nz, wx, wy, mu;
+    int sw, ntx, nty, nbt, split;
+    int64_t npos;
+};
+
+template <int NP, int NB>
+__global__ __launch_bounds__(256) void fwd_gemm_bf16_kernel(FwdB a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int sw = a.sw, sh = 16 / sw;
+    const int tpx = 4 * NP * sw, tpy = sh;
+
+    const int nblk = gridDim.x;
+    int b = blockIdx.x;
+    int per_xcd = nblk / 8;
+    if (per_xcd * 8 == nblk) b = (b % 8) * per_xcd + b / 8;
+    const int ntile = a.ntx * a.nty;
+    const int tile = b % ntile;
+    const int bt = (b / ntile) % a.nbt;
+    const int sp = b / (ntile * a.nbt);
+    const int px0 = (tile % a.ntx) * tpx, py0 = (tile / a.ntx) * tpy;
+    const int cx_lo = max(0, px0 - a.wx), cx_hi = min(a.nx - 1, px0 + tpx - 1 + a.wx);
+    const int ncol = cx_hi - cx_lo + 1;
+
+    __bf16* halo = reinterpret_cast<__bf16*>(smem);                    // [tpy*ncol + 1][CELL]
+    const int zero_cell = tpy * ncol;
+    __bf16* ptile = halo + (size_t)(zero_cell + 1) * CELL;               // [2][2][NB*16][PROW]
+    uint32_t* ulds = reinterpret_cast<uint32_t*>(ptile + 2 * 2 * NB * 16 * PROW);   // [wx+1][ZCB]
+    int* klds = reinterpret_cast<int*>(ulds + (a.wx + 1) * ZCB);         // [NB*16]
+
+    int dy_lo = max(-a.wy, py0 - (a.ny - 1));
+    int dy_hi = min(a.wy, py0 + tpy - 1);
+    const int chunk = (dy_hi - dy_lo + 1 + a.split - 1) / a.split;
+    dy_lo += sp * chunk;
+    dy_hi = min(dy_hi, dy_lo + chunk - 1);
+    const int dx_lo = max(-a.wx, px0 - (a.nx - 1));
+    const int dx_hi = min(a.wx, px0 + tpx - 1);
+
+    const int mb0 = bt * NB * 16;
+    const int nbins = min(NB * 16, a.mu - mb0);          // valid bins of this tile
+    const int nb_act = (nbins + 15) / 16;                // active bin sub-tiles
+    const int i = lane & 15, kq = lane >> 4;
+
+    for (int t = threadIdx.x; t < NB * 16; t += 256) klds[t] = t < nbins ? a.kb[mb0 + t] : 0;
+    for (int t = threadIdx.x; t < CELL; t += 256) halo[(size_t)zero_cell * CELL + t] = (__bf16)0.f;
+
+    f4 acc_re[NP][NB], acc_im[NP][NB];
+#pragma unroll
+    for (int s = 0; s < NP; ++s)
+#pragma unroll
+        for (int q = 0; q < NB; ++q) acc_re[s][q] = acc_im[s][q] = f4{0.f, 0.f, 0.f, 0.f};
+
+    const int prow_count = nb_act * 16;
+    for (int z0 = 0; z0 < a.nz; z0 += ZCB) {
+        for (int dy = dy_lo; dy <= dy_hi; ++dy) {
+            __syncthreads();
+            // stage x rows (planar bf16) and the delay slab of |dy|
+            for (int t = threadIdx.x; t < tpy * ncol * ZCB; t += 256) {
+                const int zz = t % ZCB, cell = t / ZCB;
+                const int r = cell / ncol, c = cell - r * ncol;
+                const int gy = py0 + r - dy, gx = cx_lo + c, z = z0 + zz;
+                cbf16 v = to_cbf16(0.f, 0.f);
+                if (gy >= 0 && gy < a.ny && z < a.nz) v = a.x[((int64_t)gy * a.nx + gx) * a.nz + z];
+                halo[(size_t)cell * CELL + zz] = v.re;
+                halo[(size_t)cell * CELL + ZCB + zz] = v.im;
+            }
+            const int ady = dy < 0 ? -dy : dy;
+            for (int t = threadIdx.x; t < (a.wx + 1) * ZCB; t += 256) {
+                const int adx = t / ZCB, zz = t - adx * ZCB, z = z0 + zz;
+                ulds[t] = z < a.nz ? a.u[((int64_t)ady * (a.wx + 1) + adx) * a.nz + z] : 0u;
+            }
+            __syncthreads();
+            auto gen = [&](int dx, int buf) {
+                const int adx = dx < 0 ? -dx : dx;
+                __bf16* pc = ptile + (size_t)buf * 2 * NB * 16 * PROW;
+                __bf16* ps = pc + NB * 16 * PROW;
+                gen_tile(pc, ps, prow_count, ZCB, (prow_count * ZCB + 255) / 256,
+                         [&](int r) { return klds[r]; },
+                         [&](int col) { return ulds[adx * ZCB + col]; });
+            };
+            if (dx_lo <= dx_hi) gen(dx_lo, 0);
+            __syncthreads();
+            int buf = 0;
+            for (int dx = dx_lo; dx <= dx_hi; ++dx) {
+                if (dx < dx_hi) gen(dx + 1, buf ^ 1);
+                const __bf16* pc = ptile + (size_t)buf * 2 * NB * 16 * PROW;
+                const __bf16* ps = pc + NB * 16 * PROW;
+                // A operands: x at (p - d) for this lane's position of each sub-tile
+                bf8 xr[NP], xi[NP];
+#pragma unroll
+                for (int s = 0; s < NP; ++s) {
+                    const int q = wave * NP + s;
+                    const int px = px0 + q * sw + i % sw, iy = i / sw;
+                    const int gx = px - dx;
+                    const int cell = (gx >= cx_lo && gx <= cx_hi) ? iy * ncol + (gx - cx_lo) : zero_cell;
+                    xr[s] = lds_bf8(halo + (size_t)cell * CELL + 8 * kq);
+                    xi[s] = lds_bf8(halo + (size_t)cell * CELL + ZCB + 8 * kq);
+                }
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    if (nb >= nb_act) break;
+                    const bf8 c8 = lds_bf8(pc + (nb * 16 + i) * PROW + 8 * kq);
+                    const bf8 s8 = lds_bf8(ps + (nb * 16 + i) * PROW + 8 * kq);
+                    const bf8 ns8 = neg_bf8(s8);
+#pragma unroll
+                    for (int s = 0; s < NP; ++s) {
+                        // (xr + j xi)(c - j s) = xr c + xi s + j (xi c - xr s)
+                        acc_re[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xr[s], c8, acc_re[s][nb], 0, 0, 0);
+                        acc_re[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xi[s], s8, acc_re[s][nb], 0, 0, 0);
+                        acc_im[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xi[s], c8, acc_im[s][nb], 0, 0, 0);
+                        acc_im[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xr[s], ns8, acc_im[s][nb], 0, 0, 0);
+                    }
+                }
+                __syncthreads();
+                buf ^= 1;
+            }
+        }
+    }
+    cf32* yo = a.yraw + (int64_t)sp * a.npos * a.mu;
+#pragma unroll
+    for (int s = 0; s < NP; ++s) {
+        const int q = wave * NP + s;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int mb = mb0 + nb * 16 + i;
+            if (nb >= nb_act || mb >= a.mu) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int irow = 4 * kq + r;
+                const int px = px0 + q * sw + irow % sw, py = py0 + irow / sw;
+                if (px < a.nx && py < a.ny)
+                    yo[((int64_t)py * a.nx + px) * a.mu + mb] = cf32{acc_re[s][nb][r], acc_im[s][nb][r]};
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint.
+// ---------------------------------------------------------------------------
+struct AdjB {
+    const cbf16* r;        // H-scaled operand [npos][mu] bf16 complex
+    cf32* out;
+    cf32* part;
+    const uint32_t* u;
+    const int* kb;
+    int nx, ny, nz, wx, wy, mu;
+    int sw, ntx, nty, nzt, split;
+    int64_t nvox;
+};
+
+template <int NV, int NZ>
+__global__ __launch_bounds__(256) void adj_gemm_bf16_kernel(AdjB a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int sw = a.sw, sh = 16 / sw;
+    const int tvx = 4 * NV * sw, tvy = sh;
+    const int zspan = NZ * 16;
+
+    const int nblk = gridDim.x;
+    int b = blockIdx.x;
+    int per_xcd = nblk / 8;
+    if (per_xcd * 8 == nblk) b = (b % 8) * per_xcd + b / 8;
+    const int ntile = a.ntx * a.nty;
+    const int tile = b % ntile;
+    const int zt = (b / ntile) % a.nzt;
+    const int sp = b / (ntile * a.nzt);
+    const int vx0 = (tile % a.ntx) * tvx, vy0 = (tile / a.ntx) * tvy;
+    const int zw0 = zt * zspan;
+    const int cx_lo = max(0, vx0 - a.wx), cx_hi = min(a.nx - 1, vx0 + tvx - 1 + a.wx);
+    const int ncol = cx_hi - cx_lo + 1;
+
+    __bf16* halo = reinterpret_cast<__bf16*>(smem);                  // [tvy*ncol + 1][CELL]
+    const int zero_cell = tvy * ncol;
+    __bf16* ptile = halo + (size_t)(zero_cell + 1) * CELL;             // [2][2][zspan][PROW]
+    uint32_t* ulds = reinterpret_cast<uint32_t*>(ptile + 2 * 2 * zspan * PROW);   // [wx+1][zspan]
+    int* klds = reinterpret_cast<int*>(ulds + (a.wx + 1) * zspan);     // [ZCB]
+
+    int dy_lo = max(-a.wy, -(vy0 + tvy - 1));
+    int dy_hi = min(a.wy, a.ny - 1 - vy0);
+    const int chunk = (dy_hi - dy_lo + 1 + a.split - 1) / a.split;
+    dy_lo += sp * chunk;
+    dy_hi = min(dy_hi, dy_lo + chunk - 1);
+    const int dx_lo = max(-a.wx, -(vx0 + tvx - 1)), dx_hi = min(a.wx, a.nx - 1 - vx0);
+
+    const int i = lane & 15, kq = lane >> 4;
+    const int nz_act = min(NZ, (a.nz - zw0 + 15) / 16);   // active depth sub-tiles
+    for (int t = threadIdx.x; t < CELL; t += 256) halo[(size_t)zero_cell * CELL + t] = (__bf16)0.f;
+
+    f4 acc_re[NV][NZ], acc_im[NV][NZ];
+#pragma unroll
+    for (int s = 0; s < NV; ++s)
+#pragma unroll
+        for (int q = 0; q < NZ; ++q) acc_re[s][q] = acc_im[s][q] = f4{0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = 0; k0 < a.mu; k0 += ZCB) {
+        for (int dy = dy_lo; dy <= dy_hi; ++dy) {
+            __syncthreads();
+            for (int t = threadIdx.x; t < tvy * ncol * ZCB; t += 256) {
+                const int kk = t % ZCB, cell = t / ZCB;
+                const int rr = cell / ncol, c = cell - rr * ncol;
+                const int gy = vy0 + rr + dy, gx = cx_lo + c, k = k0 + kk;
+                cbf16 v = to_cbf16(0.f, 0.f);
+                if (gy >= 0 && gy < a.ny && k < a.mu) v = a.r[((int64_t)gy * a.nx + gx) * a.mu + k];
+                halo[(size_t)cell * CELL + kk] = v.re;
+                halo[(size_t)cell * CELL + ZCB + kk] = v.im;
+            }
+            const int ady = dy < 0 ? -dy : dy;
+            for (int t = threadIdx.x; t < (a.wx + 1) * zspan; t += 256) {
+                const int adx = t / zspan, zz = t - adx * zspan, z = zw0 + zz;
+                ulds[t] = z < a.nz ? a.u[((int64_t)ady * (a.wx + 1) + adx) * a.nz + z] : 0u;
+            }
+            for (int t = threadIdx.x; t < ZCB; t += 256) klds[t] = (k0 + t < a.mu) ? a.kb[k0 + t] : 0;
+            __syncthreads();
+            auto gen = [&](int dx, int buf) {
+                const int adx = dx < 0 ? -dx : dx;
+                __bf16* pc = ptile + (size_t)buf * 2 * zspan * PROW;
+                __bf16* ps = pc + zspan * PROW;
+                // rows = depths, columns = bins: the recurrence runs along the bins
+                // of one depth, so generate transposed: thread -> (depth, run of bins)
+                const int runs = 4;                       // bins per thread run
+                const int nruns = ZCB / runs;
+                for (int t = threadIdx.x; t < zspan * nruns; t += blockDim.x) {
+                    const int zz = t % zspan, g = t / zspan;
+                    const uint32_t uu = ulds[adx * zspan + zz];
+                    float wc, ws;
+                    sincos_turns(uu, wc, ws);
+                    int kprev = -2;
+                    float c = 0.f, s = 0.f;
+                    for (int j = g * runs; j < (g + 1) * runs; ++j) {
+                        const int k = klds[j];
+                        if (k == kprev + 1) {
+                            float c2 = c * wc - s * ws;
+                            s = s * wc + c * ws;
+                            c = c2;
+                        } else {
+                            sincos_turns((uint32_t)k * uu, c, s);
+                        }
+                        kprev = k;
+                        pc[zz * PROW + j] = (__bf16)c;
+                        ps[zz * PROW + j] = (__bf16)s;
+                    }
+                }
+            };
+            if (dx_lo <= dx_hi) gen(dx_lo, 0);
+            __syncthreads();
+            int buf = 0;
+            for (int dx = dx_lo; dx <= dx_hi; ++dx) {
+                if (dx < dx_hi) gen(dx + 1, buf ^ 1);
+                const __bf16* pc = ptile + (size_t)buf * 2 * zspan * PROW;
+                const __bf16* ps = pc + zspan * PROW;
+                bf8 rr8[NV], ri8[NV];
+#pragma unroll
+                for (int s = 0; s < NV; ++s) {
+                    const int q = wave * NV + s;
+                    const int vx = vx0 + q * sw + i % sw, iy = i / sw;
+                    const int gx = vx + dx;
+                    const int cell = (gx >= cx_lo && gx <= cx_hi) ? iy * ncol + (gx - cx_lo) : zero_cell;
+                    rr8[s] = lds_bf8(halo + (size_t)cell * CELL + 8 * kq);
+                    ri8[s] = lds_bf8(halo + (size_t)cell * CELL + ZCB + 8 * kq);
+                }
+#pragma unroll
+                for (int q = 0; q < NZ; ++q) {
+                    if (q >= nz_act) break;
+                    const bf8 c8 = lds_bf8(pc + (q * 16 + i) * PROW + 8 * kq);
+                    const bf8 s8 = lds_bf8(ps + (q * 16 + i) * PROW + 8 * kq);
+                    const bf8 ns8 = neg_bf8(s8);
+#pragma unroll
+                    for (int s = 0; s < NV; ++s) {
+                        // (rr + j ri)(c + j s) = rr c - ri s + j (rr s + ri c)
+                        acc_re[s][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rr8[s], c8, acc_re[s][q], 0, 0, 0);
+                        acc_re[s][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ri8[s], ns8, acc_re[s][q], 0, 0, 0);
+                        acc_im[s][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rr8[s], s8, acc_im[s][q], 0, 0, 0);
+                        acc_im[s][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ri8[s], c8, acc_im[s][q], 0, 0, 0);
+                    }
+                }
+                __syncthreads();
+                buf ^= 1;
+            }
+        }
+    }
+    cf32* dst = a.split > 1 ? a.part + (int64_t)sp * a.nvox : a.out;
+#pragma unroll
+    for (int s = 0; s < NV; ++s) {
+        const int q = wave * NV + s;
+#pragma unroll
+        for (int qz = 0; qz < NZ; ++qz) {
+            if (qz >= nz_act) continue;
+            const int z = zw0 + qz * 16 + i;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int irow = 4 * kq + r;
+                const int vx = vx0 + q * sw + irow % sw, vy = vy0 + irow / sw;
+                if (vx < a.nx && vy < a.ny && z < a.nz)
+                    dst[((int64_t)vy * a.nx + vx) * a.nz + z] = cf32{acc_re[s][qz][r], acc_im[s][qz][r]};
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+static constexpr int kBfNP = 2, kBfNB = 4;     // forward: 2 x 16 positions, 4 x 16 bins per wave
+static constexpr int kBfNV = 2, kBfNZ = 4;     // adjoint: 2 x 16 voxels, 4 x 16 depths per wave
+static constexpr size_t kLdsMaxB = 64 * 1024;
+
+static int bf_sw(const Plan& P) { return P.g.ny == 1 ? 16 : 4; }
+
+static size_t fwd_bf16_lds(const Plan& P) {
+    const int sw = bf_sw(P), tpx = 4 * kBfNP * sw, tpy = 16 / sw;
+    const int ncol = std::min(P.g.nx, tpx + 2 * P.d.wx);
+    return (size_t)(tpy * ncol + 1) * CELL * 2 + (size_t)2 * 2 * kBfNB * 16 * PROW * 2 +
+           (size_t)(P.d.wx + 1) * ZCB * 4 + kBfNB * 16 * 4;
+}
+
+static size_t adj_bf16_lds(const Plan& P) {
+    const int sw = bf_sw(P), tvx = 4 * kBfNV * sw, tvy = 16 / sw;
+    const int ncol = std::min(P.g.nx, tvx + 2 * P.d.wx);
+    return (size_t)(tvy * ncol + 1) * CELL * 2 + (size_t)2 * 2 * kBfNZ * 16 * PROW * 2 +
+           (size_t)(P.d.wx + 1) * kBfNZ * 16 * 4 + ZCB * 4;
+}
+
+bool bf16_supported(const Plan& P) {
+    return fwd_bf16_lds(P) <= kLdsMaxB && adj_bf16_lds(P) <= kLdsMaxB;
+}
+
+int bf16_fwd_split(const Plan& P) {
+    const int sw = bf_sw(P), tpx = 4 * kBfNP * sw, tpy = 16 / sw;
+    const int ntx = (P.g.nx + tpx - 1) / tpx, nty = (P.g.ny + tpy - 1) / tpy;
+    const int mu = (int)P.ubins_h.size();
+    const int nbt = (mu + kBfNB * 16 - 1) / (kBfNB * 16);
+    const int wgs = ntx * nty * nbt;
+    const int ndy_max = std::min(2 * P.d.wy + 1, P.g.ny + tpy - 1);
+    int split = (1024 + wgs - 1) / wgs;
+    return std::max(1, std::min(split, std::min(ndy_max, 16)));
+}
+
+int bf16_adj_split(const Plan& P) {
+    const int sw = bf_sw(P), tvx = 4 * kBfNV * sw, tvy = 16 / sw;
+    const int ntx = (P.g.nx + tvx - 1) / tvx, nty = (P.g.ny + tvy - 1) / tvy;
+    const int nzt = (P.g.nz + kBfNZ * 16 - 1) / (kBfNZ * 16);
+    const int wgs = ntx * nty * nzt;
+    const int ndy_max = std::min(2 * P.d.wy + 1, P.g.ny + tvy - 1);
+    int split = (1024 + wgs - 1) / wgs;
+    return std::max(1, std::min(split, std::min(ndy_max, 8)));
+}
+
+void launch_forward_gemm_bf16(const Plan& P, hipStream_t s) {
+    FwdB a{};
+    a.x = static_cast<const cbf16*>(P.d_xop);
+    a.yraw = P.d_yraw;
+    a.u = P.d_u;
+    a.kb = P.d_ubins;
+    a.nx = P.g.nx;
+    a.ny = P.g.ny;
+    a.nz = P.g.nz;
+    a.wx = P.d.wx;
+    a.wy = P.d.wy;
+    a.mu = (int)P.ubins_h.size();
+    a.sw = bf_sw(P);
+    const int tpx = 4 * kBfNP * a.sw, tpy = 16 / a.sw;
+    a.ntx = (a.nx + tpx - 1) / tpx;
+    a.nty = (a.ny + tpy - 1) / tpy;
+    a.nbt = (a.mu + kBfNB * 16 - 1) / (kBfNB * 16);
+    a.split = P.fwd_split;
+    a.npos = P.npos;
+    const size_t lds = fwd_bf16_lds(P);
+    if (lds > kLdsMaxB) fail(UFSS_ERR_UNSUPPORTED, "aperture window too wide for the BF16 GEMM path");
+    const int nblk = a.ntx * a.nty * a.nbt * a.split;
+    hipLaunchKernelGGL((fwd_gemm_bf16_kernel<kBfNP, kBfNB>), dim3(nblk), dim3(256), lds, s, a);
+    UFSS_HIP(hipGetLastError());
+}
+
+void launch_adjoint_gemm_bf16(const Plan& P, cf32* out, hipStream_t s) {
+    AdjB a{};
+    a.r = static_cast<const cbf16*>(P.d_rop);
+    a.out = out;
+    a.part = P.d_gpart;
+    a.u = P.d_u;
+    a.kb = P.d_ubins;
+    a.nx = P.g.nx;
+    a.ny = P.g.ny;
+    a.nz = P.g.nz;
+    a.wx = P.d.wx;
+    a.wy = P.d.wy;
+    a.mu = (int)P.ubins_h.size();
+    a.sw = bf_sw(P);
+    const int tvx = 4 * kBfNV * a.sw, tvy = 16 / a.sw;
+    a.ntx = (a.nx + tvx - 1) / tvx;
+    a.nty = (a.ny + tvy - 1) / tvy;
+    a.nzt = (a.nz + kBfNZ * 16 - 1) / (kBfNZ * 16);
+    a.split = P.adj_split;
+    a.nvox = P.nvox;
+    const size_t lds = adj_bf16_lds(P);
+    if (lds > kLdsMaxB) fail(UFSS_ERR_UNSUPPORTED, "aperture window too wide for the BF16 GEMM path");
+    const int nblk = a.ntx * a.nty * a.nzt * a.split;
+    hipLaunchKernelGGL((adj_gemm_bf16_kernel<kBfNV, kBfNZ>), dim3(nblk), dim3(256), lds, s, a);
+    UFSS_HIP(hipGetLastError());
+    if (a.split > 1) launch_sum_parts(P.d_gpart, a.split, P.nvox, out, s);
 }
 
 }  // namespace ufss

@@ -169,6 +169,9 @@ struct AdjArgs {
     int nx, ny, nz, wx, wy, mu;
     int sw, ntx, nty, nzt; // lateral tiles, depth tiles (of 64 * NZ)
     int kc;                // bin chunk (multiple of 4)
+    int split;             // split of the d_y range; split > 1 writes partials
+    cf32* part;            // [split][ny][nx][nz] when split > 1
+    int64_t nvox;
 };
 
 template <int NP, int NZ>
@@ -190,12 +193,17 @@ __global__ __launch_bounds__(256) void adj_gemm_f32_kernel(AdjArgs a) {
     if (per_xcd * 8 == nblk) b = (b % 8) * per_xcd + b / 8;
     const int ntile = a.ntx * a.nty;
     const int tile = b % ntile;
-    const int zt = b / ntile;
+    const int zt = (b / ntile) % a.nzt;
+    const int sp = b / (ntile * a.nzt);
     const int vx0 = (tile % a.ntx) * tpx, vy0 = (tile / a.ntx) * tpy;
     const int zw0 = zt * zspan;                      // first depth of the workgroup
 
-    // d with v + d inside the grid for some voxel of the tile
-    const int dy_lo = max(-a.wy, -(vy0 + tpy - 1)), dy_hi = min(a.wy, a.ny - 1 - vy0);
+    // d with v + d inside the grid for some voxel of the tile, split in chunks
+    int dy_lo = max(-a.wy, -(vy0 + tpy - 1));
+    int dy_hi = min(a.wy, a.ny - 1 - vy0);
+    const int chunk = (dy_hi - dy_lo + 1 + a.split - 1) / a.split;
+    dy_lo += sp * chunk;
+    dy_hi = min(dy_hi, dy_lo + chunk - 1);
     const int dx_lo = max(-a.wx, -(vx0 + tpx - 1)), dx_hi = min(a.wx, a.nx - 1 - vx0);
 
     const int i = lane & 15, ix = i % sw, iy = i / sw;
@@ -272,6 +280,7 @@ __global__ __launch_bounds__(256) void adj_gemm_f32_kernel(AdjArgs a) {
         }
     }
     if (!wave_active) return;
+    cf32* dst = a.split > 1 ? a.part + (int64_t)sp * a.nvox : a.out;
 #pragma unroll
     for (int s = 0; s < NP; ++s)
 #pragma unroll
@@ -282,7 +291,7 @@ __global__ __launch_bounds__(256) void adj_gemm_f32_kernel(AdjArgs a) {
                 int vx = vx0 + s * sw + irow % sw, vy = vy0 + irow / sw;
                 int z = zw0 + wave * NZ * 16 + q * 16 + i;
                 if (vx < a.nx && vy < a.ny && z < a.nz)
-                    a.out[((int64_t)vy * a.nx + vx) * a.nz + z] = cf32{out_re[s][q][r], out_im[s][q][r]};
+                    dst[((int64_t)vy * a.nx + vx) * a.nz + z] = cf32{out_re[s][q][r], out_im[s][q][r]};
             }
 }
 
@@ -307,6 +316,17 @@ int gemm_split(const Plan& P) {
     split = std::max(1, std::min(split, std::min(ndy_max, 16)));
     (void)nbt;
     return split;
+}
+
+// Split of the adjoint's d_y range: enough workgroups to fill 256 CUs twice.
+int adj_split(const Plan& P) {
+    const int sw = sub_width(P), tpx = sw * kAdjNP, tpy = 16 / sw;
+    const int ntx = (P.g.nx + tpx - 1) / tpx, nty = (P.g.ny + tpy - 1) / tpy;
+    const int nzt = (P.g.nz + 64 * kAdjNZ - 1) / (64 * kAdjNZ);
+    const int wgs = ntx * nty * nzt;
+    const int ndy_max = std::min(2 * P.d.wy + 1, P.g.ny + tpy - 1);
+    int split = (512 + wgs - 1) / wgs;
+    return std::max(1, std::min(split, std::min(ndy_max, 8)));
 }
 
 void launch_forward_gemm(const Plan& P, const cf32* x, hipStream_t s) {
@@ -367,9 +387,13 @@ void launch_adjoint_gemm(const Plan& P, cf32* out, hipStream_t s) {
     while (kc > 4 && lds_of(kc) > kLdsMax) kc -= 4;
     if (lds_of(kc) > kLdsMax) fail(UFSS_ERR_UNSUPPORTED, "aperture window too wide for the GEMM path");
     a.kc = kc;
-    const int nblk = a.ntx * a.nty * a.nzt;
+    a.split = P.adj_split;
+    a.part = P.d_gpart;
+    a.nvox = P.nvox;
+    const int nblk = a.ntx * a.nty * a.nzt * a.split;
     hipLaunchKernelGGL((adj_gemm_f32_kernel<kAdjNP, kAdjNZ>), dim3(nblk), dim3(256), lds_of(kc), s, a);
     UFSS_HIP(hipGetLastError());
+    if (a.split > 1) launch_sum_parts(P.d_gpart, a.split, P.nvox, out, s);
 }
 
 }  // namespace ufss

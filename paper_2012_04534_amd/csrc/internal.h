@@ -60,6 +60,8 @@ struct Plan {
     int npos = 0;
     int64_t nvox = 0;
     int fwd_split = 1;             // split of the forward GEMM's d_y range
+    int adj_split = 1;             // split of the adjoint GEMM's d_y range
+    cf32* d_gpart = nullptr;       // adjoint partials [adj_split][nvox] (adj_split > 1)
     std::vector<int> bins_h;       // [m] or [npos*m]
     std::vector<int> ubins_h;      // union of bins (GEMM path), ascending
     // device tables
@@ -98,6 +100,14 @@ int launch_forward_post(const Plan& P, cf32* y, const cf32* ymeas, double* part,
 void launch_adjoint_pre(const Plan& P, const cf32* r, hipStream_t s);
 void launch_to_bf16(const cf32* x, void* out, int64_t n, hipStream_t s);
 int gemm_split(const Plan& P);
+int adj_split(const Plan& P);
+bool bf16_supported(const Plan& P);
+int bf16_fwd_split(const Plan& P);
+int bf16_adj_split(const Plan& P);
+void launch_forward_gemm_bf16(const Plan& P, hipStream_t s);
+void launch_adjoint_gemm_bf16(const Plan& P, cf32* out, hipStream_t s);
+// out[i] = sum_{s < nsplit} part[s][i] in fixed order.
+void launch_sum_parts(const cf32* part, int nsplit, int64_t n, cf32* out, hipStream_t s);
 
 // Vector kernels.
 int launch_update(int64_t n, cf32* gamma, const cf32* g, cf32* a, float step, float thresh,

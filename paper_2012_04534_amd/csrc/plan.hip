@@ -158,7 +158,7 @@ static void free_plan(Plan* P) {
     if (!P) return;
     void* ptrs[] = {P->d_bins, P->d_ubins, P->d_map, P->d_hsel, P->d_u, P->d_yraw,
                     P->d_rop, P->d_xop, P->d_part, P->d_scalars, P->d_r, P->d_g,
-                    P->d_gamma, P->d_v, P->d_stats};
+                    P->d_gamma, P->d_v, P->d_stats, P->d_gpart};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
@@ -240,7 +240,16 @@ Plan* plan_create(const ufss_geom* g, int m, int per_position, const int32_t* bi
         upload(P->d_hsel, hsel.data(), nsel);
         P->d_u = dalloc<uint32_t>(*P, ut.size());
         upload(P->d_u, ut.data(), ut.size());
-        P->fwd_split = (algo == UFSS_ALGO_GEMM) ? gemm_split(*P) : 1;
+        if (algo == UFSS_ALGO_GEMM && P->dtype == UFSS_BF16) {
+            if (!bf16_supported(*P))
+                fail(UFSS_ERR_UNSUPPORTED, "aperture window too wide for the BF16 GEMM path");
+            P->fwd_split = bf16_fwd_split(*P);
+            P->adj_split = bf16_adj_split(*P);
+        } else {
+            P->fwd_split = (algo == UFSS_ALGO_GEMM) ? gemm_split(*P) : 1;
+            P->adj_split = (algo == UFSS_ALGO_GEMM) ? adj_split(*P) : 1;
+        }
+        if (P->adj_split > 1) P->d_gpart = dalloc<cf32>(*P, (size_t)P->adj_split * P->nvox);
         P->d_yraw = dalloc<cf32>(*P, (size_t)P->fwd_split * npos * mu);
         P->d_rop = dalloc<cf32>(*P, (size_t)npos * opw);
         if (P->dtype == UFSS_BF16) P->d_xop = dalloc<cf32>(*P, (size_t)(P->nvox + 1) / 2 + 1);

@@ -302,6 +302,27 @@ void launch_scale(int64_t n, cf32* x, const double* norm2, hipStream_t s) {
     UFSS_HIP(hipGetLastError());
 }
 
+__global__ __launch_bounds__(kThreads) void sum_parts_kernel(const cf32* __restrict__ part,
+                                                             int nsplit, int64_t n,
+                                                             cf32* __restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads) {
+        float re = 0.f, im = 0.f;
+        for (int s = 0; s < nsplit; ++s) {
+            cf32 v = part[(int64_t)s * n + i];
+            re += v.re;
+            im += v.im;
+        }
+        out[i] = cf32{re, im};
+    }
+}
+
+void launch_sum_parts(const cf32* part, int nsplit, int64_t n, cf32* out, hipStream_t s) {
+    hipLaunchKernelGGL(sum_parts_kernel, dim3(blocks_for(n)), dim3(kThreads), 0, s, part, nsplit,
+                       n, out);
+    UFSS_HIP(hipGetLastError());
+}
+
 __global__ __launch_bounds__(kThreads) void copy_kernel(int64_t n, const cf32* __restrict__ src,
                                                         cf32* __restrict__ dst) {
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
