@@ -79,6 +79,7 @@ typedef struct ufss_plan_info {
     int32_t m, per_position, dtype, algo; /* algo actually used                */
     int32_t union_size;   /* bins in the union of per-position subsets         */
     int64_t workspace_bytes;              /* device memory owned by the plan    */
+    int32_t fwd_split, adj_split;         /* split-K factors of the GEMM path   */
 } ufss_plan_info;
 
 /* Per-iteration FISTA statistics, FP64, written to HOST arrays of length
@@ -197,6 +198,33 @@ int ufss_shrink_update(int64_t n, void* gamma, const void* g, void* a,
 /* max_v |x_v| over n complex entries (FP32 values, exact max), for the lambda
  * rule.  out HOST double.  Synchronises `stream`. */
 int ufss_absmax(int64_t n, const void* x, double* out, ufss_stream_t stream);
+
+/* Batched FISTA over n independent scans of uneven size (each with its own
+ * plan), paper Alg. 1 applied to every scan.  Each phase of an iteration runs
+ * as ONE grouped launch over all scans (forward GEMM, residual epilogue,
+ * adjoint pre pass, adjoint GEMM, split sums, fused update, FP64 reductions),
+ * and the `iters` iterations are captured in one hipGraph and launched once on
+ * `stream`.  Plans must use the GEMM algorithm (any dtype); a plan may appear
+ * only once.
+ *   ys[i]      DEVICE complex64 [ny][nx][m] of plan i
+ *   xs[i]      DEVICE complex64 [ny][nx][nz]: in = a_0, out = a_iters
+ *   lambdas[i] > 0 used as is; < 0: -lambdas[i] * max|A_i^H y_i|   (HOST array)
+ *   Ls[i]      > 0 used as is; <= 0: the plan's cached constant      (HOST array)
+ *   res_out    HOST double [n] or NULL: final ||A gamma - y|| per scan
+ * Synchronises `stream`.  Returns UFSS_ERR_DIVERGED if any scan diverges. */
+int ufss_fista_batched(int32_t n, const ufss_plan_t* plans, const void* const* ys,
+                       void* const* xs, const double* lambdas, const double* Ls,
+                       int32_t iters, double* res_out, ufss_stream_t stream);
+
+/* Autotuner for the GEMM path: times every candidate split-K factor of the
+ * forward and adjoint GEMMs of this plan's shape with HIP events, keeps the
+ * fastest pair in the plan and, with flags bit 1, appends it to the JSON cache
+ * file `cache_path` (keyed by the shape class); with flags bit 0 a cached entry
+ * is used without timing.  Overwrites the plan's internal workspace; no effect
+ * for phasor plans.  Synchronises `stream`.
+ *   fwd_split_out, adj_split_out  HOST, optional */
+int ufss_autotune(ufss_plan_t plan, const char* cache_path, int32_t flags,
+                  int32_t* fwd_split_out, int32_t* adj_split_out, ufss_stream_t stream);
 
 /* Diagnostic: average duration (ms) of the operator's core kernel, launched
  * `reps` times back to back between two HIP events recorded on `stream`.

@@ -18,6 +18,11 @@ void select_freqs(const ufss_geom* g, int m, int per_position, uint64_t seed, in
                   int32_t* band_size);
 const char* last_error();
 int phasor_forward_blocks(const Plan& P);
+int fista_batched(int n, Plan* const* plans, const cf32* const* ys, cf32* const* xs,
+                  const double* lambdas, const double* Ls, int iters, hipStream_t stream,
+                  double* res_out);
+int autotune(Plan& P, const char* cache_path, int flags, hipStream_t s, int32_t* fs_out,
+             int32_t* as_out);
 void launch_forward_gemm_bf16(const Plan& P, hipStream_t s);
 void launch_adjoint_gemm_bf16(const Plan& P, cf32* out, hipStream_t s);
 
@@ -322,6 +327,28 @@ int ufss_shrink_update(int64_t n, void* gamma, const void* g, void* a, double st
     }
     UFSS_HIP(hipFree(part));
     UFSS_HIP(hipFree(out));
+    UFSS_GUARD_END
+}
+
+int ufss_fista_batched(int32_t n, const ufss_plan_t* plans, const void* const* ys, void* const* xs,
+                       const double* lambdas, const double* Ls, int32_t iters, double* res_out,
+                       ufss_stream_t stream) {
+    UFSS_GUARD_BEGIN
+    if (n < 1 || !plans || !ys || !xs) ufss::fail(UFSS_ERR_INVALID_ARG, "bad batch arrays");
+    std::vector<Plan*> ps(n);
+    for (int i = 0; i < n; ++i) ps[i] = as_plan(plans[i]);
+    return ufss::fista_batched(n, ps.data(), reinterpret_cast<const ufss::cf32* const*>(ys),
+                               reinterpret_cast<ufss::cf32* const*>(xs), lambdas, Ls, iters,
+                               static_cast<hipStream_t>(stream), res_out);
+    UFSS_GUARD_END
+}
+
+int ufss_autotune(ufss_plan_t plan, const char* cache_path, int32_t flags, int32_t* fwd_split_out,
+                  int32_t* adj_split_out, ufss_stream_t stream) {
+    UFSS_GUARD_BEGIN
+    Plan* P = as_plan(plan);
+    ufss::autotune(*P, cache_path, flags, static_cast<hipStream_t>(stream), fwd_split_out,
+                   adj_split_out);
     UFSS_GUARD_END
 }
 

@@ -95,17 +95,15 @@ struct FwdB {
     int nx, ny, nz, wx, wy, mu;
     int sw, ntx, nty, nbt, split;
     int64_t npos;
+    int nblk;              // blocks of this plan's grid
 };
 
 template <int NP, int NB>
-__global__ __launch_bounds__(256) void fwd_gemm_bf16_kernel(FwdB a) {
-    extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nblk, unsigned char* smem) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int sw = a.sw, sh = 16 / sw;
     const int tpx = 4 * NP * sw, tpy = sh;
 
-    const int nblk = gridDim.x;
-    int b = blockIdx.x;
     int per_xcd = nblk / 8;
     if (per_xcd * 8 == nblk) b = (b % 8) * per_xcd + b / 8;
     const int ntile = a.ntx * a.nty;
@@ -229,6 +227,22 @@ __global__ __launch_bounds__(256) void fwd_gemm_bf16_kernel(FwdB a) {
     }
 }
 
+template <int NP, int NB>
+__global__ __launch_bounds__(256) void fwd_gemm_bf16_kernel(FwdB a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    fwd_bf16_body<NP, NB>(a, blockIdx.x, gridDim.x, smem);
+}
+
+// Grouped launch: block -> (plan index, block index inside that plan's grid).
+template <int NP, int NB>
+__global__ __launch_bounds__(256) void fwd_gemm_bf16_kernel_grouped(const FwdB* __restrict__ descs,
+                                                 const int2* __restrict__ blk) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int2 sb = blk[blockIdx.x];
+    const FwdB a = descs[sb.x];
+    fwd_bf16_body<NP, NB>(a, sb.y, a.nblk, smem);
+}
+
 // ---------------------------------------------------------------------------
 // Adjoint.
 // ---------------------------------------------------------------------------
@@ -241,18 +255,16 @@ struct AdjB {
     int nx, ny, nz, wx, wy, mu;
     int sw, ntx, nty, nzt, split;
     int64_t nvox;
+    int nblk;              // blocks of this plan's grid
 };
 
 template <int NV, int NZ>
-__global__ __launch_bounds__(256) void adj_gemm_bf16_kernel(AdjB a) {
-    extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nblk, unsigned char* smem) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int sw = a.sw, sh = 16 / sw;
     const int tvx = 4 * NV * sw, tvy = sh;
     const int zspan = NZ * 16;
 
-    const int nblk = gridDim.x;
-    int b = blockIdx.x;
     int per_xcd = nblk / 8;
     if (per_xcd * 8 == nblk) b = (b % 8) * per_xcd + b / 8;
     const int ntile = a.ntx * a.nty;
@@ -392,6 +404,22 @@ __global__ __launch_bounds__(256) void adj_gemm_bf16_kernel(AdjB a) {
     }
 }
 
+template <int NV, int NZ>
+__global__ __launch_bounds__(256) void adj_gemm_bf16_kernel(AdjB a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    adj_bf16_body<NV, NZ>(a, blockIdx.x, gridDim.x, smem);
+}
+
+// Grouped launch: block -> (plan index, block index inside that plan's grid).
+template <int NV, int NZ>
+__global__ __launch_bounds__(256) void adj_gemm_bf16_kernel_grouped(const AdjB* __restrict__ descs,
+                                                 const int2* __restrict__ blk) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int2 sb = blk[blockIdx.x];
+    const AdjB a = descs[sb.x];
+    adj_bf16_body<NV, NZ>(a, sb.y, a.nblk, smem);
+}
+
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
@@ -440,8 +468,8 @@ int bf16_adj_split(const Plan& P) {
     return std::max(1, std::min(split, std::min(ndy_max, 8)));
 }
 
-void launch_forward_gemm_bf16(const Plan& P, hipStream_t s) {
-    FwdB a{};
+static int fwdb_args(const Plan& P, FwdB& a, size_t& lds) {
+    a = FwdB{};
     a.x = static_cast<const cbf16*>(P.d_xop);
     a.yraw = P.d_yraw;
     a.u = P.d_u;
@@ -459,15 +487,14 @@ void launch_forward_gemm_bf16(const Plan& P, hipStream_t s) {
     a.nbt = (a.mu + kBfNB * 16 - 1) / (kBfNB * 16);
     a.split = P.fwd_split;
     a.npos = P.npos;
-    const size_t lds = fwd_bf16_lds(P);
+    lds = fwd_bf16_lds(P);
     if (lds > kLdsMaxB) fail(UFSS_ERR_UNSUPPORTED, "aperture window too wide for the BF16 GEMM path");
-    const int nblk = a.ntx * a.nty * a.nbt * a.split;
-    hipLaunchKernelGGL((fwd_gemm_bf16_kernel<kBfNP, kBfNB>), dim3(nblk), dim3(256), lds, s, a);
-    UFSS_HIP(hipGetLastError());
+    a.nblk = a.ntx * a.nty * a.nbt * a.split;
+    return a.nblk;
 }
 
-void launch_adjoint_gemm_bf16(const Plan& P, cf32* out, hipStream_t s) {
-    AdjB a{};
+static int adjb_args(const Plan& P, cf32* out, AdjB& a, size_t& lds) {
+    a = AdjB{};
     a.r = static_cast<const cbf16*>(P.d_rop);
     a.out = out;
     a.part = P.d_gpart;
@@ -486,12 +513,46 @@ void launch_adjoint_gemm_bf16(const Plan& P, cf32* out, hipStream_t s) {
     a.nzt = (a.nz + kBfNZ * 16 - 1) / (kBfNZ * 16);
     a.split = P.adj_split;
     a.nvox = P.nvox;
-    const size_t lds = adj_bf16_lds(P);
+    lds = adj_bf16_lds(P);
     if (lds > kLdsMaxB) fail(UFSS_ERR_UNSUPPORTED, "aperture window too wide for the BF16 GEMM path");
-    const int nblk = a.ntx * a.nty * a.nzt * a.split;
-    hipLaunchKernelGGL((adj_gemm_bf16_kernel<kBfNV, kBfNZ>), dim3(nblk), dim3(256), lds, s, a);
+    a.nblk = a.ntx * a.nty * a.nzt * a.split;
+    return a.nblk;
+}
+
+void launch_forward_gemm_bf16(const Plan& P, hipStream_t s) {
+    FwdB a;
+    size_t lds;
+    fwdb_args(P, a, lds);
+    hipLaunchKernelGGL((fwd_gemm_bf16_kernel<kBfNP, kBfNB>), dim3(a.nblk), dim3(256), lds, s, a);
+    UFSS_HIP(hipGetLastError());
+}
+
+void launch_adjoint_gemm_bf16(const Plan& P, cf32* out, hipStream_t s) {
+    AdjB a;
+    size_t lds;
+    adjb_args(P, out, a, lds);
+    hipLaunchKernelGGL((adj_gemm_bf16_kernel<kBfNV, kBfNZ>), dim3(a.nblk), dim3(256), lds, s, a);
     UFSS_HIP(hipGetLastError());
     if (a.split > 1) launch_sum_parts(P.d_gpart, a.split, P.nvox, out, s);
+}
+
+size_t bf16_desc_size(GemmKind k) { return k == GemmKind::FwdBF16 ? sizeof(FwdB) : sizeof(AdjB); }
+
+int bf16_make_desc(GemmKind k, const Plan& P, const void* in, void* out, void* desc, size_t* lds) {
+    (void)in;
+    if (k == GemmKind::FwdBF16) return fwdb_args(P, *static_cast<FwdB*>(desc), *lds);
+    return adjb_args(P, static_cast<cf32*>(out), *static_cast<AdjB*>(desc), *lds);
+}
+
+void bf16_launch_grouped(GemmKind k, const void* descs, const int2* blk, int nblocks, size_t lds,
+                         hipStream_t s) {
+    if (k == GemmKind::FwdBF16)
+        hipLaunchKernelGGL((fwd_gemm_bf16_kernel_grouped<kBfNP, kBfNB>), dim3(nblocks), dim3(256), lds,
+                           s, static_cast<const FwdB*>(descs), blk);
+    else
+        hipLaunchKernelGGL((adj_gemm_bf16_kernel_grouped<kBfNV, kBfNZ>), dim3(nblocks), dim3(256), lds,
+                           s, static_cast<const AdjB*>(descs), blk);
+    UFSS_HIP(hipGetLastError());
 }
 
 }  // namespace ufss

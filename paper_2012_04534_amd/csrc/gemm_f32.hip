@@ -53,11 +53,11 @@ struct FwdArgs {
     int zc;                // depth chunk (multiple of 4)
     int split;             // split of the d_y range
     int64_t npos;
+    int nblk;              // blocks of this plan's grid
 };
 
 template <int NP>
-__global__ __launch_bounds__(256) void fwd_gemm_f32_kernel(FwdArgs a) {
-    extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int nblk, unsigned char* smem) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int sw = a.sw, sh = 16 / sw;
     const int tpx = sw * NP, tpy = sh;
@@ -68,8 +68,6 @@ __global__ __launch_bounds__(256) void fwd_gemm_f32_kernel(FwdArgs a) {
 
     // block -> (split, bin tile, lateral tile); consecutive tiles of one split
     // and bin tile stay on one XCD (blocks are dealt round-robin to 8 XCDs).
-    const int nblk = gridDim.x;
-    int b = blockIdx.x;
     int per_xcd = nblk / 8;
     if (per_xcd * 8 == nblk) b = (b % 8) * per_xcd + b / 8;
     const int ntile = a.ntx * a.nty;
@@ -161,6 +159,22 @@ __global__ __launch_bounds__(256) void fwd_gemm_f32_kernel(FwdArgs a) {
     }
 }
 
+template <int NP>
+__global__ __launch_bounds__(256) void fwd_gemm_f32_kernel(FwdArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    fwd_f32_body<NP>(a, blockIdx.x, gridDim.x, smem);
+}
+
+// Grouped launch: block -> (plan index, block index inside that plan's grid).
+template <int NP>
+__global__ __launch_bounds__(256) void fwd_gemm_f32_kernel_grouped(const FwdArgs* __restrict__ descs,
+                                                 const int2* __restrict__ blk) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int2 sb = blk[blockIdx.x];
+    const FwdArgs a = descs[sb.x];
+    fwd_f32_body<NP>(a, sb.y, a.nblk, smem);
+}
+
 struct AdjArgs {
     const cf32* r;         // H-scaled operand [npos][mu]
     cf32* out;             // [ny][nx][nz]
@@ -172,11 +186,11 @@ struct AdjArgs {
     int split;             // split of the d_y range; split > 1 writes partials
     cf32* part;            // [split][ny][nx][nz] when split > 1
     int64_t nvox;
+    int nblk;              // blocks of this plan's grid
 };
 
 template <int NP, int NZ>
-__global__ __launch_bounds__(256) void adj_gemm_f32_kernel(AdjArgs a) {
-    extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int nblk, unsigned char* smem) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int sw = a.sw, sh = 16 / sw;
     const int tpx = sw * NP, tpy = sh;
@@ -187,8 +201,6 @@ __global__ __launch_bounds__(256) void adj_gemm_f32_kernel(AdjArgs a) {
     uint32_t* ulds = reinterpret_cast<uint32_t*>(halo + (size_t)tpy * hc * cs);
     int* klds = reinterpret_cast<int*>(ulds + (size_t)(a.wx + 1) * zspan);
 
-    const int nblk = gridDim.x;
-    int b = blockIdx.x;
     int per_xcd = nblk / 8;
     if (per_xcd * 8 == nblk) b = (b % 8) * per_xcd + b / 8;
     const int ntile = a.ntx * a.nty;
@@ -295,6 +307,22 @@ __global__ __launch_bounds__(256) void adj_gemm_f32_kernel(AdjArgs a) {
             }
 }
 
+template <int NP, int NZ>
+__global__ __launch_bounds__(256) void adj_gemm_f32_kernel(AdjArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    adj_f32_body<NP, NZ>(a, blockIdx.x, gridDim.x, smem);
+}
+
+// Grouped launch: block -> (plan index, block index inside that plan's grid).
+template <int NP, int NZ>
+__global__ __launch_bounds__(256) void adj_gemm_f32_kernel_grouped(const AdjArgs* __restrict__ descs,
+                                                 const int2* __restrict__ blk) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int2 sb = blk[blockIdx.x];
+    const AdjArgs a = descs[sb.x];
+    adj_f32_body<NP, NZ>(a, sb.y, a.nblk, smem);
+}
+
 // ---------------------------------------------------------------------------
 // Host launchers.
 // ---------------------------------------------------------------------------
@@ -329,8 +357,9 @@ int adj_split(const Plan& P) {
     return std::max(1, std::min(split, std::min(ndy_max, 8)));
 }
 
-void launch_forward_gemm(const Plan& P, const cf32* x, hipStream_t s) {
-    FwdArgs a{};
+// Descriptor of one plan's forward GEMM launch; returns the block count.
+static int fwd_args(const Plan& P, const cf32* x, FwdArgs& a, size_t& lds) {
+    a = FwdArgs{};
     a.x = x;
     a.yraw = P.d_yraw;
     a.u = P.d_u;
@@ -352,16 +381,15 @@ void launch_forward_gemm(const Plan& P, const cf32* x, hipStream_t s) {
     int zc = 16;
     while (zc > 4 && (size_t)tpy * hc * (zc + 1) * sizeof(cf32) + (size_t)(a.wx + 1) * zc * 4 > kLdsMax)
         zc -= 4;
-    size_t lds = (size_t)tpy * hc * (zc + 1) * sizeof(cf32) + (size_t)(a.wx + 1) * zc * 4;
+    lds = (size_t)tpy * hc * (zc + 1) * sizeof(cf32) + (size_t)(a.wx + 1) * zc * 4;
     if (lds > kLdsMax) fail(UFSS_ERR_UNSUPPORTED, "aperture window too wide for the GEMM path");
     a.zc = zc;
-    const int nblk = a.ntx * a.nty * a.nbt * a.split;
-    hipLaunchKernelGGL(fwd_gemm_f32_kernel<kFwdNP>, dim3(nblk), dim3(256), lds, s, a);
-    UFSS_HIP(hipGetLastError());
+    a.nblk = a.ntx * a.nty * a.nbt * a.split;
+    return a.nblk;
 }
 
-void launch_adjoint_gemm(const Plan& P, cf32* out, hipStream_t s) {
-    AdjArgs a{};
+static int adj_args(const Plan& P, cf32* out, AdjArgs& a, size_t& lds) {
+    a = AdjArgs{};
     a.r = static_cast<const cf32*>(P.d_rop);
     a.out = out;
     a.u = P.d_u;
@@ -387,13 +415,65 @@ void launch_adjoint_gemm(const Plan& P, cf32* out, hipStream_t s) {
     while (kc > 4 && lds_of(kc) > kLdsMax) kc -= 4;
     if (lds_of(kc) > kLdsMax) fail(UFSS_ERR_UNSUPPORTED, "aperture window too wide for the GEMM path");
     a.kc = kc;
+    lds = lds_of(kc);
     a.split = P.adj_split;
     a.part = P.d_gpart;
     a.nvox = P.nvox;
-    const int nblk = a.ntx * a.nty * a.nzt * a.split;
-    hipLaunchKernelGGL((adj_gemm_f32_kernel<kAdjNP, kAdjNZ>), dim3(nblk), dim3(256), lds_of(kc), s, a);
+    a.nblk = a.ntx * a.nty * a.nzt * a.split;
+    return a.nblk;
+}
+
+void launch_forward_gemm(const Plan& P, const cf32* x, hipStream_t s) {
+    FwdArgs a;
+    size_t lds;
+    fwd_args(P, x, a, lds);
+    hipLaunchKernelGGL(fwd_gemm_f32_kernel<kFwdNP>, dim3(a.nblk), dim3(256), lds, s, a);
+    UFSS_HIP(hipGetLastError());
+}
+
+void launch_adjoint_gemm(const Plan& P, cf32* out, hipStream_t s) {
+    AdjArgs a;
+    size_t lds;
+    adj_args(P, out, a, lds);
+    hipLaunchKernelGGL((adj_gemm_f32_kernel<kAdjNP, kAdjNZ>), dim3(a.nblk), dim3(256), lds, s, a);
     UFSS_HIP(hipGetLastError());
     if (a.split > 1) launch_sum_parts(P.d_gpart, a.split, P.nvox, out, s);
+}
+
+// Grouped launches (one grid for many plans).  Descriptors are opaque bytes.
+size_t desc_size(GemmKind k) {
+    switch (k) {
+        case GemmKind::FwdF32: return sizeof(FwdArgs);
+        case GemmKind::AdjF32: return sizeof(AdjArgs);
+        default: return bf16_desc_size(k);
+    }
+}
+
+int make_desc(GemmKind k, const Plan& P, const void* in, void* out, void* desc, size_t* lds) {
+    switch (k) {
+        case GemmKind::FwdF32:
+            return fwd_args(P, static_cast<const cf32*>(in), *static_cast<FwdArgs*>(desc), *lds);
+        case GemmKind::AdjF32:
+            return adj_args(P, static_cast<cf32*>(out), *static_cast<AdjArgs*>(desc), *lds);
+        default: return bf16_make_desc(k, P, in, out, desc, lds);
+    }
+}
+
+void launch_grouped(GemmKind k, const void* descs, const int2* blk, int nblocks, size_t lds,
+                    hipStream_t s) {
+    if (nblocks <= 0) return;
+    switch (k) {
+        case GemmKind::FwdF32:
+            hipLaunchKernelGGL(fwd_gemm_f32_kernel_grouped<kFwdNP>, dim3(nblocks), dim3(256), lds, s,
+                               static_cast<const FwdArgs*>(descs), blk);
+            break;
+        case GemmKind::AdjF32:
+            hipLaunchKernelGGL((adj_gemm_f32_kernel_grouped<kAdjNP, kAdjNZ>), dim3(nblocks), dim3(256),
+                               lds, s, static_cast<const AdjArgs*>(descs), blk);
+            break;
+        default: bf16_launch_grouped(k, descs, blk, nblocks, lds, s); return;
+    }
+    UFSS_HIP(hipGetLastError());
 }
 
 }  // namespace ufss

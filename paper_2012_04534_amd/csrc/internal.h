@@ -101,6 +101,20 @@ void launch_adjoint_pre(const Plan& P, const cf32* r, hipStream_t s);
 void launch_to_bf16(const cf32* x, void* out, int64_t n, hipStream_t s);
 int gemm_split(const Plan& P);
 int adj_split(const Plan& P);
+// Grouped GEMM launches: one grid runs the tiles of many plans.  A descriptor
+// is the kernel's argument block for one plan (opaque bytes of desc_size);
+// blk[b] = {plan index, block index inside that plan's own grid}.
+enum class GemmKind { FwdF32 = 0, AdjF32 = 1, FwdBF16 = 2, AdjBF16 = 3 };
+size_t desc_size(GemmKind k);
+// Fills `desc` for plan P (in: forward input; out: adjoint output) and the LDS
+// bytes it needs; returns the plan's block count.
+int make_desc(GemmKind k, const Plan& P, const void* in, void* out, void* desc, size_t* lds);
+void launch_grouped(GemmKind k, const void* descs, const int2* blk, int nblocks, size_t lds,
+                    hipStream_t s);
+size_t bf16_desc_size(GemmKind k);
+int bf16_make_desc(GemmKind k, const Plan& P, const void* in, void* out, void* desc, size_t* lds);
+void bf16_launch_grouped(GemmKind k, const void* descs, const int2* blk, int nblocks, size_t lds,
+                         hipStream_t s);
 bool bf16_supported(const Plan& P);
 int bf16_fwd_split(const Plan& P);
 int bf16_adj_split(const Plan& P);

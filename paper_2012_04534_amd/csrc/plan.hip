@@ -269,6 +269,30 @@ Plan* plan_create(const ufss_geom* g, int m, int per_position, const int32_t* bi
     return P;
 }
 
+// Change the split-K factors of the GEMM path (reallocating their partials).
+void plan_set_splits(Plan& P, int fs, int as) {
+    if (fs < 1 || as < 1) fail(UFSS_ERR_INVALID_ARG, "split factors must be >= 1");
+    const size_t mu = P.ubins_h.size();
+    if (fs != P.fwd_split) {
+        UFSS_HIP(hipDeviceSynchronize());
+        if (P.d_yraw) UFSS_HIP(hipFree(P.d_yraw));
+        P.ws_bytes -= (int64_t)P.fwd_split * P.npos * mu * sizeof(cf32);
+        P.d_yraw = nullptr;
+        P.d_yraw = dalloc<cf32>(P, (size_t)fs * P.npos * mu);
+        P.fwd_split = fs;
+    }
+    if (as != P.adj_split) {
+        UFSS_HIP(hipDeviceSynchronize());
+        if (P.d_gpart) {
+            UFSS_HIP(hipFree(P.d_gpart));
+            P.ws_bytes -= (int64_t)P.adj_split * P.nvox * sizeof(cf32);
+        }
+        P.d_gpart = nullptr;
+        if (as > 1) P.d_gpart = dalloc<cf32>(P, (size_t)as * P.nvox);
+        P.adj_split = as;
+    }
+}
+
 void plan_destroy(Plan* P) {
     if (!P) fail(UFSS_ERR_INVALID_ARG, "plan is NULL");
     UFSS_HIP(hipDeviceSynchronize());
@@ -291,6 +315,8 @@ void plan_info(const Plan* P, ufss_plan_info* info) {
     info->algo = P->algo;
     info->union_size = (int32_t)P->ubins_h.size();
     info->workspace_bytes = P->ws_bytes;
+    info->fwd_split = P->fwd_split;
+    info->adj_split = P->adj_split;
 }
 
 }  // namespace ufss

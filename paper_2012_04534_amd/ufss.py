@@ -26,7 +26,8 @@ ALGO_AUTO, ALGO_GEMM, ALGO_PHASOR = 0, 1, 2
 EXPORTED = [
     "ufss_last_error", "ufss_select_freqs", "ufss_plan_create", "ufss_plan_destroy",
     "ufss_plan_info_get", "ufss_forward", "ufss_adjoint", "ufss_lipschitz", "ufss_fista",
-    "ufss_shrink_update", "ufss_absmax", "ufss_time_kernel",
+    "ufss_shrink_update", "ufss_absmax", "ufss_time_kernel", "ufss_fista_batched",
+    "ufss_autotune",
 ]
 
 
@@ -58,6 +59,7 @@ class PlanInfo(ctypes.Structure):
         ("m", ctypes.c_int32), ("per_position", ctypes.c_int32), ("dtype", ctypes.c_int32),
         ("algo", ctypes.c_int32), ("union_size", ctypes.c_int32),
         ("workspace_bytes", ctypes.c_int64),
+        ("fwd_split", ctypes.c_int32), ("adj_split", ctypes.c_int32),
     ]
 
 
@@ -100,6 +102,11 @@ def lib():
             "ufss_shrink_update": ([I64, P, P, P, D, D, D, P, P, P], ctypes.c_int),
             "ufss_absmax": ([I64, P, ctypes.POINTER(D), P], ctypes.c_int),
             "ufss_time_kernel": ([P, I32, I32, ctypes.POINTER(D), P], ctypes.c_int),
+            "ufss_fista_batched": ([I32, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
+                                    ctypes.POINTER(D), ctypes.POINTER(D), I32, ctypes.POINTER(D), P],
+                                   ctypes.c_int),
+            "ufss_autotune": ([P, ctypes.c_char_p, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), P],
+                              ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -265,6 +272,37 @@ def ufss_time_kernel(plan, which, reps=10, stream=None):
     _check(lib().ufss_time_kernel(plan.handle, int(which), int(reps), ctypes.byref(ms),
                                   _stream(stream)))
     return ms.value
+
+
+def ufss_fista_batched(plans, ys, xs, lambdas, Ls, iters, stream=None):
+    """Batched FISTA (one grouped launch per phase, one hipGraph); returns the
+    final residual norm of every scan."""
+    n = len(plans)
+    if not (len(ys) == len(xs) == len(lambdas) == len(Ls) == n):
+        raise ValueError("plans, ys, xs, lambdas and Ls must have the same length")
+    for p, y, x in zip(plans, ys, xs):
+        _numel_check(x, p.nvox, "x")
+        _numel_check(y, p.nmeas, "y")
+    PA = ctypes.c_void_p * n
+    hp = PA(*[p.handle.value for p in plans])
+    yp = PA(*[_ptr(y, "y").value for y in ys])
+    xp = PA(*[_ptr(x, "x").value for x in xs])
+    lam = (ctypes.c_double * n)(*[float(v) for v in lambdas])
+    Lc = (ctypes.c_double * n)(*[float(v) for v in Ls])
+    res = (ctypes.c_double * n)()
+    _check(lib().ufss_fista_batched(n, hp, yp, xp, lam, Lc, int(iters), res, _stream(stream)))
+    return np.array(list(res))
+
+
+def ufss_autotune(plan, cache_path=None, use_cache=True, write_cache=True, stream=None):
+    """Pick the split-K factors of the plan's GEMMs by timing; returns (fwd, adj)."""
+    fs = ctypes.c_int32(0)
+    asp = ctypes.c_int32(0)
+    flags = (1 if use_cache else 0) | (2 if write_cache else 0)
+    path = cache_path.encode() if cache_path else None
+    _check(lib().ufss_autotune(plan.handle, path, flags, ctypes.byref(fs), ctypes.byref(asp),
+                               _stream(stream)))
+    return fs.value, asp.value
 
 
 def lambda_from_mu(mu):

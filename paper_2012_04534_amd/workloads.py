@@ -62,6 +62,36 @@ WORKLOADS = {
 }
 
 
+def batch_workload(seed=1004, n=64, max_lateral=64, max_depth=512):
+    """Uneven batch of scans: list of dicts like WORKLOADS entries.
+
+    Per scan: B-scan or C-scan with probability 1/2; lateral size U{16..64}
+    per side; depth N_z in {128, 192, ..., 512} with N_t = 2 N_z; M = U{32..128}
+    (capped by the caller at the band size); shared or per-position bins with
+    probability 1/2; aperture window +-16 for C-scans, full for B-scans;
+    5-50 scatterers; SNR U[10, 25] dB.  ``max_lateral`` / ``max_depth`` shrink
+    the draw for quick tests.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    depths = [d for d in range(128, 513, 64) if d <= max_depth] or [min(max_depth, 128)]
+    for i in range(n):
+        three_d = bool(rng.integers(2))
+        nx = int(rng.integers(16, max_lateral + 1))
+        ny = int(rng.integers(16, max_lateral + 1)) if three_d else 1
+        nz = int(depths[rng.integers(len(depths))])
+        nt = 2 * nz
+        m = int(rng.integers(32, 129))
+        per_pos = bool(rng.integers(2))
+        win = 16 if three_d else -1
+        g = geometry(nx, ny, nz, nt, win_x=win, win_y=win)
+        out.append(dict(geom=g, m=m, per_position=per_pos, seed=seed * 1000 + i,
+                        n_scat=int(rng.integers(5, 51)), amp=(0.5, 1.0),
+                        snr_db=float(rng.uniform(10.0, 25.0)), iters=100, mu=0.1,
+                        back_wall=None))
+    return out
+
+
 def workload(name):
     w = dict(WORKLOADS[name])
     w["geom"] = dict(w["geom"])
