@@ -226,6 +226,50 @@ int ufss_fista_batched(int32_t n, const ufss_plan_t* plans, const void* const* y
 int ufss_autotune(ufss_plan_t plan, const char* cache_path, int32_t flags,
                   int32_t* fwd_split_out, int32_t* adj_split_out, ufss_stream_t stream);
 
+/* ---- learned unrolled solver ---------------------------------------------
+ * An S-stage unrolling of FISTA (paper Alg. 1) with learned step sizes and
+ * thresholds and a 3x3x3 convolutional correction (2 -> channels -> 2 real
+ * channels = Re/Im, ReLU, zero padding); the plan's A / A^H are fixed layers.
+ * Stage i: gamma = x_i + beta_i (x_i - x_{i-1}) (FISTA momentum, beta_0 =
+ * beta_1 = 0); z = gamma - exp(rho_i)/L A^H(A gamma - y); u = soft(z,
+ * exp(kappa_i) lam / L) with lam = mu max|A^H y|; x_{i+1} = u + conv2(relu(conv1(u))).
+ * Parameters per stage, flat FP32: rho, kappa, W1[ch][2][27], b1[ch],
+ * W2[2][ch][27], b2[2] (offset e = 9(e_y+1) + 3(e_x+1) + e_z+1 over
+ * [ny][nx][nz]).  Initial rho = kappa = 0, W2 = b2 = 0, so the untrained
+ * network is exactly S FISTA iterations.  The network keeps a reference to the
+ * plan (destroy the network first) and owns its activations and Adam state. */
+typedef struct ufss_net_s* ufss_net_t;
+
+/* Create a network on `plan` (stages >= 1, 1 <= channels <= 8, L > 0, mu > 0).
+ * W1 ~ N(0, 0.01) from SplitMix64 keyed by `seed`.  out: HOST handle. */
+int ufss_unrolled_create(ufss_plan_t plan, int32_t stages, int32_t channels, double L,
+                         double mu, uint64_t seed, ufss_net_t* out);
+int ufss_unrolled_destroy(ufss_net_t net);
+
+/* Get (get_out HOST float[count] or NULL) and/or set (set_in HOST or NULL) the
+ * flat parameters; count_out HOST (optional) receives their number. */
+int ufss_unrolled_params(ufss_net_t net, float* get_out, const float* set_in, int64_t* count_out);
+
+/* Inference: x = x_S for measurements y (DEVICE complex64).  Asynchronous. */
+int ufss_unrolled_forward(ufss_net_t net, const void* y, void* x, ufss_stream_t stream);
+
+/* Loss ||x_S - target||^2 / ||target||^2 and its gradient w.r.t. every
+ * parameter (accumulate != 0 adds to the stored gradient).  grads_out HOST
+ * float[count] or NULL.  Synchronises `stream`. */
+int ufss_unrolled_grad(ufss_net_t net, const void* y, const void* target, int32_t accumulate,
+                       double* loss_out, float* grads_out, ufss_stream_t stream);
+
+/* One Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8) on the mean gradient of
+ * `batch` samples (ys[b], targets[b] DEVICE).  loss_out HOST: mean loss before
+ * the step.  Synchronises `stream`. */
+int ufss_unrolled_train_step(ufss_net_t net, int32_t batch, const void* const* ys,
+                             const void* const* targets, double lr, double* loss_out,
+                             ufss_stream_t stream);
+
+/* Checkpoint (parameters, Adam moments and step, L, mu) to / from a file. */
+int ufss_unrolled_save(ufss_net_t net, const char* path);
+int ufss_unrolled_load(ufss_net_t net, const char* path);
+
 /* Diagnostic: average duration (ms) of the operator's core kernel, launched
  * `reps` times back to back between two HIP events recorded on `stream`.
  * which = 0: forward core (windowed GEMM, or phasor forward), 1: adjoint core.

@@ -11,7 +11,8 @@ correction; it is not in the paper, so its definition is written here:
   z_i     = gamma_i - s_i A^H (A gamma_i - y),       s_i     = exp(rho_i) / L
   u_i     = soft(z_i, theta_i),                       theta_i = exp(kappa_i) lam / L
   x_{i+1} = u_i + C_i(u_i)
-  C_i(u)  = conv(W2_i, b2_i, relu(conv(W1_i, b1_i, [Re u, Im u])))   (as Re + j Im)
+  C_i(u)  = c conv(W2_i, b2_i, relu(conv(W1_i, b1_i, [Re u, Im u] / c)))   (as Re + j Im)
+  c       = lam / L  (the base threshold: makes the network homogeneous in y)
 
 conv(W, b, v)[o](p) = b[o] + sum_c sum_{e in {-1,0,1}^3} W[o, c, e] v[c](p + e),
 zero outside the grid, with p = (y, x, z) over the [ny][nx][nz] voxel grid
@@ -72,11 +73,11 @@ def conv3(W, b, v):
     return out
 
 
-def correction(st, u):
-    """C_i(u) for complex u of shape [ny, nx, nz]."""
-    v = np.stack([u.real, u.imag])
+def correction(st, u, c):
+    """C_i(u) for complex u of shape [ny, nx, nz] and scale c."""
+    v = np.stack([u.real, u.imag]) / c
     h = np.maximum(conv3(st["W1"], st["b1"], v), 0.0)
-    o = conv3(st["W2"], st["b2"], h)
+    o = c * conv3(st["W2"], st["b2"], h)
     return o[0] + 1j * o[1]
 
 
@@ -98,7 +99,7 @@ def forward(A, AH, y, params, stages, ch, L, mu, shape, return_all=False):
         g = AH(A(gam.reshape(-1)) - y).reshape(shape)
         z = gam - (math.exp(st["rho"]) / L) * g
         u = solver.soft(z, math.exp(st["kappa"]) * lam / L)
-        x_prev, x = x, u + correction(st, u)
+        x_prev, x = x, u + correction(st, u, lam / L)
         trace.append(x)
     return (x, trace) if return_all else x
 

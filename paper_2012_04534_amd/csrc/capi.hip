@@ -23,6 +23,17 @@ int fista_batched(int n, Plan* const* plans, const cf32* const* ys, cf32* const*
                   double* res_out);
 int autotune(Plan& P, const char* cache_path, int flags, hipStream_t s, int32_t* fs_out,
              int32_t* as_out);
+struct Net;
+Net* net_create(Plan* P, int S, int ch, double L, double mu, uint64_t seed);
+void net_destroy(Net* N);
+void net_forward_out(Net& N, const cf32* y, cf32* x, hipStream_t s);
+double net_grad(Net& N, const cf32* y, const cf32* aref, int accumulate, hipStream_t s);
+double net_train_step(Net& N, int batch, const cf32* const* ys, const cf32* const* refs, double lr,
+                      hipStream_t s);
+void net_params(Net& N, float* get, const float* set, int64_t* count);
+void net_grads(Net& N, float* get);
+void net_save(Net& N, const char* path);
+void net_load(Net& N, const char* path);
 void launch_forward_gemm_bf16(const Plan& P, hipStream_t s);
 void launch_adjoint_gemm_bf16(const Plan& P, cf32* out, hipStream_t s);
 
@@ -349,6 +360,73 @@ int ufss_autotune(ufss_plan_t plan, const char* cache_path, int32_t flags, int32
     Plan* P = as_plan(plan);
     ufss::autotune(*P, cache_path, flags, static_cast<hipStream_t>(stream), fwd_split_out,
                    adj_split_out);
+    UFSS_GUARD_END
+}
+
+static ufss::Net* as_net(ufss_net_t n) {
+    if (!n) ufss::fail(UFSS_ERR_INVALID_ARG, "net is NULL");
+    return reinterpret_cast<ufss::Net*>(n);
+}
+
+int ufss_unrolled_create(ufss_plan_t plan, int32_t stages, int32_t channels, double L, double mu,
+                         uint64_t seed, ufss_net_t* out) {
+    UFSS_GUARD_BEGIN
+    if (!out) ufss::fail(UFSS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    *out = reinterpret_cast<ufss_net_t>(ufss::net_create(as_plan(plan), stages, channels, L, mu, seed));
+    UFSS_GUARD_END
+}
+
+int ufss_unrolled_destroy(ufss_net_t net) {
+    UFSS_GUARD_BEGIN
+    ufss::net_destroy(as_net(net));
+    UFSS_GUARD_END
+}
+
+int ufss_unrolled_params(ufss_net_t net, float* get_out, const float* set_in, int64_t* count_out) {
+    UFSS_GUARD_BEGIN
+    ufss::net_params(*as_net(net), get_out, set_in, count_out);
+    UFSS_GUARD_END
+}
+
+int ufss_unrolled_forward(ufss_net_t net, const void* y, void* x, ufss_stream_t stream) {
+    UFSS_GUARD_BEGIN
+    ufss::net_forward_out(*as_net(net), static_cast<const ufss::cf32*>(y), static_cast<ufss::cf32*>(x),
+                          static_cast<hipStream_t>(stream));
+    UFSS_GUARD_END
+}
+
+int ufss_unrolled_grad(ufss_net_t net, const void* y, const void* target, int32_t accumulate,
+                       double* loss_out, float* grads_out, ufss_stream_t stream) {
+    UFSS_GUARD_BEGIN
+    ufss::Net& N = *as_net(net);
+    double l = ufss::net_grad(N, static_cast<const ufss::cf32*>(y), static_cast<const ufss::cf32*>(target),
+                              accumulate, static_cast<hipStream_t>(stream));
+    if (loss_out) *loss_out = l;
+    ufss::net_grads(N, grads_out);
+    UFSS_GUARD_END
+}
+
+int ufss_unrolled_train_step(ufss_net_t net, int32_t batch, const void* const* ys,
+                             const void* const* targets, double lr, double* loss_out,
+                             ufss_stream_t stream) {
+    UFSS_GUARD_BEGIN
+    double l = ufss::net_train_step(*as_net(net), batch, reinterpret_cast<const ufss::cf32* const*>(ys),
+                                    reinterpret_cast<const ufss::cf32* const*>(targets), lr,
+                                    static_cast<hipStream_t>(stream));
+    if (loss_out) *loss_out = l;
+    UFSS_GUARD_END
+}
+
+int ufss_unrolled_save(ufss_net_t net, const char* path) {
+    UFSS_GUARD_BEGIN
+    ufss::net_save(*as_net(net), path);
+    UFSS_GUARD_END
+}
+
+int ufss_unrolled_load(ufss_net_t net, const char* path) {
+    UFSS_GUARD_BEGIN
+    ufss::net_load(*as_net(net), path);
     UFSS_GUARD_END
 }
 

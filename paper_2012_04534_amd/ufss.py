@@ -27,7 +27,9 @@ EXPORTED = [
     "ufss_last_error", "ufss_select_freqs", "ufss_plan_create", "ufss_plan_destroy",
     "ufss_plan_info_get", "ufss_forward", "ufss_adjoint", "ufss_lipschitz", "ufss_fista",
     "ufss_shrink_update", "ufss_absmax", "ufss_time_kernel", "ufss_fista_batched",
-    "ufss_autotune",
+    "ufss_autotune", "ufss_unrolled_create", "ufss_unrolled_destroy", "ufss_unrolled_params",
+    "ufss_unrolled_forward", "ufss_unrolled_grad", "ufss_unrolled_train_step",
+    "ufss_unrolled_save", "ufss_unrolled_load",
 ]
 
 
@@ -107,6 +109,15 @@ def lib():
                                    ctypes.c_int),
             "ufss_autotune": ([P, ctypes.c_char_p, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), P],
                               ctypes.c_int),
+            "ufss_unrolled_create": ([P, I32, I32, D, D, U64, ctypes.POINTER(P)], ctypes.c_int),
+            "ufss_unrolled_destroy": ([P], ctypes.c_int),
+            "ufss_unrolled_params": ([P, P, P, ctypes.POINTER(I64)], ctypes.c_int),
+            "ufss_unrolled_forward": ([P, P, P, P], ctypes.c_int),
+            "ufss_unrolled_grad": ([P, P, P, I32, ctypes.POINTER(D), P, P], ctypes.c_int),
+            "ufss_unrolled_train_step": ([P, I32, ctypes.POINTER(P), ctypes.POINTER(P), D,
+                                          ctypes.POINTER(D), P], ctypes.c_int),
+            "ufss_unrolled_save": ([P, ctypes.c_char_p], ctypes.c_int),
+            "ufss_unrolled_load": ([P, ctypes.c_char_p], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -303,6 +314,83 @@ def ufss_autotune(plan, cache_path=None, use_cache=True, write_cache=True, strea
     _check(lib().ufss_autotune(plan.handle, path, flags, ctypes.byref(fs), ctypes.byref(asp),
                                _stream(stream)))
     return fs.value, asp.value
+
+
+class Net:
+    """Owning handle of a learned unrolled network (ufss_unrolled_*)."""
+
+    def __init__(self, plan, stages=16, channels=8, L=1.0, mu=0.1, seed=7):
+        h = ctypes.c_void_p()
+        _check(lib().ufss_unrolled_create(plan.handle, int(stages), int(channels), float(L),
+                                          float(mu), ctypes.c_uint64(seed), ctypes.byref(h)))
+        self.handle = h
+        self.plan = plan
+        self.stages, self.channels = int(stages), int(channels)
+        n = ctypes.c_int64(0)
+        _check(lib().ufss_unrolled_params(h, None, None, ctypes.byref(n)))
+        self.nparams = n.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(lib().ufss_unrolled_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ufss_unrolled_params(net, set_to=None):
+    """Current parameters (float32 numpy); optionally set them first."""
+    out = np.zeros(net.nparams, dtype=np.float32)
+    src = None
+    if set_to is not None:
+        src = np.ascontiguousarray(set_to, dtype=np.float32)
+        if src.size != net.nparams:
+            raise ValueError("expected %d parameters" % net.nparams)
+    _check(lib().ufss_unrolled_params(net.handle, out.ctypes.data_as(ctypes.c_void_p),
+                                      src.ctypes.data_as(ctypes.c_void_p) if src is not None else None,
+                                      None))
+    return out
+
+
+def ufss_unrolled_forward(net, y, x, stream=None):
+    _numel_check(x, net.plan.nvox, "x")
+    _numel_check(y, net.plan.nmeas, "y")
+    _check(lib().ufss_unrolled_forward(net.handle, _ptr(y, "y"), _ptr(x, "x"), _stream(stream)))
+
+
+def ufss_unrolled_grad(net, y, target, accumulate=False, stream=None):
+    """(loss, gradient as float32 numpy)."""
+    _numel_check(target, net.plan.nvox, "target")
+    _numel_check(y, net.plan.nmeas, "y")
+    g = np.zeros(net.nparams, dtype=np.float32)
+    loss = ctypes.c_double(0.0)
+    _check(lib().ufss_unrolled_grad(net.handle, _ptr(y, "y"), _ptr(target, "target"),
+                                    int(bool(accumulate)), ctypes.byref(loss),
+                                    g.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+    return loss.value, g
+
+
+def ufss_unrolled_train_step(net, ys, targets, lr, stream=None):
+    n = len(ys)
+    PA = ctypes.c_void_p * n
+    yp = PA(*[_ptr(y, "y").value for y in ys])
+    tp = PA(*[_ptr(t, "target").value for t in targets])
+    loss = ctypes.c_double(0.0)
+    _check(lib().ufss_unrolled_train_step(net.handle, n, yp, tp, float(lr), ctypes.byref(loss),
+                                          _stream(stream)))
+    return loss.value
+
+
+def ufss_unrolled_save(net, path):
+    _check(lib().ufss_unrolled_save(net.handle, str(path).encode()))
+
+
+def ufss_unrolled_load(net, path):
+    _check(lib().ufss_unrolled_load(net.handle, str(path).encode()))
 
 
 def lambda_from_mu(mu):

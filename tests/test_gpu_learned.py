@@ -1,0 +1,149 @@
+"""GPU tests of the learned unrolled solver against the FP64 oracle: the
+untrained network equals FISTA, the forward pass matches the oracle network,
+gradients match central finite differences of the oracle loss, and training
+with checkpoint / resume behaves."""
+import numpy as np
+import pytest
+
+from oracle import learned as N
+from oracle import operator as O
+from oracle import solver as V
+from paper_2012_04534_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def ufss():
+    from paper_2012_04534_amd import ufss as u
+    return u
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def tiny(u, dev, seed=2):
+    g = W.geometry(6, 5, 12, 64, win_x=2, win_y=2)
+    bins, _ = u.ufss_select_freqs(g, 5, True, 3)
+    Amat = O.dense_A(g, bins)
+    x_true = W.scene(g, 4, amp=(0.5, 1.0), seed=seed)
+    y = (Amat @ x_true.reshape(-1) + 0.05 * W.cn(Amat.shape[0], seed + 1)).astype(np.complex64)
+    yd = y.astype(np.complex128)
+    L = V.lipschitz_dense(Amat) * 1.01
+    plan = u.Plan(g, 5, True, bins, algo=u.ALGO_GEMM)
+    yt = torch.from_numpy(y.reshape(5, 6, 5)).to(dev)
+    A = lambda v: Amat @ v
+    AH = lambda v: Amat.conj().T @ v
+    return g, plan, A, AH, yd, yt, L
+
+
+def random_params(stages, ch, seed):
+    rng = np.random.default_rng(seed)
+    p = 0.05 * rng.standard_normal(stages * N.stage_size(ch))
+    return p.astype(np.float32)
+
+
+def test_untrained_network_is_fista(dev):
+    u = ufss()
+    g, plan, A, AH, yd, yt, L = tiny(u, dev)
+    net = u.Net(plan, stages=6, channels=3, L=L, mu=0.1, seed=5)
+    x = torch.zeros((5, 6, 12), dtype=torch.complex64, device=dev)
+    u.ufss_unrolled_forward(net, yt, x)
+    xf = torch.zeros_like(x)
+    u.ufss_fista(plan, yt, u.lambda_from_mu(0.1), L, 6, xf)
+    e = (torch.linalg.norm(x - xf) / torch.linalg.norm(xf)).item()
+    assert e < 1e-5, e
+    p = u.ufss_unrolled_params(net)
+    xo = N.forward(A, AH, yd, p.astype(np.float64), 6, 3, L, 0.1, (5, 6, 12))
+    lam = V.lambda_rule(AH, yd, 0.1)
+    a, _ = V.fista(A, AH, yd, lam, L, 6)
+    assert np.abs(xo.reshape(-1) - a).max() < 1e-12 * np.abs(a).max()
+    e2 = np.linalg.norm(x.cpu().numpy().reshape(-1) - a) / np.linalg.norm(a)
+    assert e2 < 1e-5, e2
+    net.close()
+    plan.close()
+
+
+def test_forward_matches_oracle_network(dev):
+    u = ufss()
+    g, plan, A, AH, yd, yt, L = tiny(u, dev)
+    S, ch = 4, 3
+    net = u.Net(plan, stages=S, channels=ch, L=L, mu=0.1)
+    p = random_params(S, ch, 11)
+    u.ufss_unrolled_params(net, set_to=p)
+    x = torch.zeros((5, 6, 12), dtype=torch.complex64, device=dev)
+    u.ufss_unrolled_forward(net, yt, x)
+    xo = N.forward(A, AH, yd, p.astype(np.float64), S, ch, L, 0.1, (5, 6, 12))
+    e = np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo)
+    assert e < 1e-5, e
+    net.close()
+    plan.close()
+
+
+def test_gradients_match_oracle_finite_differences(dev):
+    """P13: FP32 GPU gradients vs FP64 central differences (h = 1e-6) of the
+    oracle loss, for the step / threshold parameters of every stage and a
+    sample of convolution weights and biases."""
+    u = ufss()
+    g, plan, A, AH, yd, yt, L = tiny(u, dev, seed=6)
+    S, ch = 3, 2
+    shape = (5, 6, 12)
+    net = u.Net(plan, stages=S, channels=ch, L=L, mu=0.1)
+    p = random_params(S, ch, 12)
+    u.ufss_unrolled_params(net, set_to=p)
+    a_ref = (0.5 * W.cn(shape, 13)).astype(np.complex64)
+    loss, grad = u.ufss_unrolled_grad(net, yt, torch.from_numpy(a_ref).to(dev))
+    pd = p.astype(np.float64)
+    ref_loss = N.loss(A, AH, yd, pd, S, ch, L, 0.1, shape, a_ref.astype(np.complex128))
+    assert loss == pytest.approx(ref_loss, rel=1e-5)
+    n = N.stage_size(ch)
+    rng = np.random.default_rng(0)
+    idx = []
+    for i in range(S):
+        base = i * n
+        idx += [base, base + 1]                                      # rho, kappa
+        idx += list(base + 2 + rng.choice(ch * 54, 4, replace=False))  # W1
+        idx += [base + 2 + ch * 54 + int(rng.integers(ch))]             # b1
+        idx += list(base + 2 + ch * 54 + ch + rng.choice(2 * ch * 27, 4, replace=False))  # W2
+        idx += [base + n - 2, base + n - 1]                               # b2
+    fd = N.fd_grad(A, AH, yd, pd, S, ch, L, 0.1, shape, a_ref.astype(np.complex128), idx)
+    got = grad[idx].astype(np.float64)
+    err = np.linalg.norm(got - fd) / np.linalg.norm(fd)
+    assert err < 1e-3, (err, np.c_[got, fd])
+    net.close()
+    plan.close()
+
+
+def test_training_reduces_loss_and_checkpoint_roundtrip(dev, tmp_path):
+    u = ufss()
+    g, plan, A, AH, yd, yt, L = tiny(u, dev)
+    S, ch = 4, 2
+    lam = V.lambda_rule(AH, yd, 0.1)
+    ys, refs = [], []
+    for s in range(3):
+        xs = W.scene(g, 4, amp=(0.5, 1.0), seed=40 + s)
+        yv = (A(xs.reshape(-1))).astype(np.complex64)
+        lam_s = V.lambda_rule(AH, yv.astype(np.complex128), 0.1)
+        aref, _ = V.fista(A, AH, yv.astype(np.complex128), lam_s, L, 60)
+        ys.append(torch.from_numpy(yv.reshape(5, 6, 5)).to(dev))
+        refs.append(torch.from_numpy(aref.reshape(5, 6, 12).astype(np.complex64)).to(dev))
+    assert lam > 0
+    net = u.Net(plan, stages=S, channels=ch, L=L, mu=0.1, seed=1)
+    losses = [u.ufss_unrolled_train_step(net, ys, refs, 3e-3) for _ in range(25)]
+    assert losses[-1] < 0.8 * losses[0], losses
+    path = tmp_path / "net.bin"
+    u.ufss_unrolled_save(net, path)
+    net2 = u.Net(plan, stages=S, channels=ch, L=L, mu=0.1, seed=99)
+    u.ufss_unrolled_load(net2, path)
+    assert np.array_equal(u.ufss_unrolled_params(net), u.ufss_unrolled_params(net2))
+    l1 = u.ufss_unrolled_train_step(net, ys, refs, 3e-3)
+    l2 = u.ufss_unrolled_train_step(net2, ys, refs, 3e-3)
+    assert l1 == l2
+    assert np.array_equal(u.ufss_unrolled_params(net), u.ufss_unrolled_params(net2))
+    net.close()
+    net2.close()
+    plan.close()

@@ -60,8 +60,8 @@ def test_conv_matches_scipy_correlate():
 
 
 def test_fd_matches_closed_form_bias_derivative():
-    """For one stage, d loss / d b2 = 2 sum (x - a_ref) / ||a_ref||^2 over each
-    real channel (x_1 depends on b2 as a constant shift)."""
+    """For one stage, d loss / d b2 = 2 c sum (x - a_ref) / ||a_ref||^2 over each
+    real channel, c = lam / L (x_1 depends on b2 as the shift c b2)."""
     g, Amat, A, AH, y, L = tiny_problem()
     shape = (g["ny"], g["nx"], g["nz"])
     ch = 2
@@ -69,9 +69,10 @@ def test_fd_matches_closed_form_bias_derivative():
     a_ref = W.cn(shape, 9)
     x = N.forward(A, AH, y, p, 1, ch, L, 0.1, shape)
     r2 = float(np.vdot(a_ref, a_ref).real)
-    want = [2 * float((x - a_ref).real.sum()) / r2, 2 * float((x - a_ref).imag.sum()) / r2]
+    c = V.lambda_rule(AH, y, 0.1) / L
+    want = [2 * c * float((x - a_ref).real.sum()) / r2, 2 * c * float((x - a_ref).imag.sum()) / r2]
     n = N.stage_size(ch)
-    got = N.fd_grad(A, AH, y, p, 1, ch, L, 0.1, shape, a_ref, [n - 2, n - 1])
+    got = N.fd_grad(A, AH, y, p, 1, ch, L, 0.1, shape, a_ref, [n - 2, n - 1], h=1e-2)
     np.testing.assert_allclose(got, want, rtol=1e-6)
 
 
@@ -94,3 +95,15 @@ def test_fd_kappa_matches_soft_threshold_derivative():
     want /= float(np.vdot(a_ref, a_ref).real)
     got = N.fd_grad(A, AH, y, p, 1, ch, L, 0.1, shape, a_ref, [1])[0]
     assert got == pytest.approx(want, rel=1e-5)
+
+
+def test_network_is_homogeneous_in_y():
+    """With the correction scaled by c = lam / L the network commutes with a
+    positive scaling of the measurements (all parameters non-zero)."""
+    g, Amat, A, AH, y, L = tiny_problem()
+    shape = (g["ny"], g["nx"], g["nz"])
+    rng = np.random.default_rng(3)
+    p = 0.1 * rng.standard_normal(3 * N.stage_size(2))
+    x1 = N.forward(A, AH, y, p, 3, 2, L, 0.1, shape)
+    x2 = N.forward(A, AH, 7.5 * y, p, 3, 2, L, 0.1, shape)
+    np.testing.assert_allclose(x2, 7.5 * x1, rtol=0, atol=1e-12 * np.abs(x2).max())
