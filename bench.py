@@ -84,6 +84,125 @@ def cpu_baseline(w, bins, seconds=12.0):
     }
 
 
+WEIGHTS = os.path.join(ROOT, "paper_2012_04534_amd", "weights", "unrolled_cscan32_s16c8.bin")
+
+
+def fista_time(ufss, plan, y, lam, L, k, x):
+    import torch
+    x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ufss.ufss_fista(plan, y, lam, L, k, x)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def time_to_accuracy(ufss, W, plan, g, w, bins, y, lam, L, t_l, dev):
+    """Time to a relative error of 1e-2 (and coarser levels) against the plain
+    FP32 FISTA iterate at the workload's K: FP32 FISTA, BF16 FISTA and the
+    learned unrolled network (trained checkpoint, if present)."""
+    import torch
+    K = w["iters"]
+    a_ref = torch.zeros((g["ny"], g["nx"], g["nz"]), dtype=torch.complex64, device=dev)
+    ufss.ufss_fista(plan, y, lam, L, K, a_ref)
+    out = {"reference": "plain FP32 FISTA iterate after %d iterations" % K,
+           "lipschitz_s": round(t_l, 4), "L": L, "lambda": lam, "levels": [0.3, 0.1, 0.03, 0.01]}
+    x = torch.zeros_like(a_ref)
+    for tag, dt in (("fp32", ufss.F32), ("bf16", ufss.BF16)):
+        p = plan
+        if dt != ufss.F32:
+            p = ufss.Plan(g, w["m"], w["per_position"], bins, dtype=dt, algo=ufss.ALGO_GEMM)
+            ufss.ufss_autotune(p, None, False, False)
+        st = ufss.ufss_fista(p, y, lam, L, K, x, a_ref=a_ref)
+        per_it = fista_time(ufss, p, y, lam, L, 20, x) / 20
+        iters, times = [], []
+        for lev in out["levels"]:
+            hit = np.flatnonzero(st["err_ref"] <= lev)
+            k = int(hit[0]) + 1 if hit.size else None
+            iters.append(k)
+            times.append(round(k * per_it, 5) if k else None)
+        out[tag] = {"s_per_iter": round(per_it, 6), "iters_to_level": iters, "time_to_level_s": times,
+                    "err_at_K": float(st["err_ref"][-1])}
+        if dt != ufss.F32:
+            p.close()
+    if os.path.exists(WEIGHTS):
+        from paper_2012_04534_amd import learned as LN
+        net = ufss.Net(plan, stages=16, channels=8, L=L, mu=w["mu"])
+        ufss.ufss_unrolled_load(net, WEIGHTS)
+        ev = LN.make_dataset(plan, g, 4, 2005, K, L, back_wall=w["back_wall"], dev=dev)
+        r = LN.evaluate(net, plan, ev, L)
+        fp32_s = out["fp32"]["s_per_iter"]
+        err_fista_same_time = []
+        for (yy, tgt, _), tn in zip(ev, r["time_s"]):
+            k_eq = max(1, int(tn / fp32_s))
+            st = ufss.ufss_fista(plan, yy, ufss.lambda_from_mu(w["mu"]), L, min(k_eq, K), x, a_ref=tgt)
+            err_fista_same_time.append(float(st["err_ref"][-1]))
+        out["learned"] = {"checkpoint": os.path.relpath(WEIGHTS, ROOT), "eval_scenes": len(ev),
+                          "err_mean": float(r["err"].mean()), "err_max": float(r["err"].max()),
+                          "fallbacks": int(r["fallback"].sum()),
+                          "time_s_mean": float(r["time_s"].mean()),
+                          "fp32_fista_err_at_same_time": float(np.mean(err_fista_same_time))}
+        net.close()
+    return out
+
+
+def cscan64_rates(ufss, W, dev, ev_time):
+    """A + A^H rates of the 64 x 64 precision-study workload, FP32 and BF16."""
+    import torch
+    w = W.workload("cscan64")
+    g = w["geom"]
+    bins, _ = ufss.ufss_select_freqs(g, w["m"], False, w["seed"])
+    cm = window_terms(g, bins, False)
+    x = torch.from_numpy(W.cn((g["ny"], g["nx"], g["nz"]), 1).astype(np.complex64)).to(dev)
+    y = torch.empty((g["ny"], g["nx"], w["m"]), dtype=torch.complex64, device=dev)
+    out = {"cmac_per_apply": cm}
+    for tag, dt, peak in (("fp32", ufss.F32, PEAK_FP32_MFMA), ("bf16", ufss.BF16, PEAK_BF16_MFMA)):
+        p = ufss.Plan(g, w["m"], False, bins, dtype=dt)
+        ufss.ufss_autotune(p, None, False, False)
+        tf = ev_time(lambda: ufss.ufss_forward(p, x, y), 3)
+        ta = ev_time(lambda: ufss.ufss_adjoint(p, y, x), 3)
+        tfl = 16.0 * cm / ((tf + ta) * 1e-3)
+        out[tag] = {"forward_ms": round(tf, 3), "adjoint_ms": round(ta, 3),
+                    "a_plus_ah_tflops": round(tfl / 1e12, 2), "frac_of_mfma_peak": round(tfl / peak, 4)}
+        p.close()
+    return out
+
+
+def batch_rate(ufss, W, dev, iters=5):
+    """Batched FISTA over the 64 uneven scans (FP32, autotuned splits)."""
+    import torch
+    specs = W.batch_workload()
+    plans, ys, xs, Ls, cm = [], [], [], [], 0
+    t0 = time.perf_counter()
+    for s in specs:
+        g = s["geom"]
+        _, band = ufss.ufss_select_freqs(g, 1, False, 0)
+        m = min(s["m"], band)
+        bins, _ = ufss.ufss_select_freqs(g, m, s["per_position"], s["seed"])
+        p = ufss.Plan(g, m, s["per_position"], bins, algo=ufss.ALGO_GEMM)
+        ufss.ufss_autotune(p, None, use_cache=False, write_cache=False)
+        xt = torch.from_numpy(W.scene(g, s["n_scat"], amp=s["amp"], seed=s["seed"]).astype(np.complex64)).to(dev)
+        y = torch.empty((g["ny"], g["nx"], m), dtype=torch.complex64, device=dev)
+        ufss.ufss_forward(p, xt, y)
+        Ls.append(ufss.ufss_lipschitz(p, max_iters=30, rtol=1e-3, margin=0.05))
+        plans.append(p)
+        ys.append(y)
+        xs.append(torch.zeros((g["ny"], g["nx"], g["nz"]), dtype=torch.complex64, device=dev))
+        cm += window_terms(g, bins, s["per_position"])
+    setup = time.perf_counter() - t0
+    ufss.ufss_fista_batched(plans, ys, xs, [-0.1] * len(plans), Ls, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ufss.ufss_fista_batched(plans, ys, xs, [-0.1] * len(plans), Ls, iters)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for p in plans:
+        p.close()
+    return {"scans": len(specs), "iters": iters, "wall_s": round(dt, 4), "setup_s": round(setup, 2),
+            "cmac_per_apply": cm,
+            "a_plus_ah_tflops_incl_capture": round(16.0 * cm * iters / dt / 1e12, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,8 +252,11 @@ def main():
     yr = torch.empty(shape_y, dtype=torch.complex64, device=dev)
     xo = torch.empty_like(xr)
     best = None
+    tuned = {}
     for algo in algos:
         plan = ufss.Plan(g, m, per_pos, bins, algo=algo)
+        if algo == ufss.ALGO_GEMM:
+            tuned = dict(zip(("fwd_split", "adj_split"), ufss.ufss_autotune(plan, None, False, False)))
         tf = ev_time(lambda: ufss.ufss_forward(plan, xr, yr), 5)
         ta = ev_time(lambda: ufss.ufss_adjoint(plan, yr, xo), 5)
         name = {ufss.ALGO_GEMM: "gemm", ufss.ALGO_PHASOR: "phasor"}[algo]
@@ -145,6 +267,9 @@ def main():
         plan.close()
     algo, _, algo_name = best
     plan = ufss.Plan(g, m, per_pos, bins, algo=algo)
+    if algo == ufss.ALGO_GEMM:
+        ufss.ufss_autotune(plan, None, False, False)
+        extras["autotuned"] = tuned
 
     # synthetic scene and measurements: y = A x + n at the workload's SNR
     x_true = W.scene(g, w["n_scat"], amp=w["amp"], seed=w["seed"], back_wall=w["back_wall"])
@@ -209,25 +334,9 @@ def main():
     }
 
     if not args.quick:
-        # FISTA time to 1e-2 relative error against a long FP32 FISTA reference
-        a_ref = torch.zeros_like(x)
-        ufss.ufss_fista(plan, y, lam, L, 4 * w["iters"], a_ref)
-        xa = torch.zeros_like(x)
-        sa = ufss.ufss_fista(plan, y, lam, L, w["iters"], xa, a_ref=a_ref)
-        hit = np.flatnonzero(sa["err_ref"] <= 1e-2)
-        k_hit = int(hit[0]) + 1 if hit.size else None
-        fista = {"reference": "FP32 FISTA, %d iterations" % (4 * w["iters"]),
-                 "lipschitz_s": round(t_l, 4), "L": L, "lambda": lam}
-        if k_hit is not None:
-            xa.zero_()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            ufss.ufss_fista(plan, y, lam, L, k_hit, xa)
-            torch.cuda.synchronize()
-            fista["fp32_iters_to_1e-2"] = k_hit
-            fista["fp32_time_to_1e-2_s"] = round(time.perf_counter() - t0, 5)
-        fista["fp32_err_at_%d" % w["iters"]] = float(sa["err_ref"][-1])
-        result["fista"] = fista
+        result["fista"] = time_to_accuracy(ufss, W, plan, g, w, bins, y, lam, L, t_l, dev)
+        extras["cscan64"] = cscan64_rates(ufss, W, dev, ev_time)
+        extras["batch64"] = batch_rate(ufss, W, dev)
 
     result["extras"] = extras
     plan.close()

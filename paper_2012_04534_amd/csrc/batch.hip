@@ -442,6 +442,15 @@ int fista_batched(int n, Plan* const* plans, const cf32* const* ys, cf32* const*
 // ---------------------------------------------------------------------------
 void plan_set_splits(Plan& P, int fs, int as);
 
+// Waves per forward workgroup the autotuner tries (FP32 kernel): 4, and one
+// wave per 16-bin sub-tile of the whole bin list when that fits in 8.
+static std::vector<int> nw_candidates(const Plan& P) {
+    std::vector<int> c{4};
+    const int all = ((int)P.ubins_h.size() + 15) / 16;
+    if (P.dtype == UFSS_F32 && all > 4 && all <= 8) c.push_back(all);
+    return c;
+}
+
 static std::string shape_key(const Plan& P) {
     std::ostringstream o;
     o << "gfx950/nx" << P.g.nx << "/ny" << P.g.ny << "/nz" << P.g.nz << "/mu" << P.ubins_h.size()
@@ -503,7 +512,8 @@ int autotune(Plan& P, const char* cache_path, int flags, hipStream_t s, int32_t*
     const std::string key = shape_key(P);
     std::map<std::string, std::vector<double>> cache;
     if (cache_path && (flags & 1)) cache = read_cache(cache_path);
-    if (cache.count(key)) {
+    if (cache.count(key) && cache[key].size() >= 5) {
+        P.fwd_nw = (int)cache[key][4];
         plan_set_splits(P, (int)cache[key][0], (int)cache[key][1]);
     } else {
         const int tpy = P.g.ny == 1 ? 1 : 4;
@@ -515,12 +525,15 @@ int autotune(Plan& P, const char* cache_path, int flags, hipStream_t s, int32_t*
         UFSS_HIP(hipMemsetAsync(P.d_gamma, 0, P.nvox * sizeof(cf32), s));
         UFSS_HIP(hipMemsetAsync(P.d_r, 0, (size_t)P.npos * P.m * sizeof(cf32), s));
         double best_f = 1e30, best_a = 1e30;
-        int bf = P.fwd_split, ba = P.adj_split;
-        for (int c : cand) {
-            plan_set_splits(P, c, P.adj_split);
-            double t = time_ms([&]() { op_forward(P, P.d_gamma, P.d_r, nullptr, nullptr, s); }, 3, s);
-            if (t < best_f) { best_f = t; bf = c; }
-        }
+        int bf = P.fwd_split, ba = P.adj_split, bnw = P.fwd_nw;
+        for (int nw : nw_candidates(P))
+            for (int c : cand) {
+                P.fwd_nw = nw;
+                plan_set_splits(P, c, P.adj_split);
+                double t = time_ms([&]() { op_forward(P, P.d_gamma, P.d_r, nullptr, nullptr, s); }, 3, s);
+                if (t < best_f) { best_f = t; bf = c; bnw = nw; }
+            }
+        P.fwd_nw = bnw;
         for (int c : cand) {
             if (c > 8) continue;
             plan_set_splits(P, bf, c);
@@ -530,7 +543,7 @@ int autotune(Plan& P, const char* cache_path, int flags, hipStream_t s, int32_t*
         plan_set_splits(P, bf, ba);
         if (cache_path && (flags & 2)) {
             cache = read_cache(cache_path);
-            cache[key] = {(double)bf, (double)ba, best_f, best_a};
+            cache[key] = {(double)bf, (double)ba, best_f, best_a, (double)bnw};
             write_cache(cache_path, cache);
         }
     }

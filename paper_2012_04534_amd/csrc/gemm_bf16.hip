@@ -423,8 +423,8 @@ __global__ __launch_bounds__(256) void adj_gemm_bf16_kernel_grouped(const AdjB* 
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
-static constexpr int kBfNP = 2, kBfNB = 4;     // forward: 2 x 16 positions, 4 x 16 bins per wave
-static constexpr int kBfNV = 2, kBfNZ = 4;     // adjoint: 2 x 16 voxels, 4 x 16 depths per wave
+static constexpr int kBfNP = 4, kBfNB = 4;     // forward: 4 x 16 positions, 4 x 16 bins per wave
+static constexpr int kBfNV = 4, kBfNZ = 4;     // adjoint: 4 x 16 voxels, 4 x 16 depths per wave
 static constexpr size_t kLdsMaxB = 64 * 1024;
 
 static int bf_sw(const Plan& P) { return P.g.ny == 1 ? 16 : 4; }
@@ -455,7 +455,9 @@ int bf16_fwd_split(const Plan& P) {
     const int wgs = ntx * nty * nbt;
     const int ndy_max = std::min(2 * P.d.wy + 1, P.g.ny + tpy - 1);
     int split = (1024 + wgs - 1) / wgs;
-    return std::max(1, std::min(split, std::min(ndy_max, 16)));
+    split = std::max(1, std::min(split, std::min(ndy_max, 16)));
+    const int chunk = (ndy_max + split - 1) / split;
+    return (ndy_max + chunk - 1) / chunk;
 }
 
 int bf16_adj_split(const Plan& P) {
@@ -465,7 +467,9 @@ int bf16_adj_split(const Plan& P) {
     const int wgs = ntx * nty * nzt;
     const int ndy_max = std::min(2 * P.d.wy + 1, P.g.ny + tvy - 1);
     int split = (1024 + wgs - 1) / wgs;
-    return std::max(1, std::min(split, std::min(ndy_max, 8)));
+    split = std::max(1, std::min(split, std::min(ndy_max, 8)));
+    const int chunk = (ndy_max + split - 1) / split;
+    return (ndy_max + chunk - 1) / chunk;
 }
 
 static int fwdb_args(const Plan& P, FwdB& a, size_t& lds) {

@@ -49,7 +49,8 @@ struct FwdArgs {
     int nx, ny, nz, wx, wy, mu;
     int sw;                // sub-tile width (4 or 16)
     int ntx, nty;          // lateral tiles
-    int nbt;               // bin tiles of 64
+    int nbt;               // bin tiles of 16 * nw
+    int nw;                // waves with a bin sub-tile (<= blockDim / 64)
     int zc;                // depth chunk (multiple of 4)
     int split;             // split of the d_y range
     int64_t npos;
@@ -86,8 +87,8 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
     const int dx_lo = max(-a.wx, px0 - (a.nx - 1));
     const int dx_hi = min(a.wx, px0 + tpx - 1);
 
-    const int mb = bt * 64 + wave * 16 + (lane & 15);   // this lane's bin column
-    const bool wave_active = bt * 64 + wave * 16 < a.mu;
+    const int mb = bt * 16 * a.nw + wave * 16 + (lane & 15);   // this lane's bin column
+    const bool wave_active = wave < a.nw && bt * 16 * a.nw + wave * 16 < a.mu;
     const uint32_t kbin = (mb < a.mu) ? (uint32_t)a.kb[mb] : 0u;
     const int i = lane & 15, ix = i % sw, iy = i / sw;
     const int kq = lane >> 4;
@@ -101,7 +102,7 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
         for (int dy = dy_lo; dy <= dy_hi; ++dy) {
             __syncthreads();
             // stage x rows (py0 + r - dy), columns (px0 - wx + c), depths z0..z0+zc
-            for (int t = threadIdx.x; t < ncell * a.zc; t += 256) {
+            for (int t = threadIdx.x; t < ncell * a.zc; t += blockDim.x) {
                 int cell = t / a.zc, zz = t - cell * a.zc;
                 int r = cell / hc, c = cell - r * hc;
                 int gy = py0 + r - dy, gx = px0 - a.wx + c, z = z0 + zz;
@@ -111,7 +112,7 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
                 halo[cell * cs + zz] = v;
             }
             const int ady = dy < 0 ? -dy : dy;
-            for (int t = threadIdx.x; t < (a.wx + 1) * a.zc; t += 256) {
+            for (int t = threadIdx.x; t < (a.wx + 1) * a.zc; t += blockDim.x) {
                 int adx = t / a.zc, zz = t - adx * a.zc;
                 int z = z0 + zz;
                 ulds[t] = z < a.nz ? a.u[((int64_t)ady * (a.wx + 1) + adx) * a.nz + z] : 0u;
@@ -160,14 +161,14 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
 }
 
 template <int NP>
-__global__ __launch_bounds__(256) void fwd_gemm_f32_kernel(FwdArgs a) {
+__global__ __launch_bounds__(512) void fwd_gemm_f32_kernel(FwdArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     fwd_f32_body<NP>(a, blockIdx.x, gridDim.x, smem);
 }
 
 // Grouped launch: block -> (plan index, block index inside that plan's grid).
 template <int NP>
-__global__ __launch_bounds__(256) void fwd_gemm_f32_kernel_grouped(const FwdArgs* __restrict__ descs,
+__global__ __launch_bounds__(512) void fwd_gemm_f32_kernel_grouped(const FwdArgs* __restrict__ descs,
                                                  const int2* __restrict__ blk) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int2 sb = blk[blockIdx.x];
@@ -338,12 +339,14 @@ int gemm_split(const Plan& P) {
     const int ntx = (P.g.nx + tpx - 1) / tpx, nty = (P.g.ny + tpy - 1) / tpy;
     const int mu = (int)P.ubins_h.size();
     const int nbt = (mu + 63) / 64;
-    const int active_waves = ntx * nty * ((mu + 15) / 16);
+    const int nw = std::max(1, std::min(P.fwd_nw, (mu + 15) / 16));
+    const int active_waves = ntx * nty * ((mu + 16 * nw - 1) / (16 * nw)) * nw;
     const int ndy_max = std::min(2 * P.d.wy + 1, P.g.ny + tpy - 1);
-    int split = (4096 + active_waves - 1) / active_waves;
+    int split = (2048 + active_waves - 1) / active_waves;
     split = std::max(1, std::min(split, std::min(ndy_max, 16)));
+    const int chunk = (ndy_max + split - 1) / split;
     (void)nbt;
-    return split;
+    return (ndy_max + chunk - 1) / chunk;      // no split left without rows
 }
 
 // Split of the adjoint's d_y range: enough workgroups to fill 256 CUs twice.
@@ -354,7 +357,9 @@ int adj_split(const Plan& P) {
     const int wgs = ntx * nty * nzt;
     const int ndy_max = std::min(2 * P.d.wy + 1, P.g.ny + tpy - 1);
     int split = (512 + wgs - 1) / wgs;
-    return std::max(1, std::min(split, std::min(ndy_max, 8)));
+    split = std::max(1, std::min(split, std::min(ndy_max, 8)));
+    const int chunk = (ndy_max + split - 1) / split;
+    return (ndy_max + chunk - 1) / chunk;
 }
 
 // Descriptor of one plan's forward GEMM launch; returns the block count.
@@ -374,7 +379,8 @@ static int fwd_args(const Plan& P, const cf32* x, FwdArgs& a, size_t& lds) {
     const int tpx = a.sw * kFwdNP, tpy = 16 / a.sw;
     a.ntx = (a.nx + tpx - 1) / tpx;
     a.nty = (a.ny + tpy - 1) / tpy;
-    a.nbt = (a.mu + 63) / 64;
+    a.nw = std::max(1, std::min(P.fwd_nw, (a.mu + 15) / 16));
+    a.nbt = (a.mu + 16 * a.nw - 1) / (16 * a.nw);
     a.split = P.fwd_split;
     a.npos = P.npos;
     const int hc = tpx + 2 * a.wx;
@@ -427,7 +433,7 @@ void launch_forward_gemm(const Plan& P, const cf32* x, hipStream_t s) {
     FwdArgs a;
     size_t lds;
     fwd_args(P, x, a, lds);
-    hipLaunchKernelGGL(fwd_gemm_f32_kernel<kFwdNP>, dim3(a.nblk), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(fwd_gemm_f32_kernel<kFwdNP>, dim3(a.nblk), dim3(64 * a.nw), lds, s, a);
     UFSS_HIP(hipGetLastError());
 }
 
@@ -464,7 +470,7 @@ void launch_grouped(GemmKind k, const void* descs, const int2* blk, int nblocks,
     if (nblocks <= 0) return;
     switch (k) {
         case GemmKind::FwdF32:
-            hipLaunchKernelGGL(fwd_gemm_f32_kernel_grouped<kFwdNP>, dim3(nblocks), dim3(256), lds, s,
+            hipLaunchKernelGGL(fwd_gemm_f32_kernel_grouped<kFwdNP>, dim3(nblocks), dim3(512), lds, s,
                                static_cast<const FwdArgs*>(descs), blk);
             break;
         case GemmKind::AdjF32:
