@@ -300,7 +300,7 @@ int fista_batched(int n, Plan* const* plans, const cf32* const* ys, cf32* const*
             a.nvox = P.nvox;
             a.m = P.m;
             a.mu = (int)P.ubins_h.size();
-            a.fsplit = P.fwd_split;
+            a.fsplit = P.fwd_split * std::max(1, P.fwd_zsplit);
             a.asplit = P.adj_split;
             a.per_pos = P.per_position;
             a.bf16 = P.dtype == UFSS_BF16;
@@ -440,7 +440,7 @@ int fista_batched(int n, Plan* const* plans, const cf32* const* ys, cf32* const*
 // Autotuner: split-K factors of the forward and adjoint GEMMs per shape class,
 // chosen by timing every candidate with HIP events; results cached as JSON.
 // ---------------------------------------------------------------------------
-void plan_set_splits(Plan& P, int fs, int as);
+void plan_set_splits(Plan& P, int fs, int as, int zs);
 
 // Waves per forward workgroup the autotuner tries (FP32 kernel): 4, and one
 // wave per 16-bin sub-tile of the whole bin list when that fits in 8.
@@ -512,9 +512,9 @@ int autotune(Plan& P, const char* cache_path, int flags, hipStream_t s, int32_t*
     const std::string key = shape_key(P);
     std::map<std::string, std::vector<double>> cache;
     if (cache_path && (flags & 1)) cache = read_cache(cache_path);
-    if (cache.count(key) && cache[key].size() >= 5) {
+    if (cache.count(key) && cache[key].size() >= 6) {
         P.fwd_nw = (int)cache[key][4];
-        plan_set_splits(P, (int)cache[key][0], (int)cache[key][1]);
+        plan_set_splits(P, (int)cache[key][0], (int)cache[key][1], (int)cache[key][5]);
     } else {
         const int tpy = P.g.ny == 1 ? 1 : 4;
         const int ndy = std::min(2 * P.d.wy + 1, P.g.ny + tpy - 1);
@@ -525,25 +525,30 @@ int autotune(Plan& P, const char* cache_path, int flags, hipStream_t s, int32_t*
         UFSS_HIP(hipMemsetAsync(P.d_gamma, 0, P.nvox * sizeof(cf32), s));
         UFSS_HIP(hipMemsetAsync(P.d_r, 0, (size_t)P.npos * P.m * sizeof(cf32), s));
         double best_f = 1e30, best_a = 1e30;
-        int bf = P.fwd_split, ba = P.adj_split, bnw = P.fwd_nw;
+        int bf = P.fwd_split, ba = P.adj_split, bnw = P.fwd_nw, bz = P.fwd_zsplit;
+        std::vector<int> zcand{1};
+        if (P.dtype == UFSS_F32)
+            for (int z : {2, 4})
+                if (P.g.nz >= 32 * z) zcand.push_back(z);
         for (int nw : nw_candidates(P))
-            for (int c : cand) {
-                P.fwd_nw = nw;
-                plan_set_splits(P, c, P.adj_split);
-                double t = time_ms([&]() { op_forward(P, P.d_gamma, P.d_r, nullptr, nullptr, s); }, 3, s);
-                if (t < best_f) { best_f = t; bf = c; bnw = nw; }
-            }
+            for (int zs : zcand)
+                for (int c : cand) {
+                    P.fwd_nw = nw;
+                    plan_set_splits(P, c, P.adj_split, zs);
+                    double t = time_ms([&]() { op_forward(P, P.d_gamma, P.d_r, nullptr, nullptr, s); }, 3, s);
+                    if (t < best_f) { best_f = t; bf = c; bnw = nw; bz = zs; }
+                }
         P.fwd_nw = bnw;
         for (int c : cand) {
             if (c > 8) continue;
-            plan_set_splits(P, bf, c);
+            plan_set_splits(P, bf, c, bz);
             double t = time_ms([&]() { op_adjoint(P, P.d_r, P.d_g, s); }, 3, s);
             if (t < best_a) { best_a = t; ba = c; }
         }
-        plan_set_splits(P, bf, ba);
+        plan_set_splits(P, bf, ba, bz);
         if (cache_path && (flags & 2)) {
             cache = read_cache(cache_path);
-            cache[key] = {(double)bf, (double)ba, best_f, best_a, (double)bnw};
+            cache[key] = {(double)bf, (double)ba, best_f, best_a, (double)bnw, (double)bz};
             write_cache(cache_path, cache);
         }
     }

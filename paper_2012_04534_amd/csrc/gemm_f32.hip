@@ -53,6 +53,7 @@ struct FwdArgs {
     int nw;                // waves with a bin sub-tile (<= blockDim / 64)
     int zc;                // depth chunk (multiple of 4)
     int split;             // split of the d_y range
+    int zsplit;            // split of the depth range (partials = split * zsplit)
     int64_t npos;
     int nblk;              // blocks of this plan's grid
 };
@@ -74,8 +75,11 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
     const int ntile = a.ntx * a.nty;
     const int tile = b % ntile;
     const int bt = (b / ntile) % a.nbt;
-    const int sp = b / (ntile * a.nbt);
+    const int sp_all = b / (ntile * a.nbt);          // partial index: (d_y part, depth part)
+    const int sp = sp_all % a.split, spz = sp_all / a.split;
     const int px0 = (tile % a.ntx) * tpx, py0 = (tile / a.ntx) * tpy;
+    const int zper = ((a.nz + a.zc * a.zsplit - 1) / (a.zc * a.zsplit)) * a.zc;
+    const int z_lo = spz * zper, z_hi = min(a.nz, z_lo + zper);
 
     // d_y range of this split (rows that hit the grid for some tile row)
     int dy_lo = max(-a.wy, py0 - (a.ny - 1));
@@ -98,7 +102,7 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
     for (int s = 0; s < NP; ++s) out_re[s] = out_im[s] = f4{0.f, 0.f, 0.f, 0.f};
 
     const int ncell = tpy * hc;
-    for (int z0 = 0; z0 < a.nz; z0 += a.zc) {
+    for (int z0 = z_lo; z0 < z_hi; z0 += a.zc) {
         for (int dy = dy_lo; dy <= dy_hi; ++dy) {
             __syncthreads();
             // stage x rows (py0 + r - dy), columns (px0 - wx + c), depths z0..z0+zc
@@ -147,7 +151,7 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
         }
     }
     if (!wave_active || mb >= a.mu) return;
-    cf32* yo = a.yraw + (int64_t)sp * a.npos * a.mu;
+    cf32* yo = a.yraw + (int64_t)sp_all * a.npos * a.mu;
 #pragma unroll
     for (int s = 0; s < NP; ++s) {
 #pragma unroll
@@ -390,7 +394,8 @@ static int fwd_args(const Plan& P, const cf32* x, FwdArgs& a, size_t& lds) {
     lds = (size_t)tpy * hc * (zc + 1) * sizeof(cf32) + (size_t)(a.wx + 1) * zc * 4;
     if (lds > kLdsMax) fail(UFSS_ERR_UNSUPPORTED, "aperture window too wide for the GEMM path");
     a.zc = zc;
-    a.nblk = a.ntx * a.nty * a.nbt * a.split;
+    a.zsplit = std::max(1, P.fwd_zsplit);
+    a.nblk = a.ntx * a.nty * a.nbt * a.split * a.zsplit;
     return a.nblk;
 }
 

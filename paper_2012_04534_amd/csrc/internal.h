@@ -61,6 +61,8 @@ struct Plan {
     int64_t nvox = 0;
     int fwd_split = 1;             // split of the forward GEMM's d_y range
     int fwd_nw = 4;                // waves (16-bin sub-tiles) per forward FP32 workgroup
+    int fwd_zsplit = 1;            // split of the forward FP32 GEMM's depth range
+                                   // (raw output holds fwd_split * fwd_zsplit partials)
     int adj_split = 1;             // split of the adjoint GEMM's d_y range
     cf32* d_gpart = nullptr;       // adjoint partials [adj_split][nvox] (adj_split > 1)
     std::vector<int> bins_h;       // [m] or [npos*m]

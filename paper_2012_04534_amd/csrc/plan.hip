@@ -270,17 +270,19 @@ Plan* plan_create(const ufss_geom* g, int m, int per_position, const int32_t* bi
 }
 
 // Change the split-K factors of the GEMM path (reallocating their partials).
-void plan_set_splits(Plan& P, int fs, int as) {
-    if (fs < 1 || as < 1) fail(UFSS_ERR_INVALID_ARG, "split factors must be >= 1");
+void plan_set_splits(Plan& P, int fs, int as, int zs) {
+    if (fs < 1 || as < 1 || zs < 1) fail(UFSS_ERR_INVALID_ARG, "split factors must be >= 1");
+    if (P.dtype == UFSS_BF16) zs = 1;                 // the BF16 forward splits d_y only
     const size_t mu = P.ubins_h.size();
-    if (fs != P.fwd_split) {
+    if (fs * zs != P.fwd_split * P.fwd_zsplit) {
         UFSS_HIP(hipDeviceSynchronize());
         if (P.d_yraw) UFSS_HIP(hipFree(P.d_yraw));
-        P.ws_bytes -= (int64_t)P.fwd_split * P.npos * mu * sizeof(cf32);
+        P.ws_bytes -= (int64_t)P.fwd_split * P.fwd_zsplit * P.npos * mu * sizeof(cf32);
         P.d_yraw = nullptr;
-        P.d_yraw = dalloc<cf32>(P, (size_t)fs * P.npos * mu);
-        P.fwd_split = fs;
+        P.d_yraw = dalloc<cf32>(P, (size_t)fs * zs * P.npos * mu);
     }
+    P.fwd_split = fs;
+    P.fwd_zsplit = zs;
     if (as != P.adj_split) {
         UFSS_HIP(hipDeviceSynchronize());
         if (P.d_gpart) {

@@ -82,7 +82,8 @@ __global__ __launch_bounds__(kThreads) void fwd_post_kernel(
 int launch_forward_post(const Plan& P, cf32* y, const cf32* ymeas, double* part, hipStream_t s) {
     const int64_t n = (int64_t)P.npos * P.m;
     const int nb = blocks_for(n);
-    hipLaunchKernelGGL(fwd_post_kernel, dim3(nb), dim3(kThreads), 0, s, P.d_yraw, P.fwd_split,
+    hipLaunchKernelGGL(fwd_post_kernel, dim3(nb), dim3(kThreads), 0, s, P.d_yraw,
+                       P.fwd_split * std::max(1, P.fwd_zsplit),
                        (int64_t)P.npos, (int)P.ubins_h.size(), P.m, P.per_position, P.d_map,
                        P.d_hsel, ymeas, y, part);
     UFSS_HIP(hipGetLastError());
