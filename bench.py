@@ -31,6 +31,27 @@ PEAK_FP32_MFMA = 157.3e12
 PEAK_BF16_MFMA = 2.5e15
 PEAK_HBM = 8e12
 
+# HBM bytes per launch of the dominant kernels, from two rocprofv3 counter runs
+# (FETCH_SIZE, then WRITE_SIZE, each scaled by what the same counter reads for a
+# 256 MiB device copy).  Each entry holds the SHA-256 prefix of the kernel
+# source it was measured on; a changed source reports null instead.
+TRAFFIC = {}
+TRAFFIC_SRC = {"gemm": "paper_2012_04534_amd/csrc/gemm_f32.hip",
+               "phasor": "paper_2012_04534_amd/csrc/phasor.hip"}
+
+
+def source_sha(rel):
+    import hashlib
+    with open(os.path.join(ROOT, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_bytes(workload, algo_name, direction):
+    e = TRAFFIC.get("%s/%s/%s" % (workload, algo_name, direction))
+    if e is None or source_sha(TRAFFIC_SRC[algo_name]) != e["sha"]:
+        return None
+    return int(e["bytes"])
+
 
 def window_terms(g, bins, per_pos):
     """Algorithmic complex MACs of one apply (voxels inside each window x bins)."""
@@ -211,6 +232,8 @@ def main():
     ap.add_argument("--workload", default="cscan32")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true", help="skip time-to-accuracy and extras")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file for the headline workload (read and written)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -256,7 +279,9 @@ def main():
     for algo in algos:
         plan = ufss.Plan(g, m, per_pos, bins, algo=algo)
         if algo == ufss.ALGO_GEMM:
-            tuned = dict(zip(("fwd_split", "adj_split"), ufss.ufss_autotune(plan, None, False, False)))
+            tuned = dict(zip(("fwd_split", "adj_split"),
+                             ufss.ufss_autotune(plan, args.tune_cache, args.tune_cache is not None,
+                                                args.tune_cache is not None)))
         tf = ev_time(lambda: ufss.ufss_forward(plan, xr, yr), 5)
         ta = ev_time(lambda: ufss.ufss_adjoint(plan, yr, xo), 5)
         name = {ufss.ALGO_GEMM: "gemm", ufss.ALGO_PHASOR: "phasor"}[algo]
@@ -268,7 +293,7 @@ def main():
     algo, _, algo_name = best
     plan = ufss.Plan(g, m, per_pos, bins, algo=algo)
     if algo == ufss.ALGO_GEMM:
-        ufss.ufss_autotune(plan, None, False, False)
+        ufss.ufss_autotune(plan, args.tune_cache, args.tune_cache is not None, args.tune_cache is not None)
         extras["autotuned"] = tuned
 
     # synthetic scene and measurements: y = A x + n at the workload's SNR
@@ -313,7 +338,7 @@ def main():
         roof = {"bound": "mfma", "achieved": round(8.0 * cmac / (k_ms * 1e-3) / 1e12, 3),
                 "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s"}
     roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
-    roof["traffic"] = None
+    roof["traffic"] = traffic_bytes(args.workload, algo_name, dom)
     roof["kernel"] = "%s %s core (%.4f ms per launch)" % (algo_name, dom, k_ms)
     extras["kernel_ms"] = {"forward_core": round(k_f, 4), "adjoint_core": round(k_a, 4)}
 

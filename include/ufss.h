@@ -226,6 +226,19 @@ int ufss_fista_batched(int32_t n, const ufss_plan_t* plans, const void* const* y
 int ufss_autotune(ufss_plan_t plan, const char* cache_path, int32_t flags,
                   int32_t* fwd_split_out, int32_t* adj_split_out, ufss_stream_t stream);
 
+/* Manual tiling of the GEMM path (the choice ufss_autotune makes by timing):
+ *   fwd_split   parts of the forward GEMM's d_y range, 1..64
+ *   adj_split   parts of the adjoint GEMM's d_y range, 1..64
+ *   fwd_waves   16-bin sub-tiles (waves) per forward FP32 workgroup, 1..8
+ *   fwd_zsplit  parts of the forward FP32 GEMM's depth range, 1..64
+ * A value of 0 keeps the plan's current one.  Any valid setting computes the
+ * same operator; parts that receive no rows contribute zeros.  BF16 plans
+ * accept only 0 or 1 for fwd_zsplit and ignore fwd_waves.  Reallocates the
+ * plan's split workspace (synchronises the device).  Errors: INVALID_ARG for
+ * values out of range, UNSUPPORTED for phasor plans. */
+int ufss_plan_set_tiling(ufss_plan_t plan, int32_t fwd_split, int32_t adj_split,
+                         int32_t fwd_waves, int32_t fwd_zsplit);
+
 /* ---- learned unrolled solver ---------------------------------------------
  * An S-stage unrolling of FISTA (paper Alg. 1) with learned step sizes and
  * thresholds and a 3x3x3 convolutional correction (2 -> channels -> 2 real

@@ -440,7 +440,6 @@ int fista_batched(int n, Plan* const* plans, const cf32* const* ys, cf32* const*
 // Autotuner: split-K factors of the forward and adjoint GEMMs per shape class,
 // chosen by timing every candidate with HIP events; results cached as JSON.
 // ---------------------------------------------------------------------------
-void plan_set_splits(Plan& P, int fs, int as, int zs);
 
 // Waves per forward workgroup the autotuner tries (FP32 kernel): 4, and one
 // wave per 16-bin sub-tile of the whole bin list when that fits in 8.
@@ -519,7 +518,7 @@ int autotune(Plan& P, const char* cache_path, int flags, hipStream_t s, int32_t*
         const int tpy = P.g.ny == 1 ? 1 : 4;
         const int ndy = std::min(2 * P.d.wy + 1, P.g.ny + tpy - 1);
         std::vector<int> cand;
-        for (int c : {1, 2, 3, 4, 6, 8, 12, 16})
+        for (int c : {1, 2, 3, 4, 6, 8, 12, 16, 24, 32})
             if (c <= ndy) cand.push_back(c);
         // inputs: the plan's own workspace vectors hold finite values
         UFSS_HIP(hipMemsetAsync(P.d_gamma, 0, P.nvox * sizeof(cf32), s));
@@ -528,11 +527,12 @@ int autotune(Plan& P, const char* cache_path, int flags, hipStream_t s, int32_t*
         int bf = P.fwd_split, ba = P.adj_split, bnw = P.fwd_nw, bz = P.fwd_zsplit;
         std::vector<int> zcand{1};
         if (P.dtype == UFSS_F32)
-            for (int z : {2, 4})
+            for (int z : {2, 4, 8})
                 if (P.g.nz >= 32 * z) zcand.push_back(z);
         for (int nw : nw_candidates(P))
             for (int zs : zcand)
                 for (int c : cand) {
+                    if (c * zs > 96) continue;          // bounds the partial-sum workspace
                     P.fwd_nw = nw;
                     plan_set_splits(P, c, P.adj_split, zs);
                     double t = time_ms([&]() { op_forward(P, P.d_gamma, P.d_r, nullptr, nullptr, s); }, 3, s);
@@ -540,7 +540,6 @@ int autotune(Plan& P, const char* cache_path, int flags, hipStream_t s, int32_t*
                 }
         P.fwd_nw = bnw;
         for (int c : cand) {
-            if (c > 8) continue;
             plan_set_splits(P, bf, c, bz);
             double t = time_ms([&]() { op_adjoint(P, P.d_r, P.d_g, s); }, 3, s);
             if (t < best_a) { best_a = t; ba = c; }

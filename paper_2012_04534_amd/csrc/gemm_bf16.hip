@@ -423,35 +423,48 @@ __global__ __launch_bounds__(256) void adj_gemm_bf16_kernel_grouped(const AdjB* 
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
-static constexpr int kBfNP = 4, kBfNB = 4;     // forward: 4 x 16 positions, 4 x 16 bins per wave
-static constexpr int kBfNV = 4, kBfNZ = 4;     // adjoint: 4 x 16 voxels, 4 x 16 depths per wave
+static constexpr int kBfNB = 4;     // forward: 4 x 16 bins per wave
+static constexpr int kBfNZ = 4;     // adjoint: 4 x 16 depths per wave
 static constexpr size_t kLdsMaxB = 64 * 1024;
 
 static int bf_sw(const Plan& P) { return P.g.ny == 1 ? 16 : 4; }
 
-static size_t fwd_bf16_lds(const Plan& P) {
-    const int sw = bf_sw(P), tpx = 4 * kBfNP * sw, tpy = 16 / sw;
+// Lateral sub-tiles of 16 per wave: 4 when the grid is wide enough that a
+// 64-position tile row does not overhang it by much, else 2.  Batched
+// (grouped) launches always use 2 so one kernel fits every scan.
+static int bf_np(const Plan& P) { return (P.g.ny > 1 && P.g.nx >= 48) ? 4 : 2; }
+
+// Bin sub-tiles per forward tile.  (Measured: 6 x 16-bin tiles, which cover a
+// 66-bin union in one tile, ran slower than two 4 x 16 tiles, so 4 is kept.)
+static int bf_nb(const Plan&, int) { return kBfNB; }
+
+static size_t fwd_bf16_lds(const Plan& P, int np, int nb) {
+    const int sw = bf_sw(P), tpx = 4 * np * sw, tpy = 16 / sw;
     const int ncol = std::min(P.g.nx, tpx + 2 * P.d.wx);
-    return (size_t)(tpy * ncol + 1) * CELL * 2 + (size_t)2 * 2 * kBfNB * 16 * PROW * 2 +
-           (size_t)(P.d.wx + 1) * ZCB * 4 + kBfNB * 16 * 4;
+    return (size_t)(tpy * ncol + 1) * CELL * 2 + (size_t)2 * 2 * nb * 16 * PROW * 2 +
+           (size_t)(P.d.wx + 1) * ZCB * 4 + nb * 16 * 4;
 }
 
-static size_t adj_bf16_lds(const Plan& P) {
-    const int sw = bf_sw(P), tvx = 4 * kBfNV * sw, tvy = 16 / sw;
+static size_t adj_bf16_lds(const Plan& P, int nv) {
+    const int sw = bf_sw(P), tvx = 4 * nv * sw, tvy = 16 / sw;
     const int ncol = std::min(P.g.nx, tvx + 2 * P.d.wx);
     return (size_t)(tvy * ncol + 1) * CELL * 2 + (size_t)2 * 2 * kBfNZ * 16 * PROW * 2 +
            (size_t)(P.d.wx + 1) * kBfNZ * 16 * 4 + ZCB * 4;
 }
 
 bool bf16_supported(const Plan& P) {
-    return fwd_bf16_lds(P) <= kLdsMaxB && adj_bf16_lds(P) <= kLdsMaxB;
+    for (int np : {2, bf_np(P)})
+        if (fwd_bf16_lds(P, np, bf_nb(P, np)) > kLdsMaxB || adj_bf16_lds(P, np) > kLdsMaxB)
+            return false;
+    return true;
 }
 
 int bf16_fwd_split(const Plan& P) {
-    const int sw = bf_sw(P), tpx = 4 * kBfNP * sw, tpy = 16 / sw;
+    const int sw = bf_sw(P), tpx = 4 * bf_np(P) * sw, tpy = 16 / sw;
     const int ntx = (P.g.nx + tpx - 1) / tpx, nty = (P.g.ny + tpy - 1) / tpy;
     const int mu = (int)P.ubins_h.size();
-    const int nbt = (mu + kBfNB * 16 - 1) / (kBfNB * 16);
+    const int nb = bf_nb(P, bf_np(P));
+    const int nbt = (mu + nb * 16 - 1) / (nb * 16);
     const int wgs = ntx * nty * nbt;
     const int ndy_max = std::min(2 * P.d.wy + 1, P.g.ny + tpy - 1);
     int split = (1024 + wgs - 1) / wgs;
@@ -461,7 +474,7 @@ int bf16_fwd_split(const Plan& P) {
 }
 
 int bf16_adj_split(const Plan& P) {
-    const int sw = bf_sw(P), tvx = 4 * kBfNV * sw, tvy = 16 / sw;
+    const int sw = bf_sw(P), tvx = 4 * bf_np(P) * sw, tvy = 16 / sw;
     const int ntx = (P.g.nx + tvx - 1) / tvx, nty = (P.g.ny + tvy - 1) / tvy;
     const int nzt = (P.g.nz + kBfNZ * 16 - 1) / (kBfNZ * 16);
     const int wgs = ntx * nty * nzt;
@@ -472,7 +485,7 @@ int bf16_adj_split(const Plan& P) {
     return (ndy_max + chunk - 1) / chunk;
 }
 
-static int fwdb_args(const Plan& P, FwdB& a, size_t& lds) {
+static int fwdb_args(const Plan& P, FwdB& a, size_t& lds, int np, int nb) {
     a = FwdB{};
     a.x = static_cast<const cbf16*>(P.d_xop);
     a.yraw = P.d_yraw;
@@ -485,19 +498,19 @@ static int fwdb_args(const Plan& P, FwdB& a, size_t& lds) {
     a.wy = P.d.wy;
     a.mu = (int)P.ubins_h.size();
     a.sw = bf_sw(P);
-    const int tpx = 4 * kBfNP * a.sw, tpy = 16 / a.sw;
+    const int tpx = 4 * np * a.sw, tpy = 16 / a.sw;
     a.ntx = (a.nx + tpx - 1) / tpx;
     a.nty = (a.ny + tpy - 1) / tpy;
-    a.nbt = (a.mu + kBfNB * 16 - 1) / (kBfNB * 16);
+    a.nbt = (a.mu + nb * 16 - 1) / (nb * 16);
     a.split = P.fwd_split;
     a.npos = P.npos;
-    lds = fwd_bf16_lds(P);
+    lds = fwd_bf16_lds(P, np, nb);
     if (lds > kLdsMaxB) fail(UFSS_ERR_UNSUPPORTED, "aperture window too wide for the BF16 GEMM path");
     a.nblk = a.ntx * a.nty * a.nbt * a.split;
     return a.nblk;
 }
 
-static int adjb_args(const Plan& P, cf32* out, AdjB& a, size_t& lds) {
+static int adjb_args(const Plan& P, cf32* out, AdjB& a, size_t& lds, int nv) {
     a = AdjB{};
     a.r = static_cast<const cbf16*>(P.d_rop);
     a.out = out;
@@ -511,13 +524,13 @@ static int adjb_args(const Plan& P, cf32* out, AdjB& a, size_t& lds) {
     a.wy = P.d.wy;
     a.mu = (int)P.ubins_h.size();
     a.sw = bf_sw(P);
-    const int tvx = 4 * kBfNV * a.sw, tvy = 16 / a.sw;
+    const int tvx = 4 * nv * a.sw, tvy = 16 / a.sw;
     a.ntx = (a.nx + tvx - 1) / tvx;
     a.nty = (a.ny + tvy - 1) / tvy;
     a.nzt = (a.nz + kBfNZ * 16 - 1) / (kBfNZ * 16);
     a.split = P.adj_split;
     a.nvox = P.nvox;
-    lds = adj_bf16_lds(P);
+    lds = adj_bf16_lds(P, nv);
     if (lds > kLdsMaxB) fail(UFSS_ERR_UNSUPPORTED, "aperture window too wide for the BF16 GEMM path");
     a.nblk = a.ntx * a.nty * a.nzt * a.split;
     return a.nblk;
@@ -526,16 +539,24 @@ static int adjb_args(const Plan& P, cf32* out, AdjB& a, size_t& lds) {
 void launch_forward_gemm_bf16(const Plan& P, hipStream_t s) {
     FwdB a;
     size_t lds;
-    fwdb_args(P, a, lds);
-    hipLaunchKernelGGL((fwd_gemm_bf16_kernel<kBfNP, kBfNB>), dim3(a.nblk), dim3(256), lds, s, a);
+    const int np = bf_np(P), nb = bf_nb(P, np);
+    fwdb_args(P, a, lds, np, nb);
+    if (np == 4)
+        hipLaunchKernelGGL((fwd_gemm_bf16_kernel<4, kBfNB>), dim3(a.nblk), dim3(256), lds, s, a);
+    else
+        hipLaunchKernelGGL((fwd_gemm_bf16_kernel<2, kBfNB>), dim3(a.nblk), dim3(256), lds, s, a);
     UFSS_HIP(hipGetLastError());
 }
 
 void launch_adjoint_gemm_bf16(const Plan& P, cf32* out, hipStream_t s) {
     AdjB a;
     size_t lds;
-    adjb_args(P, out, a, lds);
-    hipLaunchKernelGGL((adj_gemm_bf16_kernel<kBfNV, kBfNZ>), dim3(a.nblk), dim3(256), lds, s, a);
+    const int nv = bf_np(P);
+    adjb_args(P, out, a, lds, nv);
+    if (nv == 4)
+        hipLaunchKernelGGL((adj_gemm_bf16_kernel<4, kBfNZ>), dim3(a.nblk), dim3(256), lds, s, a);
+    else
+        hipLaunchKernelGGL((adj_gemm_bf16_kernel<2, kBfNZ>), dim3(a.nblk), dim3(256), lds, s, a);
     UFSS_HIP(hipGetLastError());
     if (a.split > 1) launch_sum_parts(P.d_gpart, a.split, P.nvox, out, s);
 }
@@ -544,17 +565,17 @@ size_t bf16_desc_size(GemmKind k) { return k == GemmKind::FwdBF16 ? sizeof(FwdB)
 
 int bf16_make_desc(GemmKind k, const Plan& P, const void* in, void* out, void* desc, size_t* lds) {
     (void)in;
-    if (k == GemmKind::FwdBF16) return fwdb_args(P, *static_cast<FwdB*>(desc), *lds);
-    return adjb_args(P, static_cast<cf32*>(out), *static_cast<AdjB*>(desc), *lds);
+    if (k == GemmKind::FwdBF16) return fwdb_args(P, *static_cast<FwdB*>(desc), *lds, 2, kBfNB);
+    return adjb_args(P, static_cast<cf32*>(out), *static_cast<AdjB*>(desc), *lds, 2);
 }
 
 void bf16_launch_grouped(GemmKind k, const void* descs, const int2* blk, int nblocks, size_t lds,
                          hipStream_t s) {
     if (k == GemmKind::FwdBF16)
-        hipLaunchKernelGGL((fwd_gemm_bf16_kernel_grouped<kBfNP, kBfNB>), dim3(nblocks), dim3(256), lds,
+        hipLaunchKernelGGL((fwd_gemm_bf16_kernel_grouped<2, kBfNB>), dim3(nblocks), dim3(256), lds,
                            s, static_cast<const FwdB*>(descs), blk);
     else
-        hipLaunchKernelGGL((adj_gemm_bf16_kernel_grouped<kBfNV, kBfNZ>), dim3(nblocks), dim3(256), lds,
+        hipLaunchKernelGGL((adj_gemm_bf16_kernel_grouped<2, kBfNZ>), dim3(nblocks), dim3(256), lds,
                            s, static_cast<const AdjB*>(descs), blk);
     UFSS_HIP(hipGetLastError());
 }

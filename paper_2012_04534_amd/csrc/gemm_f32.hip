@@ -41,6 +41,42 @@ __device__ __forceinline__ void phasor(uint32_t ku, float& c, float& s) {
     s = __builtin_amdgcn_sinf(ph);              // sin(2 pi ph)
 }
 
+// Stages rows x hc cells of `chunk` consecutive complex values into LDS
+// (cell stride cs), zero outside the grid or past `ilim` along the inner axis:
+//   halo[(r * hc + c) * cs + e] = src[((ybase + r) * nx + xbase + c) * ld + i0 + e].
+// `chunk` is a power of two dividing blockDim.x, so each thread keeps one inner
+// index and walks the cells with a fixed step; UNR independent loads are in
+// flight per thread before their LDS stores.
+template <int UNR>
+__device__ __forceinline__ void stage_halo(cf32* __restrict__ halo, int cs, int rows, int hc, int chunk,
+                                           const cf32* __restrict__ src, int ny, int nx, int64_t ld,
+                                           int ybase, int xbase, int i0, int ilim) {
+    const int e = threadIdx.x & (chunk - 1);
+    const int step = blockDim.x / chunk;
+    const int total = rows * hc;
+    int cell = threadIdx.x / chunk;
+    int r = cell / hc, c = cell - r * hc;
+    const bool eok = i0 + e < ilim;
+    for (; cell < total; cell += UNR * step) {
+        cf32 v[UNR];
+        int rr = r, cc = c;
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            v[u] = cf32{0.f, 0.f};
+            const int gy = ybase + rr, gx = xbase + cc;
+            if (cell + u * step < total && eok && gy >= 0 && gy < ny && gx >= 0 && gx < nx)
+                v[u] = src[((int64_t)gy * nx + gx) * ld + i0 + e];
+            cc += step;
+            while (cc >= hc) { cc -= hc; ++rr; }
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+            if (cell + u * step < total) halo[(cell + u * step) * cs + e] = v[u];
+        r = rr;
+        c = cc;
+    }
+}
+
 struct FwdArgs {
     const cf32* x;
     cf32* yraw;            // [split][npos][mu]
@@ -101,20 +137,11 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
 #pragma unroll
     for (int s = 0; s < NP; ++s) out_re[s] = out_im[s] = f4{0.f, 0.f, 0.f, 0.f};
 
-    const int ncell = tpy * hc;
     for (int z0 = z_lo; z0 < z_hi; z0 += a.zc) {
         for (int dy = dy_lo; dy <= dy_hi; ++dy) {
             __syncthreads();
             // stage x rows (py0 + r - dy), columns (px0 - wx + c), depths z0..z0+zc
-            for (int t = threadIdx.x; t < ncell * a.zc; t += blockDim.x) {
-                int cell = t / a.zc, zz = t - cell * a.zc;
-                int r = cell / hc, c = cell - r * hc;
-                int gy = py0 + r - dy, gx = px0 - a.wx + c, z = z0 + zz;
-                cf32 v{0.f, 0.f};
-                if (gy >= 0 && gy < a.ny && gx >= 0 && gx < a.nx && z < a.nz)
-                    v = a.x[((int64_t)gy * a.nx + gx) * a.nz + z];
-                halo[cell * cs + zz] = v;
-            }
+            stage_halo<8>(halo, cs, tpy, hc, a.zc, a.x, a.ny, a.nx, a.nz, py0 - dy, px0 - a.wx, z0, a.nz);
             const int ady = dy < 0 ? -dy : dy;
             for (int t = threadIdx.x; t < (a.wx + 1) * a.zc; t += blockDim.x) {
                 int adx = t / a.zc, zz = t - adx * a.zc;
@@ -130,11 +157,20 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
                 const int adx = dx < 0 ? -dx : dx;
                 const uint32_t* urow = ulds + adx * a.zc;
                 const cf32* hrow = halo + (iy * hc + ix + a.wx - dx) * cs;
+                // sub-tiles whose shifted columns all fall outside the grid add
+                // exact zeros: skip their MFMAs (wave-uniform test)
+                bool act[NP];
+#pragma unroll
+                for (int s = 0; s < NP; ++s) {
+                    const int c0 = px0 + s * sw - dx;
+                    act[s] = c0 + sw - 1 >= 0 && c0 <= a.nx - 1;
+                }
                 for (int zz = 0; zz < a.zc; zz += 4) {
                     float c, sn;
                     phasor(kbin * urow[zz + kq], c, sn);
 #pragma unroll
                     for (int s = 0; s < NP; ++s) {
+                        if (!act[s]) continue;
                         cf32 xv = hrow[s * sw * cs + zz + kq];
                         in_re[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.re, c, in_re[s], 0, 0, 0);
                         in_re[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.im, sn, in_re[s], 0, 0, 0);
@@ -233,19 +269,10 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
 #pragma unroll
         for (int q = 0; q < NZ; ++q) out_re[s][q] = out_im[s][q] = f4{0.f, 0.f, 0.f, 0.f};
 
-    const int ncell = tpy * hc;
     for (int k0 = 0; k0 < a.mu; k0 += a.kc) {
         for (int dy = dy_lo; dy <= dy_hi; ++dy) {
             __syncthreads();
-            for (int t = threadIdx.x; t < ncell * a.kc; t += 256) {
-                int cell = t / a.kc, kk = t - cell * a.kc;
-                int rr = cell / hc, c = cell - rr * hc;
-                int gy = vy0 + rr + dy, gx = vx0 - a.wx + c, k = k0 + kk;
-                cf32 v{0.f, 0.f};
-                if (gy >= 0 && gy < a.ny && gx >= 0 && gx < a.nx && k < a.mu)
-                    v = a.r[((int64_t)gy * a.nx + gx) * a.mu + k];
-                halo[cell * cs + kk] = v;
-            }
+            stage_halo<8>(halo, cs, tpy, hc, a.kc, a.r, a.ny, a.nx, a.mu, vy0 + dy, vx0 - a.wx, k0, a.mu);
             const int ady = dy < 0 ? -dy : dy;
             for (int t = threadIdx.x; t < (a.wx + 1) * zspan; t += 256) {
                 int adx = t / zspan, zz = t - adx * zspan;
@@ -390,7 +417,7 @@ static int fwd_args(const Plan& P, const cf32* x, FwdArgs& a, size_t& lds) {
     const int hc = tpx + 2 * a.wx;
     int zc = 16;
     while (zc > 4 && (size_t)tpy * hc * (zc + 1) * sizeof(cf32) + (size_t)(a.wx + 1) * zc * 4 > kLdsMax)
-        zc -= 4;
+        zc /= 2;                                  // powers of two: the staging needs zc | blockDim
     lds = (size_t)tpy * hc * (zc + 1) * sizeof(cf32) + (size_t)(a.wx + 1) * zc * 4;
     if (lds > kLdsMax) fail(UFSS_ERR_UNSUPPORTED, "aperture window too wide for the GEMM path");
     a.zc = zc;
@@ -423,7 +450,7 @@ static int adj_args(const Plan& P, cf32* out, AdjArgs& a, size_t& lds) {
         return (size_t)tpy * hc * (k + 1) * sizeof(cf32) + (size_t)(a.wx + 1) * zspan * 4 +
                (size_t)k * 4;
     };
-    while (kc > 4 && lds_of(kc) > kLdsMax) kc -= 4;
+    while (kc > 4 && lds_of(kc) > kLdsMax) kc /= 2;   // powers of two (staging)
     if (lds_of(kc) > kLdsMax) fail(UFSS_ERR_UNSUPPORTED, "aperture window too wide for the GEMM path");
     a.kc = kc;
     lds = lds_of(kc);

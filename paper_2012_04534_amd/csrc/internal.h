@@ -104,6 +104,8 @@ void launch_adjoint_pre(const Plan& P, const cf32* r, hipStream_t s);
 void launch_to_bf16(const cf32* x, void* out, int64_t n, hipStream_t s);
 int gemm_split(const Plan& P);
 int adj_split(const Plan& P);
+// Sets the split factors (and reallocates the split workspace when they change).
+void plan_set_splits(Plan& P, int fs, int as, int zs);
 // Grouped GEMM launches: one grid runs the tiles of many plans.  A descriptor
 // is the kernel's argument block for one plan (opaque bytes of desc_size);
 // blk[b] = {plan index, block index inside that plan's own grid}.

@@ -27,7 +27,7 @@ EXPORTED = [
     "ufss_last_error", "ufss_select_freqs", "ufss_plan_create", "ufss_plan_destroy",
     "ufss_plan_info_get", "ufss_forward", "ufss_adjoint", "ufss_lipschitz", "ufss_fista",
     "ufss_shrink_update", "ufss_absmax", "ufss_time_kernel", "ufss_fista_batched",
-    "ufss_autotune", "ufss_unrolled_create", "ufss_unrolled_destroy", "ufss_unrolled_params",
+    "ufss_autotune", "ufss_plan_set_tiling", "ufss_unrolled_create", "ufss_unrolled_destroy", "ufss_unrolled_params",
     "ufss_unrolled_forward", "ufss_unrolled_grad", "ufss_unrolled_train_step",
     "ufss_unrolled_save", "ufss_unrolled_load",
 ]
@@ -109,6 +109,7 @@ def lib():
                                    ctypes.c_int),
             "ufss_autotune": ([P, ctypes.c_char_p, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), P],
                               ctypes.c_int),
+            "ufss_plan_set_tiling": ([P, I32, I32, I32, I32], ctypes.c_int),
             "ufss_unrolled_create": ([P, I32, I32, D, D, U64, ctypes.POINTER(P)], ctypes.c_int),
             "ufss_unrolled_destroy": ([P], ctypes.c_int),
             "ufss_unrolled_params": ([P, P, P, ctypes.POINTER(I64)], ctypes.c_int),
@@ -314,6 +315,12 @@ def ufss_autotune(plan, cache_path=None, use_cache=True, write_cache=True, strea
     _check(lib().ufss_autotune(plan.handle, path, flags, ctypes.byref(fs), ctypes.byref(asp),
                                _stream(stream)))
     return fs.value, asp.value
+
+
+def ufss_plan_set_tiling(plan, fwd_split=0, adj_split=0, fwd_waves=0, fwd_zsplit=0):
+    """Manual GEMM tiling (0 keeps the current value); see ufss_autotune."""
+    _check(lib().ufss_plan_set_tiling(plan.handle, int(fwd_split), int(adj_split), int(fwd_waves),
+                                      int(fwd_zsplit)))
 
 
 class Net:

@@ -52,6 +52,10 @@ CASES = [
     (dict(nx=40, ny=1, nz=70, nt=128, win=-1), 11, True),
     (dict(nx=5, ny=3, nz=9, nt=64, win=1), 1, False),
     (dict(nx=19, ny=17, nz=100, nt=256, win=5), 30, False),
+    # union of 66 bins: a second forward bin tile with one active 16-bin sub-tile
+    (dict(nx=20, ny=3, nz=20, nt=512, win=4), 40, True),
+    # grid wide enough for 64-position tiles, ragged in x
+    (dict(nx=50, ny=2, nz=16, nt=128, win=-1), 10, False),
 ]
 
 

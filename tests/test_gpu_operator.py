@@ -184,3 +184,38 @@ def test_plan_info_and_errors(dev):
     with pytest.raises(ValueError):
         u.ufss_forward(plan, x, y)
     plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_manual_tiling_same_operator(dtype, dev):
+    """Every tiling of the GEMM path computes the same operator: d_y and depth
+    splits (including parts left without rows), waves per workgroup."""
+    u = ufss()
+    g = W.geometry(11, 9, 40, 256, win_x=4, win_y=4)
+    bins, _ = u.ufss_select_freqs(g, 20, True, 77)
+    x = W.cn((g["ny"], g["nx"], g["nz"]), 5).astype(np.complex64)
+    y = W.cn((g["ny"], g["nx"], 20), 6).astype(np.complex64)
+    A = O.dense_A(g, bins)
+    y_ref = (A @ x.reshape(-1).astype(np.complex128)).reshape(y.shape)
+    x_ref = (A.conj().T @ y.reshape(-1).astype(np.complex128)).reshape(x.shape)
+    tol = TOL32 if dtype == "f32" else 1e-2
+    plan = u.Plan(g, 20, True, bins, dtype=u.F32 if dtype == "f32" else u.BF16)
+    tilings = [(1, 1, 1, 1), (3, 2, 2, 3), (9, 9, 8, 10), (64, 64, 3, 64)]
+    if dtype == "bf16":
+        tilings = [(f, a, 0, 1) for f, a, _, _ in tilings]
+    xt = torch.from_numpy(x).to(dev)
+    yt = torch.from_numpy(y).to(dev)
+    for t in tilings:
+        u.ufss_plan_set_tiling(plan, *t)
+        assert plan.info()["fwd_split"] == t[0] and plan.info()["adj_split"] == t[1]
+        yo = torch.empty_like(yt)
+        xo = torch.empty_like(xt)
+        u.ufss_forward(plan, xt, yo)
+        u.ufss_adjoint(plan, yt, xo)
+        torch.cuda.synchronize()
+        ey, ex = errs(yo.cpu().numpy(), y_ref), errs(xo.cpu().numpy(), x_ref)
+        assert max(ey) < tol and max(ex) < tol, (t, ey, ex)
+    for bad in [(-1, 0, 0, 0), (65, 0, 0, 0), (0, 0, 9, 0), (0, 0, 0, 65)]:
+        with pytest.raises(u.UfssError):
+            u.ufss_plan_set_tiling(plan, *bad)
+    plan.close()
