@@ -239,6 +239,17 @@ int ufss_autotune(ufss_plan_t plan, const char* cache_path, int32_t flags,
 int ufss_plan_set_tiling(ufss_plan_t plan, int32_t fwd_split, int32_t adj_split,
                          int32_t fwd_waves, int32_t fwd_zsplit);
 
+/* BF16 GEMM plans: the BF16 phasors exp(-j 2 pi k tau f_s / N_t) of every
+ * (|d_y|, |d_x|, z, selected bin) (paper Sec. IV-B: the operator depends on the
+ * lateral offset only through |d|) are kept in two precomputed HBM tables, one
+ * per kernel layout, when they fit in 4 GiB together (the default at plan
+ * creation); otherwise the kernels generate them.  enable = 0 frees the tables
+ * (phasors generated), 1 builds them (if they fit).  Both settings compute the
+ * same values up to BF16 rounding of the generation's angle-addition steps.
+ *   active_out  HOST, optional: 1 if the tables are in use afterwards
+ * Synchronises the device.  Errors: UNSUPPORTED for other plans. */
+int ufss_plan_set_phasor_tables(ufss_plan_t plan, int32_t enable, int32_t* active_out);
+
 /* ---- learned unrolled solver ---------------------------------------------
  * An S-stage unrolling of FISTA (paper Alg. 1) with learned step sizes and
  * thresholds and a 3x3x3 convolutional correction (2 -> channels -> 2 real

@@ -380,6 +380,16 @@ int ufss_plan_set_tiling(ufss_plan_t plan, int32_t fwd_split, int32_t adj_split,
     UFSS_GUARD_END
 }
 
+int ufss_plan_set_phasor_tables(ufss_plan_t plan, int32_t enable, int32_t* active_out) {
+    UFSS_GUARD_BEGIN
+    Plan* P = as_plan(plan);
+    if (P->algo != UFSS_ALGO_GEMM || P->dtype != UFSS_BF16)
+        ufss::fail(UFSS_ERR_UNSUPPORTED, "phasor tables apply to BF16 GEMM plans only");
+    ufss::bf16_set_tables(*P, enable != 0);
+    if (active_out) *active_out = P->d_ptab_f != nullptr;
+    UFSS_GUARD_END
+}
+
 static ufss::Net* as_net(ufss_net_t n) {
     if (!n) ufss::fail(UFSS_ERR_INVALID_ARG, "net is NULL");
     return reinterpret_cast<ufss::Net*>(n);

@@ -51,6 +51,34 @@ __device__ __forceinline__ bf8 neg_bf8(bf8 v) {
     return __builtin_bit_cast(bf8, w);
 }
 
+// Phasor tiles read from the precomputed tables: a tile is `nrows` rows of
+// 2 planes x 32 BF16 values (128 contiguous bytes per row in the table), copied
+// to pc / ps rows of PROW.  256 threads move 16 bytes each per pass, two passes
+// cover 64 rows; rows at or past `rows_valid` are zero.  Loads are issued into
+// registers first (tab_load) so they overlap the MFMA work of the current tile,
+// and written to LDS afterwards (tab_store).
+struct TabRegs {
+    u4 v[2];
+};
+
+__device__ __forceinline__ void tab_load(TabRegs& R, const __bf16* __restrict__ src, int rows_valid) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const int t = threadIdx.x + p * 256, row = t >> 3, part = t & 7;
+        R.v[p] = u4{0u, 0u, 0u, 0u};
+        if (row < rows_valid) R.v[p] = *reinterpret_cast<const u4*>(src + (size_t)row * 64 + part * 8);
+    }
+}
+
+__device__ __forceinline__ void tab_store(const TabRegs& R, __bf16* pc, __bf16* ps, int nrows) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const int t = threadIdx.x + p * 256, row = t >> 3, part = t & 7;
+        if (row < nrows)
+            *reinterpret_cast<u4*>((part < 4 ? pc : ps) + row * PROW + (part & 3) * 8) = R.v[p];
+    }
+}
+
 // Cooperative phasor generation: `rows` x ZCB entries of cos / sin(2 pi k u)
 // for the tile rows' bins.  Thread t takes one reduction index and a run of
 // `run` consecutive rows.  kidx(row) gives the bin, uval(col) the delay.
@@ -96,10 +124,12 @@ struct FwdB {
     int sw, ntx, nty, nbt, split;
     int64_t npos;
     int nblk;              // blocks of this plan's grid
+    const __bf16* tab;     // phasor tiles [wy+1][wx+1][nzc][mu][2][32] or null
 };
 
 template <int NP, int NB>
 __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nblk, unsigned char* smem) {
+    static_assert(NB * 16 <= 64, "table tiles are copied in two passes of 256 x 16 bytes");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int sw = a.sw, sh = 16 / sw;
     const int tpx = 4 * NP * sw, tpy = sh;
@@ -157,10 +187,11 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
                 halo[(size_t)cell * CELL + ZCB + zz] = v.im;
             }
             const int ady = dy < 0 ? -dy : dy;
-            for (int t = threadIdx.x; t < (a.wx + 1) * ZCB; t += 256) {
-                const int adx = t / ZCB, zz = t - adx * ZCB, z = z0 + zz;
-                ulds[t] = z < a.nz ? a.u[((int64_t)ady * (a.wx + 1) + adx) * a.nz + z] : 0u;
-            }
+            if (!a.tab)
+                for (int t = threadIdx.x; t < (a.wx + 1) * ZCB; t += 256) {
+                    const int adx = t / ZCB, zz = t - adx * ZCB, z = z0 + zz;
+                    ulds[t] = z < a.nz ? a.u[((int64_t)ady * (a.wx + 1) + adx) * a.nz + z] : 0u;
+                }
             __syncthreads();
             auto gen = [&](int dx, int buf) {
                 const int adx = dx < 0 ? -dx : dx;
@@ -170,11 +201,29 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
                          [&](int r) { return klds[r]; },
                          [&](int col) { return ulds[adx * ZCB + col]; });
             };
-            if (dx_lo <= dx_hi) gen(dx_lo, 0);
+            // table tiles of this (|d_y|, depth chunk, bin tile), one per |d_x|
+            const int nzc = (a.nz + ZCB - 1) / ZCB;
+            const __bf16* tsrc = a.tab ? a.tab + (((int64_t)ady * (a.wx + 1) * nzc + z0 / ZCB) * a.mu + mb0) * 64
+                                       : nullptr;
+            const int64_t tstep = (int64_t)nzc * a.mu * 64;
+            if (dx_lo <= dx_hi) {
+                if (a.tab) {
+                    TabRegs R;
+                    tab_load(R, tsrc + (dx_lo < 0 ? -dx_lo : dx_lo) * tstep, nbins);
+                    tab_store(R, ptile, ptile + NB * 16 * PROW, prow_count);
+                } else {
+                    gen(dx_lo, 0);
+                }
+            }
             __syncthreads();
             int buf = 0;
             for (int dx = dx_lo; dx <= dx_hi; ++dx) {
-                if (dx < dx_hi) gen(dx + 1, buf ^ 1);
+                const bool more = dx < dx_hi;
+                TabRegs R;
+                if (more) {
+                    if (a.tab) tab_load(R, tsrc + (dx + 1 < 0 ? -(dx + 1) : dx + 1) * tstep, nbins);
+                    else gen(dx + 1, buf ^ 1);
+                }
                 const __bf16* pc = ptile + (size_t)buf * 2 * NB * 16 * PROW;
                 const __bf16* ps = pc + NB * 16 * PROW;
                 // A operands: x at (p - d) for this lane's position of each sub-tile
@@ -202,6 +251,10 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
                         acc_im[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xi[s], c8, acc_im[s][nb], 0, 0, 0);
                         acc_im[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xr[s], ns8, acc_im[s][nb], 0, 0, 0);
                     }
+                }
+                if (more && a.tab) {
+                    __bf16* pn = ptile + (size_t)(buf ^ 1) * 2 * NB * 16 * PROW;
+                    tab_store(R, pn, pn + NB * 16 * PROW, prow_count);
                 }
                 __syncthreads();
                 buf ^= 1;
@@ -256,6 +309,7 @@ struct AdjB {
     int sw, ntx, nty, nzt, split;
     int64_t nvox;
     int nblk;              // blocks of this plan's grid
+    const __bf16* tab;     // phasor tiles [wy+1][wx+1][nkc][nz][2][32] or null
 };
 
 template <int NV, int NZ>
@@ -264,6 +318,7 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
     const int sw = a.sw, sh = 16 / sw;
     const int tvx = 4 * NV * sw, tvy = sh;
     const int zspan = NZ * 16;
+    static_assert(NZ * 16 <= 64, "table tiles are copied in two passes of 256 x 16 bytes");
 
     int per_xcd = nblk / 8;
     if (per_xcd * 8 == nblk) b = (b % 8) * per_xcd + b / 8;
@@ -312,10 +367,11 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
                 halo[(size_t)cell * CELL + ZCB + kk] = v.im;
             }
             const int ady = dy < 0 ? -dy : dy;
-            for (int t = threadIdx.x; t < (a.wx + 1) * zspan; t += 256) {
-                const int adx = t / zspan, zz = t - adx * zspan, z = zw0 + zz;
-                ulds[t] = z < a.nz ? a.u[((int64_t)ady * (a.wx + 1) + adx) * a.nz + z] : 0u;
-            }
+            if (!a.tab)
+                for (int t = threadIdx.x; t < (a.wx + 1) * zspan; t += 256) {
+                    const int adx = t / zspan, zz = t - adx * zspan, z = zw0 + zz;
+                    ulds[t] = z < a.nz ? a.u[((int64_t)ady * (a.wx + 1) + adx) * a.nz + z] : 0u;
+                }
             for (int t = threadIdx.x; t < ZCB; t += 256) klds[t] = (k0 + t < a.mu) ? a.kb[k0 + t] : 0;
             __syncthreads();
             auto gen = [&](int dx, int buf) {
@@ -348,11 +404,30 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
                     }
                 }
             };
-            if (dx_lo <= dx_hi) gen(dx_lo, 0);
+            // table tiles of this (|d_y|, bin chunk, depth tile), one per |d_x|
+            const int nkc = (a.mu + ZCB - 1) / ZCB;
+            const __bf16* tsrc = a.tab ? a.tab + (((int64_t)ady * (a.wx + 1) * nkc + k0 / ZCB) * a.nz + zw0) * 64
+                                       : nullptr;
+            const int64_t tstep = (int64_t)nkc * a.nz * 64;
+            const int zrows = min(zspan, a.nz - zw0);
+            if (dx_lo <= dx_hi) {
+                if (a.tab) {
+                    TabRegs R;
+                    tab_load(R, tsrc + (dx_lo < 0 ? -dx_lo : dx_lo) * tstep, zrows);
+                    tab_store(R, ptile, ptile + zspan * PROW, zspan);
+                } else {
+                    gen(dx_lo, 0);
+                }
+            }
             __syncthreads();
             int buf = 0;
             for (int dx = dx_lo; dx <= dx_hi; ++dx) {
-                if (dx < dx_hi) gen(dx + 1, buf ^ 1);
+                const bool more = dx < dx_hi;
+                TabRegs R;
+                if (more) {
+                    if (a.tab) tab_load(R, tsrc + (dx + 1 < 0 ? -(dx + 1) : dx + 1) * tstep, zrows);
+                    else gen(dx + 1, buf ^ 1);
+                }
                 const __bf16* pc = ptile + (size_t)buf * 2 * zspan * PROW;
                 const __bf16* ps = pc + zspan * PROW;
                 bf8 rr8[NV], ri8[NV];
@@ -379,6 +454,10 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
                         acc_im[s][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rr8[s], s8, acc_im[s][q], 0, 0, 0);
                         acc_im[s][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ri8[s], c8, acc_im[s][q], 0, 0, 0);
                     }
+                }
+                if (more && a.tab) {
+                    __bf16* pn = ptile + (size_t)(buf ^ 1) * 2 * zspan * PROW;
+                    tab_store(R, pn, pn + zspan * PROW, zspan);
                 }
                 __syncthreads();
                 buf ^= 1;
@@ -504,6 +583,7 @@ static int fwdb_args(const Plan& P, FwdB& a, size_t& lds, int np, int nb) {
     a.nbt = (a.mu + nb * 16 - 1) / (nb * 16);
     a.split = P.fwd_split;
     a.npos = P.npos;
+    a.tab = static_cast<const __bf16*>(P.d_ptab_f);
     lds = fwd_bf16_lds(P, np, nb);
     if (lds > kLdsMaxB) fail(UFSS_ERR_UNSUPPORTED, "aperture window too wide for the BF16 GEMM path");
     a.nblk = a.ntx * a.nty * a.nbt * a.split;
@@ -530,6 +610,7 @@ static int adjb_args(const Plan& P, cf32* out, AdjB& a, size_t& lds, int nv) {
     a.nzt = (a.nz + kBfNZ * 16 - 1) / (kBfNZ * 16);
     a.split = P.adj_split;
     a.nvox = P.nvox;
+    a.tab = static_cast<const __bf16*>(P.d_ptab_a);
     lds = adj_bf16_lds(P, nv);
     if (lds > kLdsMaxB) fail(UFSS_ERR_UNSUPPORTED, "aperture window too wide for the BF16 GEMM path");
     a.nblk = a.ntx * a.nty * a.nzt * a.split;
@@ -559,6 +640,67 @@ void launch_adjoint_gemm_bf16(const Plan& P, cf32* out, hipStream_t s) {
         hipLaunchKernelGGL((adj_gemm_bf16_kernel<2, kBfNZ>), dim3(a.nblk), dim3(256), lds, s, a);
     UFSS_HIP(hipGetLastError());
     if (a.split > 1) launch_sum_parts(P.d_gpart, a.split, P.nvox, out, s);
+}
+
+// Phasor tables: entry (|d_y|, |d_x|, z, k) = cos / sin(2 pi kb[k] u(|d_y|, |d_x|, z))
+// rounded to BF16, zero past nz or mu, written in both kernels' tile layouts.
+__global__ void build_ptab_kernel(const uint32_t* __restrict__ u, const int* __restrict__ kb, int wx,
+                                  int wy, int nz, int mu, int nzc, int nkc, __bf16* __restrict__ tf,
+                                  __bf16* __restrict__ ta) {
+    const int kw = nkc * ZCB, zw = nzc * ZCB;
+    const int64_t n = (int64_t)(wy + 1) * (wx + 1) * zw * kw;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int k = (int)(t % kw);
+        const int64_t r = t / kw;
+        const int z = (int)(r % zw);
+        const int64_t dxy = r / zw;                   // |d_y| * (wx + 1) + |d_x|
+        float c = 0.f, sn = 0.f;
+        if (z < nz && k < mu) sincos_turns((uint32_t)kb[k] * u[dxy * nz + z], c, sn);
+        if (k < mu) {
+            __bf16* f = tf + ((dxy * nzc + z / ZCB) * mu + k) * 64 + z % ZCB;
+            f[0] = (__bf16)c;
+            f[ZCB] = (__bf16)sn;
+        }
+        if (z < nz) {
+            __bf16* q = ta + ((dxy * nkc + k / ZCB) * nz + z) * 64 + k % ZCB;
+            q[0] = (__bf16)c;
+            q[ZCB] = (__bf16)sn;
+        }
+    }
+}
+
+static constexpr int64_t kPtabMax = int64_t(4) << 30;   // both tables together
+
+void bf16_set_tables(Plan& P, int enable) {
+    UFSS_HIP(hipDeviceSynchronize());
+    if (P.d_ptab_f) UFSS_HIP(hipFree(P.d_ptab_f));
+    if (P.d_ptab_a) UFSS_HIP(hipFree(P.d_ptab_a));
+    P.d_ptab_f = P.d_ptab_a = nullptr;
+    P.ws_bytes -= P.ptab_bytes;
+    P.ptab_bytes = 0;
+    if (!enable || P.dtype != UFSS_BF16 || P.algo != UFSS_ALGO_GEMM) return;
+    const int mu = (int)P.ubins_h.size();
+    const int nzc = (P.g.nz + ZCB - 1) / ZCB, nkc = (mu + ZCB - 1) / ZCB;
+    const int64_t dxy = (int64_t)(P.d.wy + 1) * (P.d.wx + 1);
+    const int64_t fb = dxy * nzc * mu * 64 * 2, ab = dxy * nkc * P.g.nz * 64 * 2;
+    if (fb + ab > kPtabMax) return;                 // phasors generated in the kernels
+    void *tf = nullptr, *ta = nullptr;
+    if (hipMalloc(&tf, fb) != hipSuccess || hipMalloc(&ta, ab) != hipSuccess) {
+        (void)hipGetLastError();                    // no room: generated in the kernels
+        if (tf) (void)hipFree(tf);
+        return;
+    }
+    const int64_t n = dxy * nzc * ZCB * nkc * ZCB;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(build_ptab_kernel, dim3(blocks), dim3(256), 0, nullptr, P.d_u, P.d_ubins, P.d.wx,
+                       P.d.wy, P.g.nz, mu, nzc, nkc, static_cast<__bf16*>(tf), static_cast<__bf16*>(ta));
+    UFSS_HIP(hipGetLastError());
+    UFSS_HIP(hipDeviceSynchronize());
+    P.d_ptab_f = tf;
+    P.d_ptab_a = ta;
+    P.ptab_bytes = fb + ab;
+    P.ws_bytes += P.ptab_bytes;
 }
 
 size_t bf16_desc_size(GemmKind k) { return k == GemmKind::FwdBF16 ? sizeof(FwdB) : sizeof(AdjB); }

@@ -270,6 +270,7 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
         for (int q = 0; q < NZ; ++q) out_re[s][q] = out_im[s][q] = f4{0.f, 0.f, 0.f, 0.f};
 
     for (int k0 = 0; k0 < a.mu; k0 += a.kc) {
+        const int kcur = min(a.kc, (a.mu - k0 + 3) & ~3);   // last chunk: valid bins, rounded to 4
         for (int dy = dy_lo; dy <= dy_hi; ++dy) {
             __syncthreads();
             stage_halo<8>(halo, cs, tpy, hc, a.kc, a.r, a.ny, a.nx, a.mu, vy0 + dy, vx0 - a.wx, k0, a.mu);
@@ -294,7 +295,7 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
 #pragma unroll
                 for (int q = 0; q < NZ; ++q) uz[q] = ulds[adx * zspan + wave * NZ * 16 + q * 16 + i];
                 const cf32* hrow = halo + (iy * hc + ix + a.wx + dx) * cs;
-                for (int kk = 0; kk < a.kc; kk += 4) {
+                for (int kk = 0; kk < kcur; kk += 4) {
                     const uint32_t k = (uint32_t)klds[kk + kq];
                     cf32 rv[NP];
 #pragma unroll

@@ -77,6 +77,13 @@ struct Plan {
     cf32* d_yraw = nullptr;        // GEMM output over union bins [npos][mu]
     void* d_rop = nullptr;         // adjoint operand (H-scaled), [npos][mu] f32 or bf16
     void* d_xop = nullptr;         // forward operand in BF16 [nvox] (BF16 plans)
+    // BF16 GEMM plans: precomputed phasor tiles (cos, sin of 2 pi k u) in BF16,
+    // laid out as the kernels' LDS tiles; null = generated inside the kernels.
+    //   forward [wy+1][wx+1][ceil(nz/32)][mu][2][32 depths]
+    //   adjoint [wy+1][wx+1][ceil(mu/32)][nz][2][32 bins]
+    void* d_ptab_f = nullptr;
+    void* d_ptab_a = nullptr;
+    int64_t ptab_bytes = 0;
     double* d_part = nullptr;      // FP64 block partials
     int part_cap = 0;
     double* d_scalars = nullptr;   // small FP64 results
@@ -121,6 +128,8 @@ int bf16_make_desc(GemmKind k, const Plan& P, const void* in, void* out, void* d
 void bf16_launch_grouped(GemmKind k, const void* descs, const int2* blk, int nblocks, size_t lds,
                          hipStream_t s);
 bool bf16_supported(const Plan& P);
+// Builds (enable != 0, if within the size limit) or frees the BF16 phasor tables.
+void bf16_set_tables(Plan& P, int enable);
 int bf16_fwd_split(const Plan& P);
 int bf16_adj_split(const Plan& P);
 void launch_forward_gemm_bf16(const Plan& P, hipStream_t s);

@@ -158,7 +158,7 @@ static void free_plan(Plan* P) {
     if (!P) return;
     void* ptrs[] = {P->d_bins, P->d_ubins, P->d_map, P->d_hsel, P->d_u, P->d_yraw,
                     P->d_rop, P->d_xop, P->d_part, P->d_scalars, P->d_r, P->d_g,
-                    P->d_gamma, P->d_v, P->d_stats, P->d_gpart};
+                    P->d_gamma, P->d_v, P->d_stats, P->d_gpart, P->d_ptab_f, P->d_ptab_a};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
@@ -253,6 +253,7 @@ Plan* plan_create(const ufss_geom* g, int m, int per_position, const int32_t* bi
         P->d_yraw = dalloc<cf32>(*P, (size_t)P->fwd_split * npos * mu);
         P->d_rop = dalloc<cf32>(*P, (size_t)npos * opw);
         if (P->dtype == UFSS_BF16) P->d_xop = dalloc<cf32>(*P, (size_t)(P->nvox + 1) / 2 + 1);
+        if (algo == UFSS_ALGO_GEMM && P->dtype == UFSS_BF16) bf16_set_tables(*P, 1);
         P->part_cap = 65536;
         P->d_part = dalloc<double>(*P, P->part_cap);
         P->d_scalars = dalloc<double>(*P, 64);

@@ -27,7 +27,7 @@ EXPORTED = [
     "ufss_last_error", "ufss_select_freqs", "ufss_plan_create", "ufss_plan_destroy",
     "ufss_plan_info_get", "ufss_forward", "ufss_adjoint", "ufss_lipschitz", "ufss_fista",
     "ufss_shrink_update", "ufss_absmax", "ufss_time_kernel", "ufss_fista_batched",
-    "ufss_autotune", "ufss_plan_set_tiling", "ufss_unrolled_create", "ufss_unrolled_destroy", "ufss_unrolled_params",
+    "ufss_autotune", "ufss_plan_set_tiling", "ufss_plan_set_phasor_tables", "ufss_unrolled_create", "ufss_unrolled_destroy", "ufss_unrolled_params",
     "ufss_unrolled_forward", "ufss_unrolled_grad", "ufss_unrolled_train_step",
     "ufss_unrolled_save", "ufss_unrolled_load",
 ]
@@ -110,6 +110,7 @@ def lib():
             "ufss_autotune": ([P, ctypes.c_char_p, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), P],
                               ctypes.c_int),
             "ufss_plan_set_tiling": ([P, I32, I32, I32, I32], ctypes.c_int),
+            "ufss_plan_set_phasor_tables": ([P, I32, ctypes.POINTER(I32)], ctypes.c_int),
             "ufss_unrolled_create": ([P, I32, I32, D, D, U64, ctypes.POINTER(P)], ctypes.c_int),
             "ufss_unrolled_destroy": ([P], ctypes.c_int),
             "ufss_unrolled_params": ([P, P, P, ctypes.POINTER(I64)], ctypes.c_int),
@@ -321,6 +322,14 @@ def ufss_plan_set_tiling(plan, fwd_split=0, adj_split=0, fwd_waves=0, fwd_zsplit
     """Manual GEMM tiling (0 keeps the current value); see ufss_autotune."""
     _check(lib().ufss_plan_set_tiling(plan.handle, int(fwd_split), int(adj_split), int(fwd_waves),
                                       int(fwd_zsplit)))
+
+
+def ufss_plan_set_phasor_tables(plan, enable):
+    """BF16 GEMM plans: build (True) or free (False) the phasor tables; returns
+    whether they are in use afterwards."""
+    act = ctypes.c_int32(0)
+    _check(lib().ufss_plan_set_phasor_tables(plan.handle, 1 if enable else 0, ctypes.byref(act)))
+    return bool(act.value)
 
 
 class Net:

@@ -172,3 +172,34 @@ def test_bf16_fista_bscan(dev):
     e = np.linalg.norm(x.cpu().numpy().reshape(-1) - a_ref) / np.linalg.norm(a_ref)
     assert e < TOL16, e
     plan.close()
+
+
+@pytest.mark.parametrize("ci", [2, 5, 6, 7])
+def test_bf16_tables_and_generation_agree(ci, dev):
+    """The precomputed phasor tables (default) and in-kernel generation give
+    the oracle's operator to BF16 accuracy, and agree closely with each other."""
+    u = ufss()
+    gs, m, per_pos = CASES[ci]
+    g = W.geometry(gs["nx"], gs["ny"], gs["nz"], gs["nt"], win_x=gs["win"], win_y=gs["win"])
+    bins, _ = u.ufss_select_freqs(g, m, per_pos, 50 + ci)
+    x = W.cn((g["ny"], g["nx"], g["nz"]), 300 + ci)
+    y = W.cn((g["ny"], g["nx"], m), 400 + ci)
+    A = O.dense_A(g, bins)
+    y_ref = (A @ x.reshape(-1)).reshape(y.shape)
+    x_ref = (A.conj().T @ y.reshape(-1)).reshape(x.shape)
+    plan = u.Plan(g, m, per_pos, bins, dtype=u.BF16)
+    out = {}
+    for enable in (True, False, True):
+        assert u.ufss_plan_set_phasor_tables(plan, enable) == enable
+        yo, xo = apply_both(u, plan, x, y, dev)
+        ey, ex = errs(yo, y_ref), errs(xo, x_ref)
+        assert max(ey) < TOL16 and max(ex) < TOL16, (enable, ey, ex)
+        out.setdefault(enable, []).append((yo, xo))
+    # tables rebuilt after freeing: identical results
+    (y1, x1), (y2, x2) = out[True]
+    assert np.array_equal(y1, y2) and np.array_equal(x1, x2)
+    plan.close()
+    fplan = u.Plan(g, m, per_pos, bins, dtype=u.F32)
+    with pytest.raises(u.UfssError):
+        u.ufss_plan_set_phasor_tables(fplan, True)
+    fplan.close()
