@@ -51,6 +51,45 @@ __device__ __forceinline__ bf8 neg_bf8(bf8 v) {
     return __builtin_bit_cast(bf8, w);
 }
 
+// Stages rows x ncol cells of ZCB complex BF16 values into planar LDS cells
+// (ZCB real parts, then ZCB imaginary parts):
+//   cell (r, c) <- src[((ybase + r) * nx + xbase + c) * ld + i0 + e], e < ZCB,
+// zero for rows outside the grid or past `ilim` along the inner axis (columns
+// are inside the grid by construction).  Each thread keeps one e and walks the
+// cells with a fixed step, with UNR loads in flight before the LDS stores.
+template <int UNR>
+__device__ __forceinline__ void stage_planar(__bf16* __restrict__ halo, int rows, int ncol,
+                                             const cbf16* __restrict__ src, int ny, int nx, int64_t ld,
+                                             int ybase, int xbase, int i0, int ilim) {
+    const int e = threadIdx.x & (ZCB - 1);
+    const int step = blockDim.x / ZCB;
+    const int total = rows * ncol;
+    int cell = threadIdx.x / ZCB;
+    int r = cell / ncol, c = cell - r * ncol;
+    const bool eok = i0 + e < ilim;
+    for (; cell < total; cell += UNR * step) {
+        cbf16 v[UNR];
+        int rr = r, cc = c;
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            v[u] = to_cbf16(0.f, 0.f);
+            const int gy = ybase + rr;
+            if (cell + u * step < total && eok && gy >= 0 && gy < ny)
+                v[u] = src[((int64_t)gy * nx + xbase + cc) * ld + i0 + e];
+            cc += step;
+            while (cc >= ncol) { cc -= ncol; ++rr; }
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+            if (cell + u * step < total) {
+                halo[(size_t)(cell + u * step) * CELL + e] = v[u].re;
+                halo[(size_t)(cell + u * step) * CELL + ZCB + e] = v[u].im;
+            }
+        r = rr;
+        c = cc;
+    }
+}
+
 // Phasor tiles read from the precomputed tables: a tile is `nrows` rows of
 // 2 planes x 32 BF16 values (128 contiguous bytes per row in the table), copied
 // to pc / ps rows of PROW.  256 threads move 16 bytes each per pass, two passes
@@ -177,15 +216,7 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
         for (int dy = dy_lo; dy <= dy_hi; ++dy) {
             __syncthreads();
             // stage x rows (planar bf16) and the delay slab of |dy|
-            for (int t = threadIdx.x; t < tpy * ncol * ZCB; t += 256) {
-                const int zz = t % ZCB, cell = t / ZCB;
-                const int r = cell / ncol, c = cell - r * ncol;
-                const int gy = py0 + r - dy, gx = cx_lo + c, z = z0 + zz;
-                cbf16 v = to_cbf16(0.f, 0.f);
-                if (gy >= 0 && gy < a.ny && z < a.nz) v = a.x[((int64_t)gy * a.nx + gx) * a.nz + z];
-                halo[(size_t)cell * CELL + zz] = v.re;
-                halo[(size_t)cell * CELL + ZCB + zz] = v.im;
-            }
+            stage_planar<8>(halo, tpy, ncol, a.x, a.ny, a.nx, a.nz, py0 - dy, cx_lo, z0, a.nz);
             const int ady = dy < 0 ? -dy : dy;
             if (!a.tab)
                 for (int t = threadIdx.x; t < (a.wx + 1) * ZCB; t += 256) {
@@ -206,11 +237,16 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
             const __bf16* tsrc = a.tab ? a.tab + (((int64_t)ady * (a.wx + 1) * nzc + z0 / ZCB) * a.mu + mb0) * 64
                                        : nullptr;
             const int64_t tstep = (int64_t)nzc * a.mu * 64;
+            auto tile_at = [&](int dx) { return tsrc + (dx < 0 ? -dx : dx) * tstep; };
+            // table path: tile dx + 1 waits in registers (Rn) while dx is consumed
+            // and dx + 2 is being loaded, so a load has two steps to arrive
+            TabRegs Rn;
             if (dx_lo <= dx_hi) {
                 if (a.tab) {
-                    TabRegs R;
-                    tab_load(R, tsrc + (dx_lo < 0 ? -dx_lo : dx_lo) * tstep, nbins);
-                    tab_store(R, ptile, ptile + NB * 16 * PROW, prow_count);
+                    TabRegs R0;
+                    tab_load(R0, tile_at(dx_lo), nbins);
+                    if (dx_lo < dx_hi) tab_load(Rn, tile_at(dx_lo + 1), nbins);
+                    tab_store(R0, ptile, ptile + NB * 16 * PROW, prow_count);
                 } else {
                     gen(dx_lo, 0);
                 }
@@ -220,9 +256,10 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
             for (int dx = dx_lo; dx <= dx_hi; ++dx) {
                 const bool more = dx < dx_hi;
                 TabRegs R;
-                if (more) {
-                    if (a.tab) tab_load(R, tsrc + (dx + 1 < 0 ? -(dx + 1) : dx + 1) * tstep, nbins);
-                    else gen(dx + 1, buf ^ 1);
+                if (a.tab) {
+                    if (dx + 2 <= dx_hi) tab_load(R, tile_at(dx + 2), nbins);
+                } else if (more) {
+                    gen(dx + 1, buf ^ 1);
                 }
                 const __bf16* pc = ptile + (size_t)buf * 2 * NB * 16 * PROW;
                 const __bf16* ps = pc + NB * 16 * PROW;
@@ -254,10 +291,11 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
                 }
                 if (more && a.tab) {
                     __bf16* pn = ptile + (size_t)(buf ^ 1) * 2 * NB * 16 * PROW;
-                    tab_store(R, pn, pn + NB * 16 * PROW, prow_count);
+                    tab_store(Rn, pn, pn + NB * 16 * PROW, prow_count);
                 }
                 __syncthreads();
                 buf ^= 1;
+                Rn = R;
             }
         }
     }
@@ -357,15 +395,7 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
     for (int k0 = 0; k0 < a.mu; k0 += ZCB) {
         for (int dy = dy_lo; dy <= dy_hi; ++dy) {
             __syncthreads();
-            for (int t = threadIdx.x; t < tvy * ncol * ZCB; t += 256) {
-                const int kk = t % ZCB, cell = t / ZCB;
-                const int rr = cell / ncol, c = cell - rr * ncol;
-                const int gy = vy0 + rr + dy, gx = cx_lo + c, k = k0 + kk;
-                cbf16 v = to_cbf16(0.f, 0.f);
-                if (gy >= 0 && gy < a.ny && k < a.mu) v = a.r[((int64_t)gy * a.nx + gx) * a.mu + k];
-                halo[(size_t)cell * CELL + kk] = v.re;
-                halo[(size_t)cell * CELL + ZCB + kk] = v.im;
-            }
+            stage_planar<8>(halo, tvy, ncol, a.r, a.ny, a.nx, a.mu, vy0 + dy, cx_lo, k0, a.mu);
             const int ady = dy < 0 ? -dy : dy;
             if (!a.tab)
                 for (int t = threadIdx.x; t < (a.wx + 1) * zspan; t += 256) {
@@ -410,11 +440,14 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
                                        : nullptr;
             const int64_t tstep = (int64_t)nkc * a.nz * 64;
             const int zrows = min(zspan, a.nz - zw0);
+            auto tile_at = [&](int dx) { return tsrc + (dx < 0 ? -dx : dx) * tstep; };
+            TabRegs Rn;                      // as in the forward: two steps of prefetch
             if (dx_lo <= dx_hi) {
                 if (a.tab) {
-                    TabRegs R;
-                    tab_load(R, tsrc + (dx_lo < 0 ? -dx_lo : dx_lo) * tstep, zrows);
-                    tab_store(R, ptile, ptile + zspan * PROW, zspan);
+                    TabRegs R0;
+                    tab_load(R0, tile_at(dx_lo), zrows);
+                    if (dx_lo < dx_hi) tab_load(Rn, tile_at(dx_lo + 1), zrows);
+                    tab_store(R0, ptile, ptile + zspan * PROW, zspan);
                 } else {
                     gen(dx_lo, 0);
                 }
@@ -424,9 +457,10 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
             for (int dx = dx_lo; dx <= dx_hi; ++dx) {
                 const bool more = dx < dx_hi;
                 TabRegs R;
-                if (more) {
-                    if (a.tab) tab_load(R, tsrc + (dx + 1 < 0 ? -(dx + 1) : dx + 1) * tstep, zrows);
-                    else gen(dx + 1, buf ^ 1);
+                if (a.tab) {
+                    if (dx + 2 <= dx_hi) tab_load(R, tile_at(dx + 2), zrows);
+                } else if (more) {
+                    gen(dx + 1, buf ^ 1);
                 }
                 const __bf16* pc = ptile + (size_t)buf * 2 * zspan * PROW;
                 const __bf16* ps = pc + zspan * PROW;
@@ -457,10 +491,11 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
                 }
                 if (more && a.tab) {
                     __bf16* pn = ptile + (size_t)(buf ^ 1) * 2 * zspan * PROW;
-                    tab_store(R, pn, pn + zspan * PROW, zspan);
+                    tab_store(Rn, pn, pn + zspan * PROW, zspan);
                 }
                 __syncthreads();
                 buf ^= 1;
+                Rn = R;
             }
         }
     }
