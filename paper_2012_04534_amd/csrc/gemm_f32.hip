@@ -16,7 +16,8 @@
 //
 // MFMA: v_mfma_f32_16x16x4_f32.  Lane l holds A[i = l%16][k = l/16],
 // B[k = l/16][j = l%16] and D[i = 4(l/16) + r][j = l%16] for r = 0..3.
-// Complex products use four real MFMAs on split real / imaginary parts.
+// Complex products use three real MFMAs on split real / imaginary parts
+// (Gauss's form: one product of sums, two products with combined phasors).
 //
 // Tiling (both kernels): a workgroup of 4 waves owns one lateral tile of
 // NP sub-tiles of 16 positions (sw x 16/sw each, sw = 4 for C-scans, 16 for
@@ -150,9 +151,12 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
             }
             __syncthreads();
             if (!wave_active) continue;
-            f4 in_re[NP], in_im[NP];
+            // Gauss's three-product form of (xr + j xi)(c - j s):
+            //   m1 = c (xr + xi), m2 = xr (-s - c), m3 = xi (c - s);
+            //   Re = m1 - m3 = xr c + xi s,  Im = m1 + m2 = xi c - xr s
+            f4 m1[NP], m2[NP], m3[NP];
 #pragma unroll
-            for (int s = 0; s < NP; ++s) in_re[s] = in_im[s] = f4{0.f, 0.f, 0.f, 0.f};
+            for (int s = 0; s < NP; ++s) m1[s] = m2[s] = m3[s] = f4{0.f, 0.f, 0.f, 0.f};
             for (int dx = dx_lo; dx <= dx_hi; ++dx) {
                 const int adx = dx < 0 ? -dx : dx;
                 const uint32_t* urow = ulds + adx * a.zc;
@@ -168,21 +172,21 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
                 for (int zz = 0; zz < a.zc; zz += 4) {
                     float c, sn;
                     phasor(kbin * urow[zz + kq], c, sn);
+                    const float bm = -sn - c, bp = c - sn;
 #pragma unroll
                     for (int s = 0; s < NP; ++s) {
                         if (!act[s]) continue;
                         cf32 xv = hrow[s * sw * cs + zz + kq];
-                        in_re[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.re, c, in_re[s], 0, 0, 0);
-                        in_re[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.im, sn, in_re[s], 0, 0, 0);
-                        in_im[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.im, c, in_im[s], 0, 0, 0);
-                        in_im[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.re, -sn, in_im[s], 0, 0, 0);
+                        m1[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.re + xv.im, c, m1[s], 0, 0, 0);
+                        m2[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.re, bm, m2[s], 0, 0, 0);
+                        m3[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.im, bp, m3[s], 0, 0, 0);
                     }
                 }
             }
 #pragma unroll
             for (int s = 0; s < NP; ++s) {
-                out_re[s] += in_re[s];
-                out_im[s] += in_im[s];
+                out_re[s] += m1[s] - m3[s];
+                out_im[s] += m1[s] + m2[s];
             }
         }
     }
@@ -284,11 +288,14 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
                 klds[t] = (k0 + t < a.mu) ? a.kb[k0 + t] : 0;
             __syncthreads();
             if (!wave_active) continue;
-            f4 in_re[NP][NZ], in_im[NP][NZ];
+            // Gauss's three-product form of (rr + j ri)(c + j s):
+            //   m1 = c (rr + ri), m2 = rr (s - c), m3 = ri (c + s);
+            //   Re = m1 - m3 = rr c - ri s,  Im = m1 + m2 = rr s + ri c
+            f4 m1[NP][NZ], m2[NP][NZ], m3[NP][NZ];
 #pragma unroll
             for (int s = 0; s < NP; ++s)
 #pragma unroll
-                for (int q = 0; q < NZ; ++q) in_re[s][q] = in_im[s][q] = f4{0.f, 0.f, 0.f, 0.f};
+                for (int q = 0; q < NZ; ++q) m1[s][q] = m2[s][q] = m3[s][q] = f4{0.f, 0.f, 0.f, 0.f};
             for (int dx = dx_lo; dx <= dx_hi; ++dx) {
                 const int adx = dx < 0 ? -dx : dx;
                 uint32_t uz[NZ];
@@ -298,19 +305,22 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
                 for (int kk = 0; kk < kcur; kk += 4) {
                     const uint32_t k = (uint32_t)klds[kk + kq];
                     cf32 rv[NP];
+                    float rs[NP];
 #pragma unroll
-                    for (int s = 0; s < NP; ++s) rv[s] = hrow[s * sw * cs + kk + kq];
+                    for (int s = 0; s < NP; ++s) {
+                        rv[s] = hrow[s * sw * cs + kk + kq];
+                        rs[s] = rv[s].re + rv[s].im;
+                    }
 #pragma unroll
                     for (int q = 0; q < NZ; ++q) {
                         float c, sn;
                         phasor(k * uz[q], c, sn);
+                        const float bm = sn - c, bp = c + sn;
 #pragma unroll
                         for (int s = 0; s < NP; ++s) {
-                            // (rr + j ri)(c + j s) = rr c - ri s + j (rr s + ri c)
-                            in_re[s][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(rv[s].re, c, in_re[s][q], 0, 0, 0);
-                            in_re[s][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(rv[s].im, -sn, in_re[s][q], 0, 0, 0);
-                            in_im[s][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(rv[s].re, sn, in_im[s][q], 0, 0, 0);
-                            in_im[s][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(rv[s].im, c, in_im[s][q], 0, 0, 0);
+                            m1[s][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(rs[s], c, m1[s][q], 0, 0, 0);
+                            m2[s][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(rv[s].re, bm, m2[s][q], 0, 0, 0);
+                            m3[s][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(rv[s].im, bp, m3[s][q], 0, 0, 0);
                         }
                     }
                 }
@@ -319,8 +329,8 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
             for (int s = 0; s < NP; ++s)
 #pragma unroll
                 for (int q = 0; q < NZ; ++q) {
-                    out_re[s][q] += in_re[s][q];
-                    out_im[s][q] += in_im[s][q];
+                    out_re[s][q] += m1[s][q] - m3[s][q];
+                    out_im[s][q] += m1[s][q] + m2[s][q];
                 }
         }
     }
