@@ -33,9 +33,14 @@ PEAK_HBM = 8e12
 
 # HBM bytes per launch of the dominant kernels, from two rocprofv3 counter runs
 # (FETCH_SIZE, then WRITE_SIZE, each scaled by what the same counter reads for a
-# 256 MiB device copy).  Each entry holds the SHA-256 prefix of the kernel
-# source it was measured on; a changed source reports null instead.
-TRAFFIC = {}
+# 256 MiB device copy), keyed by workload, kernel and tiling (split partials
+# are part of the traffic).  Each entry holds the SHA-256 prefix of the kernel
+# source it was measured on; a changed source or another tiling reports null.
+TRAFFIC = {
+    # 32 x 32 C-scan, FP32 union-GEMM, autotuned tiling (profiles/cscan32_fp32_gemm_and_phasor.md)
+    "cscan32/gemm/adjoint/as12": {"bytes": 32.289e6, "sha": "f7ef8f7e1c556eea"},
+    "cscan32/gemm/forward/fs4-zs8-nw5": {"bytes": 20.580e6, "sha": "f7ef8f7e1c556eea"},
+}
 TRAFFIC_SRC = {"gemm": "paper_2012_04534_amd/csrc/gemm_f32.hip",
                "phasor": "paper_2012_04534_amd/csrc/phasor.hip"}
 
@@ -46,8 +51,14 @@ def source_sha(rel):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_bytes(workload, algo_name, direction):
-    e = TRAFFIC.get("%s/%s/%s" % (workload, algo_name, direction))
+def tiling_key(info, direction):
+    if direction == "adjoint":
+        return "as%d" % info["adj_split"]
+    return "fs%d-zs%d-nw%d" % (info["fwd_split"], info["fwd_zsplit"], info["fwd_waves"])
+
+
+def traffic_bytes(workload, algo_name, direction, info):
+    e = TRAFFIC.get("%s/%s/%s/%s" % (workload, algo_name, direction, tiling_key(info, direction)))
     if e is None or source_sha(TRAFFIC_SRC[algo_name]) != e["sha"]:
         return None
     return int(e["bytes"])
@@ -338,7 +349,9 @@ def main():
         roof = {"bound": "mfma", "achieved": round(8.0 * cmac / (k_ms * 1e-3) / 1e12, 3),
                 "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s"}
     roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
-    roof["traffic"] = traffic_bytes(args.workload, algo_name, dom)
+    pinfo = plan.info()
+    roof["traffic"] = traffic_bytes(args.workload, algo_name, dom, pinfo)
+    roof["tiling"] = tiling_key(pinfo, dom)
     roof["kernel"] = "%s %s core (%.4f ms per launch)" % (algo_name, dom, k_ms)
     extras["kernel_ms"] = {"forward_core": round(k_f, 4), "adjoint_core": round(k_a, 4)}
 

@@ -80,6 +80,9 @@ typedef struct ufss_plan_info {
     int32_t union_size;   /* bins in the union of per-position subsets         */
     int64_t workspace_bytes;              /* device memory owned by the plan    */
     int32_t fwd_split, adj_split;         /* split-K factors of the GEMM path   */
+    int32_t fwd_waves, fwd_zsplit;       /* FP32 forward: waves per workgroup,
+                                            depth split (1 elsewhere)          */
+    int32_t phasor_tables;               /* 1: BF16 phasor tables in use       */
 } ufss_plan_info;
 
 /* Per-iteration FISTA statistics, FP64, written to HOST arrays of length

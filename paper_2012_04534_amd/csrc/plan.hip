@@ -320,6 +320,10 @@ void plan_info(const Plan* P, ufss_plan_info* info) {
     info->workspace_bytes = P->ws_bytes;
     info->fwd_split = P->fwd_split;
     info->adj_split = P->adj_split;
+    const bool f32_gemm = P->algo == UFSS_ALGO_GEMM && P->dtype == UFSS_F32;
+    info->fwd_waves = f32_gemm ? std::max(1, std::min(P->fwd_nw, ((int)P->ubins_h.size() + 15) / 16)) : 1;
+    info->fwd_zsplit = f32_gemm ? P->fwd_zsplit : 1;
+    info->phasor_tables = P->d_ptab_f != nullptr;
 }
 
 }  // namespace ufss

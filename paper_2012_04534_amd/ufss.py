@@ -62,6 +62,8 @@ class PlanInfo(ctypes.Structure):
         ("algo", ctypes.c_int32), ("union_size", ctypes.c_int32),
         ("workspace_bytes", ctypes.c_int64),
         ("fwd_split", ctypes.c_int32), ("adj_split", ctypes.c_int32),
+        ("fwd_waves", ctypes.c_int32), ("fwd_zsplit", ctypes.c_int32),
+        ("phasor_tables", ctypes.c_int32),
     ]
 
 
