@@ -205,7 +205,8 @@ int ufss_absmax(int64_t n, const void* x, double* out, ufss_stream_t stream);
 /* Batched FISTA over n independent scans of uneven size (each with its own
  * plan), paper Alg. 1 applied to every scan.  Each phase of an iteration runs
  * as ONE grouped launch over all scans (forward GEMM, residual epilogue,
- * adjoint pre pass, adjoint GEMM, split sums, fused update, FP64 reductions),
+ * adjoint pre pass, adjoint GEMM, update fused with the adjoint's split sums,
+ * FP64 reductions),
  * and the `iters` iterations are captured in one hipGraph and launched once on
  * `stream`.  Plans must use the GEMM algorithm (any dtype); a plan may appear
  * only once.
@@ -299,7 +300,8 @@ int ufss_unrolled_load(ufss_net_t net, const char* path);
 
 /* Diagnostic: average duration (ms) of the operator's core kernel, launched
  * `reps` times back to back between two HIP events recorded on `stream`.
- * which = 0: forward core (windowed GEMM, or phasor forward), 1: adjoint core.
+ * which = 0: forward core (windowed GEMM, or phasor forward), 1: adjoint core
+ * (the GEMM kernel alone: its split-K partials are not summed).
  * The kernel reads the plan's own workspace (its last operands), so call it
  * after at least one ufss_forward / ufss_adjoint.  Synchronises `stream`.
  *   ms_out HOST double */

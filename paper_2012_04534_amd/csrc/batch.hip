@@ -2,7 +2,8 @@
 // captured in one hipGraph, and a split-K autotuner with a JSON cache.
 //
 // Every phase of a FISTA iteration (forward GEMM, residual epilogue, adjoint
-// pre pass, adjoint GEMM, split sums, fused update, FP64 reductions, stats)
+// pre pass, adjoint GEMM, update fused with the adjoint's split sums, FP64
+// reductions, stats)
 // runs as ONE grouped launch that covers all scans of the batch: block b reads
 // blk[b] = {scan, local block} and the scan's descriptor, then executes the
 // same tile code as the single-scan kernels.  The momentum weights depend on
@@ -132,20 +133,6 @@ __global__ __launch_bounds__(128) void g_pre(const ScanDesc* __restrict__ d, con
     }
 }
 
-__global__ __launch_bounds__(kT) void g_sum_parts(const ScanDesc* __restrict__ d, const int2* __restrict__ blk) {
-    const int2 sb = blk[blockIdx.x];
-    const ScanDesc& a = d[sb.x];
-    for (int64_t i = (int64_t)sb.y * kT + threadIdx.x; i < a.nvox; i += (int64_t)a.nb_vox * kT) {
-        float re = 0.f, im = 0.f;
-        for (int s = 0; s < a.asplit; ++s) {
-            cf32 v = a.gpart[(int64_t)s * a.nvox + i];
-            re += v.re;
-            im += v.im;
-        }
-        a.g[i] = cf32{re, im};
-    }
-}
-
 __global__ __launch_bounds__(kT) void g_update(const ScanDesc* __restrict__ d, const int2* __restrict__ blk,
                                                float beta) {
     __shared__ double red[4][kT / 64];
@@ -153,7 +140,20 @@ __global__ __launch_bounds__(kT) void g_update(const ScanDesc* __restrict__ d, c
     const ScanDesc& a = d[sb.x];
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t i = (int64_t)sb.y * kT + threadIdx.x; i < a.nvox; i += (int64_t)a.nb_upd * kT) {
-        const cf32 gm = a.gamma[i], gg = a.g[i], aa = a.x[i];
+        const cf32 gm = a.gamma[i], aa = a.x[i];
+        cf32 gg;
+        if (a.asplit > 1) {
+            // the adjoint's split-K partials, summed in fixed order (its epilogue)
+            float re = 0.f, im = 0.f;
+            for (int q = 0; q < a.asplit; ++q) {
+                const cf32 v = a.gpart[(int64_t)q * a.nvox + i];
+                re += v.re;
+                im += v.im;
+            }
+            gg = cf32{re, im};
+        } else {
+            gg = a.g[i];
+        }
         const float zr = gm.re - a.step * gg.re, zi = gm.im - a.step * gg.im;
         const float mag = sqrtf(zr * zr + zi * zi);
         const float sc = mag > a.thresh ? 1.0f - a.thresh / mag : 0.0f;
@@ -210,8 +210,8 @@ struct Batch {
     std::map<int, int> gcount;                         // GemmKind -> total blocks
     std::map<int, int2*> gblk;                         // GemmKind -> block table
     int2 *blk_post = nullptr, *blk_pre = nullptr, *blk_vox = nullptr, *blk_upd = nullptr,
-         *blk_bf = nullptr, *blk_sum = nullptr;
-    int n_post = 0, n_pre = 0, n_vox = 0, n_upd = 0, n_bf = 0, n_sum = 0;
+         *blk_bf = nullptr;
+    int n_post = 0, n_pre = 0, n_vox = 0, n_upd = 0, n_bf = 0;
     std::vector<void*> owned;
 };
 
@@ -229,7 +229,6 @@ static void free_batch(Batch& B) {
     B.owned.clear();
 }
 
-void op_adjoint(Plan& P, const cf32* y, cf32* x, hipStream_t s);
 int launch_absmax(int64_t n, const cf32* x, double* part, hipStream_t s);
 void launch_reduce_max(const double* part, int nblk, double* out, hipStream_t s);
 void op_forward(Plan& P, const cf32* x, cf32* y, const cf32* ymeas, double* res2_out, hipStream_t s);
@@ -276,7 +275,7 @@ int fista_batched(int n, Plan* const* plans, const cf32* const* ys, cf32* const*
         }
         // descriptors
         std::vector<ScanDesc> sd(n);
-        std::vector<int2> bpost, bpre, bvox, bupd, bbf, bsum;
+        std::vector<int2> bpost, bpre, bvox, bupd, bbf;
         auto blocks_for = [](int64_t cnt) { return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (cnt + kT - 1) / kT)); };
         for (int i = 0; i < n; ++i) {
             Plan& P = *plans[i];
@@ -318,8 +317,6 @@ int fista_batched(int n, Plan* const* plans, const cf32* const* ys, cf32* const*
             for (int b = 0; b < a.nb_upd; ++b) bupd.push_back(int2{i, b});
             if (a.bf16)
                 for (int b = 0; b < a.nb_vox; ++b) bbf.push_back(int2{i, b});
-            if (a.asplit > 1)
-                for (int b = 0; b < a.nb_vox; ++b) bsum.push_back(int2{i, b});
         }
         B.d_desc = upload_vec(B, sd);
         B.blk_post = upload_vec(B, bpost);
@@ -330,8 +327,6 @@ int fista_batched(int n, Plan* const* plans, const cf32* const* ys, cf32* const*
         B.n_upd = (int)bupd.size();
         B.blk_bf = upload_vec(B, bbf);
         B.n_bf = (int)bbf.size();
-        B.blk_sum = upload_vec(B, bsum);
-        B.n_sum = (int)bsum.size();
         // grouped GEMM descriptors per kind
         for (int kind = 0; kind < 4; ++kind) {
             const GemmKind K = (GemmKind)kind;
@@ -399,7 +394,6 @@ int fista_batched(int n, Plan* const* plans, const cf32* const* ys, cf32* const*
                     if (B.gcount.count(kind))
                         launch_grouped((GemmKind)kind, B.gdesc[kind].first, B.gblk[kind], B.gcount[kind],
                                        B.gdesc[kind].second, cs);
-                if (B.n_sum) hipLaunchKernelGGL(g_sum_parts, dim3(B.n_sum), dim3(kT), 0, cs, D, B.blk_sum);
                 hipLaunchKernelGGL(g_update, dim3(B.n_upd), dim3(kT), 0, cs, D, B.blk_upd, beta);
                 hipLaunchKernelGGL(g_finish, dim3(n), dim3(kT), 0, cs, D, k);
             }

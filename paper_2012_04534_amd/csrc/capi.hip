@@ -34,8 +34,6 @@ void net_params(Net& N, float* get, const float* set, int64_t* count);
 void net_grads(Net& N, float* get);
 void net_save(Net& N, const char* path);
 void net_load(Net& N, const char* path);
-void launch_forward_gemm_bf16(const Plan& P, hipStream_t s);
-void launch_adjoint_gemm_bf16(const Plan& P, cf32* out, hipStream_t s);
 
 // y = A x (ymeas == NULL) or y = A x - ymeas.  If res2_out != NULL it receives
 // ||y||^2 (FP64, device scalar).
@@ -56,14 +54,17 @@ void op_forward(Plan& P, const cf32* x, cf32* y, const cf32* ymeas, double* res2
     if (res2_out) launch_reduce(P.d_part, nb, 1, res2_out, s);
 }
 
-void op_adjoint(Plan& P, const cf32* y, cf32* x, hipStream_t s) {
+int op_adjoint(Plan& P, const cf32* y, cf32* x, hipStream_t s, bool defer_sum) {
     launch_adjoint_pre(P, y, s);
-    if (P.algo == UFSS_ALGO_PHASOR)
+    if (P.algo == UFSS_ALGO_PHASOR) {
         launch_adjoint_phasor(P, x, s);
-    else if (P.dtype == UFSS_BF16)
-        launch_adjoint_gemm_bf16(P, x, s);
+        return 1;
+    }
+    if (P.dtype == UFSS_BF16)
+        launch_adjoint_gemm_bf16(P, x, s, !defer_sum);
     else
-        launch_adjoint_gemm(P, x, s);
+        launch_adjoint_gemm(P, x, s, !defer_sum);
+    return (defer_sum && P.adj_split > 1) ? P.adj_split : 1;
 }
 
 static void sync(hipStream_t s) { UFSS_HIP(hipStreamSynchronize(s)); }
@@ -170,10 +171,12 @@ int fista(Plan& P, const cf32* y, double lambda, double L, int iters, double tol
     int done = 0;
     for (int k = 0; k < iters; ++k) {
         op_forward(P, gamma, P.d_r, y, P.d_scalars + 0, s);
-        op_adjoint(P, P.d_r, P.d_g, s);
+        // the adjoint's split-K partials are summed inside the update (its epilogue)
+        const int ns = op_adjoint(P, P.d_r, P.d_g, s, true);
         const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * tk * tk));
         const double beta = accel ? (tk - 1.0) / tn : 0.0;
-        int nb = launch_update(P.nvox, gamma, P.d_g, x, step, thresh, (float)beta, aref, P.d_part, s);
+        int nb = launch_update(P.nvox, gamma, ns > 1 ? P.d_gpart : P.d_g, ns, x, step, thresh,
+                               (float)beta, aref, P.d_part, s);
         launch_reduce(P.d_part, nb, 5, P.d_scalars + 8, s);
         launch_fista_stats(P.d_stats, k, P.d_scalars + 8, P.d_scalars + 0, g1, lambda,
                            aref ? 1 : 0, ref2, s);
@@ -323,7 +326,7 @@ int ufss_shrink_update(int64_t n, void* gamma, const void* g, void* a, double st
     UFSS_HIP(hipMalloc(&out, 8 * sizeof(double)));
     try {
         int nb = ufss::launch_update(n, static_cast<ufss::cf32*>(gamma),
-                                     static_cast<const ufss::cf32*>(g), static_cast<ufss::cf32*>(a),
+                                     static_cast<const ufss::cf32*>(g), 1, static_cast<ufss::cf32*>(a),
                                      (float)step, (float)thresh, (float)beta,
                                      static_cast<const ufss::cf32*>(a_ref), part, s);
         ufss::launch_reduce(part, nb, 5, out, s);
@@ -479,10 +482,10 @@ int ufss_time_kernel(ufss_plan_t plan, int32_t which, int32_t reps, double* ms_o
             } else {
                 if (P->algo == UFSS_ALGO_PHASOR)
                     ufss::launch_adjoint_phasor(*P, P->d_g, s);
-                else if (P->dtype == UFSS_BF16)
-                    ufss::launch_adjoint_gemm_bf16(*P, P->d_g, s);
+                else if (P->dtype == UFSS_BF16)   // the GEMM alone, split partials not summed
+                    ufss::launch_adjoint_gemm_bf16(*P, P->d_g, s, false);
                 else
-                    ufss::launch_adjoint_gemm(*P, P->d_g, s);
+                    ufss::launch_adjoint_gemm(*P, P->d_g, s, false);
             }
         };
         launch();   // warm

@@ -664,7 +664,7 @@ void launch_forward_gemm_bf16(const Plan& P, hipStream_t s) {
     UFSS_HIP(hipGetLastError());
 }
 
-void launch_adjoint_gemm_bf16(const Plan& P, cf32* out, hipStream_t s) {
+void launch_adjoint_gemm_bf16(const Plan& P, cf32* out, hipStream_t s, bool sum) {
     AdjB a;
     size_t lds;
     const int nv = bf_np(P);
@@ -674,7 +674,7 @@ void launch_adjoint_gemm_bf16(const Plan& P, cf32* out, hipStream_t s) {
     else
         hipLaunchKernelGGL((adj_gemm_bf16_kernel<2, kBfNZ>), dim3(a.nblk), dim3(256), lds, s, a);
     UFSS_HIP(hipGetLastError());
-    if (a.split > 1) launch_sum_parts(P.d_gpart, a.split, P.nvox, out, s);
+    if (a.split > 1 && sum) launch_sum_parts(P.d_gpart, a.split, P.nvox, out, s);
 }
 
 // Phasor tables: entry (|d_y|, |d_x|, z, k) = cos / sin(2 pi kb[k] u(|d_y|, |d_x|, z))

@@ -480,13 +480,13 @@ void launch_forward_gemm(const Plan& P, const cf32* x, hipStream_t s) {
     UFSS_HIP(hipGetLastError());
 }
 
-void launch_adjoint_gemm(const Plan& P, cf32* out, hipStream_t s) {
+void launch_adjoint_gemm(const Plan& P, cf32* out, hipStream_t s, bool sum) {
     AdjArgs a;
     size_t lds;
     adj_args(P, out, a, lds);
     hipLaunchKernelGGL((adj_gemm_f32_kernel<kAdjNP, kAdjNZ>), dim3(a.nblk), dim3(256), lds, s, a);
     UFSS_HIP(hipGetLastError());
-    if (a.split > 1) launch_sum_parts(P.d_gpart, a.split, P.nvox, out, s);
+    if (a.split > 1 && sum) launch_sum_parts(P.d_gpart, a.split, P.nvox, out, s);
 }
 
 // Grouped launches (one grid for many plans).  Descriptors are opaque bytes.

@@ -100,7 +100,8 @@ struct Plan {
 
 // Kernel launchers (kernels_*.hip).  All asynchronous on `s`.
 void launch_forward_gemm(const Plan& P, const cf32* x, hipStream_t s);   // -> P.d_yraw
-void launch_adjoint_gemm(const Plan& P, cf32* out, hipStream_t s);       // P.d_rop -> out
+// P.d_rop -> out; with sum = false and a split > 1 the partials stay in P.d_gpart.
+void launch_adjoint_gemm(const Plan& P, cf32* out, hipStream_t s, bool sum = true);
 void launch_forward_phasor(const Plan& P, const cf32* x, cf32* y, const cf32* ymeas,
                            double* part, hipStream_t s);
 void launch_adjoint_phasor(const Plan& P, cf32* out, hipStream_t s);     // P.d_rop -> out
@@ -133,13 +134,14 @@ void bf16_set_tables(Plan& P, int enable);
 int bf16_fwd_split(const Plan& P);
 int bf16_adj_split(const Plan& P);
 void launch_forward_gemm_bf16(const Plan& P, hipStream_t s);
-void launch_adjoint_gemm_bf16(const Plan& P, cf32* out, hipStream_t s);
+void launch_adjoint_gemm_bf16(const Plan& P, cf32* out, hipStream_t s, bool sum = true);
 // out[i] = sum_{s < nsplit} part[s][i] in fixed order.
 void launch_sum_parts(const cf32* part, int nsplit, int64_t n, cf32* out, hipStream_t s);
 
 // Vector kernels.
-int launch_update(int64_t n, cf32* gamma, const cf32* g, cf32* a, float step, float thresh,
-                  float beta, const cf32* aref, double* part, hipStream_t s);
+// g: the gradient [n], or with nsplit > 1 the adjoint's split partials [nsplit][n].
+int launch_update(int64_t n, cf32* gamma, const cf32* g, int nsplit, cf32* a, float step,
+                  float thresh, float beta, const cf32* aref, double* part, hipStream_t s);
 // Sums nblk partial blocks of `width` doubles in fixed order into out[width].
 void launch_reduce(const double* part, int nblk, int width, double* out, hipStream_t s);
 int launch_absmax(int64_t n, const cf32* x, double* part, hipStream_t s);
@@ -156,6 +158,8 @@ int max_blocks_vec();
 // Operator drivers (operator.cpp).
 void op_forward(Plan& P, const cf32* x, cf32* y, const cf32* ymeas, double* res2_out,
                 hipStream_t s);
-void op_adjoint(Plan& P, const cf32* y, cf32* x, hipStream_t s);
+// Returns 1 when x holds A^H y; with defer_sum, the number of split partials
+// left in P.d_gpart instead (> 1) for a consumer that sums them itself.
+int op_adjoint(Plan& P, const cf32* y, cf32* x, hipStream_t s, bool defer_sum = false);
 
 }  // namespace ufss

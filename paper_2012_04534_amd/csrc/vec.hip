@@ -154,11 +154,13 @@ void launch_to_bf16(const cf32* x, void* out, int64_t n, hipStream_t s) {
 // Fused proximal-gradient update (FISTA / ISTA step), in place:
 //   z = gamma - step g;  a_new = z max(0, 1 - thresh/|z|);
 //   gamma <- a_new + beta (a_new - a);  a <- a_new.
+// With nsplit > 1, g is the adjoint GEMM's split-K partials [nsplit][n], summed
+// here in the same fixed order as sum_parts_kernel (the adjoint's epilogue).
 // Partials: ||a_new||_1, ||gamma_new||_1, ||a_new - a||^2, ||a_new||^2,
 // ||a_new - a_ref||^2.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void update_kernel(int64_t n, cf32* __restrict__ gamma,
-                                                          const cf32* __restrict__ g,
+                                                          const cf32* __restrict__ g, int nsplit,
                                                           cf32* __restrict__ a, float step,
                                                           float thresh, float beta,
                                                           const cf32* __restrict__ aref,
@@ -166,7 +168,17 @@ __global__ __launch_bounds__(kThreads) void update_kernel(int64_t n, cf32* __res
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kThreads) {
-        cf32 gm = gamma[i], gg = g[i], aa = a[i];
+        cf32 gm = gamma[i], aa = a[i];
+        cf32 gg = g[i];
+        if (nsplit > 1) {
+            float re = 0.f, im = 0.f;
+            for (int q = 0; q < nsplit; ++q) {
+                cf32 v = g[(int64_t)q * n + i];
+                re += v.re;
+                im += v.im;
+            }
+            gg = cf32{re, im};
+        }
         float zr = gm.re - step * gg.re, zi = gm.im - step * gg.im;
         float mag = sqrtf(zr * zr + zi * zi);
         float sc = mag > thresh ? 1.0f - thresh / mag : 0.0f;
@@ -188,10 +200,10 @@ __global__ __launch_bounds__(kThreads) void update_kernel(int64_t n, cf32* __res
     block_sum_write<5>(acc, part);
 }
 
-int launch_update(int64_t n, cf32* gamma, const cf32* g, cf32* a, float step, float thresh,
-                  float beta, const cf32* aref, double* part, hipStream_t s) {
+int launch_update(int64_t n, cf32* gamma, const cf32* g, int nsplit, cf32* a, float step,
+                  float thresh, float beta, const cf32* aref, double* part, hipStream_t s) {
     const int nb = blocks_for(n);
-    hipLaunchKernelGGL(update_kernel, dim3(nb), dim3(kThreads), 0, s, n, gamma, g, a, step,
+    hipLaunchKernelGGL(update_kernel, dim3(nb), dim3(kThreads), 0, s, n, gamma, g, nsplit, a, step,
                        thresh, beta, aref, part);
     UFSS_HIP(hipGetLastError());
     return nb;
