@@ -38,8 +38,8 @@ PEAK_HBM = 8e12
 # source it was measured on; a changed source or another tiling reports null.
 TRAFFIC = {
     # 32 x 32 C-scan, FP32 union-GEMM, autotuned tiling (profiles/cscan32_fp32_gemm_and_phasor.md)
-    "cscan32/gemm/adjoint/as12": {"bytes": 32.289e6, "sha": "f7ef8f7e1c556eea"},
-    "cscan32/gemm/forward/fs4-zs8-nw5": {"bytes": 20.580e6, "sha": "f7ef8f7e1c556eea"},
+    "cscan32/gemm/forward/fs4-zs8-nw5-np2": {"bytes": 20.581e6, "sha": "a33f4ddbf68a0273"},
+    "cscan32/gemm/adjoint/as12-np2": {"bytes": 32.305e6, "sha": "a33f4ddbf68a0273"},
 }
 TRAFFIC_SRC = {"gemm": "paper_2012_04534_amd/csrc/gemm_f32.hip",
                "phasor": "paper_2012_04534_amd/csrc/phasor.hip"}
@@ -53,8 +53,9 @@ def source_sha(rel):
 
 def tiling_key(info, direction):
     if direction == "adjoint":
-        return "as%d" % info["adj_split"]
-    return "fs%d-zs%d-nw%d" % (info["fwd_split"], info["fwd_zsplit"], info["fwd_waves"])
+        return "as%d-np%d" % (info["adj_split"], info["adj_tile"])
+    return "fs%d-zs%d-nw%d-np%d" % (info["fwd_split"], info["fwd_zsplit"], info["fwd_waves"],
+                                    info["fwd_tile"])
 
 
 def traffic_bytes(workload, algo_name, direction, info):
@@ -107,9 +108,20 @@ def cpu_baseline(w, bins, seconds=12.0):
     dt = time.perf_counter() - t0
     if limit is not None:
         limit.unregister()
+    host = {"affinity_cpus": len(os.sched_getaffinity(0))}
+    try:
+        with open("/proc/cpuinfo") as f:
+            host["cpu_model"] = next(ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    try:
+        cfg = np.show_config(mode="dicts")
+        host["blas"] = cfg["Build Dependencies"]["blas"]["name"]
+    except Exception:  # pragma: no cover
+        pass
     return {
         "value": round(8.0 * cmac / dt / 1e9, 4), "unit": "GFLOP/s", "cores": 1,
-        "kind": "oracle",
+        "kind": "oracle", "host": host,
         "sample": "%d rows of A x (one scan position each) and %d columns of A^H y (one voxel "
                   "column each) at the full 32x32 C-scan geometry, FP64 numpy direct sum, "
                   "1 BLAS thread, %.1f s" % (n_fwd, n_adj, dt),
@@ -169,11 +181,37 @@ def time_to_accuracy(ufss, W, plan, g, w, bins, y, lam, L, t_l, dev):
             k_eq = max(1, int(tn / fp32_s))
             st = ufss.ufss_fista(plan, yy, ufss.lambda_from_mu(w["mu"]), L, min(k_eq, K), x, a_ref=tgt)
             err_fista_same_time.append(float(st["err_ref"][-1]))
+        # the network's output as the start of plain FP32 FISTA (the hand-off the
+        # fallback rule uses), against FISTA from zero on the same scenes
+        warm, cold = [], []
+        for yy, tgt, _ in ev:
+            for dst, start_net in ((warm, True), (cold, False)):
+                x.zero_()
+                if start_net:
+                    ufss.ufss_unrolled_forward(net, yy, x)
+                st = ufss.ufss_fista(plan, yy, ufss.lambda_from_mu(w["mu"]), L, K, x, a_ref=tgt)
+                row = []
+                for lev in out["levels"]:
+                    hit = np.flatnonzero(st["err_ref"] <= lev)
+                    row.append(int(hit[0]) + 1 if hit.size else None)
+                dst.append(row)
+
+        def mean_iters(rows, j):
+            v = [rw[j] for rw in rows]
+            return None if any(q is None for q in v) else float(np.mean(v))
+
+        t_net = float(r["time_s"].mean())
+        lv = len(out["levels"])
+        warm_it = [mean_iters(warm, j) for j in range(lv)]
         out["learned"] = {"checkpoint": os.path.relpath(WEIGHTS, ROOT), "eval_scenes": len(ev),
                           "err_mean": float(r["err"].mean()), "err_max": float(r["err"].max()),
                           "fallbacks": int(r["fallback"].sum()),
-                          "time_s_mean": float(r["time_s"].mean()),
-                          "fp32_fista_err_at_same_time": float(np.mean(err_fista_same_time))}
+                          "time_s_mean": t_net,
+                          "fp32_fista_err_at_same_time": float(np.mean(err_fista_same_time)),
+                          "then_fista_iters_to_level": warm_it,
+                          "then_fista_time_to_level_s": [None if k is None else round(t_net + k * fp32_s, 5)
+                                                         for k in warm_it],
+                          "fista_from_zero_iters_to_level": [mean_iters(cold, j) for j in range(lv)]}
         net.close()
     return out
 
@@ -212,7 +250,7 @@ def batch_rate(ufss, W, dev, iters=5):
         m = min(s["m"], band)
         bins, _ = ufss.ufss_select_freqs(g, m, s["per_position"], s["seed"])
         p = ufss.Plan(g, m, s["per_position"], bins, algo=ufss.ALGO_GEMM)
-        ufss.ufss_autotune(p, None, use_cache=False, write_cache=False)
+        ufss.ufss_autotune(p, None, use_cache=False, write_cache=False, quick=True)
         xt = torch.from_numpy(W.scene(g, s["n_scat"], amp=s["amp"], seed=s["seed"]).astype(np.complex64)).to(dev)
         y = torch.empty((g["ny"], g["nx"], m), dtype=torch.complex64, device=dev)
         ufss.ufss_forward(p, xt, y)
@@ -302,7 +340,12 @@ def main():
             best = (algo, tf + ta, name)
         plan.close()
     algo, _, algo_name = best
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter()
     plan = ufss.Plan(g, m, per_pos, bins, algo=algo)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t_plan
+    extras["plan_build_s"] = round(t_plan, 4)
     if algo == ufss.ALGO_GEMM:
         ufss.ufss_autotune(plan, args.tune_cache, args.tune_cache is not None, args.tune_cache is not None)
         extras["autotuned"] = tuned

@@ -82,6 +82,8 @@ typedef struct ufss_plan_info {
     int32_t fwd_split, adj_split;         /* split-K factors of the GEMM path   */
     int32_t fwd_waves, fwd_zsplit;       /* FP32 forward: waves per workgroup,
                                             depth split (1 elsewhere)          */
+    int32_t fwd_tile, adj_tile;          /* FP32 GEMMs: 16-position sub-tiles
+                                            per wave (0 elsewhere)             */
     int32_t phasor_tables;               /* 1: BF16 phasor tables in use       */
 } ufss_plan_info;
 
@@ -220,12 +222,15 @@ int ufss_fista_batched(int32_t n, const ufss_plan_t* plans, const void* const* y
                        void* const* xs, const double* lambdas, const double* Ls,
                        int32_t iters, double* res_out, ufss_stream_t stream);
 
-/* Autotuner for the GEMM path: times every candidate split-K factor of the
- * forward and adjoint GEMMs of this plan's shape with HIP events, keeps the
- * fastest pair in the plan and, with flags bit 1, appends it to the JSON cache
- * file `cache_path` (keyed by the shape class); with flags bit 0 a cached entry
- * is used without timing.  Overwrites the plan's internal workspace; no effect
- * for phasor plans.  Synchronises `stream`.
+/* Autotuner for the GEMM path: times every candidate tiling (d_y and depth
+ * splits, waves per workgroup, sub-tiles per wave; see ufss_plan_set_tiling) of
+ * the forward and adjoint GEMMs of this plan's shape with HIP events, keeps the
+ * fastest in the plan and, with flags bit 1, appends it to the JSON cache file
+ * `cache_path` (keyed by the shape class); with flags bit 0 a cached entry is
+ * used without timing; flags bit 2 restricts the search to d_y splits and two
+ * depth splits at the default tile shape (about 9x fewer trials).  Overwrites
+ * the plan's internal workspace; no effect for phasor plans.  Synchronises
+ * `stream`.
  *   fwd_split_out, adj_split_out  HOST, optional */
 int ufss_autotune(ufss_plan_t plan, const char* cache_path, int32_t flags,
                   int32_t* fwd_split_out, int32_t* adj_split_out, ufss_stream_t stream);
@@ -235,13 +240,16 @@ int ufss_autotune(ufss_plan_t plan, const char* cache_path, int32_t flags,
  *   adj_split   parts of the adjoint GEMM's d_y range, 1..64
  *   fwd_waves   16-bin sub-tiles (waves) per forward FP32 workgroup, 1..8
  *   fwd_zsplit  parts of the forward FP32 GEMM's depth range, 1..64
+ *   fwd_tile, adj_tile  FP32 GEMMs: 16-position sub-tiles per wave, 2 or 4
  * A value of 0 keeps the plan's current one.  Any valid setting computes the
  * same operator; parts that receive no rows contribute zeros.  BF16 plans
- * accept only 0 or 1 for fwd_zsplit and ignore fwd_waves.  Reallocates the
- * plan's split workspace (synchronises the device).  Errors: INVALID_ARG for
- * values out of range, UNSUPPORTED for phasor plans. */
+ * accept only 0 or 1 for fwd_zsplit and ignore fwd_waves, fwd_tile and
+ * adj_tile.  Reallocates the plan's split workspace (synchronises the
+ * device).  Errors: INVALID_ARG for values out of range, UNSUPPORTED for
+ * phasor plans. */
 int ufss_plan_set_tiling(ufss_plan_t plan, int32_t fwd_split, int32_t adj_split,
-                         int32_t fwd_waves, int32_t fwd_zsplit);
+                         int32_t fwd_waves, int32_t fwd_zsplit, int32_t fwd_tile,
+                         int32_t adj_tile);
 
 /* BF16 GEMM plans: the BF16 phasors exp(-j 2 pi k tau f_s / N_t) of every
  * (|d_y|, |d_x|, z, selected bin) (paper Sec. IV-B: the operator depends on the

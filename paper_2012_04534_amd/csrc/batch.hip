@@ -505,8 +505,10 @@ int autotune(Plan& P, const char* cache_path, int flags, hipStream_t s, int32_t*
     const std::string key = shape_key(P);
     std::map<std::string, std::vector<double>> cache;
     if (cache_path && (flags & 1)) cache = read_cache(cache_path);
-    if (cache.count(key) && cache[key].size() >= 6) {
+    if (cache.count(key) && cache[key].size() >= 8) {
         P.fwd_nw = (int)cache[key][4];
+        P.fwd_np = (int)cache[key][6];
+        P.adj_np = (int)cache[key][7];
         plan_set_splits(P, (int)cache[key][0], (int)cache[key][1], (int)cache[key][5]);
     } else {
         const int tpy = P.g.ny == 1 ? 1 : 4;
@@ -519,29 +521,44 @@ int autotune(Plan& P, const char* cache_path, int flags, hipStream_t s, int32_t*
         UFSS_HIP(hipMemsetAsync(P.d_r, 0, (size_t)P.npos * P.m * sizeof(cf32), s));
         double best_f = 1e30, best_a = 1e30;
         int bf = P.fwd_split, ba = P.adj_split, bnw = P.fwd_nw, bz = P.fwd_zsplit;
+        int bnp = P.fwd_np, bnpa = P.adj_np;
+        // FP32: 2 or 4 position sub-tiles per wave; BF16 picks its own tile width
+        // flags bit 2: quick search (d_y splits and two depth splits at the default tile shape)
+        const bool quick = (flags & 4) != 0;
+        const std::vector<int> npc =
+            (P.dtype == UFSS_F32 && !quick) ? std::vector<int>{2, 4} : std::vector<int>{2};
         std::vector<int> zcand{1};
         if (P.dtype == UFSS_F32)
             for (int z : {2, 4, 8})
                 if (P.g.nz >= 32 * z) zcand.push_back(z);
-        for (int nw : nw_candidates(P))
-            for (int zs : zcand)
-                for (int c : cand) {
-                    if (c * zs > 96) continue;          // bounds the partial-sum workspace
-                    P.fwd_nw = nw;
-                    plan_set_splits(P, c, P.adj_split, zs);
-                    double t = time_ms([&]() { op_forward(P, P.d_gamma, P.d_r, nullptr, nullptr, s); }, 3, s);
-                    if (t < best_f) { best_f = t; bf = c; bnw = nw; bz = zs; }
-                }
+        if (quick && zcand.size() > 2) zcand = {1, zcand[2]};
+        const std::vector<int> nwc = quick ? std::vector<int>{P.fwd_nw} : nw_candidates(P);
+        for (int np : npc)
+            for (int nw : nwc)
+                for (int zs : zcand)
+                    for (int c : cand) {
+                        if (c * zs > 96) continue;          // bounds the partial-sum workspace
+                        P.fwd_nw = nw;
+                        P.fwd_np = np;
+                        plan_set_splits(P, c, P.adj_split, zs);
+                        double t = time_ms([&]() { op_forward(P, P.d_gamma, P.d_r, nullptr, nullptr, s); }, 3, s);
+                        if (t < best_f) { best_f = t; bf = c; bnw = nw; bz = zs; bnp = np; }
+                    }
         P.fwd_nw = bnw;
-        for (int c : cand) {
-            plan_set_splits(P, bf, c, bz);
-            double t = time_ms([&]() { op_adjoint(P, P.d_r, P.d_g, s); }, 3, s);
-            if (t < best_a) { best_a = t; ba = c; }
-        }
+        P.fwd_np = bnp;
+        for (int np : npc)
+            for (int c : cand) {
+                P.adj_np = np;
+                plan_set_splits(P, bf, c, bz);
+                double t = time_ms([&]() { op_adjoint(P, P.d_r, P.d_g, s); }, 3, s);
+                if (t < best_a) { best_a = t; ba = c; bnpa = np; }
+            }
+        P.adj_np = bnpa;
         plan_set_splits(P, bf, ba, bz);
         if (cache_path && (flags & 2)) {
             cache = read_cache(cache_path);
-            cache[key] = {(double)bf, (double)ba, best_f, best_a, (double)bnw, (double)bz};
+            cache[key] = {(double)bf, (double)ba, best_f, best_a, (double)bnw, (double)bz, (double)bnp,
+                          (double)bnpa};
             write_cache(cache_path, cache);
         }
     }

@@ -52,13 +52,13 @@ __device__ __forceinline__ bf8 neg_bf8(bf8 v) {
 }
 
 // Stages rows x ncol cells of ZCB complex BF16 values into planar LDS cells
-// (ZCB real parts, then ZCB imaginary parts):
+// (ZCB real parts, then ZCB imaginary parts; row pitch `pitch` cells):
 //   cell (r, c) <- src[((ybase + r) * nx + xbase + c) * ld + i0 + e], e < ZCB,
 // zero for rows outside the grid or past `ilim` along the inner axis (columns
 // are inside the grid by construction).  Each thread keeps one e and walks the
 // cells with a fixed step, with UNR loads in flight before the LDS stores.
 template <int UNR>
-__device__ __forceinline__ void stage_planar(__bf16* __restrict__ halo, int rows, int ncol,
+__device__ __forceinline__ void stage_planar(__bf16* __restrict__ halo, int rows, int ncol, int pitch,
                                              const cbf16* __restrict__ src, int ny, int nx, int64_t ld,
                                              int ybase, int xbase, int i0, int ilim) {
     const int e = threadIdx.x & (ZCB - 1);
@@ -69,10 +69,12 @@ __device__ __forceinline__ void stage_planar(__bf16* __restrict__ halo, int rows
     const bool eok = i0 + e < ilim;
     for (; cell < total; cell += UNR * step) {
         cbf16 v[UNR];
+        int dst[UNR];
         int rr = r, cc = c;
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
             v[u] = to_cbf16(0.f, 0.f);
+            dst[u] = rr * pitch + cc;
             const int gy = ybase + rr;
             if (cell + u * step < total && eok && gy >= 0 && gy < ny)
                 v[u] = src[((int64_t)gy * nx + xbase + cc) * ld + i0 + e];
@@ -82,8 +84,8 @@ __device__ __forceinline__ void stage_planar(__bf16* __restrict__ halo, int rows
 #pragma unroll
         for (int u = 0; u < UNR; ++u)
             if (cell + u * step < total) {
-                halo[(size_t)(cell + u * step) * CELL + e] = v[u].re;
-                halo[(size_t)(cell + u * step) * CELL + ZCB + e] = v[u].im;
+                halo[(size_t)dst[u] * CELL + e] = v[u].re;
+                halo[(size_t)dst[u] * CELL + ZCB + e] = v[u].im;
             }
         r = rr;
         c = cc;
@@ -183,8 +185,9 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
     const int cx_lo = max(0, px0 - a.wx), cx_hi = min(a.nx - 1, px0 + tpx - 1 + a.wx);
     const int ncol = cx_hi - cx_lo + 1;
 
-    __bf16* halo = reinterpret_cast<__bf16*>(smem);                    // [tpy*ncol + 1][CELL]
-    const int zero_cell = tpy * ncol;
+    const int pitch = ncol;
+    __bf16* halo = reinterpret_cast<__bf16*>(smem);                    // [tpy*pitch + 1][CELL]
+    const int zero_cell = tpy * pitch;
     __bf16* ptile = halo + (size_t)(zero_cell + 1) * CELL;               // [2][2][NB*16][PROW]
     uint32_t* ulds = reinterpret_cast<uint32_t*>(ptile + 2 * 2 * NB * 16 * PROW);   // [wx+1][ZCB]
     int* klds = reinterpret_cast<int*>(ulds + (a.wx + 1) * ZCB);         // [NB*16]
@@ -216,7 +219,7 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
         for (int dy = dy_lo; dy <= dy_hi; ++dy) {
             __syncthreads();
             // stage x rows (planar bf16) and the delay slab of |dy|
-            stage_planar<8>(halo, tpy, ncol, a.x, a.ny, a.nx, a.nz, py0 - dy, cx_lo, z0, a.nz);
+            stage_planar<8>(halo, tpy, ncol, pitch, a.x, a.ny, a.nx, a.nz, py0 - dy, cx_lo, z0, a.nz);
             const int ady = dy < 0 ? -dy : dy;
             if (!a.tab)
                 for (int t = threadIdx.x; t < (a.wx + 1) * ZCB; t += 256) {
@@ -270,7 +273,7 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
                     const int q = wave * NP + s;
                     const int px = px0 + q * sw + i % sw, iy = i / sw;
                     const int gx = px - dx;
-                    const int cell = (gx >= cx_lo && gx <= cx_hi) ? iy * ncol + (gx - cx_lo) : zero_cell;
+                    const int cell = (gx >= cx_lo && gx <= cx_hi) ? iy * pitch + (gx - cx_lo) : zero_cell;
                     xr[s] = lds_bf8(halo + (size_t)cell * CELL + 8 * kq);
                     xi[s] = lds_bf8(halo + (size_t)cell * CELL + ZCB + 8 * kq);
                 }
@@ -369,8 +372,9 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
     const int cx_lo = max(0, vx0 - a.wx), cx_hi = min(a.nx - 1, vx0 + tvx - 1 + a.wx);
     const int ncol = cx_hi - cx_lo + 1;
 
-    __bf16* halo = reinterpret_cast<__bf16*>(smem);                  // [tvy*ncol + 1][CELL]
-    const int zero_cell = tvy * ncol;
+    const int pitch = ncol;
+    __bf16* halo = reinterpret_cast<__bf16*>(smem);                  // [tvy*pitch + 1][CELL]
+    const int zero_cell = tvy * pitch;
     __bf16* ptile = halo + (size_t)(zero_cell + 1) * CELL;             // [2][2][zspan][PROW]
     uint32_t* ulds = reinterpret_cast<uint32_t*>(ptile + 2 * 2 * zspan * PROW);   // [wx+1][zspan]
     int* klds = reinterpret_cast<int*>(ulds + (a.wx + 1) * zspan);     // [ZCB]
@@ -395,7 +399,7 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
     for (int k0 = 0; k0 < a.mu; k0 += ZCB) {
         for (int dy = dy_lo; dy <= dy_hi; ++dy) {
             __syncthreads();
-            stage_planar<8>(halo, tvy, ncol, a.r, a.ny, a.nx, a.mu, vy0 + dy, cx_lo, k0, a.mu);
+            stage_planar<8>(halo, tvy, ncol, pitch, a.r, a.ny, a.nx, a.mu, vy0 + dy, cx_lo, k0, a.mu);
             const int ady = dy < 0 ? -dy : dy;
             if (!a.tab)
                 for (int t = threadIdx.x; t < (a.wx + 1) * zspan; t += 256) {
@@ -470,7 +474,7 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
                     const int q = wave * NV + s;
                     const int vx = vx0 + q * sw + i % sw, iy = i / sw;
                     const int gx = vx + dx;
-                    const int cell = (gx >= cx_lo && gx <= cx_hi) ? iy * ncol + (gx - cx_lo) : zero_cell;
+                    const int cell = (gx >= cx_lo && gx <= cx_hi) ? iy * pitch + (gx - cx_lo) : zero_cell;
                     rr8[s] = lds_bf8(halo + (size_t)cell * CELL + 8 * kq);
                     ri8[s] = lds_bf8(halo + (size_t)cell * CELL + ZCB + 8 * kq);
                 }

@@ -43,13 +43,14 @@ __device__ __forceinline__ void phasor(uint32_t ku, float& c, float& s) {
 }
 
 // Stages rows x hc cells of `chunk` consecutive complex values into LDS
-// (cell stride cs), zero outside the grid or past `ilim` along the inner axis:
-//   halo[(r * hc + c) * cs + e] = src[((ybase + r) * nx + xbase + c) * ld + i0 + e].
+// (cell stride cs, row pitch `pitch` cells), zero outside the grid or past
+// `ilim` along the inner axis:
+//   halo[(r * pitch + c) * cs + e] = src[((ybase + r) * nx + xbase + c) * ld + i0 + e].
 // `chunk` is a power of two dividing blockDim.x, so each thread keeps one inner
 // index and walks the cells with a fixed step; UNR independent loads are in
 // flight per thread before their LDS stores.
 template <int UNR>
-__device__ __forceinline__ void stage_halo(cf32* __restrict__ halo, int cs, int rows, int hc, int chunk,
+__device__ __forceinline__ void stage_halo(cf32* __restrict__ halo, int cs, int rows, int hc, int pitch, int chunk,
                                            const cf32* __restrict__ src, int ny, int nx, int64_t ld,
                                            int ybase, int xbase, int i0, int ilim) {
     const int e = threadIdx.x & (chunk - 1);
@@ -60,10 +61,12 @@ __device__ __forceinline__ void stage_halo(cf32* __restrict__ halo, int cs, int 
     const bool eok = i0 + e < ilim;
     for (; cell < total; cell += UNR * step) {
         cf32 v[UNR];
+        int dst[UNR];
         int rr = r, cc = c;
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
             v[u] = cf32{0.f, 0.f};
+            dst[u] = (rr * pitch + cc) * cs + e;
             const int gy = ybase + rr, gx = xbase + cc;
             if (cell + u * step < total && eok && gy >= 0 && gy < ny && gx >= 0 && gx < nx)
                 v[u] = src[((int64_t)gy * nx + gx) * ld + i0 + e];
@@ -72,7 +75,7 @@ __device__ __forceinline__ void stage_halo(cf32* __restrict__ halo, int cs, int 
         }
 #pragma unroll
         for (int u = 0; u < UNR; ++u)
-            if (cell + u * step < total) halo[(cell + u * step) * cs + e] = v[u];
+            if (cell + u * step < total) halo[dst[u]] = v[u];
         r = rr;
         c = cc;
     }
@@ -95,13 +98,15 @@ struct FwdArgs {
     int nblk;              // blocks of this plan's grid
 };
 
-template <int NP>
+// ZC: the depth chunk a.zc as a compile-time constant (16, 8 or 4).
+template <int NP, int ZC>
 __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int nblk, unsigned char* smem) {
+    constexpr int zc = ZC;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int sw = a.sw, sh = 16 / sw;
     const int tpx = sw * NP, tpy = sh;
     const int hc = tpx + 2 * a.wx;            // halo columns
-    const int cs = a.zc + 1;                  // padded cell stride (complex)
+    const int cs = zc + 1;                  // padded cell stride (complex)
     cf32* halo = reinterpret_cast<cf32*>(smem);
     uint32_t* ulds = reinterpret_cast<uint32_t*>(halo + (size_t)tpy * hc * cs);
 
@@ -115,7 +120,7 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
     const int sp_all = b / (ntile * a.nbt);          // partial index: (d_y part, depth part)
     const int sp = sp_all % a.split, spz = sp_all / a.split;
     const int px0 = (tile % a.ntx) * tpx, py0 = (tile / a.ntx) * tpy;
-    const int zper = ((a.nz + a.zc * a.zsplit - 1) / (a.zc * a.zsplit)) * a.zc;
+    const int zper = ((a.nz + zc * a.zsplit - 1) / (zc * a.zsplit)) * zc;
     const int z_lo = spz * zper, z_hi = min(a.nz, z_lo + zper);
 
     // d_y range of this split (rows that hit the grid for some tile row)
@@ -138,14 +143,14 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
 #pragma unroll
     for (int s = 0; s < NP; ++s) out_re[s] = out_im[s] = f4{0.f, 0.f, 0.f, 0.f};
 
-    for (int z0 = z_lo; z0 < z_hi; z0 += a.zc) {
+    for (int z0 = z_lo; z0 < z_hi; z0 += zc) {
         for (int dy = dy_lo; dy <= dy_hi; ++dy) {
             __syncthreads();
             // stage x rows (py0 + r - dy), columns (px0 - wx + c), depths z0..z0+zc
-            stage_halo<8>(halo, cs, tpy, hc, a.zc, a.x, a.ny, a.nx, a.nz, py0 - dy, px0 - a.wx, z0, a.nz);
+            stage_halo<8>(halo, cs, tpy, hc, hc, zc, a.x, a.ny, a.nx, a.nz, py0 - dy, px0 - a.wx, z0, a.nz);
             const int ady = dy < 0 ? -dy : dy;
-            for (int t = threadIdx.x; t < (a.wx + 1) * a.zc; t += blockDim.x) {
-                int adx = t / a.zc, zz = t - adx * a.zc;
+            for (int t = threadIdx.x; t < (a.wx + 1) * zc; t += blockDim.x) {
+                int adx = t / zc, zz = t - adx * zc;
                 int z = z0 + zz;
                 ulds[t] = z < a.nz ? a.u[((int64_t)ady * (a.wx + 1) + adx) * a.nz + z] : 0u;
             }
@@ -159,7 +164,7 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
             for (int s = 0; s < NP; ++s) m1[s] = m2[s] = m3[s] = f4{0.f, 0.f, 0.f, 0.f};
             for (int dx = dx_lo; dx <= dx_hi; ++dx) {
                 const int adx = dx < 0 ? -dx : dx;
-                const uint32_t* urow = ulds + adx * a.zc;
+                const uint32_t* urow = ulds + adx * zc;
                 const cf32* hrow = halo + (iy * hc + ix + a.wx - dx) * cs;
                 // sub-tiles whose shifted columns all fall outside the grid add
                 // exact zeros: skip their MFMAs (wave-uniform test)
@@ -169,17 +174,24 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
                     const int c0 = px0 + s * sw - dx;
                     act[s] = c0 + sw - 1 >= 0 && c0 <= a.nx - 1;
                 }
-                for (int zz = 0; zz < a.zc; zz += 4) {
-                    float c, sn;
-                    phasor(kbin * urow[zz + kq], c, sn);
-                    const float bm = -sn - c, bp = c - sn;
+                float cz[zc / 4], bmz[zc / 4], bpz[zc / 4];
 #pragma unroll
-                    for (int s = 0; s < NP; ++s) {
-                        if (!act[s]) continue;
-                        cf32 xv = hrow[s * sw * cs + zz + kq];
-                        m1[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.re + xv.im, c, m1[s], 0, 0, 0);
-                        m2[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.re, bm, m2[s], 0, 0, 0);
-                        m3[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.im, bp, m3[s], 0, 0, 0);
+                for (int j = 0; j < zc / 4; ++j) {
+                    float c, sn;
+                    phasor(kbin * urow[4 * j + kq], c, sn);
+                    cz[j] = c;
+                    bmz[j] = -sn - c;
+                    bpz[j] = c - sn;
+                }
+#pragma unroll
+                for (int s = 0; s < NP; ++s) {
+                    if (!act[s]) continue;
+#pragma unroll
+                    for (int j = 0; j < zc / 4; ++j) {
+                        cf32 xv = hrow[s * sw * cs + 4 * j + kq];
+                        m1[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.re + xv.im, cz[j], m1[s], 0, 0, 0);
+                        m2[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.re, bmz[j], m2[s], 0, 0, 0);
+                        m3[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.im, bpz[j], m3[s], 0, 0, 0);
                     }
                 }
             }
@@ -204,10 +216,10 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
     }
 }
 
-template <int NP>
+template <int NP, int ZC>
 __global__ __launch_bounds__(512) void fwd_gemm_f32_kernel(FwdArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    fwd_f32_body<NP>(a, blockIdx.x, gridDim.x, smem);
+    fwd_f32_body<NP, ZC>(a, blockIdx.x, gridDim.x, smem);
 }
 
 // Grouped launch: block -> (plan index, block index inside that plan's grid).
@@ -217,7 +229,10 @@ __global__ __launch_bounds__(512) void fwd_gemm_f32_kernel_grouped(const FwdArgs
     extern __shared__ __align__(16) unsigned char smem[];
     const int2 sb = blk[blockIdx.x];
     const FwdArgs a = descs[sb.x];
-    fwd_f32_body<NP>(a, sb.y, a.nblk, smem);
+    // scans of one batch may differ in depth chunk
+    if (a.zc == 16) fwd_f32_body<NP, 16>(a, sb.y, a.nblk, smem);
+    else if (a.zc == 8) fwd_f32_body<NP, 8>(a, sb.y, a.nblk, smem);
+    else fwd_f32_body<NP, 4>(a, sb.y, a.nblk, smem);
 }
 
 struct AdjArgs {
@@ -234,13 +249,15 @@ struct AdjArgs {
     int nblk;              // blocks of this plan's grid
 };
 
-template <int NP, int NZ>
+// KC: the bin chunk a.kc as a compile-time constant (16, 8 or 4).
+template <int NP, int NZ, int KC>
 __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int nblk, unsigned char* smem) {
+    constexpr int kc = KC;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int sw = a.sw, sh = 16 / sw;
     const int tpx = sw * NP, tpy = sh;
     const int hc = tpx + 2 * a.wx;
-    const int cs = a.kc + 1;
+    const int cs = kc + 1;
     const int zspan = 64 * NZ;                       // depths per workgroup
     cf32* halo = reinterpret_cast<cf32*>(smem);
     uint32_t* ulds = reinterpret_cast<uint32_t*>(halo + (size_t)tpy * hc * cs);
@@ -273,18 +290,18 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
 #pragma unroll
         for (int q = 0; q < NZ; ++q) out_re[s][q] = out_im[s][q] = f4{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = 0; k0 < a.mu; k0 += a.kc) {
-        const int kcur = min(a.kc, (a.mu - k0 + 3) & ~3);   // last chunk: valid bins, rounded to 4
+    for (int k0 = 0; k0 < a.mu; k0 += kc) {
+        const int kcur = min(kc, (a.mu - k0 + 3) & ~3);   // last chunk: valid bins, rounded to 4
         for (int dy = dy_lo; dy <= dy_hi; ++dy) {
             __syncthreads();
-            stage_halo<8>(halo, cs, tpy, hc, a.kc, a.r, a.ny, a.nx, a.mu, vy0 + dy, vx0 - a.wx, k0, a.mu);
+            stage_halo<8>(halo, cs, tpy, hc, hc, kc, a.r, a.ny, a.nx, a.mu, vy0 + dy, vx0 - a.wx, k0, a.mu);
             const int ady = dy < 0 ? -dy : dy;
             for (int t = threadIdx.x; t < (a.wx + 1) * zspan; t += 256) {
                 int adx = t / zspan, zz = t - adx * zspan;
                 int z = zw0 + zz;
                 ulds[t] = z < a.nz ? a.u[((int64_t)ady * (a.wx + 1) + adx) * a.nz + z] : 0u;
             }
-            for (int t = threadIdx.x; t < a.kc; t += 256)
+            for (int t = threadIdx.x; t < kc; t += 256)
                 klds[t] = (k0 + t < a.mu) ? a.kb[k0 + t] : 0;
             __syncthreads();
             if (!wave_active) continue;
@@ -302,7 +319,9 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
 #pragma unroll
                 for (int q = 0; q < NZ; ++q) uz[q] = ulds[adx * zspan + wave * NZ * 16 + q * 16 + i];
                 const cf32* hrow = halo + (iy * hc + ix + a.wx + dx) * cs;
-                for (int kk = 0; kk < kcur; kk += 4) {
+#pragma unroll
+                for (int kk = 0; kk < kc; kk += 4) {
+                    if (kk >= kcur) break;
                     const uint32_t k = (uint32_t)klds[kk + kq];
                     cf32 rv[NP];
                     float rs[NP];
@@ -350,10 +369,10 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
             }
 }
 
-template <int NP, int NZ>
+template <int NP, int NZ, int KC>
 __global__ __launch_bounds__(256) void adj_gemm_f32_kernel(AdjArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    adj_f32_body<NP, NZ>(a, blockIdx.x, gridDim.x, smem);
+    adj_f32_body<NP, NZ, KC>(a, blockIdx.x, gridDim.x, smem);
 }
 
 // Grouped launch: block -> (plan index, block index inside that plan's grid).
@@ -363,21 +382,25 @@ __global__ __launch_bounds__(256) void adj_gemm_f32_kernel_grouped(const AdjArgs
     extern __shared__ __align__(16) unsigned char smem[];
     const int2 sb = blk[blockIdx.x];
     const AdjArgs a = descs[sb.x];
-    adj_f32_body<NP, NZ>(a, sb.y, a.nblk, smem);
+    if (a.kc == 16) adj_f32_body<NP, NZ, 16>(a, sb.y, a.nblk, smem);
+    else if (a.kc == 8) adj_f32_body<NP, NZ, 8>(a, sb.y, a.nblk, smem);
+    else adj_f32_body<NP, NZ, 4>(a, sb.y, a.nblk, smem);
 }
 
 // ---------------------------------------------------------------------------
 // Host launchers.
 // ---------------------------------------------------------------------------
-static constexpr int kFwdNP = 2;
-static constexpr int kAdjNP = 2;
+static constexpr int kGroupNP = 2;   // grouped (batched) launches: one shape for every scan
+
+int fwd_tile_np(const Plan& P) { return P.fwd_np == 4 ? 4 : 2; }
+int adj_tile_np(const Plan& P) { return P.adj_np == 4 ? 4 : 2; }
 static constexpr int kAdjNZ = 1;
 static constexpr size_t kLdsMax = 64 * 1024;
 
 static int sub_width(const Plan& P) { return P.g.ny == 1 ? 16 : 4; }
 
 int gemm_split(const Plan& P) {
-    const int sw = sub_width(P), tpx = sw * kFwdNP, tpy = 16 / sw;
+    const int sw = sub_width(P), tpx = sw * fwd_tile_np(P), tpy = 16 / sw;
     const int ntx = (P.g.nx + tpx - 1) / tpx, nty = (P.g.ny + tpy - 1) / tpy;
     const int mu = (int)P.ubins_h.size();
     const int nbt = (mu + 63) / 64;
@@ -393,7 +416,7 @@ int gemm_split(const Plan& P) {
 
 // Split of the adjoint's d_y range: enough workgroups to fill 256 CUs twice.
 int adj_split(const Plan& P) {
-    const int sw = sub_width(P), tpx = sw * kAdjNP, tpy = 16 / sw;
+    const int sw = sub_width(P), tpx = sw * adj_tile_np(P), tpy = 16 / sw;
     const int ntx = (P.g.nx + tpx - 1) / tpx, nty = (P.g.ny + tpy - 1) / tpy;
     const int nzt = (P.g.nz + 64 * kAdjNZ - 1) / (64 * kAdjNZ);
     const int wgs = ntx * nty * nzt;
@@ -405,7 +428,7 @@ int adj_split(const Plan& P) {
 }
 
 // Descriptor of one plan's forward GEMM launch; returns the block count.
-static int fwd_args(const Plan& P, const cf32* x, FwdArgs& a, size_t& lds) {
+static int fwd_args(const Plan& P, const cf32* x, FwdArgs& a, size_t& lds, int np) {
     a = FwdArgs{};
     a.x = x;
     a.yraw = P.d_yraw;
@@ -418,7 +441,7 @@ static int fwd_args(const Plan& P, const cf32* x, FwdArgs& a, size_t& lds) {
     a.wy = P.d.wy;
     a.mu = (int)P.ubins_h.size();
     a.sw = sub_width(P);
-    const int tpx = a.sw * kFwdNP, tpy = 16 / a.sw;
+    const int tpx = a.sw * np, tpy = 16 / a.sw;
     a.ntx = (a.nx + tpx - 1) / tpx;
     a.nty = (a.ny + tpy - 1) / tpy;
     a.nw = std::max(1, std::min(P.fwd_nw, (a.mu + 15) / 16));
@@ -427,9 +450,11 @@ static int fwd_args(const Plan& P, const cf32* x, FwdArgs& a, size_t& lds) {
     a.npos = P.npos;
     const int hc = tpx + 2 * a.wx;
     int zc = 16;
-    while (zc > 4 && (size_t)tpy * hc * (zc + 1) * sizeof(cf32) + (size_t)(a.wx + 1) * zc * 4 > kLdsMax)
-        zc /= 2;                                  // powers of two: the staging needs zc | blockDim
-    lds = (size_t)tpy * hc * (zc + 1) * sizeof(cf32) + (size_t)(a.wx + 1) * zc * 4;
+    auto lds_of = [&](int z) {
+        return (size_t)tpy * hc * (z + 1) * sizeof(cf32) + (size_t)(a.wx + 1) * z * 4;
+    };
+    while (zc > 4 && lds_of(zc) > kLdsMax) zc /= 2;   // powers of two: the staging needs zc | blockDim
+    lds = lds_of(zc);
     if (lds > kLdsMax) fail(UFSS_ERR_UNSUPPORTED, "aperture window too wide for the GEMM path");
     a.zc = zc;
     a.zsplit = std::max(1, P.fwd_zsplit);
@@ -437,7 +462,7 @@ static int fwd_args(const Plan& P, const cf32* x, FwdArgs& a, size_t& lds) {
     return a.nblk;
 }
 
-static int adj_args(const Plan& P, cf32* out, AdjArgs& a, size_t& lds) {
+static int adj_args(const Plan& P, cf32* out, AdjArgs& a, size_t& lds, int np) {
     a = AdjArgs{};
     a.r = static_cast<const cf32*>(P.d_rop);
     a.out = out;
@@ -450,7 +475,7 @@ static int adj_args(const Plan& P, cf32* out, AdjArgs& a, size_t& lds) {
     a.wy = P.d.wy;
     a.mu = (int)P.ubins_h.size();
     a.sw = sub_width(P);
-    const int tpx = a.sw * kAdjNP, tpy = 16 / a.sw;
+    const int tpx = a.sw * np, tpy = 16 / a.sw;
     a.ntx = (a.nx + tpx - 1) / tpx;
     a.nty = (a.ny + tpy - 1) / tpy;
     const int zspan = 64 * kAdjNZ;
@@ -475,16 +500,32 @@ static int adj_args(const Plan& P, cf32* out, AdjArgs& a, size_t& lds) {
 void launch_forward_gemm(const Plan& P, const cf32* x, hipStream_t s) {
     FwdArgs a;
     size_t lds;
-    fwd_args(P, x, a, lds);
-    hipLaunchKernelGGL(fwd_gemm_f32_kernel<kFwdNP>, dim3(a.nblk), dim3(64 * a.nw), lds, s, a);
+    const int np = fwd_tile_np(P);
+    fwd_args(P, x, a, lds, np);
+    const dim3 grid(a.nblk), block(64 * a.nw);
+#define UFSS_FWD(NPV, ZCV) hipLaunchKernelGGL((fwd_gemm_f32_kernel<NPV, ZCV>), grid, block, lds, s, a)
+    if (np == 4) {
+        if (a.zc == 16) UFSS_FWD(4, 16); else if (a.zc == 8) UFSS_FWD(4, 8); else UFSS_FWD(4, 4);
+    } else {
+        if (a.zc == 16) UFSS_FWD(2, 16); else if (a.zc == 8) UFSS_FWD(2, 8); else UFSS_FWD(2, 4);
+    }
+#undef UFSS_FWD
     UFSS_HIP(hipGetLastError());
 }
 
 void launch_adjoint_gemm(const Plan& P, cf32* out, hipStream_t s, bool sum) {
     AdjArgs a;
     size_t lds;
-    adj_args(P, out, a, lds);
-    hipLaunchKernelGGL((adj_gemm_f32_kernel<kAdjNP, kAdjNZ>), dim3(a.nblk), dim3(256), lds, s, a);
+    const int np = adj_tile_np(P);
+    adj_args(P, out, a, lds, np);
+    const dim3 grid(a.nblk), block(256);
+#define UFSS_ADJ(NPV, KCV) hipLaunchKernelGGL((adj_gemm_f32_kernel<NPV, kAdjNZ, KCV>), grid, block, lds, s, a)
+    if (np == 4) {
+        if (a.kc == 16) UFSS_ADJ(4, 16); else if (a.kc == 8) UFSS_ADJ(4, 8); else UFSS_ADJ(4, 4);
+    } else {
+        if (a.kc == 16) UFSS_ADJ(2, 16); else if (a.kc == 8) UFSS_ADJ(2, 8); else UFSS_ADJ(2, 4);
+    }
+#undef UFSS_ADJ
     UFSS_HIP(hipGetLastError());
     if (a.split > 1 && sum) launch_sum_parts(P.d_gpart, a.split, P.nvox, out, s);
 }
@@ -501,9 +542,9 @@ size_t desc_size(GemmKind k) {
 int make_desc(GemmKind k, const Plan& P, const void* in, void* out, void* desc, size_t* lds) {
     switch (k) {
         case GemmKind::FwdF32:
-            return fwd_args(P, static_cast<const cf32*>(in), *static_cast<FwdArgs*>(desc), *lds);
+            return fwd_args(P, static_cast<const cf32*>(in), *static_cast<FwdArgs*>(desc), *lds, kGroupNP);
         case GemmKind::AdjF32:
-            return adj_args(P, static_cast<cf32*>(out), *static_cast<AdjArgs*>(desc), *lds);
+            return adj_args(P, static_cast<cf32*>(out), *static_cast<AdjArgs*>(desc), *lds, kGroupNP);
         default: return bf16_make_desc(k, P, in, out, desc, lds);
     }
 }
@@ -513,11 +554,11 @@ void launch_grouped(GemmKind k, const void* descs, const int2* blk, int nblocks,
     if (nblocks <= 0) return;
     switch (k) {
         case GemmKind::FwdF32:
-            hipLaunchKernelGGL(fwd_gemm_f32_kernel_grouped<kFwdNP>, dim3(nblocks), dim3(512), lds, s,
+            hipLaunchKernelGGL(fwd_gemm_f32_kernel_grouped<kGroupNP>, dim3(nblocks), dim3(512), lds, s,
                                static_cast<const FwdArgs*>(descs), blk);
             break;
         case GemmKind::AdjF32:
-            hipLaunchKernelGGL((adj_gemm_f32_kernel_grouped<kAdjNP, kAdjNZ>), dim3(nblocks), dim3(256),
+            hipLaunchKernelGGL((adj_gemm_f32_kernel_grouped<kGroupNP, kAdjNZ>), dim3(nblocks), dim3(256),
                                lds, s, static_cast<const AdjArgs*>(descs), blk);
             break;
         default: bf16_launch_grouped(k, descs, blk, nblocks, lds, s); return;

@@ -63,6 +63,7 @@ struct Plan {
     int fwd_nw = 4;                // waves (16-bin sub-tiles) per forward FP32 workgroup
     int fwd_zsplit = 1;            // split of the forward FP32 GEMM's depth range
                                    // (raw output holds fwd_split * fwd_zsplit partials)
+    int fwd_np = 2, adj_np = 2;    // FP32 GEMMs: 16-position sub-tiles per wave (2 or 4)
     int adj_split = 1;             // split of the adjoint GEMM's d_y range
     cf32* d_gpart = nullptr;       // adjoint partials [adj_split][nvox] (adj_split > 1)
     std::vector<int> bins_h;       // [m] or [npos*m]
@@ -114,6 +115,9 @@ int gemm_split(const Plan& P);
 int adj_split(const Plan& P);
 // Sets the split factors (and reallocates the split workspace when they change).
 void plan_set_splits(Plan& P, int fs, int as, int zs);
+// Lateral tile shape of the FP32 GEMMs (sub-tiles per wave, 2 or 4).
+int fwd_tile_np(const Plan& P);
+int adj_tile_np(const Plan& P);
 // Grouped GEMM launches: one grid runs the tiles of many plans.  A descriptor
 // is the kernel's argument block for one plan (opaque bytes of desc_size);
 // blk[b] = {plan index, block index inside that plan's own grid}.

@@ -324,6 +324,8 @@ void plan_info(const Plan* P, ufss_plan_info* info) {
     info->fwd_waves = f32_gemm ? std::max(1, std::min(P->fwd_nw, ((int)P->ubins_h.size() + 15) / 16)) : 1;
     info->fwd_zsplit = f32_gemm ? P->fwd_zsplit : 1;
     info->phasor_tables = P->d_ptab_f != nullptr;
+    info->fwd_tile = f32_gemm ? fwd_tile_np(*P) : 0;
+    info->adj_tile = f32_gemm ? adj_tile_np(*P) : 0;
 }
 
 }  // namespace ufss

@@ -63,6 +63,7 @@ class PlanInfo(ctypes.Structure):
         ("workspace_bytes", ctypes.c_int64),
         ("fwd_split", ctypes.c_int32), ("adj_split", ctypes.c_int32),
         ("fwd_waves", ctypes.c_int32), ("fwd_zsplit", ctypes.c_int32),
+        ("fwd_tile", ctypes.c_int32), ("adj_tile", ctypes.c_int32),
         ("phasor_tables", ctypes.c_int32),
     ]
 
@@ -111,7 +112,7 @@ def lib():
                                    ctypes.c_int),
             "ufss_autotune": ([P, ctypes.c_char_p, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), P],
                               ctypes.c_int),
-            "ufss_plan_set_tiling": ([P, I32, I32, I32, I32], ctypes.c_int),
+            "ufss_plan_set_tiling": ([P, I32, I32, I32, I32, I32, I32], ctypes.c_int),
             "ufss_plan_set_phasor_tables": ([P, I32, ctypes.POINTER(I32)], ctypes.c_int),
             "ufss_unrolled_create": ([P, I32, I32, D, D, U64, ctypes.POINTER(P)], ctypes.c_int),
             "ufss_unrolled_destroy": ([P], ctypes.c_int),
@@ -309,21 +310,22 @@ def ufss_fista_batched(plans, ys, xs, lambdas, Ls, iters, stream=None):
     return np.array(list(res))
 
 
-def ufss_autotune(plan, cache_path=None, use_cache=True, write_cache=True, stream=None):
-    """Pick the split-K factors of the plan's GEMMs by timing; returns (fwd, adj)."""
+def ufss_autotune(plan, cache_path=None, use_cache=True, write_cache=True, stream=None, quick=False):
+    """Pick the tiling of the plan's GEMMs by timing; returns the (fwd, adj) d_y splits."""
     fs = ctypes.c_int32(0)
     asp = ctypes.c_int32(0)
-    flags = (1 if use_cache else 0) | (2 if write_cache else 0)
+    flags = (1 if use_cache else 0) | (2 if write_cache else 0) | (4 if quick else 0)
     path = cache_path.encode() if cache_path else None
     _check(lib().ufss_autotune(plan.handle, path, flags, ctypes.byref(fs), ctypes.byref(asp),
                                _stream(stream)))
     return fs.value, asp.value
 
 
-def ufss_plan_set_tiling(plan, fwd_split=0, adj_split=0, fwd_waves=0, fwd_zsplit=0):
+def ufss_plan_set_tiling(plan, fwd_split=0, adj_split=0, fwd_waves=0, fwd_zsplit=0, fwd_tile=0,
+                         adj_tile=0):
     """Manual GEMM tiling (0 keeps the current value); see ufss_autotune."""
     _check(lib().ufss_plan_set_tiling(plan.handle, int(fwd_split), int(adj_split), int(fwd_waves),
-                                      int(fwd_zsplit)))
+                                      int(fwd_zsplit), int(fwd_tile), int(adj_tile)))
 
 
 def ufss_plan_set_phasor_tables(plan, enable):

@@ -73,3 +73,28 @@ def test_plan_rejects_bad_bins_before_touching_the_gpu():
     with pytest.raises(ufss.UfssError) as e:
         ufss.Plan(bad, 2, False, np.array([4, 5]), dtype=ufss.BF16, algo=ufss.ALGO_PHASOR)
     assert e.value.name in ("UNSUPPORTED", "INVALID_ARG")
+
+
+def header_struct_fields(name):
+    """Field names of `typedef struct name {...} name;` in include/ufss.h, in order."""
+    text = open(os.path.join(ROOT, "include", "ufss.h")).read()
+    body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (name, name), text, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        names = decl.split(None, 1)[1]
+        fields += [n.strip().lstrip("*").strip() for n in names.split(",")]
+    return fields
+
+
+@pytest.mark.parametrize("cname,pyname", [("ufss_geom", "Geom"), ("ufss_plan_info", "PlanInfo"),
+                                           ("ufss_fista_stats", "FistaStats"),
+                                           ("ufss_fista_state", "FistaState")])
+def test_binding_structs_match_header(cname, pyname):
+    """The ctypes mirrors of the C structs list the same fields in the same order."""
+    cls = getattr(ufss, pyname)
+    py = [f.rstrip("_") for f, _ in cls._fields_]
+    assert py == header_struct_fields(cname)

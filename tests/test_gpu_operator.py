@@ -200,14 +200,17 @@ def test_manual_tiling_same_operator(dtype, dev):
     x_ref = (A.conj().T @ y.reshape(-1).astype(np.complex128)).reshape(x.shape)
     tol = TOL32 if dtype == "f32" else 1e-2
     plan = u.Plan(g, 20, True, bins, dtype=u.F32 if dtype == "f32" else u.BF16)
-    tilings = [(1, 1, 1, 1), (3, 2, 2, 3), (9, 9, 8, 10), (64, 64, 3, 64)]
+    tilings = [(1, 1, 1, 1, 2, 2), (3, 2, 2, 3, 4, 4), (9, 9, 8, 10, 4, 2), (64, 64, 3, 64, 2, 4)]
     if dtype == "bf16":
-        tilings = [(f, a, 0, 1) for f, a, _, _ in tilings]
+        tilings = [(t[0], t[1], 0, 1, 0, 0) for t in tilings]
     xt = torch.from_numpy(x).to(dev)
     yt = torch.from_numpy(y).to(dev)
     for t in tilings:
         u.ufss_plan_set_tiling(plan, *t)
-        assert plan.info()["fwd_split"] == t[0] and plan.info()["adj_split"] == t[1]
+        info = plan.info()
+        assert info["fwd_split"] == t[0] and info["adj_split"] == t[1]
+        if dtype == "f32":
+            assert (info["fwd_tile"], info["adj_tile"], info["fwd_zsplit"]) == (t[4], t[5], t[3])
         yo = torch.empty_like(yt)
         xo = torch.empty_like(xt)
         u.ufss_forward(plan, xt, yo)
@@ -215,7 +218,8 @@ def test_manual_tiling_same_operator(dtype, dev):
         torch.cuda.synchronize()
         ey, ex = errs(yo.cpu().numpy(), y_ref), errs(xo.cpu().numpy(), x_ref)
         assert max(ey) < tol and max(ex) < tol, (t, ey, ex)
-    for bad in [(-1, 0, 0, 0), (65, 0, 0, 0), (0, 0, 9, 0), (0, 0, 0, 65)]:
+    for bad in [(-1, 0, 0, 0, 0, 0), (65, 0, 0, 0, 0, 0), (0, 0, 9, 0, 0, 0), (0, 0, 0, 65, 0, 0),
+                (0, 0, 0, 0, 3, 0), (0, 0, 0, 0, 0, 8)]:
         with pytest.raises(u.UfssError):
             u.ufss_plan_set_tiling(plan, *bad)
     plan.close()
