@@ -505,10 +505,12 @@ int autotune(Plan& P, const char* cache_path, int flags, hipStream_t s, int32_t*
     const std::string key = shape_key(P);
     std::map<std::string, std::vector<double>> cache;
     if (cache_path && (flags & 1)) cache = read_cache(cache_path);
-    if (cache.count(key) && cache[key].size() >= 8) {
+    if (cache.count(key) && cache[key].size() >= 10) {
         P.fwd_nw = (int)cache[key][4];
         P.fwd_np = (int)cache[key][6];
         P.adj_np = (int)cache[key][7];
+        P.bf_fwd_rows = (int)cache[key][8];
+        P.bf_adj_rows = (int)cache[key][9];
         plan_set_splits(P, (int)cache[key][0], (int)cache[key][1], (int)cache[key][5]);
     } else {
         const int tpy = P.g.ny == 1 ? 1 : 4;
@@ -521,10 +523,13 @@ int autotune(Plan& P, const char* cache_path, int flags, hipStream_t s, int32_t*
         UFSS_HIP(hipMemsetAsync(P.d_r, 0, (size_t)P.npos * P.m * sizeof(cf32), s));
         double best_f = 1e30, best_a = 1e30;
         int bf = P.fwd_split, ba = P.adj_split, bnw = P.fwd_nw, bz = P.fwd_zsplit;
-        int bnp = P.fwd_np, bnpa = P.adj_np;
-        // FP32: 2 or 4 position sub-tiles per wave; BF16 picks its own tile width
+        int bnp = P.fwd_np, bnpa = P.adj_np, bfr = P.bf_fwd_rows, bar = P.bf_adj_rows;
         // flags bit 2: quick search (d_y splits and two depth splits at the default tile shape)
         const bool quick = (flags & 4) != 0;
+        // BF16 C-scans: one or two rows of waves per tile
+        std::vector<int> rows{1};
+        if (P.dtype == UFSS_BF16 && !quick && bf16_rows_ok(P, 2, 2)) rows.push_back(2);
+        // FP32: 2 or 4 position sub-tiles per wave; BF16 picks its own tile width
         const std::vector<int> npc =
             (P.dtype == UFSS_F32 && !quick) ? std::vector<int>{2, 4} : std::vector<int>{2};
         std::vector<int> zcand{1};
@@ -533,32 +538,38 @@ int autotune(Plan& P, const char* cache_path, int flags, hipStream_t s, int32_t*
                 if (P.g.nz >= 32 * z) zcand.push_back(z);
         if (quick && zcand.size() > 2) zcand = {1, zcand[2]};
         const std::vector<int> nwc = quick ? std::vector<int>{P.fwd_nw} : nw_candidates(P);
-        for (int np : npc)
-            for (int nw : nwc)
-                for (int zs : zcand)
-                    for (int c : cand) {
-                        if (c * zs > 96) continue;          // bounds the partial-sum workspace
-                        P.fwd_nw = nw;
-                        P.fwd_np = np;
-                        plan_set_splits(P, c, P.adj_split, zs);
-                        double t = time_ms([&]() { op_forward(P, P.d_gamma, P.d_r, nullptr, nullptr, s); }, 3, s);
-                        if (t < best_f) { best_f = t; bf = c; bnw = nw; bz = zs; bnp = np; }
-                    }
+        for (int wr : rows)
+            for (int np : npc)
+                for (int nw : nwc)
+                    for (int zs : zcand)
+                        for (int c : cand) {
+                            if (c * zs > 96) continue;          // bounds the partial-sum workspace
+                            P.fwd_nw = nw;
+                            P.fwd_np = np;
+                            P.bf_fwd_rows = wr;
+                            plan_set_splits(P, c, P.adj_split, zs);
+                            double t = time_ms([&]() { op_forward(P, P.d_gamma, P.d_r, nullptr, nullptr, s); }, 3, s);
+                            if (t < best_f) { best_f = t; bf = c; bnw = nw; bz = zs; bnp = np; bfr = wr; }
+                        }
         P.fwd_nw = bnw;
         P.fwd_np = bnp;
-        for (int np : npc)
-            for (int c : cand) {
-                P.adj_np = np;
-                plan_set_splits(P, bf, c, bz);
-                double t = time_ms([&]() { op_adjoint(P, P.d_r, P.d_g, s); }, 3, s);
-                if (t < best_a) { best_a = t; ba = c; bnpa = np; }
-            }
+        P.bf_fwd_rows = bfr;
+        for (int wr : rows)
+            for (int np : npc)
+                for (int c : cand) {
+                    P.adj_np = np;
+                    P.bf_adj_rows = wr;
+                    plan_set_splits(P, bf, c, bz);
+                    double t = time_ms([&]() { op_adjoint(P, P.d_r, P.d_g, s); }, 3, s);
+                    if (t < best_a) { best_a = t; ba = c; bnpa = np; bar = wr; }
+                }
         P.adj_np = bnpa;
+        P.bf_adj_rows = bar;
         plan_set_splits(P, bf, ba, bz);
         if (cache_path && (flags & 2)) {
             cache = read_cache(cache_path);
             cache[key] = {(double)bf, (double)ba, best_f, best_a, (double)bnw, (double)bz, (double)bnp,
-                          (double)bnpa};
+                          (double)bnpa, (double)bfr, (double)bar};
             write_cache(cache_path, cache);
         }
     }

@@ -168,12 +168,17 @@ struct FwdB {
     const __bf16* tab;     // phasor tiles [wy+1][wx+1][nzc][mu][2][32] or null
 };
 
-template <int NP, int NB>
+// WR: rows of waves in a tile (1: the 4 waves side by side along x; 2: a 2 x 2
+// arrangement, half as wide and twice as tall, which needs fewer offsets per
+// useful one when the aperture covers the whole grid).
+template <int NP, int NB, int WR>
 __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nblk, unsigned char* smem) {
     static_assert(NB * 16 <= 64, "table tiles are copied in two passes of 256 x 16 bytes");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int sw = a.sw, sh = 16 / sw;
-    const int tpx = 4 * NP * sw, tpy = sh;
+    constexpr int WC = 4 / WR;                   // waves per tile row
+    const int tpx = WC * NP * sw, tpy = WR * sh;
+    const int wave_x = wave % WC, wave_y = wave / WC;
 
     int per_xcd = nblk / 8;
     if (per_xcd * 8 == nblk) b = (b % 8) * per_xcd + b / 8;
@@ -189,8 +194,9 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
     __bf16* halo = reinterpret_cast<__bf16*>(smem);                    // [tpy*pitch + 1][CELL]
     const int zero_cell = tpy * pitch;
     __bf16* ptile = halo + (size_t)(zero_cell + 1) * CELL;               // [2][2][NB*16][PROW]
-    uint32_t* ulds = reinterpret_cast<uint32_t*>(ptile + 2 * 2 * NB * 16 * PROW);   // [wx+1][ZCB]
-    int* klds = reinterpret_cast<int*>(ulds + (a.wx + 1) * ZCB);         // [NB*16]
+    // delay slab [wx+1][ZCB] (phasor generation only: absent with tables), then bins [NB*16]
+    uint32_t* ulds = reinterpret_cast<uint32_t*>(ptile + 2 * 2 * NB * 16 * PROW);
+    int* klds = reinterpret_cast<int*>(ulds + (a.tab ? 0 : (a.wx + 1) * ZCB));
 
     int dy_lo = max(-a.wy, py0 - (a.ny - 1));
     int dy_hi = min(a.wy, py0 + tpy - 1);
@@ -270,8 +276,8 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
                 bf8 xr[NP], xi[NP];
 #pragma unroll
                 for (int s = 0; s < NP; ++s) {
-                    const int q = wave * NP + s;
-                    const int px = px0 + q * sw + i % sw, iy = i / sw;
+                    const int q = wave_x * NP + s;
+                    const int px = px0 + q * sw + i % sw, iy = wave_y * sh + i / sw;
                     const int gx = px - dx;
                     const int cell = (gx >= cx_lo && gx <= cx_hi) ? iy * pitch + (gx - cx_lo) : zero_cell;
                     xr[s] = lds_bf8(halo + (size_t)cell * CELL + 8 * kq);
@@ -305,7 +311,7 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
     cf32* yo = a.yraw + (int64_t)sp * a.npos * a.mu;
 #pragma unroll
     for (int s = 0; s < NP; ++s) {
-        const int q = wave * NP + s;
+        const int q = wave_x * NP + s;
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             const int mb = mb0 + nb * 16 + i;
@@ -313,7 +319,7 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int irow = 4 * kq + r;
-                const int px = px0 + q * sw + irow % sw, py = py0 + irow / sw;
+                const int px = px0 + q * sw + irow % sw, py = py0 + wave_y * sh + irow / sw;
                 if (px < a.nx && py < a.ny)
                     yo[((int64_t)py * a.nx + px) * a.mu + mb] = cf32{acc_re[s][nb][r], acc_im[s][nb][r]};
             }
@@ -321,10 +327,10 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
     }
 }
 
-template <int NP, int NB>
+template <int NP, int NB, int WR>
 __global__ __launch_bounds__(256) void fwd_gemm_bf16_kernel(FwdB a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    fwd_bf16_body<NP, NB>(a, blockIdx.x, gridDim.x, smem);
+    fwd_bf16_body<NP, NB, WR>(a, blockIdx.x, gridDim.x, smem);
 }
 
 // Grouped launch: block -> (plan index, block index inside that plan's grid).
@@ -334,7 +340,7 @@ __global__ __launch_bounds__(256) void fwd_gemm_bf16_kernel_grouped(const FwdB* 
     extern __shared__ __align__(16) unsigned char smem[];
     const int2 sb = blk[blockIdx.x];
     const FwdB a = descs[sb.x];
-    fwd_bf16_body<NP, NB>(a, sb.y, a.nblk, smem);
+    fwd_bf16_body<NP, NB, 1>(a, sb.y, a.nblk, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -353,11 +359,13 @@ struct AdjB {
     const __bf16* tab;     // phasor tiles [wy+1][wx+1][nkc][nz][2][32] or null
 };
 
-template <int NV, int NZ>
+template <int NV, int NZ, int WR>
 __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nblk, unsigned char* smem) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int sw = a.sw, sh = 16 / sw;
-    const int tvx = 4 * NV * sw, tvy = sh;
+    constexpr int WC = 4 / WR;                   // waves per tile row
+    const int tvx = WC * NV * sw, tvy = WR * sh;
+    const int wave_x = wave % WC, wave_y = wave / WC;
     const int zspan = NZ * 16;
     static_assert(NZ * 16 <= 64, "table tiles are copied in two passes of 256 x 16 bytes");
 
@@ -376,8 +384,9 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
     __bf16* halo = reinterpret_cast<__bf16*>(smem);                  // [tvy*pitch + 1][CELL]
     const int zero_cell = tvy * pitch;
     __bf16* ptile = halo + (size_t)(zero_cell + 1) * CELL;             // [2][2][zspan][PROW]
-    uint32_t* ulds = reinterpret_cast<uint32_t*>(ptile + 2 * 2 * zspan * PROW);   // [wx+1][zspan]
-    int* klds = reinterpret_cast<int*>(ulds + (a.wx + 1) * zspan);     // [ZCB]
+    // delay slab [wx+1][zspan] (phasor generation only: absent with tables), then bins [ZCB]
+    uint32_t* ulds = reinterpret_cast<uint32_t*>(ptile + 2 * 2 * zspan * PROW);
+    int* klds = reinterpret_cast<int*>(ulds + (a.tab ? 0 : (a.wx + 1) * zspan));
 
     int dy_lo = max(-a.wy, -(vy0 + tvy - 1));
     int dy_hi = min(a.wy, a.ny - 1 - vy0);
@@ -471,8 +480,8 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
                 bf8 rr8[NV], ri8[NV];
 #pragma unroll
                 for (int s = 0; s < NV; ++s) {
-                    const int q = wave * NV + s;
-                    const int vx = vx0 + q * sw + i % sw, iy = i / sw;
+                    const int q = wave_x * NV + s;
+                    const int vx = vx0 + q * sw + i % sw, iy = wave_y * sh + i / sw;
                     const int gx = vx + dx;
                     const int cell = (gx >= cx_lo && gx <= cx_hi) ? iy * pitch + (gx - cx_lo) : zero_cell;
                     rr8[s] = lds_bf8(halo + (size_t)cell * CELL + 8 * kq);
@@ -506,7 +515,7 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
     cf32* dst = a.split > 1 ? a.part + (int64_t)sp * a.nvox : a.out;
 #pragma unroll
     for (int s = 0; s < NV; ++s) {
-        const int q = wave * NV + s;
+        const int q = wave_x * NV + s;
 #pragma unroll
         for (int qz = 0; qz < NZ; ++qz) {
             if (qz >= nz_act) continue;
@@ -514,7 +523,7 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int irow = 4 * kq + r;
-                const int vx = vx0 + q * sw + irow % sw, vy = vy0 + irow / sw;
+                const int vx = vx0 + q * sw + irow % sw, vy = vy0 + wave_y * sh + irow / sw;
                 if (vx < a.nx && vy < a.ny && z < a.nz)
                     dst[((int64_t)vy * a.nx + vx) * a.nz + z] = cf32{acc_re[s][qz][r], acc_im[s][qz][r]};
             }
@@ -522,10 +531,10 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
     }
 }
 
-template <int NV, int NZ>
+template <int NV, int NZ, int WR>
 __global__ __launch_bounds__(256) void adj_gemm_bf16_kernel(AdjB a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    adj_bf16_body<NV, NZ>(a, blockIdx.x, gridDim.x, smem);
+    adj_bf16_body<NV, NZ, WR>(a, blockIdx.x, gridDim.x, smem);
 }
 
 // Grouped launch: block -> (plan index, block index inside that plan's grid).
@@ -535,7 +544,7 @@ __global__ __launch_bounds__(256) void adj_gemm_bf16_kernel_grouped(const AdjB* 
     extern __shared__ __align__(16) unsigned char smem[];
     const int2 sb = blk[blockIdx.x];
     const AdjB a = descs[sb.x];
-    adj_bf16_body<NV, NZ>(a, sb.y, a.nblk, smem);
+    adj_bf16_body<NV, NZ, 1>(a, sb.y, a.nblk, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -549,36 +558,56 @@ static int bf_sw(const Plan& P) { return P.g.ny == 1 ? 16 : 4; }
 
 // Lateral sub-tiles of 16 per wave: 4 when the grid is wide enough that a
 // 64-position tile row does not overhang it by much, else 2.  Batched
-// (grouped) launches always use 2 so one kernel fits every scan.
+// (grouped) launches always use 2 and one wave row so one kernel fits every scan.
 static int bf_np(const Plan& P) { return (P.g.ny > 1 && P.g.nx >= 48) ? 4 : 2; }
 
 // Bin sub-tiles per forward tile.  (Measured: 6 x 16-bin tiles, which cover a
 // 66-bin union in one tile, ran slower than two 4 x 16 tiles, so 4 is kept.)
 static int bf_nb(const Plan&, int) { return kBfNB; }
 
-static size_t fwd_bf16_lds(const Plan& P, int np, int nb) {
-    const int sw = bf_sw(P), tpx = 4 * np * sw, tpy = 16 / sw;
+// Tile of np sub-tiles per wave, 4 waves in wr rows.
+static void bf_tile(const Plan& P, int np, int wr, int& tx, int& ty) {
+    const int sw = bf_sw(P);
+    tx = (4 / wr) * np * sw;
+    ty = wr * (16 / sw);
+}
+
+// LDS bytes; `tables`: phasors copied from the tables (no delay slab needed).
+static size_t fwd_bf16_lds(const Plan& P, int np, int nb, int wr, bool tables) {
+    int tpx, tpy;
+    bf_tile(P, np, wr, tpx, tpy);
     const int ncol = std::min(P.g.nx, tpx + 2 * P.d.wx);
     return (size_t)(tpy * ncol + 1) * CELL * 2 + (size_t)2 * 2 * nb * 16 * PROW * 2 +
-           (size_t)(P.d.wx + 1) * ZCB * 4 + nb * 16 * 4;
+           (tables ? 0 : (size_t)(P.d.wx + 1) * ZCB * 4) + nb * 16 * 4;
 }
 
-static size_t adj_bf16_lds(const Plan& P, int nv) {
-    const int sw = bf_sw(P), tvx = 4 * nv * sw, tvy = 16 / sw;
+static size_t adj_bf16_lds(const Plan& P, int nv, int wr, bool tables) {
+    int tvx, tvy;
+    bf_tile(P, nv, wr, tvx, tvy);
     const int ncol = std::min(P.g.nx, tvx + 2 * P.d.wx);
     return (size_t)(tvy * ncol + 1) * CELL * 2 + (size_t)2 * 2 * kBfNZ * 16 * PROW * 2 +
-           (size_t)(P.d.wx + 1) * kBfNZ * 16 * 4 + ZCB * 4;
+           (tables ? 0 : (size_t)(P.d.wx + 1) * kBfNZ * 16 * 4) + ZCB * 4;
 }
 
+// One-row tiles must fit with in-kernel phasor generation (the fallback).
 bool bf16_supported(const Plan& P) {
     for (int np : {2, bf_np(P)})
-        if (fwd_bf16_lds(P, np, bf_nb(P, np)) > kLdsMaxB || adj_bf16_lds(P, np) > kLdsMaxB)
+        if (fwd_bf16_lds(P, np, bf_nb(P, np), 1, false) > kLdsMaxB ||
+            adj_bf16_lds(P, np, 1, false) > kLdsMaxB)
             return false;
     return true;
 }
 
+bool bf16_rows_ok(const Plan& P, int fwd_rows, int adj_rows) {
+    const int np = bf_np(P);
+    if (P.g.ny == 1 && (fwd_rows > 1 || adj_rows > 1)) return false;   // B-scans: one row
+    return fwd_bf16_lds(P, np, bf_nb(P, np), fwd_rows, P.d_ptab_f != nullptr) <= kLdsMaxB &&
+           adj_bf16_lds(P, np, adj_rows, P.d_ptab_a != nullptr) <= kLdsMaxB;
+}
+
 int bf16_fwd_split(const Plan& P) {
-    const int sw = bf_sw(P), tpx = 4 * bf_np(P) * sw, tpy = 16 / sw;
+    int tpx, tpy;
+    bf_tile(P, bf_np(P), P.bf_fwd_rows, tpx, tpy);
     const int ntx = (P.g.nx + tpx - 1) / tpx, nty = (P.g.ny + tpy - 1) / tpy;
     const int mu = (int)P.ubins_h.size();
     const int nb = bf_nb(P, bf_np(P));
@@ -592,7 +621,8 @@ int bf16_fwd_split(const Plan& P) {
 }
 
 int bf16_adj_split(const Plan& P) {
-    const int sw = bf_sw(P), tvx = 4 * bf_np(P) * sw, tvy = 16 / sw;
+    int tvx, tvy;
+    bf_tile(P, bf_np(P), P.bf_adj_rows, tvx, tvy);
     const int ntx = (P.g.nx + tvx - 1) / tvx, nty = (P.g.ny + tvy - 1) / tvy;
     const int nzt = (P.g.nz + kBfNZ * 16 - 1) / (kBfNZ * 16);
     const int wgs = ntx * nty * nzt;
@@ -603,7 +633,7 @@ int bf16_adj_split(const Plan& P) {
     return (ndy_max + chunk - 1) / chunk;
 }
 
-static int fwdb_args(const Plan& P, FwdB& a, size_t& lds, int np, int nb) {
+static int fwdb_args(const Plan& P, FwdB& a, size_t& lds, int np, int nb, int wr) {
     a = FwdB{};
     a.x = static_cast<const cbf16*>(P.d_xop);
     a.yraw = P.d_yraw;
@@ -616,20 +646,21 @@ static int fwdb_args(const Plan& P, FwdB& a, size_t& lds, int np, int nb) {
     a.wy = P.d.wy;
     a.mu = (int)P.ubins_h.size();
     a.sw = bf_sw(P);
-    const int tpx = 4 * np * a.sw, tpy = 16 / a.sw;
+    int tpx, tpy;
+    bf_tile(P, np, wr, tpx, tpy);
     a.ntx = (a.nx + tpx - 1) / tpx;
     a.nty = (a.ny + tpy - 1) / tpy;
     a.nbt = (a.mu + nb * 16 - 1) / (nb * 16);
     a.split = P.fwd_split;
     a.npos = P.npos;
     a.tab = static_cast<const __bf16*>(P.d_ptab_f);
-    lds = fwd_bf16_lds(P, np, nb);
+    lds = fwd_bf16_lds(P, np, nb, wr, a.tab != nullptr);
     if (lds > kLdsMaxB) fail(UFSS_ERR_UNSUPPORTED, "aperture window too wide for the BF16 GEMM path");
     a.nblk = a.ntx * a.nty * a.nbt * a.split;
     return a.nblk;
 }
 
-static int adjb_args(const Plan& P, cf32* out, AdjB& a, size_t& lds, int nv) {
+static int adjb_args(const Plan& P, cf32* out, AdjB& a, size_t& lds, int nv, int wr) {
     a = AdjB{};
     a.r = static_cast<const cbf16*>(P.d_rop);
     a.out = out;
@@ -643,14 +674,15 @@ static int adjb_args(const Plan& P, cf32* out, AdjB& a, size_t& lds, int nv) {
     a.wy = P.d.wy;
     a.mu = (int)P.ubins_h.size();
     a.sw = bf_sw(P);
-    const int tvx = 4 * nv * a.sw, tvy = 16 / a.sw;
+    int tvx, tvy;
+    bf_tile(P, nv, wr, tvx, tvy);
     a.ntx = (a.nx + tvx - 1) / tvx;
     a.nty = (a.ny + tvy - 1) / tvy;
     a.nzt = (a.nz + kBfNZ * 16 - 1) / (kBfNZ * 16);
     a.split = P.adj_split;
     a.nvox = P.nvox;
     a.tab = static_cast<const __bf16*>(P.d_ptab_a);
-    lds = adj_bf16_lds(P, nv);
+    lds = adj_bf16_lds(P, nv, wr, a.tab != nullptr);
     if (lds > kLdsMaxB) fail(UFSS_ERR_UNSUPPORTED, "aperture window too wide for the BF16 GEMM path");
     a.nblk = a.ntx * a.nty * a.nzt * a.split;
     return a.nblk;
@@ -659,24 +691,32 @@ static int adjb_args(const Plan& P, cf32* out, AdjB& a, size_t& lds, int nv) {
 void launch_forward_gemm_bf16(const Plan& P, hipStream_t s) {
     FwdB a;
     size_t lds;
-    const int np = bf_np(P), nb = bf_nb(P, np);
-    fwdb_args(P, a, lds, np, nb);
-    if (np == 4)
-        hipLaunchKernelGGL((fwd_gemm_bf16_kernel<4, kBfNB>), dim3(a.nblk), dim3(256), lds, s, a);
-    else
-        hipLaunchKernelGGL((fwd_gemm_bf16_kernel<2, kBfNB>), dim3(a.nblk), dim3(256), lds, s, a);
+    const int np = bf_np(P), nb = bf_nb(P, np), wr = P.bf_fwd_rows == 2 ? 2 : 1;
+    fwdb_args(P, a, lds, np, nb, wr);
+    const dim3 grid(a.nblk), block(256);
+#define UFSS_FB(NPV, WRV) hipLaunchKernelGGL((fwd_gemm_bf16_kernel<NPV, kBfNB, WRV>), grid, block, lds, s, a)
+    if (np == 4) {
+        if (wr == 2) UFSS_FB(4, 2); else UFSS_FB(4, 1);
+    } else {
+        if (wr == 2) UFSS_FB(2, 2); else UFSS_FB(2, 1);
+    }
+#undef UFSS_FB
     UFSS_HIP(hipGetLastError());
 }
 
 void launch_adjoint_gemm_bf16(const Plan& P, cf32* out, hipStream_t s, bool sum) {
     AdjB a;
     size_t lds;
-    const int nv = bf_np(P);
-    adjb_args(P, out, a, lds, nv);
-    if (nv == 4)
-        hipLaunchKernelGGL((adj_gemm_bf16_kernel<4, kBfNZ>), dim3(a.nblk), dim3(256), lds, s, a);
-    else
-        hipLaunchKernelGGL((adj_gemm_bf16_kernel<2, kBfNZ>), dim3(a.nblk), dim3(256), lds, s, a);
+    const int nv = bf_np(P), wr = P.bf_adj_rows == 2 ? 2 : 1;
+    adjb_args(P, out, a, lds, nv, wr);
+    const dim3 grid(a.nblk), block(256);
+#define UFSS_AB(NVV, WRV) hipLaunchKernelGGL((adj_gemm_bf16_kernel<NVV, kBfNZ, WRV>), grid, block, lds, s, a)
+    if (nv == 4) {
+        if (wr == 2) UFSS_AB(4, 2); else UFSS_AB(4, 1);
+    } else {
+        if (wr == 2) UFSS_AB(2, 2); else UFSS_AB(2, 1);
+    }
+#undef UFSS_AB
     UFSS_HIP(hipGetLastError());
     if (a.split > 1 && sum) launch_sum_parts(P.d_gpart, a.split, P.nvox, out, s);
 }
@@ -711,14 +751,7 @@ __global__ void build_ptab_kernel(const uint32_t* __restrict__ u, const int* __r
 
 static constexpr int64_t kPtabMax = int64_t(4) << 30;   // both tables together
 
-void bf16_set_tables(Plan& P, int enable) {
-    UFSS_HIP(hipDeviceSynchronize());
-    if (P.d_ptab_f) UFSS_HIP(hipFree(P.d_ptab_f));
-    if (P.d_ptab_a) UFSS_HIP(hipFree(P.d_ptab_a));
-    P.d_ptab_f = P.d_ptab_a = nullptr;
-    P.ws_bytes -= P.ptab_bytes;
-    P.ptab_bytes = 0;
-    if (!enable || P.dtype != UFSS_BF16 || P.algo != UFSS_ALGO_GEMM) return;
+static void bf16_build_tables(Plan& P) {
     const int mu = (int)P.ubins_h.size();
     const int nzc = (P.g.nz + ZCB - 1) / ZCB, nkc = (mu + ZCB - 1) / ZCB;
     const int64_t dxy = (int64_t)(P.d.wy + 1) * (P.d.wx + 1);
@@ -742,12 +775,26 @@ void bf16_set_tables(Plan& P, int enable) {
     P.ws_bytes += P.ptab_bytes;
 }
 
+void bf16_set_tables(Plan& P, int enable) {
+    UFSS_HIP(hipDeviceSynchronize());
+    if (P.d_ptab_f) UFSS_HIP(hipFree(P.d_ptab_f));
+    if (P.d_ptab_a) UFSS_HIP(hipFree(P.d_ptab_a));
+    P.d_ptab_f = P.d_ptab_a = nullptr;
+    P.ws_bytes -= P.ptab_bytes;
+    P.ptab_bytes = 0;
+    if (P.dtype != UFSS_BF16 || P.algo != UFSS_ALGO_GEMM) return;
+    if (enable) bf16_build_tables(P);
+    // without tables the kernels also stage the delay slab: fall back to one-row
+    // tiles where two rows no longer fit
+    if (!bf16_rows_ok(P, P.bf_fwd_rows, P.bf_adj_rows)) P.bf_fwd_rows = P.bf_adj_rows = 1;
+}
+
 size_t bf16_desc_size(GemmKind k) { return k == GemmKind::FwdBF16 ? sizeof(FwdB) : sizeof(AdjB); }
 
 int bf16_make_desc(GemmKind k, const Plan& P, const void* in, void* out, void* desc, size_t* lds) {
     (void)in;
-    if (k == GemmKind::FwdBF16) return fwdb_args(P, *static_cast<FwdB*>(desc), *lds, 2, kBfNB);
-    return adjb_args(P, static_cast<cf32*>(out), *static_cast<AdjB*>(desc), *lds, 2);
+    if (k == GemmKind::FwdBF16) return fwdb_args(P, *static_cast<FwdB*>(desc), *lds, 2, kBfNB, 1);
+    return adjb_args(P, static_cast<cf32*>(out), *static_cast<AdjB*>(desc), *lds, 2, 1);
 }
 
 void bf16_launch_grouped(GemmKind k, const void* descs, const int2* blk, int nblocks, size_t lds,

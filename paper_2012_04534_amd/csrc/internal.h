@@ -64,6 +64,7 @@ struct Plan {
     int fwd_zsplit = 1;            // split of the forward FP32 GEMM's depth range
                                    // (raw output holds fwd_split * fwd_zsplit partials)
     int fwd_np = 2, adj_np = 2;    // FP32 GEMMs: 16-position sub-tiles per wave (2 or 4)
+    int bf_fwd_rows = 1, bf_adj_rows = 1;   // BF16 GEMMs: rows of waves in a tile (1 or 2)
     int adj_split = 1;             // split of the adjoint GEMM's d_y range
     cf32* d_gpart = nullptr;       // adjoint partials [adj_split][nvox] (adj_split > 1)
     std::vector<int> bins_h;       // [m] or [npos*m]
@@ -133,6 +134,7 @@ int bf16_make_desc(GemmKind k, const Plan& P, const void* in, void* out, void* d
 void bf16_launch_grouped(GemmKind k, const void* descs, const int2* blk, int nblocks, size_t lds,
                          hipStream_t s);
 bool bf16_supported(const Plan& P);
+bool bf16_rows_ok(const Plan& P, int fwd_rows, int adj_rows);   // tile shapes fit in LDS
 // Builds (enable != 0, if within the size limit) or frees the BF16 phasor tables.
 void bf16_set_tables(Plan& P, int enable);
 int bf16_fwd_split(const Plan& P);

@@ -326,6 +326,9 @@ void plan_info(const Plan* P, ufss_plan_info* info) {
     info->phasor_tables = P->d_ptab_f != nullptr;
     info->fwd_tile = f32_gemm ? fwd_tile_np(*P) : 0;
     info->adj_tile = f32_gemm ? adj_tile_np(*P) : 0;
+    const bool bf_gemm = P->algo == UFSS_ALGO_GEMM && P->dtype == UFSS_BF16;
+    info->fwd_rows = bf_gemm ? P->bf_fwd_rows : 0;
+    info->adj_rows = bf_gemm ? P->bf_adj_rows : 0;
 }
 
 }  // namespace ufss

@@ -64,6 +64,7 @@ class PlanInfo(ctypes.Structure):
         ("fwd_split", ctypes.c_int32), ("adj_split", ctypes.c_int32),
         ("fwd_waves", ctypes.c_int32), ("fwd_zsplit", ctypes.c_int32),
         ("fwd_tile", ctypes.c_int32), ("adj_tile", ctypes.c_int32),
+        ("fwd_rows", ctypes.c_int32), ("adj_rows", ctypes.c_int32),
         ("phasor_tables", ctypes.c_int32),
     ]
 
@@ -112,7 +113,7 @@ def lib():
                                    ctypes.c_int),
             "ufss_autotune": ([P, ctypes.c_char_p, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), P],
                               ctypes.c_int),
-            "ufss_plan_set_tiling": ([P, I32, I32, I32, I32, I32, I32], ctypes.c_int),
+            "ufss_plan_set_tiling": ([P, I32, I32, I32, I32, I32, I32, I32, I32], ctypes.c_int),
             "ufss_plan_set_phasor_tables": ([P, I32, ctypes.POINTER(I32)], ctypes.c_int),
             "ufss_unrolled_create": ([P, I32, I32, D, D, U64, ctypes.POINTER(P)], ctypes.c_int),
             "ufss_unrolled_destroy": ([P], ctypes.c_int),
@@ -322,10 +323,11 @@ def ufss_autotune(plan, cache_path=None, use_cache=True, write_cache=True, strea
 
 
 def ufss_plan_set_tiling(plan, fwd_split=0, adj_split=0, fwd_waves=0, fwd_zsplit=0, fwd_tile=0,
-                         adj_tile=0):
+                         adj_tile=0, fwd_rows=0, adj_rows=0):
     """Manual GEMM tiling (0 keeps the current value); see ufss_autotune."""
     _check(lib().ufss_plan_set_tiling(plan.handle, int(fwd_split), int(adj_split), int(fwd_waves),
-                                      int(fwd_zsplit), int(fwd_tile), int(adj_tile)))
+                                      int(fwd_zsplit), int(fwd_tile), int(adj_tile), int(fwd_rows),
+                                      int(adj_rows)))
 
 
 def ufss_plan_set_phasor_tables(plan, enable):

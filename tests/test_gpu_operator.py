@@ -202,7 +202,8 @@ def test_manual_tiling_same_operator(dtype, dev):
     plan = u.Plan(g, 20, True, bins, dtype=u.F32 if dtype == "f32" else u.BF16)
     tilings = [(1, 1, 1, 1, 2, 2), (3, 2, 2, 3, 4, 4), (9, 9, 8, 10, 4, 2), (64, 64, 3, 64, 2, 4)]
     if dtype == "bf16":
-        tilings = [(t[0], t[1], 0, 1, 0, 0) for t in tilings]
+        rows = [(1, 1), (2, 2), (1, 2), (2, 1)]
+        tilings = [(t[0], t[1], 0, 1, 0, 0) + rows[n] for n, t in enumerate(tilings)]
     xt = torch.from_numpy(x).to(dev)
     yt = torch.from_numpy(y).to(dev)
     for t in tilings:
@@ -211,6 +212,8 @@ def test_manual_tiling_same_operator(dtype, dev):
         assert info["fwd_split"] == t[0] and info["adj_split"] == t[1]
         if dtype == "f32":
             assert (info["fwd_tile"], info["adj_tile"], info["fwd_zsplit"]) == (t[4], t[5], t[3])
+        else:
+            assert (info["fwd_rows"], info["adj_rows"]) == (t[6], t[7])
         yo = torch.empty_like(yt)
         xo = torch.empty_like(xt)
         u.ufss_forward(plan, xt, yo)
@@ -219,7 +222,7 @@ def test_manual_tiling_same_operator(dtype, dev):
         ey, ex = errs(yo.cpu().numpy(), y_ref), errs(xo.cpu().numpy(), x_ref)
         assert max(ey) < tol and max(ex) < tol, (t, ey, ex)
     for bad in [(-1, 0, 0, 0, 0, 0), (65, 0, 0, 0, 0, 0), (0, 0, 9, 0, 0, 0), (0, 0, 0, 65, 0, 0),
-                (0, 0, 0, 0, 3, 0), (0, 0, 0, 0, 0, 8)]:
+                (0, 0, 0, 0, 3, 0), (0, 0, 0, 0, 0, 8), (0, 0, 0, 0, 0, 0, 3, 0), (0, 0, 0, 0, 0, 0, 0, -1)]:
         with pytest.raises(u.UfssError):
             u.ufss_plan_set_tiling(plan, *bad)
     plan.close()
