@@ -42,6 +42,7 @@ TRAFFIC = {
     "cscan32/gemm/adjoint/as12-np2": {"bytes": 32.305e6, "sha": "a33f4ddbf68a0273"},
 }
 TRAFFIC_SRC = {"gemm": "paper_2012_04534_amd/csrc/gemm_f32.hip",
+               "gemm-bf16": "paper_2012_04534_amd/csrc/gemm_bf16.hip",
                "phasor": "paper_2012_04534_amd/csrc/phasor.hip"}
 
 
@@ -52,6 +53,9 @@ def source_sha(rel):
 
 
 def tiling_key(info, direction):
+    if info["dtype"] == 1:          # BF16: d_y split and wave rows
+        return ("as%d-wr%d" % (info["adj_split"], info["adj_rows"]) if direction == "adjoint"
+                else "fs%d-wr%d" % (info["fwd_split"], info["fwd_rows"]))
     if direction == "adjoint":
         return "as%d-np%d" % (info["adj_split"], info["adj_tile"])
     return "fs%d-zs%d-nw%d-np%d" % (info["fwd_split"], info["fwd_zsplit"], info["fwd_waves"],
@@ -147,6 +151,10 @@ def time_to_accuracy(ufss, W, plan, g, w, bins, y, lam, L, t_l, dev):
     learned unrolled network (trained checkpoint, if present)."""
     import torch
     K = w["iters"]
+    own = None
+    if plan.info()["dtype"] != ufss.F32:      # the reference and the FP32 rows need an FP32 plan
+        own = plan = ufss.Plan(g, w["m"], w["per_position"], bins, dtype=ufss.F32)
+        ufss.ufss_autotune(plan, None, False, False)
     a_ref = torch.zeros((g["ny"], g["nx"], g["nz"]), dtype=torch.complex64, device=dev)
     ufss.ufss_fista(plan, y, lam, L, K, a_ref)
     out = {"reference": "plain FP32 FISTA iterate after %d iterations" % K,
@@ -213,6 +221,8 @@ def time_to_accuracy(ufss, W, plan, g, w, bins, y, lam, L, t_l, dev):
                                                          for k in warm_it],
                           "fista_from_zero_iters_to_level": [mean_iters(cold, j) for j in range(lv)]}
         net.close()
+    if own is not None:
+        own.close()
     return out
 
 
@@ -281,6 +291,8 @@ def main():
     ap.add_argument("--workload", default="cscan32")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true", help="skip time-to-accuracy and extras")
+    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16"],
+                    help="operator precision of the timed FISTA steps (default f32, the headline)")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file for the headline workload (read and written)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -319,21 +331,24 @@ def main():
     shape_y = (g["ny"], g["nx"], m)
     extras = {"algos": {}}
     # pick the operator algorithm by measurement (FP32)
-    algos = [ufss.ALGO_GEMM, ufss.ALGO_PHASOR] if per_pos else [ufss.ALGO_GEMM]
+    bf16 = args.dtype == "bf16"
+    pdt = ufss.BF16 if bf16 else ufss.F32
+    # the phasor algorithm is FP32 only
+    algos = [ufss.ALGO_GEMM, ufss.ALGO_PHASOR] if (per_pos and not bf16) else [ufss.ALGO_GEMM]
     xr = torch.from_numpy(W.cn(shape_x, 1).astype(np.complex64)).to(dev)
     yr = torch.empty(shape_y, dtype=torch.complex64, device=dev)
     xo = torch.empty_like(xr)
     best = None
     tuned = {}
     for algo in algos:
-        plan = ufss.Plan(g, m, per_pos, bins, algo=algo)
+        plan = ufss.Plan(g, m, per_pos, bins, algo=algo, dtype=pdt)
         if algo == ufss.ALGO_GEMM:
             tuned = dict(zip(("fwd_split", "adj_split"),
                              ufss.ufss_autotune(plan, args.tune_cache, args.tune_cache is not None,
                                                 args.tune_cache is not None)))
         tf = ev_time(lambda: ufss.ufss_forward(plan, xr, yr), 5)
         ta = ev_time(lambda: ufss.ufss_adjoint(plan, yr, xo), 5)
-        name = {ufss.ALGO_GEMM: "gemm", ufss.ALGO_PHASOR: "phasor"}[algo]
+        name = {ufss.ALGO_GEMM: "gemm-bf16" if bf16 else "gemm", ufss.ALGO_PHASOR: "phasor"}[algo]
         extras["algos"][name] = {"forward_ms": round(tf, 4), "adjoint_ms": round(ta, 4),
                                  "a_plus_ah_gflops": round(flop_pair / ((tf + ta) * 1e-3) / 1e9, 1)}
         if best is None or tf + ta < best[1]:
@@ -342,7 +357,7 @@ def main():
     algo, _, algo_name = best
     torch.cuda.synchronize()
     t_plan = time.perf_counter()
-    plan = ufss.Plan(g, m, per_pos, bins, algo=algo)
+    plan = ufss.Plan(g, m, per_pos, bins, algo=algo, dtype=pdt)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t_plan
     extras["plan_build_s"] = round(t_plan, 4)
@@ -390,7 +405,7 @@ def main():
                 "peak": 157.3, "unit": "TFLOP/s"}
     else:
         roof = {"bound": "mfma", "achieved": round(8.0 * cmac / (k_ms * 1e-3) / 1e12, 3),
-                "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s"}
+                "peak": (PEAK_BF16_MFMA if bf16 else PEAK_FP32_MFMA) / 1e12, "unit": "TFLOP/s"}
     roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
     pinfo = plan.info()
     roof["traffic"] = traffic_bytes(args.workload, algo_name, dom, pinfo)
@@ -401,7 +416,7 @@ def main():
     result = {
         "metric": METRIC, "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
         "data": "synthetic",
         "config": {"workload": "%s: %dx%d scan positions, %dx%dx%d voxels, N_t=%d, M=%d %s bins, "
                                "%s window, %d scatterers%s, %g dB SNR, FISTA mu=%g" % (
