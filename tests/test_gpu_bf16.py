@@ -80,25 +80,6 @@ def test_bf16_small(ci, dev):
     plan.close()
 
 
-def test_bf16_cscan64_full_sampled(dev):
-    u = ufss()
-    w = W.workload("cscan64")
-    g = w["geom"]
-    bins, _ = u.ufss_select_freqs(g, w["m"], False, w["seed"])
-    x = W.cn((g["ny"], g["nx"], g["nz"]), 7)
-    y = W.cn((g["ny"], g["nx"], w["m"]), 8)
-    plan = u.Plan(g, w["m"], False, bins, dtype=u.BF16)
-    yo, xo = apply_both(u, plan, x, y, dev)
-    pos = [(0, 0), (63, 63), (31, 32), (5, 60)]
-    cols = [(0, 63), (40, 17)]
-    y_ref = np.stack([O.apply_A_at(g, bins, x, py, px) for (py, px) in pos])
-    x_ref = np.stack([O.apply_AH_at(g, bins, y, vy, vx) for (vy, vx) in cols])
-    ey = errs(np.stack([yo[py, px] for (py, px) in pos]), y_ref)
-    ex = errs(np.stack([xo[vy, vx] for (vy, vx) in cols]), x_ref)
-    assert max(ey) < TOL16 and max(ex) < TOL16, (ey, ex)
-    plan.close()
-
-
 def test_precision_study_subvolume(dev, record_property):
     """64 x 64 C-scan physics (same 128 bins and window start) on sub-volumes:
     the operator on 16 x 16 x 128 (outputs sampled one position / voxel column

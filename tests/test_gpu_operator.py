@@ -139,9 +139,21 @@ def test_bscan_workload_full(dev):
     plan.close()
 
 
-@pytest.mark.parametrize("name", ["cscan32", "cscan64"])
-def test_cscan_workloads_full_sampled(name, dev):
-    """Full-size C-scan workloads, in the bench's launch configuration, checked
+# Tilings the autotuner chose for these workloads on MI355X (fwd_split, adj_split,
+# fwd_waves, fwd_zsplit, fwd_tile, adj_tile, fwd_rows, adj_rows); the bench runs
+# the autotuned configuration, so each workload is checked at the plan's default
+# tiling and at these.
+BENCH_TILINGS = {
+    ("cscan32", "f32"): [(4, 12, 5, 8, 2, 2, 0, 0)],
+    ("cscan64", "f32"): [(12, 3, 8, 8, 4, 4, 0, 0)],
+    ("cscan32", "bf16"): [(24, 24, 0, 1, 0, 0, 2, 1)],
+    ("cscan64", "bf16"): [(16, 4, 0, 1, 0, 0, 1, 1)],
+}
+
+
+@pytest.mark.parametrize("name,dtype", sorted(BENCH_TILINGS))
+def test_cscan_workloads_full_sampled(name, dtype, dev):
+    """Full-size C-scan workloads, in the bench's launch configurations, checked
     on positions / voxel columns the oracle evaluates one at a time (corners,
     edges and the centre)."""
     u = ufss()
@@ -156,18 +168,27 @@ def test_cscan_workloads_full_sampled(name, dev):
     cols = [(0, nx - 1), (ny // 2 + 1, nx // 2 - 2)]
     y_ref = np.stack([O.apply_A_at(g, bins, x, py, px) for (py, px) in pos])
     x_ref = np.stack([O.apply_AH_at(g, bins, y, vy, vx) for (vy, vx) in cols])
-    for algo in algos(w["per_position"]):
-        plan = u.Plan(g, m, w["per_position"], bins, algo=algo)
-        yt = run_op(plan, x, y.shape, dev)
+    tol = TOL32 if dtype == "f32" else 1e-2
+    runs = [(u.ALGO_GEMM, None)] + [(u.ALGO_GEMM, t) for t in BENCH_TILINGS[(name, dtype)]]
+    if dtype == "f32" and w["per_position"]:
+        runs.append((u.ALGO_PHASOR, None))
+    xd = torch.from_numpy(x).to(dev)
+    yd = torch.from_numpy(y).to(dev)
+    for algo, tiling in runs:
+        plan = u.Plan(g, m, w["per_position"], bins, algo=algo, dtype=u.F32 if dtype == "f32" else u.BF16)
+        if tiling is not None:
+            u.ufss_plan_set_tiling(plan, *tiling)
+        yt = torch.empty(y.shape, dtype=torch.complex64, device=dev)
         xt = torch.empty(x.shape, dtype=torch.complex64, device=dev)
-        u.ufss_adjoint(plan, torch.from_numpy(y).to(dev), xt)
+        u.ufss_forward(plan, xd, yt)
+        u.ufss_adjoint(plan, yd, xt)
         torch.cuda.synchronize()
         yg = yt.cpu().numpy()
         xg = xt.cpu().numpy()
         ey = errs(np.stack([yg[py, px] for (py, px) in pos]), y_ref)
         ex = errs(np.stack([xg[vy, vx] for (vy, vx) in cols]), x_ref)
-        assert max(ey) < TOL32, (name, algo, ey)
-        assert max(ex) < TOL32, (name, algo, ex)
+        assert max(ey) < tol, (name, dtype, algo, tiling, ey)
+        assert max(ex) < tol, (name, dtype, algo, tiling, ex)
         plan.close()
 
 
