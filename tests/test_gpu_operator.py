@@ -247,3 +247,37 @@ def test_manual_tiling_same_operator(dtype, dev):
         with pytest.raises(u.UfssError):
             u.ufss_plan_set_tiling(plan, *bad)
     plan.close()
+
+
+@pytest.mark.parametrize("name,dtype", sorted(BENCH_TILINGS))
+def test_full_size_frobenius_hutchinson(name, dtype, dev):
+    """Whole operator at full size, bench tiling: for x ~ CN(0, I), E||A x||^2 =
+    ||A||_F^2 and likewise E||A^H y||^2 (Hutchinson), with ||A||_F^2 counted
+    in closed form by the oracle.  The tolerance is four standard errors of
+    the sample mean (at least 0.5%): a wrong scale, a missing block of terms
+    or a dropped factor moves the mean by far more."""
+    u = ufss()
+    w = W.workload(name)
+    g = w["geom"]
+    m = w["m"]
+    bins, _ = u.ufss_select_freqs(g, m, w["per_position"], w["seed"])
+    fro = O.frobenius_sq(g, bins)
+    plan = u.Plan(g, m, w["per_position"], bins, dtype=u.F32 if dtype == "f32" else u.BF16)
+    u.ufss_plan_set_tiling(plan, *BENCH_TILINGS[(name, dtype)][0])
+    gen = torch.Generator(device=dev).manual_seed(11)
+    shx, shy = (g["ny"], g["nx"], g["nz"]), (g["ny"], g["nx"], m)
+    ax, ahy = [], []
+    yo = torch.empty(shy, dtype=torch.complex64, device=dev)
+    xo = torch.empty(shx, dtype=torch.complex64, device=dev)
+    n = 32
+    for _ in range(n):
+        x = torch.randn(shx, dtype=torch.complex64, device=dev, generator=gen)
+        y = torch.randn(shy, dtype=torch.complex64, device=dev, generator=gen)
+        u.ufss_forward(plan, x, yo)
+        u.ufss_adjoint(plan, y, xo)
+        ax.append(float((yo.abs() ** 2).sum().item()))
+        ahy.append(float((xo.abs() ** 2).sum().item()))
+    plan.close()
+    for v in (np.array(ax), np.array(ahy)):
+        tol = max(0.005, 4 * v.std(ddof=1) / np.sqrt(n) / fro)
+        assert abs(v.mean() / fro - 1) < tol, (v.mean(), fro, tol)

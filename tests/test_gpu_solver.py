@@ -193,3 +193,20 @@ def test_fista_per_position_small(algo_name, dev):
     err = np.linalg.norm(x.cpu().numpy().reshape(-1) - a_ref) / np.linalg.norm(a_ref)
     assert err < 1e-5, err
     plan.close()
+
+
+@pytest.mark.parametrize("mu", [1.0, 2.5])
+def test_mu_at_least_one_keeps_zero_iterate(mu, dev):
+    """lambda = mu max|A^H y| with mu >= 1: the soft threshold removes every
+    entry of the first step from a = 0, so all iterates stay exactly zero."""
+    u = ufss()
+    w, g, bins, A, _, y = bscan_problem()
+    plan = u.Plan(g, w["m"], False, bins)
+    L = float(V.lipschitz_dense(A))
+    yt = to_dev(y.reshape(g["ny"], g["nx"], w["m"]), dev)
+    x = torch.zeros((g["ny"], g["nx"], g["nz"]), dtype=torch.complex64, device=dev)
+    st = u.ufss_fista(plan, yt, u.lambda_from_mu(mu), L, 5, x)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(x).item() == 0
+    assert st["lambda"] > 0
+    plan.close()
