@@ -57,9 +57,9 @@ def tiling_key(info, direction):
         return ("as%d-wr%d" % (info["adj_split"], info["adj_rows"]) if direction == "adjoint"
                 else "fs%d-wr%d" % (info["fwd_split"], info["fwd_rows"]))
     if direction == "adjoint":
-        return "as%d-np%d" % (info["adj_split"], info["adj_tile"])
-    return "fs%d-zs%d-nw%d-np%d" % (info["fwd_split"], info["fwd_zsplit"], info["fwd_waves"],
-                                    info["fwd_tile"])
+        return "as%d-np%d-kc%d" % (info["adj_split"], info["adj_tile"], info["adj_chunk"])
+    return "fs%d-zs%d-nw%d-np%d-zc%d" % (info["fwd_split"], info["fwd_zsplit"], info["fwd_waves"],
+                                         info["fwd_tile"], info["fwd_chunk"])
 
 
 def traffic_bytes(workload, algo_name, direction, info):

@@ -86,6 +86,8 @@ typedef struct ufss_plan_info {
                                             per wave (0 elsewhere)             */
     int32_t fwd_rows, adj_rows;          /* BF16 GEMMs: rows of waves in a
                                             tile (0 elsewhere)                 */
+    int32_t fwd_chunk, adj_chunk;        /* FP32 GEMMs: staged depth / bin
+                                            chunk (0 elsewhere)                */
     int32_t phasor_tables;               /* 1: BF16 phasor tables in use       */
 } ufss_plan_info;
 
@@ -237,24 +239,32 @@ int ufss_fista_batched(int32_t n, const ufss_plan_t* plans, const void* const* y
 int ufss_autotune(ufss_plan_t plan, const char* cache_path, int32_t flags,
                   int32_t* fwd_split_out, int32_t* adj_split_out, ufss_stream_t stream);
 
-/* Manual tiling of the GEMM path (the choice ufss_autotune makes by timing):
+/* Tiling of the GEMM path (what ufss_autotune chooses by timing).  In
+ * ufss_plan_set_tiling a field of 0 keeps the plan's current value.
  *   fwd_split   parts of the forward GEMM's d_y range, 1..64
  *   adj_split   parts of the adjoint GEMM's d_y range, 1..64
- *   fwd_waves   16-bin sub-tiles (waves) per forward FP32 workgroup, 1..8
- *   fwd_zsplit  parts of the forward FP32 GEMM's depth range, 1..64
- *   fwd_tile, adj_tile  FP32 GEMMs: 16-position sub-tiles per wave, 2 or 4
- *   fwd_rows, adj_rows  BF16 GEMMs: rows of waves in a tile, 1 or 2 (2: half
- *               as wide and twice as tall; C-scans only)
- * A value of 0 keeps the plan's current one.  Any valid setting computes the
- * same operator; parts that receive no rows contribute zeros.  BF16 plans
- * accept only 0 or 1 for fwd_zsplit and ignore fwd_waves, fwd_tile and
- * adj_tile; FP32 plans ignore fwd_rows and adj_rows.  Reallocates the plan's
+ *   fwd_waves   FP32 forward: 16-bin sub-tiles (waves) per workgroup, 1..8
+ *   fwd_zsplit  FP32 forward: parts of the depth range, 1..64
+ *   fwd_tile, adj_tile    FP32: 16-position sub-tiles per wave, 2 or 4
+ *   fwd_rows, adj_rows    BF16: rows of waves in a tile, 1 or 2 (2: half as
+ *               wide and twice as tall; C-scans only)
+ *   fwd_chunk, adj_chunk  FP32: depths (forward) or bins (adjoint) staged in
+ *               LDS per step, 16 or 8 (8 halves the halo and admits more
+ *               workgroups per CU; shrunk further if the window needs it)
+ * Any valid setting computes the same operator; parts that receive no rows
+ * contribute zeros.  BF16 plans accept only 0 or 1 for fwd_zsplit and ignore
+ * the FP32-only fields; FP32 plans ignore the rows.  Reallocates the plan's
  * split workspace (synchronises the device).  Errors: INVALID_ARG for values
- * out of range, UNSUPPORTED for phasor plans or a BF16 tile shape that does
- * not fit in LDS. */
-int ufss_plan_set_tiling(ufss_plan_t plan, int32_t fwd_split, int32_t adj_split,
-                         int32_t fwd_waves, int32_t fwd_zsplit, int32_t fwd_tile,
-                         int32_t adj_tile, int32_t fwd_rows, int32_t adj_rows);
+ * out of range or NULL, UNSUPPORTED for phasor plans or a BF16 tile shape that
+ * does not fit in LDS. */
+typedef struct ufss_tiling {
+    int32_t fwd_split, adj_split;
+    int32_t fwd_waves, fwd_zsplit;
+    int32_t fwd_tile, adj_tile;
+    int32_t fwd_rows, adj_rows;
+    int32_t fwd_chunk, adj_chunk;
+} ufss_tiling;
+int ufss_plan_set_tiling(ufss_plan_t plan, const ufss_tiling* tiling);
 
 /* BF16 GEMM plans: the BF16 phasors exp(-j 2 pi k tau f_s / N_t) of every
  * (|d_y|, |d_x|, z, selected bin) (paper Sec. IV-B: the operator depends on the

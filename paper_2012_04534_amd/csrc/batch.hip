@@ -505,12 +505,14 @@ int autotune(Plan& P, const char* cache_path, int flags, hipStream_t s, int32_t*
     const std::string key = shape_key(P);
     std::map<std::string, std::vector<double>> cache;
     if (cache_path && (flags & 1)) cache = read_cache(cache_path);
-    if (cache.count(key) && cache[key].size() >= 10) {
+    if (cache.count(key) && cache[key].size() >= 12) {
         P.fwd_nw = (int)cache[key][4];
         P.fwd_np = (int)cache[key][6];
         P.adj_np = (int)cache[key][7];
         P.bf_fwd_rows = (int)cache[key][8];
         P.bf_adj_rows = (int)cache[key][9];
+        P.fwd_zc = (int)cache[key][10];
+        P.adj_kc = (int)cache[key][11];
         plan_set_splits(P, (int)cache[key][0], (int)cache[key][1], (int)cache[key][5]);
     } else {
         const int tpy = P.g.ny == 1 ? 1 : 4;
@@ -554,6 +556,18 @@ int autotune(Plan& P, const char* cache_path, int flags, hipStream_t s, int32_t*
         P.fwd_nw = bnw;
         P.fwd_np = bnp;
         P.bf_fwd_rows = bfr;
+        // then the smaller depth chunk at that shape (FP32)
+        int bzc = 16;
+        if (P.dtype == UFSS_F32 && !quick) {
+            for (int c : cand) {
+                if (c * bz > 96) continue;
+                P.fwd_zc = 8;
+                plan_set_splits(P, c, P.adj_split, bz);
+                double t = time_ms([&]() { op_forward(P, P.d_gamma, P.d_r, nullptr, nullptr, s); }, 3, s);
+                if (t < best_f) { best_f = t; bf = c; bzc = 8; }
+            }
+        }
+        P.fwd_zc = bzc;
         for (int wr : rows)
             for (int np : npc)
                 for (int c : cand) {
@@ -565,11 +579,22 @@ int autotune(Plan& P, const char* cache_path, int flags, hipStream_t s, int32_t*
                 }
         P.adj_np = bnpa;
         P.bf_adj_rows = bar;
+        // then the smaller bin chunk at that shape (FP32)
+        int bkc = 16;
+        if (P.dtype == UFSS_F32 && !quick) {
+            for (int c : cand) {
+                P.adj_kc = 8;
+                plan_set_splits(P, bf, c, bz);
+                double t = time_ms([&]() { op_adjoint(P, P.d_r, P.d_g, s); }, 3, s);
+                if (t < best_a) { best_a = t; ba = c; bkc = 8; }
+            }
+        }
+        P.adj_kc = bkc;
         plan_set_splits(P, bf, ba, bz);
         if (cache_path && (flags & 2)) {
             cache = read_cache(cache_path);
             cache[key] = {(double)bf, (double)ba, best_f, best_a, (double)bnw, (double)bz, (double)bnp,
-                          (double)bnpa, (double)bfr, (double)bar};
+                          (double)bnpa, (double)bfr, (double)bar, (double)bzc, (double)bkc};
             write_cache(cache_path, cache);
         }
     }

@@ -366,32 +366,36 @@ int ufss_autotune(ufss_plan_t plan, const char* cache_path, int32_t flags, int32
     UFSS_GUARD_END
 }
 
-int ufss_plan_set_tiling(ufss_plan_t plan, int32_t fwd_split, int32_t adj_split, int32_t fwd_waves,
-                         int32_t fwd_zsplit, int32_t fwd_tile, int32_t adj_tile, int32_t fwd_rows,
-                         int32_t adj_rows) {
+int ufss_plan_set_tiling(ufss_plan_t plan, const ufss_tiling* t) {
     UFSS_GUARD_BEGIN
     Plan* P = as_plan(plan);
+    if (!t) ufss::fail(UFSS_ERR_INVALID_ARG, "tiling is NULL");
     if (P->algo != UFSS_ALGO_GEMM) ufss::fail(UFSS_ERR_UNSUPPORTED, "tiling applies to GEMM plans only");
     auto in = [](int v, int hi) { return v >= 0 && v <= hi; };
-    auto tile_ok = [](int v) { return v == 0 || v == 2 || v == 4; };
-    if (!in(fwd_split, 64) || !in(adj_split, 64) || !in(fwd_waves, 8) || !in(fwd_zsplit, 64) ||
-        !tile_ok(fwd_tile) || !tile_ok(adj_tile) || !in(fwd_rows, 2) || !in(adj_rows, 2))
+    auto one_of = [](int v, int a, int b) { return v == 0 || v == a || v == b; };
+    if (!in(t->fwd_split, 64) || !in(t->adj_split, 64) || !in(t->fwd_waves, 8) || !in(t->fwd_zsplit, 64) ||
+        !one_of(t->fwd_tile, 2, 4) || !one_of(t->adj_tile, 2, 4) || !in(t->fwd_rows, 2) ||
+        !in(t->adj_rows, 2) || !one_of(t->fwd_chunk, 8, 16) || !one_of(t->adj_chunk, 8, 16))
         ufss::fail(UFSS_ERR_INVALID_ARG, "tiling value out of range");
-    if (P->dtype == UFSS_BF16 && fwd_zsplit > 1)
+    if (P->dtype == UFSS_BF16 && t->fwd_zsplit > 1)
         ufss::fail(UFSS_ERR_INVALID_ARG, "the BF16 forward GEMM does not split depth");
-    if (fwd_waves > 0 && P->dtype == UFSS_F32) P->fwd_nw = fwd_waves;
-    if (fwd_tile > 0 && P->dtype == UFSS_F32) P->fwd_np = fwd_tile;
-    if (adj_tile > 0 && P->dtype == UFSS_F32) P->adj_np = adj_tile;
-    if (P->dtype == UFSS_BF16 && (fwd_rows > 0 || adj_rows > 0)) {
-        const int fr = fwd_rows > 0 ? fwd_rows : P->bf_fwd_rows, ar = adj_rows > 0 ? adj_rows : P->bf_adj_rows;
+    if (P->dtype == UFSS_F32) {
+        if (t->fwd_waves > 0) P->fwd_nw = t->fwd_waves;
+        if (t->fwd_tile > 0) P->fwd_np = t->fwd_tile;
+        if (t->adj_tile > 0) P->adj_np = t->adj_tile;
+        if (t->fwd_chunk > 0) P->fwd_zc = t->fwd_chunk;
+        if (t->adj_chunk > 0) P->adj_kc = t->adj_chunk;
+    } else if (t->fwd_rows > 0 || t->adj_rows > 0) {
+        const int fr = t->fwd_rows > 0 ? t->fwd_rows : P->bf_fwd_rows;
+        const int ar = t->adj_rows > 0 ? t->adj_rows : P->bf_adj_rows;
         if (!ufss::bf16_rows_ok(*P, fr, ar))
             ufss::fail(UFSS_ERR_UNSUPPORTED, "this BF16 tile shape does not fit the grid or LDS");
         P->bf_fwd_rows = fr;
         P->bf_adj_rows = ar;
     }
-    ufss::plan_set_splits(*P, fwd_split > 0 ? fwd_split : P->fwd_split,
-                          adj_split > 0 ? adj_split : P->adj_split,
-                          fwd_zsplit > 0 ? fwd_zsplit : P->fwd_zsplit);
+    ufss::plan_set_splits(*P, t->fwd_split > 0 ? t->fwd_split : P->fwd_split,
+                          t->adj_split > 0 ? t->adj_split : P->adj_split,
+                          t->fwd_zsplit > 0 ? t->fwd_zsplit : P->fwd_zsplit);
     UFSS_GUARD_END
 }
 

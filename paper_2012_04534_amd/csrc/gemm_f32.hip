@@ -375,6 +375,16 @@ __global__ __launch_bounds__(256) void adj_gemm_f32_kernel(AdjArgs a) {
     adj_f32_body<NP, NZ, KC>(a, blockIdx.x, gridDim.x, smem);
 }
 
+// Two sub-tiles per wave: registers capped for 6 waves per SIMD, which pays
+// when a small LDS chunk admits that many workgroups per CU (measured on the
+// 32 x 32 and 64 x 64 C-scans).
+template <int NZ, int KC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8)))
+void adj_gemm_f32_kernel_np2(AdjArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    adj_f32_body<2, NZ, KC>(a, blockIdx.x, gridDim.x, smem);
+}
+
 // Grouped launch: block -> (plan index, block index inside that plan's grid).
 template <int NP, int NZ>
 __global__ __launch_bounds__(256) void adj_gemm_f32_kernel_grouped(const AdjArgs* __restrict__ descs,
@@ -394,6 +404,23 @@ static constexpr int kGroupNP = 2;   // grouped (batched) launches: one shape fo
 
 int fwd_tile_np(const Plan& P) { return P.fwd_np == 4 ? 4 : 2; }
 int adj_tile_np(const Plan& P) { return P.adj_np == 4 ? 4 : 2; }
+
+static int fwd_args(const Plan& P, const cf32* x, FwdArgs& a, size_t& lds, int np);
+static int adj_args(const Plan& P, cf32* out, AdjArgs& a, size_t& lds, int np);
+
+int fwd_chunk(const Plan& P) {
+    FwdArgs a;
+    size_t lds;
+    fwd_args(P, nullptr, a, lds, fwd_tile_np(P));
+    return a.zc;
+}
+
+int adj_chunk(const Plan& P) {
+    AdjArgs a;
+    size_t lds;
+    adj_args(P, nullptr, a, lds, adj_tile_np(P));
+    return a.kc;
+}
 static constexpr int kAdjNZ = 1;
 static constexpr size_t kLdsMax = 64 * 1024;
 
@@ -449,7 +476,7 @@ static int fwd_args(const Plan& P, const cf32* x, FwdArgs& a, size_t& lds, int n
     a.split = P.fwd_split;
     a.npos = P.npos;
     const int hc = tpx + 2 * a.wx;
-    int zc = 16;
+    int zc = P.fwd_zc == 8 ? 8 : 16;
     auto lds_of = [&](int z) {
         return (size_t)tpy * hc * (z + 1) * sizeof(cf32) + (size_t)(a.wx + 1) * z * 4;
     };
@@ -481,7 +508,7 @@ static int adj_args(const Plan& P, cf32* out, AdjArgs& a, size_t& lds, int np) {
     const int zspan = 64 * kAdjNZ;
     a.nzt = (a.nz + zspan - 1) / zspan;
     const int hc = tpx + 2 * a.wx;
-    int kc = 16;
+    int kc = P.adj_kc == 8 ? 8 : 16;
     auto lds_of = [&](int k) {
         return (size_t)tpy * hc * (k + 1) * sizeof(cf32) + (size_t)(a.wx + 1) * zspan * 4 +
                (size_t)k * 4;
@@ -520,11 +547,13 @@ void launch_adjoint_gemm(const Plan& P, cf32* out, hipStream_t s, bool sum) {
     adj_args(P, out, a, lds, np);
     const dim3 grid(a.nblk), block(256);
 #define UFSS_ADJ(NPV, KCV) hipLaunchKernelGGL((adj_gemm_f32_kernel<NPV, kAdjNZ, KCV>), grid, block, lds, s, a)
+#define UFSS_ADJ2(KCV) hipLaunchKernelGGL((adj_gemm_f32_kernel_np2<kAdjNZ, KCV>), grid, block, lds, s, a)
     if (np == 4) {
         if (a.kc == 16) UFSS_ADJ(4, 16); else if (a.kc == 8) UFSS_ADJ(4, 8); else UFSS_ADJ(4, 4);
     } else {
-        if (a.kc == 16) UFSS_ADJ(2, 16); else if (a.kc == 8) UFSS_ADJ(2, 8); else UFSS_ADJ(2, 4);
+        if (a.kc == 16) UFSS_ADJ2(16); else if (a.kc == 8) UFSS_ADJ2(8); else UFSS_ADJ2(4);
     }
+#undef UFSS_ADJ2
 #undef UFSS_ADJ
     UFSS_HIP(hipGetLastError());
     if (a.split > 1 && sum) launch_sum_parts(P.d_gpart, a.split, P.nvox, out, s);

@@ -65,6 +65,7 @@ struct Plan {
                                    // (raw output holds fwd_split * fwd_zsplit partials)
     int fwd_np = 2, adj_np = 2;    // FP32 GEMMs: 16-position sub-tiles per wave (2 or 4)
     int bf_fwd_rows = 1, bf_adj_rows = 1;   // BF16 GEMMs: rows of waves in a tile (1 or 2)
+    int fwd_zc = 16, adj_kc = 16;  // FP32 GEMMs: preferred staged depth / bin chunk (16 or 8)
     int adj_split = 1;             // split of the adjoint GEMM's d_y range
     cf32* d_gpart = nullptr;       // adjoint partials [adj_split][nvox] (adj_split > 1)
     std::vector<int> bins_h;       // [m] or [npos*m]
@@ -119,6 +120,9 @@ void plan_set_splits(Plan& P, int fs, int as, int zs);
 // Lateral tile shape of the FP32 GEMMs (sub-tiles per wave, 2 or 4).
 int fwd_tile_np(const Plan& P);
 int adj_tile_np(const Plan& P);
+// The staged chunk the FP32 GEMMs actually use (the preference, halved until LDS fits).
+int fwd_chunk(const Plan& P);
+int adj_chunk(const Plan& P);
 // Grouped GEMM launches: one grid runs the tiles of many plans.  A descriptor
 // is the kernel's argument block for one plan (opaque bytes of desc_size);
 // blk[b] = {plan index, block index inside that plan's own grid}.

@@ -329,6 +329,8 @@ void plan_info(const Plan* P, ufss_plan_info* info) {
     const bool bf_gemm = P->algo == UFSS_ALGO_GEMM && P->dtype == UFSS_BF16;
     info->fwd_rows = bf_gemm ? P->bf_fwd_rows : 0;
     info->adj_rows = bf_gemm ? P->bf_adj_rows : 0;
+    info->fwd_chunk = f32_gemm ? fwd_chunk(*P) : 0;
+    info->adj_chunk = f32_gemm ? adj_chunk(*P) : 0;
 }
 
 }  // namespace ufss

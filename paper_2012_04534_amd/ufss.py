@@ -65,8 +65,16 @@ class PlanInfo(ctypes.Structure):
         ("fwd_waves", ctypes.c_int32), ("fwd_zsplit", ctypes.c_int32),
         ("fwd_tile", ctypes.c_int32), ("adj_tile", ctypes.c_int32),
         ("fwd_rows", ctypes.c_int32), ("adj_rows", ctypes.c_int32),
+        ("fwd_chunk", ctypes.c_int32), ("adj_chunk", ctypes.c_int32),
         ("phasor_tables", ctypes.c_int32),
     ]
+
+
+class Tiling(ctypes.Structure):
+    """GEMM tiling (ufss_tiling); 0 keeps the plan's current value."""
+    _fields_ = [(f, ctypes.c_int32) for f in (
+        "fwd_split", "adj_split", "fwd_waves", "fwd_zsplit", "fwd_tile", "adj_tile",
+        "fwd_rows", "adj_rows", "fwd_chunk", "adj_chunk")]
 
 
 class FistaStats(ctypes.Structure):
@@ -113,7 +121,7 @@ def lib():
                                    ctypes.c_int),
             "ufss_autotune": ([P, ctypes.c_char_p, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), P],
                               ctypes.c_int),
-            "ufss_plan_set_tiling": ([P, I32, I32, I32, I32, I32, I32, I32, I32], ctypes.c_int),
+            "ufss_plan_set_tiling": ([P, ctypes.POINTER(Tiling)], ctypes.c_int),
             "ufss_plan_set_phasor_tables": ([P, I32, ctypes.POINTER(I32)], ctypes.c_int),
             "ufss_unrolled_create": ([P, I32, I32, D, D, U64, ctypes.POINTER(P)], ctypes.c_int),
             "ufss_unrolled_destroy": ([P], ctypes.c_int),
@@ -322,12 +330,18 @@ def ufss_autotune(plan, cache_path=None, use_cache=True, write_cache=True, strea
     return fs.value, asp.value
 
 
-def ufss_plan_set_tiling(plan, fwd_split=0, adj_split=0, fwd_waves=0, fwd_zsplit=0, fwd_tile=0,
-                         adj_tile=0, fwd_rows=0, adj_rows=0):
-    """Manual GEMM tiling (0 keeps the current value); see ufss_autotune."""
-    _check(lib().ufss_plan_set_tiling(plan.handle, int(fwd_split), int(adj_split), int(fwd_waves),
-                                      int(fwd_zsplit), int(fwd_tile), int(adj_tile), int(fwd_rows),
-                                      int(adj_rows)))
+def ufss_plan_set_tiling(plan, *values, **fields):
+    """Manual GEMM tiling: values in ufss_tiling's field order and/or by name;
+    0 (or absent) keeps the plan's current value.  See ufss_autotune."""
+    names = [f for f, _ in Tiling._fields_]
+    if len(values) > len(names):
+        raise TypeError("at most %d tiling values" % len(names))
+    t = Tiling()
+    for f, v in list(zip(names, values)) + list(fields.items()):
+        if f not in names:
+            raise TypeError("unknown tiling field " + f)
+        setattr(t, f, int(v))
+    _check(lib().ufss_plan_set_tiling(plan.handle, ctypes.byref(t)))
 
 
 def ufss_plan_set_phasor_tables(plan, enable):

@@ -92,7 +92,8 @@ def header_struct_fields(name):
 
 @pytest.mark.parametrize("cname,pyname", [("ufss_geom", "Geom"), ("ufss_plan_info", "PlanInfo"),
                                            ("ufss_fista_stats", "FistaStats"),
-                                           ("ufss_fista_state", "FistaState")])
+                                           ("ufss_fista_state", "FistaState"),
+                                           ("ufss_tiling", "Tiling")])
 def test_binding_structs_match_header(cname, pyname):
     """The ctypes mirrors of the C structs list the same fields in the same order."""
     cls = getattr(ufss, pyname)

@@ -221,10 +221,13 @@ def test_manual_tiling_same_operator(dtype, dev):
     x_ref = (A.conj().T @ y.reshape(-1).astype(np.complex128)).reshape(x.shape)
     tol = TOL32 if dtype == "f32" else 1e-2
     plan = u.Plan(g, 20, True, bins, dtype=u.F32 if dtype == "f32" else u.BF16)
-    tilings = [(1, 1, 1, 1, 2, 2), (3, 2, 2, 3, 4, 4), (9, 9, 8, 10, 4, 2), (64, 64, 3, 64, 2, 4)]
+    # (fwd_split, adj_split, fwd_waves, fwd_zsplit, fwd_tile, adj_tile, fwd_rows,
+    #  adj_rows, fwd_chunk, adj_chunk)
+    tilings = [(1, 1, 1, 1, 2, 2, 0, 0, 16, 16), (3, 2, 2, 3, 4, 4, 0, 0, 8, 8),
+               (9, 9, 8, 10, 4, 2, 0, 0, 16, 8), (64, 64, 3, 64, 2, 4, 0, 0, 8, 16)]
     if dtype == "bf16":
         rows = [(1, 1), (2, 2), (1, 2), (2, 1)]
-        tilings = [(t[0], t[1], 0, 1, 0, 0) + rows[n] for n, t in enumerate(tilings)]
+        tilings = [(t[0], t[1], 0, 1, 0, 0) + rows[n] + (0, 0) for n, t in enumerate(tilings)]
     xt = torch.from_numpy(x).to(dev)
     yt = torch.from_numpy(y).to(dev)
     for t in tilings:
@@ -233,6 +236,7 @@ def test_manual_tiling_same_operator(dtype, dev):
         assert info["fwd_split"] == t[0] and info["adj_split"] == t[1]
         if dtype == "f32":
             assert (info["fwd_tile"], info["adj_tile"], info["fwd_zsplit"]) == (t[4], t[5], t[3])
+            assert (info["fwd_chunk"], info["adj_chunk"]) == (t[8], t[9])
         else:
             assert (info["fwd_rows"], info["adj_rows"]) == (t[6], t[7])
         yo = torch.empty_like(yt)
@@ -243,7 +247,8 @@ def test_manual_tiling_same_operator(dtype, dev):
         ey, ex = errs(yo.cpu().numpy(), y_ref), errs(xo.cpu().numpy(), x_ref)
         assert max(ey) < tol and max(ex) < tol, (t, ey, ex)
     for bad in [(-1, 0, 0, 0, 0, 0), (65, 0, 0, 0, 0, 0), (0, 0, 9, 0, 0, 0), (0, 0, 0, 65, 0, 0),
-                (0, 0, 0, 0, 3, 0), (0, 0, 0, 0, 0, 8), (0, 0, 0, 0, 0, 0, 3, 0), (0, 0, 0, 0, 0, 0, 0, -1)]:
+                (0, 0, 0, 0, 3, 0), (0, 0, 0, 0, 0, 8), (0, 0, 0, 0, 0, 0, 3, 0), (0, 0, 0, 0, 0, 0, 0, -1),
+                (0, 0, 0, 0, 0, 0, 0, 0, 4, 0), (0, 0, 0, 0, 0, 0, 0, 0, 0, 12)]:
         with pytest.raises(u.UfssError):
             u.ufss_plan_set_tiling(plan, *bad)
     plan.close()
