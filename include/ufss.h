@@ -321,6 +321,18 @@ int ufss_unrolled_train_step(ufss_net_t net, int32_t batch, const void* const* y
 int ufss_unrolled_save(ufss_net_t net, const char* path);
 int ufss_unrolled_load(ufss_net_t net, const char* path);
 
+/* Kernel timing mode.  While enabled, every forward / adjoint core kernel
+ * launch of this plan (the windowed GEMM or the phasor kernel, without the
+ * gather, scatter and split-sum passes) is bracketed by two HIP events
+ * recorded on its launch stream; enabling clears earlier records, at most 4096
+ * launches per direction are kept.  Not for use under graph capture.
+ * ufss_plan_kernel_times synchronises on the recorded events and returns the
+ * average duration (ms) and the number of timed launches per direction
+ * (0 where none); all outputs HOST, optional. */
+int ufss_plan_kernel_timing(ufss_plan_t plan, int32_t enable);
+int ufss_plan_kernel_times(ufss_plan_t plan, double* fwd_ms, double* adj_ms, int32_t* fwd_n,
+                           int32_t* adj_n);
+
 /* Diagnostic: average duration (ms) of the operator's core kernel, launched
  * `reps` times back to back between two HIP events recorded on `stream`.
  * which = 0: forward core (windowed GEMM, or phasor forward), 1: adjoint core

@@ -37,18 +37,42 @@ void net_load(Net& N, const char* path);
 
 // y = A x (ymeas == NULL) or y = A x - ymeas.  If res2_out != NULL it receives
 // ||y||^2 (FP64, device scalar).
+// Kernel timing mode: an event pair around one core kernel launch.
+static constexpr int kMaxTimed = 4096;        // pairs kept per direction
+static void ktime_begin(Plan& P, int w, hipStream_t s) {
+    if (!P.ktime || P.kev_used[w] >= kMaxTimed) return;
+    auto& ev = P.kev[w];
+    while ((int)ev.size() < 2 * (P.kev_used[w] + 1)) {
+        hipEvent_t e;
+        UFSS_HIP(hipEventCreate(&e));
+        ev.push_back(e);
+    }
+    UFSS_HIP(hipEventRecord(ev[2 * P.kev_used[w]], s));
+}
+static void ktime_end(Plan& P, int w, hipStream_t s) {
+    if (!P.ktime || P.kev_used[w] >= kMaxTimed) return;
+    UFSS_HIP(hipEventRecord(P.kev[w][2 * P.kev_used[w] + 1], s));
+    ++P.kev_used[w];
+}
+
 void op_forward(Plan& P, const cf32* x, cf32* y, const cf32* ymeas, double* res2_out,
                 hipStream_t s) {
     if (P.algo == UFSS_ALGO_PHASOR) {
+        ktime_begin(P, 0, s);
         launch_forward_phasor(P, x, y, ymeas, P.d_part, s);
+        ktime_end(P, 0, s);
         if (res2_out) launch_reduce(P.d_part, phasor_forward_blocks(P), 1, res2_out, s);
         return;
     }
     if (P.dtype == UFSS_BF16) {
         launch_to_bf16(x, P.d_xop, P.nvox, s);
+        ktime_begin(P, 0, s);
         launch_forward_gemm_bf16(P, s);
+        ktime_end(P, 0, s);
     } else {
+        ktime_begin(P, 0, s);
         launch_forward_gemm(P, x, s);
+        ktime_end(P, 0, s);
     }
     int nb = launch_forward_post(P, y, ymeas, P.d_part, s);
     if (res2_out) launch_reduce(P.d_part, nb, 1, res2_out, s);
@@ -56,14 +80,18 @@ void op_forward(Plan& P, const cf32* x, cf32* y, const cf32* ymeas, double* res2
 
 int op_adjoint(Plan& P, const cf32* y, cf32* x, hipStream_t s, bool defer_sum) {
     launch_adjoint_pre(P, y, s);
+    ktime_begin(P, 1, s);
     if (P.algo == UFSS_ALGO_PHASOR) {
         launch_adjoint_phasor(P, x, s);
+        ktime_end(P, 1, s);
         return 1;
     }
     if (P.dtype == UFSS_BF16)
-        launch_adjoint_gemm_bf16(P, x, s, !defer_sum);
+        launch_adjoint_gemm_bf16(P, x, s, false);
     else
-        launch_adjoint_gemm(P, x, s, !defer_sum);
+        launch_adjoint_gemm(P, x, s, false);
+    ktime_end(P, 1, s);
+    if (P.adj_split > 1 && !defer_sum) launch_sum_parts(P.d_gpart, P.adj_split, P.nvox, x, s);
     return (defer_sum && P.adj_split > 1) ? P.adj_split : 1;
 }
 
@@ -101,18 +129,36 @@ double lipschitz(Plan& P, int max_iters, double rtol, double margin, uint64_t se
     int nb = launch_norm2(P.nvox, P.d_v, P.d_part, s);
     launch_reduce(P.d_part, nb, 2, nrm, s);
     launch_scale(P.nvox, P.d_v, nrm, s);
+    // Iterations run in blocks of 8 without a host round trip; the quotients
+    // of a block are then read and tested in order, and the first one that
+    // meets the test is the result (the extra iterations of the block only
+    // move the internal vector).
+    constexpr int kBlock = 8;
+    double* rho_dev = P.d_scalars + 48;                 // [kBlock]
     double rho = 0.0, rho_old = 0.0;
-    for (int it = 1; it <= max_iters; ++it) {
-        op_forward(P, P.d_v, P.d_r, nullptr, P.d_scalars + 34, s);   // rho = ||A v||^2
-        op_adjoint(P, P.d_r, P.d_g, s);
-        nb = launch_norm2(P.nvox, P.d_g, P.d_part, s);
-        launch_reduce(P.d_part, nb, 2, nrm, s);
-        launch_copy(P.nvox, P.d_g, P.d_v, s);
-        launch_scale(P.nvox, P.d_v, nrm, s);
-        rho = read_scalar(P.d_scalars + 34, s);
-        if (!std::isfinite(rho)) fail(UFSS_ERR_DIVERGED, "non-finite Rayleigh quotient");
-        if (rho_old > 0 && std::fabs(rho - rho_old) <= rtol * rho) break;
-        rho_old = rho;
+    bool done = false;
+    for (int it0 = 1; it0 <= max_iters && !done; it0 += kBlock) {
+        const int nit = std::min(kBlock, max_iters - it0 + 1);
+        for (int j = 0; j < nit; ++j) {
+            op_forward(P, P.d_v, P.d_r, nullptr, rho_dev + j, s);      // rho = ||A v||^2
+            op_adjoint(P, P.d_r, P.d_g, s);
+            nb = launch_norm2(P.nvox, P.d_g, P.d_part, s);
+            launch_reduce(P.d_part, nb, 2, nrm, s);
+            launch_copy(P.nvox, P.d_g, P.d_v, s);
+            launch_scale(P.nvox, P.d_v, nrm, s);
+        }
+        double h[kBlock];
+        UFSS_HIP(hipMemcpyAsync(h, rho_dev, nit * sizeof(double), hipMemcpyDeviceToHost, s));
+        sync(s);
+        for (int j = 0; j < nit; ++j) {
+            rho = h[j];
+            if (!std::isfinite(rho)) fail(UFSS_ERR_DIVERGED, "non-finite Rayleigh quotient");
+            if (rho_old > 0 && std::fabs(rho - rho_old) <= rtol * rho) {
+                done = true;
+                break;
+            }
+            rho_old = rho;
+        }
     }
     P.lipschitz = (1.0 + margin) * rho;
     return P.lipschitz;
@@ -473,6 +519,37 @@ int ufss_unrolled_save(ufss_net_t net, const char* path) {
 int ufss_unrolled_load(ufss_net_t net, const char* path) {
     UFSS_GUARD_BEGIN
     ufss::net_load(*as_net(net), path);
+    UFSS_GUARD_END
+}
+
+int ufss_plan_kernel_timing(ufss_plan_t plan, int32_t enable) {
+    UFSS_GUARD_BEGIN
+    Plan* P = as_plan(plan);
+    if (enable) P->kev_used[0] = P->kev_used[1] = 0;
+    P->ktime = enable != 0;
+    UFSS_GUARD_END
+}
+
+int ufss_plan_kernel_times(ufss_plan_t plan, double* fwd_ms, double* adj_ms, int32_t* fwd_n,
+                           int32_t* adj_n) {
+    UFSS_GUARD_BEGIN
+    Plan* P = as_plan(plan);
+    double avg[2] = {0.0, 0.0};
+    for (int w = 0; w < 2; ++w) {
+        const int n = P->kev_used[w];
+        double tot = 0.0;
+        for (int i = 0; i < n; ++i) {
+            UFSS_HIP(hipEventSynchronize(P->kev[w][2 * i + 1]));
+            float ms = 0.f;
+            UFSS_HIP(hipEventElapsedTime(&ms, P->kev[w][2 * i], P->kev[w][2 * i + 1]));
+            tot += ms;
+        }
+        avg[w] = n > 0 ? tot / n : 0.0;
+    }
+    if (fwd_ms) *fwd_ms = avg[0];
+    if (adj_ms) *adj_ms = avg[1];
+    if (fwd_n) *fwd_n = P->kev_used[0];
+    if (adj_n) *adj_n = P->kev_used[1];
     UFSS_GUARD_END
 }
 

@@ -99,6 +99,11 @@ struct Plan {
     double lipschitz = 0.0;
     int64_t ws_bytes = 0;
     hipStream_t cap_stream = nullptr;
+    // kernel timing mode: HIP event pairs around each core kernel launch
+    // (index 0 forward, 1 adjoint), recorded on the launch stream
+    bool ktime = false;
+    std::vector<hipEvent_t> kev[2];
+    int kev_used[2] = {0, 0};
 };
 
 // Kernel launchers (kernels_*.hip).  All asynchronous on `s`.

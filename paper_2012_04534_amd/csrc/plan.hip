@@ -161,6 +161,8 @@ static void free_plan(Plan* P) {
                     P->d_gamma, P->d_v, P->d_stats, P->d_gpart, P->d_ptab_f, P->d_ptab_a};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
+    for (auto& v : P->kev)
+        for (hipEvent_t e : v) (void)hipEventDestroy(e);
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
     delete P;
 }

@@ -27,7 +27,7 @@ EXPORTED = [
     "ufss_last_error", "ufss_select_freqs", "ufss_plan_create", "ufss_plan_destroy",
     "ufss_plan_info_get", "ufss_forward", "ufss_adjoint", "ufss_lipschitz", "ufss_fista",
     "ufss_shrink_update", "ufss_absmax", "ufss_time_kernel", "ufss_fista_batched",
-    "ufss_autotune", "ufss_plan_set_tiling", "ufss_plan_set_phasor_tables", "ufss_unrolled_create", "ufss_unrolled_destroy", "ufss_unrolled_params",
+    "ufss_autotune", "ufss_plan_set_tiling", "ufss_plan_kernel_timing", "ufss_plan_kernel_times", "ufss_plan_set_phasor_tables", "ufss_unrolled_create", "ufss_unrolled_destroy", "ufss_unrolled_params",
     "ufss_unrolled_forward", "ufss_unrolled_grad", "ufss_unrolled_train_step",
     "ufss_unrolled_save", "ufss_unrolled_load",
 ]
@@ -122,6 +122,9 @@ def lib():
             "ufss_autotune": ([P, ctypes.c_char_p, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), P],
                               ctypes.c_int),
             "ufss_plan_set_tiling": ([P, ctypes.POINTER(Tiling)], ctypes.c_int),
+            "ufss_plan_kernel_timing": ([P, I32], ctypes.c_int),
+            "ufss_plan_kernel_times": ([P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I32),
+                                        ctypes.POINTER(I32)], ctypes.c_int),
             "ufss_plan_set_phasor_tables": ([P, I32, ctypes.POINTER(I32)], ctypes.c_int),
             "ufss_unrolled_create": ([P, I32, I32, D, D, U64, ctypes.POINTER(P)], ctypes.c_int),
             "ufss_unrolled_destroy": ([P], ctypes.c_int),
@@ -342,6 +345,21 @@ def ufss_plan_set_tiling(plan, *values, **fields):
             raise TypeError("unknown tiling field " + f)
         setattr(t, f, int(v))
     _check(lib().ufss_plan_set_tiling(plan.handle, ctypes.byref(t)))
+
+
+def ufss_plan_kernel_timing(plan, enable):
+    """Start (clearing earlier records) or stop timing the core kernel launches."""
+    _check(lib().ufss_plan_kernel_timing(plan.handle, 1 if enable else 0))
+
+
+def ufss_plan_kernel_times(plan):
+    """(forward ms, adjoint ms, forward launches, adjoint launches) averaged over
+    the launches timed since timing was enabled."""
+    f, a = ctypes.c_double(0), ctypes.c_double(0)
+    nf, na = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib().ufss_plan_kernel_times(plan.handle, ctypes.byref(f), ctypes.byref(a), ctypes.byref(nf),
+                                        ctypes.byref(na)))
+    return f.value, a.value, nf.value, na.value
 
 
 def ufss_plan_set_phasor_tables(plan, enable):

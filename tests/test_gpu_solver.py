@@ -210,3 +210,26 @@ def test_mu_at_least_one_keeps_zero_iterate(mu, dev):
     assert torch.count_nonzero(x).item() == 0
     assert st["lambda"] > 0
     plan.close()
+
+
+def test_kernel_timing_mode_counts_core_launches(dev):
+    """Timing mode brackets each core kernel launch: K FISTA iterations give K
+    forward and K adjoint records; enabling again clears them; off records none."""
+    u = ufss()
+    w, g, bins, A, _, y = bscan_problem()
+    plan = u.Plan(g, w["m"], False, bins)
+    L = float(V.lipschitz_dense(A))
+    yt = to_dev(y.reshape(g["ny"], g["nx"], w["m"]), dev)
+    x = torch.zeros((g["ny"], g["nx"], g["nz"]), dtype=torch.complex64, device=dev)
+    u.ufss_plan_kernel_timing(plan, True)
+    u.ufss_fista(plan, yt, u.lambda_from_mu(0.1), L, 7, x)
+    u.ufss_plan_kernel_timing(plan, False)
+    f, a, nf, na = u.ufss_plan_kernel_times(plan)
+    # the lambda rule adds one adjoint (A^H y) before the iterations
+    assert nf == 7 and na == 8 and f > 0 and a > 0
+    u.ufss_fista(plan, yt, u.lambda_from_mu(0.1), L, 3, x)
+    assert u.ufss_plan_kernel_times(plan)[2:] == (7, 8)
+    u.ufss_plan_kernel_timing(plan, True)
+    assert u.ufss_plan_kernel_times(plan)[2:] == (0, 0)
+    u.ufss_plan_kernel_timing(plan, False)
+    plan.close()
