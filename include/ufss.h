@@ -164,7 +164,9 @@ int ufss_adjoint(ufss_plan_t plan, const void* y, void* x, ufss_stream_t stream)
  * FISTA diverge, so L = (1 + margin) rho).  Vectors in the plan's operator
  * precision, norms and quotient in FP64.  Start vector CN(0, I) from SplitMix64
  * keyed by `seed`.  Stops when |rho_k - rho_{k-1}| <= rtol rho_k or after
- * max_iters.  Synchronises `stream`; caches L in the plan.
+ * max_iters; iterations run in blocks of 8 between host checks and rho is the
+ * first quotient that meets the test.  Synchronises `stream`; caches L in the
+ * plan.
  *   L_out  HOST double */
 int ufss_lipschitz(ufss_plan_t plan, int32_t max_iters, double rtol,
                    double margin, uint64_t seed, double* L_out,
@@ -226,9 +228,10 @@ int ufss_fista_batched(int32_t n, const ufss_plan_t* plans, const void* const* y
                        void* const* xs, const double* lambdas, const double* Ls,
                        int32_t iters, double* res_out, ufss_stream_t stream);
 
-/* Autotuner for the GEMM path: times every candidate tiling (d_y and depth
- * splits, waves per workgroup, sub-tiles per wave; see ufss_plan_set_tiling) of
- * the forward and adjoint GEMMs of this plan's shape with HIP events, keeps the
+/* Autotuner for the GEMM path: times candidate tilings (d_y and depth splits,
+ * waves per workgroup, sub-tiles per wave, BF16 wave rows, then the smaller
+ * FP32 staged chunk at the best of those; see ufss_plan_set_tiling) of the
+ * forward and adjoint GEMMs of this plan's shape with HIP events, keeps the
  * fastest in the plan and, with flags bit 1, appends it to the JSON cache file
  * `cache_path` (keyed by the shape class); with flags bit 0 a cached entry is
  * used without timing; flags bit 2 restricts the search to d_y splits and two
@@ -283,7 +286,9 @@ int ufss_plan_set_phasor_tables(ufss_plan_t plan, int32_t enable, int32_t* activ
  * channels = Re/Im, ReLU, zero padding); the plan's A / A^H are fixed layers.
  * Stage i: gamma = x_i + beta_i (x_i - x_{i-1}) (FISTA momentum, beta_0 =
  * beta_1 = 0); z = gamma - exp(rho_i)/L A^H(A gamma - y); u = soft(z,
- * exp(kappa_i) lam / L) with lam = mu max|A^H y|; x_{i+1} = u + conv2(relu(conv1(u))).
+ * exp(kappa_i) lam / L) with lam = mu max|A^H y|; x_{i+1} = u +
+ * c conv2(relu(conv1(u / c))) with c = lam / L, so the correction scales with
+ * the data (the network is positively homogeneous in y).
  * Parameters per stage, flat FP32: rho, kappa, W1[ch][2][27], b1[ch],
  * W2[2][ch][27], b2[2] (offset e = 9(e_y+1) + 3(e_x+1) + e_z+1 over
  * [ny][nx][nz]).  Initial rho = kappa = 0, W2 = b2 = 0, so the untrained
