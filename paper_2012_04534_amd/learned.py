@@ -21,8 +21,9 @@ from . import workloads as W
 
 
 def make_dataset(plan, geom, n, seed0, ref_iters, L, mu=0.1, n_scat=(5, 30), snr=(10.0, 20.0),
-                 back_wall=None, dev=None):
-    """List of (y, target, x_true) device tensors for n seeded scenes."""
+                 back_wall=None, dev=None, log=None):
+    """List of (y, target, x_true) device tensors for n seeded scenes; `log`
+    (optional) receives a progress line every 64 scenes."""
     import torch
     dev = dev or torch.device("cuda:0")
     rng = np.random.default_rng(seed0)
@@ -43,6 +44,8 @@ def make_dataset(plan, geom, n, seed0, ref_iters, L, mu=0.1, n_scat=(5, 30), snr
         tgt = torch.zeros(shape_x, dtype=torch.complex64, device=dev)
         ufss.ufss_fista(plan, y, ufss.lambda_from_mu(mu), L, ref_iters, tgt)
         out.append((y, tgt, xt))
+        if log and (i + 1) % 64 == 0:
+            log("%d / %d scenes" % (i + 1, n))
     return out
 
 
