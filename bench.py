@@ -133,6 +133,15 @@ def cpu_baseline(w, bins, seconds=12.0):
 
 
 WEIGHTS = os.path.join(ROOT, "paper_2012_04534_amd", "weights", "unrolled_cscan32_s16c8.bin")
+# Tilings the autotuner chose on MI355X for the workloads timed here (read-only;
+# --retune times the candidates again, --tune-cache uses another file).
+SHIPPED_TUNING = os.path.join(ROOT, "paper_2012_04534_amd", "tuning_gfx950.json")
+
+
+def autotune(ufss, plan, cfg):
+    """Tiling from the cache of `cfg` (path, read, write), else by timing."""
+    path, read, write = cfg
+    return ufss.ufss_autotune(plan, path, read, write)
 
 
 def fista_time(ufss, plan, y, lam, L, k, x):
@@ -145,7 +154,7 @@ def fista_time(ufss, plan, y, lam, L, k, x):
     return time.perf_counter() - t0
 
 
-def time_to_accuracy(ufss, W, plan, g, w, bins, y, lam, L, t_l, dev):
+def time_to_accuracy(ufss, W, plan, g, w, bins, y, lam, L, t_l, dev, tcfg):
     """Time to a relative error of 1e-2 (and coarser levels) against the plain
     FP32 FISTA iterate at the workload's K: FP32 FISTA, BF16 FISTA and the
     learned unrolled network (trained checkpoint, if present)."""
@@ -154,7 +163,7 @@ def time_to_accuracy(ufss, W, plan, g, w, bins, y, lam, L, t_l, dev):
     own = None
     if plan.info()["dtype"] != ufss.F32:      # the reference and the FP32 rows need an FP32 plan
         own = plan = ufss.Plan(g, w["m"], w["per_position"], bins, dtype=ufss.F32)
-        ufss.ufss_autotune(plan, None, False, False)
+        autotune(ufss, plan, tcfg)
     a_ref = torch.zeros((g["ny"], g["nx"], g["nz"]), dtype=torch.complex64, device=dev)
     ufss.ufss_fista(plan, y, lam, L, K, a_ref)
     out = {"reference": "plain FP32 FISTA iterate after %d iterations" % K,
@@ -164,7 +173,7 @@ def time_to_accuracy(ufss, W, plan, g, w, bins, y, lam, L, t_l, dev):
         p = plan
         if dt != ufss.F32:
             p = ufss.Plan(g, w["m"], w["per_position"], bins, dtype=dt, algo=ufss.ALGO_GEMM)
-            ufss.ufss_autotune(p, None, False, False)
+            autotune(ufss, p, tcfg)
         st = ufss.ufss_fista(p, y, lam, L, K, x, a_ref=a_ref)
         per_it = fista_time(ufss, p, y, lam, L, 20, x) / 20
         iters, times = [], []
@@ -226,7 +235,7 @@ def time_to_accuracy(ufss, W, plan, g, w, bins, y, lam, L, t_l, dev):
     return out
 
 
-def cscan64_rates(ufss, W, dev, ev_time):
+def cscan64_rates(ufss, W, dev, ev_time, tcfg):
     """A + A^H rates of the 64 x 64 precision-study workload, FP32 and BF16."""
     import torch
     w = W.workload("cscan64")
@@ -238,7 +247,7 @@ def cscan64_rates(ufss, W, dev, ev_time):
     out = {"cmac_per_apply": cm}
     for tag, dt, peak in (("fp32", ufss.F32, PEAK_FP32_MFMA), ("bf16", ufss.BF16, PEAK_BF16_MFMA)):
         p = ufss.Plan(g, w["m"], False, bins, dtype=dt)
-        ufss.ufss_autotune(p, None, False, False)
+        autotune(ufss, p, tcfg)
         tf = ev_time(lambda: ufss.ufss_forward(p, x, y), 3)
         ta = ev_time(lambda: ufss.ufss_adjoint(p, y, x), 3)
         tfl = 16.0 * cm / ((tf + ta) * 1e-3)
@@ -294,10 +303,18 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16"],
                     help="operator precision of the timed FISTA steps (default f32, the headline)")
     ap.add_argument("--tune-cache", default=None,
-                    help="autotuner cache file for the headline workload (read and written)")
+                    help="autotuner cache file (read and written) instead of the shipped one")
+    ap.add_argument("--retune", action="store_true", help="time the tiling candidates again")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
+    # autotuner cache: (path, read, write)
+    if args.tune_cache:
+        tcfg = (args.tune_cache, True, True)
+    elif args.retune or not os.path.exists(SHIPPED_TUNING):
+        tcfg = (None, False, False)
+    else:
+        tcfg = (SHIPPED_TUNING, True, False)
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(see the sharding design); run with --gpus 1", file=sys.stderr)
@@ -343,9 +360,7 @@ def main():
     for algo in algos:
         plan = ufss.Plan(g, m, per_pos, bins, algo=algo, dtype=pdt)
         if algo == ufss.ALGO_GEMM:
-            tuned = dict(zip(("fwd_split", "adj_split"),
-                             ufss.ufss_autotune(plan, args.tune_cache, args.tune_cache is not None,
-                                                args.tune_cache is not None)))
+            tuned = dict(zip(("fwd_split", "adj_split"), autotune(ufss, plan, tcfg)))
         tf = ev_time(lambda: ufss.ufss_forward(plan, xr, yr), 5)
         ta = ev_time(lambda: ufss.ufss_adjoint(plan, yr, xo), 5)
         name = {ufss.ALGO_GEMM: "gemm-bf16" if bf16 else "gemm", ufss.ALGO_PHASOR: "phasor"}[algo]
@@ -362,8 +377,10 @@ def main():
     t_plan = time.perf_counter() - t_plan
     extras["plan_build_s"] = round(t_plan, 4)
     if algo == ufss.ALGO_GEMM:
-        ufss.ufss_autotune(plan, args.tune_cache, args.tune_cache is not None, args.tune_cache is not None)
+        autotune(ufss, plan, tcfg)
         extras["autotuned"] = tuned
+        extras["tuning"] = ("shipped cache" if tcfg[0] == SHIPPED_TUNING else
+                            "cache " + tcfg[0] if tcfg[0] else "timed")
 
     # synthetic scene and measurements: y = A x + n at the workload's SNR
     x_true = W.scene(g, w["n_scat"], amp=w["amp"], seed=w["seed"], back_wall=w["back_wall"])
@@ -432,8 +449,8 @@ def main():
     }
 
     if not args.quick:
-        result["fista"] = time_to_accuracy(ufss, W, plan, g, w, bins, y, lam, L, t_l, dev)
-        extras["cscan64"] = cscan64_rates(ufss, W, dev, ev_time)
+        result["fista"] = time_to_accuracy(ufss, W, plan, g, w, bins, y, lam, L, t_l, dev, tcfg)
+        extras["cscan64"] = cscan64_rates(ufss, W, dev, ev_time, tcfg)
         extras["batch64"] = batch_rate(ufss, W, dev)
 
     result["extras"] = extras

@@ -6,6 +6,9 @@ Cases: tiny grids for every mode, ragged sizes spanning several tiles, edge
 cases, the full B-scan workload (dense oracle), and the full C-scan workloads
 on outputs the oracle computes one position / one voxel column at a time.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -139,19 +142,27 @@ def test_bscan_workload_full(dev):
     plan.close()
 
 
-# Tilings the autotuner chose for these workloads on MI355X (fwd_split, adj_split,
-# fwd_waves, fwd_zsplit, fwd_tile, adj_tile, fwd_rows, adj_rows); the bench runs
-# the autotuned configuration, so each workload is checked at the plan's default
-# tiling and at these.
-BENCH_TILINGS = {
-    ("cscan32", "f32"): [(4, 12, 5, 8, 2, 2, 0, 0)],
-    ("cscan64", "f32"): [(12, 3, 8, 8, 4, 4, 0, 0)],
-    ("cscan32", "bf16"): [(24, 24, 0, 1, 0, 0, 2, 1)],
-    ("cscan64", "bf16"): [(16, 4, 0, 1, 0, 0, 1, 1)],
-}
+# The bench runs the tilings of the shipped autotuner cache; each full-size
+# workload is checked at the plan's default tiling and at that one.
+SHIPPED = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "paper_2012_04534_amd", "tuning_gfx950.json")
+WORKLOADS = [("cscan32", "f32"), ("cscan32", "bf16"), ("cscan64", "f32"), ("cscan64", "bf16")]
 
 
-@pytest.mark.parametrize("name,dtype", sorted(BENCH_TILINGS))
+def shipped_tiling(plan, g, dtype):
+    """ufss_tiling values of the shipped cache entry for this plan's shape, or None."""
+    info = plan.info()
+    key = "gfx950/nx%d/ny%d/nz%d/mu%d/m%d/wx%d/wy%d/%s" % (
+        g["nx"], g["ny"], g["nz"], info["union_size"], info["m"], info["win_x"], info["win_y"], dtype)
+    e = json.load(open(SHIPPED)).get(key)
+    if e is None or len(e) < 12:
+        return None
+    fs, as_, _, _, nw, zs, npf, npa, rf, ra, zc, kc = [int(v) for v in e]
+    return dict(fwd_split=fs, adj_split=as_, fwd_waves=nw, fwd_zsplit=zs, fwd_tile=npf, adj_tile=npa,
+                fwd_rows=rf, adj_rows=ra, fwd_chunk=zc, adj_chunk=kc)
+
+
+@pytest.mark.parametrize("name,dtype", WORKLOADS)
 def test_cscan_workloads_full_sampled(name, dtype, dev):
     """Full-size C-scan workloads, in the bench's launch configurations, checked
     on positions / voxel columns the oracle evaluates one at a time (corners,
@@ -169,15 +180,17 @@ def test_cscan_workloads_full_sampled(name, dtype, dev):
     y_ref = np.stack([O.apply_A_at(g, bins, x, py, px) for (py, px) in pos])
     x_ref = np.stack([O.apply_AH_at(g, bins, y, vy, vx) for (vy, vx) in cols])
     tol = TOL32 if dtype == "f32" else 1e-2
-    runs = [(u.ALGO_GEMM, None)] + [(u.ALGO_GEMM, t) for t in BENCH_TILINGS[(name, dtype)]]
+    runs = [(u.ALGO_GEMM, None), (u.ALGO_GEMM, "shipped")]
     if dtype == "f32" and w["per_position"]:
         runs.append((u.ALGO_PHASOR, None))
     xd = torch.from_numpy(x).to(dev)
     yd = torch.from_numpy(y).to(dev)
     for algo, tiling in runs:
         plan = u.Plan(g, m, w["per_position"], bins, algo=algo, dtype=u.F32 if dtype == "f32" else u.BF16)
-        if tiling is not None:
-            u.ufss_plan_set_tiling(plan, *tiling)
+        if tiling == "shipped":
+            tiling = shipped_tiling(plan, g, dtype)
+            assert tiling is not None, "no shipped tiling for %s %s" % (name, dtype)
+            u.ufss_plan_set_tiling(plan, **tiling)
         yt = torch.empty(y.shape, dtype=torch.complex64, device=dev)
         xt = torch.empty(x.shape, dtype=torch.complex64, device=dev)
         u.ufss_forward(plan, xd, yt)
@@ -254,7 +267,7 @@ def test_manual_tiling_same_operator(dtype, dev):
     plan.close()
 
 
-@pytest.mark.parametrize("name,dtype", sorted(BENCH_TILINGS))
+@pytest.mark.parametrize("name,dtype", WORKLOADS)
 def test_full_size_frobenius_hutchinson(name, dtype, dev):
     """Whole operator at full size, bench tiling: for x ~ CN(0, I), E||A x||^2 =
     ||A||_F^2 and likewise E||A^H y||^2 (Hutchinson), with ||A||_F^2 counted
@@ -268,7 +281,7 @@ def test_full_size_frobenius_hutchinson(name, dtype, dev):
     bins, _ = u.ufss_select_freqs(g, m, w["per_position"], w["seed"])
     fro = O.frobenius_sq(g, bins)
     plan = u.Plan(g, m, w["per_position"], bins, dtype=u.F32 if dtype == "f32" else u.BF16)
-    u.ufss_plan_set_tiling(plan, *BENCH_TILINGS[(name, dtype)][0])
+    u.ufss_plan_set_tiling(plan, **shipped_tiling(plan, g, dtype))
     gen = torch.Generator(device=dev).manual_seed(11)
     shx, shy = (g["ny"], g["nx"], g["nz"]), (g["ny"], g["nx"], m)
     ax, ahy = [], []
