@@ -52,13 +52,15 @@ __device__ __forceinline__ bf8 neg_bf8(bf8 v) {
 }
 
 // Stages rows x ncol cells of ZCB complex BF16 values into planar LDS cells
-// (ZCB real parts, then ZCB imaginary parts; row pitch `pitch` cells):
-//   cell (r, c) <- src[((ybase + r) * nx + xbase + c) * ld + i0 + e], e < ZCB,
+// (ZCB real parts, then ZCB imaginary parts; row pitch `pitch` cells; grid row
+// gy = ybase + r in row slot gy & slot_mask, so a window of consecutive rows
+// that moves by one row only needs the entering row staged):
+//   cell (gy & slot_mask, c) <- src[(gy * nx + xbase + c) * ld + i0 + e], e < ZCB,
 // zero for rows outside the grid or past `ilim` along the inner axis (columns
 // are inside the grid by construction).  Each thread keeps one e and walks the
 // cells with a fixed step, with UNR loads in flight before the LDS stores.
 template <int UNR>
-__device__ __forceinline__ void stage_planar(__bf16* __restrict__ halo, int rows, int ncol, int pitch,
+__device__ __forceinline__ void stage_planar(__bf16* __restrict__ halo, int rows, int ncol, int pitch, int slot_mask,
                                              const cbf16* __restrict__ src, int ny, int nx, int64_t ld,
                                              int ybase, int xbase, int i0, int ilim) {
     const int e = threadIdx.x & (ZCB - 1);
@@ -74,7 +76,7 @@ __device__ __forceinline__ void stage_planar(__bf16* __restrict__ halo, int rows
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
             v[u] = to_cbf16(0.f, 0.f);
-            dst[u] = rr * pitch + cc;
+            dst[u] = ((ybase + rr) & slot_mask) * pitch + cc;
             const int gy = ybase + rr;
             if (cell + u * step < total && eok && gy >= 0 && gy < ny)
                 v[u] = src[((int64_t)gy * nx + xbase + cc) * ld + i0 + e];
@@ -225,7 +227,10 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
         for (int dy = dy_lo; dy <= dy_hi; ++dy) {
             __syncthreads();
             // stage x rows (planar bf16) and the delay slab of |dy|
-            stage_planar<8>(halo, tpy, ncol, pitch, a.x, a.ny, a.nx, a.nz, py0 - dy, cx_lo, z0, a.nz);
+            // rows live in slot (grid row mod tpy): after the first d_y only the
+            // row entering the window is loaded
+            stage_planar<8>(halo, dy == dy_lo ? tpy : 1, ncol, pitch, tpy - 1, a.x, a.ny, a.nx, a.nz, py0 - dy,
+                            cx_lo, z0, a.nz);
             const int ady = dy < 0 ? -dy : dy;
             if (!a.tab)
                 for (int t = threadIdx.x; t < (a.wx + 1) * ZCB; t += 256) {
@@ -279,7 +284,7 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
                     const int q = wave_x * NP + s;
                     const int px = px0 + q * sw + i % sw, iy = wave_y * sh + i / sw;
                     const int gx = px - dx;
-                    const int cell = (gx >= cx_lo && gx <= cx_hi) ? iy * pitch + (gx - cx_lo) : zero_cell;
+                    const int cell = (gx >= cx_lo && gx <= cx_hi) ? ((py0 + iy - dy) & (tpy - 1)) * pitch + (gx - cx_lo) : zero_cell;
                     xr[s] = lds_bf8(halo + (size_t)cell * CELL + 8 * kq);
                     xi[s] = lds_bf8(halo + (size_t)cell * CELL + ZCB + 8 * kq);
                 }
@@ -408,7 +413,8 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
     for (int k0 = 0; k0 < a.mu; k0 += ZCB) {
         for (int dy = dy_lo; dy <= dy_hi; ++dy) {
             __syncthreads();
-            stage_planar<8>(halo, tvy, ncol, pitch, a.r, a.ny, a.nx, a.mu, vy0 + dy, cx_lo, k0, a.mu);
+            stage_planar<8>(halo, dy == dy_lo ? tvy : 1, ncol, pitch, tvy - 1, a.r, a.ny, a.nx, a.mu,
+                            dy == dy_lo ? vy0 + dy : vy0 + dy + tvy - 1, cx_lo, k0, a.mu);
             const int ady = dy < 0 ? -dy : dy;
             if (!a.tab)
                 for (int t = threadIdx.x; t < (a.wx + 1) * zspan; t += 256) {
@@ -483,7 +489,7 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
                     const int q = wave_x * NV + s;
                     const int vx = vx0 + q * sw + i % sw, iy = wave_y * sh + i / sw;
                     const int gx = vx + dx;
-                    const int cell = (gx >= cx_lo && gx <= cx_hi) ? iy * pitch + (gx - cx_lo) : zero_cell;
+                    const int cell = (gx >= cx_lo && gx <= cx_hi) ? ((vy0 + iy + dy) & (tvy - 1)) * pitch + (gx - cx_lo) : zero_cell;
                     rr8[s] = lds_bf8(halo + (size_t)cell * CELL + 8 * kq);
                     ri8[s] = lds_bf8(halo + (size_t)cell * CELL + ZCB + 8 * kq);
                 }

@@ -44,13 +44,15 @@ __device__ __forceinline__ void phasor(uint32_t ku, float& c, float& s) {
 
 // Stages rows x hc cells of `chunk` consecutive complex values into LDS
 // (cell stride cs, row pitch `pitch` cells), zero outside the grid or past
-// `ilim` along the inner axis:
-//   halo[(r * pitch + c) * cs + e] = src[((ybase + r) * nx + xbase + c) * ld + i0 + e].
+// `ilim` along the inner axis.  Grid row gy = ybase + r lands in row slot
+// gy & slot_mask, so a window of slot_mask + 1 consecutive rows that moves by
+// one row only needs the entering row staged:
+//   halo[((gy & slot_mask) * pitch + c) * cs + e] = src[(gy * nx + xbase + c) * ld + i0 + e].
 // `chunk` is a power of two dividing blockDim.x, so each thread keeps one inner
 // index and walks the cells with a fixed step; UNR independent loads are in
 // flight per thread before their LDS stores.
 template <int UNR>
-__device__ __forceinline__ void stage_halo(cf32* __restrict__ halo, int cs, int rows, int hc, int pitch, int chunk,
+__device__ __forceinline__ void stage_halo(cf32* __restrict__ halo, int cs, int rows, int hc, int pitch, int slot_mask, int chunk,
                                            const cf32* __restrict__ src, int ny, int nx, int64_t ld,
                                            int ybase, int xbase, int i0, int ilim) {
     const int e = threadIdx.x & (chunk - 1);
@@ -66,8 +68,8 @@ __device__ __forceinline__ void stage_halo(cf32* __restrict__ halo, int cs, int 
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
             v[u] = cf32{0.f, 0.f};
-            dst[u] = (rr * pitch + cc) * cs + e;
             const int gy = ybase + rr, gx = xbase + cc;
+            dst[u] = ((gy & slot_mask) * pitch + cc) * cs + e;
             if (cell + u * step < total && eok && gy >= 0 && gy < ny && gx >= 0 && gx < nx)
                 v[u] = src[((int64_t)gy * nx + gx) * ld + i0 + e];
             cc += step;
@@ -147,7 +149,10 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
         for (int dy = dy_lo; dy <= dy_hi; ++dy) {
             __syncthreads();
             // stage x rows (py0 + r - dy), columns (px0 - wx + c), depths z0..z0+zc
-            stage_halo<8>(halo, cs, tpy, hc, hc, zc, a.x, a.ny, a.nx, a.nz, py0 - dy, px0 - a.wx, z0, a.nz);
+            // rows live in slot (grid row mod tpy): after the first d_y only the row
+            // entering the window is loaded
+            stage_halo<8>(halo, cs, dy == dy_lo ? tpy : 1, hc, hc, tpy - 1, zc, a.x, a.ny, a.nx, a.nz,
+                          py0 - dy, px0 - a.wx, z0, a.nz);
             const int ady = dy < 0 ? -dy : dy;
             for (int t = threadIdx.x; t < (a.wx + 1) * zc; t += blockDim.x) {
                 int adx = t / zc, zz = t - adx * zc;
@@ -165,7 +170,7 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
             for (int dx = dx_lo; dx <= dx_hi; ++dx) {
                 const int adx = dx < 0 ? -dx : dx;
                 const uint32_t* urow = ulds + adx * zc;
-                const cf32* hrow = halo + (iy * hc + ix + a.wx - dx) * cs;
+                const cf32* hrow = halo + ((((py0 + iy - dy) & (tpy - 1)) * hc) + ix + a.wx - dx) * cs;
                 // sub-tiles whose shifted columns all fall outside the grid add
                 // exact zeros: skip their MFMAs (wave-uniform test)
                 bool act[NP];
@@ -294,7 +299,8 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
         const int kcur = min(kc, (a.mu - k0 + 3) & ~3);   // last chunk: valid bins, rounded to 4
         for (int dy = dy_lo; dy <= dy_hi; ++dy) {
             __syncthreads();
-            stage_halo<8>(halo, cs, tpy, hc, hc, kc, a.r, a.ny, a.nx, a.mu, vy0 + dy, vx0 - a.wx, k0, a.mu);
+            stage_halo<8>(halo, cs, dy == dy_lo ? tpy : 1, hc, hc, tpy - 1, kc, a.r, a.ny, a.nx, a.mu,
+                          dy == dy_lo ? vy0 + dy : vy0 + dy + tpy - 1, vx0 - a.wx, k0, a.mu);
             const int ady = dy < 0 ? -dy : dy;
             for (int t = threadIdx.x; t < (a.wx + 1) * zspan; t += 256) {
                 int adx = t / zspan, zz = t - adx * zspan;
@@ -318,7 +324,7 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
                 uint32_t uz[NZ];
 #pragma unroll
                 for (int q = 0; q < NZ; ++q) uz[q] = ulds[adx * zspan + wave * NZ * 16 + q * 16 + i];
-                const cf32* hrow = halo + (iy * hc + ix + a.wx + dx) * cs;
+                const cf32* hrow = halo + ((((vy0 + iy + dy) & (tpy - 1)) * hc) + ix + a.wx + dx) * cs;
 #pragma unroll
                 for (int kk = 0; kk < kc; kk += 4) {
                     if (kk >= kcur) break;
