@@ -37,9 +37,9 @@ PEAK_HBM = 8e12
 # are part of the traffic).  Each entry holds the SHA-256 prefix of the kernel
 # source it was measured on; a changed source or another tiling reports null.
 TRAFFIC = {
-    # 32 x 32 C-scan, FP32 union-GEMM, autotuned tiling (profiles/cscan32_fp32_gemm_and_phasor.md)
-    "cscan32/gemm/forward/fs4-zs8-nw5-np2-zc8": {"bytes": 20.580e6, "sha": "cf473d5d63f1bf38"},
-    "cscan32/gemm/adjoint/as12-np2-kc8": {"bytes": 32.298e6, "sha": "cf473d5d63f1bf38"},
+    # 32 x 32 C-scan, FP32 union-GEMM, shipped tiling (profiles/cscan32_fp32_gemm_and_phasor.md)
+    "cscan32/gemm/forward/fs4-zs8-nw5-np2-zc8": {"bytes": 20.579e6, "sha": "5c52ed5ce783316f"},
+    "cscan32/gemm/adjoint/as12-np2-kc16": {"bytes": 32.297e6, "sha": "5c52ed5ce783316f"},
 }
 TRAFFIC_SRC = {"gemm": "paper_2012_04534_amd/csrc/gemm_f32.hip",
                "gemm-bf16": "paper_2012_04534_amd/csrc/gemm_bf16.hip",
