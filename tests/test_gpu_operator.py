@@ -299,3 +299,54 @@ def test_full_size_frobenius_hutchinson(name, dtype, dev):
     for v in (np.array(ax), np.array(ahy)):
         tol = max(0.005, 4 * v.std(ddof=1) / np.sqrt(n) / fro)
         assert abs(v.mean() / fro - 1) < tol, (v.mean(), fro, tol)
+
+
+def random_case(rng):
+    """Seeded random small problem: shape, window, bins, precision and a valid tiling."""
+    ny = int(rng.choice([1, 1, 2, 3, 5, 8]))
+    nx = int(rng.integers(1, 33 if ny == 1 else 13))
+    nz = int(rng.integers(1, 49))
+    nt = int(rng.choice([64, 128, 256]))
+    win = int(rng.choice([-1, 0, 1, 2, 5]))
+    g = W.geometry(nx, ny, nz, nt, win_x=win, win_y=win)
+    band = {64: 8, 128: 17, 256: 33}[nt]
+    m = int(rng.integers(1, min(16, band) + 1))
+    per_pos = bool(rng.integers(0, 2))
+    dtype = "bf16" if rng.random() < 0.35 else "f32"
+    t = dict(fwd_split=int(rng.integers(1, 9)), adj_split=int(rng.integers(1, 9)))
+    if dtype == "f32":
+        t.update(fwd_waves=int(rng.integers(1, 9)), fwd_zsplit=int(rng.integers(1, 5)),
+                 fwd_tile=int(rng.choice([2, 4])), adj_tile=int(rng.choice([2, 4])),
+                 fwd_chunk=int(rng.choice([8, 16])), adj_chunk=int(rng.choice([8, 16])))
+    elif ny > 1:
+        t.update(fwd_rows=int(rng.integers(1, 3)), adj_rows=int(rng.integers(1, 3)))
+    return g, m, per_pos, dtype, t
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_small_problems_against_dense_oracle(seed, dev):
+    """Randomised parity sweep: every draw is checked element-wise against the
+    dense FP64 oracle (FP32 1e-5, BF16 1e-2)."""
+    u = ufss()
+    rng = np.random.default_rng(9000 + seed)
+    g, m, per_pos, dtype, t = random_case(rng)
+    bins, _ = u.ufss_select_freqs(g, m, per_pos, 700 + seed)
+    x = W.cn((g["ny"], g["nx"], g["nz"]), 800 + seed).astype(np.complex64)
+    y = W.cn((g["ny"], g["nx"], m), 900 + seed).astype(np.complex64)
+    A = O.dense_A(g, bins)
+    y_ref = (A @ x.reshape(-1).astype(np.complex128)).reshape(y.shape)
+    x_ref = (A.conj().T @ y.reshape(-1).astype(np.complex128)).reshape(x.shape)
+    plan = u.Plan(g, m, per_pos, bins, dtype=u.F32 if dtype == "f32" else u.BF16)
+    try:
+        u.ufss_plan_set_tiling(plan, **t)
+    except u.UfssError:
+        pass                     # a shape the option does not fit: default tiling
+    yo = torch.empty(y.shape, dtype=torch.complex64, device=dev)
+    xo = torch.empty(x.shape, dtype=torch.complex64, device=dev)
+    u.ufss_forward(plan, torch.from_numpy(x).to(dev), yo)
+    u.ufss_adjoint(plan, torch.from_numpy(y).to(dev), xo)
+    torch.cuda.synchronize()
+    tol = TOL32 if dtype == "f32" else 1e-2
+    ey, ex = errs(yo.cpu().numpy(), y_ref), errs(xo.cpu().numpy(), x_ref)
+    assert max(ey) < tol and max(ex) < tol, (g["nx"], g["ny"], g["nz"], g["nt"], m, per_pos, dtype, t, ey, ex)
+    plan.close()
