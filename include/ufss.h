@@ -129,6 +129,32 @@ const char* ufss_last_error(void);
 int ufss_select_freqs(const ufss_geom* g, int32_t m, int32_t per_position,
                       uint64_t seed, int32_t* bins_out, int32_t* band_size_out);
 
+/* ---- frequency sampling strategies (paper Sec. III-A, Table I) ---------- */
+#define UFSS_SAMPLE_RND   0  /* uniform over the band, shared (Sigma = I)        */
+#define UFSS_SAMPLE_RND_F 1  /* uniform over the band, one subset per position   */
+#define UFSS_SAMPLE_MAX   2  /* the m bins of largest |H_k| (maximal sampling)   */
+#define UFSS_SAMPLE_NRG   3  /* energy-based: drawn with probability |H_k| /
+                                ||H||_1 without replacement, shared             */
+#define UFSS_SAMPLE_NRG_F 4  /* energy-based, one subset per position           */
+
+/* Select m DFT bins by one of the strategies of Sec. III-A.  RND / RND_F are
+ * ufss_select_freqs.  MAX, NRG and NRG_F take their candidates from bins
+ * 0..nt/2 (the complex Gabor pulse has no energy at negative frequencies) with
+ * weights w_k = exp(-(f_k - f_c)^2 / (2 sigma_f^2)), proportional to |H_k|.
+ * MAX keeps the m largest weights, ties to the lower bin.  NRG draws m times
+ * without replacement: a draw takes u = (next() >> 11) 2^-53 from the
+ * SplitMix64 stream, scales it by the FP64 sum of the remaining weights in
+ * ascending bin order, and takes the first remaining bin whose running sum
+ * exceeds it; the bin is then removed (the remaining weights renormalise).
+ * NRG_F keys position p = ix + nx*iy with seed XOR mix64(p + 1).  Subsets are
+ * sorted ascending.
+ *   bins_out          HOST int32 [m] (RND, MAX, NRG) or [ny][nx][m] (RND_F,
+ *                     NRG_F)
+ *   per_position_out  HOST, optional: 1 for the per-position strategies
+ * Errors: INVALID_ARG, BAND_TOO_SMALL (m above the candidates). */
+int ufss_sample_bins(const ufss_geom* g, int32_t m, int32_t strategy, uint64_t seed,
+                     int32_t* bins_out, int32_t* per_position_out);
+
 /* Build a plan: derived geometry (FP64 on the host), the integer-turn delay
  * table, H_k and the device workspace.  Paper Sec. IV-B: the operator is block
  * 2-level Toeplitz in the lateral offset, which the kernels exploit.

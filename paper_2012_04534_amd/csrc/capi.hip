@@ -16,6 +16,8 @@ void plan_destroy(Plan* P);
 void plan_info(const Plan* P, ufss_plan_info* info);
 void select_freqs(const ufss_geom* g, int m, int per_position, uint64_t seed, int32_t* out,
                   int32_t* band_size);
+void sample_bins(const ufss_geom* g, int m, int strategy, uint64_t seed, int32_t* out,
+                 int32_t* per_position_out);
 const char* last_error();
 int phasor_forward_blocks(const Plan& P);
 int fista_batched(int n, Plan* const* plans, const cf32* const* ys, cf32* const* xs,
@@ -298,6 +300,13 @@ int ufss_select_freqs(const ufss_geom* g, int32_t m, int32_t per_position, uint6
                       int32_t* bins_out, int32_t* band_size_out) {
     UFSS_GUARD_BEGIN
     ufss::select_freqs(g, m, per_position, seed, bins_out, band_size_out);
+    UFSS_GUARD_END
+}
+
+int ufss_sample_bins(const ufss_geom* g, int32_t m, int32_t strategy, uint64_t seed,
+                     int32_t* bins_out, int32_t* per_position_out) {
+    UFSS_GUARD_BEGIN
+    ufss::sample_bins(g, m, strategy, seed, bins_out, per_position_out);
     UFSS_GUARD_END
 }
 

@@ -137,6 +137,84 @@ void select_freqs(const ufss_geom* g, int m, int per_position, uint64_t seed, in
         }
 }
 
+// Knowledge-based strategies (Sec. III-A maximal / energy-based sampling,
+// Table I per-A-scan variant).  Candidates are bins 0..nt/2 weighted by the
+// Gaussian envelope of |H_k|; energy-based draws go without replacement, each
+// from the running sum of the remaining weights in ascending bin order, FP64.
+static std::vector<double> energy_weights(const ufss_geom& g, const Derived& d) {
+    std::vector<double> w(g.nt / 2 + 1);
+    for (int k = 0; k <= g.nt / 2; ++k) {
+        double f = (double)k * g.fs / g.nt;
+        double e = f - g.fc;
+        w[k] = std::exp(-(e * e) / (2.0 * d.sigma_f * d.sigma_f));
+    }
+    return w;
+}
+
+static void take_max(const std::vector<double>& w, int m, int32_t* out) {
+    std::vector<int> idx(w.size());
+    for (size_t k = 0; k < w.size(); ++k) idx[k] = (int)k;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return w[a] > w[b]; });
+    std::sort(idx.begin(), idx.begin() + m);
+    for (int i = 0; i < m; ++i) out[i] = idx[i];
+}
+
+static void draw_energy(const std::vector<double>& w, int m, uint64_t key, int32_t* out) {
+    std::vector<char> left(w.size());
+    for (size_t k = 0; k < w.size(); ++k) left[k] = w[k] > 0.0;
+    SplitMix64 rng(key);
+    for (int i = 0; i < m; ++i) {
+        double total = 0.0;
+        for (size_t k = 0; k < w.size(); ++k)
+            if (left[k]) total += w[k];
+        double target = (double)(rng.next() >> 11) * (1.0 / 9007199254740992.0) * total;
+        double run = 0.0;
+        int pick = -1;
+        for (size_t k = 0; k < w.size(); ++k) {
+            if (!left[k]) continue;
+            run += w[k];
+            pick = (int)k;
+            if (run > target) break;
+        }
+        left[pick] = 0;
+        out[i] = pick;
+    }
+    std::sort(out, out + m);
+}
+
+void sample_bins(const ufss_geom* g, int m, int strategy, uint64_t seed, int32_t* out,
+                 int32_t* per_position_out) {
+    validate_geom(g);
+    if (!out) fail(UFSS_ERR_INVALID_ARG, "bins_out is NULL");
+    if (m < 1) fail(UFSS_ERR_INVALID_ARG, "m must be >= 1");
+    if (strategy < UFSS_SAMPLE_RND || strategy > UFSS_SAMPLE_NRG_F)
+        fail(UFSS_ERR_INVALID_ARG, "unknown sampling strategy");
+    const bool per = strategy == UFSS_SAMPLE_RND_F || strategy == UFSS_SAMPLE_NRG_F;
+    if (per_position_out) *per_position_out = per ? 1 : 0;
+    if (strategy == UFSS_SAMPLE_RND || strategy == UFSS_SAMPLE_RND_F) {
+        select_freqs(g, m, per ? 1 : 0, seed, out, nullptr);
+        return;
+    }
+    Derived d = derive(*g);
+    std::vector<double> w = energy_weights(*g, d);
+    int positive = 0;
+    for (double v : w) positive += v > 0.0;
+    if (m > positive)
+        fail(UFSS_ERR_BAND_TOO_SMALL, "m = " + std::to_string(m) + " exceeds the " +
+                                          std::to_string(positive) + " bins with energy");
+    if (strategy == UFSS_SAMPLE_MAX) {
+        take_max(w, m, out);
+    } else if (strategy == UFSS_SAMPLE_NRG) {
+        draw_energy(w, m, seed, out);
+    } else {
+        for (int iy = 0; iy < g->ny; ++iy)
+            for (int ix = 0; ix < g->nx; ++ix) {
+                int64_t p = ix + (int64_t)g->nx * iy;
+                draw_energy(w, m, seed ^ mix64((uint64_t)p + 1), out + p * m);
+            }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Plan.
 // ---------------------------------------------------------------------------

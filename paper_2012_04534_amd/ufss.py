@@ -22,9 +22,10 @@ ERRORS = {
 }
 F32, BF16 = 0, 1
 ALGO_AUTO, ALGO_GEMM, ALGO_PHASOR = 0, 1, 2
+SAMPLE_RND, SAMPLE_RND_F, SAMPLE_MAX, SAMPLE_NRG, SAMPLE_NRG_F = 0, 1, 2, 3, 4
 
 EXPORTED = [
-    "ufss_last_error", "ufss_select_freqs", "ufss_plan_create", "ufss_plan_destroy",
+    "ufss_last_error", "ufss_select_freqs", "ufss_sample_bins", "ufss_plan_create", "ufss_plan_destroy",
     "ufss_plan_info_get", "ufss_forward", "ufss_adjoint", "ufss_lipschitz", "ufss_fista",
     "ufss_shrink_update", "ufss_absmax", "ufss_time_kernel", "ufss_fista_batched",
     "ufss_autotune", "ufss_plan_set_tiling", "ufss_plan_kernel_timing", "ufss_plan_kernel_times", "ufss_plan_set_phasor_tables", "ufss_unrolled_create", "ufss_unrolled_destroy", "ufss_unrolled_params",
@@ -105,6 +106,7 @@ def lib():
         sig = {
             "ufss_last_error": ([], ctypes.c_char_p),
             "ufss_select_freqs": ([ctypes.POINTER(Geom), I32, I32, U64, P, P], ctypes.c_int),
+            "ufss_sample_bins": ([ctypes.POINTER(Geom), I32, I32, U64, P, P], ctypes.c_int),
             "ufss_plan_create": ([ctypes.POINTER(Geom), I32, I32, P, ctypes.POINTER(P)], ctypes.c_int),
             "ufss_plan_destroy": ([P], ctypes.c_int),
             "ufss_plan_info_get": ([P, ctypes.POINTER(PlanInfo)], ctypes.c_int),
@@ -186,6 +188,20 @@ def ufss_select_freqs(g, m, per_position, seed):
                                    ctypes.c_uint64(seed & (2 ** 64 - 1)),
                                    out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(band)))
     return out, band.value
+
+
+def ufss_sample_bins(g, m, strategy, seed):
+    """Bins of one sampling strategy (SAMPLE_*) and whether they are per position."""
+    geom = make_geom(g)
+    per = strategy in (SAMPLE_RND_F, SAMPLE_NRG_F)
+    shape = (g["ny"], g["nx"], m) if per else (m,)
+    out = np.zeros(shape, dtype=np.int32)
+    flag = ctypes.c_int32(-1)
+    _check(lib().ufss_sample_bins(ctypes.byref(geom), int(m), int(strategy),
+                                  ctypes.c_uint64(seed & (2 ** 64 - 1)),
+                                  out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(flag)))
+    assert flag.value == int(per)
+    return out, per
 
 
 class Plan:

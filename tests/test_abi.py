@@ -61,6 +61,38 @@ def test_select_freqs_errors():
     assert list(full) == list(range(10, 43))
 
 
+@pytest.mark.parametrize("strategy", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("name,m", [("bscan32", 1), ("bscan32", 10), ("cscan32", 64),
+                                    ("cscan64", 128), ("cscan64", 513)])
+def test_sample_bins_bit_identical_to_oracle(strategy, name, m):
+    w = W.workload(name)
+    g = dict(w["geom"])
+    if name != "bscan32":
+        g.update(nx=6, ny=5)     # per-position draws in Python stay quick
+    band = {256: 33, 512: 66, 1024: 132}[g["nt"]]
+    if strategy in (S.STRATEGY_RND, S.STRATEGY_RND_F) and m > band:
+        with pytest.raises(ufss.UfssError):
+            ufss.ufss_sample_bins(g, m, strategy, 5)
+        return
+    for seed in (w["seed"], 0, 2 ** 64 - 1):
+        b, per = ufss.ufss_sample_bins(g, m, strategy, seed)
+        o = S.sample_bins(g, m, strategy, seed)
+        assert per == (o.ndim == 3)
+        assert np.array_equal(b, o), (strategy, name, m, seed)
+
+
+def test_sample_bins_errors():
+    g = W.workload("bscan32")["geom"]
+    with pytest.raises(ufss.UfssError) as e:
+        ufss.ufss_sample_bins(g, 130, ufss.SAMPLE_NRG, 1)
+    assert e.value.name == "BAND_TOO_SMALL"
+    with pytest.raises(ufss.UfssError) as e:
+        ufss.ufss_sample_bins(g, 4, 5, 1)
+    assert e.value.name == "INVALID_ARG"
+    full, _ = ufss.ufss_sample_bins(g, 129, ufss.SAMPLE_NRG, 3)
+    assert list(full) == list(range(129))
+
+
 def test_plan_rejects_bad_bins_before_touching_the_gpu():
     g = W.geometry(8, 4, 16, 64)
     with pytest.raises(ufss.UfssError) as e:
