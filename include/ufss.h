@@ -155,6 +155,31 @@ int ufss_select_freqs(const ufss_geom* g, int32_t m, int32_t per_position,
 int ufss_sample_bins(const ufss_geom* g, int32_t m, int32_t strategy, uint64_t seed,
                      int32_t* bins_out, int32_t* per_position_out);
 
+/* Estimate of the largest singular value of A from its Frobenius norm (paper
+ * Sec. IV-C, estimation by the geometric mean of the Frobenius bounds).  Host
+ * only, FP64, no device work.
+ *   fro_sq            ||A||_F^2, exact: sum over positions p and bins of
+ *                     H_k^2 N_z (lateral voxels inside the window of p)
+ *   fro_sq_central    the paper's approximation: N_x N_y N_z times the squared
+ *                     norm of the column of voxel ((nx-1)/2, (ny-1)/2)
+ *   n                 N = N_x N_y min(m, N_z), a bound on the rank of A
+ *   sigma_hat         sqrt(fro_sq) / N^(1/4)
+ *   sigma_hat_central sqrt(fro_sq_central) / N^(1/4)
+ * sigma_hat^2 can stand in for L in ufss_fista; it is not guaranteed to bound
+ * the true L from above, and FISTA reports UFSS_ERR_DIVERGED when it does not
+ * suffice. */
+typedef struct ufss_sigma_est {
+    double fro_sq, fro_sq_central;
+    int64_t n;
+    double sigma_hat, sigma_hat_central;
+} ufss_sigma_est;
+
+/*   bins  HOST int32 [m] or [ny][nx][m], as for ufss_plan_create
+ *   out   HOST
+ * Errors: INVALID_ARG. */
+int ufss_sigma_estimate(const ufss_geom* g, int32_t m, int32_t per_position,
+                        const int32_t* bins, ufss_sigma_est* out);
+
 /* Build a plan: derived geometry (FP64 on the host), the integer-turn delay
  * table, H_k and the device workspace.  Paper Sec. IV-B: the operator is block
  * 2-level Toeplitz in the lateral offset, which the kernels exploit.

@@ -144,3 +144,37 @@ def frobenius_sq(g, bins):
             h = geometry.pulse_spectrum(g, _bins_at(bins, py, px))
             total += float(np.sum(h * h)) * g["nz"] * nx_in * ny_in
     return total
+
+
+def central_column_sq(g, bins):
+    """Squared norm of one column of A: the voxel below the grid centre,
+    ((N_x - 1) // 2, (N_y - 1) // 2), at any depth.  Every position whose
+    window holds that voxel contributes sum_m |H_{k_m(p)}|^2."""
+    wx, wy = geometry.window(g)
+    vx, vy = (g["nx"] - 1) // 2, (g["ny"] - 1) // 2
+    total = 0.0
+    for py in range(max(vy - wy, 0), min(vy + wy, g["ny"] - 1) + 1):
+        for px in range(max(vx - wx, 0), min(vx + wx, g["nx"] - 1) + 1):
+            h = geometry.pulse_spectrum(g, _bins_at(bins, py, px))
+            total += float(np.sum(h * h))
+    return total
+
+
+def sigma_estimate(g, bins):
+    """Sec. IV-C estimate of the largest singular value.
+
+    ||A||_F / sqrt(N) <= sigma_max <= ||A||_F when N bounds the rank; the
+    estimate is the geometric mean of the two bounds, ||A||_F / N^(1/4).
+    Reading: N = min(rows, columns) = N_x N_y min(M, N_z).  The paper
+    approximates ||A||_F^2 by N_x N_y N_z times the squared norm of one
+    central column (boundary effects neglected); both versions are returned.
+    Returns dict(fro_sq, fro_sq_central, n, sigma_hat, sigma_hat_central).
+    """
+    m = bins.shape[-1]
+    npos = g["nx"] * g["ny"]
+    n = npos * min(m, g["nz"])
+    fro = frobenius_sq(g, bins)
+    cen = npos * g["nz"] * central_column_sq(g, bins)
+    return dict(fro_sq=fro, fro_sq_central=cen, n=n,
+                sigma_hat=math.sqrt(fro) / n ** 0.25,
+                sigma_hat_central=math.sqrt(cen) / n ** 0.25)

@@ -18,6 +18,8 @@ void select_freqs(const ufss_geom* g, int m, int per_position, uint64_t seed, in
                   int32_t* band_size);
 void sample_bins(const ufss_geom* g, int m, int strategy, uint64_t seed, int32_t* out,
                  int32_t* per_position_out);
+void sigma_estimate(const ufss_geom* g, int m, int per_position, const int32_t* bins,
+                    ufss_sigma_est* out);
 const char* last_error();
 int phasor_forward_blocks(const Plan& P);
 int fista_batched(int n, Plan* const* plans, const cf32* const* ys, cf32* const* xs,
@@ -307,6 +309,13 @@ int ufss_sample_bins(const ufss_geom* g, int32_t m, int32_t strategy, uint64_t s
                      int32_t* bins_out, int32_t* per_position_out) {
     UFSS_GUARD_BEGIN
     ufss::sample_bins(g, m, strategy, seed, bins_out, per_position_out);
+    UFSS_GUARD_END
+}
+
+int ufss_sigma_estimate(const ufss_geom* g, int32_t m, int32_t per_position,
+                        const int32_t* bins, ufss_sigma_est* out) {
+    UFSS_GUARD_BEGIN
+    ufss::sigma_estimate(g, m, per_position, bins, out);
     UFSS_GUARD_END
 }
 

@@ -245,15 +245,9 @@ static void free_plan(Plan* P) {
     delete P;
 }
 
-Plan* plan_create(const ufss_geom* g, int m, int per_position, const int32_t* bins) {
-    validate_geom(g);
-    if (!bins) fail(UFSS_ERR_INVALID_ARG, "bins is NULL");
-    if (m < 1 || m > 4096) fail(UFSS_ERR_INVALID_ARG, "m must be in [1, 4096]");
-    Derived d = derive(*g);
-    const int npos = g->nx * g->ny;
-    const int64_t nsel = per_position ? (int64_t)npos * m : m;
-    // validate bins: strictly ascending inside [0, nt/2]
-    const int nrows = per_position ? npos : 1;
+// Subsets must be strictly ascending inside [0, nt/2].
+static void validate_bins(const ufss_geom* g, int m, int per_position, const int32_t* bins) {
+    const int nrows = per_position ? g->nx * g->ny : 1;
     for (int r = 0; r < nrows; ++r) {
         const int32_t* b = bins + (int64_t)r * m;
         for (int i = 0; i < m; ++i) {
@@ -263,6 +257,60 @@ Plan* plan_create(const ufss_geom* g, int m, int per_position, const int32_t* bi
                 fail(UFSS_ERR_INVALID_ARG, "bins of a position must be strictly ascending");
         }
     }
+}
+
+// Sec. IV-C estimate of sigma_max from the Frobenius norm.  Every non-zero
+// entry of A has modulus H_k, so ||A||_F^2 = sum_p sum_m H_{k_m(p)}^2 N_z
+// (voxels in the window of p); the paper's cheaper form takes N_x N_y N_z times
+// the squared norm of the column below the grid centre.  N = min(rows, cols)
+// bounds the rank, and sigma_hat = ||A||_F / N^(1/4) is the geometric mean of
+// ||A||_F / sqrt(N) <= sigma_max <= ||A||_F.  Host only, FP64.
+void sigma_estimate(const ufss_geom* g, int m, int per_position, const int32_t* bins,
+                    ufss_sigma_est* out) {
+    validate_geom(g);
+    if (!bins || !out) fail(UFSS_ERR_INVALID_ARG, "bins or out is NULL");
+    if (m < 1) fail(UFSS_ERR_INVALID_ARG, "m must be >= 1");
+    validate_bins(g, m, per_position, bins);
+    Derived d = derive(*g);
+    auto hsq = [&](int py, int px) {
+        const int32_t* b = bins + (per_position ? ((int64_t)py * g->nx + px) * m : 0);
+        double s = 0.0;
+        for (int i = 0; i < m; ++i) {
+            double h = pulse_spectrum(*g, d, b[i]);
+            s += h * h;
+        }
+        return s;
+    };
+    double fro = 0.0;
+    for (int py = 0; py < g->ny; ++py) {
+        int ny_in = std::min(py + d.wy, g->ny - 1) - std::max(py - d.wy, 0) + 1;
+        for (int px = 0; px < g->nx; ++px) {
+            int nx_in = std::min(px + d.wx, g->nx - 1) - std::max(px - d.wx, 0) + 1;
+            fro += hsq(py, px) * g->nz * nx_in * ny_in;
+        }
+    }
+    const int vx = (g->nx - 1) / 2, vy = (g->ny - 1) / 2;
+    double col = 0.0;
+    for (int py = std::max(vy - d.wy, 0); py <= std::min(vy + d.wy, g->ny - 1); ++py)
+        for (int px = std::max(vx - d.wx, 0); px <= std::min(vx + d.wx, g->nx - 1); ++px)
+            col += hsq(py, px);
+    const double npos = (double)g->nx * g->ny;
+    out->fro_sq = fro;
+    out->fro_sq_central = npos * g->nz * col;
+    out->n = (int64_t)g->nx * g->ny * std::min(m, g->nz);
+    const double q = std::pow((double)out->n, 0.25);
+    out->sigma_hat = std::sqrt(out->fro_sq) / q;
+    out->sigma_hat_central = std::sqrt(out->fro_sq_central) / q;
+}
+
+Plan* plan_create(const ufss_geom* g, int m, int per_position, const int32_t* bins) {
+    validate_geom(g);
+    if (!bins) fail(UFSS_ERR_INVALID_ARG, "bins is NULL");
+    if (m < 1 || m > 4096) fail(UFSS_ERR_INVALID_ARG, "m must be in [1, 4096]");
+    Derived d = derive(*g);
+    const int npos = g->nx * g->ny;
+    const int64_t nsel = per_position ? (int64_t)npos * m : m;
+    validate_bins(g, m, per_position, bins);
     int algo = g->algo;
     if (algo == UFSS_ALGO_AUTO) algo = UFSS_ALGO_GEMM;
     if (algo == UFSS_ALGO_PHASOR && g->dtype == UFSS_BF16)

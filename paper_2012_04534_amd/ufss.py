@@ -25,7 +25,8 @@ ALGO_AUTO, ALGO_GEMM, ALGO_PHASOR = 0, 1, 2
 SAMPLE_RND, SAMPLE_RND_F, SAMPLE_MAX, SAMPLE_NRG, SAMPLE_NRG_F = 0, 1, 2, 3, 4
 
 EXPORTED = [
-    "ufss_last_error", "ufss_select_freqs", "ufss_sample_bins", "ufss_plan_create", "ufss_plan_destroy",
+    "ufss_last_error", "ufss_select_freqs", "ufss_sample_bins", "ufss_sigma_estimate",
+    "ufss_plan_create", "ufss_plan_destroy",
     "ufss_plan_info_get", "ufss_forward", "ufss_adjoint", "ufss_lipschitz", "ufss_fista",
     "ufss_shrink_update", "ufss_absmax", "ufss_time_kernel", "ufss_fista_batched",
     "ufss_autotune", "ufss_plan_set_tiling", "ufss_plan_kernel_timing", "ufss_plan_kernel_times", "ufss_plan_set_phasor_tables", "ufss_unrolled_create", "ufss_unrolled_destroy", "ufss_unrolled_params",
@@ -107,6 +108,8 @@ def lib():
             "ufss_last_error": ([], ctypes.c_char_p),
             "ufss_select_freqs": ([ctypes.POINTER(Geom), I32, I32, U64, P, P], ctypes.c_int),
             "ufss_sample_bins": ([ctypes.POINTER(Geom), I32, I32, U64, P, P], ctypes.c_int),
+            "ufss_sigma_estimate": ([ctypes.POINTER(Geom), I32, I32, P,
+                                     ctypes.POINTER(SigmaEst)], ctypes.c_int),
             "ufss_plan_create": ([ctypes.POINTER(Geom), I32, I32, P, ctypes.POINTER(P)], ctypes.c_int),
             "ufss_plan_destroy": ([P], ctypes.c_int),
             "ufss_plan_info_get": ([P, ctypes.POINTER(PlanInfo)], ctypes.c_int),
@@ -202,6 +205,25 @@ def ufss_sample_bins(g, m, strategy, seed):
                                   out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(flag)))
     assert flag.value == int(per)
     return out, per
+
+
+class SigmaEst(ctypes.Structure):
+    _fields_ = [("fro_sq", ctypes.c_double), ("fro_sq_central", ctypes.c_double),
+                ("n", ctypes.c_int64), ("sigma_hat", ctypes.c_double),
+                ("sigma_hat_central", ctypes.c_double)]
+
+
+def ufss_sigma_estimate(g, m, per_position, bins):
+    """Sec. IV-C Frobenius estimate of sigma_max (dict of the struct's fields)."""
+    geom = make_geom(g)
+    b = np.ascontiguousarray(bins, dtype=np.int32)
+    want = g["nx"] * g["ny"] * m if per_position else m
+    if b.size != want:
+        raise ValueError("bins has %d entries, expected %d" % (b.size, want))
+    out = SigmaEst()
+    _check(lib().ufss_sigma_estimate(ctypes.byref(geom), int(m), int(bool(per_position)),
+                                     b.ctypes.data_as(ctypes.c_void_p), ctypes.byref(out)))
+    return {f: getattr(out, f) for f, _ in SigmaEst._fields_}
 
 
 class Plan:

@@ -93,6 +93,25 @@ def test_sample_bins_errors():
     assert list(full) == list(range(129))
 
 
+@pytest.mark.parametrize("name", ["bscan32", "cscan32", "cscan64"])
+def test_sigma_estimate_matches_oracle(name):
+    from oracle import operator as O
+    w = W.workload(name)
+    g = dict(w["geom"])
+    if name == "cscan32":
+        g.update(nx=9, ny=7)      # per-position sums in Python stay quick
+    bins = S.select_freqs(g, w["m"], w["per_position"], w["seed"])
+    got = ufss.ufss_sigma_estimate(g, w["m"], w["per_position"], bins)
+    ref = O.sigma_estimate(g, bins)
+    assert got["n"] == ref["n"]
+    for k in ("fro_sq", "fro_sq_central", "sigma_hat", "sigma_hat_central"):
+        assert got[k] == pytest.approx(ref[k], rel=1e-12), k
+    with pytest.raises(ufss.UfssError):
+        bad = np.array(bins)
+        bad.reshape(-1)[1] = bad.reshape(-1)[0]
+        ufss.ufss_sigma_estimate(g, w["m"], w["per_position"], bad)
+
+
 def test_plan_rejects_bad_bins_before_touching_the_gpu():
     g = W.geometry(8, 4, 16, 64)
     with pytest.raises(ufss.UfssError) as e:
@@ -125,7 +144,8 @@ def header_struct_fields(name):
 @pytest.mark.parametrize("cname,pyname", [("ufss_geom", "Geom"), ("ufss_plan_info", "PlanInfo"),
                                            ("ufss_fista_stats", "FistaStats"),
                                            ("ufss_fista_state", "FistaState"),
-                                           ("ufss_tiling", "Tiling")])
+                                           ("ufss_tiling", "Tiling"),
+                                           ("ufss_sigma_est", "SigmaEst")])
 def test_binding_structs_match_header(cname, pyname):
     """The ctypes mirrors of the C structs list the same fields in the same order."""
     cls = getattr(ufss, pyname)

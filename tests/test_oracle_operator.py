@@ -106,6 +106,45 @@ def test_frobenius_count_and_norm_bounds(case):
     assert fro / N <= L * (1 + 1e-12) and L <= fro * (1 + 1e-12)
 
 
+@pytest.mark.parametrize("case", range(5))
+def test_sigma_estimate_against_dense(case):
+    """Sec. IV-C estimate: the central column norm is that column of the dense
+    matrix, sigma_hat is the geometric mean of the two Frobenius bounds, and
+    N = min(rows, cols) keeps the lower bound below sigma_max (singular values
+    of the dense matrix)."""
+    g, bins = tiny_cases()[case]
+    A = O.dense_A(g, bins)
+    est = O.sigma_estimate(g, bins)
+    vx, vy = (g["nx"] - 1) // 2, (g["ny"] - 1) // 2
+    for jz in (0, g["nz"] - 1):
+        col = (vy * g["nx"] + vx) * g["nz"] + jz
+        assert est["fro_sq_central"] / (g["nx"] * g["ny"] * g["nz"]) == \
+            pytest.approx(float(np.sum(np.abs(A[:, col]) ** 2)), rel=1e-12)
+    assert est["n"] == min(A.shape)
+    fro = float(np.sum(np.abs(A) ** 2))
+    smax = float(np.linalg.svd(A, compute_uv=False)[0])
+    lo, hi = math.sqrt(fro / est["n"]), math.sqrt(fro)
+    assert lo <= smax * (1 + 1e-12) and smax <= hi * (1 + 1e-12)
+    assert est["sigma_hat"] == pytest.approx(math.sqrt(lo * hi), rel=1e-12)
+
+
+def test_sigma_estimate_zero_window_central_is_exact():
+    # With a zero aperture every column sees exactly one position, so for shared
+    # bins the central-column approximation has no boundary error.
+    g = tiny(nx=5, ny=4, nz=6, nt=64, win=0)
+    bins = S.select_freqs(g, 5, False, 3)
+    est = O.sigma_estimate(g, bins)
+    assert est["fro_sq_central"] == pytest.approx(est["fro_sq"], rel=1e-13)
+    # and A is block diagonal over positions with identical M x N_z blocks, so
+    # sigma_max is the top singular value of one block
+    A = O.dense_A(g, bins)
+    m, nz = len(bins), g["nz"]
+    blk = A[:m, :nz]
+    assert np.abs(A[:m, nz:]).max() == 0.0
+    assert float(np.linalg.svd(A, compute_uv=False)[0]) == \
+        pytest.approx(float(np.linalg.svd(blk, compute_uv=False)[0]), rel=1e-12)
+
+
 def test_shift_invariance():
     """P11 (Theorem on block 2-level Toeplitz structure): translating an
     interior scene laterally translates A x, for shared bins."""
