@@ -123,3 +123,61 @@ def power_iteration(A, AH, v0, max_iters=200, rtol=1e-6):
             return rho, it
         rho_old = rho
     return rho, max_iters
+
+
+def fista_backtracking(A, AH, y, lam, L0, eta, iters, a0=None, a_ref=None, slack=0.0,
+                       max_trials=200):
+    """FISTA with backtracking (Sec. IV-C, backtracking; Beck & Teboulle 2009).
+
+    Needs only a lower start value L0 and a growth factor eta > 1.  At the
+    extrapolated point gamma_k, trial constants L = L_{k-1} eta^i (i = 0, 1,
+    ...) are tried in turn: p = soft(gamma - grad f(gamma) / L, lam / L) is
+    accepted as soon as
+
+        f(p) <= f(gamma) + Re<p - gamma, grad f(gamma)> + L/2 ||p - gamma||^2 (+ slack f(gamma)),
+
+    with f = 1/2 ||A . - y||^2 (the l1 terms of F and of its quadratic model
+    cancel).  ``slack`` (default 0) admits a relative rounding margin.  The
+    momentum is that of plain FISTA.
+    Returns (a_K, stats): per iteration the objective F(a_k), ||A a_k - y||,
+    ||a_k - a_{k-1}|| / ||a_k||, the accepted L_k, the trial count and, if
+    a_ref is given, ||a_k - a_ref|| / ||a_ref||.
+    """
+    if not (eta > 1.0) or not (L0 > 0.0):
+        raise ValueError("need L0 > 0 and eta > 1")
+    y = np.asarray(y, dtype=np.complex128)
+    shape = AH(y).shape if a0 is None else np.shape(a0)
+    a = np.zeros(shape, np.complex128) if a0 is None else np.array(a0, np.complex128)
+    gamma = a.copy()
+    t, L = 1.0, float(L0)
+    ref_norm = None if a_ref is None else float(np.linalg.norm(a_ref))
+    stats = {"obj": [], "res": [], "rel_change": [], "L": [], "trials": [], "err_ref": []}
+    for _ in range(iters):
+        r = A(gamma) - y
+        f_gamma = 0.5 * float(np.vdot(r, r).real)
+        grad = AH(r)
+        trials = 0
+        while True:
+            trials += 1
+            if trials > max_trials:
+                raise RuntimeError("backtracking did not terminate")
+            p = soft(gamma - grad / L, lam / L)
+            rp = A(p) - y
+            f_p = 0.5 * float(np.vdot(rp, rp).real)
+            d = p - gamma
+            model = f_gamma + float(np.vdot(d, grad).real) + 0.5 * L * float(np.vdot(d, d).real)
+            if f_p <= model + slack * f_gamma:
+                break
+            L *= eta
+        t_new = (1.0 + math.sqrt(1.0 + 4.0 * t * t)) / 2.0
+        gamma = p + ((t - 1.0) / t_new) * (p - a)
+        nrm = float(np.linalg.norm(p))
+        stats["obj"].append(f_p + lam * float(np.abs(p).sum()))
+        stats["res"].append(math.sqrt(2.0 * f_p))
+        stats["rel_change"].append(float(np.linalg.norm(p - a)) / nrm if nrm > 0 else 0.0)
+        stats["L"].append(L)
+        stats["trials"].append(trials)
+        if a_ref is not None:
+            stats["err_ref"].append(float(np.linalg.norm(p - a_ref)) / ref_norm)
+        a, t = p, t_new
+    return a, stats

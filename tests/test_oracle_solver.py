@@ -157,3 +157,49 @@ def test_underestimated_lipschitz_diverges():
         _, st = V.fista(A, AH, y, lam, L / 4, 200)
     res = np.array(st["res"])
     assert not np.all(np.isfinite(res)) or res[-1] > 1e6 * res[0]
+
+
+def test_backtracking_unitary_closed_form():
+    """Backtracking on A = I: f(p) - f(gamma) - <p - gamma, grad> = 1/2 ||p - gamma||^2,
+    so a trial L is accepted exactly when L >= 1; from L0 = 0.1 and eta = 2 the
+    first accepted constant is 1.6 after five trials, and the first step from
+    gamma = 0 (gradient -y) is soft(y/1.6, lam/1.6)."""
+    y = W.cn(40, 5)
+    A = lambda v: v
+    lam = 0.3
+    a, st = V.fista_backtracking(A, A, y, lam, 0.1, 2.0, 3)
+    assert st["L"] == [1.6, 1.6, 1.6]
+    assert st["trials"] == [5, 1, 1]
+    a1, _ = V.fista_backtracking(A, A, y, lam, 0.1, 2.0, 1)
+    np.testing.assert_allclose(a1, V.soft(y / 1.6, lam / 1.6), rtol=0, atol=1e-15)
+
+
+def test_backtracking_from_upper_bound_is_fista():
+    """With L0 at or above sigma_max^2 no trial is rejected and the iterates are
+    those of plain FISTA with L = L0."""
+    _, _, Amat, A, AH, _, y = problem(nx=12, nz=32, m=8, n_scat=3, snr_db=30.0)
+    L = V.lipschitz_dense(Amat)
+    lam = V.lambda_rule(AH, y, 0.1)
+    a_bt, st = V.fista_backtracking(A, AH, y, lam, 1.5 * L, 2.0, 40)
+    a_pl, _ = V.fista(A, AH, y, lam, 1.5 * L, 40)
+    assert st["trials"] == [1] * 40 and st["L"] == [1.5 * L] * 40
+    np.testing.assert_allclose(a_bt, a_pl, rtol=0, atol=1e-12 * np.abs(a_pl).max())
+
+
+def test_backtracking_bound_from_low_start():
+    """Beck & Teboulle (2009, Thm. 4.4): from L0 <= L(f) the accepted constants
+    never exceed eta L(f) and F(a_k) - F* <= 2 eta L(f) ||a0 - a*||^2 / (k+1)^2."""
+    _, _, Amat, A, AH, _, y = problem(nx=12, nz=32, m=8, n_scat=3, snr_db=30.0)
+    L = V.lipschitz_dense(Amat)
+    lam = V.lambda_rule(AH, y, 0.1)
+    a_star, _ = V.fista(A, AH, y, lam, L, 6000)
+    F_star = V.objective(A, y, a_star, lam)
+    eta = 2.0
+    _, st = V.fista_backtracking(A, AH, y, lam, L / 1000.0, eta, 200)
+    Ls = st["L"]
+    assert all(Ls[i] <= Ls[i + 1] for i in range(len(Ls) - 1))
+    assert Ls[-1] <= eta * L and Ls[0] > L / 1000.0
+    bound_c = 2 * eta * L * float(np.vdot(a_star, a_star).real)
+    for k in (1, 5, 20, 100, 200):
+        gap = st["obj"][k - 1] - F_star
+        assert gap <= bound_c / (k + 1) ** 2 + 1e-12 * F_star
