@@ -49,7 +49,9 @@ extern "C" {
 #define UFSS_BF16 1   /* BF16 phasors and operands, FP32 accumulation           */
 
 /* ---- operator algorithm -------------------------------------------------- */
-#define UFSS_ALGO_AUTO   0  /* GEMM for shared bins; per-position: fastest     */
+#define UFSS_ALGO_AUTO   0  /* GEMM (per-position subsets run over their union:
+                               measured faster than the phasor path even at
+                               one bin per position)                          */
 #define UFSS_ALGO_GEMM   1  /* windowed complex GEMM over (offset, depth) on MFMA;
                                per-position subsets run over their union of bins
                                and are gathered / scattered                    */
@@ -242,6 +244,31 @@ int ufss_fista(ufss_plan_t plan, const void* y, double lambda, double L,
                int32_t iters, double tol, int32_t accel, void* x,
                const void* a_ref, ufss_fista_stats* stats,
                ufss_fista_state* state, ufss_stream_t stream);
+
+/* FISTA with backtracking (paper Sec. IV-C, backtracking, after Beck and
+ * Teboulle): needs no Lipschitz constant, only a start value L0 and a growth
+ * factor eta.  At the extrapolated point gamma_k the constants L_{k-1} eta^i,
+ * i = 0, 1, ..., are tried until p = soft(gamma - A^H(A gamma - y)/L, lambda/L)
+ * satisfies
+ *   f(p) <= f(gamma) + Re<p - gamma, grad f(gamma)> + L/2 ||p - gamma||^2 + s,
+ * f = 1/2 ||A . - y||^2, s = eps * 1/2 ||y||^2, a margin for the rounding of
+ * the residuals: eps = 1e-6 (FP32 plans) or 2^-8 (BF16 plans, whose input
+ * rounding makes f noisy at that level); p is a_k and L_k = L.  Momentum as ufss_fista.
+ * Sums and the test are FP64 on the host, one synchronisation per trial.  The
+ * residual at gamma_{k+1} is formed from the two accepted residuals (A is
+ * linear), so an iteration costs one adjoint and one forward per trial.
+ *   lambda, y, x, a_ref, tol   as ufss_fista (tol is checked every iteration)
+ *   L0     > 0; eta > 1
+ *   stats  HOST or NULL: obj[k] = F(a_k) (at the iterate, not at gamma_k),
+ *          res[k] = ||A a_k - y||, rel_change, err_ref (0 without a_ref)
+ *   L_out  HOST double [iters] or NULL: accepted L_k
+ *   trials_out HOST int32 [iters] or NULL: trials of iteration k (>= 1)
+ * Errors: INVALID_ARG, DIVERGED (non-finite residual, or no acceptable step in
+ * 100 trials).  Synchronises `stream`.  Does not resume. */
+int ufss_fista_backtracking(ufss_plan_t plan, const void* y, double lambda, double L0,
+                            double eta, int32_t iters, double tol, void* x, const void* a_ref,
+                            ufss_fista_stats* stats, double* L_out, int32_t* trials_out,
+                            ufss_stream_t stream);
 
 /* Fused proximal-gradient update, standalone (paper Alg. 1, threshold and
  * momentum lines; ISTA is beta = 0).  For each of n complex entries:

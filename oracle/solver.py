@@ -134,10 +134,10 @@ def fista_backtracking(A, AH, y, lam, L0, eta, iters, a0=None, a_ref=None, slack
     ...) are tried in turn: p = soft(gamma - grad f(gamma) / L, lam / L) is
     accepted as soon as
 
-        f(p) <= f(gamma) + Re<p - gamma, grad f(gamma)> + L/2 ||p - gamma||^2 (+ slack f(gamma)),
+        f(p) <= f(gamma) + Re<p - gamma, grad f(gamma)> + L/2 ||p - gamma||^2 (+ slack),
 
     with f = 1/2 ||A . - y||^2 (the l1 terms of F and of its quadratic model
-    cancel).  ``slack`` (default 0) admits a relative rounding margin.  The
+    cancel).  ``slack`` (default 0) is an absolute margin for rounding.  The
     momentum is that of plain FISTA.
     Returns (a_K, stats): per iteration the objective F(a_k), ||A a_k - y||,
     ||a_k - a_{k-1}|| / ||a_k||, the accepted L_k, the trial count and, if
@@ -166,7 +166,7 @@ def fista_backtracking(A, AH, y, lam, L0, eta, iters, a0=None, a_ref=None, slack
             f_p = 0.5 * float(np.vdot(rp, rp).real)
             d = p - gamma
             model = f_gamma + float(np.vdot(d, grad).real) + 0.5 * L * float(np.vdot(d, d).real)
-            if f_p <= model + slack * f_gamma:
+            if f_p <= model + slack:
                 break
             L *= eta
         t_new = (1.0 + math.sqrt(1.0 + 4.0 * t * t)) / 2.0

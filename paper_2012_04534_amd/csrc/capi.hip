@@ -262,6 +262,114 @@ int fista(Plan& P, const cf32* y, double lambda, double L, int iters, double tol
     return UFSS_OK;
 }
 
+// FISTA with backtracking (Sec. IV-C; Beck & Teboulle 2009).  Trial constants
+// L = L_{k-1} eta^i are tried at the extrapolated point gamma_k until
+//   f(p) <= f(gamma) + Re<p - gamma, grad f(gamma)> + L/2 ||p - gamma||^2 + slack,
+// f = 1/2 ||A . - y||^2, slack = eps * 1/2 ||y||^2 with eps = 1e-6 for the FP32
+// operator and 2^-8 (one BF16 unit in the last place) for the BF16 operator,
+// whose input rounding makes f(p) - f(gamma) noisy at that level: with a
+// smaller margin no constant passes once the iterates settle.  A is linear, so the residual at the next extrapolated point
+// is (1 + beta) r_k - beta r_{k-1} of the two accepted residuals: an iteration
+// costs one adjoint plus one forward per trial (two operator applications when
+// the first trial is accepted, as plain FISTA).
+static constexpr double kBtSlackF32 = 1e-6;
+static constexpr double kBtSlackBF16 = 0.00390625;
+static constexpr int kBtMaxTrials = 100;
+
+int fista_backtracking(Plan& P, const cf32* y, double lambda, double L0, double eta, int iters,
+                       double tol, cf32* x, const cf32* aref, ufss_fista_stats* stats,
+                       double* L_out, int32_t* trials_out, hipStream_t s) {
+    if (!y || !x) fail(UFSS_ERR_INVALID_ARG, "y and x must be device pointers");
+    if (iters < 0) fail(UFSS_ERR_INVALID_ARG, "iters must be >= 0");
+    if (!(tol >= 0)) fail(UFSS_ERR_INVALID_ARG, "tol must be >= 0");
+    if (!(L0 > 0) || !std::isfinite(L0)) fail(UFSS_ERR_INVALID_ARG, "L0 must be > 0");
+    if (!(eta > 1) || !std::isfinite(eta)) fail(UFSS_ERR_INVALID_ARG, "eta must be > 1");
+    if (lambda == 0 || std::isnan(lambda)) fail(UFSS_ERR_INVALID_ARG, "lambda must be non-zero");
+    if (lambda < 0) {
+        op_adjoint(P, y, P.d_g, s);
+        lambda = -lambda * absmax_dev(P.nvox, P.d_g, P.d_part, P.d_scalars + 40, s);
+    }
+    const int64_t nv = P.nvox, nm = (int64_t)P.npos * P.m;
+    if (!P.d_bt) {
+        UFSS_HIP(hipMalloc(&P.d_bt, (size_t)(3 * nv + 3 * nm) * sizeof(cf32)));
+        UFSS_HIP(hipMalloc(&P.d_bt_scal, 16 * sizeof(double)));
+        P.ws_bytes += (3 * nv + 3 * nm) * sizeof(cf32) + 16 * sizeof(double);
+    }
+    cf32* X[3] = {P.d_bt, P.d_bt + nv, P.d_bt + 2 * nv};
+    cf32* R[3] = {P.d_bt + 3 * nv, P.d_bt + 3 * nv + nm, P.d_bt + 3 * nv + 2 * nm};
+    int cur = 0, prev = 1, cand = 2;
+    double* sc = P.d_bt_scal;   // [0] ||r_p||^2, [1..6] trial sums, [8] ||r_gamma||^2, [10] ||y||^2
+    double ref2 = 0.0;
+    if (aref) {
+        int nb = launch_norm2(nv, aref, P.d_part, s);
+        launch_reduce(P.d_part, nb, 2, P.d_scalars + 44, s);
+        ref2 = read_scalar(P.d_scalars + 44, s);
+        if (!(ref2 > 0)) fail(UFSS_ERR_INVALID_ARG, "a_ref is zero");
+    }
+    {
+        int nb = launch_norm2(nm, y, P.d_part, s);
+        launch_reduce(P.d_part, nb, 2, sc + 10, s);
+    }
+    const double eps = P.dtype == UFSS_BF16 ? kBtSlackBF16 : kBtSlackF32;
+    const double slack = eps * 0.5 * read_scalar(sc + 10, s);
+    launch_copy(nv, x, X[cur], s);
+    launch_copy(nv, x, P.d_gamma, s);
+    op_forward(P, X[cur], R[cur], y, sc + 8, s);
+    launch_copy(nm, R[cur], P.d_r, s);
+    double tk = 1.0, L = L0;
+    int done = 0;
+    double h[9];
+    for (int k = 0; k < iters; ++k) {
+        op_adjoint(P, P.d_r, P.d_g, s);
+        int trials = 0;
+        for (;;) {
+            if (++trials > kBtMaxTrials)
+                fail(UFSS_ERR_DIVERGED, "backtracking found no step in " +
+                                            std::to_string(kBtMaxTrials) + " trials");
+            int nb = launch_bt_prox(nv, P.d_gamma, P.d_g, (float)(1.0 / L), (float)(lambda / L),
+                                    X[cand], X[cur], aref, P.d_part, s);
+            launch_reduce(P.d_part, nb, 6, sc + 1, s);
+            op_forward(P, X[cand], R[cand], y, sc + 0, s);
+            UFSS_HIP(hipMemcpyAsync(h, sc, 9 * sizeof(double), hipMemcpyDeviceToHost, s));
+            sync(s);
+            if (!std::isfinite(h[0]) || !std::isfinite(h[8]) || !std::isfinite(h[1]))
+                fail(UFSS_ERR_DIVERGED, "non-finite residual at iteration " + std::to_string(k));
+            const double model = 0.5 * h[8] + h[1] + 0.5 * L * h[2];
+            if (0.5 * h[0] <= model + slack) break;
+            L *= eta;
+            if (!(L < 1e300)) fail(UFSS_ERR_DIVERGED, "backtracking constant overflowed");
+        }
+        const double rel = h[5] > 0 ? std::sqrt(h[4] / h[5]) : 0.0;
+        if (stats) {
+            if (stats->obj) stats->obj[k] = 0.5 * h[0] + lambda * h[3];
+            if (stats->res) stats->res[k] = std::sqrt(h[0]);
+            if (stats->rel_change) stats->rel_change[k] = rel;
+            if (stats->err_ref) stats->err_ref[k] = aref ? std::sqrt(h[6] / ref2) : 0.0;
+        }
+        if (L_out) L_out[k] = L;
+        if (trials_out) trials_out[k] = trials;
+        const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * tk * tk));
+        const float beta = (float)((tk - 1.0) / tn);
+        const int old_prev = prev;
+        prev = cur;
+        cur = cand;
+        cand = old_prev;
+        launch_extrap(nv, X[cur], X[prev], beta, P.d_gamma, P.d_part, s);
+        int nb = launch_extrap(nm, R[cur], R[prev], beta, P.d_r, P.d_part, s);
+        launch_reduce(P.d_part, nb, 1, sc + 8, s);
+        tk = tn;
+        done = k + 1;
+        if (tol > 0 && rel <= tol) break;
+    }
+    launch_copy(nv, X[cur], x, s);
+    sync(s);
+    if (stats) {
+        stats->iters_done = done;
+        stats->lambda = lambda;
+    }
+    return done;
+}
+
 }  // namespace ufss
 
 // ---------------------------------------------------------------------------
@@ -375,6 +483,18 @@ int ufss_fista(ufss_plan_t plan, const void* y, double lambda, double L, int32_t
     return ufss::fista(*P, static_cast<const ufss::cf32*>(y), lambda, L, iters, tol, accel,
                        static_cast<ufss::cf32*>(x), static_cast<const ufss::cf32*>(a_ref), stats,
                        state, static_cast<hipStream_t>(stream));
+    UFSS_GUARD_END
+}
+
+int ufss_fista_backtracking(ufss_plan_t plan, const void* y, double lambda, double L0,
+                            double eta, int32_t iters, double tol, void* x, const void* a_ref,
+                            ufss_fista_stats* stats, double* L_out, int32_t* trials_out,
+                            ufss_stream_t stream) {
+    UFSS_GUARD_BEGIN
+    Plan* P = as_plan(plan);
+    ufss::fista_backtracking(*P, static_cast<const ufss::cf32*>(y), lambda, L0, eta, iters, tol,
+                             static_cast<ufss::cf32*>(x), static_cast<const ufss::cf32*>(a_ref),
+                             stats, L_out, trials_out, static_cast<hipStream_t>(stream));
     UFSS_GUARD_END
 }
 

@@ -95,6 +95,10 @@ struct Plan {
     cf32* d_gamma = nullptr;       // FISTA extrapolated point [nvox]
     cf32* d_v = nullptr;           // power-iteration vector [nvox]
     double* d_stats = nullptr;     // FISTA per-iteration statistics
+    // backtracking FISTA workspace (allocated on first use): three iterate
+    // buffers [nvox], three residual buffers [npos*m], 16 FP64 results
+    cf32* d_bt = nullptr;
+    double* d_bt_scal = nullptr;
     int stats_cap = 0;
     double lipschitz = 0.0;
     int64_t ws_bytes = 0;
@@ -167,6 +171,13 @@ void launch_copy(int64_t n, const cf32* src, cf32* dst, hipStream_t s);
 void launch_fista_stats(double* stats, int k, const double* upd, const double* res2,
                         const double* g1_prev, double lam, int have_ref, double ref2,
                         hipStream_t s);
+
+// Backtracking FISTA: trial step p = soft(gamma - step g, thresh) with six
+// FP64 partials per block (see vec.hip); out = a + beta (a - b) with ||out||^2.
+int launch_bt_prox(int64_t n, const cf32* gamma, const cf32* g, float step, float thresh,
+                   cf32* p, const cf32* prev, const cf32* aref, double* part, hipStream_t s);
+int launch_extrap(int64_t n, const cf32* a, const cf32* b, float beta, cf32* out, double* part,
+                  hipStream_t s);
 
 int max_blocks_vec();
 

@@ -236,7 +236,8 @@ static void free_plan(Plan* P) {
     if (!P) return;
     void* ptrs[] = {P->d_bins, P->d_ubins, P->d_map, P->d_hsel, P->d_u, P->d_yraw,
                     P->d_rop, P->d_xop, P->d_part, P->d_scalars, P->d_r, P->d_g,
-                    P->d_gamma, P->d_v, P->d_stats, P->d_gpart, P->d_ptab_f, P->d_ptab_a};
+                    P->d_gamma, P->d_v, P->d_stats, P->d_gpart, P->d_ptab_f, P->d_ptab_a,
+                    P->d_bt, P->d_bt_scal};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& v : P->kev)

@@ -210,6 +210,79 @@ int launch_update(int64_t n, cf32* gamma, const cf32* g, int nsplit, cf32* a, fl
 }
 
 // ---------------------------------------------------------------------------
+// Backtracking FISTA (Sec. IV-C): the proximal trial step at one constant L,
+// p = soft(gamma - g / L, lam / L), with FP64 partials of
+//   Re<p - gamma, g>, ||p - gamma||^2, ||p||_1, ||p - prev||^2, ||p||^2,
+//   ||p - aref||^2 (0 without aref)
+// for the sufficient-decrease test and the iteration statistics.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void bt_prox_kernel(int64_t n,
+                                                           const cf32* __restrict__ gamma,
+                                                           const cf32* __restrict__ g, float step,
+                                                           float thresh, cf32* __restrict__ p,
+                                                           const cf32* __restrict__ prev,
+                                                           const cf32* __restrict__ aref,
+                                                           double* __restrict__ part) {
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads) {
+        cf32 gm = gamma[i], gg = g[i], pv = prev[i];
+        float zr = gm.re - step * gg.re, zi = gm.im - step * gg.im;
+        float mag = sqrtf(zr * zr + zi * zi);
+        float sc = mag > thresh ? 1.0f - thresh / mag : 0.0f;
+        float ar = zr * sc, ai = zi * sc;
+        p[i] = cf32{ar, ai};
+        double dr = (double)ar - gm.re, di = (double)ai - gm.im;
+        acc[0] += dr * gg.re + di * gg.im;
+        acc[1] += dr * dr + di * di;
+        acc[2] += sqrt((double)ar * ar + (double)ai * ai);
+        double er = (double)ar - pv.re, ei = (double)ai - pv.im;
+        acc[3] += er * er + ei * ei;
+        acc[4] += (double)ar * ar + (double)ai * ai;
+        if (aref) {
+            cf32 q = aref[i];
+            double fr = (double)ar - q.re, fi = (double)ai - q.im;
+            acc[5] += fr * fr + fi * fi;
+        }
+    }
+    block_sum_write<6>(acc, part);
+}
+
+int launch_bt_prox(int64_t n, const cf32* gamma, const cf32* g, float step, float thresh,
+                   cf32* p, const cf32* prev, const cf32* aref, double* part, hipStream_t s) {
+    const int nb = blocks_for(n);
+    hipLaunchKernelGGL(bt_prox_kernel, dim3(nb), dim3(kThreads), 0, s, n, gamma, g, step, thresh,
+                       p, prev, aref, part);
+    UFSS_HIP(hipGetLastError());
+    return nb;
+}
+
+// out = a + beta (a - b) (FISTA extrapolation; by linearity also of residuals),
+// with FP64 partials of ||out||^2.
+__global__ __launch_bounds__(kThreads) void extrap_kernel(int64_t n, const cf32* __restrict__ a,
+                                                          const cf32* __restrict__ b, float beta,
+                                                          cf32* __restrict__ out,
+                                                          double* __restrict__ part) {
+    double acc[1] = {0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads) {
+        cf32 u = a[i], v = b[i];
+        float re = u.re + beta * (u.re - v.re), im = u.im + beta * (u.im - v.im);
+        out[i] = cf32{re, im};
+        acc[0] += (double)re * re + (double)im * im;
+    }
+    block_sum_write<1>(acc, part);
+}
+
+int launch_extrap(int64_t n, const cf32* a, const cf32* b, float beta, cf32* out, double* part,
+                  hipStream_t s) {
+    const int nb = blocks_for(n);
+    hipLaunchKernelGGL(extrap_kernel, dim3(nb), dim3(kThreads), 0, s, n, a, b, beta, out, part);
+    UFSS_HIP(hipGetLastError());
+    return nb;
+}
+
+// ---------------------------------------------------------------------------
 // Fixed-order reductions.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void reduce_kernel(const double* __restrict__ part,

@@ -28,6 +28,7 @@ EXPORTED = [
     "ufss_last_error", "ufss_select_freqs", "ufss_sample_bins", "ufss_sigma_estimate",
     "ufss_plan_create", "ufss_plan_destroy",
     "ufss_plan_info_get", "ufss_forward", "ufss_adjoint", "ufss_lipschitz", "ufss_fista",
+    "ufss_fista_backtracking",
     "ufss_shrink_update", "ufss_absmax", "ufss_time_kernel", "ufss_fista_batched",
     "ufss_autotune", "ufss_plan_set_tiling", "ufss_plan_kernel_timing", "ufss_plan_kernel_times", "ufss_plan_set_phasor_tables", "ufss_unrolled_create", "ufss_unrolled_destroy", "ufss_unrolled_params",
     "ufss_unrolled_forward", "ufss_unrolled_grad", "ufss_unrolled_train_step",
@@ -116,6 +117,8 @@ def lib():
             "ufss_forward": ([P, P, P, P], ctypes.c_int),
             "ufss_adjoint": ([P, P, P, P], ctypes.c_int),
             "ufss_lipschitz": ([P, I32, D, D, U64, ctypes.POINTER(D), P], ctypes.c_int),
+            "ufss_fista_backtracking": ([P, P, D, D, D, I32, D, P, P,
+                                         ctypes.POINTER(FistaStats), P, P, P], ctypes.c_int),
             "ufss_fista": ([P, P, D, D, I32, D, I32, P, P, ctypes.POINTER(FistaStats),
                             ctypes.POINTER(FistaState), P], ctypes.c_int),
             "ufss_shrink_update": ([I64, P, P, P, D, D, D, P, P, P], ctypes.c_int),
@@ -308,6 +311,31 @@ def ufss_fista(plan, y, lam, L, iters, x, tol=0.0, accel=True, a_ref=None, state
     _check(code)
     k = st.iters_done
     out = {key: v[:k].copy() for key, v in arrs.items()}
+    out["iters_done"] = k
+    out["lambda"] = st.lambda_
+    return out
+
+
+def ufss_fista_backtracking(plan, y, lam, L0, eta, iters, x, tol=0.0, a_ref=None,
+                            stream=None):
+    """FISTA with backtracking; per-iteration FP64 statistics plus the accepted
+    constants ("L") and trial counts ("trials")."""
+    _numel_check(x, plan.nvox, "x")
+    _numel_check(y, plan.nmeas, "y")
+    n = max(int(iters), 1)
+    arrs = {k: np.zeros(n) for k in ("obj", "res", "rel_change", "err_ref", "L")}
+    trials = np.zeros(n, dtype=np.int32)
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    st = FistaStats(dp(arrs["obj"]), dp(arrs["res"]), dp(arrs["rel_change"]),
+                    dp(arrs["err_ref"]), 0, 0.0)
+    _check(lib().ufss_fista_backtracking(
+        plan.handle, _ptr(y, "y"), float(lam), float(L0), float(eta), int(iters), float(tol),
+        _ptr(x, "x"), _ptr(a_ref, "a_ref") if a_ref is not None else None, ctypes.byref(st),
+        arrs["L"].ctypes.data_as(ctypes.c_void_p), trials.ctypes.data_as(ctypes.c_void_p),
+        _stream(stream)))
+    k = st.iters_done
+    out = {key: v[:k].copy() for key, v in arrs.items()}
+    out["trials"] = trials[:k].copy()
     out["iters_done"] = k
     out["lambda"] = st.lambda_
     return out

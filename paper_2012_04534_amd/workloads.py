@@ -18,6 +18,10 @@ Workloads (one per measured configuration):
             64 bins drawn per position, full aperture
   cscan64   C-scan, 64 x 64 positions, 64 x 64 x 512 voxels, N_t = 1024,
             128 shared bins, aperture window of +-16 voxels
+  sim50     the simulated specimen of Sec. VII / Table III: 50 x 50 positions,
+            50 depths, f_c = 3.2 MHz, f_s = 20 MHz, c = 5920 m/s, t0 = 10 us,
+            N_t = 256, full aperture; line and tilted-rectangle defects of
+            amplitude exp(j pi/4), noise free; n_f in {1, 2, 5, 10}
 Scenes are distinct on-grid point scatterers; noise is circular complex
 Gaussian scaled to a target SNR over all measured values (the scaling needs
 ||A x||, which the caller computes with its own operator).
@@ -60,6 +64,48 @@ WORKLOADS = {
         per_position=False, seed=1003, n_scat=50, amp=(0.5, 1.0), snr_db=15.0,
         iters=100, mu=0.1, back_wall=None),
 }
+
+
+# Sec. VII simulation (Table III).  Readings: the garbled "N_z = 20 MHz" entry
+# is the sampling rate; alpha = (0.65 f_c)^2 is the envelope exp(-alpha t^2), so
+# sigma_t = 1 / (0.65 f_c sqrt(2)) and the -6 dB fractional bandwidth is
+# 2 sqrt(2 ln 2) * 0.65 sqrt(2) / (2 pi) = 0.3445; N_t (not given) = 256 covers
+# the delays of the whole aperture from t0 = 10 us; depth pitch c / (2 f_s).
+SIM_FRAC_BW = 2.0 * math.sqrt(2.0 * math.log(2.0)) * 0.65 * math.sqrt(2.0) / (2.0 * math.pi)
+SIM50 = dict(nx=50, ny=50, nz=50, nt=256, c=5920.0, fs=20e6, fc=3.2e6, t0=10e-6,
+             z_start=29.6e-3, dx=0.5e-3, dy=0.5e-3, dz=5920.0 / (2 * 20e6),
+             frac_bw=SIM_FRAC_BW, band_db=40.0, win_x=-1, win_y=-1)
+SIM_NF = (1, 2, 5, 10)
+SIM_ITERS = 80
+SIM_MU = (0.1, 0.6)
+SIM_AMP = complex(math.cos(math.pi / 4), math.sin(math.pi / 4))
+
+
+def sim_geometry():
+    return dict(SIM50)
+
+
+def sim_line(g=None, depth=25, x_span=(10, 40)):
+    """Line defect along x at the centre row, one depth (Sec. VII, first scene)."""
+    g = g or SIM50
+    x = np.zeros((g["ny"], g["nx"], g["nz"]), dtype=np.complex128)
+    x[g["ny"] // 2, x_span[0]:x_span[1], depth] = SIM_AMP
+    return x
+
+
+def sim_rectangle(g=None, diag=40, width=40):
+    """Rectangle tilted by 45 degrees in the z-x plane: ``diag`` voxels of
+    length along the diagonal (diag / sqrt 2 steps in x and z) and ``width``
+    voxels along y, centred in the volume (Sec. VII, second scene)."""
+    g = g or SIM50
+    n = int(round(diag / math.sqrt(2.0)))
+    x0 = (g["nx"] - n) // 2
+    z0 = (g["nz"] - n) // 2
+    y0 = (g["ny"] - width) // 2
+    x = np.zeros((g["ny"], g["nx"], g["nz"]), dtype=np.complex128)
+    for i in range(n):
+        x[y0:y0 + width, x0 + i, z0 + i] = SIM_AMP
+    return x
 
 
 def batch_workload(seed=1004, n=64, max_lateral=64, max_depth=512):

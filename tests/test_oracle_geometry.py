@@ -128,3 +128,28 @@ def test_select_draw_by_hand():
     j = (v * 5) >> 64
     got = S.draw_subset(pool, 1, 1234567)
     assert got == [pool[j]]
+
+
+def test_sim50_replica_geometry():
+    """Table III readings: the Gaussian envelope exp(-alpha t^2) with alpha =
+    (0.65 f_c)^2 has the -6 dB bandwidth the workload uses; every delay of the
+    full aperture, with three pulse widths on either side, lies inside the
+    window [t0, t0 + N_t / f_s); the first voxel sits at the window start
+    (t0 = 10 us = 2 z_d / c0 up to 0.1%)."""
+    import math
+    from paper_2012_04534_amd import workloads as W
+    g = W.sim_geometry()
+    sigma_f, sigma_t = G.pulse_sigmas(g)
+    alpha = (0.65 * g["fc"]) ** 2
+    assert 1.0 / (2.0 * sigma_t ** 2) == pytest.approx(alpha, rel=1e-12)
+    tmin = float(G.tau(g, 0.0, 0.0, G.depth(g, 0)))
+    far = float(G.tau(g, (g["nx"] - 1) * g["dx"], (g["ny"] - 1) * g["dy"],
+                      G.depth(g, g["nz"] - 1)))
+    assert tmin == pytest.approx(g["t0"], rel=1e-3)
+    assert far + 3 * sigma_t < g["t0"] + g["nt"] / g["fs"]
+    assert np.count_nonzero(W.sim_line(g)) == 30
+    rect = W.sim_rectangle(g)
+    assert np.count_nonzero(rect) == 28 * 40
+    iy, ix, iz = np.nonzero(rect)
+    assert np.all(iz - ix == iz[0] - ix[0])          # 45 degrees in the z-x plane
+    assert np.allclose(rect[rect != 0], np.exp(1j * math.pi / 4))
