@@ -30,8 +30,11 @@ Readings taken where the paper is silent or garbled:
     dz = c / (2 f_s) is used so that depth steps are whole samples.
   * Window start.  Not given; t0 centres the delay span of the aperture:
     t0 = (tau_min + tau_max)/2 - N_t / (2 f_s).
-  * Directivity g.  The printed Gaussian is dimensionally garbled; g is taken as
-    1 inside the per-axis window |d_x| <= W_x, |d_y| <= W_y and 0 outside.
+  * Directivity g.  The printed Gaussian of Sec. VI is dimensionally garbled;
+    its printed x-derivative, -2 (x_1 - x_i) / (z_1 tan theta)^2 g, fixes it as
+    g = exp(-r^2 / (z tan theta)^2), r the lateral distance, theta the beam's
+    half-angle (geometry key ``theta``; 0 or absent: no Gaussian, g = 1).  The
+    per-axis window |d_x| <= W_x, |d_y| <= W_y applies in both cases.
 """
 import math
 
@@ -78,6 +81,16 @@ def window(g):
     wx = g["nx"] - 1 if g["win_x"] < 0 else min(g["win_x"], g["nx"] - 1)
     wy = g["ny"] - 1 if g["win_y"] < 0 else min(g["win_y"], g["ny"] - 1)
     return wx, wy
+
+
+def directivity(g, ddx, ddy, z):
+    """Gaussian beam amplitude for lateral offsets (ddx, ddy) in metres at depth z."""
+    ddx, ddy, z = (np.asarray(a, dtype=np.float64) for a in (ddx, ddy, z))
+    theta = g.get("theta", 0.0)
+    if not theta:
+        return np.ones(np.broadcast(ddx, ddy, z).shape)
+    w = z * math.tan(theta)
+    return np.exp(-(ddx * ddx + ddy * ddy) / (w * w))
 
 
 def depth(g, jz):

@@ -38,12 +38,13 @@ def entries(g, k, px, py, vx, vy, jz, unit_spectrum=False):
     vx, vy, jz = (np.asarray(a) for a in (vx, vy, jz))
     wx, wy = geometry.window(g)
     inside = (np.abs(px - vx) <= wx) & (np.abs(py - vy) <= wy)
-    delay = geometry.tau(g, (px - vx) * g["dx"], (py - vy) * g["dy"],
-                         geometry.depth(g, jz)) - geometry.t0(g)
+    ddx, ddy, z = (px - vx) * g["dx"], (py - vy) * g["dy"], geometry.depth(g, jz)
+    delay = geometry.tau(g, ddx, ddy, z) - geometry.t0(g)
+    beam = geometry.directivity(g, ddx, ddy, z) * inside
     f = geometry.bin_freq(g, k)
     amp = np.ones_like(f) if unit_spectrum else geometry.pulse_spectrum(g, k)
     phase = np.exp(-2j * math.pi * f[:, None] * delay[None, :])
-    return amp[:, None] * phase * inside[None, :]
+    return amp[:, None] * phase * beam[None, :]
 
 
 def _all_voxels(g):
@@ -128,35 +129,48 @@ def apply_AH_at(g, bins, y, vy, vx):
     return out
 
 
+def _beam_sq_sums(g):
+    """S[|dy|, |dx|] = sum over depths of g(d, z)^2 (N_z without a Gaussian beam)."""
+    wx, wy = geometry.window(g)
+    ady, adx = np.meshgrid(np.arange(wy + 1), np.arange(wx + 1), indexing="ij")
+    z = geometry.depth(g, np.arange(g["nz"]))
+    b = geometry.directivity(g, adx[..., None] * g["dx"], ady[..., None] * g["dy"], z)
+    return np.sum(b * b, axis=2)
+
+
 def frobenius_sq(g, bins):
     """||A||_F^2 counted from the structure of the entries.
 
-    Each non-zero entry of A has modulus |H_k|, so the squared Frobenius norm is
-    the sum over positions p and bins m of |H_{k_m(p)}|^2 times N_z times the
-    number of lateral voxels inside the window of p (Sec. IV-C norm bounds).
+    A non-zero entry has modulus |H_k| g(d, z), so the squared Frobenius norm
+    is the sum over positions p and bins m of |H_{k_m(p)}|^2 times the sum of
+    g^2 over the voxels inside the window of p (N_z times their lateral count
+    without a Gaussian beam; Sec. IV-C norm bounds).
     """
     wx, wy = geometry.window(g)
+    S = _beam_sq_sums(g)
     total = 0.0
     for py in range(g["ny"]):
-        ny_in = min(py + wy, g["ny"] - 1) - max(py - wy, 0) + 1
+        ry = np.abs(np.arange(max(py - wy, 0), min(py + wy, g["ny"] - 1) + 1) - py)
         for px in range(g["nx"]):
-            nx_in = min(px + wx, g["nx"] - 1) - max(px - wx, 0) + 1
+            rx = np.abs(np.arange(max(px - wx, 0), min(px + wx, g["nx"] - 1) + 1) - px)
             h = geometry.pulse_spectrum(g, _bins_at(bins, py, px))
-            total += float(np.sum(h * h)) * g["nz"] * nx_in * ny_in
+            total += float(np.sum(h * h)) * float(S[np.ix_(ry, rx)].sum())
     return total
 
 
 def central_column_sq(g, bins):
-    """Squared norm of one column of A: the voxel below the grid centre,
-    ((N_x - 1) // 2, (N_y - 1) // 2), at any depth.  Every position whose
-    window holds that voxel contributes sum_m |H_{k_m(p)}|^2."""
+    """Squared norms of the columns of the voxel below the grid centre,
+    ((N_x - 1) // 2, (N_y - 1) // 2), summed over depth.  Every position p
+    whose window holds that voxel contributes sum_m |H_{k_m(p)}|^2 times the
+    depth sum of g^2 at its offset."""
     wx, wy = geometry.window(g)
+    S = _beam_sq_sums(g)
     vx, vy = (g["nx"] - 1) // 2, (g["ny"] - 1) // 2
     total = 0.0
     for py in range(max(vy - wy, 0), min(vy + wy, g["ny"] - 1) + 1):
         for px in range(max(vx - wx, 0), min(vx + wx, g["nx"] - 1) + 1):
             h = geometry.pulse_spectrum(g, _bins_at(bins, py, px))
-            total += float(np.sum(h * h))
+            total += float(np.sum(h * h)) * float(S[abs(py - vy), abs(px - vx)])
     return total
 
 
@@ -166,15 +180,16 @@ def sigma_estimate(g, bins):
     ||A||_F / sqrt(N) <= sigma_max <= ||A||_F when N bounds the rank; the
     estimate is the geometric mean of the two bounds, ||A||_F / N^(1/4).
     Reading: N = min(rows, columns) = N_x N_y min(M, N_z).  The paper
-    approximates ||A||_F^2 by N_x N_y N_z times the squared norm of one
-    central column (boundary effects neglected); both versions are returned.
+    approximates ||A||_F^2 by N_x N_y times the squared norms of the central
+    columns summed over depth (boundary effects neglected); both versions are
+    returned.
     Returns dict(fro_sq, fro_sq_central, n, sigma_hat, sigma_hat_central).
     """
     m = bins.shape[-1]
     npos = g["nx"] * g["ny"]
     n = npos * min(m, g["nz"])
     fro = frobenius_sq(g, bins)
-    cen = npos * g["nz"] * central_column_sq(g, bins)
+    cen = npos * central_column_sq(g, bins)
     return dict(fro_sq=fro, fro_sq_central=cen, n=n,
                 sigma_hat=math.sqrt(fro) / n ** 0.25,
                 sigma_hat_central=math.sqrt(cen) / n ** 0.25)

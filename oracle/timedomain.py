@@ -1,7 +1,7 @@
 """Oracle time-domain pulse-echo A-scans (test infrastructure only).
 
 Sec. II-A pulse-echo model: the analytic A-scan at position p is the sum over
-reflectors of a_v g h(t - tau); sampling at t = t0 + n / f_s gives b_p[n].
+reflectors of a_v g h(t - tau) (g: the beam amplitude of the geometry); sampling at t = t0 + n / f_s gives b_p[n].
 The DFT of one recorded window equals the frequency-domain operator exactly
 when the record is the periodised echo (Poisson summation), so the samples
 are summed over whole-window shifts q in {-2..2}; terms further out are below
@@ -32,12 +32,13 @@ def ascans(g, x, shifts=2):
             sel = nz_mask & (np.abs(px - vx) <= wx) & (np.abs(py - vy) <= wy)
             if not np.any(sel):
                 continue
-            delay = geometry.tau(g, (px - vx[sel]) * g["dx"],
-                                 (py - vy[sel]) * g["dy"],
-                                 geometry.depth(g, jz[sel]))
+            ddx, ddy = (px - vx[sel]) * g["dx"], (py - vy[sel]) * g["dy"]
+            z = geometry.depth(g, jz[sel])
+            delay = geometry.tau(g, ddx, ddy, z)
+            refl = x[sel] * geometry.directivity(g, ddx, ddy, z)
             acc = np.zeros(g["nt"], dtype=np.complex128)
             for q in range(-shifts, shifts + 1):
                 t = t_start + (n[None, :] + q * g["nt"]) / g["fs"] - delay[:, None]
-                acc += (x[sel][:, None] * geometry.pulse_time(g, t)).sum(axis=0)
+                acc += (refl[:, None] * geometry.pulse_time(g, t)).sum(axis=0)
             b[py, px] = acc
     return b

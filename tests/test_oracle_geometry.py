@@ -153,3 +153,37 @@ def test_sim50_replica_geometry():
     iy, ix, iz = np.nonzero(rect)
     assert np.all(iz - ix == iz[0] - ix[0])          # 45 degrees in the z-x plane
     assert np.allclose(rect[rect != 0], np.exp(1j * math.pi / 4))
+
+
+def test_directivity_matches_printed_derivative():
+    """Sec. VI prints dg/dx_1 = -2 (x_1 - x_i) / (z_1 tan theta)^2 g for the
+    Gaussian beam; a central difference of the oracle's g reproduces it, so
+    g = exp(-r^2 / (z tan theta)^2) (the printed g itself is garbled)."""
+    g = W.geometry(4, 4, 4, 64)
+    g["theta"] = math.radians(30.0)
+    z = 31.2e-3
+    for ddx, ddy in ((0.0, 0.0), (2.5e-3, 0.0), (-4e-3, 1.5e-3), (9e-3, -7e-3)):
+        h = 1e-7
+        fd = (G.directivity(g, ddx + h, ddy, z) - G.directivity(g, ddx - h, ddy, z)) / (2 * h)
+        printed = -2.0 * ddx / (z * math.tan(g["theta"])) ** 2 * G.directivity(g, ddx, ddy, z)
+        assert float(fd) == pytest.approx(float(printed), rel=1e-6, abs=1e-9)
+
+
+def test_directivity_shape():
+    """The beam falls to 1/e at lateral distance z tan theta, is separable in
+    x and y, is 1 on axis, and tends to 1 everywhere as theta -> 90 deg; with
+    no theta the geometry has no Gaussian factor."""
+    g = W.geometry(4, 4, 4, 64)
+    g["theta"] = math.radians(30.0)
+    z = 40e-3
+    r = z * math.tan(g["theta"])
+    assert float(G.directivity(g, r, 0.0, z)) == pytest.approx(math.exp(-1.0), rel=1e-14)
+    assert float(G.directivity(g, 0.6 * r, 0.8 * r, z)) == pytest.approx(math.exp(-1.0), rel=1e-14)
+    a = G.directivity(g, 3e-3, 5e-3, z)
+    assert float(a) == pytest.approx(float(G.directivity(g, 3e-3, 0.0, z) *
+                                           G.directivity(g, 0.0, 5e-3, z)), rel=1e-14)
+    assert float(G.directivity(g, 0.0, 0.0, z)) == 1.0
+    g["theta"] = math.radians(89.9999)
+    assert float(G.directivity(g, 10e-3, 10e-3, z)) > 1.0 - 1e-9
+    g["theta"] = 0.0
+    assert float(G.directivity(g, 10e-3, 10e-3, z)) == 1.0

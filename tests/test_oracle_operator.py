@@ -30,10 +30,13 @@ def tiny_cases():
             out.append((g, bins))
     g2 = W.geometry(9, 1, 20, 64, win_x=3)      # B-scan, windowed
     out.append((g2, S.select_freqs(g2, 5, True, 5)))
+    g3 = tiny(win=2)                              # Gaussian beam (half-angle 5 deg)
+    g3["theta"] = math.radians(5.0)
+    out.append((g3, S.select_freqs(g3, 6, True, 13)))
     return out
 
 
-@pytest.mark.parametrize("case", range(5))
+@pytest.mark.parametrize("case", range(6))
 def test_adjointness_dense_and_direct(case):
     """P1: <A x, y> = <x, A^H y> to 1e-12 (dense and direct-sum modes)."""
     g, bins = tiny_cases()[case]
@@ -52,10 +55,13 @@ def test_adjointness_dense_and_direct(case):
 
 
 @pytest.mark.parametrize("win", [-1, 2])
-def test_full_spectrum_equals_dft_of_time_domain_model(win):
+@pytest.mark.parametrize("theta_deg", [0.0, 4.0])
+def test_full_spectrum_equals_dft_of_time_domain_model(win, theta_deg):
     """P3 (check c): with every non-negative bin selected, A x at each position
-    equals numpy.fft of the periodised sampled pulse-echo A-scan."""
+    equals numpy.fft of the periodised sampled pulse-echo A-scan (also with a
+    Gaussian beam, which scales each echo by a real amplitude)."""
     g = tiny(nx=5, ny=4, nz=16, nt=64, win=win)
+    g["theta"] = math.radians(theta_deg)
     x = W.scene(g, 6, amp=(0.5, 1.0), seed=3, phase=0.7)
     x[1, 2, 5] = 0.3 - 0.8j
     bins = np.arange(0, g["nt"] // 2 + 1)
@@ -94,7 +100,7 @@ def test_saft_special_case():
     np.testing.assert_allclose(img, g["nt"] * b[5:5 + g["nz"]], rtol=0, atol=1e-10)
 
 
-@pytest.mark.parametrize("case", range(5))
+@pytest.mark.parametrize("case", range(6))
 def test_frobenius_count_and_norm_bounds(case):
     """P6: ||A||_F^2 equals the structural count; L lies in [||A||_F^2/N, ||A||_F^2]."""
     g, bins = tiny_cases()[case]
@@ -106,20 +112,19 @@ def test_frobenius_count_and_norm_bounds(case):
     assert fro / N <= L * (1 + 1e-12) and L <= fro * (1 + 1e-12)
 
 
-@pytest.mark.parametrize("case", range(5))
+@pytest.mark.parametrize("case", range(6))
 def test_sigma_estimate_against_dense(case):
-    """Sec. IV-C estimate: the central column norm is that column of the dense
-    matrix, sigma_hat is the geometric mean of the two Frobenius bounds, and
+    """Sec. IV-C estimate: the central columns' norms (summed over depth) are
+    those of the dense matrix, sigma_hat is the geometric mean of the two Frobenius bounds, and
     N = min(rows, cols) keeps the lower bound below sigma_max (singular values
     of the dense matrix)."""
     g, bins = tiny_cases()[case]
     A = O.dense_A(g, bins)
     est = O.sigma_estimate(g, bins)
     vx, vy = (g["nx"] - 1) // 2, (g["ny"] - 1) // 2
-    for jz in (0, g["nz"] - 1):
-        col = (vy * g["nx"] + vx) * g["nz"] + jz
-        assert est["fro_sq_central"] / (g["nx"] * g["ny"] * g["nz"]) == \
-            pytest.approx(float(np.sum(np.abs(A[:, col]) ** 2)), rel=1e-12)
+    col0 = (vy * g["nx"] + vx) * g["nz"]
+    cols = float(np.sum(np.abs(A[:, col0:col0 + g["nz"]]) ** 2))
+    assert est["fro_sq_central"] / (g["nx"] * g["ny"]) == pytest.approx(cols, rel=1e-12)
     assert est["n"] == min(A.shape)
     fro = float(np.sum(np.abs(A) ** 2))
     smax = float(np.linalg.svd(A, compute_uv=False)[0])
