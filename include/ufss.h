@@ -60,13 +60,18 @@ extern "C" {
 /* Scan and pulse geometry (SI units).  Paper Sec. II-A (grids, delay, pulse),
  * Sec. VI (Gabor pulse).  t0 = NaN selects the window that centres the delay
  * span of the aperture: t0 = (tau_min + tau_max)/2 - nt/(2 fs).  ny = 1 is a
- * B-scan.  win_x / win_y < 0 means the full grid. */
+ * B-scan.  win_x / win_y < 0 means the full grid.  theta > 0 adds the Gaussian
+ * beam of Sec. VI / VII: every entry of A is scaled by
+ * g = exp(-r^2 / (z tan theta)^2), r the lateral distance between position and
+ * voxel, z the voxel depth (the form whose x-derivative the paper prints);
+ * theta = 0: g = 1.  The window applies either way. */
 typedef struct ufss_geom {
     int32_t nx, ny, nz, nt;
     double dx, dy, dz, z_start, t0, c, fs, fc, frac_bw, band_db;
     int32_t win_x, win_y;
     int32_t dtype;      /* UFSS_F32 or UFSS_BF16 */
     int32_t algo;       /* UFSS_ALGO_* */
+    double theta;       /* beam half-angle in radians, [0, pi/2); 0 = none */
 } ufss_geom;
 
 typedef struct ufss_plan_s* ufss_plan_t;
@@ -161,9 +166,11 @@ int ufss_sample_bins(const ufss_geom* g, int32_t m, int32_t strategy, uint64_t s
  * Sec. IV-C, estimation by the geometric mean of the Frobenius bounds).  Host
  * only, FP64, no device work.
  *   fro_sq            ||A||_F^2, exact: sum over positions p and bins of
- *                     H_k^2 N_z (lateral voxels inside the window of p)
- *   fro_sq_central    the paper's approximation: N_x N_y N_z times the squared
- *                     norm of the column of voxel ((nx-1)/2, (ny-1)/2)
+ *                     H_k^2 times the sum of g^2 over the voxels inside the
+ *                     window of p (their count without a Gaussian beam)
+ *   fro_sq_central    the paper's approximation: N_x N_y times the squared
+ *                     norms of the columns of voxel ((nx-1)/2, (ny-1)/2),
+ *                     summed over depth
  *   n                 N = N_x N_y min(m, N_z), a bound on the rank of A
  *   sigma_hat         sqrt(fro_sq) / N^(1/4)
  *   sigma_hat_central sqrt(fro_sq_central) / N^(1/4)

@@ -243,6 +243,8 @@ int fista_batched(int n, Plan* const* plans, const cf32* const* ys, cf32* const*
         if (!plans[i] || !ys[i] || !xs[i]) fail(UFSS_ERR_INVALID_ARG, "NULL plan or buffer");
         if (plans[i]->algo != UFSS_ALGO_GEMM)
             fail(UFSS_ERR_UNSUPPORTED, "batched FISTA needs GEMM-path plans");
+        if (plans[i]->d_amp)
+            fail(UFSS_ERR_UNSUPPORTED, "batched FISTA does not take a Gaussian beam");
         for (int j = 0; j < i; ++j)
             if (plans[j] == plans[i]) fail(UFSS_ERR_INVALID_ARG, "a plan appears twice in the batch");
     }
@@ -448,6 +450,7 @@ static std::string shape_key(const Plan& P) {
     std::ostringstream o;
     o << "gfx950/nx" << P.g.nx << "/ny" << P.g.ny << "/nz" << P.g.nz << "/mu" << P.ubins_h.size()
       << "/m" << P.m << "/wx" << P.d.wx << "/wy" << P.d.wy << "/" << (P.dtype == UFSS_BF16 ? "bf16" : "f32");
+    if (P.d_amp) o << "/beam";       // beam plans run other kernel variants
     return o.str();
 }
 

@@ -741,8 +741,10 @@ void launch_adjoint_gemm_bf16(const Plan& P, cf32* out, hipStream_t s, bool sum)
 }
 
 // Phasor tables: entry (|d_y|, |d_x|, z, k) = cos / sin(2 pi kb[k] u(|d_y|, |d_x|, z))
-// rounded to BF16, zero past nz or mu, written in both kernels' tile layouts.
-__global__ void build_ptab_kernel(const uint32_t* __restrict__ u, const int* __restrict__ kb, int wx,
+// times the beam amplitude (when there is one), rounded to BF16, zero past nz
+// or mu, written in both kernels' tile layouts.
+__global__ void build_ptab_kernel(const uint32_t* __restrict__ u, const float* __restrict__ amp,
+                                  const int* __restrict__ kb, int wx,
                                   int wy, int nz, int mu, int nzc, int nkc, __bf16* __restrict__ tf,
                                   __bf16* __restrict__ ta) {
     const int kw = nkc * ZCB, zw = nzc * ZCB;
@@ -754,7 +756,14 @@ __global__ void build_ptab_kernel(const uint32_t* __restrict__ u, const int* __r
         const int z = (int)(r % zw);
         const int64_t dxy = r / zw;                   // |d_y| * (wx + 1) + |d_x|
         float c = 0.f, sn = 0.f;
-        if (z < nz && k < mu) sincos_turns((uint32_t)kb[k] * u[dxy * nz + z], c, sn);
+        if (z < nz && k < mu) {
+            sincos_turns((uint32_t)kb[k] * u[dxy * nz + z], c, sn);
+            if (amp) {
+                const float gb = amp[dxy * nz + z];
+                c *= gb;
+                sn *= gb;
+            }
+        }
         if (k < mu) {
             __bf16* f = tf + ((dxy * nzc + z / ZCB) * mu + k) * 64 + z % ZCB;
             f[0] = (__bf16)c;
@@ -784,7 +793,8 @@ static void bf16_build_tables(Plan& P) {
     }
     const int64_t n = dxy * nzc * ZCB * nkc * ZCB;
     const int blocks = (int)std::min<int64_t>((n + 255) / 256, 65536);
-    hipLaunchKernelGGL(build_ptab_kernel, dim3(blocks), dim3(256), 0, nullptr, P.d_u, P.d_ubins, P.d.wx,
+    hipLaunchKernelGGL(build_ptab_kernel, dim3(blocks), dim3(256), 0, nullptr, P.d_u, P.d_amp,
+                       P.d_ubins, P.d.wx,
                        P.d.wy, P.g.nz, mu, nzc, nkc, static_cast<__bf16*>(tf), static_cast<__bf16*>(ta));
     UFSS_HIP(hipGetLastError());
     UFSS_HIP(hipDeviceSynchronize());
@@ -795,6 +805,11 @@ static void bf16_build_tables(Plan& P) {
 }
 
 void bf16_set_tables(Plan& P, int enable) {
+    const bool bf_gemm = P.dtype == UFSS_BF16 && P.algo == UFSS_ALGO_GEMM;
+    // the in-kernel phasor generation has no beam amplitude: a Gaussian beam
+    // needs the tables
+    if (bf_gemm && P.d_amp && !enable)
+        fail(UFSS_ERR_UNSUPPORTED, "a BF16 plan with a Gaussian beam needs its phasor tables");
     UFSS_HIP(hipDeviceSynchronize());
     if (P.d_ptab_f) UFSS_HIP(hipFree(P.d_ptab_f));
     if (P.d_ptab_a) UFSS_HIP(hipFree(P.d_ptab_a));
@@ -803,6 +818,8 @@ void bf16_set_tables(Plan& P, int enable) {
     P.ptab_bytes = 0;
     if (P.dtype != UFSS_BF16 || P.algo != UFSS_ALGO_GEMM) return;
     if (enable) bf16_build_tables(P);
+    if (P.d_amp && !P.d_ptab_f)
+        fail(UFSS_ERR_UNSUPPORTED, "BF16 phasor tables do not fit; a Gaussian beam needs them");
     // without tables the kernels also stage the delay slab: fall back to one-row
     // tiles where two rows no longer fit
     if (!bf16_rows_ok(P, P.bf_fwd_rows, P.bf_adj_rows)) P.bf_fwd_rows = P.bf_adj_rows = 1;

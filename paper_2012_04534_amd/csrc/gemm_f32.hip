@@ -87,6 +87,7 @@ struct FwdArgs {
     const cf32* x;
     cf32* yraw;            // [split][npos][mu]
     const uint32_t* u;     // [wy+1][wx+1][nz]
+    const float* amp;      // beam amplitude, same layout (DIR kernels only)
     const int* kb;         // [mu]
     int nx, ny, nz, wx, wy, mu;
     int sw;                // sub-tile width (4 or 16)
@@ -101,7 +102,9 @@ struct FwdArgs {
 };
 
 // ZC: the depth chunk a.zc as a compile-time constant (16, 8 or 4).
-template <int NP, int ZC>
+// DIR: scale each phasor by the beam amplitude g(|d_x|, |d_y|, z) (staged in
+// LDS beside the delay table).
+template <int NP, int ZC, bool DIR = false>
 __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int nblk, unsigned char* smem) {
     constexpr int zc = ZC;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -111,6 +114,7 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
     const int cs = zc + 1;                  // padded cell stride (complex)
     cf32* halo = reinterpret_cast<cf32*>(smem);
     uint32_t* ulds = reinterpret_cast<uint32_t*>(halo + (size_t)tpy * hc * cs);
+    float* glds = reinterpret_cast<float*>(ulds + (size_t)(a.wx + 1) * zc);
 
     // block -> (split, bin tile, lateral tile); consecutive tiles of one split
     // and bin tile stay on one XCD (blocks are dealt round-robin to 8 XCDs).
@@ -157,7 +161,9 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
             for (int t = threadIdx.x; t < (a.wx + 1) * zc; t += blockDim.x) {
                 int adx = t / zc, zz = t - adx * zc;
                 int z = z0 + zz;
-                ulds[t] = z < a.nz ? a.u[((int64_t)ady * (a.wx + 1) + adx) * a.nz + z] : 0u;
+                const int64_t o = ((int64_t)ady * (a.wx + 1) + adx) * a.nz + z;
+                ulds[t] = z < a.nz ? a.u[o] : 0u;
+                if (DIR) glds[t] = z < a.nz ? a.amp[o] : 0.f;
             }
             __syncthreads();
             if (!wave_active) continue;
@@ -184,6 +190,11 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
                 for (int j = 0; j < zc / 4; ++j) {
                     float c, sn;
                     phasor(kbin * urow[4 * j + kq], c, sn);
+                    if (DIR) {
+                        const float gv = glds[adx * zc + 4 * j + kq];
+                        c *= gv;
+                        sn *= gv;
+                    }
                     cz[j] = c;
                     bmz[j] = -sn - c;
                     bpz[j] = c - sn;
@@ -221,10 +232,10 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
     }
 }
 
-template <int NP, int ZC>
+template <int NP, int ZC, bool DIR = false>
 __global__ __launch_bounds__(512) void fwd_gemm_f32_kernel(FwdArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    fwd_f32_body<NP, ZC>(a, blockIdx.x, gridDim.x, smem);
+    fwd_f32_body<NP, ZC, DIR>(a, blockIdx.x, gridDim.x, smem);
 }
 
 // Grouped launch: block -> (plan index, block index inside that plan's grid).
@@ -244,6 +255,7 @@ struct AdjArgs {
     const cf32* r;         // H-scaled operand [npos][mu]
     cf32* out;             // [ny][nx][nz]
     const uint32_t* u;
+    const float* amp;      // beam amplitude, same layout as u (DIR kernels only)
     const int* kb;
     int nx, ny, nz, wx, wy, mu;
     int sw, ntx, nty, nzt; // lateral tiles, depth tiles (of 64 * NZ)
@@ -255,7 +267,8 @@ struct AdjArgs {
 };
 
 // KC: the bin chunk a.kc as a compile-time constant (16, 8 or 4).
-template <int NP, int NZ, int KC>
+// DIR: scale each phasor by the beam amplitude (staged in LDS after the bins).
+template <int NP, int NZ, int KC, bool DIR = false>
 __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int nblk, unsigned char* smem) {
     constexpr int kc = KC;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -267,6 +280,7 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
     cf32* halo = reinterpret_cast<cf32*>(smem);
     uint32_t* ulds = reinterpret_cast<uint32_t*>(halo + (size_t)tpy * hc * cs);
     int* klds = reinterpret_cast<int*>(ulds + (size_t)(a.wx + 1) * zspan);
+    float* glds = reinterpret_cast<float*>(klds + kc);
 
     int per_xcd = nblk / 8;
     if (per_xcd * 8 == nblk) b = (b % 8) * per_xcd + b / 8;
@@ -305,7 +319,9 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
             for (int t = threadIdx.x; t < (a.wx + 1) * zspan; t += 256) {
                 int adx = t / zspan, zz = t - adx * zspan;
                 int z = zw0 + zz;
-                ulds[t] = z < a.nz ? a.u[((int64_t)ady * (a.wx + 1) + adx) * a.nz + z] : 0u;
+                const int64_t o = ((int64_t)ady * (a.wx + 1) + adx) * a.nz + z;
+                ulds[t] = z < a.nz ? a.u[o] : 0u;
+                if (DIR) glds[t] = z < a.nz ? a.amp[o] : 0.f;
             }
             for (int t = threadIdx.x; t < kc; t += 256)
                 klds[t] = (k0 + t < a.mu) ? a.kb[k0 + t] : 0;
@@ -322,8 +338,12 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
             for (int dx = dx_lo; dx <= dx_hi; ++dx) {
                 const int adx = dx < 0 ? -dx : dx;
                 uint32_t uz[NZ];
+                float gz[NZ];
 #pragma unroll
-                for (int q = 0; q < NZ; ++q) uz[q] = ulds[adx * zspan + wave * NZ * 16 + q * 16 + i];
+                for (int q = 0; q < NZ; ++q) {
+                    uz[q] = ulds[adx * zspan + wave * NZ * 16 + q * 16 + i];
+                    gz[q] = DIR ? glds[adx * zspan + wave * NZ * 16 + q * 16 + i] : 1.f;
+                }
                 const cf32* hrow = halo + ((((vy0 + iy + dy) & (tpy - 1)) * hc) + ix + a.wx + dx) * cs;
 #pragma unroll
                 for (int kk = 0; kk < kc; kk += 4) {
@@ -340,6 +360,10 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
                     for (int q = 0; q < NZ; ++q) {
                         float c, sn;
                         phasor(k * uz[q], c, sn);
+                        if (DIR) {
+                            c *= gz[q];
+                            sn *= gz[q];
+                        }
                         const float bm = sn - c, bp = c + sn;
 #pragma unroll
                         for (int s = 0; s < NP; ++s) {
@@ -375,20 +399,20 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
             }
 }
 
-template <int NP, int NZ, int KC>
+template <int NP, int NZ, int KC, bool DIR = false>
 __global__ __launch_bounds__(256) void adj_gemm_f32_kernel(AdjArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    adj_f32_body<NP, NZ, KC>(a, blockIdx.x, gridDim.x, smem);
+    adj_f32_body<NP, NZ, KC, DIR>(a, blockIdx.x, gridDim.x, smem);
 }
 
 // Two sub-tiles per wave: registers capped for 6 waves per SIMD, which pays
 // when a small LDS chunk admits that many workgroups per CU (measured on the
 // 32 x 32 and 64 x 64 C-scans).
-template <int NZ, int KC>
+template <int NZ, int KC, bool DIR = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8)))
 void adj_gemm_f32_kernel_np2(AdjArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    adj_f32_body<2, NZ, KC>(a, blockIdx.x, gridDim.x, smem);
+    adj_f32_body<2, NZ, KC, DIR>(a, blockIdx.x, gridDim.x, smem);
 }
 
 // Grouped launch: block -> (plan index, block index inside that plan's grid).
@@ -466,6 +490,7 @@ static int fwd_args(const Plan& P, const cf32* x, FwdArgs& a, size_t& lds, int n
     a.x = x;
     a.yraw = P.d_yraw;
     a.u = P.d_u;
+    a.amp = P.d_amp;
     a.kb = P.d_ubins;
     a.nx = P.g.nx;
     a.ny = P.g.ny;
@@ -483,8 +508,9 @@ static int fwd_args(const Plan& P, const cf32* x, FwdArgs& a, size_t& lds, int n
     a.npos = P.npos;
     const int hc = tpx + 2 * a.wx;
     int zc = P.fwd_zc == 8 ? 8 : 16;
+    const size_t tab = P.d_amp ? 8 : 4;      // delay (+ beam) table bytes per entry
     auto lds_of = [&](int z) {
-        return (size_t)tpy * hc * (z + 1) * sizeof(cf32) + (size_t)(a.wx + 1) * z * 4;
+        return (size_t)tpy * hc * (z + 1) * sizeof(cf32) + (size_t)(a.wx + 1) * z * tab;
     };
     while (zc > 4 && lds_of(zc) > kLdsMax) zc /= 2;   // powers of two: the staging needs zc | blockDim
     lds = lds_of(zc);
@@ -500,6 +526,7 @@ static int adj_args(const Plan& P, cf32* out, AdjArgs& a, size_t& lds, int np) {
     a.r = static_cast<const cf32*>(P.d_rop);
     a.out = out;
     a.u = P.d_u;
+    a.amp = P.d_amp;
     a.kb = P.d_ubins;
     a.nx = P.g.nx;
     a.ny = P.g.ny;
@@ -515,8 +542,9 @@ static int adj_args(const Plan& P, cf32* out, AdjArgs& a, size_t& lds, int np) {
     a.nzt = (a.nz + zspan - 1) / zspan;
     const int hc = tpx + 2 * a.wx;
     int kc = P.adj_kc == 8 ? 8 : 16;
+    const size_t tab = P.d_amp ? 8 : 4;      // delay (+ beam) table bytes per entry
     auto lds_of = [&](int k) {
-        return (size_t)tpy * hc * (k + 1) * sizeof(cf32) + (size_t)(a.wx + 1) * zspan * 4 +
+        return (size_t)tpy * hc * (k + 1) * sizeof(cf32) + (size_t)(a.wx + 1) * zspan * tab +
                (size_t)k * 4;
     };
     while (kc > 4 && lds_of(kc) > kLdsMax) kc /= 2;   // powers of two (staging)
@@ -537,11 +565,19 @@ void launch_forward_gemm(const Plan& P, const cf32* x, hipStream_t s) {
     fwd_args(P, x, a, lds, np);
     const dim3 grid(a.nblk), block(64 * a.nw);
 #define UFSS_FWD(NPV, ZCV) hipLaunchKernelGGL((fwd_gemm_f32_kernel<NPV, ZCV>), grid, block, lds, s, a)
-    if (np == 4) {
+#define UFSS_FWDG(NPV, ZCV) hipLaunchKernelGGL((fwd_gemm_f32_kernel<NPV, ZCV, true>), grid, block, lds, s, a)
+    if (a.amp) {
+        if (np == 4) {
+            if (a.zc == 16) UFSS_FWDG(4, 16); else if (a.zc == 8) UFSS_FWDG(4, 8); else UFSS_FWDG(4, 4);
+        } else {
+            if (a.zc == 16) UFSS_FWDG(2, 16); else if (a.zc == 8) UFSS_FWDG(2, 8); else UFSS_FWDG(2, 4);
+        }
+    } else if (np == 4) {
         if (a.zc == 16) UFSS_FWD(4, 16); else if (a.zc == 8) UFSS_FWD(4, 8); else UFSS_FWD(4, 4);
     } else {
         if (a.zc == 16) UFSS_FWD(2, 16); else if (a.zc == 8) UFSS_FWD(2, 8); else UFSS_FWD(2, 4);
     }
+#undef UFSS_FWDG
 #undef UFSS_FWD
     UFSS_HIP(hipGetLastError());
 }
@@ -554,11 +590,21 @@ void launch_adjoint_gemm(const Plan& P, cf32* out, hipStream_t s, bool sum) {
     const dim3 grid(a.nblk), block(256);
 #define UFSS_ADJ(NPV, KCV) hipLaunchKernelGGL((adj_gemm_f32_kernel<NPV, kAdjNZ, KCV>), grid, block, lds, s, a)
 #define UFSS_ADJ2(KCV) hipLaunchKernelGGL((adj_gemm_f32_kernel_np2<kAdjNZ, KCV>), grid, block, lds, s, a)
-    if (np == 4) {
+#define UFSS_ADJG(NPV, KCV) hipLaunchKernelGGL((adj_gemm_f32_kernel<NPV, kAdjNZ, KCV, true>), grid, block, lds, s, a)
+#define UFSS_ADJ2G(KCV) hipLaunchKernelGGL((adj_gemm_f32_kernel_np2<kAdjNZ, KCV, true>), grid, block, lds, s, a)
+    if (a.amp) {
+        if (np == 4) {
+            if (a.kc == 16) UFSS_ADJG(4, 16); else if (a.kc == 8) UFSS_ADJG(4, 8); else UFSS_ADJG(4, 4);
+        } else {
+            if (a.kc == 16) UFSS_ADJ2G(16); else if (a.kc == 8) UFSS_ADJ2G(8); else UFSS_ADJ2G(4);
+        }
+    } else if (np == 4) {
         if (a.kc == 16) UFSS_ADJ(4, 16); else if (a.kc == 8) UFSS_ADJ(4, 8); else UFSS_ADJ(4, 4);
     } else {
         if (a.kc == 16) UFSS_ADJ2(16); else if (a.kc == 8) UFSS_ADJ2(8); else UFSS_ADJ2(4);
     }
+#undef UFSS_ADJ2G
+#undef UFSS_ADJG
 #undef UFSS_ADJ2
 #undef UFSS_ADJ
     UFSS_HIP(hipGetLastError());
@@ -575,6 +621,7 @@ size_t desc_size(GemmKind k) {
 }
 
 int make_desc(GemmKind k, const Plan& P, const void* in, void* out, void* desc, size_t* lds) {
+    if (P.d_amp) fail(UFSS_ERR_UNSUPPORTED, "grouped launches do not take a Gaussian beam");
     switch (k) {
         case GemmKind::FwdF32:
             return fwd_args(P, static_cast<const cf32*>(in), *static_cast<FwdArgs*>(desc), *lds, kGroupNP);

@@ -76,6 +76,7 @@ struct Plan {
     int* d_map = nullptr;          // per (p, m): index into the union list
     float* d_hsel = nullptr;       // H_k per selection entry [m] or [npos*m]
     uint32_t* d_u = nullptr;       // integer-turn delay table [wy+1][wx+1][nz]
+    float* d_amp = nullptr;        // Gaussian beam amplitude, same layout (theta > 0)
     // device workspace
     cf32* d_yraw = nullptr;        // GEMM output over union bins [npos][mu]
     void* d_rop = nullptr;         // adjoint operand (H-scaled), [npos][mu] f32 or bf16

@@ -30,8 +30,9 @@ __device__ __forceinline__ void phasor_p(uint32_t ku, float& c, float& s) {
 static constexpr int kMB = 32;   // bins per forward workgroup
 
 __global__ __launch_bounds__(256) void fwd_phasor_kernel(
-    const cf32* __restrict__ x, const uint32_t* __restrict__ ut, const int* __restrict__ bins,
-    const float* __restrict__ hsel, const cf32* __restrict__ ymeas, cf32* __restrict__ y,
+    const cf32* __restrict__ x, const uint32_t* __restrict__ ut, const float* __restrict__ amp,
+    const int* __restrict__ bins, const float* __restrict__ hsel, const cf32* __restrict__ ymeas,
+    cf32* __restrict__ y,
     double* __restrict__ part, int nx, int ny, int nz, int wx, int wy, int m, int ngroups) {
     __shared__ float red[2 * kMB][4];
     const int p = blockIdx.x / ngroups, grp = blockIdx.x - p * ngroups;
@@ -55,9 +56,15 @@ __global__ __launch_bounds__(256) void fwd_phasor_kernel(
     int w = (int)(t / nz), z = (int)(t - (int64_t)w * nz);
     for (; t < total; t += 256) {
         const int vx = vx_lo + w % nvx, vy = vy_lo + w / nvx;
-        const cf32 xv = x[((int64_t)vy * nx + vx) * nz + z];
+        cf32 xv = x[((int64_t)vy * nx + vx) * nz + z];
         const int adx = px > vx ? px - vx : vx - px, ady = py > vy ? py - vy : vy - py;
-        const uint32_t u = ut[((int64_t)ady * (wx + 1) + adx) * nz + z];
+        const int64_t o = ((int64_t)ady * (wx + 1) + adx) * nz + z;
+        const uint32_t u = ut[o];
+        if (amp) {                       // Gaussian beam: g scales every bin's term
+            const float gb = amp[o];
+            xv.re *= gb;
+            xv.im *= gb;
+        }
 #pragma unroll
         for (int j = 0; j < kMB; ++j) {
             float c, s;
@@ -119,7 +126,7 @@ void launch_forward_phasor(const Plan& P, const cf32* x, cf32* y, const cf32* ym
     const int ngroups = (P.m + kMB - 1) / kMB;
     const int nblk = P.npos * ngroups;
     if (nblk > P.part_cap) fail(UFSS_ERR_UNSUPPORTED, "too many positions for the phasor path");
-    hipLaunchKernelGGL(fwd_phasor_kernel, dim3(nblk), dim3(256), 0, s, x, P.d_u, P.d_bins,
+    hipLaunchKernelGGL(fwd_phasor_kernel, dim3(nblk), dim3(256), 0, s, x, P.d_u, P.d_amp, P.d_bins,
                        P.d_hsel, ymeas, y, part, P.g.nx, P.g.ny, P.g.nz, P.d.wx, P.d.wy, P.m,
                        ngroups);
     UFSS_HIP(hipGetLastError());
@@ -128,8 +135,9 @@ void launch_forward_phasor(const Plan& P, const cf32* x, cf32* y, const cf32* ym
 int phasor_forward_blocks(const Plan& P) { return P.npos * ((P.m + kMB - 1) / kMB); }
 
 __global__ __launch_bounds__(256) void adj_phasor_kernel(
-    const cf32* __restrict__ rop, const uint32_t* __restrict__ ut, const int* __restrict__ bins,
-    cf32* __restrict__ out, int nx, int ny, int nz, int wx, int wy, int m, int nzc) {
+    const cf32* __restrict__ rop, const uint32_t* __restrict__ ut, const float* __restrict__ amp,
+    const int* __restrict__ bins, cf32* __restrict__ out, int nx, int ny, int nz, int wx, int wy,
+    int m, int nzc) {
     const int v = blockIdx.x / nzc, zc = blockIdx.x - v * nzc;
     const int vx = v % nx, vy = v / nx;
     const int z = zc * 256 + threadIdx.x;
@@ -141,7 +149,8 @@ __global__ __launch_bounds__(256) void adj_phasor_kernel(
         const int ady = py > vy ? py - vy : vy - py;
         for (int px = px_lo; px <= px_hi; ++px) {
             const int adx = px > vx ? px - vx : vx - px;
-            const uint32_t u = ut[((int64_t)ady * (wx + 1) + adx) * nz + zl];
+            const int64_t o = ((int64_t)ady * (wx + 1) + adx) * nz + zl;
+            const uint32_t u = ut[o];
             const int64_t prow = ((int64_t)py * nx + px) * m;
             float in_re = 0.f, in_im = 0.f;
             for (int mi = 0; mi < m; ++mi) {
@@ -153,8 +162,9 @@ __global__ __launch_bounds__(256) void adj_phasor_kernel(
                 in_re += rv.re * c - rv.im * s;
                 in_im += rv.re * s + rv.im * c;
             }
-            acc_re += in_re;
-            acc_im += in_im;
+            const float gb = amp ? amp[o] : 1.f;
+            acc_re += gb * in_re;
+            acc_im += gb * in_im;
         }
     }
     if (z < nz) out[(int64_t)v * nz + z] = cf32{acc_re, acc_im};
@@ -163,7 +173,7 @@ __global__ __launch_bounds__(256) void adj_phasor_kernel(
 void launch_adjoint_phasor(const Plan& P, cf32* out, hipStream_t s) {
     const int nzc = (P.g.nz + 255) / 256;
     hipLaunchKernelGGL(adj_phasor_kernel, dim3(P.npos * nzc), dim3(256), 0, s,
-                       static_cast<const cf32*>(P.d_rop), P.d_u, P.d_bins, out, P.g.nx, P.g.ny,
+                       static_cast<const cf32*>(P.d_rop), P.d_u, P.d_amp, P.d_bins, out, P.g.nx, P.g.ny,
                        P.g.nz, P.d.wx, P.d.wy, P.m, nzc);
     UFSS_HIP(hipGetLastError());
 }

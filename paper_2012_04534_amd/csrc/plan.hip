@@ -83,6 +83,17 @@ static void validate_geom(const ufss_geom* g) {
         fail(UFSS_ERR_INVALID_ARG, "dtype must be UFSS_F32 or UFSS_BF16");
     if (g->algo < UFSS_ALGO_AUTO || g->algo > UFSS_ALGO_PHASOR)
         fail(UFSS_ERR_INVALID_ARG, "unknown algo");
+    if (!(g->theta >= 0) || !(g->theta < 0.5 * M_PI))
+        fail(UFSS_ERR_INVALID_ARG, "theta must be in [0, pi/2)");
+}
+
+// Gaussian beam amplitude g = exp(-r^2 / (z tan theta)^2) at lateral offset
+// (ix dx, iy dy) and depth index z (Sec. VI); 1 without a beam.
+static double beam(const ufss_geom& g, int ix, int iy, int z) {
+    if (!(g.theta > 0)) return 1.0;
+    double w = (g.z_start + z * g.dz) * std::tan(g.theta);
+    double rx = ix * g.dx, ry = iy * g.dy;
+    return std::exp(-(rx * rx + ry * ry) / (w * w));
 }
 
 // ---------------------------------------------------------------------------
@@ -237,7 +248,7 @@ static void free_plan(Plan* P) {
     void* ptrs[] = {P->d_bins, P->d_ubins, P->d_map, P->d_hsel, P->d_u, P->d_yraw,
                     P->d_rop, P->d_xop, P->d_part, P->d_scalars, P->d_r, P->d_g,
                     P->d_gamma, P->d_v, P->d_stats, P->d_gpart, P->d_ptab_f, P->d_ptab_a,
-                    P->d_bt, P->d_bt_scal};
+                    P->d_bt, P->d_bt_scal, P->d_amp};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& v : P->kev)
@@ -261,9 +272,10 @@ static void validate_bins(const ufss_geom* g, int m, int per_position, const int
 }
 
 // Sec. IV-C estimate of sigma_max from the Frobenius norm.  Every non-zero
-// entry of A has modulus H_k, so ||A||_F^2 = sum_p sum_m H_{k_m(p)}^2 N_z
-// (voxels in the window of p); the paper's cheaper form takes N_x N_y N_z times
-// the squared norm of the column below the grid centre.  N = min(rows, cols)
+// entry of A has modulus H_k g, so ||A||_F^2 = sum_p sum_m H_{k_m(p)}^2 times
+// the sum of g^2 over the voxels in the window of p; the paper's cheaper form
+// takes N_x N_y times the squared norms of the columns below the grid centre,
+// summed over depth.  N = min(rows, cols)
 // bounds the rank, and sigma_hat = ||A||_F / N^(1/4) is the geometric mean of
 // ||A||_F / sqrt(N) <= sigma_max <= ||A||_F.  Host only, FP64.
 void sigma_estimate(const ufss_geom* g, int m, int per_position, const int32_t* bins,
@@ -282,22 +294,35 @@ void sigma_estimate(const ufss_geom* g, int m, int per_position, const int32_t* 
         }
         return s;
     };
-    double fro = 0.0;
-    for (int py = 0; py < g->ny; ++py) {
-        int ny_in = std::min(py + d.wy, g->ny - 1) - std::max(py - d.wy, 0) + 1;
-        for (int px = 0; px < g->nx; ++px) {
-            int nx_in = std::min(px + d.wx, g->nx - 1) - std::max(px - d.wx, 0) + 1;
-            fro += hsq(py, px) * g->nz * nx_in * ny_in;
+    // S[|dy|][|dx|] = sum over depth of g^2 (N_z without a beam)
+    std::vector<double> S((size_t)(d.wy + 1) * (d.wx + 1), 0.0);
+    for (int iy = 0; iy <= d.wy; ++iy)
+        for (int ix = 0; ix <= d.wx; ++ix) {
+            double acc = 0.0;
+            for (int z = 0; z < g->nz; ++z) {
+                double b = beam(*g, ix, iy, z);
+                acc += b * b;
+            }
+            S[(size_t)iy * (d.wx + 1) + ix] = acc;
         }
-    }
+    auto wsum = [&](int py, int px) {
+        double acc = 0.0;
+        for (int vy = std::max(py - d.wy, 0); vy <= std::min(py + d.wy, g->ny - 1); ++vy)
+            for (int vx = std::max(px - d.wx, 0); vx <= std::min(px + d.wx, g->nx - 1); ++vx)
+                acc += S[(size_t)std::abs(vy - py) * (d.wx + 1) + std::abs(vx - px)];
+        return acc;
+    };
+    double fro = 0.0;
+    for (int py = 0; py < g->ny; ++py)
+        for (int px = 0; px < g->nx; ++px) fro += hsq(py, px) * wsum(py, px);
     const int vx = (g->nx - 1) / 2, vy = (g->ny - 1) / 2;
     double col = 0.0;
     for (int py = std::max(vy - d.wy, 0); py <= std::min(vy + d.wy, g->ny - 1); ++py)
         for (int px = std::max(vx - d.wx, 0); px <= std::min(vx + d.wx, g->nx - 1); ++px)
-            col += hsq(py, px);
+            col += hsq(py, px) * S[(size_t)std::abs(py - vy) * (d.wx + 1) + std::abs(px - vx)];
     const double npos = (double)g->nx * g->ny;
     out->fro_sq = fro;
-    out->fro_sq_central = npos * g->nz * col;
+    out->fro_sq_central = npos * col;
     out->n = (int64_t)g->nx * g->ny * std::min(m, g->nz);
     const double q = std::pow((double)out->n, 0.25);
     out->sigma_hat = std::sqrt(out->fro_sq) / q;
@@ -369,6 +394,16 @@ Plan* plan_create(const ufss_geom* g, int m, int per_position, const int32_t* bi
         upload(P->d_hsel, hsel.data(), nsel);
         P->d_u = dalloc<uint32_t>(*P, ut.size());
         upload(P->d_u, ut.data(), ut.size());
+        if (g->theta > 0) {
+            // beam amplitude table, same layout as the delay table
+            std::vector<float> at(ut.size());
+            for (int j = 0; j <= wy; ++j)
+                for (int i = 0; i <= wx; ++i)
+                    for (int z = 0; z < g->nz; ++z)
+                        at[((size_t)j * (wx + 1) + i) * g->nz + z] = (float)beam(*g, i, j, z);
+            P->d_amp = dalloc<float>(*P, at.size());
+            upload(P->d_amp, at.data(), at.size());
+        }
         if (algo == UFSS_ALGO_GEMM && P->dtype == UFSS_BF16) {
             if (!bf16_supported(*P))
                 fail(UFSS_ERR_UNSUPPORTED, "aperture window too wide for the BF16 GEMM path");

@@ -53,6 +53,7 @@ class Geom(ctypes.Structure):
         ("band_db", ctypes.c_double),
         ("win_x", ctypes.c_int32), ("win_y", ctypes.c_int32),
         ("dtype", ctypes.c_int32), ("algo", ctypes.c_int32),
+        ("theta", ctypes.c_double),
     ]
 
 
@@ -161,7 +162,8 @@ def make_geom(g, dtype=F32, algo=ALGO_AUTO):
     """ctypes geometry from a geometry dict (see workloads.geometry)."""
     return Geom(int(g["nx"]), int(g["ny"]), int(g["nz"]), int(g["nt"]), g["dx"], g["dy"], g["dz"],
                 g["z_start"], g["t0"], g["c"], g["fs"], g["fc"], g["frac_bw"], g["band_db"],
-                int(g["win_x"]), int(g["win_y"]), int(dtype), int(algo))
+                int(g["win_x"]), int(g["win_y"]), int(dtype), int(algo),
+                float(g.get("theta", 0.0)))
 
 
 def _stream(stream):

@@ -20,7 +20,8 @@ Workloads (one per measured configuration):
             128 shared bins, aperture window of +-16 voxels
   sim50     the simulated specimen of Sec. VII / Table III: 50 x 50 positions,
             50 depths, f_c = 3.2 MHz, f_s = 20 MHz, c = 5920 m/s, t0 = 10 us,
-            N_t = 256, full aperture; line and tilted-rectangle defects of
+            N_t = 256, full aperture with a Gaussian beam of half-angle 30
+            degrees; line and tilted-rectangle defects of
             amplitude exp(j pi/4), noise free; n_f in {1, 2, 5, 10}
 Scenes are distinct on-grid point scatterers; noise is circular complex
 Gaussian scaled to a target SNR over all measured values (the scaling needs
@@ -47,7 +48,7 @@ def geometry(nx, ny, nz, nt, win_x=-1, win_y=-1, t0=float("nan"), **over):
     """Geometry dict (SI units) with the common physical constants."""
     g = dict(nx=nx, ny=ny, nz=nz, nt=nt, dx=PITCH, dy=PITCH, dz=DZ,
              z_start=Z_START, t0=t0, c=C_SOUND, fs=FS, fc=FC,
-             frac_bw=FRAC_BW, band_db=BAND_DB, win_x=win_x, win_y=win_y)
+             frac_bw=FRAC_BW, band_db=BAND_DB, win_x=win_x, win_y=win_y, theta=0.0)
     g.update(over)
     return g
 
@@ -70,11 +71,13 @@ WORKLOADS = {
 # is the sampling rate; alpha = (0.65 f_c)^2 is the envelope exp(-alpha t^2), so
 # sigma_t = 1 / (0.65 f_c sqrt(2)) and the -6 dB fractional bandwidth is
 # 2 sqrt(2 ln 2) * 0.65 sqrt(2) / (2 pi) = 0.3445; N_t (not given) = 256 covers
-# the delays of the whole aperture from t0 = 10 us; depth pitch c / (2 f_s).
+# the delays of the whole aperture from t0 = 10 us; depth pitch c / (2 f_s);
+# Gaussian beam of half-angle theta = 30 degrees over the full aperture.
 SIM_FRAC_BW = 2.0 * math.sqrt(2.0 * math.log(2.0)) * 0.65 * math.sqrt(2.0) / (2.0 * math.pi)
 SIM50 = dict(nx=50, ny=50, nz=50, nt=256, c=5920.0, fs=20e6, fc=3.2e6, t0=10e-6,
              z_start=29.6e-3, dx=0.5e-3, dy=0.5e-3, dz=5920.0 / (2 * 20e6),
-             frac_bw=SIM_FRAC_BW, band_db=40.0, win_x=-1, win_y=-1)
+             frac_bw=SIM_FRAC_BW, band_db=40.0, win_x=-1, win_y=-1,
+             theta=math.radians(30.0))
 SIM_NF = (1, 2, 5, 10)
 SIM_ITERS = 80
 SIM_MU = (0.1, 0.6)

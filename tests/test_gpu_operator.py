@@ -350,3 +350,66 @@ def test_random_small_problems_against_dense_oracle(seed, dev):
     ey, ex = errs(yo.cpu().numpy(), y_ref), errs(xo.cpu().numpy(), x_ref)
     assert max(ey) < tol and max(ex) < tol, (g["nx"], g["ny"], g["nz"], g["nt"], m, per_pos, dtype, t, ey, ex)
     plan.close()
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_beam_problems_against_dense_oracle(seed, dev):
+    """Gaussian beam (Sec. VI directivity): random small problems with a beam
+    half-angle of 5-60 degrees, every path (FP32 GEMM with a random tiling,
+    phasor path for per-position bins, BF16 with phasor tables) against the
+    dense FP64 oracle."""
+    u = ufss()
+    rng = np.random.default_rng(12000 + seed)
+    g, m, per_pos, dtype, t = random_case(rng)
+    g["theta"] = float(np.radians(rng.choice([5.0, 15.0, 30.0, 60.0])))
+    algo = u.ALGO_PHASOR if (per_pos and dtype == "f32" and rng.random() < 0.5) else u.ALGO_AUTO
+    bins, _ = u.ufss_select_freqs(g, m, per_pos, 1700 + seed)
+    x = W.cn((g["ny"], g["nx"], g["nz"]), 1800 + seed).astype(np.complex64)
+    y = W.cn((g["ny"], g["nx"], m), 1900 + seed).astype(np.complex64)
+    A = O.dense_A(g, bins)
+    y_ref = (A @ x.reshape(-1).astype(np.complex128)).reshape(y.shape)
+    x_ref = (A.conj().T @ y.reshape(-1).astype(np.complex128)).reshape(x.shape)
+    plan = u.Plan(g, m, per_pos, bins, dtype=u.F32 if dtype == "f32" else u.BF16, algo=algo)
+    if algo == u.ALGO_AUTO:
+        try:
+            u.ufss_plan_set_tiling(plan, **t)
+        except u.UfssError:
+            pass
+    yo = torch.empty(y.shape, dtype=torch.complex64, device=dev)
+    xo = torch.empty(x.shape, dtype=torch.complex64, device=dev)
+    u.ufss_forward(plan, torch.from_numpy(x).to(dev), yo)
+    u.ufss_adjoint(plan, torch.from_numpy(y).to(dev), xo)
+    torch.cuda.synchronize()
+    tol = TOL32 if dtype == "f32" else 1e-2
+    ey, ex = errs(yo.cpu().numpy(), y_ref), errs(xo.cpu().numpy(), x_ref)
+    assert max(ey) < tol and max(ex) < tol, (g, m, per_pos, dtype, algo, t, ey, ex)
+    plan.close()
+
+
+def test_beam_limits(dev):
+    """A BF16 plan with a beam keeps its phasor tables (the in-kernel generation
+    has no amplitude); batched FISTA refuses beam plans; theta outside
+    [0, pi/2) is an argument error."""
+    u = ufss()
+    g = W.geometry(8, 6, 24, 128, win_x=3, win_y=3)
+    g["theta"] = float(np.radians(20.0))
+    bins, _ = u.ufss_select_freqs(g, 8, False, 3)
+    pb = u.Plan(g, 8, False, bins, dtype=u.BF16)
+    assert pb.info()["phasor_tables"] == 1
+    with pytest.raises(u.UfssError) as e:
+        u.ufss_plan_set_phasor_tables(pb, 0)
+    assert e.value.name == "UNSUPPORTED"
+    assert u.ufss_plan_set_phasor_tables(pb, 1) == 1
+    pf = u.Plan(g, 8, False, bins)
+    y = torch.zeros((6, 8, 8), dtype=torch.complex64, device=dev)
+    x = torch.zeros((6, 8, 24), dtype=torch.complex64, device=dev)
+    with pytest.raises(u.UfssError) as e:
+        u.ufss_fista_batched([pf], [y], [x], [1.0], [1.0], 2)
+    assert e.value.name == "UNSUPPORTED"
+    for bad in (-0.1, float(np.pi / 2), float("nan")):
+        gb = dict(g, theta=bad)
+        with pytest.raises(u.UfssError) as e:
+            u.Plan(gb, 8, False, bins)
+        assert e.value.name == "INVALID_ARG"
+    pb.close()
+    pf.close()
