@@ -189,6 +189,35 @@ typedef struct ufss_sigma_est {
 int ufss_sigma_estimate(const ufss_geom* g, int32_t m, int32_t per_position,
                         const int32_t* bins, ufss_sigma_est* out);
 
+/* One point scatterer for ufss_crb: position (x, y) in metres on the scan grid
+ * (position (ix, iy) sits at (ix dx, iy dy)), depth z (> 0), amplitude amp
+ * (> 0), phase (rad; the bound does not depend on it) and the noise variance
+ * sigma2 (> 0) of each measured coefficient. */
+typedef struct ufss_crb_point {
+    double x, y, z, amp, phase, sigma2;
+} ufss_crb_point;
+
+/* Cramer-Rao bound on the scatterer's position for `trials` bin selections
+ * at once (paper Sec. VI: Slepian-Bangs Fisher information of the measured
+ * coefficients, position block of its inverse by the Schur complement of the
+ * amplitude / phase block).  The measurement of bin k at position i is
+ * a e^{j phase} H_k g_i exp(-j 2 pi f_k (tau_i - t0)), with the operator's
+ * H_k, delay and Gaussian beam; positions outside the aperture window of the
+ * scatterer do not measure it.  Derivatives: d tau / d x = (2/c)(x - x_i)/R,
+ * d g / d x = -2 (x - x_i) / (z tan theta)^2 g, d g / d z =
+ * 2 r^2 / (z^3 tan^2 theta) g.  Sums in FP64 on the device (one workgroup per
+ * selection, fixed order); the 5 x 5 algebra on the host in FP64.
+ *   bins      HOST int32 [trials][m] (shared) or [trials][ny][nx][m], each
+ *             subset as for ufss_plan_create
+ *   fim_out   HOST double [trials][5][5] or NULL: J, parameters (x, y, z,
+ *             amp, phase)
+ *   crb_out   HOST double [trials][3]: (C_x, C_y, C_z) in m^2
+ * Synchronises `stream`.  Allocates and frees two device buffers.
+ * Errors: INVALID_ARG (also for a singular information matrix), HIP, OOM. */
+int ufss_crb(const ufss_geom* g, int32_t m, int32_t per_position, int32_t trials,
+             const int32_t* bins, const ufss_crb_point* pt, double* fim_out, double* crb_out,
+             ufss_stream_t stream);
+
 /* Build a plan: derived geometry (FP64 on the host), the integer-turn delay
  * table, H_k and the device workspace.  Paper Sec. IV-B: the operator is block
  * 2-level Toeplitz in the lateral offset, which the kernels exploit.

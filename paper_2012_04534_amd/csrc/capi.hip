@@ -20,6 +20,8 @@ void sample_bins(const ufss_geom* g, int m, int strategy, uint64_t seed, int32_t
                  int32_t* per_position_out);
 void sigma_estimate(const ufss_geom* g, int m, int per_position, const int32_t* bins,
                     ufss_sigma_est* out);
+void crb(const ufss_geom* g, int m, int per_position, int trials, const int32_t* bins,
+         const ufss_crb_point* pt, double* fim_out, double* crb_out, hipStream_t s);
 const char* last_error();
 int phasor_forward_blocks(const Plan& P);
 int fista_batched(int n, Plan* const* plans, const cf32* const* ys, cf32* const* xs,
@@ -424,6 +426,15 @@ int ufss_sigma_estimate(const ufss_geom* g, int32_t m, int32_t per_position,
                         const int32_t* bins, ufss_sigma_est* out) {
     UFSS_GUARD_BEGIN
     ufss::sigma_estimate(g, m, per_position, bins, out);
+    UFSS_GUARD_END
+}
+
+int ufss_crb(const ufss_geom* g, int32_t m, int32_t per_position, int32_t trials,
+             const int32_t* bins, const ufss_crb_point* pt, double* fim_out, double* crb_out,
+             ufss_stream_t stream) {
+    UFSS_GUARD_BEGIN
+    ufss::crb(g, m, per_position, trials, bins, pt, fim_out, crb_out,
+              static_cast<hipStream_t>(stream));
     UFSS_GUARD_END
 }
 

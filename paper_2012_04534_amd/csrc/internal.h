@@ -42,6 +42,8 @@ struct Derived {
     std::vector<int> band;              // ascending band bins
 };
 Derived derive(const ufss_geom& g);
+// Geometry and bin-subset checks of ufss_plan_create (throws INVALID_ARG).
+void validate_bins_public(const ufss_geom* g, int m, int per_position, const int32_t* bins);
 double pulse_spectrum(const ufss_geom& g, const Derived& d, int k);
 
 // Launch description of the operator kernels.  Everything a kernel needs is in

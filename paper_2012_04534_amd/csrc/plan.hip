@@ -271,6 +271,11 @@ static void validate_bins(const ufss_geom* g, int m, int per_position, const int
     }
 }
 
+void validate_bins_public(const ufss_geom* g, int m, int per_position, const int32_t* bins) {
+    validate_geom(g);
+    validate_bins(g, m, per_position, bins);
+}
+
 // Sec. IV-C estimate of sigma_max from the Frobenius norm.  Every non-zero
 // entry of A has modulus H_k g, so ||A||_F^2 = sum_p sum_m H_{k_m(p)}^2 times
 // the sum of g^2 over the voxels in the window of p; the paper's cheaper form

@@ -15,11 +15,18 @@ Reported per run (one JSON line each):
   ms_per_iter  FISTA time per iteration (forward + adjoint + update)
   algo         operator algorithm the plan used (GEMM or phasor)
 
-Usage: python -m paper_2012_04534_amd.replica [--quick] [--algos]
+The asymptotic study of Sec. VI is ``--crb``: the Cramer-Rao bound on the
+position of one scatterer 33.3 mm below the centre of the same scan grid, for
+n_f in {1, 2, 5, 10, 20} under each strategy (50 seeded draws for the random
+ones), relative to the bound with every bin 0..N_t/2 measured.
+
+Usage: python -m paper_2012_04534_amd.replica [--quick] [--algos] [--crb]
   --algos  also times A + A^H under both per-position algorithms for each n_f
+  --crb    the Cramer-Rao study only
 """
 import argparse
 import json
+import math
 import sys
 import time
 
@@ -102,16 +109,50 @@ def time_algos(g, nf, seed, dev, reps=20):
     return out
 
 
+CRB_NF = (1, 2, 5, 10, 20)
+CRB_TRIALS = 50
+
+
+def crb_study(g, seed):
+    """Bounds relative to the full band, per strategy and n_f (one JSON line each)."""
+    pt = dict(x=(g["nx"] - 1) / 2 * g["dx"], y=(g["ny"] - 1) / 2 * g["dy"], z=33.3e-3,
+              amp=1.0, phase=math.pi / 4, sigma2=1.0)
+    full = np.arange(0, g["nt"] // 2 + 1, dtype=np.int32)
+    c_full, _ = ufss.ufss_crb(g, len(full), False, full, pt)
+    print(json.dumps(dict(kind="crb_full", crb_m2=[float(v) for v in c_full])), flush=True)
+    for nf in CRB_NF:
+        for strat, code in STRATEGIES.items():
+            trials = 1 if strat == "max" else CRB_TRIALS
+            sel = []
+            per = False
+            for t in range(trials):
+                b, per = ufss.ufss_sample_bins(g, nf, code, seed + 1000 * nf + t)
+                sel.append(b)
+            t0 = time.perf_counter()
+            c, _ = ufss.ufss_crb(g, nf, per, np.stack(sel), pt)
+            ms = (time.perf_counter() - t0) * 1e3
+            ratio = c / c_full[None, :]
+            print(json.dumps(dict(kind="crb", strategy=strat, n_f=nf, trials=trials,
+                                  mean=[round(float(v), 4) for v in ratio.mean(axis=0)],
+                                  best=[round(float(v), 4) for v in ratio.min(axis=0)],
+                                  worst=[round(float(v), 4) for v in ratio.max(axis=0)],
+                                  call_ms=round(ms, 3))), flush=True)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--quick", action="store_true", help="n_f in {1, 10}, mu = 0.1 only")
     ap.add_argument("--algos", action="store_true", help="time both per-position algorithms")
+    ap.add_argument("--crb", action="store_true", help="the Cramer-Rao study only")
     ap.add_argument("--seed", type=int, default=5001)
     args = ap.parse_args(argv)
     if not torch.cuda.is_available():
         sys.exit("replica: needs a GPU (the operator runs only in the HIP library)")
     dev = torch.device("cuda:0")
     g = W.sim_geometry()
+    if args.crb:
+        crb_study(g, args.seed)
+        return
     scenes = {"line": W.sim_line(g), "rectangle": W.sim_rectangle(g)}
     nfs = (1, 10) if args.quick else W.SIM_NF
     mus = (0.1,) if args.quick else W.SIM_MU

@@ -25,7 +25,7 @@ ALGO_AUTO, ALGO_GEMM, ALGO_PHASOR = 0, 1, 2
 SAMPLE_RND, SAMPLE_RND_F, SAMPLE_MAX, SAMPLE_NRG, SAMPLE_NRG_F = 0, 1, 2, 3, 4
 
 EXPORTED = [
-    "ufss_last_error", "ufss_select_freqs", "ufss_sample_bins", "ufss_sigma_estimate",
+    "ufss_last_error", "ufss_select_freqs", "ufss_sample_bins", "ufss_sigma_estimate", "ufss_crb",
     "ufss_plan_create", "ufss_plan_destroy",
     "ufss_plan_info_get", "ufss_forward", "ufss_adjoint", "ufss_lipschitz", "ufss_fista",
     "ufss_fista_backtracking",
@@ -112,6 +112,8 @@ def lib():
             "ufss_sample_bins": ([ctypes.POINTER(Geom), I32, I32, U64, P, P], ctypes.c_int),
             "ufss_sigma_estimate": ([ctypes.POINTER(Geom), I32, I32, P,
                                      ctypes.POINTER(SigmaEst)], ctypes.c_int),
+            "ufss_crb": ([ctypes.POINTER(Geom), I32, I32, I32, P, ctypes.POINTER(CrbPoint), P, P,
+                          P], ctypes.c_int),
             "ufss_plan_create": ([ctypes.POINTER(Geom), I32, I32, P, ctypes.POINTER(P)], ctypes.c_int),
             "ufss_plan_destroy": ([P], ctypes.c_int),
             "ufss_plan_info_get": ([P, ctypes.POINTER(PlanInfo)], ctypes.c_int),
@@ -229,6 +231,36 @@ def ufss_sigma_estimate(g, m, per_position, bins):
     _check(lib().ufss_sigma_estimate(ctypes.byref(geom), int(m), int(bool(per_position)),
                                      b.ctypes.data_as(ctypes.c_void_p), ctypes.byref(out)))
     return {f: getattr(out, f) for f, _ in SigmaEst._fields_}
+
+
+class CrbPoint(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_double), ("y", ctypes.c_double), ("z", ctypes.c_double),
+                ("amp", ctypes.c_double), ("phase", ctypes.c_double), ("sigma2", ctypes.c_double)]
+
+
+def ufss_crb(g, m, per_position, bins, point, stream=None):
+    """Cramer-Rao bounds for a stack of bin selections.
+
+    bins: int array [trials, m] (shared) or [trials, ny, nx, m]; a single
+    selection without the leading axis is accepted.  point: dict with x, y, z,
+    amp, phase, sigma2.  Returns (crb [trials, 3], fim [trials, 5, 5])."""
+    b = np.ascontiguousarray(bins, dtype=np.int32)
+    one = b.ndim == (3 if per_position else 1)
+    if one:
+        b = b[None]
+    trials = b.shape[0]
+    want = g["nx"] * g["ny"] * m if per_position else m
+    if b[0].size != want:
+        raise ValueError("each selection has %d entries, expected %d" % (b[0].size, want))
+    geom = make_geom(g)
+    pt = CrbPoint(*(float(point[k]) for k in ("x", "y", "z", "amp", "phase", "sigma2")))
+    crb = np.zeros((trials, 3))
+    fim = np.zeros((trials, 5, 5))
+    _check(lib().ufss_crb(ctypes.byref(geom), int(m), int(bool(per_position)), int(trials),
+                          b.ctypes.data_as(ctypes.c_void_p), ctypes.byref(pt),
+                          fim.ctypes.data_as(ctypes.c_void_p), crb.ctypes.data_as(ctypes.c_void_p),
+                          _stream(stream)))
+    return (crb[0], fim[0]) if one else (crb, fim)
 
 
 class Plan:

@@ -145,7 +145,8 @@ def header_struct_fields(name):
                                            ("ufss_fista_stats", "FistaStats"),
                                            ("ufss_fista_state", "FistaState"),
                                            ("ufss_tiling", "Tiling"),
-                                           ("ufss_sigma_est", "SigmaEst")])
+                                           ("ufss_sigma_est", "SigmaEst"),
+                                           ("ufss_crb_point", "CrbPoint")])
 def test_binding_structs_match_header(cname, pyname):
     """The ctypes mirrors of the C structs list the same fields in the same order."""
     cls = getattr(ufss, pyname)
