@@ -56,6 +56,13 @@ extern "C" {
                                per-position subsets run over their union of bins
                                and are gathered / scattered                    */
 #define UFSS_ALGO_PHASOR 2  /* per-position on-the-fly phasors (VALU); FP32 only */
+#define UFSS_ALGO_FFT    3  /* transform domain (Sec. IV-B, Alg. 2): the windowed
+                               correlation as a cyclic lateral transform of size
+                               L >= N + W per axis, contracted over depth / bins
+                               with a precomputed transformed kernel table
+                               ((ly/2+1)(lx/2+1) nz (union bins) complex64, built
+                               in FP64); shared or per-position (over the union)
+                               subsets; FP32 only; no grouped (batched) launches */
 
 /* Scan and pulse geometry (SI units).  Paper Sec. II-A (grids, delay, pulse),
  * Sec. VI (Gabor pulse).  t0 = NaN selects the window that centres the delay

@@ -70,7 +70,13 @@ void op_forward(Plan& P, const cf32* x, cf32* y, const cf32* ymeas, double* res2
         if (res2_out) launch_reduce(P.d_part, phasor_forward_blocks(P), 1, res2_out, s);
         return;
     }
-    if (P.dtype == UFSS_BF16) {
+    if (P.algo == UFSS_ALGO_FFT) {
+        fft_fwd_transform(P, x, s);
+        ktime_begin(P, 0, s);
+        fft_fwd_contract(P, s);
+        ktime_end(P, 0, s);
+        fft_fwd_inverse(P, s);
+    } else if (P.dtype == UFSS_BF16) {
         launch_to_bf16(x, P.d_xop, P.nvox, s);
         ktime_begin(P, 0, s);
         launch_forward_gemm_bf16(P, s);
@@ -86,6 +92,14 @@ void op_forward(Plan& P, const cf32* x, cf32* y, const cf32* ymeas, double* res2
 
 int op_adjoint(Plan& P, const cf32* y, cf32* x, hipStream_t s, bool defer_sum) {
     launch_adjoint_pre(P, y, s);
+    if (P.algo == UFSS_ALGO_FFT) {
+        fft_adj_transform(P, s);
+        ktime_begin(P, 1, s);
+        fft_adj_contract(P, s);
+        ktime_end(P, 1, s);
+        fft_adj_inverse(P, x, s);
+        return 1;
+    }
     ktime_begin(P, 1, s);
     if (P.algo == UFSS_ALGO_PHASOR) {
         launch_adjoint_phasor(P, x, s);
@@ -714,7 +728,12 @@ int ufss_time_kernel(ufss_plan_t plan, int32_t which, int32_t reps, double* ms_o
     UFSS_HIP(hipEventCreate(&e1));
     try {
         auto launch = [&]() {
-            if (which == 0) {
+            if (P->algo == UFSS_ALGO_FFT) {    // the contraction (transform inputs as left)
+                if (which == 0)
+                    ufss::fft_fwd_contract(*P, s);
+                else
+                    ufss::fft_adj_contract(*P, s);
+            } else if (which == 0) {
                 if (P->algo == UFSS_ALGO_PHASOR)
                     ufss::launch_forward_phasor(*P, P->d_gamma, P->d_r, nullptr, P->d_part, s);
                 else if (P->dtype == UFSS_BF16)

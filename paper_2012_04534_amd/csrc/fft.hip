@@ -1,0 +1,348 @@
+// Transform-domain operator (paper Sec. IV-B, Alg. 2): the block two-level
+// Toeplitz structure makes A a lateral 2-D correlation, which a cyclic
+// transform of size L >= N + W per axis evaluates exactly on the scan grid.
+//
+//   forward  X^[q][z] = DFT_2(x)              (separable twiddle products)
+//            Y^[q][k] = sum_z K^[q][z][k] X^[q][z]
+//            y[p][k]  = IDFT_2(Y^) on the N x N grid positions, then H_k
+//   adjoint  R^[q][k] = DFT_2(H r)
+//            X'[q][z] = sum_k conj(K^[q][z][k]) R^[q][k]
+//            x[v][z]  = IDFT_2(X') on the grid voxels
+//
+// K^[q][z][k] = sum_{|d| <= W} P_d[k][z] exp(-j 2 pi (q_x d_x / L_x + q_y d_y / L_y))
+// with P_d the windowed, beam-weighted phasor of the other paths (same
+// integer-turn delays).  P_d is even in d_x and in d_y, so K^ is a cosine
+// transform, even in q_x and q_y: only the quadrant q_x <= L_x / 2,
+// q_y <= L_y / 2 is stored, and each stored entry serves up to four q.
+// K^ is built once per plan in FP64 and stored in FP32; the applies run in
+// FP32.  The contraction streams K^ once per apply and is bound by HBM (or by
+// the last-level cache when K^ fits there); the lateral transforms are small
+// products with twiddle tables.
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+
+namespace ufss {
+
+static constexpr int kTwT = 256;   // threads of the twiddle products (channels)
+static constexpr int kTwI = 8;     // outputs per thread along the transformed axis
+
+// out[b][i][c] = sum_j W[i][j] in[b][j][c]  (complex, FP32; c contiguous).
+__global__ __launch_bounds__(kTwT) void twiddle_kernel(cf32* __restrict__ out,
+                                                      const cf32* __restrict__ in,
+                                                      const cf32* __restrict__ W, int I, int J,
+                                                      int C, int64_t sib, int64_t sij,
+                                                      int64_t sob, int64_t soi) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cf32* wl = reinterpret_cast<cf32*>(smem);          // [kTwI][J]
+    const int c = blockIdx.x * kTwT + threadIdx.x;
+    const int i0 = blockIdx.y * kTwI;
+    const int b = blockIdx.z;
+    for (int t = threadIdx.x; t < kTwI * J; t += kTwT) {
+        const int ii = t / J, j = t - ii * J;
+        wl[t] = (i0 + ii < I) ? W[(int64_t)(i0 + ii) * J + j] : cf32{0.f, 0.f};
+    }
+    __syncthreads();
+    if (c >= C) return;
+    float ar[kTwI], ai[kTwI];
+#pragma unroll
+    for (int ii = 0; ii < kTwI; ++ii) ar[ii] = ai[ii] = 0.f;
+    const cf32* src = in + (int64_t)b * sib + c;
+    for (int j = 0; j < J; ++j) {
+        const cf32 v = src[(int64_t)j * sij];
+#pragma unroll
+        for (int ii = 0; ii < kTwI; ++ii) {
+            const cf32 w = wl[ii * J + j];
+            ar[ii] += w.re * v.re - w.im * v.im;
+            ai[ii] += w.re * v.im + w.im * v.re;
+        }
+    }
+    cf32* dst = out + (int64_t)b * sob + c;
+#pragma unroll
+    for (int ii = 0; ii < kTwI; ++ii)
+        if (i0 + ii < I) dst[(int64_t)(i0 + ii) * soi] = cf32{ar[ii], ai[ii]};
+}
+
+static void twiddle(cf32* out, const cf32* in, const cf32* W, int B, int I, int J, int C,
+                    int64_t sib, int64_t sij, int64_t sob, int64_t soi, hipStream_t s) {
+    const dim3 grid((C + kTwT - 1) / kTwT, (I + kTwI - 1) / kTwI, B);
+    hipLaunchKernelGGL(twiddle_kernel, grid, dim3(kTwT), (size_t)kTwI * J * sizeof(cf32), s, out,
+                       in, W, I, J, C, sib, sij, sob, soi);
+    UFSS_HIP(hipGetLastError());
+}
+
+// The up-to-four transform indices (q_y, q_x) of quadrant entry (oy, ox).
+__device__ __forceinline__ int orbit(int oy, int ox, int ly, int lx, int* qy, int* qx) {
+    const int ny2 = (oy == 0 || 2 * oy == ly) ? 1 : 2;
+    const int nx2 = (ox == 0 || 2 * ox == lx) ? 1 : 2;
+    int n = 0;
+    for (int a = 0; a < ny2; ++a)
+        for (int b = 0; b < nx2; ++b) {
+            qy[n] = a ? ly - oy : oy;
+            qx[n] = b ? lx - ox : ox;
+            ++n;
+        }
+    return n;
+}
+
+// Forward contraction: one workgroup per quadrant entry, lanes over bins.
+__global__ __launch_bounds__(256) void contract_fwd_kernel(const cf32* __restrict__ khat,
+                                                          const cf32* __restrict__ xh,
+                                                          cf32* __restrict__ yh, int ly, int lx,
+                                                          int nox, int nz, int mu) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cf32* xs = reinterpret_cast<cf32*>(smem);          // [4][nz]
+    const int o = blockIdx.x, oy = o / nox, ox = o - oy * nox;
+    int qy[4], qx[4];
+    const int nq = orbit(oy, ox, ly, lx, qy, qx);
+    for (int t = threadIdx.x; t < nq * nz; t += blockDim.x) {
+        const int q = t / nz, z = t - q * nz;
+        xs[t] = xh[((int64_t)qy[q] * lx + qx[q]) * nz + z];
+    }
+    __syncthreads();
+    const cf32* kb = khat + (int64_t)o * nz * mu;
+    for (int k = threadIdx.x; k < mu; k += blockDim.x) {
+        float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int z = 0; z < nz; ++z) {
+            const cf32 kv = kb[(int64_t)z * mu + k];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (q >= nq) break;
+                const cf32 v = xs[q * nz + z];
+                ar[q] += kv.re * v.re - kv.im * v.im;
+                ai[q] += kv.re * v.im + kv.im * v.re;
+            }
+        }
+        for (int q = 0; q < nq; ++q)
+            yh[((int64_t)qy[q] * lx + qx[q]) * mu + k] = cf32{ar[q], ai[q]};
+    }
+}
+
+// Adjoint contraction: one workgroup per quadrant entry, lanes over depth.
+__global__ __launch_bounds__(256) void contract_adj_kernel(const cf32* __restrict__ khat,
+                                                          const cf32* __restrict__ rh,
+                                                          cf32* __restrict__ xh, int ly, int lx,
+                                                          int nox, int nz, int mu) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cf32* rs = reinterpret_cast<cf32*>(smem);          // [4][mu]
+    const int o = blockIdx.x, oy = o / nox, ox = o - oy * nox;
+    int qy[4], qx[4];
+    const int nq = orbit(oy, ox, ly, lx, qy, qx);
+    for (int t = threadIdx.x; t < nq * mu; t += blockDim.x) {
+        const int q = t / mu, k = t - q * mu;
+        rs[t] = rh[((int64_t)qy[q] * lx + qx[q]) * mu + k];
+    }
+    __syncthreads();
+    const cf32* kb = khat + (int64_t)o * nz * mu;
+    for (int z = threadIdx.x; z < nz; z += blockDim.x) {
+        float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
+        const cf32* row = kb + (int64_t)z * mu;
+        for (int k = 0; k < mu; ++k) {
+            const cf32 kv = row[k];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (q >= nq) break;
+                const cf32 v = rs[q * mu + k];
+                // conj(kv) * v
+                ar[q] += kv.re * v.re + kv.im * v.im;
+                ai[q] += kv.re * v.im - kv.im * v.re;
+            }
+        }
+        for (int q = 0; q < nq; ++q)
+            xh[((int64_t)qy[q] * lx + qx[q]) * nz + z] = cf32{ar[q], ai[q]};
+    }
+}
+
+// ---- plan-time construction of K^ (FP64) -------------------------------------
+// P64[dy][dx][z][k] = g(dx, dy, z) exp(-j 2 pi (kb[k] u(dy, dx, z) mod 2^32) / 2^32)
+__global__ void phasor64_kernel(const uint32_t* __restrict__ u, const float* __restrict__ amp,
+                                const int* __restrict__ kb, int64_t ncell, int mu,
+                                double2* __restrict__ out) {
+    const int64_t n = ncell * mu;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t cell = t / mu;
+        const int k = (int)(t - cell * mu);
+        const uint32_t ph = (uint32_t)kb[k] * u[cell];
+        const double turns = (double)ph * (1.0 / 4294967296.0);
+        double sn, cs;
+        sincos(2.0 * M_PI * turns, &sn, &cs);
+        const double g = amp ? (double)amp[cell] : 1.0;
+        out[t] = double2{g * cs, -g * sn};
+    }
+}
+
+// out[b][i][c] = sum_j C[i][j] in[b][j][c] with a real FP64 weight table
+// (the cosine transforms of the build); OUTF: FP32 output.
+template <bool OUTF>
+__global__ __launch_bounds__(256) void cos_kernel(void* __restrict__ out, const double2* __restrict__ in,
+                                                  const double* __restrict__ Cw, int I, int J,
+                                                  int64_t C, int64_t sib, int64_t sij,
+                                                  int64_t sob, int64_t soi) {
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int i = blockIdx.y, b = blockIdx.z;
+    if (c >= C || i >= I) return;
+    double re = 0.0, im = 0.0;
+    const double2* src = in + (int64_t)b * sib + c;
+    for (int j = 0; j < J; ++j) {
+        const double w = Cw[(int64_t)i * J + j];
+        const double2 v = src[(int64_t)j * sij];
+        re += w * v.x;
+        im += w * v.y;
+    }
+    const int64_t o = (int64_t)b * sob + (int64_t)i * soi + c;
+    if (OUTF)
+        static_cast<cf32*>(out)[o] = cf32{(float)re, (float)im};
+    else
+        static_cast<double2*>(out)[o] = double2{re, im};
+}
+
+// Cyclic transform size per axis: the smallest L >= N + W (and >= 1).
+static int fft_len(int n, int w) { return std::max(1, n + w); }
+
+int64_t fft_table_bytes(const Plan& P) {
+    const int lx = fft_len(P.g.nx, P.d.wx), ly = fft_len(P.g.ny, P.d.wy);
+    return (int64_t)(ly / 2 + 1) * (lx / 2 + 1) * P.g.nz * (int64_t)P.ubins_h.size() * 8;
+}
+
+static constexpr int64_t kFftTableMax = int64_t(32) << 30;
+
+void fft_setup(Plan& P) {
+    const int nx = P.g.nx, ny = P.g.ny, nz = P.g.nz, wx = P.d.wx, wy = P.d.wy;
+    const int mu = (int)P.ubins_h.size();
+    const int lx = fft_len(nx, wx), ly = fft_len(ny, wy);
+    const int nox = lx / 2 + 1, noy = ly / 2 + 1;
+    if (fft_table_bytes(P) > kFftTableMax)
+        fail(UFSS_ERR_UNSUPPORTED, "transform table larger than 32 GiB");
+    // LDS staging: twiddle rows (8 x L) and four transform rows (4 x nz or mu)
+    if (std::max(lx, ly) > 1024 || std::max(nz, mu) > 2048)
+        fail(UFSS_ERR_UNSUPPORTED, "grid too large for the transform path (L <= 1024, nz and bins <= 2048)");
+    P.fft_lx = lx;
+    P.fft_ly = ly;
+    // twiddle tables (FP64 angles from exact integer products, stored FP32)
+    auto tw = [](int rows, int cols, int L, double sign, double scale) {
+        std::vector<cf32> t((size_t)rows * cols);
+        for (int r = 0; r < rows; ++r)
+            for (int c = 0; c < cols; ++c) {
+                const double a = 2.0 * M_PI * (double)(((int64_t)r * c) % L) / L;
+                t[(size_t)r * cols + c] = cf32{(float)(scale * std::cos(a)), (float)(scale * sign * std::sin(a))};
+            }
+        return t;
+    };
+    auto up = [&](const std::vector<cf32>& h) {
+        void* d = nullptr;
+        UFSS_HIP(hipMalloc(&d, h.size() * sizeof(cf32)));
+        UFSS_HIP(hipMemcpy(d, h.data(), h.size() * sizeof(cf32), hipMemcpyHostToDevice));
+        P.ws_bytes += h.size() * sizeof(cf32);
+        return static_cast<cf32*>(d);
+    };
+    P.d_tw_fx = up(tw(lx, nx, lx, -1.0, 1.0));          // [qx][nx]
+    P.d_tw_fy = up(tw(ly, ny, ly, -1.0, 1.0));          // [qy][ny]
+    P.d_tw_ix = up(tw(nx, lx, lx, +1.0, 1.0 / lx));     // [px][qx]
+    P.d_tw_iy = up(tw(ny, ly, ly, +1.0, 1.0 / ly));     // [py][qy]
+    const int64_t cmax = std::max(nz, mu);
+    const int64_t wbytes = (int64_t)ly * lx * cmax * sizeof(cf32);
+    const int64_t tbytes = (int64_t)std::max((int64_t)ny * lx, (int64_t)ly * nx) * cmax * sizeof(cf32);
+    UFSS_HIP(hipMalloc(&P.d_fa, wbytes));
+    UFSS_HIP(hipMalloc(&P.d_fb, wbytes));
+    UFSS_HIP(hipMalloc(&P.d_ft, tbytes));
+    P.ws_bytes += 2 * wbytes + tbytes;
+
+    // K^ in FP64: phasors, cosine transform over d_x, then over d_y
+    const int64_t ncell = (int64_t)(wy + 1) * (wx + 1) * nz;
+    const int64_t zc = (int64_t)nz * mu;                 // channels (z, k)
+    double2 *p64 = nullptr, *s64 = nullptr;
+    double *cx = nullptr, *cy = nullptr;
+    std::vector<double> hx((size_t)nox * (wx + 1)), hy((size_t)noy * (wy + 1));
+    for (int q = 0; q < nox; ++q)
+        for (int d = 0; d <= wx; ++d)
+            hx[(size_t)q * (wx + 1) + d] = (d == 0 ? 1.0 : 2.0) * std::cos(2.0 * M_PI * (double)(((int64_t)q * d) % lx) / lx);
+    for (int q = 0; q < noy; ++q)
+        for (int d = 0; d <= wy; ++d)
+            hy[(size_t)q * (wy + 1) + d] = (d == 0 ? 1.0 : 2.0) * std::cos(2.0 * M_PI * (double)(((int64_t)q * d) % ly) / ly);
+    try {
+        UFSS_HIP(hipMalloc(&p64, ncell * mu * sizeof(double2)));
+        UFSS_HIP(hipMalloc(&s64, (int64_t)(wy + 1) * nox * zc * sizeof(double2)));
+        UFSS_HIP(hipMalloc(&cx, hx.size() * sizeof(double)));
+        UFSS_HIP(hipMalloc(&cy, hy.size() * sizeof(double)));
+        UFSS_HIP(hipMalloc(&P.d_khat, (int64_t)noy * nox * zc * sizeof(cf32)));
+        P.ws_bytes += (int64_t)noy * nox * zc * sizeof(cf32);
+        UFSS_HIP(hipMemcpy(cx, hx.data(), hx.size() * sizeof(double), hipMemcpyHostToDevice));
+        UFSS_HIP(hipMemcpy(cy, hy.data(), hy.size() * sizeof(double), hipMemcpyHostToDevice));
+        const int64_t n = ncell * mu;
+        const int blocks = (int)std::min<int64_t>((n + 255) / 256, 65536);
+        hipLaunchKernelGGL(phasor64_kernel, dim3(blocks), dim3(256), 0, nullptr, P.d_u, P.d_amp,
+                           P.d_ubins, ncell, mu, p64);
+        UFSS_HIP(hipGetLastError());
+        // S[dy][qx][z][k] = sum_dx hx[qx][dx] P[dy][dx][z][k]
+        hipLaunchKernelGGL(cos_kernel<false>, dim3((unsigned)((zc + 255) / 256), nox, wy + 1), dim3(256),
+                           0, nullptr, (void*)s64, p64, cx, nox, wx + 1, zc, (int64_t)(wx + 1) * zc, zc,
+                           (int64_t)nox * zc, zc);
+        UFSS_HIP(hipGetLastError());
+        // K^[qy][qx][z][k] = sum_dy hy[qy][dy] S[dy][qx][z][k]
+        hipLaunchKernelGGL(cos_kernel<true>, dim3((unsigned)((zc + 255) / 256), noy, nox), dim3(256),
+                           0, nullptr, (void*)P.d_khat, s64, cy, noy, wy + 1, zc, zc, (int64_t)nox * zc,
+                           zc, (int64_t)nox * zc);
+        UFSS_HIP(hipGetLastError());
+        UFSS_HIP(hipDeviceSynchronize());
+    } catch (...) {
+        if (p64) (void)hipFree(p64);
+        if (s64) (void)hipFree(s64);
+        if (cx) (void)hipFree(cx);
+        if (cy) (void)hipFree(cy);
+        throw;
+    }
+    (void)hipFree(p64);
+    (void)hipFree(s64);
+    (void)hipFree(cx);
+    (void)hipFree(cy);
+}
+
+// Forward, in three steps (the contraction is the core kernel):
+//   x[ny][nx][nz] -> T[ny][lx][nz] -> X^[ly][lx][nz]
+void fft_fwd_transform(const Plan& P, const cf32* x, hipStream_t s) {
+    const int nx = P.g.nx, ny = P.g.ny, nz = P.g.nz, lx = P.fft_lx, ly = P.fft_ly;
+    twiddle(P.d_ft, x, P.d_tw_fx, ny, lx, nx, nz, (int64_t)nx * nz, nz, (int64_t)lx * nz, nz, s);
+    twiddle(P.d_fa, P.d_ft, P.d_tw_fy, lx, ly, ny, nz, nz, (int64_t)lx * nz, nz, (int64_t)lx * nz, s);
+}
+
+//   Y^[q][k] = sum_z K^[q][z][k] X^[q][z]
+void fft_fwd_contract(const Plan& P, hipStream_t s) {
+    const int lx = P.fft_lx, ly = P.fft_ly, nox = lx / 2 + 1, noy = ly / 2 + 1;
+    hipLaunchKernelGGL(contract_fwd_kernel, dim3(noy * nox), dim3(256), (size_t)4 * P.g.nz * sizeof(cf32),
+                       s, static_cast<const cf32*>(P.d_khat), P.d_fa, P.d_fb, ly, lx, nox, P.g.nz,
+                       (int)P.ubins_h.size());
+    UFSS_HIP(hipGetLastError());
+}
+
+//   Y^[ly][lx][mu] -> U[ly][nx][mu] -> y_raw[ny][nx][mu]
+void fft_fwd_inverse(const Plan& P, hipStream_t s) {
+    const int nx = P.g.nx, ny = P.g.ny, lx = P.fft_lx, ly = P.fft_ly, mu = (int)P.ubins_h.size();
+    twiddle(P.d_ft, P.d_fb, P.d_tw_ix, ly, nx, lx, mu, (int64_t)lx * mu, mu, (int64_t)nx * mu, mu, s);
+    twiddle(P.d_yraw, P.d_ft, P.d_tw_iy, nx, ny, ly, mu, mu, (int64_t)nx * mu, mu, (int64_t)nx * mu, s);
+}
+
+// Adjoint, in three steps; the operand is the H-scaled union-bin rows in P.d_rop.
+void fft_adj_transform(const Plan& P, hipStream_t s) {
+    const int nx = P.g.nx, ny = P.g.ny, lx = P.fft_lx, ly = P.fft_ly, mu = (int)P.ubins_h.size();
+    const cf32* r = static_cast<const cf32*>(P.d_rop);
+    twiddle(P.d_ft, r, P.d_tw_fx, ny, lx, nx, mu, (int64_t)nx * mu, mu, (int64_t)lx * mu, mu, s);
+    twiddle(P.d_fa, P.d_ft, P.d_tw_fy, lx, ly, ny, mu, mu, (int64_t)lx * mu, mu, (int64_t)lx * mu, s);
+}
+
+void fft_adj_contract(const Plan& P, hipStream_t s) {
+    const int lx = P.fft_lx, ly = P.fft_ly, nox = lx / 2 + 1, noy = ly / 2 + 1;
+    const int mu = (int)P.ubins_h.size();
+    hipLaunchKernelGGL(contract_adj_kernel, dim3(noy * nox), dim3(256), (size_t)4 * mu * sizeof(cf32), s,
+                       static_cast<const cf32*>(P.d_khat), P.d_fa, P.d_fb, ly, lx, nox, P.g.nz, mu);
+    UFSS_HIP(hipGetLastError());
+}
+
+void fft_adj_inverse(const Plan& P, cf32* out, hipStream_t s) {
+    const int nx = P.g.nx, ny = P.g.ny, nz = P.g.nz, lx = P.fft_lx, ly = P.fft_ly;
+    twiddle(P.d_ft, P.d_fb, P.d_tw_ix, ly, nx, lx, nz, (int64_t)lx * nz, nz, (int64_t)nx * nz, nz, s);
+    twiddle(out, P.d_ft, P.d_tw_iy, nx, ny, ly, nz, nz, (int64_t)nx * nz, nz, (int64_t)nx * nz, s);
+}
+
+}  // namespace ufss

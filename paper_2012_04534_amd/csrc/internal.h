@@ -79,6 +79,12 @@ struct Plan {
     float* d_hsel = nullptr;       // H_k per selection entry [m] or [npos*m]
     uint32_t* d_u = nullptr;       // integer-turn delay table [wy+1][wx+1][nz]
     float* d_amp = nullptr;        // Gaussian beam amplitude, same layout (theta > 0)
+    // transform path (UFSS_ALGO_FFT): sizes, K^ quadrant [ly/2+1][lx/2+1][nz][mu],
+    // twiddle tables and three work buffers
+    int fft_lx = 0, fft_ly = 0;
+    void* d_khat = nullptr;
+    cf32 *d_tw_fx = nullptr, *d_tw_fy = nullptr, *d_tw_ix = nullptr, *d_tw_iy = nullptr;
+    cf32 *d_fa = nullptr, *d_fb = nullptr, *d_ft = nullptr;
     // device workspace
     cf32* d_yraw = nullptr;        // GEMM output over union bins [npos][mu]
     void* d_rop = nullptr;         // adjoint operand (H-scaled), [npos][mu] f32 or bf16
@@ -174,6 +180,16 @@ void launch_copy(int64_t n, const cf32* src, cf32* dst, hipStream_t s);
 void launch_fista_stats(double* stats, int k, const double* upd, const double* res2,
                         const double* g1_prev, double lam, int have_ref, double ref2,
                         hipStream_t s);
+
+// Transform path (fft.hip).
+void fft_setup(Plan& P);
+int64_t fft_table_bytes(const Plan& P);
+void fft_fwd_transform(const Plan& P, const cf32* x, hipStream_t s);
+void fft_fwd_contract(const Plan& P, hipStream_t s);
+void fft_fwd_inverse(const Plan& P, hipStream_t s);
+void fft_adj_transform(const Plan& P, hipStream_t s);
+void fft_adj_contract(const Plan& P, hipStream_t s);
+void fft_adj_inverse(const Plan& P, cf32* out, hipStream_t s);
 
 // Backtracking FISTA: trial step p = soft(gamma - step g, thresh) with six
 // FP64 partials per block (see vec.hip); out = a + beta (a - b) with ||out||^2.

@@ -81,7 +81,7 @@ static void validate_geom(const ufss_geom* g) {
         fail(UFSS_ERR_INVALID_ARG, "physical parameters must be positive");
     if (g->dtype != UFSS_F32 && g->dtype != UFSS_BF16)
         fail(UFSS_ERR_INVALID_ARG, "dtype must be UFSS_F32 or UFSS_BF16");
-    if (g->algo < UFSS_ALGO_AUTO || g->algo > UFSS_ALGO_PHASOR)
+    if (g->algo < UFSS_ALGO_AUTO || g->algo > UFSS_ALGO_FFT)
         fail(UFSS_ERR_INVALID_ARG, "unknown algo");
     if (!(g->theta >= 0) || !(g->theta < 0.5 * M_PI))
         fail(UFSS_ERR_INVALID_ARG, "theta must be in [0, pi/2)");
@@ -248,7 +248,8 @@ static void free_plan(Plan* P) {
     void* ptrs[] = {P->d_bins, P->d_ubins, P->d_map, P->d_hsel, P->d_u, P->d_yraw,
                     P->d_rop, P->d_xop, P->d_part, P->d_scalars, P->d_r, P->d_g,
                     P->d_gamma, P->d_v, P->d_stats, P->d_gpart, P->d_ptab_f, P->d_ptab_a,
-                    P->d_bt, P->d_bt_scal, P->d_amp};
+                    P->d_bt, P->d_bt_scal, P->d_amp, P->d_khat, P->d_tw_fx, P->d_tw_fy,
+                    P->d_tw_ix, P->d_tw_iy, P->d_fa, P->d_fb, P->d_ft};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& v : P->kev)
@@ -347,6 +348,8 @@ Plan* plan_create(const ufss_geom* g, int m, int per_position, const int32_t* bi
     if (algo == UFSS_ALGO_PHASOR && g->dtype == UFSS_BF16)
         fail(UFSS_ERR_UNSUPPORTED, "the phasor path is FP32 only");
     if (algo == UFSS_ALGO_PHASOR && !per_position) algo = UFSS_ALGO_GEMM;
+    if (algo == UFSS_ALGO_FFT && g->dtype == UFSS_BF16)
+        fail(UFSS_ERR_UNSUPPORTED, "the transform path is FP32 only");
 
     Plan* P = new (std::nothrow) Plan();
     if (!P) fail(UFSS_ERR_OOM, "host allocation failed");
@@ -423,6 +426,7 @@ Plan* plan_create(const ufss_geom* g, int m, int per_position, const int32_t* bi
         P->d_rop = dalloc<cf32>(*P, (size_t)npos * opw);
         if (P->dtype == UFSS_BF16) P->d_xop = dalloc<cf32>(*P, (size_t)(P->nvox + 1) / 2 + 1);
         if (algo == UFSS_ALGO_GEMM && P->dtype == UFSS_BF16) bf16_set_tables(*P, 1);
+        if (algo == UFSS_ALGO_FFT) fft_setup(*P);
         P->part_cap = 65536;
         P->d_part = dalloc<double>(*P, P->part_cap);
         P->d_scalars = dalloc<double>(*P, 64);

@@ -21,7 +21,7 @@ ERRORS = {
     -5: "UNSUPPORTED", -6: "DIVERGED",
 }
 F32, BF16 = 0, 1
-ALGO_AUTO, ALGO_GEMM, ALGO_PHASOR = 0, 1, 2
+ALGO_AUTO, ALGO_GEMM, ALGO_PHASOR, ALGO_FFT = 0, 1, 2, 3
 SAMPLE_RND, SAMPLE_RND_F, SAMPLE_MAX, SAMPLE_NRG, SAMPLE_NRG_F = 0, 1, 2, 3, 4
 
 EXPORTED = [

@@ -183,6 +183,8 @@ def test_cscan_workloads_full_sampled(name, dtype, dev):
     runs = [(u.ALGO_GEMM, None), (u.ALGO_GEMM, "shipped")]
     if dtype == "f32" and w["per_position"]:
         runs.append((u.ALGO_PHASOR, None))
+    if dtype == "f32":
+        runs.append((u.ALGO_FFT, None))
     xd = torch.from_numpy(x).to(dev)
     yd = torch.from_numpy(y).to(dev)
     for algo, tiling in runs:
