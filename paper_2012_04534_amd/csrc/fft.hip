@@ -14,8 +14,9 @@
 // integer-turn delays).  P_d is even in d_x and in d_y, so K^ is a cosine
 // transform, even in q_x and q_y: only the quadrant q_x <= L_x / 2,
 // q_y <= L_y / 2 is stored, and each stored entry serves up to four q.
-// K^ is built once per plan in FP64 and stored in FP32; the applies run in
-// FP32.  The contraction streams K^ once per apply and is bound by HBM (or by
+// K^ is built once per plan in FP64 and stored in FP32, also as a transposed
+// copy [q][k][z] so that both contractions read rows in order; the applies run
+// in FP32.  The contraction streams K^ once per apply and is bound by HBM (or by
 // the last-level cache when K^ fits there); the lateral transforms are small
 // products with twiddle tables.
 #include <algorithm>
@@ -86,71 +87,86 @@ __device__ __forceinline__ int orbit(int oy, int ox, int ly, int lx, int* qy, in
     return n;
 }
 
-// Forward contraction: one workgroup per quadrant entry, lanes over bins.
-__global__ __launch_bounds__(256) void contract_fwd_kernel(const cf32* __restrict__ khat,
-                                                          const cf32* __restrict__ xh,
-                                                          cf32* __restrict__ yh, int ly, int lx,
-                                                          int nox, int nz, int mu) {
+// Contraction, both directions: one workgroup per quadrant entry (its up to
+// four transform indices q), out[q][c] = sum_r T[o][r][c] in[q][r] (CONJ:
+// conj(T)).  Forward: c = bin, r = depth, T = K^[o][z][k]; adjoint: c = depth,
+// r = bin, T = the transposed copy K^t[o][k][z].  Consecutive threads take
+// consecutive c (coalesced rows of T); when C < 256 the reduction range is
+// split over G = 256 / C thread groups whose partial sums meet in LDS in a
+// fixed order.
+template <bool CONJ>
+__global__ __launch_bounds__(256) void contract_kernel(const cf32* __restrict__ tab,
+                                                      const cf32* __restrict__ in,
+                                                      cf32* __restrict__ out, int ly, int lx,
+                                                      int nox, int C, int R) {
     extern __shared__ __align__(16) unsigned char smem[];
-    cf32* xs = reinterpret_cast<cf32*>(smem);          // [4][nz]
+    cf32* vs = reinterpret_cast<cf32*>(smem);                 // [4][R] input rows
+    float* red = reinterpret_cast<float*>(vs + 4 * R);        // [G][4][C][2] partials
     const int o = blockIdx.x, oy = o / nox, ox = o - oy * nox;
     int qy[4], qx[4];
     const int nq = orbit(oy, ox, ly, lx, qy, qx);
-    for (int t = threadIdx.x; t < nq * nz; t += blockDim.x) {
-        const int q = t / nz, z = t - q * nz;
-        xs[t] = xh[((int64_t)qy[q] * lx + qx[q]) * nz + z];
+    for (int t = threadIdx.x; t < nq * R; t += blockDim.x) {
+        const int q = t / R, r = t - q * R;
+        vs[t] = in[((int64_t)qy[q] * lx + qx[q]) * R + r];
     }
     __syncthreads();
-    const cf32* kb = khat + (int64_t)o * nz * mu;
-    for (int k = threadIdx.x; k < mu; k += blockDim.x) {
+    const cf32* tb = tab + (int64_t)o * R * C;
+    const int G = C >= 256 ? 1 : 256 / C;
+    const int grp = threadIdx.x / (C >= 256 ? 256 : C);
+    const int lane_c = threadIdx.x - grp * (C >= 256 ? 256 : C);
+    const int rper = (R + G - 1) / G;
+    const int r0 = grp * rper, r1 = min(R, r0 + rper);
+    for (int c = lane_c; c < C && grp < G; c += (C >= 256 ? 256 : C)) {
         float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int z = 0; z < nz; ++z) {
-            const cf32 kv = kb[(int64_t)z * mu + k];
+#pragma unroll 4
+        for (int r = r0; r < r1; ++r) {
+            const cf32 kv = tb[(int64_t)r * C + c];
+            const float ki = CONJ ? -kv.im : kv.im;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 if (q >= nq) break;
-                const cf32 v = xs[q * nz + z];
-                ar[q] += kv.re * v.re - kv.im * v.im;
-                ai[q] += kv.re * v.im + kv.im * v.re;
+                const cf32 v = vs[q * R + r];
+                ar[q] += kv.re * v.re - ki * v.im;
+                ai[q] += kv.re * v.im + ki * v.re;
             }
         }
-        for (int q = 0; q < nq; ++q)
-            yh[((int64_t)qy[q] * lx + qx[q]) * mu + k] = cf32{ar[q], ai[q]};
+        if (G == 1) {
+            for (int q = 0; q < nq; ++q)
+                out[((int64_t)qy[q] * lx + qx[q]) * C + c] = cf32{ar[q], ai[q]};
+        } else {
+            for (int q = 0; q < nq; ++q) {
+                red[((grp * 4 + q) * C + c) * 2] = ar[q];
+                red[((grp * 4 + q) * C + c) * 2 + 1] = ai[q];
+            }
+        }
+    }
+    if (G == 1) return;
+    __syncthreads();
+    for (int t = threadIdx.x; t < nq * C; t += blockDim.x) {
+        const int q = t / C, c = t - q * C;
+        float sr = 0.f, si = 0.f;
+        for (int g2 = 0; g2 < G; ++g2) {
+            sr += red[((g2 * 4 + q) * C + c) * 2];
+            si += red[((g2 * 4 + q) * C + c) * 2 + 1];
+        }
+        out[((int64_t)qy[q] * lx + qx[q]) * C + c] = cf32{sr, si};
     }
 }
 
-// Adjoint contraction: one workgroup per quadrant entry, lanes over depth.
-__global__ __launch_bounds__(256) void contract_adj_kernel(const cf32* __restrict__ khat,
-                                                          const cf32* __restrict__ rh,
-                                                          cf32* __restrict__ xh, int ly, int lx,
-                                                          int nox, int nz, int mu) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    cf32* rs = reinterpret_cast<cf32*>(smem);          // [4][mu]
-    const int o = blockIdx.x, oy = o / nox, ox = o - oy * nox;
-    int qy[4], qx[4];
-    const int nq = orbit(oy, ox, ly, lx, qy, qx);
-    for (int t = threadIdx.x; t < nq * mu; t += blockDim.x) {
-        const int q = t / mu, k = t - q * mu;
-        rs[t] = rh[((int64_t)qy[q] * lx + qx[q]) * mu + k];
-    }
-    __syncthreads();
-    const cf32* kb = khat + (int64_t)o * nz * mu;
-    for (int z = threadIdx.x; z < nz; z += blockDim.x) {
-        float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
-        const cf32* row = kb + (int64_t)z * mu;
-        for (int k = 0; k < mu; ++k) {
-            const cf32 kv = row[k];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (q >= nq) break;
-                const cf32 v = rs[q * mu + k];
-                // conj(kv) * v
-                ar[q] += kv.re * v.re + kv.im * v.im;
-                ai[q] += kv.re * v.im - kv.im * v.re;
-            }
-        }
-        for (int q = 0; q < nq; ++q)
-            xh[((int64_t)qy[q] * lx + qx[q]) * nz + z] = cf32{ar[q], ai[q]};
+static size_t contract_lds(int C, int R) {
+    const int G = C >= 256 ? 1 : 256 / C;
+    return (size_t)4 * R * sizeof(cf32) + (G > 1 ? (size_t)G * 4 * C * 2 * sizeof(float) : 0);
+}
+
+// Plan time: T[o][b][a] = S[o][a][b] for S of shape [A][B] per entry (the
+// transposed copy of K^: A = nz, B = mu).
+__global__ void transpose_kernel(const cf32* __restrict__ src, cf32* __restrict__ dst, int A, int B) {
+    const int o = blockIdx.y;
+    const cf32* s = src + (int64_t)o * A * B;
+    cf32* d = dst + (int64_t)o * A * B;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < A * B; t += gridDim.x * blockDim.x) {
+        const int b = t / A, a = t - b * A;
+        d[t] = s[(int64_t)a * B + b];
     }
 }
 
@@ -216,8 +232,8 @@ void fft_setup(Plan& P) {
     if (fft_table_bytes(P) > kFftTableMax)
         fail(UFSS_ERR_UNSUPPORTED, "transform table larger than 32 GiB");
     // LDS staging: twiddle rows (8 x L) and four transform rows (4 x nz or mu)
-    if (std::max(lx, ly) > 1024 || std::max(nz, mu) > 2048)
-        fail(UFSS_ERR_UNSUPPORTED, "grid too large for the transform path (L <= 1024, nz and bins <= 2048)");
+    if (std::max(lx, ly) > 1024 || std::max(nz, mu) > 1536)
+        fail(UFSS_ERR_UNSUPPORTED, "grid too large for the transform path (L <= 1024, nz and bins <= 1536)");
     P.fft_lx = lx;
     P.fft_ly = ly;
     // twiddle tables (FP64 angles from exact integer products, stored FP32)
@@ -267,7 +283,8 @@ void fft_setup(Plan& P) {
         UFSS_HIP(hipMalloc(&cx, hx.size() * sizeof(double)));
         UFSS_HIP(hipMalloc(&cy, hy.size() * sizeof(double)));
         UFSS_HIP(hipMalloc(&P.d_khat, (int64_t)noy * nox * zc * sizeof(cf32)));
-        P.ws_bytes += (int64_t)noy * nox * zc * sizeof(cf32);
+        UFSS_HIP(hipMalloc(&P.d_khat_t, (int64_t)noy * nox * zc * sizeof(cf32)));
+        P.ws_bytes += 2 * (int64_t)noy * nox * zc * sizeof(cf32);
         UFSS_HIP(hipMemcpy(cx, hx.data(), hx.size() * sizeof(double), hipMemcpyHostToDevice));
         UFSS_HIP(hipMemcpy(cy, hy.data(), hy.size() * sizeof(double), hipMemcpyHostToDevice));
         const int64_t n = ncell * mu;
@@ -284,6 +301,10 @@ void fft_setup(Plan& P) {
         hipLaunchKernelGGL(cos_kernel<true>, dim3((unsigned)((zc + 255) / 256), noy, nox), dim3(256),
                            0, nullptr, (void*)P.d_khat, s64, cy, noy, wy + 1, zc, zc, (int64_t)nox * zc,
                            zc, (int64_t)nox * zc);
+        UFSS_HIP(hipGetLastError());
+        hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)std::min<int64_t>((zc + 255) / 256, 1024), noy * nox),
+                           dim3(256), 0, nullptr, static_cast<const cf32*>(P.d_khat),
+                           static_cast<cf32*>(P.d_khat_t), nz, mu);
         UFSS_HIP(hipGetLastError());
         UFSS_HIP(hipDeviceSynchronize());
     } catch (...) {
@@ -310,9 +331,9 @@ void fft_fwd_transform(const Plan& P, const cf32* x, hipStream_t s) {
 //   Y^[q][k] = sum_z K^[q][z][k] X^[q][z]
 void fft_fwd_contract(const Plan& P, hipStream_t s) {
     const int lx = P.fft_lx, ly = P.fft_ly, nox = lx / 2 + 1, noy = ly / 2 + 1;
-    hipLaunchKernelGGL(contract_fwd_kernel, dim3(noy * nox), dim3(256), (size_t)4 * P.g.nz * sizeof(cf32),
-                       s, static_cast<const cf32*>(P.d_khat), P.d_fa, P.d_fb, ly, lx, nox, P.g.nz,
-                       (int)P.ubins_h.size());
+    const int mu = (int)P.ubins_h.size(), nz = P.g.nz;
+    hipLaunchKernelGGL(contract_kernel<false>, dim3(noy * nox), dim3(256), contract_lds(mu, nz), s,
+                       static_cast<const cf32*>(P.d_khat), P.d_fa, P.d_fb, ly, lx, nox, mu, nz);
     UFSS_HIP(hipGetLastError());
 }
 
@@ -334,8 +355,9 @@ void fft_adj_transform(const Plan& P, hipStream_t s) {
 void fft_adj_contract(const Plan& P, hipStream_t s) {
     const int lx = P.fft_lx, ly = P.fft_ly, nox = lx / 2 + 1, noy = ly / 2 + 1;
     const int mu = (int)P.ubins_h.size();
-    hipLaunchKernelGGL(contract_adj_kernel, dim3(noy * nox), dim3(256), (size_t)4 * mu * sizeof(cf32), s,
-                       static_cast<const cf32*>(P.d_khat), P.d_fa, P.d_fb, ly, lx, nox, P.g.nz, mu);
+    const int nz = P.g.nz;
+    hipLaunchKernelGGL(contract_kernel<true>, dim3(noy * nox), dim3(256), contract_lds(nz, mu), s,
+                       static_cast<const cf32*>(P.d_khat_t), P.d_fa, P.d_fb, ly, lx, nox, nz, mu);
     UFSS_HIP(hipGetLastError());
 }
 

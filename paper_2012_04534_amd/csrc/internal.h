@@ -83,6 +83,7 @@ struct Plan {
     // twiddle tables and three work buffers
     int fft_lx = 0, fft_ly = 0;
     void* d_khat = nullptr;
+    void* d_khat_t = nullptr;      // the same, transposed per entry: [..][mu][nz]
     cf32 *d_tw_fx = nullptr, *d_tw_fy = nullptr, *d_tw_ix = nullptr, *d_tw_iy = nullptr;
     cf32 *d_fa = nullptr, *d_fb = nullptr, *d_ft = nullptr;
     // device workspace

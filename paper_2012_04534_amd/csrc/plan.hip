@@ -248,7 +248,7 @@ static void free_plan(Plan* P) {
     void* ptrs[] = {P->d_bins, P->d_ubins, P->d_map, P->d_hsel, P->d_u, P->d_yraw,
                     P->d_rop, P->d_xop, P->d_part, P->d_scalars, P->d_r, P->d_g,
                     P->d_gamma, P->d_v, P->d_stats, P->d_gpart, P->d_ptab_f, P->d_ptab_a,
-                    P->d_bt, P->d_bt_scal, P->d_amp, P->d_khat, P->d_tw_fx, P->d_tw_fy,
+                    P->d_bt, P->d_bt_scal, P->d_amp, P->d_khat, P->d_khat_t, P->d_tw_fx, P->d_tw_fy,
                     P->d_tw_ix, P->d_tw_iy, P->d_fa, P->d_fb, P->d_ft};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
