@@ -38,8 +38,8 @@ PEAK_HBM = 8e12
 # source it was measured on; a changed source or another tiling reports null.
 TRAFFIC = {
     # 32 x 32 C-scan, FP32 union-GEMM, shipped tiling (profiles/cscan32_fp32_gemm_and_phasor.md)
-    "cscan32/gemm/forward/fs4-zs8-nw5-np2-zc8": {"bytes": 20.579e6, "sha": "5c52ed5ce783316f"},
-    "cscan32/gemm/adjoint/as12-np2-kc16": {"bytes": 32.297e6, "sha": "5c52ed5ce783316f"},
+    "cscan32/gemm/forward/fs4-zs8-nw5-np2-zc8": {"bytes": 20.579e6, "sha": "367ebf0abcea85ec"},
+    "cscan32/gemm/adjoint/as12-np2-kc16": {"bytes": 32.304e6, "sha": "367ebf0abcea85ec"},
 }
 TRAFFIC_SRC = {"gemm": "paper_2012_04534_amd/csrc/gemm_f32.hip",
                "gemm-bf16": "paper_2012_04534_amd/csrc/gemm_bf16.hip",
@@ -169,11 +169,14 @@ def time_to_accuracy(ufss, W, plan, g, w, bins, y, lam, L, t_l, dev, tcfg):
     out = {"reference": "plain FP32 FISTA iterate after %d iterations" % K,
            "lipschitz_s": round(t_l, 4), "L": L, "lambda": lam, "levels": [0.3, 0.1, 0.03, 0.01]}
     x = torch.zeros_like(a_ref)
-    for tag, dt in (("fp32", ufss.F32), ("bf16", ufss.BF16)):
+    for tag, dt, algo in (("fp32", ufss.F32, None), ("fp32_transform", ufss.F32, ufss.ALGO_FFT),
+                          ("bf16", ufss.BF16, ufss.ALGO_GEMM)):
         p = plan
-        if dt != ufss.F32:
-            p = ufss.Plan(g, w["m"], w["per_position"], bins, dtype=dt, algo=ufss.ALGO_GEMM)
-            autotune(ufss, p, tcfg)
+        if algo is not None:
+            p = ufss.Plan(g, w["m"], w["per_position"], bins, dtype=dt, algo=algo)
+            if algo == ufss.ALGO_GEMM:
+                autotune(ufss, p, tcfg)
+        x.zero_()                      # every row starts from zero, as the reference did
         st = ufss.ufss_fista(p, y, lam, L, K, x, a_ref=a_ref)
         per_it = fista_time(ufss, p, y, lam, L, 20, x) / 20
         iters, times = [], []
@@ -184,7 +187,7 @@ def time_to_accuracy(ufss, W, plan, g, w, bins, y, lam, L, t_l, dev, tcfg):
             times.append(round(k * per_it, 5) if k else None)
         out[tag] = {"s_per_iter": round(per_it, 6), "iters_to_level": iters, "time_to_level_s": times,
                     "err_at_K": float(st["err_ref"][-1])}
-        if dt != ufss.F32:
+        if p is not plan:
             p.close()
     if os.path.exists(WEIGHTS):
         from paper_2012_04534_amd import learned as LN
@@ -230,6 +233,16 @@ def time_to_accuracy(ufss, W, plan, g, w, bins, y, lam, L, t_l, dev, tcfg):
                                                          for k in warm_it],
                           "fista_from_zero_iters_to_level": [mean_iters(cold, j) for j in range(lv)]}
         net.close()
+        # the same checkpoint with the transform-domain operator as its fixed layers
+        pt = ufss.Plan(g, w["m"], w["per_position"], bins, algo=ufss.ALGO_FFT)
+        nt_ = ufss.Net(pt, stages=16, channels=8, L=L, mu=w["mu"])
+        ufss.ufss_unrolled_load(nt_, WEIGHTS)
+        rt = LN.evaluate(nt_, pt, ev, L)
+        out["learned"]["transform_operator"] = {"time_s_mean": float(rt["time_s"].mean()),
+                                                "err_mean": float(rt["err"].mean()),
+                                                "err_max": float(rt["err"].max())}
+        nt_.close()
+        pt.close()
     if own is not None:
         own.close()
     return out
@@ -245,16 +258,41 @@ def cscan64_rates(ufss, W, dev, ev_time, tcfg):
     x = torch.from_numpy(W.cn((g["ny"], g["nx"], g["nz"]), 1).astype(np.complex64)).to(dev)
     y = torch.empty((g["ny"], g["nx"], w["m"]), dtype=torch.complex64, device=dev)
     out = {"cmac_per_apply": cm}
+    xo = torch.empty_like(x)          # adjoint output (the inputs stay fixed)
     for tag, dt, peak in (("fp32", ufss.F32, PEAK_FP32_MFMA), ("bf16", ufss.BF16, PEAK_BF16_MFMA)):
         p = ufss.Plan(g, w["m"], False, bins, dtype=dt)
         autotune(ufss, p, tcfg)
         tf = ev_time(lambda: ufss.ufss_forward(p, x, y), 3)
-        ta = ev_time(lambda: ufss.ufss_adjoint(p, y, x), 3)
+        ta = ev_time(lambda: ufss.ufss_adjoint(p, y, xo), 3)
         tfl = 16.0 * cm / ((tf + ta) * 1e-3)
         out[tag] = {"forward_ms": round(tf, 3), "adjoint_ms": round(ta, 3),
                     "a_plus_ah_tflops": round(tfl / 1e12, 2), "frac_of_mfma_peak": round(tfl / peak, 4)}
         p.close()
+    out["fp32_transform"] = transform_rates(ufss, g, w["m"], False, bins, x, y, xo, ev_time, cm)
     return out
+
+
+def transform_rates(ufss, g, m, per_pos, bins, x, y, xo, ev_time, cm):
+    """The transform-domain operator (UFSS_ALGO_FFT) on the same problem: apply
+    times, the direct-sum-equivalent rate (the same algorithmic count as the
+    GEMM rows, so the two compare as times) and its contraction kernels against
+    HBM: each streams its table of (ly/2+1)(lx/2+1) nz mu complex64 once."""
+    p = ufss.Plan(g, m, per_pos, bins, algo=ufss.ALGO_FFT)
+    tf = ev_time(lambda: ufss.ufss_forward(p, x, y), 3)
+    ta = ev_time(lambda: ufss.ufss_adjoint(p, y, xo), 3)
+    cf = ufss.ufss_time_kernel(p, 0, 20)
+    ca = ufss.ufss_time_kernel(p, 1, 20)
+    info = p.info()
+    lx, ly = g["nx"] + info["win_x"], g["ny"] + info["win_y"]
+    tab = (ly // 2 + 1) * (lx // 2 + 1) * g["nz"] * info["union_size"] * 8
+    p.close()
+    return {"forward_ms": round(tf, 4), "adjoint_ms": round(ta, 4),
+            "direct_sum_equivalent_tflops": round(16.0 * cm / ((tf + ta) * 1e-3) / 1e12, 1),
+            "transform_size": [ly, lx], "table_bytes": tab,
+            "contraction_ms": [round(cf, 4), round(ca, 4)],
+            "contraction_gbs": [round(tab / (cf * 1e-3) / 1e9, 1), round(tab / (ca * 1e-3) / 1e9, 1)],
+            "contraction_frac_of_hbm": [round(tab / (cf * 1e-3) / PEAK_HBM, 3),
+                                        round(tab / (ca * 1e-3) / PEAK_HBM, 3)]}
 
 
 def batch_rate(ufss, W, dev, iters=5):
@@ -298,6 +336,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cscan32")
+    ap.add_argument("--algo", default="auto", choices=["auto", "fft"],
+                    help="auto: the windowed GEMM (or, if faster, the phasor path); fft: time "
+                         "the transform-domain operator instead (FP32)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true", help="skip time-to-accuracy and extras")
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16"],
@@ -352,6 +393,10 @@ def main():
     pdt = ufss.BF16 if bf16 else ufss.F32
     # the phasor algorithm is FP32 only
     algos = [ufss.ALGO_GEMM, ufss.ALGO_PHASOR] if (per_pos and not bf16) else [ufss.ALGO_GEMM]
+    if args.algo == "fft":
+        if bf16:
+            sys.exit("bench: the transform-domain operator is FP32 only")
+        algos = [ufss.ALGO_FFT]
     xr = torch.from_numpy(W.cn(shape_x, 1).astype(np.complex64)).to(dev)
     yr = torch.empty(shape_y, dtype=torch.complex64, device=dev)
     xo = torch.empty_like(xr)
@@ -363,13 +408,18 @@ def main():
             tuned = dict(zip(("fwd_split", "adj_split"), autotune(ufss, plan, tcfg)))
         tf = ev_time(lambda: ufss.ufss_forward(plan, xr, yr), 5)
         ta = ev_time(lambda: ufss.ufss_adjoint(plan, yr, xo), 5)
-        name = {ufss.ALGO_GEMM: "gemm-bf16" if bf16 else "gemm", ufss.ALGO_PHASOR: "phasor"}[algo]
+        name = {ufss.ALGO_GEMM: "gemm-bf16" if bf16 else "gemm", ufss.ALGO_PHASOR: "phasor",
+                ufss.ALGO_FFT: "transform"}[algo]
         extras["algos"][name] = {"forward_ms": round(tf, 4), "adjoint_ms": round(ta, 4),
                                  "a_plus_ah_gflops": round(flop_pair / ((tf + ta) * 1e-3) / 1e9, 1)}
         if best is None or tf + ta < best[1]:
             best = (algo, tf + ta, name)
         plan.close()
     algo, _, algo_name = best
+    if not bf16 and algo != ufss.ALGO_FFT:
+        # the transform-domain operator on the same problem, reported beside the
+        # windowed GEMM (which stays the timed path)
+        extras["transform"] = transform_rates(ufss, g, m, per_pos, bins, xr, yr, xo, ev_time, cmac)
     torch.cuda.synchronize()
     t_plan = time.perf_counter()
     plan = ufss.Plan(g, m, per_pos, bins, algo=algo, dtype=pdt)
@@ -418,7 +468,15 @@ def main():
     k_f, k_a, n_f, n_a = ufss.ufss_plan_kernel_times(plan)
     extras["kernel_launches_timed"] = {"forward": n_f, "adjoint": n_a}
     dom, k_ms = ("adjoint", k_a) if k_a >= k_f else ("forward", k_f)
-    if algo == ufss.ALGO_PHASOR:
+    if algo == ufss.ALGO_FFT:
+        # the contraction streams its table of (ly/2+1)(lx/2+1) nz mu complex64
+        # once per launch: bound by HBM
+        pi = plan.info()
+        tab = ((g["ny"] + pi["win_y"]) // 2 + 1) * ((g["nx"] + pi["win_x"]) // 2 + 1) * g["nz"] * \
+            pi["union_size"] * 8
+        roof = {"bound": "hbm", "achieved": round(tab / (k_ms * 1e-3) / 1e9, 1),
+                "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
+    elif algo == ufss.ALGO_PHASOR:
         # per term: one complex MAC (8 flops) on the VALU; peak is the FP32 vector rate
         roof = {"bound": "alu", "achieved": round(8.0 * cmac / (k_ms * 1e-3) / 1e12, 3),
                 "peak": 157.3, "unit": "TFLOP/s"}
@@ -427,7 +485,8 @@ def main():
                 "peak": (PEAK_BF16_MFMA if bf16 else PEAK_FP32_MFMA) / 1e12, "unit": "TFLOP/s"}
     roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
     pinfo = plan.info()
-    roof["traffic"] = traffic_bytes(args.workload, algo_name, dom, pinfo)
+    roof["traffic"] = traffic_bytes(args.workload, algo_name, dom, pinfo) \
+        if algo_name in TRAFFIC_SRC else None
     roof["tiling"] = tiling_key(pinfo, dom)
     roof["kernel"] = "%s %s core (%.4f ms per launch)" % (algo_name, dom, k_ms)
     extras["kernel_ms"] = {"forward_core": round(k_f, 4), "adjoint_core": round(k_a, 4)}

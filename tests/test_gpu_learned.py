@@ -147,3 +147,32 @@ def test_training_reduces_loss_and_checkpoint_roundtrip(dev, tmp_path):
     net.close()
     net2.close()
     plan.close()
+
+
+def test_network_on_transform_operator_matches_oracle(dev):
+    """The unrolled network with the transform-domain operator as its fixed
+    layers: forward against the oracle network, and gradients equal to those
+    on the GEMM plan (same parameters)."""
+    u = ufss()
+    g, plan, A, AH, yd, yt, L = tiny(u, dev)
+    bins, _ = u.ufss_select_freqs(g, 5, True, 3)        # the bins of tiny()
+    pf = u.Plan(g, 5, True, bins, algo=u.ALGO_FFT)
+    S, ch = 4, 3
+    p = random_params(S, ch, 21)
+    out = []
+    for pl in (pf, plan):
+        net = u.Net(pl, stages=S, channels=ch, L=L, mu=0.1)
+        u.ufss_unrolled_params(net, set_to=p)
+        x = torch.zeros((5, 6, 12), dtype=torch.complex64, device=dev)
+        u.ufss_unrolled_forward(net, yt, x)
+        a_ref = torch.from_numpy((0.5 * W.cn((5, 6, 12), 23)).astype(np.complex64)).to(dev)
+        loss, grad = u.ufss_unrolled_grad(net, yt, a_ref)
+        out.append((x.cpu().numpy(), loss, np.asarray(grad)))
+        net.close()
+    xo = N.forward(A, AH, yd, p.astype(np.float64), S, ch, L, 0.1, (5, 6, 12))
+    assert np.linalg.norm(out[0][0] - xo) / np.linalg.norm(xo) < 1e-5
+    assert out[0][1] == pytest.approx(out[1][1], rel=1e-5)
+    ga, gb = out[0][2], out[1][2]
+    assert np.abs(ga - gb).max() <= 1e-4 * np.abs(gb).max()
+    pf.close()
+    plan.close()
