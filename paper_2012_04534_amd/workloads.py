@@ -177,6 +177,24 @@ def scene(g, n_scat, amp=(1.0, 1.0), seed=0, back_wall=None, phase=0.0,
     return x
 
 
+def rademacher(shape, seed):
+    """Independent uniform signs in {-1, +1} (int8), for the mixing Sigma of the
+    random sampling strategy."""
+    rng = np.random.default_rng(seed)
+    return (2 * rng.integers(0, 2, size=shape) - 1).astype(np.int8)
+
+
+def uniform_subsets(nt, m, lead_shape, seed):
+    """m distinct DFT bins of [0, nt) per entry of lead_shape, each subset
+    uniform over all such subsets and sorted (int32 [*lead_shape, m])."""
+    rng = np.random.default_rng(seed)
+    n = int(np.prod(lead_shape)) if len(lead_shape) else 1
+    out = np.empty((n, m), dtype=np.int32)
+    for i in range(n):
+        out[i] = np.sort(rng.choice(nt, size=m, replace=False))
+    return out.reshape(tuple(lead_shape) + (m,))
+
+
 def cn(shape, seed):
     """Circular complex Gaussian CN(0, 1) array (complex128)."""
     rng = np.random.default_rng(seed)
