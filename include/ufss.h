@@ -235,6 +235,27 @@ int ufss_crb(const ufss_geom* g, int32_t m, int32_t per_position, int32_t trials
 int ufss_plan_create(const ufss_geom* g, int32_t m, int32_t per_position,
                      const int32_t* bins, ufss_plan_t* out);
 
+/* A plan whose measurements are randomly mixed (paper Sec. II-B compression
+ * Phi_i = S_i F Sigma_i with the random sampling strategy of Sec. III-A:
+ * Sigma_i = Diag(xi_i), xi_i Rademacher; Table I Phi_rnd, Phi_rnd,m and
+ * Phi_rnd,m,f).  The measurement of position i is y_i = S_i F Sigma_i b_i with
+ * b_i the sampled A-scan, i.e. y_i[m] = sum_j xih_i[(k_m - j) mod nt] B_i[j]
+ * with B_i = F b_i over every DFT index j (the signed bin j or j - nt: the
+ * Gabor spectrum's small negative-frequency part is kept) and
+ * xih_i = F xi_i / nt (FP64 on the host, stored FP32).  The operator core
+ * (FP32 GEMM or transform, g->algo) runs over all nt indices; the mixing and
+ * its adjoint replace the bin gather / scatter.  Every other call (forward,
+ * adjoint, lipschitz, fista, backtracking, the unrolled network) takes the plan
+ * as usual; batched FISTA refuses it.
+ *   bins   HOST int32 [m] or [ny][nx][m] (per_position): strictly ascending in
+ *          [0, nt) (any DFT coefficient of the mixed A-scan)
+ *   signs  HOST int8 [nt] or [ny][nx][nt] (per_position_signs) of +1 / -1
+ * nt must be a power of two with 8 nt + 12 m <= 65536 (LDS rows of the mixing).
+ * Errors: INVALID_ARG, UNSUPPORTED (BF16, phasor path, nt, m), OOM, HIP. */
+int ufss_plan_create_mixed(const ufss_geom* g, int32_t m, int32_t per_position,
+                           const int32_t* bins, int32_t per_position_signs,
+                           const int8_t* signs, ufss_plan_t* out);
+
 /* Release a plan and its device memory (synchronises the device). */
 int ufss_plan_destroy(ufss_plan_t plan);
 

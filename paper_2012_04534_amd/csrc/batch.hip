@@ -245,6 +245,8 @@ int fista_batched(int n, Plan* const* plans, const cf32* const* ys, cf32* const*
             fail(UFSS_ERR_UNSUPPORTED, "batched FISTA needs GEMM-path plans");
         if (plans[i]->d_amp)
             fail(UFSS_ERR_UNSUPPORTED, "batched FISTA does not take a Gaussian beam");
+        if (plans[i]->mix)
+            fail(UFSS_ERR_UNSUPPORTED, "batched FISTA does not take mixed plans");
         for (int j = 0; j < i; ++j)
             if (plans[j] == plans[i]) fail(UFSS_ERR_INVALID_ARG, "a plan appears twice in the batch");
     }

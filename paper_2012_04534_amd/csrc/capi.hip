@@ -11,7 +11,8 @@
 
 namespace ufss {
 
-Plan* plan_create(const ufss_geom* g, int m, int per_position, const int32_t* bins);
+Plan* plan_create(const ufss_geom* g, int m, int per_position, const int32_t* bins,
+                  const MixSpec* mix = nullptr);
 void plan_destroy(Plan* P);
 void plan_info(const Plan* P, ufss_plan_info* info);
 void select_freqs(const ufss_geom* g, int m, int per_position, uint64_t seed, int32_t* out,
@@ -86,12 +87,16 @@ void op_forward(Plan& P, const cf32* x, cf32* y, const cf32* ymeas, double* res2
         launch_forward_gemm(P, x, s);
         ktime_end(P, 0, s);
     }
-    int nb = launch_forward_post(P, y, ymeas, P.d_part, s);
+    int nb = P.mix ? launch_mix_post(P, y, ymeas, P.d_part, s)
+                   : launch_forward_post(P, y, ymeas, P.d_part, s);
     if (res2_out) launch_reduce(P.d_part, nb, 1, res2_out, s);
 }
 
 int op_adjoint(Plan& P, const cf32* y, cf32* x, hipStream_t s, bool defer_sum) {
-    launch_adjoint_pre(P, y, s);
+    if (P.mix)
+        launch_mix_pre(P, y, s);
+    else
+        launch_adjoint_pre(P, y, s);
     if (P.algo == UFSS_ALGO_FFT) {
         fft_adj_transform(P, s);
         ktime_begin(P, 1, s);
@@ -458,6 +463,18 @@ int ufss_plan_create(const ufss_geom* g, int32_t m, int32_t per_position, const 
     if (!out) ufss::fail(UFSS_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     *out = reinterpret_cast<ufss_plan_t>(ufss::plan_create(g, m, per_position, bins));
+    UFSS_GUARD_END
+}
+
+int ufss_plan_create_mixed(const ufss_geom* g, int32_t m, int32_t per_position, const int32_t* bins,
+                           int32_t per_position_signs, const int8_t* signs, ufss_plan_t* out) {
+    UFSS_GUARD_BEGIN
+    if (!out) ufss::fail(UFSS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    ufss::MixSpec mix;
+    mix.per_sign = per_position_signs ? 1 : 0;
+    mix.signs = signs;
+    *out = reinterpret_cast<ufss_plan_t>(ufss::plan_create(g, m, per_position, bins, &mix));
     UFSS_GUARD_END
 }
 

@@ -622,6 +622,7 @@ size_t desc_size(GemmKind k) {
 
 int make_desc(GemmKind k, const Plan& P, const void* in, void* out, void* desc, size_t* lds) {
     if (P.d_amp) fail(UFSS_ERR_UNSUPPORTED, "grouped launches do not take a Gaussian beam");
+    if (P.mix) fail(UFSS_ERR_UNSUPPORTED, "grouped launches do not take mixed plans");
     switch (k) {
         case GemmKind::FwdF32:
             return fwd_args(P, static_cast<const cf32*>(in), *static_cast<FwdArgs*>(desc), *lds, kGroupNP);

@@ -42,6 +42,11 @@ struct Derived {
     std::vector<int> band;              // ascending band bins
 };
 Derived derive(const ufss_geom& g);
+// Random mixing of a plan: the Rademacher signs, one row or one per position.
+struct MixSpec {
+    int per_sign = 0;
+    const int8_t* signs = nullptr;   // [1 or npos][nt] of +-1
+};
 // Geometry and bin-subset checks of ufss_plan_create (throws INVALID_ARG).
 void validate_bins_public(const ufss_geom* g, int m, int per_position, const int32_t* bins);
 double pulse_spectrum(const ufss_geom& g, const Derived& d, int k);
@@ -79,6 +84,11 @@ struct Plan {
     float* d_hsel = nullptr;       // H_k per selection entry [m] or [npos*m]
     uint32_t* d_u = nullptr;       // integer-turn delay table [wy+1][wx+1][nz]
     float* d_amp = nullptr;        // Gaussian beam amplitude, same layout (theta > 0)
+    // random mixing (Rademacher signs): the union is every DFT index (signed
+    // bins), d_hsel holds H over the union and d_xih the transformed signs
+    // [1 or npos][nt]
+    int mix = 0, mix_per_sign = 0;
+    void* d_xih = nullptr;
     // transform path (UFSS_ALGO_FFT): sizes, K^ quadrant [ly/2+1][lx/2+1][nz][mu],
     // twiddle tables and three work buffers
     int fft_lx = 0, fft_ly = 0;
@@ -191,6 +201,11 @@ void fft_fwd_inverse(const Plan& P, hipStream_t s);
 void fft_adj_transform(const Plan& P, hipStream_t s);
 void fft_adj_contract(const Plan& P, hipStream_t s);
 void fft_adj_inverse(const Plan& P, cf32* out, hipStream_t s);
+
+// Random mixing passes (vec.hip): they replace launch_forward_post and
+// launch_adjoint_pre on mixed plans.
+int launch_mix_post(const Plan& P, cf32* y, const cf32* ymeas, double* part, hipStream_t s);
+void launch_mix_pre(const Plan& P, const cf32* r, hipStream_t s);
 
 // Backtracking FISTA: trial step p = soft(gamma - step g, thresh) with six
 // FP64 partials per block (see vec.hip); out = a + beta (a - b) with ||out||^2.

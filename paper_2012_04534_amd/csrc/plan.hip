@@ -248,7 +248,7 @@ static void free_plan(Plan* P) {
     void* ptrs[] = {P->d_bins, P->d_ubins, P->d_map, P->d_hsel, P->d_u, P->d_yraw,
                     P->d_rop, P->d_xop, P->d_part, P->d_scalars, P->d_r, P->d_g,
                     P->d_gamma, P->d_v, P->d_stats, P->d_gpart, P->d_ptab_f, P->d_ptab_a,
-                    P->d_bt, P->d_bt_scal, P->d_amp, P->d_khat, P->d_khat_t, P->d_tw_fx, P->d_tw_fy,
+                    P->d_bt, P->d_bt_scal, P->d_amp, P->d_xih, P->d_khat, P->d_khat_t, P->d_tw_fx, P->d_tw_fy,
                     P->d_tw_ix, P->d_tw_iy, P->d_fa, P->d_fb, P->d_ft};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -335,16 +335,72 @@ void sigma_estimate(const ufss_geom* g, int m, int per_position, const int32_t* 
     out->sigma_hat_central = std::sqrt(out->fro_sq_central) / q;
 }
 
-Plan* plan_create(const ufss_geom* g, int m, int per_position, const int32_t* bins) {
+// F xi / nt of one row of signs, FP64 radix-2 FFT (nt a power of two).
+static void signs_dft(const int8_t* xi, int nt, std::vector<double>& re, std::vector<double>& im) {
+    re.assign(nt, 0.0);
+    im.assign(nt, 0.0);
+    int bits = 0;
+    while ((1 << bits) < nt) ++bits;
+    for (int i = 0; i < nt; ++i) {
+        int r = 0;
+        for (int b = 0; b < bits; ++b)
+            if (i & (1 << b)) r |= 1 << (bits - 1 - b);
+        re[r] = xi[i];
+    }
+    for (int len = 2; len <= nt; len <<= 1) {
+        for (int i = 0; i < nt; i += len)
+            for (int j = 0; j < len / 2; ++j) {
+                const double a = -2.0 * M_PI * j / len;
+                const double wr = std::cos(a), wi = std::sin(a);
+                const int u = i + j, v = i + j + len / 2;
+                const double tr = re[v] * wr - im[v] * wi, ti = re[v] * wi + im[v] * wr;
+                re[v] = re[u] - tr;
+                im[v] = im[u] - ti;
+                re[u] += tr;
+                im[u] += ti;
+            }
+    }
+    for (int i = 0; i < nt; ++i) {
+        re[i] /= nt;
+        im[i] /= nt;
+    }
+}
+
+Plan* plan_create(const ufss_geom* g, int m, int per_position, const int32_t* bins,
+                  const MixSpec* mix) {
     validate_geom(g);
     if (!bins) fail(UFSS_ERR_INVALID_ARG, "bins is NULL");
     if (m < 1 || m > 4096) fail(UFSS_ERR_INVALID_ARG, "m must be in [1, 4096]");
     Derived d = derive(*g);
     const int npos = g->nx * g->ny;
     const int64_t nsel = per_position ? (int64_t)npos * m : m;
-    validate_bins(g, m, per_position, bins);
     int algo = g->algo;
     if (algo == UFSS_ALGO_AUTO) algo = UFSS_ALGO_GEMM;
+    if (mix) {
+        // bins anywhere in [0, nt), signs +-1; FP32 GEMM or transform core
+        if (!mix->signs) fail(UFSS_ERR_INVALID_ARG, "signs is NULL");
+        if (g->nt > 4096 || (g->nt & (g->nt - 1)))
+            fail(UFSS_ERR_UNSUPPORTED, "mixing needs nt a power of two, at most 4096");
+        if (g->dtype != UFSS_F32 || algo == UFSS_ALGO_PHASOR)
+            fail(UFSS_ERR_UNSUPPORTED, "mixing runs on the FP32 GEMM or transform path");
+        // the mixing passes stage a position's rows in LDS (64 KiB)
+        if (8 * (int64_t)g->nt + 12 * (int64_t)m > 65536)
+            fail(UFSS_ERR_UNSUPPORTED, "mixing: 8 nt + 12 m must not exceed 65536");
+        const int nrows = per_position ? npos : 1;
+        for (int r = 0; r < nrows; ++r)
+            for (int i = 0; i < m; ++i) {
+                const int32_t k = bins[(int64_t)r * m + i];
+                if (k < 0 || k >= g->nt) fail(UFSS_ERR_INVALID_ARG, "bin index outside [0, nt)");
+                if (i > 0 && k <= bins[(int64_t)r * m + i - 1])
+                    fail(UFSS_ERR_INVALID_ARG, "bins of a position must be strictly ascending");
+            }
+        const int64_t ns = (int64_t)(mix->per_sign ? npos : 1) * g->nt;
+        for (int64_t i = 0; i < ns; ++i)
+            if (mix->signs[i] != 1 && mix->signs[i] != -1)
+                fail(UFSS_ERR_INVALID_ARG, "signs must be +1 or -1");
+    } else {
+        validate_bins(g, m, per_position, bins);
+    }
     if (algo == UFSS_ALGO_PHASOR && g->dtype == UFSS_BF16)
         fail(UFSS_ERR_UNSUPPORTED, "the phasor path is FP32 only");
     if (algo == UFSS_ALGO_PHASOR && !per_position) algo = UFSS_ALGO_GEMM;
@@ -363,21 +419,30 @@ Plan* plan_create(const ufss_geom* g, int m, int per_position, const int32_t* bi
         P->npos = npos;
         P->nvox = (int64_t)npos * g->nz;
         P->bins_h.assign(bins, bins + nsel);
-        // union of bins (GEMM path over per-position subsets)
+        // union of bins (GEMM path over per-position subsets); a mixed plan runs
+        // over every DFT index as a signed bin: j (j <= nt/2) or j - nt
         std::vector<int> u(P->bins_h);
         std::sort(u.begin(), u.end());
         u.erase(std::unique(u.begin(), u.end()), u.end());
+        if (mix) {
+            u.resize(g->nt);
+            for (int j = 0; j < g->nt; ++j) u[j] = j <= g->nt / 2 ? j : j - g->nt;
+        }
         P->ubins_h = u;
         const int mu = (int)u.size();
         const int opw = (algo == UFSS_ALGO_PHASOR) ? m : mu;   // operand row width
-        std::vector<int> map(nsel);
-        std::vector<float> hsel(nsel);
-        for (int64_t i = 0; i < nsel; ++i) {
-            int k = P->bins_h[i];
-            map[i] = (algo == UFSS_ALGO_PHASOR)
-                         ? (int)(i % m)
-                         : (int)(std::lower_bound(u.begin(), u.end(), k) - u.begin());
-            hsel[i] = (float)pulse_spectrum(*g, d, k);
+        std::vector<int> map(mix ? 1 : nsel, 0);
+        std::vector<float> hsel(mix ? mu : nsel);
+        if (mix) {
+            for (int j = 0; j < mu; ++j) hsel[j] = (float)pulse_spectrum(*g, d, u[j]);
+        } else {
+            for (int64_t i = 0; i < nsel; ++i) {
+                int k = P->bins_h[i];
+                map[i] = (algo == UFSS_ALGO_PHASOR)
+                             ? (int)(i % m)
+                             : (int)(std::lower_bound(u.begin(), u.end(), k) - u.begin());
+                hsel[i] = (float)pulse_spectrum(*g, d, k);
+            }
         }
         // integer-turn delay table: u(|dx|, |dy|, z) = round(2^32 frac((tau - t0) fs / nt))
         const int wx = d.wx, wy = d.wy;
@@ -396,10 +461,24 @@ Plan* plan_create(const ufss_geom* g, int m, int per_position, const int32_t* bi
         upload(P->d_bins, P->bins_h.data(), nsel);
         P->d_ubins = dalloc<int>(*P, mu);
         upload(P->d_ubins, u.data(), mu);
-        P->d_map = dalloc<int>(*P, nsel);
-        upload(P->d_map, map.data(), nsel);
-        P->d_hsel = dalloc<float>(*P, nsel);
-        upload(P->d_hsel, hsel.data(), nsel);
+        P->d_map = dalloc<int>(*P, map.size());
+        upload(P->d_map, map.data(), map.size());
+        P->d_hsel = dalloc<float>(*P, hsel.size());
+        upload(P->d_hsel, hsel.data(), hsel.size());
+        if (mix) {
+            const int nrow = mix->per_sign ? npos : 1;
+            std::vector<cf32> xh((size_t)nrow * g->nt);
+            std::vector<double> re, im;
+            for (int r = 0; r < nrow; ++r) {
+                signs_dft(mix->signs + (int64_t)r * g->nt, g->nt, re, im);
+                for (int j = 0; j < g->nt; ++j)
+                    xh[(size_t)r * g->nt + j] = cf32{(float)re[j], (float)im[j]};
+            }
+            P->d_xih = dalloc<cf32>(*P, xh.size());
+            upload(static_cast<cf32*>(P->d_xih), xh.data(), xh.size());
+            P->mix = 1;
+            P->mix_per_sign = mix->per_sign ? 1 : 0;
+        }
         P->d_u = dalloc<uint32_t>(*P, ut.size());
         upload(P->d_u, ut.data(), ut.size());
         if (g->theta > 0) {

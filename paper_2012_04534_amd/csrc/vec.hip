@@ -5,6 +5,8 @@
 // walks the data in a fixed order, each block writes FP64 partials to its own
 // slot, and a single-block kernel sums the slots in a fixed order.  No float
 // atomics anywhere, so results are bitwise reproducible run to run.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace ufss {
@@ -207,6 +209,113 @@ int launch_update(int64_t n, cf32* gamma, const cf32* g, int nsplit, cf32* a, fl
                        thresh, beta, aref, part);
     UFSS_HIP(hipGetLastError());
     return nb;
+}
+
+// ---------------------------------------------------------------------------
+// Random mixing (Rademacher Sigma, Sec. III-A).  The plan's union holds every
+// DFT index j of the A-scan spectrum B (signed bins), so y_raw[p][j] is B_p[j] / H_j.
+//   post:  y[p][m] = sum_j xih[(k_m - j) mod nt] H_j y_raw[p][j]  (- ymeas)
+//   pre:   rop[p][j] = H_j sum_m conj(xih[(k_m - j) mod nt]) r[p][m]
+// with xih = F xi / nt the transformed signs of the position's row (nt is a
+// power of two).  One workgroup per position at a time stages its rows in LDS.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void mix_post_kernel(
+    const cf32* __restrict__ yraw, int split, int64_t npos, int nt, int m, int per_bins,
+    const int* __restrict__ bins, const float* __restrict__ hu, const cf32* __restrict__ xih,
+    int per_sign, const cf32* __restrict__ ymeas, cf32* __restrict__ y, double* __restrict__ part) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cf32* v = reinterpret_cast<cf32*>(smem);       // [nt] H_j y_raw[p][j]
+    cf32* xr = v + nt;                             // [nt] transformed signs
+    double acc[1] = {0.0};
+    const int mask = nt - 1;
+    for (int64_t p = blockIdx.x; p < npos; p += gridDim.x) {
+        __syncthreads();
+        const cf32* xs = xih + (per_sign ? p * nt : 0);
+        for (int j = threadIdx.x; j < nt; j += kThreads) {
+            float re = 0.f, im = 0.f;
+            for (int sp = 0; sp < split; ++sp) {
+                const cf32 q = yraw[((int64_t)sp * npos + p) * nt + j];
+                re += q.re;
+                im += q.im;
+            }
+            const float h = hu[j];
+            v[j] = cf32{h * re, h * im};
+            xr[j] = xs[j];
+        }
+        __syncthreads();
+        const int* kb = bins + (per_bins ? p * m : 0);
+        for (int mi = threadIdx.x; mi < m; mi += kThreads) {
+            const int k = kb[mi];
+            float re = 0.f, im = 0.f;
+            for (int j = 0; j < nt; ++j) {
+                const cf32 a = xr[(k - j) & mask], b = v[j];
+                re += a.re * b.re - a.im * b.im;
+                im += a.re * b.im + a.im * b.re;
+            }
+            const int64_t o = p * m + mi;
+            if (ymeas) {
+                re -= ymeas[o].re;
+                im -= ymeas[o].im;
+            }
+            y[o] = cf32{re, im};
+            acc[0] += (double)re * re + (double)im * im;
+        }
+    }
+    block_sum_write<1>(acc, part);
+}
+
+int launch_mix_post(const Plan& P, cf32* y, const cf32* ymeas, double* part, hipStream_t s) {
+    const int nb = (int)std::min<int64_t>(P.npos, kMaxBlocks);
+    const int nt = P.g.nt;
+    hipLaunchKernelGGL(mix_post_kernel, dim3(nb), dim3(kThreads), (size_t)2 * nt * sizeof(cf32), s,
+                       P.d_yraw, P.fwd_split * std::max(1, P.fwd_zsplit), (int64_t)P.npos, nt, P.m,
+                       P.per_position, P.d_bins, P.d_hsel, static_cast<const cf32*>(P.d_xih),
+                       P.mix_per_sign, ymeas, y, part);
+    UFSS_HIP(hipGetLastError());
+    return nb;
+}
+
+__global__ __launch_bounds__(kThreads) void mix_pre_kernel(
+    const cf32* __restrict__ r, int64_t npos, int nt, int m, int per_bins,
+    const int* __restrict__ bins, const float* __restrict__ hu, const cf32* __restrict__ xih,
+    int per_sign, cf32* __restrict__ rop) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cf32* xr = reinterpret_cast<cf32*>(smem);      // [nt]
+    cf32* rr = xr + nt;                            // [m]
+    int* kk = reinterpret_cast<int*>(rr + m);      // [m]
+    const int mask = nt - 1;
+    for (int64_t p = blockIdx.x; p < npos; p += gridDim.x) {
+        __syncthreads();
+        const cf32* xs = xih + (per_sign ? p * nt : 0);
+        for (int j = threadIdx.x; j < nt; j += kThreads) xr[j] = xs[j];
+        const int* kb = bins + (per_bins ? p * m : 0);
+        for (int mi = threadIdx.x; mi < m; mi += kThreads) {
+            rr[mi] = r[p * m + mi];
+            kk[mi] = kb[mi];
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < nt; j += kThreads) {
+            float re = 0.f, im = 0.f;
+            for (int mi = 0; mi < m; ++mi) {
+                const cf32 a = xr[(kk[mi] - j) & mask], b = rr[mi];
+                // conj(a) * b
+                re += a.re * b.re + a.im * b.im;
+                im += a.re * b.im - a.im * b.re;
+            }
+            const float h = hu[j];
+            rop[p * nt + j] = cf32{h * re, h * im};
+        }
+    }
+}
+
+void launch_mix_pre(const Plan& P, const cf32* r, hipStream_t s) {
+    const int nb = (int)std::min<int64_t>(P.npos, kMaxBlocks);
+    const int nt = P.g.nt;
+    hipLaunchKernelGGL(mix_pre_kernel, dim3(nb), dim3(kThreads),
+                       (size_t)nt * sizeof(cf32) + (size_t)P.m * (sizeof(cf32) + sizeof(int)), s, r,
+                       (int64_t)P.npos, nt, P.m, P.per_position, P.d_bins, P.d_hsel,
+                       static_cast<const cf32*>(P.d_xih), P.mix_per_sign, static_cast<cf32*>(P.d_rop));
+    UFSS_HIP(hipGetLastError());
 }
 
 // ---------------------------------------------------------------------------

@@ -26,7 +26,7 @@ SAMPLE_RND, SAMPLE_RND_F, SAMPLE_MAX, SAMPLE_NRG, SAMPLE_NRG_F = 0, 1, 2, 3, 4
 
 EXPORTED = [
     "ufss_last_error", "ufss_select_freqs", "ufss_sample_bins", "ufss_sigma_estimate", "ufss_crb",
-    "ufss_plan_create", "ufss_plan_destroy",
+    "ufss_plan_create", "ufss_plan_create_mixed", "ufss_plan_destroy",
     "ufss_plan_info_get", "ufss_forward", "ufss_adjoint", "ufss_lipschitz", "ufss_fista",
     "ufss_fista_backtracking",
     "ufss_shrink_update", "ufss_absmax", "ufss_time_kernel", "ufss_fista_batched",
@@ -114,6 +114,7 @@ def lib():
                                      ctypes.POINTER(SigmaEst)], ctypes.c_int),
             "ufss_crb": ([ctypes.POINTER(Geom), I32, I32, I32, P, ctypes.POINTER(CrbPoint), P, P,
                           P], ctypes.c_int),
+            "ufss_plan_create_mixed": ([ctypes.POINTER(Geom), I32, I32, P, I32, P, P], ctypes.c_int),
             "ufss_plan_create": ([ctypes.POINTER(Geom), I32, I32, P, ctypes.POINTER(P)], ctypes.c_int),
             "ufss_plan_destroy": ([P], ctypes.c_int),
             "ufss_plan_info_get": ([P, ctypes.POINTER(PlanInfo)], ctypes.c_int),
@@ -264,9 +265,12 @@ def ufss_crb(g, m, per_position, bins, point, stream=None):
 
 
 class Plan:
-    """Owning handle of a ufss plan (ufss_plan_create / ufss_plan_destroy)."""
+    """Owning handle of a ufss plan (ufss_plan_create / ufss_plan_destroy).
 
-    def __init__(self, g, m, per_position, bins, dtype=F32, algo=ALGO_AUTO):
+    ``signs`` (int8 +-1, [nt] or [ny, nx, nt]) makes a randomly mixed plan
+    (ufss_plan_create_mixed); its bins may then lie anywhere in [0, nt)."""
+
+    def __init__(self, g, m, per_position, bins, dtype=F32, algo=ALGO_AUTO, signs=None):
         self.g = dict(g)
         self.m = int(m)
         self.per_position = bool(per_position)
@@ -276,8 +280,17 @@ class Plan:
         if b.size != want:
             raise ValueError("bins has %d entries, expected %d" % (b.size, want))
         h = ctypes.c_void_p()
-        _check(lib().ufss_plan_create(ctypes.byref(geom), self.m, int(self.per_position),
-                                      b.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)))
+        if signs is None:
+            _check(lib().ufss_plan_create(ctypes.byref(geom), self.m, int(self.per_position),
+                                          b.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)))
+        else:
+            sg = np.ascontiguousarray(signs, dtype=np.int8)
+            per_s = sg.ndim == 3
+            if sg.size != (g["nx"] * g["ny"] if per_s else 1) * g["nt"]:
+                raise ValueError("signs must be [nt] or [ny, nx, nt]")
+            _check(lib().ufss_plan_create_mixed(ctypes.byref(geom), self.m, int(self.per_position),
+                                                b.ctypes.data_as(ctypes.c_void_p), int(per_s),
+                                                sg.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)))
         self.handle = h
         self.nvox = g["nx"] * g["ny"] * g["nz"]
         self.nmeas = g["nx"] * g["ny"] * m
