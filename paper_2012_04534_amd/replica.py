@@ -3,7 +3,8 @@
 The 50 x 50 x 50 specimen of Table III (line and tilted-rectangle defects of
 amplitude exp(j pi/4), noise free) is measured with n_f in {1, 2, 5, 10}
 coefficients per A-scan under each sampling strategy of Sec. III-A (random
-with Sigma = I, maximal, energy-based; shared or per position) and recovered
+with Sigma = I or with Rademacher mixing, maximal, energy-based; shared or per
+position) and recovered
 with FISTA (80 iterations, lambda = mu ||A^H y||_inf, L by power iteration).
 
 Reported per run (one JSON line each):
@@ -40,7 +41,11 @@ STRATEGIES = {
     "rnd": ufss.SAMPLE_RND, "max": ufss.SAMPLE_MAX, "nrg": ufss.SAMPLE_NRG,
     "rnd_f": ufss.SAMPLE_RND_F, "nrg_f": ufss.SAMPLE_NRG_F,
 }
-ALGO_NAMES = {ufss.ALGO_GEMM: "gemm", ufss.ALGO_PHASOR: "phasor"}
+# random mixing (Rademacher signs before the DFT; uniform subsets of all N_t
+# coefficients): one sign row for all positions, one per position, and per
+# position signs and subsets (Table I Phi_rnd, Phi_rnd,m, Phi_rnd,m,f)
+MIXED = {"rnd_mix": (False, False), "rnd_m": (True, False), "rnd_mf": (True, True)}
+ALGO_NAMES = {ufss.ALGO_GEMM: "gemm", ufss.ALGO_PHASOR: "phasor", ufss.ALGO_FFT: "transform"}
 
 
 def depth_metrics(xhat, xtrue):
@@ -57,9 +62,17 @@ def depth_metrics(xhat, xtrue):
 
 
 def run(g, scene_name, xtrue, strategy, nf, mu, iters, seed, dev, algo=ufss.ALGO_AUTO):
-    bins, per = ufss.ufss_sample_bins(g, nf, STRATEGIES[strategy], seed)
+    signs = None
+    if strategy in MIXED:
+        per_sign, per = MIXED[strategy]
+        lead = (g["ny"], g["nx"])
+        bins = W.uniform_subsets(g["nt"], nf, lead if per else (), seed)
+        signs = W.rademacher(lead + (g["nt"],) if per_sign else (g["nt"],), seed + 1)
+        algo = ufss.ALGO_FFT             # the core runs over all N_t bins: the transform path
+    else:
+        bins, per = ufss.ufss_sample_bins(g, nf, STRATEGIES[strategy], seed)
     t0 = time.perf_counter()
-    plan = ufss.Plan(g, nf, per, bins, algo=algo)
+    plan = ufss.Plan(g, nf, per, bins, algo=algo, signs=signs)
     info = plan.info()
     xt = torch.from_numpy(xtrue.astype(np.complex64)).to(dev)
     y = torch.empty((g["ny"], g["nx"], nf), dtype=torch.complex64, device=dev)
@@ -163,7 +176,7 @@ def main(argv=None):
     for sname, xtrue in scenes.items():
         for mu in mus:
             for nf in nfs:
-                for strat in STRATEGIES:
+                for strat in list(STRATEGIES) + list(MIXED):
                     r = run(g, sname, xtrue, strat, nf, mu, W.SIM_ITERS, args.seed, dev)
                     print(json.dumps(dict(kind="recon", **r)), flush=True)
 
