@@ -51,12 +51,15 @@ def momentum_weights(iters, t1=1.0):
     return t, beta
 
 
-def fista(A, AH, y, lam, L, iters, a0=None, accel=True, a_ref=None, state=None):
+def fista(A, AH, y, lam, L, iters, a0=None, accel=True, a_ref=None, state=None, real=False):
     """Run ``iters`` FISTA (or ISTA) iterations in complex128.
 
     A, AH    callables for x -> A x and y -> A^H y
     a0       start value (zeros if None)
     state    optional dict {"a", "gamma", "t", "k"} to resume; updated on return
+    real     reconstruct a real reflectivity (the Re{H} comparison of Sec. VII):
+             the gradient with respect to a real a is Re(A^H r), so the step
+             keeps the real part before the threshold and every iterate is real
     Returns (a_K, stats) where stats holds, per iteration k, the objective at
     gamma_k, ||A gamma_k - y||, ||a_k - a_{k-1}|| / ||a_k|| and, if a_ref is
     given, ||a_k - a_ref|| / ||a_ref||.
@@ -79,7 +82,8 @@ def fista(A, AH, y, lam, L, iters, a0=None, accel=True, a_ref=None, state=None):
         res = float(np.linalg.norm(r))
         stats["obj"].append(0.5 * res * res + lam * float(np.abs(gamma).sum()))
         grad = AH(r)
-        a_new = soft(gamma - grad / L, lam / L)
+        z = gamma - grad / L
+        a_new = soft(z.real if real else z, lam / L).astype(np.complex128)
         t_new = (1.0 + math.sqrt(1.0 + 4.0 * t * t)) / 2.0
         if accel:
             gamma = a_new + ((t - 1.0) / t_new) * (a_new - a)

@@ -203,3 +203,43 @@ def test_backtracking_bound_from_low_start():
     for k in (1, 5, 20, 100, 200):
         gap = st["obj"][k - 1] - F_star
         assert gap <= bound_c / (k + 1) ** 2 + 1e-12 * F_star
+
+
+def test_real_iterates_kkt_and_real_operator():
+    """Real-reflectivity FISTA (the Re{H} comparison): at convergence the KKT
+    conditions of min 1/2||A a - y||^2 + lam ||a||_1 over real a hold with the
+    real gradient Re(A^H r); and for a real operator and real data the real
+    and complex iterations coincide."""
+    _, _, Amat, A, AH, _, y = problem(nx=10, nz=24, m=10, n_scat=2, snr_db=40.0)
+    L = V.lipschitz_dense(Amat)
+    lam = V.lambda_rule(AH, y, 0.3)
+    a, _ = V.fista(A, AH, y, lam, L, 20000, real=True)
+    assert np.all(a.imag == 0)
+    c = np.real(AH(y - A(a)))
+    on = np.abs(a) > 0
+    assert on.any()
+    np.testing.assert_allclose(c[on], lam * np.sign(a[on].real), rtol=0, atol=1e-5 * lam)
+    assert np.all(np.abs(c[~on]) <= lam * (1 + 1e-5))
+    R = np.real(Amat)
+    yr = np.real(y)
+    Ar = lambda v: R @ v
+    ARh = lambda v: R.T @ v
+    Lr = V.lipschitz_dense(R)
+    a1, _ = V.fista(Ar, ARh, yr, 0.1, Lr, 50, real=True)
+    a2, _ = V.fista(Ar, ARh, yr, 0.1, Lr, 50)
+    np.testing.assert_allclose(a1, a2, rtol=0, atol=1e-12 * np.abs(a2).max())
+
+
+def test_mirrored_coefficients_equal_real_constraint():
+    """Adding each measured coefficient's mirror conj(y_k) at -k (rows conj(A))
+    gives, for real a, the operator [A; conj A] with gradient 2 Re(A^H r):
+    real FISTA on it with 2L equals real FISTA on A with L."""
+    _, _, Amat, A, AH, _, y = problem(nx=8, nz=20, m=6, n_scat=2, snr_db=30.0)
+    M = np.concatenate([Amat, Amat.conj()], axis=0)
+    ym = np.concatenate([y, y.conj()])
+    L = V.lipschitz_dense(Amat)
+    Lm = V.lipschitz_dense(M)
+    assert Lm <= 2 * L * (1 + 1e-12)
+    a1, _ = V.fista(A, AH, y, 0.2, L, 80, real=True)
+    a2, _ = V.fista(lambda v: M @ v, lambda v: M.conj().T @ v, ym, 0.4, 2 * L, 80, real=True)
+    np.testing.assert_allclose(a1, a2, rtol=0, atol=1e-10 * np.abs(a1).max())
