@@ -298,6 +298,10 @@ int ufss_lipschitz(ufss_plan_t plan, int32_t max_iters, double rtol,
  *   iters   number of iterations (>= 0)
  *   tol     > 0: stop early once ||a_k - a_{k-1}|| <= tol ||a_k|| (checked every
  *           8 iterations); 0: run exactly `iters`
+ *   accel   bit 0: 1 = FISTA momentum, 0 = ISTA; bit 1: real reflectivity (the
+ *           Re{H} comparison of Sec. VII: the gradient step keeps its real part
+ *           before the threshold, so every iterate is real; the imaginary part
+ *           of a_0 is dropped by the first step); other bits: INVALID_ARG
  *   x       DEVICE complex64 [ny][nx][nz]: in = a_0 (ignored when resuming), out = a_K
  *   a_ref   DEVICE complex64 [ny][nx][nz] or NULL (enables stats->err_ref)
  *   stats   HOST or NULL; state HOST or NULL (see the struct comments)

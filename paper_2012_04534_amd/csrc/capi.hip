@@ -195,10 +195,12 @@ static double absmax_dev(int64_t n, const cf32* x, double* part, double* out, hi
     return read_scalar(out, s);
 }
 
-int fista(Plan& P, const cf32* y, double lambda, double L, int iters, double tol, int accel,
+int fista(Plan& P, const cf32* y, double lambda, double L, int iters, double tol, int flags,
           cf32* x, const cf32* aref, ufss_fista_stats* stats, ufss_fista_state* state,
           hipStream_t s) {
     if (!y || !x) fail(UFSS_ERR_INVALID_ARG, "y and x must be device pointers");
+    if (flags & ~3) fail(UFSS_ERR_INVALID_ARG, "unknown FISTA flag bits");
+    const int accel = flags & 1, real = (flags >> 1) & 1;
     if (iters < 0) fail(UFSS_ERR_INVALID_ARG, "iters must be >= 0");
     if (!(tol >= 0)) fail(UFSS_ERR_INVALID_ARG, "tol must be >= 0");
     if (!(L > 0)) L = P.lipschitz;
@@ -247,7 +249,7 @@ int fista(Plan& P, const cf32* y, double lambda, double L, int iters, double tol
         const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * tk * tk));
         const double beta = accel ? (tk - 1.0) / tn : 0.0;
         int nb = launch_update(P.nvox, gamma, ns > 1 ? P.d_gpart : P.d_g, ns, x, step, thresh,
-                               (float)beta, aref, P.d_part, s);
+                               (float)beta, aref, P.d_part, s, real);
         launch_reduce(P.d_part, nb, 5, P.d_scalars + 8, s);
         launch_fista_stats(P.d_stats, k, P.d_scalars + 8, P.d_scalars + 0, g1, lambda,
                            aref ? 1 : 0, ref2, s);

@@ -180,7 +180,7 @@ void launch_sum_parts(const cf32* part, int nsplit, int64_t n, cf32* out, hipStr
 // Vector kernels.
 // g: the gradient [n], or with nsplit > 1 the adjoint's split partials [nsplit][n].
 int launch_update(int64_t n, cf32* gamma, const cf32* g, int nsplit, cf32* a, float step,
-                  float thresh, float beta, const cf32* aref, double* part, hipStream_t s);
+                  float thresh, float beta, const cf32* aref, double* part, hipStream_t s, int real = 0);
 // Sums nblk partial blocks of `width` doubles in fixed order into out[width].
 void launch_reduce(const double* part, int nblk, int width, double* out, hipStream_t s);
 int launch_absmax(int64_t n, const cf32* x, double* part, hipStream_t s);

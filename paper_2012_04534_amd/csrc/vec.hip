@@ -164,7 +164,7 @@ void launch_to_bf16(const cf32* x, void* out, int64_t n, hipStream_t s) {
 __global__ __launch_bounds__(kThreads) void update_kernel(int64_t n, cf32* __restrict__ gamma,
                                                           const cf32* __restrict__ g, int nsplit,
                                                           cf32* __restrict__ a, float step,
-                                                          float thresh, float beta,
+                                                          float thresh, float beta, int real,
                                                           const cf32* __restrict__ aref,
                                                           double* __restrict__ part) {
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -181,7 +181,8 @@ __global__ __launch_bounds__(kThreads) void update_kernel(int64_t n, cf32* __res
             }
             gg = cf32{re, im};
         }
-        float zr = gm.re - step * gg.re, zi = gm.im - step * gg.im;
+        // real: the reflectivity is real, the gradient step keeps Re (Re{H} model)
+        float zr = gm.re - step * gg.re, zi = real ? 0.f : gm.im - step * gg.im;
         float mag = sqrtf(zr * zr + zi * zi);
         float sc = mag > thresh ? 1.0f - thresh / mag : 0.0f;
         float ar = zr * sc, ai = zi * sc;
@@ -203,10 +204,10 @@ __global__ __launch_bounds__(kThreads) void update_kernel(int64_t n, cf32* __res
 }
 
 int launch_update(int64_t n, cf32* gamma, const cf32* g, int nsplit, cf32* a, float step,
-                  float thresh, float beta, const cf32* aref, double* part, hipStream_t s) {
+                  float thresh, float beta, const cf32* aref, double* part, hipStream_t s, int real) {
     const int nb = blocks_for(n);
     hipLaunchKernelGGL(update_kernel, dim3(nb), dim3(kThreads), 0, s, n, gamma, g, nsplit, a, step,
-                       thresh, beta, aref, part);
+                       thresh, beta, real, aref, part);
     UFSS_HIP(hipGetLastError());
     return nb;
 }

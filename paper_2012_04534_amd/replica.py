@@ -45,6 +45,9 @@ STRATEGIES = {
 # coefficients): one sign row for all positions, one per position, and per
 # position signs and subsets (Table I Phi_rnd, Phi_rnd,m, Phi_rnd,m,f)
 MIXED = {"rnd_mix": (False, False), "rnd_m": (True, False), "rnd_mf": (True, True)}
+# the Re{H} comparison of Sec. VII: the same measurements recovered as a real
+# reflectivity (its "mirrored" variant is the same problem for a real unknown)
+REAL = {"max_re": "max", "rnd_f_re": "rnd_f"}
 ALGO_NAMES = {ufss.ALGO_GEMM: "gemm", ufss.ALGO_PHASOR: "phasor", ufss.ALGO_FFT: "transform"}
 
 
@@ -63,14 +66,16 @@ def depth_metrics(xhat, xtrue):
 
 def run(g, scene_name, xtrue, strategy, nf, mu, iters, seed, dev, algo=ufss.ALGO_AUTO):
     signs = None
-    if strategy in MIXED:
-        per_sign, per = MIXED[strategy]
+    real = strategy in REAL
+    base = REAL.get(strategy, strategy)
+    if base in MIXED:
+        per_sign, per = MIXED[base]
         lead = (g["ny"], g["nx"])
         bins = W.uniform_subsets(g["nt"], nf, lead if per else (), seed)
         signs = W.rademacher(lead + (g["nt"],) if per_sign else (g["nt"],), seed + 1)
         algo = ufss.ALGO_FFT             # the core runs over all N_t bins: the transform path
     else:
-        bins, per = ufss.ufss_sample_bins(g, nf, STRATEGIES[strategy], seed)
+        bins, per = ufss.ufss_sample_bins(g, nf, STRATEGIES[base], seed)
     t0 = time.perf_counter()
     plan = ufss.Plan(g, nf, per, bins, algo=algo, signs=signs)
     info = plan.info()
@@ -82,7 +87,7 @@ def run(g, scene_name, xtrue, strategy, nf, mu, iters, seed, dev, algo=ufss.ALGO
     x = torch.zeros_like(xt)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    st = ufss.ufss_fista(plan, y, ufss.lambda_from_mu(mu), L, iters, x)
+    st = ufss.ufss_fista(plan, y, ufss.lambda_from_mu(mu), L, iters, x, real=real)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t1) * 1e3 / iters
     xh = x.cpu().numpy().astype(np.complex128)
@@ -176,7 +181,7 @@ def main(argv=None):
     for sname, xtrue in scenes.items():
         for mu in mus:
             for nf in nfs:
-                for strat in list(STRATEGIES) + list(MIXED):
+                for strat in list(STRATEGIES) + list(MIXED) + list(REAL):
                     r = run(g, sname, xtrue, strat, nf, mu, W.SIM_ITERS, args.seed, dev)
                     print(json.dumps(dict(kind="recon", **r)), flush=True)
 

@@ -332,7 +332,7 @@ def ufss_lipschitz(plan, max_iters=200, rtol=1e-6, margin=0.01, seed=4, stream=N
 
 
 def ufss_fista(plan, y, lam, L, iters, x, tol=0.0, accel=True, a_ref=None, state=None,
-               stream=None):
+               stream=None, real=False):
     """Run FISTA/ISTA; returns a dict of per-iteration FP64 statistics.
 
     ``state`` may be a dict {"gamma": tensor, "k_done": int}; it is updated.
@@ -349,7 +349,7 @@ def ufss_fista(plan, y, lam, L, iters, x, tol=0.0, accel=True, a_ref=None, state
         _numel_check(state["gamma"], plan.nvox, "state gamma")
         cst = FistaState(_ptr(state["gamma"], "gamma"), int(state.get("k_done", 0)))
     code = lib().ufss_fista(plan.handle, _ptr(y, "y"), float(lam), float(L), int(iters),
-                            float(tol), int(bool(accel)), _ptr(x, "x"),
+                            float(tol), int(bool(accel)) | (2 if real else 0), _ptr(x, "x"),
                             _ptr(a_ref, "a_ref") if a_ref is not None else None,
                             ctypes.byref(st), ctypes.byref(cst) if cst is not None else None,
                             _stream(stream))

@@ -360,3 +360,27 @@ def test_sigma_hat_as_lipschitz_bscan(dev):
     gap = (sa["obj"][-1] - sb["obj"][-1]) / sb["obj"][-1]
     assert abs(gap) < 2e-3, gap
     plan.close()
+
+
+def test_fista_real_iterates_match_oracle(dev):
+    """Real-reflectivity FISTA (accel bit 1, the Re{H} comparison) on the
+    B-scan workload: iterates real and equal to the oracle's; unknown flag
+    bits are refused."""
+    u = ufss()
+    w, g, bins, A, x_true, y = bscan_problem()
+    yd = y.reshape(-1).astype(np.complex128)
+    L = V.lipschitz_dense(A) * 1.01
+    lam = V.lambda_rule(lambda v: A.conj().T @ v, yd, w["mu"])
+    a_ref, _ = V.fista(lambda v: A @ v, lambda v: A.conj().T @ v, yd, lam, L, 100, real=True)
+    plan = u.Plan(g, w["m"], False, bins)
+    x = torch.zeros((g["ny"], g["nx"], g["nz"]), dtype=torch.complex64, device=dev)
+    yt = to_dev(y.reshape(g["ny"], g["nx"], w["m"]), dev)
+    u.ufss_fista(plan, yt, lam, L, 100, x, real=True)
+    a = x.cpu().numpy().reshape(-1)
+    assert np.all(a.imag == 0)
+    assert np.linalg.norm(a - a_ref) / np.linalg.norm(a_ref) < 1e-5
+    with pytest.raises(u.UfssError) as e:
+        u._check(u.lib().ufss_fista(plan.handle, u._ptr(yt, "y"), lam, L, 2, 0.0, 4,
+                                    u._ptr(x, "x"), None, None, None, u._stream(None)))
+    assert e.value.name == "INVALID_ARG"
+    plan.close()
