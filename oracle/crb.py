@@ -96,3 +96,23 @@ def crb_position(J):
     Q = Jn - Jpn.T @ Jp_inv @ Jpn
     C = Jp_inv + Jp_inv @ Jpn @ np.linalg.inv(Q) @ Jpn.T @ Jp_inv
     return np.diag(C).copy()
+
+
+def fisher_mixed(g, bins, signs, u, sigma2):
+    """FIM of mixed measurements (Rademacher Sigma, Sec. III-A): position i
+    measures M_i B_i with M_i the rows of S_i F Sigma_i F^{-1} over every DFT
+    index (signed bins), so the derivative rows are M_i D_i with D_i over all
+    N_t signed bins; J = (2 / sigma^2) Re{sum_i (M_i D_i)^H (M_i D_i)}."""
+    from . import mixing as X
+    nt = g["nt"]
+    full = X.signed_bins(nt)
+    D = derivatives(g, full, u)                      # [npos * nt, 5], position-major
+    J = np.zeros((5, 5))
+    for iy in range(g["ny"]):
+        for ix in range(g["nx"]):
+            p = iy * g["nx"] + ix
+            k = bins if np.ndim(bins) == 1 else bins[iy, ix]
+            xi = signs if np.ndim(signs) == 1 else signs[iy, ix]
+            MD = X.mixing_rows(g, k, xi) @ D[p * nt:(p + 1) * nt]
+            J += np.real(MD.conj().T @ MD)
+    return (2.0 / sigma2) * J

@@ -88,3 +88,39 @@ def test_window_drops_far_positions():
         for ix in range(g["nx"]):
             far = abs(U[0] - ix * g["dx"]) > g["dx"] or abs(U[1] - iy * g["dy"]) > g["dy"]
             assert (np.abs(b[iy * g["nx"] + ix]).max() == 0) == far
+
+
+def test_mixed_fim_reductions():
+    """Mixed measurements: all signs +1 reduce to bin selection; every
+    coefficient selected gives the full-band information (F Sigma F^-1 is
+    unitary); the mixed model's derivatives match finite differences."""
+    from oracle import mixing as X
+    g = small()
+    nt = g["nt"]
+    bins = S.select_freqs(g, 5, True, 9)
+    J1 = K.fisher_mixed(g, bins, np.ones(nt), U, 0.2)
+    J0 = K.fisher(g, bins, U, 0.2)
+    np.testing.assert_allclose(J1, J0, rtol=0, atol=1e-10 * np.abs(J0).max())
+    signs = W.rademacher((g["ny"], g["nx"], nt), 3)
+    Jm = K.fisher_mixed(g, np.arange(nt), signs, U, 0.2)
+    Jf = K.fisher(g, X.signed_bins(nt), U, 0.2)
+    np.testing.assert_allclose(Jm, Jf, rtol=0, atol=1e-9 * np.abs(Jf).max())
+    # derivatives of the mixed model by central differences
+    sub = W.uniform_subsets(nt, 4, (g["ny"], g["nx"]), 4)
+    def ymix(uu):
+        b = K.model(g, X.signed_bins(nt), uu)
+        return np.concatenate([X.mixing_rows(g, sub[iy, ix], signs[iy, ix]) @ b[iy * g["nx"] + ix]
+                               for iy in range(g["ny"]) for ix in range(g["nx"])])
+    D = K.derivatives(g, X.signed_bins(nt), U)
+    MD = np.concatenate([X.mixing_rows(g, sub[iy, ix], signs[iy, ix]) @
+                         D[(iy * g["nx"] + ix) * nt:(iy * g["nx"] + ix + 1) * nt]
+                         for iy in range(g["ny"]) for ix in range(g["nx"])])
+    for j, h in enumerate((1e-7, 1e-7, 1e-7, 1e-6, 1e-6)):
+        up, dn = list(U), list(U)
+        up[j] += h
+        dn[j] -= h
+        fd = (ymix(up) - ymix(dn)) / (2 * h)
+        np.testing.assert_allclose(MD[:, j], fd, rtol=0, atol=2e-6 * np.abs(MD[:, j]).max())
+    Jd = (2 / 0.2) * np.real(MD.conj().T @ MD)
+    np.testing.assert_allclose(K.fisher_mixed(g, sub, signs, U, 0.2), Jd, rtol=0,
+                               atol=1e-10 * np.abs(Jd).max())
