@@ -225,6 +225,23 @@ int ufss_crb(const ufss_geom* g, int32_t m, int32_t per_position, int32_t trials
              const int32_t* bins, const ufss_crb_point* pt, double* fim_out, double* crb_out,
              ufss_stream_t stream);
 
+/* The same bound for randomly mixed measurements (Rademacher Sigma, as
+ * ufss_plan_create_mixed): position i measures M_i B_i with M_i the rows
+ * xih_i[(k_m - j) mod nt] over every DFT index j of the spectrum B_i, so the
+ * derivative rows are M_i D_i over all nt signed bins and
+ * J = (2 / sigma^2) Re{sum_i (M_i D_i)^H (M_i D_i)}.  FP64 on the device: the
+ * rows D_i once per call, the transformed signs of every trial, then one
+ * workgroup per trial.
+ *   bins   HOST int32 [trials][m] or [trials][ny][nx][m], in [0, nt), ascending
+ *   signs  HOST int8 [trials][nt] or [trials][ny][nx][nt] (per_position_signs),
+ *          +1 / -1
+ * nt must be a power of two, at most 4096.  Other arguments as ufss_crb.
+ * Errors: INVALID_ARG, UNSUPPORTED (nt), HIP, OOM. */
+int ufss_crb_mixed(const ufss_geom* g, int32_t m, int32_t per_position, int32_t trials,
+                   const int32_t* bins, int32_t per_position_signs, const int8_t* signs,
+                   const ufss_crb_point* pt, double* fim_out, double* crb_out,
+                   ufss_stream_t stream);
+
 /* Build a plan: derived geometry (FP64 on the host), the integer-turn delay
  * table, H_k and the device workspace.  Paper Sec. IV-B: the operator is block
  * 2-level Toeplitz in the lateral offset, which the kernels exploit.

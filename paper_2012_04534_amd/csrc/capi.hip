@@ -23,6 +23,9 @@ void sigma_estimate(const ufss_geom* g, int m, int per_position, const int32_t* 
                     ufss_sigma_est* out);
 void crb(const ufss_geom* g, int m, int per_position, int trials, const int32_t* bins,
          const ufss_crb_point* pt, double* fim_out, double* crb_out, hipStream_t s);
+void crb_mixed(const ufss_geom* g, int m, int per_position, int trials, const int32_t* bins,
+               int per_position_signs, const int8_t* signs, const ufss_crb_point* pt,
+               double* fim_out, double* crb_out, hipStream_t s);
 const char* last_error();
 int phasor_forward_blocks(const Plan& P);
 int fista_batched(int n, Plan* const* plans, const cf32* const* ys, cf32* const* xs,
@@ -456,6 +459,16 @@ int ufss_crb(const ufss_geom* g, int32_t m, int32_t per_position, int32_t trials
     UFSS_GUARD_BEGIN
     ufss::crb(g, m, per_position, trials, bins, pt, fim_out, crb_out,
               static_cast<hipStream_t>(stream));
+    UFSS_GUARD_END
+}
+
+int ufss_crb_mixed(const ufss_geom* g, int32_t m, int32_t per_position, int32_t trials,
+                   const int32_t* bins, int32_t per_position_signs, const int8_t* signs,
+                   const ufss_crb_point* pt, double* fim_out, double* crb_out,
+                   ufss_stream_t stream) {
+    UFSS_GUARD_BEGIN
+    ufss::crb_mixed(g, m, per_position, trials, bins, per_position_signs, signs, pt, fim_out,
+                    crb_out, static_cast<hipStream_t>(stream));
     UFSS_GUARD_END
 }
 

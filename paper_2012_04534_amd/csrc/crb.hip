@@ -101,6 +101,142 @@ __global__ __launch_bounds__(kCrbThreads) void crb_fim_kernel(CrbArgs a) {
     }
 }
 
+// ---- mixed measurements (Rademacher Sigma) ----------------------------------
+// Derivative rows over every signed bin j (DFT index order) of every position:
+// BC[p][j][n] = b_{p,j} c_{p,j,n}, b = a e^{j phi} H_j g_p exp(-j 2 pi f_j (tau_p - t0)).
+struct CrbMixArgs {
+    CrbArgs base;
+    double t0, phase;
+};
+
+__global__ __launch_bounds__(256) void crb_bc_kernel(CrbMixArgs m, double2* __restrict__ bc) {
+    const CrbArgs& a = m.base;
+    const int64_t n = (int64_t)a.nx * a.ny * a.nt;
+    const double hs = a.fs * sqrt(2.0 * M_PI) * a.sigma_t;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = t / a.nt;
+        const int j = (int)(t - p * a.nt);
+        const int ix = (int)(p % a.nx), iy = (int)(p / a.nx);
+        const double dxm = a.x1 - ix * a.dx, dym = a.y1 - iy * a.dy;
+        double2* out = bc + t * 5;
+        if (fabs(dxm) > a.wx * a.dx + 1e-12 || fabs(dym) > a.wy * a.dy + 1e-12) {
+            for (int q = 0; q < 5; ++q) out[q] = double2{0.0, 0.0};
+            continue;
+        }
+        const double R = sqrt(dxm * dxm + dym * dym + a.z1 * a.z1);
+        const double k2c = 2.0 / a.c;
+        const double tx = k2c * dxm / R, ty = k2c * dym / R, tz = k2c * a.z1 / R;
+        double gx = 0.0, gy = 0.0, gz = 0.0, gb = 1.0;
+        if (a.tan_theta > 0.0) {
+            const double w = a.z1 * a.tan_theta, w2 = w * w, r2 = dxm * dxm + dym * dym;
+            gb = exp(-r2 / w2);
+            gx = -2.0 * dxm / w2;
+            gy = -2.0 * dym / w2;
+            gz = 2.0 * r2 / (w2 * a.z1);
+        }
+        const int k = j <= a.nt / 2 ? j : j - a.nt;
+        const double f = (double)k * a.fs / a.nt, e = f - a.fc;
+        const double h = hs * exp(-(e * e) / (2.0 * a.sigma_f * a.sigma_f));
+        const double ang = m.phase - 2.0 * M_PI * f * (k2c * R - m.t0);
+        double sn, cs;
+        sincos(ang, &sn, &cs);
+        const double br = a.amp * h * gb * cs, bi = a.amp * h * gb * sn;
+        const double om = 2.0 * M_PI * f;
+        // c = (g. - j om t.) for x, y, z; 1/a; j
+        const double cr[5] = {gx, gy, gz, 1.0 / a.amp, 0.0};
+        const double ci[5] = {-om * tx, -om * ty, -om * tz, 0.0, 1.0};
+        for (int q = 0; q < 5; ++q) out[q] = double2{br * cr[q] - bi * ci[q], br * ci[q] + bi * cr[q]};
+    }
+}
+
+// xih[r][k] = (1/nt) sum_n xi[r][n] exp(-j 2 pi k n / nt)  (nt a power of two)
+__global__ __launch_bounds__(256) void crb_signs_dft_kernel(const int8_t* __restrict__ xi, int64_t rows,
+                                                            int nt, double2* __restrict__ out) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    double2* w = reinterpret_cast<double2*>(smem);     // [nt] twiddles
+    for (int n = threadIdx.x; n < nt; n += blockDim.x) {
+        double sn, cs;
+        sincos(-2.0 * M_PI * n / nt, &sn, &cs);
+        w[n] = double2{cs, sn};
+    }
+    __syncthreads();
+    const int mask = nt - 1;
+    const int64_t total = rows * nt;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = t / nt;
+        const int k = (int)(t - r * nt);
+        const int8_t* x = xi + r * nt;
+        double re = 0.0, im = 0.0;
+        for (int n = 0; n < nt; ++n) {
+            const double2 tw = w[(k * n) & mask];
+            re += x[n] * tw.x;
+            im += x[n] * tw.y;
+        }
+        out[t] = double2{re / nt, im / nt};
+    }
+}
+
+// One workgroup per trial, threads over positions: z_m = sum_j xih[(k_m - j) mod nt] BC[p][j],
+// J += Re{z_m^H z_m} (the 15 distinct entries in the order of crb_fim_kernel).
+__global__ __launch_bounds__(256) void crb_fim_mixed_kernel(const double2* __restrict__ bc,
+                                                            const double2* __restrict__ xih,
+                                                            const int* __restrict__ bins, int npos,
+                                                            int nt, int m, int per_pos, int per_sign,
+                                                            double* __restrict__ out) {
+    const int trial = blockIdx.x;
+    const int mask = nt - 1;
+    const int* tb = bins + (int64_t)trial * (per_pos ? (int64_t)npos * m : m);
+    const double2* tx = xih + (int64_t)trial * (per_sign ? (int64_t)npos * nt : nt);
+    double acc[15];
+#pragma unroll
+    for (int e = 0; e < 15; ++e) acc[e] = 0.0;
+    const int pr[15][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}, {0, 3}, {0, 4},
+                           {1, 3}, {1, 4}, {2, 3}, {2, 4}, {3, 3}, {3, 4}, {4, 4}};
+    for (int p = threadIdx.x; p < npos; p += blockDim.x) {
+        const double2* row = bc + (int64_t)p * nt * 5;
+        const double2* xs = tx + (per_sign ? (int64_t)p * nt : 0);
+        const int* kb = tb + (per_pos ? (int64_t)p * m : 0);
+        for (int m0 = 0; m0 < m; m0 += 4) {
+            const int mb = min(4, m - m0);
+            double zr[4][5], zi[4][5];
+            for (int i = 0; i < 4; ++i)
+                for (int q = 0; q < 5; ++q) zr[i][q] = zi[i][q] = 0.0;
+            for (int j = 0; j < nt; ++j) {
+                double2 v[5];
+                for (int q = 0; q < 5; ++q) v[q] = row[(int64_t)j * 5 + q];
+                for (int i = 0; i < 4; ++i) {
+                    if (i >= mb) break;
+                    const double2 w = xs[(kb[m0 + i] - j) & mask];
+                    for (int q = 0; q < 5; ++q) {
+                        zr[i][q] += w.x * v[q].x - w.y * v[q].y;
+                        zi[i][q] += w.x * v[q].y + w.y * v[q].x;
+                    }
+                }
+            }
+            for (int i = 0; i < mb; ++i)
+                for (int e = 0; e < 15; ++e) {
+                    const int q = pr[e][0], r = pr[e][1];
+                    acc[e] += zr[i][q] * zr[i][r] + zi[i][q] * zi[i][r];
+                }
+        }
+    }
+    __shared__ double red[15][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int e = 0; e < 15; ++e) {
+        double v = acc[e];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) red[e][wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 15) {
+        double sm = 0.0;
+        for (int w2 = 0; w2 < 4; ++w2) sm += red[threadIdx.x][w2];
+        out[(int64_t)trial * 15 + threadIdx.x] = sm;
+    }
+}
+
 // Gauss-Jordan inverse with partial pivoting of a small row-major matrix.
 static void small_inverse(int n, const double* A, double* out) {
     std::vector<double> M((size_t)n * 2 * n, 0.0);
@@ -233,6 +369,98 @@ void crb(const ufss_geom* g, int m, int per_position, int trials, const int32_t*
     }
     (void)hipFree(dbins);
     (void)hipFree(dout);
+    const double scale = 2.0 / pt->sigma2;
+    for (int t = 0; t < trials; ++t) {
+        double J[25];
+        unpack_fim(h.data() + (size_t)t * 15, scale, J);
+        if (fim_out)
+            for (int i = 0; i < 25; ++i) fim_out[(size_t)t * 25 + i] = J[i];
+        crb_from_fim(J, crb_out + (size_t)t * 3);
+    }
+}
+
+void crb_mixed(const ufss_geom* g, int m, int per_position, int trials, const int32_t* bins,
+               int per_position_signs, const int8_t* signs, const ufss_crb_point* pt,
+               double* fim_out, double* crb_out, hipStream_t s) {
+    if (!g || !bins || !signs || !pt || !crb_out) fail(UFSS_ERR_INVALID_ARG, "NULL argument");
+    if (m < 1 || trials < 1) fail(UFSS_ERR_INVALID_ARG, "m and trials must be >= 1");
+    if (!(pt->z > 0) || !(pt->amp > 0) || !(pt->sigma2 > 0) || !std::isfinite(pt->x) ||
+        !std::isfinite(pt->y) || !std::isfinite(pt->phase))
+        fail(UFSS_ERR_INVALID_ARG, "need z > 0, amp > 0, sigma2 > 0 and finite x, y, phase");
+    validate_geom_public(g);
+    const int nt = g->nt, npos = g->nx * g->ny;
+    if (nt > 4096 || (nt & (nt - 1))) fail(UFSS_ERR_UNSUPPORTED, "mixing needs nt a power of two, at most 4096");
+    const int64_t per = per_position ? (int64_t)npos * m : m;
+    for (int t = 0; t < trials; ++t)
+        for (int64_t r = 0; r < (per_position ? npos : 1); ++r)
+            for (int i = 0; i < m; ++i) {
+                const int32_t k = bins[t * per + r * m + i];
+                if (k < 0 || k >= nt) fail(UFSS_ERR_INVALID_ARG, "bin index outside [0, nt)");
+                if (i > 0 && k <= bins[t * per + r * m + i - 1])
+                    fail(UFSS_ERR_INVALID_ARG, "bins of a position must be strictly ascending");
+            }
+    const int64_t srow = per_position_signs ? npos : 1;
+    const int64_t ns = (int64_t)trials * srow * nt;
+    for (int64_t i = 0; i < ns; ++i)
+        if (signs[i] != 1 && signs[i] != -1) fail(UFSS_ERR_INVALID_ARG, "signs must be +1 or -1");
+    Derived d = derive(*g);
+    CrbMixArgs a{};
+    a.base.nx = g->nx;
+    a.base.ny = g->ny;
+    a.base.nt = nt;
+    a.base.wx = d.wx;
+    a.base.wy = d.wy;
+    a.base.dx = g->dx;
+    a.base.dy = g->dy;
+    a.base.c = g->c;
+    a.base.fs = g->fs;
+    a.base.fc = g->fc;
+    a.base.sigma_f = d.sigma_f;
+    a.base.sigma_t = d.sigma_t;
+    a.base.tan_theta = g->theta > 0 ? std::tan(g->theta) : 0.0;
+    a.base.x1 = pt->x;
+    a.base.y1 = pt->y;
+    a.base.z1 = pt->z;
+    a.base.amp = pt->amp;
+    a.t0 = d.t0;
+    a.phase = pt->phase;
+    int* dbins = nullptr;
+    int8_t* dsig = nullptr;
+    double2 *dbc = nullptr, *dxih = nullptr;
+    double* dout = nullptr;
+    std::vector<double> h((size_t)trials * 15);
+    auto release = [&]() {
+        if (dbins) (void)hipFree(dbins);
+        if (dsig) (void)hipFree(dsig);
+        if (dbc) (void)hipFree(dbc);
+        if (dxih) (void)hipFree(dxih);
+        if (dout) (void)hipFree(dout);
+    };
+    try {
+        UFSS_HIP(hipMalloc(&dbins, (size_t)trials * per * sizeof(int)));
+        UFSS_HIP(hipMalloc(&dsig, (size_t)ns));
+        UFSS_HIP(hipMalloc(&dbc, (size_t)npos * nt * 5 * sizeof(double2)));
+        UFSS_HIP(hipMalloc(&dxih, (size_t)ns * sizeof(double2)));
+        UFSS_HIP(hipMalloc(&dout, (size_t)trials * 15 * sizeof(double)));
+        UFSS_HIP(hipMemcpyAsync(dbins, bins, (size_t)trials * per * sizeof(int), hipMemcpyHostToDevice, s));
+        UFSS_HIP(hipMemcpyAsync(dsig, signs, (size_t)ns, hipMemcpyHostToDevice, s));
+        const int64_t nbc = (int64_t)npos * nt;
+        hipLaunchKernelGGL(crb_bc_kernel, dim3((unsigned)std::min<int64_t>((nbc + 255) / 256, 65536)),
+                           dim3(256), 0, s, a, dbc);
+        UFSS_HIP(hipGetLastError());
+        hipLaunchKernelGGL(crb_signs_dft_kernel, dim3((unsigned)std::min<int64_t>((ns + 255) / 256, 65536)),
+                           dim3(256), (size_t)nt * sizeof(double2), s, dsig, (int64_t)trials * srow, nt, dxih);
+        UFSS_HIP(hipGetLastError());
+        hipLaunchKernelGGL(crb_fim_mixed_kernel, dim3(trials), dim3(256), 0, s, dbc, dxih, dbins, npos, nt,
+                           m, per_position ? 1 : 0, per_position_signs ? 1 : 0, dout);
+        UFSS_HIP(hipGetLastError());
+        UFSS_HIP(hipMemcpyAsync(h.data(), dout, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        UFSS_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+        release();
+        throw;
+    }
+    release();
     const double scale = 2.0 / pt->sigma2;
     for (int t = 0; t < trials; ++t) {
         double J[25];

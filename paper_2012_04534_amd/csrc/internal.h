@@ -49,6 +49,7 @@ struct MixSpec {
 };
 // Geometry and bin-subset checks of ufss_plan_create (throws INVALID_ARG).
 void validate_bins_public(const ufss_geom* g, int m, int per_position, const int32_t* bins);
+void validate_geom_public(const ufss_geom* g);
 double pulse_spectrum(const ufss_geom& g, const Derived& d, int k);
 
 // Launch description of the operator kernels.  Everything a kernel needs is in

@@ -272,6 +272,8 @@ static void validate_bins(const ufss_geom* g, int m, int per_position, const int
     }
 }
 
+void validate_geom_public(const ufss_geom* g) { validate_geom(g); }
+
 void validate_bins_public(const ufss_geom* g, int m, int per_position, const int32_t* bins) {
     validate_geom(g);
     validate_bins(g, m, per_position, bins);

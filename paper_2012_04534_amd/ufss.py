@@ -25,7 +25,7 @@ ALGO_AUTO, ALGO_GEMM, ALGO_PHASOR, ALGO_FFT = 0, 1, 2, 3
 SAMPLE_RND, SAMPLE_RND_F, SAMPLE_MAX, SAMPLE_NRG, SAMPLE_NRG_F = 0, 1, 2, 3, 4
 
 EXPORTED = [
-    "ufss_last_error", "ufss_select_freqs", "ufss_sample_bins", "ufss_sigma_estimate", "ufss_crb",
+    "ufss_last_error", "ufss_select_freqs", "ufss_sample_bins", "ufss_sigma_estimate", "ufss_crb", "ufss_crb_mixed",
     "ufss_plan_create", "ufss_plan_create_mixed", "ufss_plan_destroy",
     "ufss_plan_info_get", "ufss_forward", "ufss_adjoint", "ufss_lipschitz", "ufss_fista",
     "ufss_fista_backtracking",
@@ -114,6 +114,8 @@ def lib():
                                      ctypes.POINTER(SigmaEst)], ctypes.c_int),
             "ufss_crb": ([ctypes.POINTER(Geom), I32, I32, I32, P, ctypes.POINTER(CrbPoint), P, P,
                           P], ctypes.c_int),
+            "ufss_crb_mixed": ([ctypes.POINTER(Geom), I32, I32, I32, P, I32, P,
+                                ctypes.POINTER(CrbPoint), P, P, P], ctypes.c_int),
             "ufss_plan_create_mixed": ([ctypes.POINTER(Geom), I32, I32, P, I32, P, P], ctypes.c_int),
             "ufss_plan_create": ([ctypes.POINTER(Geom), I32, I32, P, ctypes.POINTER(P)], ctypes.c_int),
             "ufss_plan_destroy": ([P], ctypes.c_int),
@@ -239,8 +241,10 @@ class CrbPoint(ctypes.Structure):
                 ("amp", ctypes.c_double), ("phase", ctypes.c_double), ("sigma2", ctypes.c_double)]
 
 
-def ufss_crb(g, m, per_position, bins, point, stream=None):
-    """Cramer-Rao bounds for a stack of bin selections.
+def ufss_crb(g, m, per_position, bins, point, stream=None, signs=None):
+    """Cramer-Rao bounds for a stack of bin selections (with ``signs``: of
+    randomly mixed measurements, ufss_crb_mixed; signs int8 [trials, nt] or
+    [trials, ny, nx, nt], or without the trial axis for one selection).
 
     bins: int array [trials, m] (shared) or [trials, ny, nx, m]; a single
     selection without the leading axis is accepted.  point: dict with x, y, z,
@@ -257,10 +261,23 @@ def ufss_crb(g, m, per_position, bins, point, stream=None):
     pt = CrbPoint(*(float(point[k]) for k in ("x", "y", "z", "amp", "phase", "sigma2")))
     crb = np.zeros((trials, 3))
     fim = np.zeros((trials, 5, 5))
-    _check(lib().ufss_crb(ctypes.byref(geom), int(m), int(bool(per_position)), int(trials),
-                          b.ctypes.data_as(ctypes.c_void_p), ctypes.byref(pt),
-                          fim.ctypes.data_as(ctypes.c_void_p), crb.ctypes.data_as(ctypes.c_void_p),
-                          _stream(stream)))
+    if signs is None:
+        _check(lib().ufss_crb(ctypes.byref(geom), int(m), int(bool(per_position)), int(trials),
+                              b.ctypes.data_as(ctypes.c_void_p), ctypes.byref(pt),
+                              fim.ctypes.data_as(ctypes.c_void_p),
+                              crb.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+    else:
+        sg = np.ascontiguousarray(signs, dtype=np.int8)
+        if one:
+            sg = sg[None]
+        per_s = sg.ndim == 4
+        if sg.shape[0] != trials or sg[0].size != (g["nx"] * g["ny"] if per_s else 1) * g["nt"]:
+            raise ValueError("signs must be [trials, nt] or [trials, ny, nx, nt]")
+        _check(lib().ufss_crb_mixed(ctypes.byref(geom), int(m), int(bool(per_position)), int(trials),
+                                    b.ctypes.data_as(ctypes.c_void_p), int(per_s),
+                                    sg.ctypes.data_as(ctypes.c_void_p), ctypes.byref(pt),
+                                    fim.ctypes.data_as(ctypes.c_void_p),
+                                    crb.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
     return (crb[0], fim[0]) if one else (crb, fim)
 
 

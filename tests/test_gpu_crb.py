@@ -76,3 +76,41 @@ def test_crb_errors(dev):
         assert e.value.name == "INVALID_ARG"
     with pytest.raises(u.UfssError):
         u.ufss_crb(g2, 2, False, np.array([31, 30]), POINT)
+
+
+@pytest.mark.parametrize("per_sign,per_bins,theta_deg", [(False, False, 30.0), (True, False, 0.0),
+                                                         (True, True, 30.0)])
+def test_crb_mixed_matches_oracle(per_sign, per_bins, theta_deg, dev):
+    """Mixed measurements (Rademacher signs): three trials in one call against
+    the oracle's mixed Fisher information and bounds."""
+    from paper_2012_04534_amd import ufss as u
+    g = W.geometry(9, 7, 8, 64, win_x=-1, win_y=-1)
+    g["theta"] = math.radians(theta_deg)
+    nt, m, trials = g["nt"], 3, 3
+    pt = dict(POINT, x=4.1 * g["dx"], y=2.9 * g["dy"])
+    lead = (g["ny"], g["nx"])
+    sel = np.stack([W.uniform_subsets(nt, m, lead if per_bins else (), 60 + t) for t in range(trials)])
+    sg = np.stack([W.rademacher(lead + (nt,) if per_sign else (nt,), 70 + t) for t in range(trials)])
+    c, J = u.ufss_crb(g, m, per_bins, sel, pt, signs=sg)
+    for t in range(trials):
+        Jo = K.fisher_mixed(g, sel[t], sg[t], _u(pt), pt["sigma2"])
+        np.testing.assert_allclose(J[t], Jo, rtol=0, atol=1e-9 * np.abs(Jo).max())
+        np.testing.assert_allclose(c[t], K.crb_position(Jo), rtol=1e-7)
+
+
+def test_crb_mixed_full_selection_is_full_band(dev):
+    """Every coefficient of the mixed A-scan measured: the bound equals the
+    full-band bound over every signed bin (the mixing is unitary)."""
+    from oracle import mixing as X
+    from paper_2012_04534_amd import ufss as u
+    g = W.geometry(6, 5, 8, 64)
+    nt = g["nt"]
+    pt = dict(POINT, x=2.2 * g["dx"], y=1.7 * g["dy"])
+    sg = W.rademacher((g["ny"], g["nx"], nt), 80)
+    c_mix, _ = u.ufss_crb(g, nt, False, np.arange(nt, dtype=np.int32), pt, signs=sg)
+    Jf = K.fisher(g, X.signed_bins(nt), _u(pt), pt["sigma2"])
+    np.testing.assert_allclose(c_mix, K.crb_position(Jf), rtol=1e-7)
+    with pytest.raises(u.UfssError) as e:
+        u.ufss_crb(W.geometry(6, 5, 8, 96), 2, False, np.array([1, 90], np.int32), pt,
+                   signs=np.ones(96, np.int8))
+    assert e.value.name == "UNSUPPORTED"
