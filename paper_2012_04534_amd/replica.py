@@ -18,8 +18,9 @@ Reported per run (one JSON line each):
 
 The asymptotic study of Sec. VI is ``--crb``: the Cramer-Rao bound on the
 position of one scatterer 33.3 mm below the centre of the same scan grid, for
-n_f in {1, 2, 5, 10, 20} under each strategy (50 seeded draws for the random
-ones), relative to the bound with every bin 0..N_t/2 measured.
+n_f in {1, 2, 5, 10, 20} under each strategy, the mixed ones included (50
+seeded draws for the random ones), relative to the bound with every bin
+0..N_t/2 measured.
 
 Usage: python -m paper_2012_04534_amd.replica [--quick] [--algos] [--crb]
   --algos  also times A + A^H under both per-position algorithms for each n_f
@@ -137,17 +138,30 @@ def crb_study(g, seed):
               amp=1.0, phase=math.pi / 4, sigma2=1.0)
     full = np.arange(0, g["nt"] // 2 + 1, dtype=np.int32)
     c_full, _ = ufss.ufss_crb(g, len(full), False, full, pt)
+    # every coefficient of a mixed A-scan carries the whole spectrum: its full
+    # selection gives the bound over every signed bin (the mixing is unitary)
+    c_all, _ = ufss.ufss_crb(g, g["nt"], False, np.arange(g["nt"], dtype=np.int32), pt,
+                             signs=np.ones(g["nt"], np.int8))
+    print(json.dumps(dict(kind="crb_full_signed", crb_m2=[float(v) for v in c_all])), flush=True)
     print(json.dumps(dict(kind="crb_full", crb_m2=[float(v) for v in c_full])), flush=True)
+    lead = (g["ny"], g["nx"])
     for nf in CRB_NF:
-        for strat, code in STRATEGIES.items():
+        for strat in list(STRATEGIES) + list(MIXED):
             trials = 1 if strat == "max" else CRB_TRIALS
-            sel = []
+            sel, sg = [], None
             per = False
             for t in range(trials):
-                b, per = ufss.ufss_sample_bins(g, nf, code, seed + 1000 * nf + t)
-                sel.append(b)
+                sd = seed + 1000 * nf + t
+                if strat in MIXED:
+                    per_sign, per = MIXED[strat]
+                    sel.append(W.uniform_subsets(g["nt"], nf, lead if per else (), sd))
+                    sg = (sg or []) + [W.rademacher(lead + (g["nt"],) if per_sign else (g["nt"],), sd + 1)]
+                else:
+                    b, per = ufss.ufss_sample_bins(g, nf, STRATEGIES[strat], sd)
+                    sel.append(b)
             t0 = time.perf_counter()
-            c, _ = ufss.ufss_crb(g, nf, per, np.stack(sel), pt)
+            c, _ = ufss.ufss_crb(g, nf, per, np.stack(sel), pt,
+                                 signs=None if sg is None else np.stack(sg))
             ms = (time.perf_counter() - t0) * 1e3
             ratio = c / c_full[None, :]
             print(json.dumps(dict(kind="crb", strategy=strat, n_f=nf, trials=trials,
