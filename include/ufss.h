@@ -399,7 +399,7 @@ int ufss_fista_batched(int32_t n, const ufss_plan_t* plans, const void* const* y
  * `cache_path` (keyed by the shape class); with flags bit 0 a cached entry is
  * used without timing; flags bit 2 restricts the search to d_y splits and two
  * depth splits at the default tile shape (about 9x fewer trials).  Overwrites
- * the plan's internal workspace; no effect for phasor plans.  Synchronises
+ * the plan's internal workspace; no effect for phasor and transform plans.  Synchronises
  * `stream`.
  *   fwd_split_out, adj_split_out  HOST, optional */
 int ufss_autotune(ufss_plan_t plan, const char* cache_path, int32_t flags,
@@ -490,8 +490,9 @@ int ufss_unrolled_save(ufss_net_t net, const char* path);
 int ufss_unrolled_load(ufss_net_t net, const char* path);
 
 /* Kernel timing mode.  While enabled, every forward / adjoint core kernel
- * launch of this plan (the windowed GEMM or the phasor kernel, without the
- * gather, scatter and split-sum passes) is bracketed by two HIP events
+ * launch of this plan (the windowed GEMM, the phasor kernel or the transform
+ * path's contraction, without the gather, scatter, mixing, lateral transform
+ * and split-sum passes) is bracketed by two HIP events
  * recorded on its launch stream; enabling clears earlier records, at most 4096
  * launches per direction are kept.  Not for use under graph capture.
  * ufss_plan_kernel_times synchronises on the recorded events and returns the
@@ -503,8 +504,9 @@ int ufss_plan_kernel_times(ufss_plan_t plan, double* fwd_ms, double* adj_ms, int
 
 /* Diagnostic: average duration (ms) of the operator's core kernel, launched
  * `reps` times back to back between two HIP events recorded on `stream`.
- * which = 0: forward core (windowed GEMM, or phasor forward), 1: adjoint core
- * (the GEMM kernel alone: its split-K partials are not summed).
+ * which = 0: forward core (windowed GEMM, phasor forward, or the transform
+ * path's contraction), 1: adjoint core (the GEMM kernel alone: its split-K
+ * partials are not summed; the transform path's adjoint contraction).
  * The kernel reads the plan's own workspace (its last operands), so call it
  * after at least one ufss_forward / ufss_adjoint.  Synchronises `stream`.
  *   ms_out HOST double */
