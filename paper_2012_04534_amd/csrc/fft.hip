@@ -27,49 +27,71 @@
 namespace ufss {
 
 static constexpr int kTwT = 256;   // threads of the twiddle products (channels)
-static constexpr int kTwI = 8;     // outputs per thread along the transformed axis
 
-// out[b][i][c] = sum_j W[i][j] in[b][j][c]  (complex, FP32; c contiguous).
+// out[b][i][c] = sum_j W[i][j] in[b][j][c]  (complex, FP32; c contiguous).  TI
+// outputs per thread along the transformed axis; the launch picks TI so the
+// product has enough threads to cover the chip.
+template <int TI>
 __global__ __launch_bounds__(kTwT) void twiddle_kernel(cf32* __restrict__ out,
                                                       const cf32* __restrict__ in,
                                                       const cf32* __restrict__ W, int I, int J,
                                                       int C, int64_t sib, int64_t sij,
                                                       int64_t sob, int64_t soi) {
     extern __shared__ __align__(16) unsigned char smem[];
-    cf32* wl = reinterpret_cast<cf32*>(smem);          // [kTwI][J]
+    cf32* wl = reinterpret_cast<cf32*>(smem);          // [TI][J]
     const int c = blockIdx.x * kTwT + threadIdx.x;
-    const int i0 = blockIdx.y * kTwI;
+    const int i0 = blockIdx.y * TI;
     const int b = blockIdx.z;
-    for (int t = threadIdx.x; t < kTwI * J; t += kTwT) {
+    for (int t = threadIdx.x; t < TI * J; t += kTwT) {
         const int ii = t / J, j = t - ii * J;
         wl[t] = (i0 + ii < I) ? W[(int64_t)(i0 + ii) * J + j] : cf32{0.f, 0.f};
     }
     __syncthreads();
     if (c >= C) return;
-    float ar[kTwI], ai[kTwI];
+    float ar[TI], ai[TI];
 #pragma unroll
-    for (int ii = 0; ii < kTwI; ++ii) ar[ii] = ai[ii] = 0.f;
+    for (int ii = 0; ii < TI; ++ii) ar[ii] = ai[ii] = 0.f;
     const cf32* src = in + (int64_t)b * sib + c;
-    for (int j = 0; j < J; ++j) {
-        const cf32 v = src[(int64_t)j * sij];
+    if (TI <= 2) {
+        // narrow variants: unroll the walk so several loads are in flight
+#pragma unroll 4
+        for (int j = 0; j < J; ++j) {
+            const cf32 v = src[(int64_t)j * sij];
 #pragma unroll
-        for (int ii = 0; ii < kTwI; ++ii) {
-            const cf32 w = wl[ii * J + j];
-            ar[ii] += w.re * v.re - w.im * v.im;
-            ai[ii] += w.re * v.im + w.im * v.re;
+            for (int ii = 0; ii < TI; ++ii) {
+                const cf32 w = wl[ii * J + j];
+                ar[ii] += w.re * v.re - w.im * v.im;
+                ai[ii] += w.re * v.im + w.im * v.re;
+            }
+        }
+    } else {
+        for (int j = 0; j < J; ++j) {
+            const cf32 v = src[(int64_t)j * sij];
+#pragma unroll
+            for (int ii = 0; ii < TI; ++ii) {
+                const cf32 w = wl[ii * J + j];
+                ar[ii] += w.re * v.re - w.im * v.im;
+                ai[ii] += w.re * v.im + w.im * v.re;
+            }
         }
     }
     cf32* dst = out + (int64_t)b * sob + c;
 #pragma unroll
-    for (int ii = 0; ii < kTwI; ++ii)
+    for (int ii = 0; ii < TI; ++ii)
         if (i0 + ii < I) dst[(int64_t)(i0 + ii) * soi] = cf32{ar[ii], ai[ii]};
 }
 
 static void twiddle(cf32* out, const cf32* in, const cf32* W, int B, int I, int J, int C,
                     int64_t sib, int64_t sij, int64_t sob, int64_t soi, hipStream_t s) {
-    const dim3 grid((C + kTwT - 1) / kTwT, (I + kTwI - 1) / kTwI, B);
-    hipLaunchKernelGGL(twiddle_kernel, grid, dim3(kTwT), (size_t)kTwI * J * sizeof(cf32), s, out,
-                       in, W, I, J, C, sib, sij, sob, soi);
+    // outputs per thread: as many as keep at least ~64K threads in flight
+    const int64_t base = (int64_t)B * C;
+    int ti = 8;
+    while (ti > 1 && base * ((I + ti - 1) / ti) < 65536) ti /= 2;
+    const dim3 grid((C + kTwT - 1) / kTwT, (I + ti - 1) / ti, B);
+    const size_t lds = (size_t)ti * J * sizeof(cf32);
+#define UFSS_TW(T) hipLaunchKernelGGL(twiddle_kernel<T>, grid, dim3(kTwT), lds, s, out, in, W, I, J, C, sib, sij, sob, soi)
+    if (ti == 8) UFSS_TW(8); else if (ti == 4) UFSS_TW(4); else if (ti == 2) UFSS_TW(2); else UFSS_TW(1);
+#undef UFSS_TW
     UFSS_HIP(hipGetLastError());
 }
 
