@@ -113,11 +113,11 @@ __device__ __forceinline__ int orbit(int oy, int ox, int ly, int lx, int* qy, in
 // four transform indices q), out[q][c] = sum_r T[o][r][c] in[q][r] (CONJ:
 // conj(T)).  Forward: c = bin, r = depth, T = K^[o][z][k]; adjoint: c = depth,
 // r = bin, T = the transposed copy K^t[o][k][z].  Consecutive threads take
-// consecutive c (coalesced rows of T); when C < 256 the reduction range is
-// split over G = 256 / C thread groups whose partial sums meet in LDS in a
-// fixed order.
-template <bool CONJ>
-__global__ __launch_bounds__(256) void contract_kernel(const cf32* __restrict__ tab,
+// consecutive c (coalesced rows of T); when C is below the workgroup size NT
+// the reduction range is split over G = NT / C thread groups whose partial
+// sums meet in LDS in a fixed order.
+template <bool CONJ, int NT>
+__global__ __launch_bounds__(NT) void contract_kernel(const cf32* __restrict__ tab,
                                                       const cf32* __restrict__ in,
                                                       cf32* __restrict__ out, int ly, int lx,
                                                       int nox, int C, int R) {
@@ -133,12 +133,12 @@ __global__ __launch_bounds__(256) void contract_kernel(const cf32* __restrict__ 
     }
     __syncthreads();
     const cf32* tb = tab + (int64_t)o * R * C;
-    const int G = C >= 256 ? 1 : 256 / C;
-    const int grp = threadIdx.x / (C >= 256 ? 256 : C);
-    const int lane_c = threadIdx.x - grp * (C >= 256 ? 256 : C);
+    const int G = C >= NT ? 1 : NT / C;
+    const int grp = threadIdx.x / (C >= NT ? NT : C);
+    const int lane_c = threadIdx.x - grp * (C >= NT ? NT : C);
     const int rper = (R + G - 1) / G;
     const int r0 = grp * rper, r1 = min(R, r0 + rper);
-    for (int c = lane_c; c < C && grp < G; c += (C >= 256 ? 256 : C)) {
+    for (int c = lane_c; c < C && grp < G; c += (C >= NT ? NT : C)) {
         float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll 4
         for (int r = r0; r < r1; ++r) {
@@ -175,8 +175,14 @@ __global__ __launch_bounds__(256) void contract_kernel(const cf32* __restrict__ 
     }
 }
 
+// Threads per workgroup: 512 when the contiguous index is short (more groups
+// over the reduction, more loads in flight), else 256 (measured on the 32 x 32
+// and 64 x 64 C-scans).
+static int contract_threads(int C) { return C <= 128 ? 512 : 256; }
+
 static size_t contract_lds(int C, int R) {
-    const int G = C >= 256 ? 1 : 256 / C;
+    const int NT = contract_threads(C);
+    const int G = C >= NT ? 1 : NT / C;
     return (size_t)4 * R * sizeof(cf32) + (G > 1 ? (size_t)G * 4 * C * 2 * sizeof(float) : 0);
 }
 
@@ -354,8 +360,12 @@ void fft_fwd_transform(const Plan& P, const cf32* x, hipStream_t s) {
 void fft_fwd_contract(const Plan& P, hipStream_t s) {
     const int lx = P.fft_lx, ly = P.fft_ly, nox = lx / 2 + 1, noy = ly / 2 + 1;
     const int mu = (int)P.ubins_h.size(), nz = P.g.nz;
-    hipLaunchKernelGGL(contract_kernel<false>, dim3(noy * nox), dim3(256), contract_lds(mu, nz), s,
-                       static_cast<const cf32*>(P.d_khat), P.d_fa, P.d_fb, ly, lx, nox, mu, nz);
+    if (contract_threads(mu) == 512)
+        hipLaunchKernelGGL((contract_kernel<false, 512>), dim3(noy * nox), dim3(512), contract_lds(mu, nz), s,
+                           static_cast<const cf32*>(P.d_khat), P.d_fa, P.d_fb, ly, lx, nox, mu, nz);
+    else
+        hipLaunchKernelGGL((contract_kernel<false, 256>), dim3(noy * nox), dim3(256), contract_lds(mu, nz), s,
+                           static_cast<const cf32*>(P.d_khat), P.d_fa, P.d_fb, ly, lx, nox, mu, nz);
     UFSS_HIP(hipGetLastError());
 }
 
@@ -378,8 +388,12 @@ void fft_adj_contract(const Plan& P, hipStream_t s) {
     const int lx = P.fft_lx, ly = P.fft_ly, nox = lx / 2 + 1, noy = ly / 2 + 1;
     const int mu = (int)P.ubins_h.size();
     const int nz = P.g.nz;
-    hipLaunchKernelGGL(contract_kernel<true>, dim3(noy * nox), dim3(256), contract_lds(nz, mu), s,
-                       static_cast<const cf32*>(P.d_khat_t), P.d_fa, P.d_fb, ly, lx, nox, nz, mu);
+    if (contract_threads(nz) == 512)
+        hipLaunchKernelGGL((contract_kernel<true, 512>), dim3(noy * nox), dim3(512), contract_lds(nz, mu), s,
+                           static_cast<const cf32*>(P.d_khat_t), P.d_fa, P.d_fb, ly, lx, nox, nz, mu);
+    else
+        hipLaunchKernelGGL((contract_kernel<true, 256>), dim3(noy * nox), dim3(256), contract_lds(nz, mu), s,
+                           static_cast<const cf32*>(P.d_khat_t), P.d_fa, P.d_fb, ly, lx, nox, nz, mu);
     UFSS_HIP(hipGetLastError());
 }
 
