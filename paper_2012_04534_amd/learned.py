@@ -49,8 +49,9 @@ def make_dataset(plan, geom, n, seed0, ref_iters, L, mu=0.1, n_scat=(5, 30), snr
     return out
 
 
-def train(net, data, epochs, batch, lr, seed=0, log=None):
-    """Adam over shuffled mini-batches; returns the mean loss per epoch."""
+def train(net, data, epochs, batch, lr, seed=0, log=None, log_every=0):
+    """Adam over shuffled mini-batches; returns the mean loss per epoch.
+    ``log_every`` > 0 also logs the running loss every that many batches."""
     rng = np.random.default_rng(seed)
     hist = []
     for ep in range(epochs):
@@ -61,6 +62,8 @@ def train(net, data, epochs, batch, lr, seed=0, log=None):
             l = ufss.ufss_unrolled_train_step(net, [data[i][0] for i in idx],
                                               [data[i][1] for i in idx], lr)
             losses.append(l)
+            if log and log_every > 0 and len(losses) % log_every == 0:
+                log("epoch %d batch %d running loss %.5f" % (ep, len(losses), float(np.mean(losses))))
         hist.append(float(np.mean(losses)))
         if log:
             log("epoch %d loss %.5f" % (ep, hist[-1]))

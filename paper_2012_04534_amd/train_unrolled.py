@@ -34,6 +34,8 @@ def main():
     ap.add_argument("--channels", type=int, default=8)
     ap.add_argument("--ref-iters", type=int, default=100)
     ap.add_argument("--bf16", action="store_true", help="BF16 operator inside the network")
+    ap.add_argument("--transform", action="store_true",
+                    help="the transform-domain operator (FP32) for the data and the network")
     ap.add_argument("--init", default=None, help="checkpoint to continue from")
     ap.add_argument("--autotune", action="store_true", help="tune the operator's tiling first")
     ap.add_argument("--lr-decay", type=float, default=1.0, help="learning-rate factor per epoch")
@@ -52,8 +54,9 @@ def main():
     w = W.workload("cscan32")
     g = w["geom"]
     bins, _ = ufss.ufss_select_freqs(g, w["m"], True, w["seed"])
-    plan = ufss.Plan(g, w["m"], True, bins, algo=ufss.ALGO_GEMM)
-    if args.autotune:
+    plan = ufss.Plan(g, w["m"], True, bins,
+                     algo=ufss.ALGO_FFT if args.transform else ufss.ALGO_GEMM)
+    if args.autotune and not args.transform:
         ufss.ufss_autotune(plan, None, False, False)
     L = ufss.ufss_lipschitz(plan, max_iters=200, rtol=1e-6, margin=0.01)
     print("L %.6e" % L, flush=True)
@@ -76,7 +79,8 @@ def main():
     hist = []
     lr = args.lr
     for ep in range(args.epochs):
-        h = LN.train(net, train, 1, args.batch, lr, seed=ep)
+        h = LN.train(net, train, 1, args.batch, lr, seed=ep,
+                     log=lambda m: print(m, flush=True), log_every=64)
         hist += h
         ufss.ufss_unrolled_save(net, args.out)
         print("epoch %d loss %.5f lr %.2e (%.1f s)" % (ep, h[0], lr, time.time() - t0), flush=True)
@@ -89,7 +93,8 @@ def main():
     rep = {
         "stages": args.stages, "channels": args.channels, "train_scenes": args.train,
         "eval_scenes": args.eval, "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
-        "operator": "bf16" if args.bf16 else "f32", "ref_iters": args.ref_iters, "L": L,
+        "operator": "bf16" if args.bf16 else ("f32 transform" if args.transform else "f32"),
+        "ref_iters": args.ref_iters, "L": L,
         "init": os.path.basename(args.init) if args.init else None, "lr_decay": args.lr_decay,
         "epochs_run": len(hist), "start_err_mean": float(r0["err"].mean()),
         "loss_per_epoch": hist, "train_s": t_train,
