@@ -193,20 +193,20 @@ __global__ __launch_bounds__(kLT) void k_conv1_bwd(Dims d, int ch, const float* 
     }
 }
 
-// grad[(o * cin + c) * 27 + e] += sum_v dout_o(v) in_c(v + e); bias[o] += sum_v dout_o(v),
-// each optionally times c = lam / L (the correction's scale, see the stage definition).
+// Weight-gradient partials: block (r, oc) with oc = o * cin + c sums, over its
+// voxel range r, dout_o(v) in_c(v + e) for the 27 offsets e and dout_o(v) (slot
+// 27, the bias), into part[(oc * nsplit + r) * 28 + slot] in FP64.
 // Channel accessors: value = base[c * cstride + v * vstride].
 __global__ __launch_bounds__(kLT) void k_wgrad(Dims d, const float* __restrict__ dout, int64_t ocs,
                                                int ovs, const float* __restrict__ in, int64_t ics,
-                                               int ivs, int cin, float* __restrict__ gW,
-                                               float* __restrict__ gb, const double* __restrict__ lam,
-                                               float invL, int scale_w, int scale_b) {
-    const double cs = lam[0] * (double)invL;
+                                               int ivs, int cin, int nsplit, double* __restrict__ part) {
     __shared__ double red[28][kLT / 64];
-    const int o = blockIdx.x / cin, c = blockIdx.x % cin;
+    const int oc = blockIdx.y, o = oc / cin, c = oc % cin;
+    const int64_t chunk = (d.n + nsplit - 1) / nsplit;
+    const int64_t v0 = (int64_t)blockIdx.x * chunk, v1 = std::min<int64_t>(d.n, v0 + chunk);
     float acc[28];
     for (int e = 0; e < 28; ++e) acc[e] = 0.f;
-    for (int64_t v = threadIdx.x; v < d.n; v += kLT) {
+    for (int64_t v = v0 + threadIdx.x; v < v1; v += kLT) {
         const float g = dout[o * ocs + v * ovs];
         if (g == 0.f) continue;
         for (int e = 0; e < 27; ++e) {
@@ -223,12 +223,32 @@ __global__ __launch_bounds__(kLT) void k_wgrad(Dims d, const float* __restrict__
     }
     __syncthreads();
     if (threadIdx.x < 28) {
-        const int e = threadIdx.x;
         double s = 0.0;
-        for (int i = 0; i < kLT / 64; ++i) s += red[e][i];
-        if (e < 27) gW[(o * cin + c) * 27 + e] += (float)(scale_w ? cs * s : s);
-        else if (c == 0) gb[o] += (float)(scale_b ? cs * s : s);
+        for (int i = 0; i < kLT / 64; ++i) s += red[threadIdx.x][i];
+        part[((int64_t)oc * nsplit + blockIdx.x) * 28 + threadIdx.x] = s;
     }
+}
+
+// grad[(o * cin + c) * 27 + e] += sum over the ranges of the partials (fixed
+// order); bias[o] += the slot-27 sum of channel 0; each optionally times
+// c = lam / L (the correction's scale, see the stage definition).
+__global__ void k_wgrad_sum(const double* __restrict__ part, int nsplit, int cin,
+                            float* __restrict__ gW, float* __restrict__ gb,
+                            const double* __restrict__ lam, float invL, int scale_w, int scale_b) {
+    const int oc = blockIdx.x, o = oc / cin, c = oc % cin, e = threadIdx.x;
+    if (e >= 28) return;
+    const double cs = lam[0] * (double)invL;
+    double s = 0.0;
+    for (int r = 0; r < nsplit; ++r) s += part[((int64_t)oc * nsplit + r) * 28 + e];
+    if (e < 27) gW[oc * 27 + e] += (float)(scale_w ? cs * s : s);
+    else if (c == 0) gb[o] += (float)(scale_b ? cs * s : s);
+}
+
+// Voxel ranges per weight-gradient launch: about 16 voxels per thread, at
+// most kWgSplit ranges (with 2 ch <= 16 (o, c) pairs, up to 2048 workgroups).
+static constexpr int kWgSplit = 128;
+static int wgrad_split(int64_t n) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>(kWgSplit, (n + 16 * kLT - 1) / (16 * kLT)));
 }
 
 // Soft-threshold backward and the step-size gradient partials.
@@ -348,7 +368,7 @@ struct Net {
     std::vector<float*> h;
     cf32 *du = nullptr, *dz = nullptr, *tmp = nullptr, *rtmp = nullptr;
     float* dh = nullptr;
-    double *d_lam = nullptr, *d_part = nullptr, *d_sc = nullptr;
+    double *d_lam = nullptr, *d_part = nullptr, *d_sc = nullptr, *d_wpart = nullptr;
     std::vector<float> beta;
     std::vector<void*> owned;
 };
@@ -406,6 +426,7 @@ Net* net_create(Plan* P, int S, int ch, double L, double mu, uint64_t seed) {
         N->d_lam = nalloc<double>(*N, 4);
         N->d_part = nalloc<double>(*N, 4096);
         N->d_sc = nalloc<double>(*N, 16);
+        N->d_wpart = nalloc<double>(*N, (size_t)2 * kMaxCh * kWgSplit * 28);
         // FISTA momentum weights (stage i = iteration i + 1)
         double t = 1.0;
         for (int i = 0; i < S; ++i) {
@@ -490,6 +511,7 @@ static void net_backward(Net& N, const cf32* aref, hipStream_t s) {
     const float invL = (float)(1.0 / N.L);
     const Dims d = dims_of(N);
     const int ch = N.ch;
+    const int nsp = wgrad_split(n);
     int nb = launch_norm2(n, aref, P.d_part, s);
     launch_reduce(P.d_part, nb, 2, N.d_sc + 2, s);   // [2] = ||a_ref||^2
     for (int i = 0; i <= N.S; ++i) UFSS_HIP(hipMemsetAsync(N.dxs[i], 0, n * sizeof(cf32), s));
@@ -508,12 +530,15 @@ static void net_backward(Net& N, const cf32* aref, hipStream_t s) {
         float* gb2 = gW2 + 2 * ch * 27;
         // conv correction backward
         hipLaunchKernelGGL(k_conv2_bwd, dim3(nbl), dim3(kLT), 0, s, d, ch, N.dxs[i + 1], W2, N.h[i], N.dh);
-        hipLaunchKernelGGL(k_wgrad, dim3(2 * ch), dim3(kLT), 0, s, d,
+        hipLaunchKernelGGL(k_wgrad, dim3(nsp, 2 * ch), dim3(kLT), 0, s, d,
                            reinterpret_cast<const float*>(N.dxs[i + 1]), (int64_t)1, 2, N.h[i], (int64_t)n, 1,
-                           ch, gW2, gb2, N.d_lam, invL, 1, 1);
-        hipLaunchKernelGGL(k_wgrad, dim3(ch * 2), dim3(kLT), 0, s, d, N.dh, (int64_t)n, 1,
-                           reinterpret_cast<const float*>(N.u[i]), (int64_t)1, 2, 2, gW1, gb1, N.d_lam,
-                           invL, 0, 1);
+                           ch, nsp, N.d_wpart);
+        hipLaunchKernelGGL(k_wgrad_sum, dim3(2 * ch), dim3(64), 0, s, N.d_wpart, nsp, ch, gW2, gb2,
+                           N.d_lam, invL, 1, 1);
+        hipLaunchKernelGGL(k_wgrad, dim3(nsp, ch * 2), dim3(kLT), 0, s, d, N.dh, (int64_t)n, 1,
+                           reinterpret_cast<const float*>(N.u[i]), (int64_t)1, 2, 2, nsp, N.d_wpart);
+        hipLaunchKernelGGL(k_wgrad_sum, dim3(ch * 2), dim3(64), 0, s, N.d_wpart, nsp, 2, gW1, gb1,
+                           N.d_lam, invL, 0, 1);
         hipLaunchKernelGGL(k_conv1_bwd, dim3(nbl), dim3(kLT), 0, s, d, ch, N.dh, W1, N.dxs[i + 1], N.du);
         // soft threshold backward, theta / step partials
         hipLaunchKernelGGL(k_soft_bwd, dim3(nbl), dim3(kLT), 0, s, n, N.z[i], N.du, N.g[i], par, invL,
