@@ -30,7 +30,13 @@ static constexpr int kTwT = 256;   // threads of the twiddle products (channels)
 
 // out[b][i][c] = sum_j W[i][j] in[b][j][c]  (complex, FP32; c contiguous).  TI
 // outputs per thread along the transformed axis; the launch picks TI so the
-// product has enough threads to cover the chip.
+// product has enough threads to cover the chip.  The walk over j loads kTwJ
+// inputs before using them, so that many loads are in flight per thread; the
+// twiddle rows in LDS are padded with zeros to a multiple of kTwJ.
+static constexpr int kTwJ = 8;
+
+__host__ __device__ static inline int tw_stride(int J) { return (J + kTwJ - 1) / kTwJ * kTwJ; }
+
 template <int TI>
 __global__ __launch_bounds__(kTwT) void twiddle_kernel(cf32* __restrict__ out,
                                                       const cf32* __restrict__ in,
@@ -38,13 +44,14 @@ __global__ __launch_bounds__(kTwT) void twiddle_kernel(cf32* __restrict__ out,
                                                       int C, int64_t sib, int64_t sij,
                                                       int64_t sob, int64_t soi) {
     extern __shared__ __align__(16) unsigned char smem[];
-    cf32* wl = reinterpret_cast<cf32*>(smem);          // [TI][J]
+    cf32* wl = reinterpret_cast<cf32*>(smem);          // [TI][Jp]
+    const int Jp = tw_stride(J);
     const int c = blockIdx.x * kTwT + threadIdx.x;
     const int i0 = blockIdx.y * TI;
     const int b = blockIdx.z;
-    for (int t = threadIdx.x; t < TI * J; t += kTwT) {
-        const int ii = t / J, j = t - ii * J;
-        wl[t] = (i0 + ii < I) ? W[(int64_t)(i0 + ii) * J + j] : cf32{0.f, 0.f};
+    for (int t = threadIdx.x; t < TI * Jp; t += kTwT) {
+        const int ii = t / Jp, j = t - ii * Jp;
+        wl[t] = (i0 + ii < I && j < J) ? W[(int64_t)(i0 + ii) * J + j] : cf32{0.f, 0.f};
     }
     __syncthreads();
     if (c >= C) return;
@@ -52,26 +59,21 @@ __global__ __launch_bounds__(kTwT) void twiddle_kernel(cf32* __restrict__ out,
 #pragma unroll
     for (int ii = 0; ii < TI; ++ii) ar[ii] = ai[ii] = 0.f;
     const cf32* src = in + (int64_t)b * sib + c;
-    if (TI <= 2) {
-        // narrow variants: unroll the walk so several loads are in flight
-#pragma unroll 4
-        for (int j = 0; j < J; ++j) {
-            const cf32 v = src[(int64_t)j * sij];
+    for (int j0 = 0; j0 < J; j0 += kTwJ) {
+        cf32 v[kTwJ];
+#pragma unroll
+        for (int t = 0; t < kTwJ; ++t)
+            v[t] = (j0 + t < J) ? src[(int64_t)(j0 + t) * sij] : cf32{0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < kTwJ; ++t) {
 #pragma unroll
             for (int ii = 0; ii < TI; ++ii) {
-                const cf32 w = wl[ii * J + j];
-                ar[ii] += w.re * v.re - w.im * v.im;
-                ai[ii] += w.re * v.im + w.im * v.re;
-            }
-        }
-    } else {
-        for (int j = 0; j < J; ++j) {
-            const cf32 v = src[(int64_t)j * sij];
-#pragma unroll
-            for (int ii = 0; ii < TI; ++ii) {
-                const cf32 w = wl[ii * J + j];
-                ar[ii] += w.re * v.re - w.im * v.im;
-                ai[ii] += w.re * v.im + w.im * v.re;
+                // four FMAs per complex product (no separate multiplies and adds)
+                const cf32 w = wl[ii * Jp + j0 + t];
+                ar[ii] = fmaf(w.re, v[t].re, ar[ii]);
+                ar[ii] = fmaf(-w.im, v[t].im, ar[ii]);
+                ai[ii] = fmaf(w.re, v[t].im, ai[ii]);
+                ai[ii] = fmaf(w.im, v[t].re, ai[ii]);
             }
         }
     }
@@ -88,7 +90,7 @@ static void twiddle(cf32* out, const cf32* in, const cf32* W, int B, int I, int 
     int ti = 8;
     while (ti > 1 && base * ((I + ti - 1) / ti) < 65536) ti /= 2;
     const dim3 grid((C + kTwT - 1) / kTwT, (I + ti - 1) / ti, B);
-    const size_t lds = (size_t)ti * J * sizeof(cf32);
+    const size_t lds = (size_t)ti * tw_stride(J) * sizeof(cf32);
 #define UFSS_TW(T) hipLaunchKernelGGL(twiddle_kernel<T>, grid, dim3(kTwT), lds, s, out, in, W, I, J, C, sib, sij, sob, soi)
     if (ti == 8) UFSS_TW(8); else if (ti == 4) UFSS_TW(4); else if (ti == 2) UFSS_TW(2); else UFSS_TW(1);
 #undef UFSS_TW
@@ -116,6 +118,12 @@ __device__ __forceinline__ int orbit(int oy, int ox, int ly, int lx, int* qy, in
 // consecutive c (coalesced rows of T); when C is below the workgroup size NT
 // the reduction range is split over G = NT / C thread groups whose partial
 // sums meet in LDS in a fixed order.
+//
+// The table is streamed kPF rows ahead: each thread holds the current block of
+// kPF entries of its column while the next block is in flight, and the first
+// block is requested before the input rows are staged.
+static constexpr int kPF = 8;
+
 template <bool CONJ, int NT>
 __global__ __launch_bounds__(NT) void contract_kernel(const cf32* __restrict__ tab,
                                                       const cf32* __restrict__ in,
@@ -127,30 +135,50 @@ __global__ __launch_bounds__(NT) void contract_kernel(const cf32* __restrict__ t
     const int o = blockIdx.x, oy = o / nox, ox = o - oy * nox;
     int qy[4], qx[4];
     const int nq = orbit(oy, ox, ly, lx, qy, qx);
+    const cf32* tb = tab + (int64_t)o * R * C;
+    const int W = C >= NT ? NT : C;                           // threads per group (c stride)
+    const int G = C >= NT ? 1 : NT / C;
+    const int grp = threadIdx.x / W;
+    const int lane_c = threadIdx.x - grp * W;
+    const int rper = (R + G - 1) / G;
+    const int r0 = grp * rper, r1 = min(R, r0 + rper);
+    const bool active = grp < G;
+    cf32 cur[kPF];
+#pragma unroll
+    for (int t = 0; t < kPF; ++t)
+        cur[t] = (active && lane_c < C && r0 + t < r1) ? tb[(int64_t)(r0 + t) * C + lane_c] : cf32{0.f, 0.f};
     for (int t = threadIdx.x; t < nq * R; t += blockDim.x) {
         const int q = t / R, r = t - q * R;
         vs[t] = in[((int64_t)qy[q] * lx + qx[q]) * R + r];
     }
     __syncthreads();
-    const cf32* tb = tab + (int64_t)o * R * C;
-    const int G = C >= NT ? 1 : NT / C;
-    const int grp = threadIdx.x / (C >= NT ? NT : C);
-    const int lane_c = threadIdx.x - grp * (C >= NT ? NT : C);
-    const int rper = (R + G - 1) / G;
-    const int r0 = grp * rper, r1 = min(R, r0 + rper);
-    for (int c = lane_c; c < C && grp < G; c += (C >= NT ? NT : C)) {
+    for (int c = lane_c; c < C && active; c += W) {
+        const cf32* col = tb + c;
         float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
-        for (int r = r0; r < r1; ++r) {
-            const cf32 kv = tb[(int64_t)r * C + c];
-            const float ki = CONJ ? -kv.im : kv.im;
+        for (int rb = r0; rb < r1; rb += kPF) {
+            cf32 nxt[kPF];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (q >= nq) break;
-                const cf32 v = vs[q * R + r];
-                ar[q] += kv.re * v.re - ki * v.im;
-                ai[q] += kv.re * v.im + ki * v.re;
+            for (int t = 0; t < kPF; ++t) {
+                const int r = rb + kPF + t;
+                nxt[t] = r < r1 ? col[(int64_t)r * C] : cf32{0.f, 0.f};
             }
+#pragma unroll
+            for (int t = 0; t < kPF; ++t) {
+                if (rb + t >= r1) break;
+                const cf32 kv = cur[t];
+                const float ki = CONJ ? -kv.im : kv.im;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (q >= nq) break;
+                    const cf32 v = vs[q * R + rb + t];
+                    ar[q] = fmaf(kv.re, v.re, ar[q]);
+                    ar[q] = fmaf(-ki, v.im, ar[q]);
+                    ai[q] = fmaf(kv.re, v.im, ai[q]);
+                    ai[q] = fmaf(ki, v.re, ai[q]);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < kPF; ++t) cur[t] = nxt[t];
         }
         if (G == 1) {
             for (int q = 0; q < nq; ++q)
@@ -161,6 +189,11 @@ __global__ __launch_bounds__(NT) void contract_kernel(const cf32* __restrict__ t
                 red[((grp * 4 + q) * C + c) * 2 + 1] = ai[q];
             }
         }
+        // first block of this thread's next column (C > NT only)
+        const int cn = c + W;
+#pragma unroll
+        for (int t = 0; t < kPF; ++t)
+            cur[t] = (cn < C && r0 + t < r1) ? tb[(int64_t)(r0 + t) * C + cn] : cf32{0.f, 0.f};
     }
     if (G == 1) return;
     __syncthreads();
@@ -176,9 +209,10 @@ __global__ __launch_bounds__(NT) void contract_kernel(const cf32* __restrict__ t
 }
 
 // Threads per workgroup: 512 when the contiguous index is short (more groups
-// over the reduction, more loads in flight), else 256 (measured on the 32 x 32
-// and 64 x 64 C-scans).
-static int contract_threads(int C) { return C <= 128 ? 512 : 256; }
+// over the reduction, more loads in flight) or long enough to give every
+// thread one column of its own, else 256 (measured on the 32 x 32 and 64 x 64
+// C-scans).
+static int contract_threads(int C) { return (C <= 128 || C >= 512) ? 512 : 256; }
 
 static size_t contract_lds(int C, int R) {
     const int NT = contract_threads(C);
