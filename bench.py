@@ -9,8 +9,9 @@ multiply-accumulate of the windowed direct sum, selected bins only), with the
 inputs resident in HBM.
 
 Prints ONE JSON line.  Extra fields: the dominant kernel's roofline, the FP64
-oracle timed on host cores ("cpu_baseline"), the FISTA time to a relative
-error of 1e-2, and per-kernel timings.
+oracle timed on host cores ("cpu_baseline", with a structured FP64 baseline of
+one BLAS complex GEMM per lateral offset beside it), the FISTA time to a
+relative error of 1e-2, and per-kernel timings.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -130,6 +131,128 @@ def cpu_baseline(w, bins, seconds=12.0):
                   "column each) at the full 32x32 C-scan geometry, FP64 numpy direct sum, "
                   "1 BLAS thread, %.1f s" % (n_fwd, n_adj, dt),
     }
+
+
+def window_offsets(g):
+    """Lateral offsets d = p - v inside the aperture window, (d_y, d_x) pairs."""
+    wx = g["nx"] - 1 if g["win_x"] < 0 else min(g["win_x"], g["nx"] - 1)
+    wy = g["ny"] - 1 if g["win_y"] < 0 else min(g["win_y"], g["ny"] - 1)
+    return [(dy, dx) for dy in range(-wy, wy + 1) for dx in range(-wx, wx + 1)]
+
+
+def structured_plan(g, bins, offsets):
+    """Tables of the structured CPU baseline: for each offset d the phasors
+    P_d[z][k] = g(d, z) exp(-j 2 pi f_k (tau(d, z) - t0)) over the union of the
+    selected bins (FP64), H_k on that union and each selection's union index."""
+    from oracle import geometry as G
+    bins = np.asarray(bins)
+    ub = np.unique(bins)
+    f = G.bin_freq(g, ub)
+    z = G.depth(g, np.arange(g["nz"]))
+    t0 = G.t0(g)
+    tabs = {}
+    for dy, dx in offsets:
+        ddx, ddy = dx * g["dx"], dy * g["dy"]
+        delay = G.tau(g, ddx, ddy, z) - t0
+        tabs[(dy, dx)] = np.exp(-2j * math.pi * np.outer(delay, f)) * G.directivity(g, ddx, ddy, z)[:, None]
+    return ub, G.pulse_spectrum(g, ub), tabs, np.searchsorted(ub, bins)
+
+
+def _shift_ranges(n_y, n_x, dy, dx):
+    return max(0, dy), min(n_y, n_y + dy), max(0, dx), min(n_x, n_x + dx)
+
+
+def structured_forward(plan, x, offsets):
+    """y = A x as one BLAS GEMM per lateral offset (positions p = v + d):
+    Y[p][k] += sum_z x[p - d][z] P_d[z][k], then selection and H_k."""
+    ub, H, tabs, sel = plan
+    n_y, n_x, n_z = x.shape
+    Y = np.zeros((n_y, n_x, len(ub)), complex)
+    for dy, dx in offsets:
+        y0, y1, x0, x1 = _shift_ranges(n_y, n_x, dy, dx)
+        if y0 >= y1 or x0 >= x1:
+            continue
+        xs = x[y0 - dy:y1 - dy, x0 - dx:x1 - dx, :].reshape(-1, n_z)
+        Y[y0:y1, x0:x1, :] += (xs @ tabs[(dy, dx)]).reshape(y1 - y0, x1 - x0, -1)
+    if sel.ndim == 1:
+        return Y[:, :, sel] * H[sel]
+    return np.take_along_axis(Y, sel, axis=2) * H[sel]
+
+
+def structured_adjoint(plan, y, offsets, n_z):
+    """x = A^H y as one BLAS GEMM per lateral offset (voxels v = p - d):
+    x[v][z] += sum_k conj(P_d[z][k]) (H r)[v + d][k]."""
+    ub, H, tabs, sel = plan
+    n_y, n_x, _ = y.shape
+    R = np.zeros((n_y, n_x, len(ub)), complex)
+    if sel.ndim == 1:
+        R[:, :, sel] = y * H[sel]
+    else:
+        np.put_along_axis(R, sel, y * H[sel], axis=2)
+    X = np.zeros((n_y, n_x, n_z), complex)
+    for dy, dx in offsets:
+        y0, y1, x0, x1 = _shift_ranges(n_y, n_x, dy, dx)
+        if y0 >= y1 or x0 >= x1:
+            continue
+        rs = R[y0:y1, x0:x1, :].reshape(-1, len(ub))
+        X[y0 - dy:y1 - dy, x0 - dx:x1 - dx, :] += np.conj(np.conj(rs) @ tabs[(dy, dx)].T).reshape(
+            y1 - y0, x1 - x0, n_z)
+    return X
+
+
+def _offset_terms(g, m, offsets):
+    """Algorithmic complex MACs of the given offsets (in-grid positions x N_z x M)."""
+    t = 0
+    for dy, dx in offsets:
+        t += max(0, g["ny"] - abs(dy)) * max(0, g["nx"] - abs(dx))
+    return t * g["nz"] * m
+
+
+def structured_rate(g, bins, m, offsets, threads):
+    """FP64 A + A^H rate of the structured baseline over the given offsets."""
+    from threadpoolctl import threadpool_limits
+    from paper_2012_04534_amd import workloads as W
+    with threadpool_limits(limits=threads):
+        t0 = time.perf_counter()
+        plan = structured_plan(g, bins, offsets)
+        t_plan = time.perf_counter() - t0
+        x = W.cn((g["ny"], g["nx"], g["nz"]), 5)
+        y = W.cn((g["ny"], g["nx"], m), 6)
+        t0 = time.perf_counter()
+        structured_forward(plan, x, offsets)
+        structured_adjoint(plan, y, offsets, g["nz"])
+        dt = time.perf_counter() - t0
+    cmac = 2 * _offset_terms(g, m, offsets)
+    return {"value": round(8.0 * cmac / dt / 1e9, 3), "unit": "GFLOP/s", "cores": threads,
+            "apply_s": round(dt, 3), "plan_s": round(t_plan, 3), "offsets": len(offsets)}
+
+
+def cpu_structured(w, bins):
+    """The structured FP64 CPU baseline: A and A^H as one complex GEMM per
+    lateral offset (numpy / BLAS), phasor tables built once per plan; on all
+    host cores of this process (at most 16) at the full 32 x 32 C-scan, on one
+    core over every 16th offset, and on all cores over 48 offsets of the 64 x 64
+    C-scan (shared bins, window +-16)."""
+    from paper_2012_04534_amd import workloads as W
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    g = w["geom"]
+    offs = window_offsets(g)
+    out = structured_rate(g, bins, w["m"], offs, threads)
+    out["kind"] = "structured FP64 CPU baseline (one BLAS complex GEMM per lateral offset)"
+    out["sample"] = "one A and one A^H at the full 32x32 C-scan (all %d offsets)" % len(offs)
+    one = structured_rate(g, bins, w["m"], offs[::16], 1)
+    one["sample"] = "one A and one A^H over every 16th offset of the 32x32 C-scan"
+    out["single_core"] = one
+    from oracle import select as S
+    w3 = W.workload("cscan64")
+    g3 = w3["geom"]
+    b3 = S.select_freqs(g3, w3["m"], w3["per_position"], w3["seed"])
+    o3 = window_offsets(g3)
+    o3 = o3[::max(1, len(o3) // 48)][:48]
+    c3 = structured_rate(g3, b3, w3["m"], o3, threads)
+    c3["sample"] = "one A and one A^H over 48 of the %d offsets of the 64x64 C-scan" % len(window_offsets(g3))
+    out["cscan64_sample"] = c3
+    return out
 
 
 WEIGHTS = os.path.join(ROOT, "paper_2012_04534_amd", "weights", "unrolled_cscan32_s16c8.bin")
@@ -526,6 +649,7 @@ def main():
 
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(w, bins)
+        result["cpu_baseline"]["structured"] = cpu_structured(w, bins)
     print(json.dumps(result), flush=True)
 
 
