@@ -252,7 +252,35 @@ def cpu_structured(w, bins):
     c3 = structured_rate(g3, b3, w3["m"], o3, threads)
     c3["sample"] = "one A and one A^H over 48 of the %d offsets of the 64x64 C-scan" % len(window_offsets(g3))
     out["cscan64_sample"] = c3
+    # FISTA at this rate: K iterations of one A and one A^H each (extrapolated)
+    out["fista_%d_extrapolated_s" % w["iters"]] = round(w["iters"] * out["apply_s"], 2)
     return out
+
+
+def cpu_oracle_fista_bscan():
+    """The plain oracle's FISTA (200 iterations, dense FP64 A, one core) on the
+    32-position B-scan workload, with L from its eigenvalues and the lambda rule."""
+    from threadpoolctl import threadpool_limits
+    from oracle import operator as O
+    from oracle import select as S
+    from oracle import solver as V
+    from paper_2012_04534_amd import workloads as W
+    w = W.workload("bscan32")
+    g = w["geom"]
+    bins = S.select_freqs(g, w["m"], w["per_position"], w["seed"])
+    y = W.cn((g["ny"], g["nx"], w["m"]), 7).reshape(-1)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        A = O.dense_A(g, bins)
+        L = V.lipschitz_dense(A)
+        t_setup = time.perf_counter() - t0
+        lam = V.lambda_rule(lambda v: A.conj().T @ v, y, w["mu"])
+        t0 = time.perf_counter()
+        V.fista(lambda v: A @ v, lambda v: A.conj().T @ v, y, lam, L, w["iters"])
+        dt = time.perf_counter() - t0
+    return {"iters": w["iters"], "solve_s": round(dt, 3), "setup_s": round(t_setup, 3), "cores": 1,
+            "sample": "the 32-position B-scan workload in full: dense FP64 A (%d x %d), numpy, "
+                      "one BLAS thread" % A.shape}
 
 
 WEIGHTS = os.path.join(ROOT, "paper_2012_04534_amd", "weights", "unrolled_cscan32_s16c8.bin")
@@ -453,6 +481,31 @@ def batch_rate(ufss, W, dev, iters=5):
             "a_plus_ah_tflops_incl_capture": round(16.0 * cm * iters / dt / 1e12, 2)}
 
 
+def bscan_fista(ufss, W, dev):
+    """FISTA on the 32-position B-scan workload (shared bins, K = 200), the
+    configuration the oracle's own FISTA is timed on: plan, L and solve times."""
+    import torch
+    w = W.workload("bscan32")
+    g = w["geom"]
+    t0 = time.perf_counter()
+    bins, _ = ufss.ufss_select_freqs(g, w["m"], w["per_position"], w["seed"])
+    plan = ufss.Plan(g, w["m"], w["per_position"], bins)
+    L = ufss.ufss_lipschitz(plan, margin=0.01)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    y = torch.from_numpy(W.cn((g["ny"], g["nx"], w["m"]), 7).astype(np.complex64)).to(dev)
+    x = torch.zeros((g["ny"], g["nx"], g["nz"]), dtype=torch.complex64, device=dev)
+    ufss.ufss_fista(plan, y, ufss.lambda_from_mu(w["mu"]), L, 5, x)
+    x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ufss.ufss_fista(plan, y, ufss.lambda_from_mu(w["mu"]), L, w["iters"], x)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    plan.close()
+    return {"iters": w["iters"], "solve_s": round(dt, 4), "plan_and_L_s": round(setup, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -634,6 +687,7 @@ def main():
         result["fista"] = time_to_accuracy(ufss, W, plan, g, w, bins, y, lam, L, t_l, dev, tcfg)
         extras["cscan64"] = cscan64_rates(ufss, W, dev, ev_time, tcfg)
         extras["batch64"] = batch_rate(ufss, W, dev)
+        extras["bscan32_fista"] = bscan_fista(ufss, W, dev)
 
     result["extras"] = extras
     plan.close()
@@ -650,6 +704,7 @@ def main():
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(w, bins)
         result["cpu_baseline"]["structured"] = cpu_structured(w, bins)
+        result["cpu_baseline"]["bscan32_oracle_fista"] = cpu_oracle_fista_bscan()
     print(json.dumps(result), flush=True)
 
 
