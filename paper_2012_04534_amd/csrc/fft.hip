@@ -83,8 +83,125 @@ __global__ __launch_bounds__(kTwT) void twiddle_kernel(cf32* __restrict__ out,
         if (i0 + ii < I) dst[(int64_t)(i0 + ii) * soi] = cf32{ar[ii], ai[ii]};
 }
 
+// The same product on the FP32 matrix cores (v_mfma_f32_16x16x4f32: rows i,
+// columns c, reduction over j four at a time; four real products per complex
+// one, the imaginary part of W negated for the real accumulator).  A workgroup
+// is 4 waves on 4 consecutive 16-column tiles of one b and one block of 16 NI
+// rows.  The plan keeps each twiddle table also in operand order,
+//   Wop[(T ks + s) 64 + lane] = W[16 T + lane % 16][4 s + lane / 16]
+// (row tile T, reduction step s, ks = ceil(J / 4) steps, zero outside I x J),
+// so a block's tiles are one contiguous range: it is copied to LDS with 16-byte
+// loads and each lane then reads 8 contiguous bytes per operand.  Each lane
+// streams its column of the input kTmPK reduction steps ahead.
+typedef float f4v __attribute__((ext_vector_type(4)));
+static constexpr int kTmMaxNI = 8;
+static constexpr int kTmPK = 4;
+static constexpr size_t kTmLds = 64 * 1024;   // bytes of staged twiddles per workgroup
+
+template <int NI>
+__global__ __launch_bounds__(256) void twiddle_mfma_kernel(cf32* __restrict__ out,
+                                                           const cf32* __restrict__ in,
+                                                           const cf32* __restrict__ Wop, int I, int J,
+                                                           int C, int64_t sib, int64_t sij,
+                                                           int64_t sob, int64_t soi) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cf32* wl = reinterpret_cast<cf32*>(smem);            // [NI][ks][64]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ks = (J + 3) / 4;
+    const int tiles = (I + 15) / 16;
+    const int t0 = blockIdx.y * NI, i0 = 16 * t0;
+    const int b = blockIdx.z;
+    {
+        // this block's tiles: a contiguous run of 32-byte pairs of entries,
+        // zero past the last tile of W
+        const int nvalid = min(NI, tiles - t0) * ks * 32;   // 16-byte units present
+        const int nall = NI * ks * 32;
+        const float4* src4 = reinterpret_cast<const float4*>(Wop + (int64_t)t0 * ks * 64);
+        float4* dst4 = reinterpret_cast<float4*>(wl);
+        for (int t = threadIdx.x; t < nall; t += 256)
+            dst4[t] = t < nvalid ? src4[t] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    __syncthreads();
+    const int c0 = (blockIdx.x * 4 + wave) * 16;
+    if (c0 >= C) return;                                  // wave-uniform
+    const int c = c0 + (lane & 15), kq = lane >> 4;
+    const bool cok = c < C;
+    const cf32* src = in + (int64_t)b * sib + (cok ? c : 0);
+    f4v ar[NI], ai[NI];
+#pragma unroll
+    for (int t = 0; t < NI; ++t) ar[t] = ai[t] = f4v{0.f, 0.f, 0.f, 0.f};
+    cf32 cur[kTmPK];
+#pragma unroll
+    for (int p = 0; p < kTmPK; ++p) {
+        const int j = 4 * p + kq;
+        cur[p] = (cok && j < J) ? src[(int64_t)j * sij] : cf32{0.f, 0.f};
+    }
+    for (int s0 = 0; s0 < ks; s0 += kTmPK) {
+        cf32 nxt[kTmPK];
+#pragma unroll
+        for (int p = 0; p < kTmPK; ++p) {
+            const int j = 4 * (s0 + kTmPK + p) + kq;
+            nxt[p] = (cok && j < J) ? src[(int64_t)j * sij] : cf32{0.f, 0.f};
+        }
+#pragma unroll
+        for (int p = 0; p < kTmPK; ++p) {
+            const int st = s0 + p;
+            if (st >= ks) break;                          // wave-uniform
+            const cf32 bv = cur[p];
+#pragma unroll
+            for (int t = 0; t < NI; ++t) {
+                const cf32 a = wl[(t * ks + st) * 64 + lane];
+                ar[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.re, bv.re, ar[t], 0, 0, 0);
+                ar[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.im, bv.im, ar[t], 0, 0, 0);
+                ai[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.re, bv.im, ai[t], 0, 0, 0);
+                ai[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.im, bv.re, ai[t], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < kTmPK; ++p) cur[p] = nxt[p];
+    }
+    if (!cok) return;
+    cf32* dst = out + (int64_t)b * sob + c;
+#pragma unroll
+    for (int t = 0; t < NI; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = i0 + 16 * t + 4 * kq + r;
+            if (i < I) dst[(int64_t)i * soi] = cf32{ar[t][r], ai[t][r]};
+        }
+}
+
+// Row tiles per wave for the matrix-core product: enough to cover I (at most
+// kTmMaxNI), no more than the LDS budget holds; 0 when not even one fits.
+static int tm_tiles(int I, int J) {
+    const int ks = (J + 3) / 4;
+    const int by_lds = (int)(kTmLds / ((size_t)ks * 64 * sizeof(cf32)));
+    return std::min(std::min(kTmMaxNI, (I + 15) / 16), by_lds);
+}
+
 static void twiddle(cf32* out, const cf32* in, const cf32* W, int B, int I, int J, int C,
                     int64_t sib, int64_t sij, int64_t sob, int64_t soi, hipStream_t s) {
+    const int ni = tm_tiles(I, J);
+    if (ni >= 1) {
+        const dim3 grid((C + 63) / 64, (I + 16 * ni - 1) / (16 * ni), B);
+        const size_t lds = (size_t)((J + 3) / 4) * ni * 64 * sizeof(cf32);
+        const cf32* Wop = W + (((int64_t)I * J + 1) & ~(int64_t)1);   // operand-order copy (16-byte aligned)
+#define UFSS_TM(T) hipLaunchKernelGGL(twiddle_mfma_kernel<T>, grid, dim3(256), lds, s, out, in, Wop, I, J, C, sib, sij, sob, soi)
+        switch (ni) {
+            case 1: UFSS_TM(1); break;
+            case 2: UFSS_TM(2); break;
+            case 3: UFSS_TM(3); break;
+            case 4: UFSS_TM(4); break;
+            case 5: UFSS_TM(5); break;
+            case 6: UFSS_TM(6); break;
+            case 7: UFSS_TM(7); break;
+            default: UFSS_TM(8); break;
+        }
+#undef UFSS_TM
+        UFSS_HIP(hipGetLastError());
+        return;
+    }
+    // vector-ALU product for twiddle blocks too large for LDS
     // outputs per thread: as many as keep at least ~64K threads in flight
     const int64_t base = (int64_t)B * C;
     int ti = 8;
@@ -315,10 +432,26 @@ void fft_setup(Plan& P) {
         P.ws_bytes += h.size() * sizeof(cf32);
         return static_cast<cf32*>(d);
     };
-    P.d_tw_fx = up(tw(lx, nx, lx, -1.0, 1.0));          // [qx][nx]
-    P.d_tw_fy = up(tw(ly, ny, ly, -1.0, 1.0));          // [qy][ny]
-    P.d_tw_ix = up(tw(nx, lx, lx, +1.0, 1.0 / lx));     // [px][qx]
-    P.d_tw_iy = up(tw(ny, ly, ly, +1.0, 1.0 / ly));     // [py][qy]
+    // each table [rows][cols] is followed, from the next even entry (16-byte
+    // alignment), by its copy in matrix-core operand order
+    // [ceil(rows/16)][ceil(cols/4)][64] (see twiddle_mfma_kernel)
+    auto with_op = [](std::vector<cf32> t, int rows, int cols) {
+        const int tiles = (rows + 15) / 16, ks = (cols + 3) / 4;
+        const size_t base = (t.size() + 1) & ~(size_t)1;
+        t.resize(base + (size_t)tiles * ks * 64, cf32{0.f, 0.f});
+        for (int T = 0; T < tiles; ++T)
+            for (int st = 0; st < ks; ++st)
+                for (int l = 0; l < 64; ++l) {
+                    const int r = 16 * T + (l & 15), c = 4 * st + (l >> 4);
+                    if (r < rows && c < cols)
+                        t[base + ((size_t)T * ks + st) * 64 + l] = t[(size_t)r * cols + c];
+                }
+        return t;
+    };
+    P.d_tw_fx = up(with_op(tw(lx, nx, lx, -1.0, 1.0), lx, nx));          // [qx][nx]
+    P.d_tw_fy = up(with_op(tw(ly, ny, ly, -1.0, 1.0), ly, ny));          // [qy][ny]
+    P.d_tw_ix = up(with_op(tw(nx, lx, lx, +1.0, 1.0 / lx), nx, lx));     // [px][qx]
+    P.d_tw_iy = up(with_op(tw(ny, ly, ly, +1.0, 1.0 / ly), ny, ly));     // [py][qy]
     const int64_t cmax = std::max(nz, mu);
     const int64_t wbytes = (int64_t)ly * lx * cmax * sizeof(cf32);
     const int64_t tbytes = (int64_t)std::max((int64_t)ny * lx, (int64_t)ly * nx) * cmax * sizeof(cf32);
