@@ -64,6 +64,9 @@ def check(g, m, per_pos, seed, dev, theta_deg=0.0):
     (10, 8, 33, 128, 3, 6, True, 20.0),      # beam, ragged depth
     (7, 11, 17, 64, 4, 8, False, 45.0),      # even L_x = 11, odd L_y = 15
     (1, 1, 16, 64, -1, 4, False, 0.0),       # one position
+    (300, 1, 6, 64, -1, 3, False, 0.0),      # long B-scan, L_x = 599: the inverse lateral
+                                             # product (599 inputs) takes the vector-ALU kernel,
+                                             # the forward one 38 row blocks of one tile
 ])
 def test_fft_small_against_dense(nx, ny, nz, nt, win, m, per_pos, theta, dev):
     check(W.geometry(nx, ny, nz, nt, win_x=win, win_y=win), m, per_pos, 300 + nx + nz, dev, theta)
