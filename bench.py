@@ -41,8 +41,15 @@ TRAFFIC = {
     # 32 x 32 C-scan, FP32 union-GEMM, shipped tiling (profiles/cscan32_fp32_gemm_and_phasor.md)
     "cscan32/gemm/forward/fs4-zs8-nw5-np2-zc8": {"bytes": 20.579e6, "sha": "367ebf0abcea85ec"},
     "cscan32/gemm/adjoint/as12-np2-kc16": {"bytes": 32.304e6, "sha": "367ebf0abcea85ec"},
+    # transform-domain contraction (profiles/cscan32_fp32_transform.md, cscan64_fp32_transform.md):
+    # the table once plus the transform rows in and out
+    "cscan32/transform/forward/fs1-zs1-nw1-np0-zc0": {"bytes": 149.589e6, "sha": "13a7615769c0da90"},
+    "cscan32/transform/adjoint/as1-np0-kc0": {"bytes": 149.186e6, "sha": "13a7615769c0da90"},
+    "cscan64/transform/forward/fs1-zs1-nw1-np0-zc0": {"bytes": 914.139e6, "sha": "13a7615769c0da90"},
+    "cscan64/transform/adjoint/as1-np0-kc0": {"bytes": 914.140e6, "sha": "13a7615769c0da90"},
 }
 TRAFFIC_SRC = {"gemm": "paper_2012_04534_amd/csrc/gemm_f32.hip",
+               "transform": "paper_2012_04534_amd/csrc/fft.hip",
                "gemm-bf16": "paper_2012_04534_amd/csrc/gemm_bf16.hip",
                "phasor": "paper_2012_04534_amd/csrc/phasor.hip"}
 
