@@ -214,19 +214,23 @@ static void twiddle(cf32* out, const cf32* in, const cf32* W, int B, int I, int 
     UFSS_HIP(hipGetLastError());
 }
 
-// The up-to-four transform indices (q_y, q_x) of quadrant entry (oy, ox).
-__device__ __forceinline__ int orbit(int oy, int ox, int ly, int lx, int* qy, int* qx) {
-    const int ny2 = (oy == 0 || 2 * oy == ly) ? 1 : 2;
-    const int nx2 = (ox == 0 || 2 * ox == lx) ? 1 : 2;
-    int n = 0;
-    for (int a = 0; a < ny2; ++a)
-        for (int b = 0; b < nx2; ++b) {
-            qy[n] = a ? ly - oy : oy;
-            qx[n] = b ? lx - ox : ox;
-            ++n;
-        }
-    return n;
-}
+// The up-to-four transform indices (q_y, q_x) of quadrant entry (oy, ox),
+// enumerated as q = a nx2 + b with q_y = oy or ly - oy (a) and q_x = ox or
+// lx - ox (b); nx2 (ny2) is 1 on the axis's self-mirrored entries.  Computed
+// per use (no per-thread arrays, which would live in scratch memory).
+struct Orbit {
+    int oy, ox, ly, lx, nx2, n;
+    __device__ Orbit(int oy_, int ox_, int ly_, int lx_) : oy(oy_), ox(ox_), ly(ly_), lx(lx_) {
+        const int ny2 = (oy == 0 || 2 * oy == ly) ? 1 : 2;
+        nx2 = (ox == 0 || 2 * ox == lx) ? 1 : 2;
+        n = ny2 * nx2;
+    }
+    // row index q_y lx + q_x of member q
+    __device__ int64_t row(int q) const {
+        const int a = q / nx2, b = q - a * nx2;
+        return (int64_t)(a ? ly - oy : oy) * lx + (b ? lx - ox : ox);
+    }
+};
 
 // Contraction, both directions: one workgroup per quadrant entry (its up to
 // four transform indices q), out[q][c] = sum_r T[o][r][c] in[q][r] (CONJ:
@@ -238,11 +242,15 @@ __device__ __forceinline__ int orbit(int oy, int ox, int ly, int lx, int* qy, in
 //
 // The table is streamed kPF rows ahead: each thread holds the current block of
 // kPF entries of its column while the next block is in flight, and the first
-// block is requested before the input rows are staged.
-static constexpr int kPF = 8;
+// block is requested before the input rows are staged.  Four rows ahead keep
+// the kernel within 64 registers, so eight waves fit per SIMD (four
+// 512-thread workgroups per CU): more workgroups in flight and fewer rounds
+// over the chip than eight rows ahead at six waves (measured on the 32 x 32
+// and 64 x 64 C-scans).
+static constexpr int kPF = 4;
 
 template <bool CONJ, int NT>
-__global__ __launch_bounds__(NT) void contract_kernel(const cf32* __restrict__ tab,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void contract_kernel(const cf32* __restrict__ tab,
                                                       const cf32* __restrict__ in,
                                                       cf32* __restrict__ out, int ly, int lx,
                                                       int nox, int C, int R) {
@@ -250,8 +258,8 @@ __global__ __launch_bounds__(NT) void contract_kernel(const cf32* __restrict__ t
     cf32* vs = reinterpret_cast<cf32*>(smem);                 // [4][R] input rows
     float* red = reinterpret_cast<float*>(vs + 4 * R);        // [G][4][C][2] partials
     const int o = blockIdx.x, oy = o / nox, ox = o - oy * nox;
-    int qy[4], qx[4];
-    const int nq = orbit(oy, ox, ly, lx, qy, qx);
+    const Orbit orb(oy, ox, ly, lx);
+    const int nq = orb.n;
     const cf32* tb = tab + (int64_t)o * R * C;
     const int W = C >= NT ? NT : C;                           // threads per group (c stride)
     const int G = C >= NT ? 1 : NT / C;
@@ -266,7 +274,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const cf32* __restrict__ t
         cur[t] = (active && lane_c < C && r0 + t < r1) ? tb[(int64_t)(r0 + t) * C + lane_c] : cf32{0.f, 0.f};
     for (int t = threadIdx.x; t < nq * R; t += blockDim.x) {
         const int q = t / R, r = t - q * R;
-        vs[t] = in[((int64_t)qy[q] * lx + qx[q]) * R + r];
+        vs[t] = in[orb.row(q) * R + r];
     }
     __syncthreads();
     for (int c = lane_c; c < C && active; c += W) {
@@ -299,7 +307,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const cf32* __restrict__ t
         }
         if (G == 1) {
             for (int q = 0; q < nq; ++q)
-                out[((int64_t)qy[q] * lx + qx[q]) * C + c] = cf32{ar[q], ai[q]};
+                out[orb.row(q) * C + c] = cf32{ar[q], ai[q]};
         } else {
             for (int q = 0; q < nq; ++q) {
                 red[((grp * 4 + q) * C + c) * 2] = ar[q];
@@ -321,7 +329,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const cf32* __restrict__ t
             sr += red[((g2 * 4 + q) * C + c) * 2];
             si += red[((g2 * 4 + q) * C + c) * 2 + 1];
         }
-        out[((int64_t)qy[q] * lx + qx[q]) * C + c] = cf32{sr, si};
+        out[orb.row(q) * C + c] = cf32{sr, si};
     }
 }
 
