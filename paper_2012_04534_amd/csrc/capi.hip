@@ -253,9 +253,8 @@ int fista(Plan& P, const cf32* y, double lambda, double L, int iters, double tol
         const double beta = accel ? (tk - 1.0) / tn : 0.0;
         int nb = launch_update(P.nvox, gamma, ns > 1 ? P.d_gpart : P.d_g, ns, x, step, thresh,
                                (float)beta, aref, P.d_part, s, real);
-        launch_reduce(P.d_part, nb, 5, P.d_scalars + 8, s);
-        launch_fista_stats(P.d_stats, k, P.d_scalars + 8, P.d_scalars + 0, g1, lambda,
-                           aref ? 1 : 0, ref2, s);
+        launch_reduce_fista_stats(P.d_part, nb, P.d_scalars + 8, P.d_stats, k, P.d_scalars + 0, g1,
+                                  lambda, aref ? 1 : 0, ref2, s);
         tk = tn;
         done = k + 1;
         if (tol > 0 && (done % 8 == 0)) {

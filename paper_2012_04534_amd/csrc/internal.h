@@ -189,9 +189,12 @@ void launch_reduce_max(const double* part, int nblk, double* out, hipStream_t s)
 int launch_norm2(int64_t n, const cf32* x, double* part, hipStream_t s);
 void launch_scale(int64_t n, cf32* x, const double* norm2, hipStream_t s);   // x /= sqrt(norm2)
 void launch_copy(int64_t n, const cf32* src, cf32* dst, hipStream_t s);
-void launch_fista_stats(double* stats, int k, const double* upd, const double* res2,
-                        const double* g1_prev, double lam, int have_ref, double ref2,
-                        hipStream_t s);
+// the update's five partial columns reduced into upd_out, then the FISTA
+// statistics of iteration k (objective, residual, relative change, error vs a
+// reference) and the next ||gamma||_1, in one launch
+void launch_reduce_fista_stats(const double* part, int nblk, double* upd_out, double* stats, int k,
+                               const double* res2, double* g1, double lam, int have_ref,
+                               double ref2, hipStream_t s);
 
 // Transform path (fft.hip).
 void fft_setup(Plan& P);

@@ -395,10 +395,12 @@ int launch_extrap(int64_t n, const cf32* a, const cf32* b, float beta, cf32* out
 // ---------------------------------------------------------------------------
 // Fixed-order reductions.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void reduce_kernel(const double* __restrict__ part,
-                                                          int nblk, int width,
-                                                          double* __restrict__ out) {
-    __shared__ double red[kThreads];
+// out[w] = sum over b of part[b][w], one workgroup of kThreads, fixed order
+// (strided per-thread sums, then a tree); every thread returns after the last
+// barrier, and thread 0 also keeps the sums in `keep` when given.
+__device__ __forceinline__ void block_reduce_cols(const double* __restrict__ part, int nblk,
+                                                  int width, double* __restrict__ out,
+                                                  double* red, double* keep) {
     for (int w = 0; w < width; ++w) {
         double s = 0.0;
         for (int b = threadIdx.x; b < nblk; b += kThreads) s += part[(int64_t)b * width + w];
@@ -408,9 +410,19 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const double* __restri
             if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
             __syncthreads();
         }
-        if (threadIdx.x == 0) out[w] = red[0];
+        if (threadIdx.x == 0) {
+            out[w] = red[0];
+            if (keep) keep[w] = red[0];
+        }
         __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(kThreads) void reduce_kernel(const double* __restrict__ part,
+                                                          int nblk, int width,
+                                                          double* __restrict__ out) {
+    __shared__ double red[kThreads];
+    block_reduce_cols(part, nblk, width, out, red, nullptr);
 }
 
 void launch_reduce(const double* part, int nblk, int width, double* out, hipStream_t s) {
@@ -531,26 +543,33 @@ void launch_copy(int64_t n, const cf32* src, cf32* dst, hipStream_t s) {
     UFSS_HIP(hipGetLastError());
 }
 
-// stats[k] = {1/2 res2 + lam g1, sqrt(res2), sqrt(dA2 / a2), sqrt(ref2diff / ref2)};
-// then g1 <- ||gamma_new||_1 for the next iteration.
-// upd = {l1a, l1g, dA2, a2, ref2diff}; res2 = ||A gamma_k - y||^2; g1 = ||gamma_k||_1.
-__global__ void fista_stats_kernel(double* stats, int k, const double* upd, const double* res2,
-                                   double* g1, double lam, int have_ref, double ref2) {
+// The update's five partial columns reduced (as reduce_kernel, same order) and
+// the iteration's statistics, in one launch: upd_out <- the five sums
+// {l1a, l1g, dA2, a2, ref2diff}, then with res2 = ||A gamma_k - y||^2 and
+// g1 = ||gamma_k||_1
+//   stats[k] = {1/2 res2 + lam g1, sqrt(res2), sqrt(dA2 / a2), sqrt(ref2diff / ref2)}
+// and g1 <- ||gamma_new||_1 for the next iteration.
+__global__ __launch_bounds__(kThreads) void reduce_fista_stats_kernel(
+    const double* __restrict__ part, int nblk, double* __restrict__ upd_out, double* stats, int k,
+    const double* res2, double* g1, double lam, int have_ref, double ref2) {
+    __shared__ double red[kThreads];
+    __shared__ double upd[5];
+    block_reduce_cols(part, nblk, 5, upd_out, red, upd);
     if (threadIdx.x != 0) return;
-    double r2 = res2[0];
-    double* s = stats + 4 * (int64_t)k;
-    s[0] = 0.5 * r2 + lam * g1[0];
-    s[1] = sqrt(r2);
-    s[2] = upd[3] > 0.0 ? sqrt(upd[2] / upd[3]) : 0.0;
-    s[3] = have_ref ? sqrt(upd[4] / ref2) : 0.0;
+    const double r2 = res2[0];
+    double* st = stats + 4 * (int64_t)k;
+    st[0] = 0.5 * r2 + lam * g1[0];
+    st[1] = sqrt(r2);
+    st[2] = upd[3] > 0.0 ? sqrt(upd[2] / upd[3]) : 0.0;
+    st[3] = have_ref ? sqrt(upd[4] / ref2) : 0.0;
     g1[0] = upd[1];
 }
 
-void launch_fista_stats(double* stats, int k, const double* upd, const double* res2,
-                        const double* g1_prev, double lam, int have_ref, double ref2,
-                        hipStream_t s) {
-    hipLaunchKernelGGL(fista_stats_kernel, dim3(1), dim3(64), 0, s, stats, k, upd, res2,
-                       const_cast<double*>(g1_prev), lam, have_ref, ref2);
+void launch_reduce_fista_stats(const double* part, int nblk, double* upd_out, double* stats, int k,
+                               const double* res2, double* g1, double lam, int have_ref,
+                               double ref2, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_fista_stats_kernel, dim3(1), dim3(kThreads), 0, s, part, nblk, upd_out,
+                       stats, k, res2, g1, lam, have_ref, ref2);
     UFSS_HIP(hipGetLastError());
 }
 
