@@ -181,7 +181,13 @@ static int tm_tiles(int I, int J) {
 
 static void twiddle(cf32* out, const cf32* in, const cf32* W, int B, int I, int J, int C,
                     int64_t sib, int64_t sij, int64_t sob, int64_t soi, hipStream_t s) {
-    const int ni = tm_tiles(I, J);
+    // row tiles per wave: as many as fit, then fewer (more waves, each input
+    // column read by more of them) while the launch has under 2048 waves
+    int ni = tm_tiles(I, J);
+    {
+        const int64_t tiles = (I + 15) / 16, col_waves = (int64_t)((C + 15) / 16) * B;
+        while (ni > 1 && col_waves * ((tiles + ni - 1) / ni) < 2048) --ni;
+    }
     if (ni >= 1) {
         const dim3 grid((C + 63) / 64, (I + 16 * ni - 1) / (16 * ni), B);
         const size_t lds = (size_t)((J + 3) / 4) * ni * 64 * sizeof(cf32);

@@ -395,37 +395,50 @@ int launch_extrap(int64_t n, const cf32* a, const cf32* b, float beta, cf32* out
 // ---------------------------------------------------------------------------
 // Fixed-order reductions.
 // ---------------------------------------------------------------------------
-// out[w] = sum over b of part[b][w], one workgroup of kThreads, fixed order
-// (strided per-thread sums, then a tree); every thread returns after the last
-// barrier, and thread 0 also keeps the sums in `keep` when given.
+// out[w] = sum over b of part[b][w] for w < width <= kRedW, one workgroup of
+// kThreads, fixed order: thread t sums b = t, t + kThreads, ... per column,
+// then one tree over the threads carries all columns at once (the same pairs
+// as a tree per column, with one barrier per level for all of them).  Thread
+// w < width writes out[w] (and keep[w] when given); every thread returns after
+// the last barrier.
+static constexpr int kRedW = 8;
+
 __device__ __forceinline__ void block_reduce_cols(const double* __restrict__ part, int nblk,
                                                   int width, double* __restrict__ out,
                                                   double* red, double* keep) {
-    for (int w = 0; w < width; ++w) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += kThreads) s += part[(int64_t)b * width + w];
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int off = kThreads / 2; off > 0; off >>= 1) {
-            if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            out[w] = red[0];
-            if (keep) keep[w] = red[0];
-        }
+    double acc[kRedW];
+#pragma unroll
+    for (int w = 0; w < kRedW; ++w) acc[w] = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kThreads) {
+#pragma unroll
+        for (int w = 0; w < kRedW; ++w)
+            if (w < width) acc[w] += part[(int64_t)b * width + w];
+    }
+#pragma unroll
+    for (int w = 0; w < kRedW; ++w)
+        if (w < width) red[w * kThreads + threadIdx.x] = acc[w];
+    __syncthreads();
+    for (int off = kThreads / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            for (int w = 0; w < width; ++w) red[w * kThreads + threadIdx.x] += red[w * kThreads + threadIdx.x + off];
         __syncthreads();
     }
+    if (threadIdx.x < width) {
+        out[threadIdx.x] = red[threadIdx.x * kThreads];
+        if (keep) keep[threadIdx.x] = red[threadIdx.x * kThreads];
+    }
+    __syncthreads();
 }
 
 __global__ __launch_bounds__(kThreads) void reduce_kernel(const double* __restrict__ part,
                                                           int nblk, int width,
                                                           double* __restrict__ out) {
-    __shared__ double red[kThreads];
+    __shared__ double red[kRedW * kThreads];
     block_reduce_cols(part, nblk, width, out, red, nullptr);
 }
 
 void launch_reduce(const double* part, int nblk, int width, double* out, hipStream_t s) {
+    if (width < 1 || width > kRedW) fail(UFSS_ERR_INVALID_ARG, "reduction width must be in [1, 8]");
     hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, s, part, nblk, width, out);
     UFSS_HIP(hipGetLastError());
 }
@@ -552,7 +565,7 @@ void launch_copy(int64_t n, const cf32* src, cf32* dst, hipStream_t s) {
 __global__ __launch_bounds__(kThreads) void reduce_fista_stats_kernel(
     const double* __restrict__ part, int nblk, double* __restrict__ upd_out, double* stats, int k,
     const double* res2, double* g1, double lam, int have_ref, double ref2) {
-    __shared__ double red[kThreads];
+    __shared__ double red[kRedW * kThreads];
     __shared__ double upd[5];
     block_reduce_cols(part, nblk, 5, upd_out, red, upd);
     if (threadIdx.x != 0) return;
