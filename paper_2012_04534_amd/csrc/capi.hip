@@ -65,14 +65,13 @@ static void ktime_end(Plan& P, int w, hipStream_t s) {
     ++P.kev_used[w];
 }
 
-void op_forward(Plan& P, const cf32* x, cf32* y, const cf32* ymeas, double* res2_out,
-                hipStream_t s) {
+int op_forward_partials(Plan& P, const cf32* x, cf32* y, const cf32* ymeas, double* part,
+                        hipStream_t s) {
     if (P.algo == UFSS_ALGO_PHASOR) {
         ktime_begin(P, 0, s);
-        launch_forward_phasor(P, x, y, ymeas, P.d_part, s);
+        launch_forward_phasor(P, x, y, ymeas, part, s);
         ktime_end(P, 0, s);
-        if (res2_out) launch_reduce(P.d_part, phasor_forward_blocks(P), 1, res2_out, s);
-        return;
+        return phasor_forward_blocks(P);
     }
     if (P.algo == UFSS_ALGO_FFT) {
         fft_fwd_transform(P, x, s);
@@ -90,8 +89,12 @@ void op_forward(Plan& P, const cf32* x, cf32* y, const cf32* ymeas, double* res2
         launch_forward_gemm(P, x, s);
         ktime_end(P, 0, s);
     }
-    int nb = P.mix ? launch_mix_post(P, y, ymeas, P.d_part, s)
-                   : launch_forward_post(P, y, ymeas, P.d_part, s);
+    return P.mix ? launch_mix_post(P, y, ymeas, part, s) : launch_forward_post(P, y, ymeas, part, s);
+}
+
+void op_forward(Plan& P, const cf32* x, cf32* y, const cf32* ymeas, double* res2_out,
+                hipStream_t s) {
+    const int nb = op_forward_partials(P, x, y, ymeas, P.d_part, s);
     if (res2_out) launch_reduce(P.d_part, nb, 1, res2_out, s);
 }
 
@@ -246,15 +249,16 @@ int fista(Plan& P, const cf32* y, double lambda, double L, int iters, double tol
     const float step = (float)(1.0 / L), thresh = (float)(lambda / L);
     int done = 0;
     for (int k = 0; k < iters; ++k) {
-        op_forward(P, gamma, P.d_r, y, P.d_scalars + 0, s);
+        // the residual's partials wait in their own buffer for the statistics kernel
+        const int nbr = op_forward_partials(P, gamma, P.d_r, y, P.d_part_res, s);
         // the adjoint's split-K partials are summed inside the update (its epilogue)
         const int ns = op_adjoint(P, P.d_r, P.d_g, s, true);
         const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * tk * tk));
         const double beta = accel ? (tk - 1.0) / tn : 0.0;
         int nb = launch_update(P.nvox, gamma, ns > 1 ? P.d_gpart : P.d_g, ns, x, step, thresh,
                                (float)beta, aref, P.d_part, s, real);
-        launch_reduce_fista_stats(P.d_part, nb, P.d_scalars + 8, P.d_stats, k, P.d_scalars + 0, g1,
-                                  lambda, aref ? 1 : 0, ref2, s);
+        launch_reduce_fista_stats(P.d_part_res, nbr, P.d_scalars + 0, P.d_part, nb, P.d_scalars + 8,
+                                  P.d_stats, k, g1, lambda, aref ? 1 : 0, ref2, s);
         tk = tn;
         done = k + 1;
         if (tol > 0 && (done % 8 == 0)) {

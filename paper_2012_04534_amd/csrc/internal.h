@@ -109,6 +109,7 @@ struct Plan {
     void* d_ptab_a = nullptr;
     int64_t ptab_bytes = 0;
     double* d_part = nullptr;      // FP64 block partials
+    double* d_part_res = nullptr;  // FP64 partials of the residual norm, kept for a later reduction
     int part_cap = 0;
     double* d_scalars = nullptr;   // small FP64 results
     cf32* d_r = nullptr;           // residual [npos*m]
@@ -189,12 +190,13 @@ void launch_reduce_max(const double* part, int nblk, double* out, hipStream_t s)
 int launch_norm2(int64_t n, const cf32* x, double* part, hipStream_t s);
 void launch_scale(int64_t n, cf32* x, const double* norm2, hipStream_t s);   // x /= sqrt(norm2)
 void launch_copy(int64_t n, const cf32* src, cf32* dst, hipStream_t s);
-// the update's five partial columns reduced into upd_out, then the FISTA
-// statistics of iteration k (objective, residual, relative change, error vs a
-// reference) and the next ||gamma||_1, in one launch
-void launch_reduce_fista_stats(const double* part, int nblk, double* upd_out, double* stats, int k,
-                               const double* res2, double* g1, double lam, int have_ref,
-                               double ref2, hipStream_t s);
+// the residual's partials reduced into res2_out and the update's five partial
+// columns into upd_out, then the FISTA statistics of iteration k (objective,
+// residual, relative change, error vs a reference) and the next ||gamma||_1,
+// in one launch
+void launch_reduce_fista_stats(const double* res_part, int res_nblk, double* res2_out,
+                               const double* part, int nblk, double* upd_out, double* stats, int k,
+                               double* g1, double lam, int have_ref, double ref2, hipStream_t s);
 
 // Transform path (fft.hip).
 void fft_setup(Plan& P);
@@ -221,6 +223,10 @@ int launch_extrap(int64_t n, const cf32* a, const cf32* b, float beta, cf32* out
 int max_blocks_vec();
 
 // Operator drivers (operator.cpp).
+// The forward operator with its residual epilogue, the FP64 block partials of
+// ||y - ymeas||^2 left in part (capacity part_cap); returns their count.
+int op_forward_partials(Plan& P, const cf32* x, cf32* y, const cf32* ymeas, double* part,
+                        hipStream_t s);
 void op_forward(Plan& P, const cf32* x, cf32* y, const cf32* ymeas, double* res2_out,
                 hipStream_t s);
 // Returns 1 when x holds A^H y; with defer_sum, the number of split partials

@@ -246,7 +246,7 @@ static void upload(T* dst, const T* src, size_t count) {
 static void free_plan(Plan* P) {
     if (!P) return;
     void* ptrs[] = {P->d_bins, P->d_ubins, P->d_map, P->d_hsel, P->d_u, P->d_yraw,
-                    P->d_rop, P->d_xop, P->d_part, P->d_scalars, P->d_r, P->d_g,
+                    P->d_rop, P->d_xop, P->d_part, P->d_part_res, P->d_scalars, P->d_r, P->d_g,
                     P->d_gamma, P->d_v, P->d_stats, P->d_gpart, P->d_ptab_f, P->d_ptab_a,
                     P->d_bt, P->d_bt_scal, P->d_amp, P->d_xih, P->d_khat, P->d_khat_t, P->d_tw_fx, P->d_tw_fy,
                     P->d_tw_ix, P->d_tw_iy, P->d_fa, P->d_fb, P->d_ft};
@@ -510,6 +510,7 @@ Plan* plan_create(const ufss_geom* g, int m, int per_position, const int32_t* bi
         if (algo == UFSS_ALGO_FFT) fft_setup(*P);
         P->part_cap = 65536;
         P->d_part = dalloc<double>(*P, P->part_cap);
+        P->d_part_res = dalloc<double>(*P, P->part_cap);
         P->d_scalars = dalloc<double>(*P, 64);
         P->d_r = dalloc<cf32>(*P, (size_t)npos * m);
         P->d_g = dalloc<cf32>(*P, P->nvox);

@@ -556,20 +556,22 @@ void launch_copy(int64_t n, const cf32* src, cf32* dst, hipStream_t s) {
     UFSS_HIP(hipGetLastError());
 }
 
-// The update's five partial columns reduced (as reduce_kernel, same order) and
-// the iteration's statistics, in one launch: upd_out <- the five sums
-// {l1a, l1g, dA2, a2, ref2diff}, then with res2 = ||A gamma_k - y||^2 and
-// g1 = ||gamma_k||_1
+// The residual's partials and the update's five partial columns reduced (each
+// as reduce_kernel, same order) and the iteration's statistics, in one launch:
+// res2_out <- ||A gamma_k - y||^2, upd_out <- the five sums
+// {l1a, l1g, dA2, a2, ref2diff}, then with g1 = ||gamma_k||_1
 //   stats[k] = {1/2 res2 + lam g1, sqrt(res2), sqrt(dA2 / a2), sqrt(ref2diff / ref2)}
 // and g1 <- ||gamma_new||_1 for the next iteration.
 __global__ __launch_bounds__(kThreads) void reduce_fista_stats_kernel(
+    const double* __restrict__ res_part, int res_nblk, double* __restrict__ res2_out,
     const double* __restrict__ part, int nblk, double* __restrict__ upd_out, double* stats, int k,
-    const double* res2, double* g1, double lam, int have_ref, double ref2) {
+    double* g1, double lam, int have_ref, double ref2) {
     __shared__ double red[kRedW * kThreads];
-    __shared__ double upd[5];
+    __shared__ double upd[6];
+    block_reduce_cols(res_part, res_nblk, 1, res2_out, red, upd + 5);
     block_reduce_cols(part, nblk, 5, upd_out, red, upd);
     if (threadIdx.x != 0) return;
-    const double r2 = res2[0];
+    const double r2 = upd[5];
     double* st = stats + 4 * (int64_t)k;
     st[0] = 0.5 * r2 + lam * g1[0];
     st[1] = sqrt(r2);
@@ -578,11 +580,11 @@ __global__ __launch_bounds__(kThreads) void reduce_fista_stats_kernel(
     g1[0] = upd[1];
 }
 
-void launch_reduce_fista_stats(const double* part, int nblk, double* upd_out, double* stats, int k,
-                               const double* res2, double* g1, double lam, int have_ref,
-                               double ref2, hipStream_t s) {
-    hipLaunchKernelGGL(reduce_fista_stats_kernel, dim3(1), dim3(kThreads), 0, s, part, nblk, upd_out,
-                       stats, k, res2, g1, lam, have_ref, ref2);
+void launch_reduce_fista_stats(const double* res_part, int res_nblk, double* res2_out,
+                               const double* part, int nblk, double* upd_out, double* stats, int k,
+                               double* g1, double lam, int have_ref, double ref2, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_fista_stats_kernel, dim3(1), dim3(kThreads), 0, s, res_part, res_nblk,
+                       res2_out, part, nblk, upd_out, stats, k, g1, lam, have_ref, ref2);
     UFSS_HIP(hipGetLastError());
 }
 
