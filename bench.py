@@ -540,8 +540,8 @@ def main():
     else:
         tcfg = (SHIPPED_TUNING, True, False)
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see the sharding design); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(its sharding is a design only); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

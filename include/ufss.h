@@ -41,7 +41,7 @@ extern "C" {
 #define UFSS_ERR_BAND_TOO_SMALL -2  /* m exceeds the number of band bins      */
 #define UFSS_ERR_HIP            -3  /* a HIP runtime call failed              */
 #define UFSS_ERR_OOM            -4  /* device allocation failed               */
-#define UFSS_ERR_UNSUPPORTED    -5  /* valid request this build cannot serve  */
+#define UFSS_ERR_UNSUPPORTED    -5  /* valid request the library cannot serve  */
 #define UFSS_ERR_DIVERGED       -6  /* non-finite or exploding FISTA iterates */
 
 /* ---- operator precision ------------------------------------------------ */
