@@ -328,7 +328,7 @@ def time_to_accuracy(ufss, W, plan, g, w, bins, y, lam, L, t_l, dev, tcfg):
            "lipschitz_s": round(t_l, 4), "L": L, "lambda": lam, "levels": [0.3, 0.1, 0.03, 0.01]}
     x = torch.zeros_like(a_ref)
     for tag, dt, algo in (("fp32", ufss.F32, None), ("fp32_transform", ufss.F32, ufss.ALGO_FFT),
-                          ("bf16", ufss.BF16, ufss.ALGO_GEMM)):
+                          ("bf16", ufss.BF16, ufss.ALGO_GEMM), ("bf16_transform", ufss.BF16, ufss.ALGO_FFT)):
         p = plan
         if algo is not None:
             p = ufss.Plan(g, w["m"], w["per_position"], bins, dtype=dt, algo=algo)
@@ -577,8 +577,6 @@ def main():
     # the phasor algorithm is FP32 only
     algos = [ufss.ALGO_GEMM, ufss.ALGO_PHASOR] if (per_pos and not bf16) else [ufss.ALGO_GEMM]
     if args.algo == "fft":
-        if bf16:
-            sys.exit("bench: the transform-domain operator is FP32 only")
         algos = [ufss.ALGO_FFT]
     xr = torch.from_numpy(W.cn(shape_x, 1).astype(np.complex64)).to(dev)
     yr = torch.empty(shape_y, dtype=torch.complex64, device=dev)
@@ -592,7 +590,7 @@ def main():
         tf = ev_time(lambda: ufss.ufss_forward(plan, xr, yr), 5)
         ta = ev_time(lambda: ufss.ufss_adjoint(plan, yr, xo), 5)
         name = {ufss.ALGO_GEMM: "gemm-bf16" if bf16 else "gemm", ufss.ALGO_PHASOR: "phasor",
-                ufss.ALGO_FFT: "transform"}[algo]
+                ufss.ALGO_FFT: "transform-bf16" if bf16 else "transform"}[algo]
         extras["algos"][name] = {"forward_ms": round(tf, 4), "adjoint_ms": round(ta, 4),
                                  "a_plus_ah_gflops": round(flop_pair / ((tf + ta) * 1e-3) / 1e9, 1)}
         if best is None or tf + ta < best[1]:
@@ -652,11 +650,11 @@ def main():
     extras["kernel_launches_timed"] = {"forward": n_f, "adjoint": n_a}
     dom, k_ms = ("adjoint", k_a) if k_a >= k_f else ("forward", k_f)
     if algo == ufss.ALGO_FFT:
-        # the contraction streams its table of (ly/2+1)(lx/2+1) nz mu complex64
-        # once per launch: bound by HBM
+        # the contraction streams its table of (ly/2+1)(lx/2+1) nz mu complex
+        # entries (8 bytes, 4 in BF16) once per launch: bound by HBM
         pi = plan.info()
         tab = ((g["ny"] + pi["win_y"]) // 2 + 1) * ((g["nx"] + pi["win_x"]) // 2 + 1) * g["nz"] * \
-            pi["union_size"] * 8
+            pi["union_size"] * (4 if bf16 else 8)
         roof = {"bound": "hbm", "achieved": round(tab / (k_ms * 1e-3) / 1e9, 1),
                 "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
     elif algo == ufss.ALGO_PHASOR:

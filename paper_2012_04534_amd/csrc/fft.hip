@@ -255,8 +255,13 @@ struct Orbit {
 // and 64 x 64 C-scans).
 static constexpr int kPF = 4;
 
-template <bool CONJ, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void contract_kernel(const cf32* __restrict__ tab,
+// Table entries as FP32 pairs (FP32 plans) or BF16 pairs (BF16 plans: the table
+// rounded to nearest even once at plan time, products and sums in FP32).
+__device__ __forceinline__ cf32 entry(const cf32& v) { return v; }
+__device__ __forceinline__ cf32 entry(const cbf16& v) { return cf32{(float)v.re, (float)v.im}; }
+
+template <bool CONJ, int NT, typename TT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void contract_kernel(const TT* __restrict__ tab,
                                                       const cf32* __restrict__ in,
                                                       cf32* __restrict__ out, int ly, int lx,
                                                       int nox, int C, int R) {
@@ -266,7 +271,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     const int o = blockIdx.x, oy = o / nox, ox = o - oy * nox;
     const Orbit orb(oy, ox, ly, lx);
     const int nq = orb.n;
-    const cf32* tb = tab + (int64_t)o * R * C;
+    const TT* tb = tab + (int64_t)o * R * C;
     const int W = C >= NT ? NT : C;                           // threads per group (c stride)
     const int G = C >= NT ? 1 : NT / C;
     const int grp = threadIdx.x / W;
@@ -274,29 +279,29 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     const int rper = (R + G - 1) / G;
     const int r0 = grp * rper, r1 = min(R, r0 + rper);
     const bool active = grp < G;
-    cf32 cur[kPF];
+    TT cur[kPF];
 #pragma unroll
     for (int t = 0; t < kPF; ++t)
-        cur[t] = (active && lane_c < C && r0 + t < r1) ? tb[(int64_t)(r0 + t) * C + lane_c] : cf32{0.f, 0.f};
+        cur[t] = (active && lane_c < C && r0 + t < r1) ? tb[(int64_t)(r0 + t) * C + lane_c] : TT{};
     for (int t = threadIdx.x; t < nq * R; t += blockDim.x) {
         const int q = t / R, r = t - q * R;
         vs[t] = in[orb.row(q) * R + r];
     }
     __syncthreads();
     for (int c = lane_c; c < C && active; c += W) {
-        const cf32* col = tb + c;
+        const TT* col = tb + c;
         float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
         for (int rb = r0; rb < r1; rb += kPF) {
-            cf32 nxt[kPF];
+            TT nxt[kPF];
 #pragma unroll
             for (int t = 0; t < kPF; ++t) {
                 const int r = rb + kPF + t;
-                nxt[t] = r < r1 ? col[(int64_t)r * C] : cf32{0.f, 0.f};
+                nxt[t] = r < r1 ? col[(int64_t)r * C] : TT{};
             }
 #pragma unroll
             for (int t = 0; t < kPF; ++t) {
                 if (rb + t >= r1) break;
-                const cf32 kv = cur[t];
+                const cf32 kv = entry(cur[t]);
                 const float ki = CONJ ? -kv.im : kv.im;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -324,7 +329,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         const int cn = c + W;
 #pragma unroll
         for (int t = 0; t < kPF; ++t)
-            cur[t] = (cn < C && r0 + t < r1) ? tb[(int64_t)(r0 + t) * C + cn] : cf32{0.f, 0.f};
+            cur[t] = (cn < C && r0 + t < r1) ? tb[(int64_t)(r0 + t) * C + cn] : TT{};
     }
     if (G == 1) return;
     __syncthreads();
@@ -515,6 +520,28 @@ void fft_setup(Plan& P) {
                            dim3(256), 0, nullptr, static_cast<const cf32*>(P.d_khat),
                            static_cast<cf32*>(P.d_khat_t), nz, mu);
         UFSS_HIP(hipGetLastError());
+        if (P.dtype == UFSS_BF16) {
+            // BF16 plans stream both copies of the table in BF16 (rounded to
+            // nearest even once, here); the FP32 copies are released
+            const int64_t n = (int64_t)noy * nox * zc;
+            void* k16 = nullptr;
+            void* kt16 = nullptr;
+            try {
+                UFSS_HIP(hipMalloc(&k16, n * sizeof(cbf16)));
+                UFSS_HIP(hipMalloc(&kt16, n * sizeof(cbf16)));
+            } catch (...) {
+                if (k16) (void)hipFree(k16);
+                throw;
+            }
+            launch_to_bf16(static_cast<const cf32*>(P.d_khat), k16, n, nullptr);
+            launch_to_bf16(static_cast<const cf32*>(P.d_khat_t), kt16, n, nullptr);
+            UFSS_HIP(hipDeviceSynchronize());
+            (void)hipFree(P.d_khat);
+            (void)hipFree(P.d_khat_t);
+            P.d_khat = k16;
+            P.d_khat_t = kt16;
+            P.ws_bytes -= 2 * n * (int64_t)(sizeof(cf32) - sizeof(cbf16));
+        }
         UFSS_HIP(hipDeviceSynchronize());
     } catch (...) {
         if (p64) (void)hipFree(p64);
@@ -541,12 +568,21 @@ void fft_fwd_transform(const Plan& P, const cf32* x, hipStream_t s) {
 void fft_fwd_contract(const Plan& P, hipStream_t s) {
     const int lx = P.fft_lx, ly = P.fft_ly, nox = lx / 2 + 1, noy = ly / 2 + 1;
     const int mu = (int)P.ubins_h.size(), nz = P.g.nz;
-    if (contract_threads(mu) == 512)
-        hipLaunchKernelGGL((contract_kernel<false, 512>), dim3(noy * nox), dim3(512), contract_lds(mu, nz), s,
-                           static_cast<const cf32*>(P.d_khat), P.d_fa, P.d_fb, ly, lx, nox, mu, nz);
-    else
-        hipLaunchKernelGGL((contract_kernel<false, 256>), dim3(noy * nox), dim3(256), contract_lds(mu, nz), s,
-                           static_cast<const cf32*>(P.d_khat), P.d_fa, P.d_fb, ly, lx, nox, mu, nz);
+    const size_t lds = contract_lds(mu, nz);
+    const dim3 grid(noy * nox);
+    if (P.dtype == UFSS_BF16) {
+        const cbf16* t = static_cast<const cbf16*>(P.d_khat);
+        if (contract_threads(mu) == 512)
+            hipLaunchKernelGGL((contract_kernel<false, 512, cbf16>), grid, dim3(512), lds, s, t, P.d_fa, P.d_fb, ly, lx, nox, mu, nz);
+        else
+            hipLaunchKernelGGL((contract_kernel<false, 256, cbf16>), grid, dim3(256), lds, s, t, P.d_fa, P.d_fb, ly, lx, nox, mu, nz);
+    } else {
+        const cf32* t = static_cast<const cf32*>(P.d_khat);
+        if (contract_threads(mu) == 512)
+            hipLaunchKernelGGL((contract_kernel<false, 512, cf32>), grid, dim3(512), lds, s, t, P.d_fa, P.d_fb, ly, lx, nox, mu, nz);
+        else
+            hipLaunchKernelGGL((contract_kernel<false, 256, cf32>), grid, dim3(256), lds, s, t, P.d_fa, P.d_fb, ly, lx, nox, mu, nz);
+    }
     UFSS_HIP(hipGetLastError());
 }
 
@@ -569,12 +605,21 @@ void fft_adj_contract(const Plan& P, hipStream_t s) {
     const int lx = P.fft_lx, ly = P.fft_ly, nox = lx / 2 + 1, noy = ly / 2 + 1;
     const int mu = (int)P.ubins_h.size();
     const int nz = P.g.nz;
-    if (contract_threads(nz) == 512)
-        hipLaunchKernelGGL((contract_kernel<true, 512>), dim3(noy * nox), dim3(512), contract_lds(nz, mu), s,
-                           static_cast<const cf32*>(P.d_khat_t), P.d_fa, P.d_fb, ly, lx, nox, nz, mu);
-    else
-        hipLaunchKernelGGL((contract_kernel<true, 256>), dim3(noy * nox), dim3(256), contract_lds(nz, mu), s,
-                           static_cast<const cf32*>(P.d_khat_t), P.d_fa, P.d_fb, ly, lx, nox, nz, mu);
+    const size_t lds = contract_lds(nz, mu);
+    const dim3 grid(noy * nox);
+    if (P.dtype == UFSS_BF16) {
+        const cbf16* t = static_cast<const cbf16*>(P.d_khat_t);
+        if (contract_threads(nz) == 512)
+            hipLaunchKernelGGL((contract_kernel<true, 512, cbf16>), grid, dim3(512), lds, s, t, P.d_fa, P.d_fb, ly, lx, nox, nz, mu);
+        else
+            hipLaunchKernelGGL((contract_kernel<true, 256, cbf16>), grid, dim3(256), lds, s, t, P.d_fa, P.d_fb, ly, lx, nox, nz, mu);
+    } else {
+        const cf32* t = static_cast<const cf32*>(P.d_khat_t);
+        if (contract_threads(nz) == 512)
+            hipLaunchKernelGGL((contract_kernel<true, 512, cf32>), grid, dim3(512), lds, s, t, P.d_fa, P.d_fb, ly, lx, nox, nz, mu);
+        else
+            hipLaunchKernelGGL((contract_kernel<true, 256, cf32>), grid, dim3(256), lds, s, t, P.d_fa, P.d_fb, ly, lx, nox, nz, mu);
+    }
     UFSS_HIP(hipGetLastError());
 }
 

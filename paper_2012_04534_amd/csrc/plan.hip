@@ -406,8 +406,6 @@ Plan* plan_create(const ufss_geom* g, int m, int per_position, const int32_t* bi
     if (algo == UFSS_ALGO_PHASOR && g->dtype == UFSS_BF16)
         fail(UFSS_ERR_UNSUPPORTED, "the phasor path is FP32 only");
     if (algo == UFSS_ALGO_PHASOR && !per_position) algo = UFSS_ALGO_GEMM;
-    if (algo == UFSS_ALGO_FFT && g->dtype == UFSS_BF16)
-        fail(UFSS_ERR_UNSUPPORTED, "the transform path is FP32 only");
 
     Plan* P = new (std::nothrow) Plan();
     if (!P) fail(UFSS_ERR_OOM, "host allocation failed");
@@ -505,7 +503,7 @@ Plan* plan_create(const ufss_geom* g, int m, int per_position, const int32_t* bi
         if (P->adj_split > 1) P->d_gpart = dalloc<cf32>(*P, (size_t)P->adj_split * P->nvox);
         P->d_yraw = dalloc<cf32>(*P, (size_t)P->fwd_split * npos * mu);
         P->d_rop = dalloc<cf32>(*P, (size_t)npos * opw);
-        if (P->dtype == UFSS_BF16) P->d_xop = dalloc<cf32>(*P, (size_t)(P->nvox + 1) / 2 + 1);
+        if (algo == UFSS_ALGO_GEMM && P->dtype == UFSS_BF16) P->d_xop = dalloc<cf32>(*P, (size_t)(P->nvox + 1) / 2 + 1);
         if (algo == UFSS_ALGO_GEMM && P->dtype == UFSS_BF16) bf16_set_tables(*P, 1);
         if (algo == UFSS_ALGO_FFT) fft_setup(*P);
         P->part_cap = 65536;

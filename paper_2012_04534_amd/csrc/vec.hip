@@ -127,7 +127,7 @@ __global__ __launch_bounds__(128) void adj_pre_kernel(const cf32* __restrict__ r
 
 void launch_adjoint_pre(const Plan& P, const cf32* r, hipStream_t s) {
     const int w = (P.algo == UFSS_ALGO_PHASOR) ? P.m : (int)P.ubins_h.size();
-    if (P.dtype == UFSS_BF16)
+    if (P.dtype == UFSS_BF16 && P.algo == UFSS_ALGO_GEMM)     // BF16 operand of the BF16 GEMM
         hipLaunchKernelGGL(adj_pre_kernel<true>, dim3(P.npos), dim3(128), 0, s, r, P.m, w,
                            P.per_position, P.d_map, P.d_hsel, P.d_rop);
     else
