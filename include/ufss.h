@@ -60,9 +60,11 @@ extern "C" {
                                correlation as a cyclic lateral transform of size
                                L >= N + W per axis, contracted over depth / bins
                                with a precomputed transformed kernel table
-                               ((ly/2+1)(lx/2+1) nz (union bins) complex64, built
-                               in FP64); shared or per-position (over the union)
-                               subsets; FP32 only; no grouped (batched) launches */
+                               ((ly/2+1)(lx/2+1) nz (union bins) complex, built
+                               in FP64, stored FP32, or BF16 for BF16 plans with
+                               transforms and sums still in FP32); shared or
+                               per-position (over the union) subsets; no grouped
+                               (batched) launches */
 
 /* Scan and pulse geometry (SI units).  Paper Sec. II-A (grids, delay, pulse),
  * Sec. VI (Gabor pulse).  t0 = NaN selects the window that centres the delay
