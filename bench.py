@@ -39,8 +39,8 @@ PEAK_HBM = 8e12
 # source it was measured on; a changed source or another tiling reports null.
 TRAFFIC = {
     # 32 x 32 C-scan, FP32 union-GEMM, shipped tiling (profiles/cscan32_fp32_gemm_and_phasor.md)
-    "cscan32/gemm/forward/fs4-zs8-nw5-np2-zc8": {"bytes": 20.579e6, "sha": "367ebf0abcea85ec"},
-    "cscan32/gemm/adjoint/as12-np2-kc16": {"bytes": 32.304e6, "sha": "367ebf0abcea85ec"},
+    "cscan32/gemm/forward/fs4-zs8-nw5-np2-zc8": {"bytes": 20.579e6, "sha": "07604cb76073e38b"},
+    "cscan32/gemm/adjoint/as12-np2-kc16": {"bytes": 32.304e6, "sha": "07604cb76073e38b"},
     # transform-domain contraction (profiles/cscan32_fp32_transform.md, cscan64_fp32_transform.md):
     # the table once plus the transform rows in and out
     "cscan32/transform/forward/fs1-zs1-nw1-np0-zc0": {"bytes": 149.649e6, "sha": "130f6e5e72ba81e0"},
