@@ -46,3 +46,21 @@ def test_b_scan_offsets():
     x = W.cn((1, 9, 8), 4)
     np.testing.assert_allclose(bench.structured_forward(bench.structured_plan(g, bins, offs), x, offs),
                                O.apply_A(g, bins, x), rtol=1e-12, atol=1e-12)
+
+
+def test_traffic_entry_needs_the_measured_source(monkeypatch):
+    """A counted traffic figure is reported only for the kernel source it was
+    measured on (same SHA-256 prefix) and for the same tiling; otherwise null."""
+    key = next(iter(bench.TRAFFIC))
+    workload, algo, direction, _ = key.split("/")
+    entry = bench.TRAFFIC[key]
+    info = {"fwd_split": 4, "fwd_zsplit": 8, "fwd_waves": 5, "fwd_tile": 2, "fwd_chunk": 8,
+            "adj_split": 12, "adj_tile": 2, "adj_chunk": 16}
+    monkeypatch.setattr(bench, "tiling_key", lambda i, d: key.split("/")[3])
+    monkeypatch.setattr(bench, "source_sha", lambda rel: entry["sha"])
+    assert bench.traffic_bytes(workload, algo, direction, info) == int(entry["bytes"])
+    monkeypatch.setattr(bench, "source_sha", lambda rel: "0" * 16)
+    assert bench.traffic_bytes(workload, algo, direction, info) is None
+    monkeypatch.setattr(bench, "source_sha", lambda rel: entry["sha"])
+    monkeypatch.setattr(bench, "tiling_key", lambda i, d: "another-tiling")
+    assert bench.traffic_bytes(workload, algo, direction, info) is None
