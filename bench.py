@@ -47,9 +47,15 @@ TRAFFIC = {
     "cscan32/transform/adjoint/as1-np0-kc0": {"bytes": 149.147e6, "sha": "130f6e5e72ba81e0"},
     "cscan64/transform/forward/fs1-zs1-nw1-np0-zc0": {"bytes": 914.111e6, "sha": "130f6e5e72ba81e0"},
     "cscan64/transform/adjoint/as1-np0-kc0": {"bytes": 914.115e6, "sha": "130f6e5e72ba81e0"},
+    # the same with the BF16 table (profiles/cscan32_bf16_transform.md, cscan64_bf16_transform.md)
+    "cscan32/transform-bf16/adjoint/as1-np0-kc0": {"bytes": 79.961e6, "sha": "130f6e5e72ba81e0"},
+    "cscan32/transform-bf16/forward/fs1-zs1-nw1-np0-zc0": {"bytes": 80.372e6, "sha": "130f6e5e72ba81e0"},
+    "cscan64/transform-bf16/adjoint/as1-np0-kc0": {"bytes": 473.496e6, "sha": "130f6e5e72ba81e0"},
+    "cscan64/transform-bf16/forward/fs1-zs1-nw1-np0-zc0": {"bytes": 473.496e6, "sha": "130f6e5e72ba81e0"},
 }
 TRAFFIC_SRC = {"gemm": "paper_2012_04534_amd/csrc/gemm_f32.hip",
                "transform": "paper_2012_04534_amd/csrc/fft.hip",
+               "transform-bf16": "paper_2012_04534_amd/csrc/fft.hip",
                "gemm-bf16": "paper_2012_04534_amd/csrc/gemm_bf16.hip",
                "phasor": "paper_2012_04534_amd/csrc/phasor.hip"}
 
