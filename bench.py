@@ -494,6 +494,20 @@ def batch_rate(ufss, W, dev, iters=5):
             "a_plus_ah_tflops_incl_capture": round(16.0 * cm * iters / dt / 1e12, 2)}
 
 
+def gpu_clocks():
+    """Current GPU clocks (not locked on the box), read once with rocm-smi in a
+    child process; a failure is reported, never raised."""
+    import subprocess
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True,
+                           timeout=10)
+        data = json.loads(r.stdout)
+        card = next(iter(data.values()))
+        return {k: v for k, v in card.items() if "clock" in k.lower() or "clk" in k.lower()}
+    except Exception as e:  # noqa: BLE001 - reporting only
+        return {"unavailable": type(e).__name__}
+
+
 def bscan_fista(ufss, W, dev):
     """FISTA on the 32-position B-scan workload (shared bins, K = 200), the
     configuration the oracle's own FISTA is timed on: plan, L and solve times."""
@@ -700,6 +714,7 @@ def main():
         extras["batch64"] = batch_rate(ufss, W, dev)
         extras["bscan32_fista"] = bscan_fista(ufss, W, dev)
 
+    extras["gpu_clocks"] = gpu_clocks()
     result["extras"] = extras
     plan.close()
 
