@@ -375,6 +375,20 @@ int ufss_shrink_update(int64_t n, void* gamma, const void* g, void* a,
  * rule.  out HOST double.  Synchronises `stream`. */
 int ufss_absmax(int64_t n, const void* x, double* out, ufss_stream_t stream);
 
+/* ufss_shrink_update without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and errors as ufss_shrink_update.
+ * Its FP64 partials live in a fixed 41 KB device array that each GPU holds
+ * until the process ends: every n is accepted (the update's grid is capped), no
+ * hipMalloc / hipFree is called, and the library looks the array's address up
+ * once per device on the first call there.  Calls on one GPU share that array:
+ * calls that overlap on one GPU (several streams or host threads) race, so the
+ * caller serialises them.  Synchronises `stream` only if norms_out. */
+int ufss_shrink_update_noalloc(int64_t n, void* gamma, const void* g, void* a,
+                               double step, double thresh, double beta,
+                               const void* a_ref, double* norms_out,
+                               ufss_stream_t stream);
+
 /* Batched FISTA over n independent scans of uneven size (each with its own
  * plan), paper Alg. 1 applied to every scan.  Each phase of an iteration runs
  * as ONE grouped launch over all scans (forward GEMM, residual epilogue,

@@ -29,7 +29,7 @@ EXPORTED = [
     "ufss_plan_create", "ufss_plan_create_mixed", "ufss_plan_destroy",
     "ufss_plan_info_get", "ufss_forward", "ufss_adjoint", "ufss_lipschitz", "ufss_fista",
     "ufss_fista_backtracking",
-    "ufss_shrink_update", "ufss_absmax", "ufss_time_kernel", "ufss_fista_batched",
+    "ufss_shrink_update", "ufss_shrink_update_noalloc", "ufss_absmax", "ufss_time_kernel", "ufss_fista_batched",
     "ufss_autotune", "ufss_plan_set_tiling", "ufss_plan_kernel_timing", "ufss_plan_kernel_times", "ufss_plan_set_phasor_tables", "ufss_unrolled_create", "ufss_unrolled_destroy", "ufss_unrolled_params",
     "ufss_unrolled_forward", "ufss_unrolled_grad", "ufss_unrolled_train_step",
     "ufss_unrolled_save", "ufss_unrolled_load",
@@ -128,6 +128,7 @@ def lib():
             "ufss_fista": ([P, P, D, D, I32, D, I32, P, P, ctypes.POINTER(FistaStats),
                             ctypes.POINTER(FistaState), P], ctypes.c_int),
             "ufss_shrink_update": ([I64, P, P, P, D, D, D, P, P, P], ctypes.c_int),
+            "ufss_shrink_update_noalloc": ([I64, P, P, P, D, D, D, P, P, P], ctypes.c_int),
             "ufss_absmax": ([I64, P, ctypes.POINTER(D), P], ctypes.c_int),
             "ufss_time_kernel": ([P, I32, I32, ctypes.POINTER(D), P], ctypes.c_int),
             "ufss_fista_batched": ([I32, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
@@ -415,6 +416,21 @@ def ufss_shrink_update(gamma, g, a, step, thresh, beta, a_ref=None, stream=None)
                                     float(step), float(thresh), float(beta),
                                     _ptr(a_ref, "a_ref") if a_ref is not None else None,
                                     out.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+    return out
+
+
+def ufss_shrink_update_noalloc(gamma, g, a, step, thresh, beta, a_ref=None, stream=None,
+                               want_norms=True):
+    """ufss_shrink_update without device allocation; returns the 5 FP64 norms
+    (None when ``want_norms`` is False: then nothing synchronises)."""
+    n = a.numel()
+    for t, nm in ((gamma, "gamma"), (g, "g")):
+        _numel_check(t, n, nm)
+    out = np.zeros(5) if want_norms else None
+    _check(lib().ufss_shrink_update_noalloc(
+        n, _ptr(gamma, "gamma"), _ptr(g, "g"), _ptr(a, "a"), float(step), float(thresh),
+        float(beta), _ptr(a_ref, "a_ref") if a_ref is not None else None,
+        out.ctypes.data_as(ctypes.c_void_p) if out is not None else None, _stream(stream)))
     return out
 
 
