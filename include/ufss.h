@@ -49,9 +49,9 @@ extern "C" {
 #define UFSS_BF16 1   /* BF16 phasors and operands, FP32 accumulation           */
 
 /* ---- operator algorithm -------------------------------------------------- */
-#define UFSS_ALGO_AUTO   0  /* GEMM (per-position subsets run over their union:
-                               measured faster than the phasor path even at
-                               one bin per position)                          */
+#define UFSS_ALGO_AUTO   0  /* GEMM, except FP32 per-position subsets whose
+                               union holds at least 5 times the bins of one
+                               position: phasor path (measured faster there)  */
 #define UFSS_ALGO_GEMM   1  /* windowed complex GEMM over (offset, depth) on MFMA;
                                per-position subsets run over their union of bins
                                and are gathered / scattered                    */
@@ -406,6 +406,33 @@ int ufss_shrink_update_noalloc(int64_t n, void* gamma, const void* g, void* a,
 int ufss_fista_batched(int32_t n, const ufss_plan_t* plans, const void* const* ys,
                        void* const* xs, const double* lambdas, const double* Ls,
                        int32_t iters, double* res_out, ufss_stream_t stream);
+
+/* Persistent batch (paper Alg. 1 on every scan of an uneven batch): the same
+ * grouped launches as ufss_fista_batched, with the start state (gamma = x,
+ * ||gamma||_1) and `iters` iterations captured ONCE into a hipGraph at
+ * creation; every ufss_batch_run replays that graph on `stream` (no capture,
+ * no host round trip inside the iterations) from the current contents of the
+ * xs buffers (a_0) with the current contents of the ys buffers.  The batch
+ * keeps the buffer pointers given at creation; the caller keeps them alive
+ * and may overwrite their contents between runs (new scans of the same
+ * shapes).  While a batch exists its plans are held: ufss_plan_destroy,
+ * ufss_plan_set_tiling, ufss_autotune and ufss_plan_set_phasor_tables on
+ * them fail with UFSS_ERR_INVALID_ARG, and a plan can be held by one batch.
+ * Arguments as ufss_fista_batched; lambdas with the mu rule are resolved from
+ * the ys contents at creation and again by ufss_batch_set_lambdas (they are
+ * read from device memory at run time, so no new capture is needed).
+ * create: synchronises `stream`; out HOST. */
+typedef struct ufss_batch_s* ufss_batch_t;
+int ufss_batch_create(int32_t n, const ufss_plan_t* plans, const void* const* ys,
+                      void* const* xs, const double* lambdas, const double* Ls,
+                      int32_t iters, ufss_stream_t stream, ufss_batch_t* out);
+/* Replays the captured iterations; res_out / lambdas_out HOST double [n] or
+ * NULL (final ||A gamma - y|| and the lambda used, per scan).  Synchronises
+ * `stream`; UFSS_ERR_DIVERGED if any scan diverges. */
+int ufss_batch_run(ufss_batch_t batch, double* res_out, double* lambdas_out, ufss_stream_t stream);
+/* New lambdas (HOST double [n], same convention as at creation). */
+int ufss_batch_set_lambdas(ufss_batch_t batch, const double* lambdas, ufss_stream_t stream);
+int ufss_batch_destroy(ufss_batch_t batch);
 
 /* Autotuner for the GEMM path: times candidate tilings (d_y and depth splits,
  * waves per workgroup, sub-tiles per wave, BF16 wave rows, then the smaller

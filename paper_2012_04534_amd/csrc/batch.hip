@@ -233,9 +233,79 @@ int launch_absmax(int64_t n, const cf32* x, double* part, hipStream_t s);
 void launch_reduce_max(const double* part, int nblk, double* out, hipStream_t s);
 void op_forward(Plan& P, const cf32* x, cf32* y, const cf32* ymeas, double* res2_out, hipStream_t s);
 
-int fista_batched(int n, Plan* const* plans, const cf32* const* ys, cf32* const* xs,
-                  const double* lambdas, const double* Ls, int iters, hipStream_t stream,
-                  double* res_out) {
+// Persistent batch: descriptors built and K iterations captured in one hipGraph
+// at creation; every run replays that graph (no capture, no host round trip
+// inside the K iterations).  A run starts from the caller's x buffers (gamma =
+// x and ||gamma||_1 are computed inside the graph), so replays with new
+// measurements in the same y buffers solve the new problems.  The descriptors
+// live in device memory and are read at run time: new lambdas need no capture.
+struct BatchRun {
+    Batch B;
+    std::vector<Plan*> plans;
+    std::vector<const cf32*> ys;
+    std::vector<cf32*> xs;
+    std::vector<double> L;
+    std::vector<ScanDesc> sd;
+    double* d_stats = nullptr;      // [n][iters][4], owned by the batch
+    int n = 0, iters = 0;
+    bool pinned = false;            // the plans' batch_refs were raised
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+// x -> gamma and FP64 partials of ||gamma||_1 (in part + 8192, one column)
+__global__ __launch_bounds__(kT) void g_init(const ScanDesc* __restrict__ d, const int2* __restrict__ blk) {
+    __shared__ double red[1][kT / 64];
+    const int2 sb = blk[blockIdx.x];
+    const ScanDesc& a = d[sb.x];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)sb.y * kT + threadIdx.x; i < a.nvox; i += (int64_t)a.nb_upd * kT) {
+        const cf32 v = a.x[i];
+        a.gamma[i] = v;
+        acc += sqrt((double)v.re * v.re + (double)v.im * v.im);
+    }
+    wave_block_sum(&acc, 1, a.part + 8192, sb.y, red);
+}
+
+// one block per scan: ||gamma_0||_1 into scal[16], in fixed order
+__global__ __launch_bounds__(kT) void g_init_finish(const ScanDesc* __restrict__ d) {
+    __shared__ double red[kT];
+    const ScanDesc& a = d[blockIdx.x];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < a.nb_upd; b += kT) s += a.part[8192 + b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = kT / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.scal[16] = red[0];
+}
+
+static double resolve_lambda(Plan& P, const cf32* y, double lam, hipStream_t stream) {
+    if (lam == 0 || std::isnan(lam)) fail(UFSS_ERR_INVALID_ARG, "lambda must be non-zero");
+    if (lam > 0) return lam;
+    op_adjoint(P, y, P.d_g, stream);
+    int nb = launch_absmax(P.nvox, P.d_g, P.d_part, stream);
+    launch_reduce_max(P.d_part, nb, P.d_scalars + 40, stream);
+    double mx = 0;
+    UFSS_HIP(hipMemcpyAsync(&mx, P.d_scalars + 40, 8, hipMemcpyDeviceToHost, stream));
+    UFSS_HIP(hipStreamSynchronize(stream));
+    return -lam * mx;
+}
+
+static void batch_free(BatchRun* R) {
+    if (!R) return;
+    if (R->exec) (void)hipGraphExecDestroy(R->exec);
+    if (R->graph) (void)hipGraphDestroy(R->graph);
+    free_batch(R->B);
+    if (R->pinned)
+        for (Plan* P : R->plans) --P->batch_refs;
+    delete R;
+}
+
+BatchRun* batch_create(int n, Plan* const* plans, const cf32* const* ys, cf32* const* xs,
+                       const double* lambdas, const double* Ls, int iters, hipStream_t stream) {
     if (n < 1) fail(UFSS_ERR_INVALID_ARG, "n must be >= 1");
     if (iters < 1) fail(UFSS_ERR_INVALID_ARG, "iters must be >= 1");
     if (!plans || !ys || !xs || !lambdas || !Ls) fail(UFSS_ERR_INVALID_ARG, "NULL array");
@@ -247,39 +317,38 @@ int fista_batched(int n, Plan* const* plans, const cf32* const* ys, cf32* const*
             fail(UFSS_ERR_UNSUPPORTED, "batched FISTA does not take a Gaussian beam");
         if (plans[i]->mix)
             fail(UFSS_ERR_UNSUPPORTED, "batched FISTA does not take mixed plans");
+        if (plans[i]->batch_refs > 0)
+            fail(UFSS_ERR_INVALID_ARG, "a plan is already held by another persistent batch");
         for (int j = 0; j < i; ++j)
             if (plans[j] == plans[i]) fail(UFSS_ERR_INVALID_ARG, "a plan appears twice in the batch");
     }
-    Batch B;
+    BatchRun* R = new BatchRun();
+    Batch& B = R->B;
     try {
+        R->n = n;
+        R->iters = iters;
+        R->plans.assign(plans, plans + n);
+        R->ys.assign(ys, ys + n);
+        R->xs.assign(xs, xs + n);
         // lambda (mu rule) and L per scan, resolved before capture
-        std::vector<double> lam(n), L(n);
+        std::vector<double> lam(n);
+        R->L.resize(n);
         for (int i = 0; i < n; ++i) {
             Plan& P = *plans[i];
-            L[i] = Ls[i] > 0 ? Ls[i] : P.lipschitz;
-            if (!(L[i] > 0)) fail(UFSS_ERR_INVALID_ARG, "scan without a Lipschitz constant");
-            lam[i] = lambdas[i];
-            if (lam[i] == 0 || std::isnan(lam[i])) fail(UFSS_ERR_INVALID_ARG, "lambda must be non-zero");
-            if (lam[i] < 0) {
-                op_adjoint(P, ys[i], P.d_g, stream);
-                int nb = launch_absmax(P.nvox, P.d_g, P.d_part, stream);
-                launch_reduce_max(P.d_part, nb, P.d_scalars + 40, stream);
-                double mx = 0;
-                UFSS_HIP(hipMemcpyAsync(&mx, P.d_scalars + 40, 8, hipMemcpyDeviceToHost, stream));
-                UFSS_HIP(hipStreamSynchronize(stream));
-                lam[i] = -lam[i] * mx;
-            }
-            if (P.stats_cap < iters) {
-                if (P.d_stats) UFSS_HIP(hipFree(P.d_stats));
-                P.d_stats = nullptr;
-                P.stats_cap = 0;
-                UFSS_HIP(hipMalloc(&P.d_stats, (size_t)iters * 4 * sizeof(double)));
-                P.stats_cap = iters;
-            }
+            R->L[i] = Ls[i] > 0 ? Ls[i] : P.lipschitz;
+            if (!(R->L[i] > 0)) fail(UFSS_ERR_INVALID_ARG, "scan without a Lipschitz constant");
+            lam[i] = resolve_lambda(P, ys[i], lambdas[i], stream);
+        }
+        {
+            void* p = nullptr;
+            UFSS_HIP(hipMalloc(&p, (size_t)n * iters * 4 * sizeof(double)));
+            B.owned.push_back(p);
+            R->d_stats = static_cast<double*>(p);
         }
         // descriptors
-        std::vector<ScanDesc> sd(n);
-        std::vector<int2> bpost, bpre, bvox, bupd, bbf;
+        std::vector<ScanDesc>& sd = R->sd;
+        sd.resize(n);
+        std::vector<int2> bpost, bpre, bupd, bbf;
         auto blocks_for = [](int64_t cnt) { return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (cnt + kT - 1) / kT)); };
         for (int i = 0; i < n; ++i) {
             Plan& P = *plans[i];
@@ -298,7 +367,7 @@ int fista_batched(int n, Plan* const* plans, const cf32* const* ys, cf32* const*
             a.hsel = P.d_hsel;
             a.part = P.d_part;
             a.scal = P.d_scalars;
-            a.stats = P.d_stats;
+            a.stats = R->d_stats + (size_t)i * iters * 4;
             a.npos = P.npos;
             a.nvox = P.nvox;
             a.m = P.m;
@@ -308,8 +377,8 @@ int fista_batched(int n, Plan* const* plans, const cf32* const* ys, cf32* const*
             a.per_pos = P.per_position;
             a.bf16 = P.dtype == UFSS_BF16;
             a.opw = a.mu;
-            a.step = (float)(1.0 / L[i]);
-            a.thresh = (float)(lam[i] / L[i]);
+            a.step = (float)(1.0 / R->L[i]);
+            a.thresh = (float)(lam[i] / R->L[i]);
             a.lam = lam[i];
             a.nb_post = blocks_for(P.npos * (int64_t)P.m);
             a.nb_upd = blocks_for(P.nvox);
@@ -359,29 +428,16 @@ int fista_batched(int n, Plan* const* plans, const cf32* const* ys, cf32* const*
             B.gblk[kind] = upload_vec(B, blk);
             B.gcount[kind] = (int)blk.size();
         }
-        // initial state: gamma = x, ||gamma||_1
-        for (int i = 0; i < n; ++i) {
-            Plan& P = *plans[i];
-            launch_copy(P.nvox, xs[i], P.d_gamma, stream);
-            int nb = launch_norm2(P.nvox, P.d_gamma, P.d_part, stream);
-            launch_reduce(P.d_part, nb, 2, P.d_scalars + 20, stream);
-            UFSS_HIP(hipMemcpyAsync(P.d_scalars + 16, P.d_scalars + 21, 8, hipMemcpyDeviceToDevice, stream));
-        }
         UFSS_HIP(hipStreamSynchronize(stream));
 
-        // capture K iterations
+        // capture: start state, then K iterations
         hipStream_t cs;
         UFSS_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-        hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
-        auto cleanup = [&]() {
-            if (exec) (void)hipGraphExecDestroy(exec);
-            if (graph) (void)hipGraphDestroy(graph);
-            (void)hipStreamDestroy(cs);
-        };
         try {
             UFSS_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
             const ScanDesc* D = static_cast<const ScanDesc*>(B.d_desc);
+            hipLaunchKernelGGL(g_init, dim3(B.n_upd), dim3(kT), 0, cs, D, B.blk_upd);
+            hipLaunchKernelGGL(g_init_finish, dim3(n), dim3(kT), 0, cs, D);
             double t = 1.0;
             for (int k = 0; k < iters; ++k) {
                 const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
@@ -401,10 +457,8 @@ int fista_batched(int n, Plan* const* plans, const cf32* const* ys, cf32* const*
                 hipLaunchKernelGGL(g_update, dim3(B.n_upd), dim3(kT), 0, cs, D, B.blk_upd, beta);
                 hipLaunchKernelGGL(g_finish, dim3(n), dim3(kT), 0, cs, D, k);
             }
-            UFSS_HIP(hipStreamEndCapture(cs, &graph));
-            UFSS_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-            UFSS_HIP(hipGraphLaunch(exec, stream));
-            UFSS_HIP(hipStreamSynchronize(stream));
+            UFSS_HIP(hipStreamEndCapture(cs, &R->graph));
+            UFSS_HIP(hipGraphInstantiate(&R->exec, R->graph, nullptr, nullptr, 0));
         } catch (...) {
             hipStreamCaptureStatus st;
             if (hipStreamIsCapturing(cs, &st) == hipSuccess && st == hipStreamCaptureStatusActive) {
@@ -412,25 +466,65 @@ int fista_batched(int n, Plan* const* plans, const cf32* const* ys, cf32* const*
                 (void)hipStreamEndCapture(cs, &g2);
                 if (g2) (void)hipGraphDestroy(g2);
             }
-            cleanup();
+            (void)hipStreamDestroy(cs);
             throw;
         }
-        cleanup();
-        // divergence check and final residuals
-        for (int i = 0; i < n; ++i) {
-            std::vector<double> h((size_t)iters * 4);
-            UFSS_HIP(hipMemcpy(h.data(), plans[i]->d_stats, h.size() * sizeof(double), hipMemcpyDeviceToHost));
-            if (res_out) res_out[i] = h[4 * (iters - 1) + 1];
-            for (int k = 0; k < iters; ++k)
-                if (!std::isfinite(h[4 * k]) || !std::isfinite(h[4 * k + 1]) || h[4 * k + 1] > 1e6 * h[1] + 1e-300)
-                    fail(UFSS_ERR_DIVERGED, "scan " + std::to_string(i) + " diverged at iteration " +
-                                                std::to_string(k));
-        }
+        UFSS_HIP(hipStreamDestroy(cs));
+        for (Plan* P : R->plans) ++P->batch_refs;
+        R->pinned = true;
     } catch (...) {
-        free_batch(B);
+        batch_free(R);
         throw;
     }
-    free_batch(B);
+    return R;
+}
+
+void batch_set_lambdas(BatchRun& R, const double* lambdas, hipStream_t stream) {
+    if (!lambdas) fail(UFSS_ERR_INVALID_ARG, "lambdas is NULL");
+    std::vector<double> lam(R.n);
+    for (int i = 0; i < R.n; ++i) lam[i] = resolve_lambda(*R.plans[i], R.ys[i], lambdas[i], stream);
+    for (int i = 0; i < R.n; ++i) {
+        R.sd[i].lam = lam[i];
+        R.sd[i].thresh = (float)(lam[i] / R.L[i]);
+    }
+    UFSS_HIP(hipMemcpyAsync(R.B.d_desc, R.sd.data(), R.sd.size() * sizeof(ScanDesc),
+                            hipMemcpyHostToDevice, stream));
+    UFSS_HIP(hipStreamSynchronize(stream));
+}
+
+void batch_run(BatchRun& R, double* res_out, double* lambdas_out, hipStream_t stream) {
+    UFSS_HIP(hipGraphLaunch(R.exec, stream));
+    std::vector<double> h((size_t)R.n * R.iters * 4);
+    UFSS_HIP(hipMemcpyAsync(h.data(), R.d_stats, h.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+    UFSS_HIP(hipStreamSynchronize(stream));
+    for (int i = 0; i < R.n; ++i) {
+        const double* st = h.data() + (size_t)i * R.iters * 4;
+        if (res_out) res_out[i] = st[4 * (R.iters - 1) + 1];
+        if (lambdas_out) lambdas_out[i] = R.sd[i].lam;
+        for (int k = 0; k < R.iters; ++k)
+            if (!std::isfinite(st[4 * k]) || !std::isfinite(st[4 * k + 1]) || st[4 * k + 1] > 1e6 * st[1] + 1e-300)
+                fail(UFSS_ERR_DIVERGED, "scan " + std::to_string(i) + " diverged at iteration " +
+                                            std::to_string(k));
+    }
+}
+
+void batch_destroy(BatchRun* R) {
+    if (!R) fail(UFSS_ERR_INVALID_ARG, "batch is NULL");
+    UFSS_HIP(hipDeviceSynchronize());
+    batch_free(R);
+}
+
+int fista_batched(int n, Plan* const* plans, const cf32* const* ys, cf32* const* xs,
+                  const double* lambdas, const double* Ls, int iters, hipStream_t stream,
+                  double* res_out) {
+    BatchRun* R = batch_create(n, plans, ys, xs, lambdas, Ls, iters, stream);
+    try {
+        batch_run(*R, res_out, nullptr, stream);
+    } catch (...) {
+        batch_free(R);
+        throw;
+    }
+    batch_free(R);
     return UFSS_OK;
 }
 

@@ -31,6 +31,12 @@ int phasor_forward_blocks(const Plan& P);
 int fista_batched(int n, Plan* const* plans, const cf32* const* ys, cf32* const* xs,
                   const double* lambdas, const double* Ls, int iters, hipStream_t stream,
                   double* res_out);
+struct BatchRun;
+BatchRun* batch_create(int n, Plan* const* plans, const cf32* const* ys, cf32* const* xs,
+                       const double* lambdas, const double* Ls, int iters, hipStream_t stream);
+void batch_set_lambdas(BatchRun& R, const double* lambdas, hipStream_t stream);
+void batch_run(BatchRun& R, double* res_out, double* lambdas_out, hipStream_t stream);
+void batch_destroy(BatchRun* R);
 int autotune(Plan& P, const char* cache_path, int flags, hipStream_t s, int32_t* fs_out,
              int32_t* as_out);
 struct Net;
@@ -431,6 +437,15 @@ static Plan* as_plan(ufss_plan_t p) {
     return reinterpret_cast<Plan*>(p);
 }
 
+// A persistent batch's captured graph holds pointers into the plan's workspace:
+// calls that free or reallocate it are refused until the batch is destroyed.
+static Plan* as_unpinned_plan(ufss_plan_t p) {
+    Plan* P = as_plan(p);
+    if (P->batch_refs > 0)
+        ufss::fail(UFSS_ERR_INVALID_ARG, "plan is held by a persistent batch (destroy the batch first)");
+    return P;
+}
+
 extern "C" {
 
 const char* ufss_last_error(void) { return ufss::last_error(); }
@@ -498,7 +513,7 @@ int ufss_plan_create_mixed(const ufss_geom* g, int32_t m, int32_t per_position, 
 
 int ufss_plan_destroy(ufss_plan_t plan) {
     UFSS_GUARD_BEGIN
-    ufss::plan_destroy(as_plan(plan));
+    ufss::plan_destroy(as_unpinned_plan(plan));
     UFSS_GUARD_END
 }
 
@@ -601,10 +616,48 @@ int ufss_fista_batched(int32_t n, const ufss_plan_t* plans, const void* const* y
     UFSS_GUARD_END
 }
 
+static ufss::BatchRun* as_batch(ufss_batch_t b) {
+    if (!b) ufss::fail(UFSS_ERR_INVALID_ARG, "batch is NULL");
+    return reinterpret_cast<ufss::BatchRun*>(b);
+}
+
+int ufss_batch_create(int32_t n, const ufss_plan_t* plans, const void* const* ys, void* const* xs,
+                      const double* lambdas, const double* Ls, int32_t iters, ufss_stream_t stream,
+                      ufss_batch_t* out) {
+    UFSS_GUARD_BEGIN
+    if (!out) ufss::fail(UFSS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !plans || !ys || !xs) ufss::fail(UFSS_ERR_INVALID_ARG, "bad batch arrays");
+    std::vector<Plan*> ps(n);
+    for (int i = 0; i < n; ++i) ps[i] = as_plan(plans[i]);
+    *out = reinterpret_cast<ufss_batch_t>(ufss::batch_create(
+        n, ps.data(), reinterpret_cast<const ufss::cf32* const*>(ys),
+        reinterpret_cast<ufss::cf32* const*>(xs), lambdas, Ls, iters, static_cast<hipStream_t>(stream)));
+    UFSS_GUARD_END
+}
+
+int ufss_batch_run(ufss_batch_t batch, double* res_out, double* lambdas_out, ufss_stream_t stream) {
+    UFSS_GUARD_BEGIN
+    ufss::batch_run(*as_batch(batch), res_out, lambdas_out, static_cast<hipStream_t>(stream));
+    UFSS_GUARD_END
+}
+
+int ufss_batch_set_lambdas(ufss_batch_t batch, const double* lambdas, ufss_stream_t stream) {
+    UFSS_GUARD_BEGIN
+    ufss::batch_set_lambdas(*as_batch(batch), lambdas, static_cast<hipStream_t>(stream));
+    UFSS_GUARD_END
+}
+
+int ufss_batch_destroy(ufss_batch_t batch) {
+    UFSS_GUARD_BEGIN
+    ufss::batch_destroy(as_batch(batch));
+    UFSS_GUARD_END
+}
+
 int ufss_autotune(ufss_plan_t plan, const char* cache_path, int32_t flags, int32_t* fwd_split_out,
                   int32_t* adj_split_out, ufss_stream_t stream) {
     UFSS_GUARD_BEGIN
-    Plan* P = as_plan(plan);
+    Plan* P = as_unpinned_plan(plan);
     ufss::autotune(*P, cache_path, flags, static_cast<hipStream_t>(stream), fwd_split_out,
                    adj_split_out);
     UFSS_GUARD_END
@@ -612,7 +665,7 @@ int ufss_autotune(ufss_plan_t plan, const char* cache_path, int32_t flags, int32
 
 int ufss_plan_set_tiling(ufss_plan_t plan, const ufss_tiling* t) {
     UFSS_GUARD_BEGIN
-    Plan* P = as_plan(plan);
+    Plan* P = as_unpinned_plan(plan);
     if (!t) ufss::fail(UFSS_ERR_INVALID_ARG, "tiling is NULL");
     if (P->algo != UFSS_ALGO_GEMM) ufss::fail(UFSS_ERR_UNSUPPORTED, "tiling applies to GEMM plans only");
     auto in = [](int v, int hi) { return v >= 0 && v <= hi; };
@@ -645,7 +698,7 @@ int ufss_plan_set_tiling(ufss_plan_t plan, const ufss_tiling* t) {
 
 int ufss_plan_set_phasor_tables(ufss_plan_t plan, int32_t enable, int32_t* active_out) {
     UFSS_GUARD_BEGIN
-    Plan* P = as_plan(plan);
+    Plan* P = as_unpinned_plan(plan);
     if (P->algo != UFSS_ALGO_GEMM || P->dtype != UFSS_BF16)
         ufss::fail(UFSS_ERR_UNSUPPORTED, "phasor tables apply to BF16 GEMM plans only");
     ufss::bf16_set_tables(*P, enable != 0);

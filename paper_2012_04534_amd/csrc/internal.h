@@ -122,6 +122,7 @@ struct Plan {
     cf32* d_bt = nullptr;
     double* d_bt_scal = nullptr;
     int stats_cap = 0;
+    int batch_refs = 0;            // persistent batches whose graph holds this plan's workspace
     double lipschitz = 0.0;
     int64_t ws_bytes = 0;
     hipStream_t cap_stream = nullptr;

@@ -30,6 +30,7 @@ EXPORTED = [
     "ufss_plan_info_get", "ufss_forward", "ufss_adjoint", "ufss_lipschitz", "ufss_fista",
     "ufss_fista_backtracking",
     "ufss_shrink_update", "ufss_shrink_update_noalloc", "ufss_absmax", "ufss_time_kernel", "ufss_fista_batched",
+    "ufss_batch_create", "ufss_batch_run", "ufss_batch_set_lambdas", "ufss_batch_destroy",
     "ufss_autotune", "ufss_plan_set_tiling", "ufss_plan_kernel_timing", "ufss_plan_kernel_times", "ufss_plan_set_phasor_tables", "ufss_unrolled_create", "ufss_unrolled_destroy", "ufss_unrolled_params",
     "ufss_unrolled_forward", "ufss_unrolled_grad", "ufss_unrolled_train_step",
     "ufss_unrolled_save", "ufss_unrolled_load",
@@ -104,6 +105,13 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libufss.so is not built (run __graft_entry__.build()); "
                                "there is no fallback path")
+        # torch ships its own HIP runtime: loaded first, it also serves this
+        # library (one runtime per process); loaded second, it finds the GPU
+        # already taken by the other runtime
+        try:
+            import torch  # noqa: F401
+        except ImportError:  # pragma: no cover
+            pass
         L = ctypes.CDLL(LIB_PATH)
         P, I32, I64, D, U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64
         sig = {
@@ -134,6 +142,12 @@ def lib():
             "ufss_fista_batched": ([I32, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
                                     ctypes.POINTER(D), ctypes.POINTER(D), I32, ctypes.POINTER(D), P],
                                    ctypes.c_int),
+            "ufss_batch_create": ([I32, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
+                                   ctypes.POINTER(D), ctypes.POINTER(D), I32, P, ctypes.POINTER(P)],
+                                  ctypes.c_int),
+            "ufss_batch_run": ([P, ctypes.POINTER(D), ctypes.POINTER(D), P], ctypes.c_int),
+            "ufss_batch_set_lambdas": ([P, ctypes.POINTER(D), P], ctypes.c_int),
+            "ufss_batch_destroy": ([P], ctypes.c_int),
             "ufss_autotune": ([P, ctypes.c_char_p, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), P],
                               ctypes.c_int),
             "ufss_plan_set_tiling": ([P, ctypes.POINTER(Tiling)], ctypes.c_int),
@@ -466,6 +480,57 @@ def ufss_fista_batched(plans, ys, xs, lambdas, Ls, iters, stream=None):
     res = (ctypes.c_double * n)()
     _check(lib().ufss_fista_batched(n, hp, yp, xp, lam, Lc, int(iters), res, _stream(stream)))
     return np.array(list(res))
+
+
+class Batch:
+    """Owning handle of a persistent batch (ufss_batch_create / _run /
+    _set_lambdas / _destroy): the iterations are captured once and replayed by
+    every run.  Keeps references to the plans and buffers it was built on."""
+
+    def __init__(self, plans, ys, xs, lambdas, Ls, iters, stream=None):
+        n = len(plans)
+        if not (len(ys) == len(xs) == len(lambdas) == len(Ls) == n):
+            raise ValueError("plans, ys, xs, lambdas and Ls must have the same length")
+        for p, y, x in zip(plans, ys, xs):
+            _numel_check(x, p.nvox, "x")
+            _numel_check(y, p.nmeas, "y")
+        PA = ctypes.c_void_p * n
+        hp = PA(*[p.handle.value for p in plans])
+        yp = PA(*[_ptr(y, "y").value for y in ys])
+        xp = PA(*[_ptr(x, "x").value for x in xs])
+        lam = (ctypes.c_double * n)(*[float(v) for v in lambdas])
+        Lc = (ctypes.c_double * n)(*[float(v) for v in Ls])
+        h = ctypes.c_void_p()
+        _check(lib().ufss_batch_create(n, hp, yp, xp, lam, Lc, int(iters), _stream(stream),
+                                       ctypes.byref(h)))
+        self.handle = h
+        self.n = n
+        self.iters = int(iters)
+        self._keep = (list(plans), list(ys), list(xs))
+
+    def run(self, stream=None):
+        """Replay; returns (final residual norms, lambdas used) per scan."""
+        res = (ctypes.c_double * self.n)()
+        lam = (ctypes.c_double * self.n)()
+        _check(lib().ufss_batch_run(self.handle, res, lam, _stream(stream)))
+        return np.array(list(res)), np.array(list(lam))
+
+    def set_lambdas(self, lambdas, stream=None):
+        if len(lambdas) != self.n:
+            raise ValueError("expected %d lambdas" % self.n)
+        lam = (ctypes.c_double * self.n)(*[float(v) for v in lambdas])
+        _check(lib().ufss_batch_set_lambdas(self.handle, lam, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(lib().ufss_batch_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def ufss_autotune(plan, cache_path=None, use_cache=True, write_cache=True, stream=None, quick=False):

@@ -1,5 +1,6 @@
-"""GPU tests of batched FISTA (one grouped launch per phase, graph-captured)
-and of the split-K autotuner."""
+"""GPU tests of batched FISTA (one grouped launch per phase, graph-captured),
+of the persistent batch (captured once, replayed), of the 64-scan uneven batch
+at its own shapes, and of the split-K autotuner."""
 import json
 import os
 
@@ -51,7 +52,8 @@ def small_batch():
 def test_batched_matches_single_scan_fista(dev):
     u = ufss()
     specs, dts = small_batch()
-    assert len({s["geom"]["ny"] == 1 for s in specs}) == 2 or True
+    assert {s["geom"]["ny"] == 1 for s in specs} == {True, False}       # B- and C-scans
+    assert {s["per_position"] for s in specs} == {True, False}           # both bin modes
     scans = [make_scan(u, s, dt, dev) for s, dt in zip(specs, dts)]
     Ls = [u.ufss_lipschitz(p, max_iters=100, rtol=1e-5) for p, _, _, _ in scans]
     lams = []
@@ -163,3 +165,126 @@ def test_autotune_cache_and_correctness(dev, tmp_path):
         p.close()
         p2.close()
     assert os.path.exists(cache)
+
+
+def test_persistent_batch_replays_new_data_and_holds_plans(dev):
+    """ufss_batch_*: the captured iterations replayed; every replay starts from
+    the x buffers' contents and reads the y buffers' contents, so replays equal
+    single-scan FISTA on whatever the buffers hold; plans are held meanwhile."""
+    u = ufss()
+    specs, dts = small_batch()
+    scans = [make_scan(u, s, dt, dev) for s, dt in zip(specs, dts)]
+    plans = [sc[0] for sc in scans]
+    ys = [sc[3] for sc in scans]
+    Ls = [u.ufss_lipschitz(p, max_iters=100, rtol=1e-5) for p in plans]
+    xs = [torch.zeros(p.nvox, dtype=torch.complex64, device=dev) for p in plans]
+    K = 15
+    b = u.Batch(plans, ys, xs, [-0.1] * len(plans), Ls, K)
+    _, lam1 = b.run()
+    first = [x.clone() for x in xs]
+    for x in xs:
+        x.zero_()
+    _, lam2 = b.run()
+    assert np.array_equal(lam1, lam2)
+    for a, c in zip(first, xs):
+        assert torch.equal(a, c)                      # replay is bitwise repeatable
+    tol = lambda i: 1e-4 if dts[i] else 1e-5
+    for i, (p, y) in enumerate(zip(plans, ys)):
+        x1 = torch.zeros(p.nvox, dtype=torch.complex64, device=dev)
+        st = u.ufss_fista(p, y, u.lambda_from_mu(0.1), Ls[i], K, x1)
+        assert st["lambda"] == pytest.approx(lam1[i], rel=1e-6)
+        e = (torch.linalg.norm(xs[i] - x1) / torch.linalg.norm(x1)).item()
+        assert e < tol(i), (i, e)
+    # warm start: a replay continues from the current x (momentum restarted)
+    start = [x.clone() for x in xs]
+    b.run()
+    for i, (p, y) in enumerate(zip(plans, ys)):
+        x1 = start[i].clone()
+        u.ufss_fista(p, y, lam1[i], Ls[i], K, x1)
+        e = (torch.linalg.norm(xs[i] - x1) / torch.linalg.norm(x1)).item()
+        assert e < tol(i), (i, e)
+    # new measurements in the same buffers, lambdas re-resolved by the mu rule
+    for i, y in enumerate(ys):
+        y.copy_(torch.from_numpy(W.cn(tuple(y.shape), 500 + i).astype(np.complex64)).to(dev))
+    b.set_lambdas([-0.1] * len(plans))
+    for x in xs:
+        x.zero_()
+    _, lam3 = b.run()
+    assert not np.allclose(lam3, lam1)
+    for i, (p, y) in enumerate(zip(plans, ys)):
+        x1 = torch.zeros(p.nvox, dtype=torch.complex64, device=dev)
+        st = u.ufss_fista(p, y, u.lambda_from_mu(0.1), Ls[i], K, x1)
+        assert st["lambda"] == pytest.approx(lam3[i], rel=1e-6)
+        e = (torch.linalg.norm(xs[i] - x1) / torch.linalg.norm(x1)).item()
+        assert e < tol(i), (i, e)
+    # held plans: no destroy, retile or second batch while the batch lives
+    with pytest.raises(u.UfssError) as e:
+        u.ufss_plan_set_tiling(plans[0], fwd_split=1)
+    assert e.value.name == "INVALID_ARG"
+    with pytest.raises(u.UfssError) as e:
+        u.ufss_autotune(plans[0], None, False, False)
+    assert e.value.name == "INVALID_ARG"
+    with pytest.raises(u.UfssError) as e:
+        plans[0].close()
+    assert e.value.name == "INVALID_ARG"
+    with pytest.raises(u.UfssError) as e:
+        u.Batch(plans[:1], ys[:1], xs[:1], [1.0], Ls[:1], 2)
+    assert e.value.name == "INVALID_ARG"
+    b.close()
+    u.ufss_plan_set_tiling(plans[0], fwd_split=1)
+    for p in plans:
+        p.close()
+
+
+def test_config4_batch_at_full_shapes(dev):
+    """The 64 uneven scans of the batched workload at their own shapes (lateral
+    16-58, depth 128-512, 32-128 shared or per-position bins, B- and C-scans),
+    with the tilings the autotuner picks (quick search, as in the benchmark):
+    three batched iterations equal single-scan FISTA on every scan, and the
+    operator of the two largest scans matches the oracle on sampled positions
+    and voxel columns."""
+    u = ufss()
+    specs = W.batch_workload()
+    plans, ys, bins_l = [], [], []
+    for s in specs:
+        p, bins, m, y = make_scan(u, s, u.F32, dev)
+        u.ufss_autotune(p, None, use_cache=False, write_cache=False, quick=True)
+        plans.append(p)
+        ys.append(y)
+        bins_l.append(bins)
+    # any L above ||A||^2 keeps FISTA stable; the Frobenius norm is one
+    Ls = [u.ufss_sigma_estimate(s["geom"], p.m, s["per_position"], b)["fro_sq"]
+          for s, p, b in zip(specs, plans, bins_l)]
+    K = 3
+    xs = [torch.zeros(p.nvox, dtype=torch.complex64, device=dev) for p in plans]
+    b = u.Batch(plans, ys, xs, [-0.1] * len(plans), Ls, K)
+    res, lam = b.run()
+    assert np.all(np.isfinite(res)) and np.all(lam > 0)
+    b.close()
+    worst = 0.0
+    for i, (p, y) in enumerate(zip(plans, ys)):
+        x1 = torch.zeros(p.nvox, dtype=torch.complex64, device=dev)
+        u.ufss_fista(p, y, lam[i], Ls[i], K, x1)
+        e = (torch.linalg.norm(xs[i] - x1) / torch.linalg.norm(x1)).item()
+        worst = max(worst, e)
+        assert e < 1e-5, (i, e)
+    # the operator of the two largest scans against the oracle, sampled
+    big = sorted(range(len(specs)), key=lambda i: -plans[i].nvox)[:2]
+    for i in big:
+        g = specs[i]["geom"]
+        p = plans[i]
+        x = W.cn((g["ny"], g["nx"], g["nz"]), 70 + i)
+        yv = W.cn((g["ny"], g["nx"], p.m), 80 + i)
+        yo = torch.empty((g["ny"], g["nx"], p.m), dtype=torch.complex64, device=dev)
+        xo = torch.empty((g["ny"], g["nx"], g["nz"]), dtype=torch.complex64, device=dev)
+        u.ufss_forward(p, torch.from_numpy(x.astype(np.complex64)).to(dev), yo)
+        u.ufss_adjoint(p, torch.from_numpy(yv.astype(np.complex64)).to(dev), xo)
+        yg, xg = yo.cpu().numpy(), xo.cpu().numpy()
+        for py, px in ((0, 0), (g["ny"] // 2, g["nx"] - 1), (g["ny"] - 1, g["nx"] // 3)):
+            want = O.apply_A_at(g, bins_l[i], x, py, px)
+            assert np.abs(yg[py, px] - want).max() <= 1e-5 * np.abs(want).max(), (i, py, px)
+        for vy, vx in ((g["ny"] - 1, 0), (g["ny"] // 2, g["nx"] // 2)):
+            want = O.apply_AH_at(g, bins_l[i], yv, vy, vx)
+            assert np.abs(xg[vy, vx] - want).max() <= 1e-5 * np.abs(want).max(), (i, vy, vx)
+    for p in plans:
+        p.close()
