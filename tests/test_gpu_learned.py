@@ -176,3 +176,82 @@ def test_network_on_transform_operator_matches_oracle(dev):
     assert np.abs(ga - gb).max() <= 1e-4 * np.abs(gb).max()
     pf.close()
     plan.close()
+
+
+def test_fallback_forced_runs_warm_started_fista_vs_oracle(dev):
+    """The inference fallback rule (learned.solve): with factor 0 every
+    network answer falls back, and the result is plain FISTA warm-started from
+    the network's output -- against the oracle network followed by the oracle
+    FISTA from that start.  With factor = inf nothing falls back and the result
+    is the network's output."""
+    from paper_2012_04534_amd import learned as LN
+    u = ufss()
+    g, plan, A, AH, yd, yt, L = tiny(u, dev, seed=8)
+    S, ch, K = 4, 3, 30
+    shape = (5, 6, 12)
+    net = u.Net(plan, stages=S, channels=ch, L=L, mu=0.1)
+    p = random_params(S, ch, 31)
+    u.ufss_unrolled_params(net, set_to=p)
+    xo_net = N.forward(A, AH, yd, p.astype(np.float64), S, ch, L, 0.1, shape)
+    lam = V.lambda_rule(AH, yd, 0.1)
+    a_fb, _ = V.fista(A, AH, yd, lam, L, K, a0=xo_net.reshape(-1))
+    x, info = LN.solve(net, plan, yt, L, 0.1, ref_res=1.0, factor=0.0, fallback_iters=K)
+    assert info["fallback"] and info["t_fallback"] > 0
+    xg = x.cpu().numpy().reshape(-1)
+    e = np.linalg.norm(xg - a_fb) / np.linalg.norm(a_fb)
+    assert e < 1e-5, e
+    # the warm start matters: FISTA from zero ends elsewhere
+    a0, _ = V.fista(A, AH, yd, lam, L, K)
+    assert np.linalg.norm(a0 - a_fb) / np.linalg.norm(a_fb) > 1e-3
+    x2, info2 = LN.solve(net, plan, yt, L, 0.1, ref_res=1.0, factor=float("inf"), fallback_iters=K)
+    assert not info2["fallback"] and info2["t_fallback"] == 0.0
+    e2 = np.linalg.norm(x2.cpu().numpy() - xo_net) / np.linalg.norm(xo_net)
+    assert e2 < 1e-5, e2
+    # the residual the rule compares is ||A x_net - y|| of the oracle's x_net
+    r_or = np.linalg.norm(A(xo_net.reshape(-1)) - yd)
+    assert info2["res_net"] == pytest.approx(r_or, rel=1e-5)
+    net.close()
+    plan.close()
+
+
+def test_shipped_checkpoint_beats_untrained_and_equal_time_fista(dev):
+    """The shipped checkpoint on held-out scenes of the 32 x 32 C-scan rule
+    (evaluation set, never trained on), against the FISTA-200 answer: its
+    error is far below the untrained network's (16 plain FISTA iterations) and
+    below plain FISTA given the network's wall time, with the fallback rule."""
+    import os
+    from paper_2012_04534_amd import learned as LN
+    u = ufss()
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    path = os.path.join(root, "paper_2012_04534_amd", "weights", "unrolled_cscan32_s16c8.bin")
+    w = W.workload("cscan32")
+    g = w["geom"]
+    bins, _ = u.ufss_select_freqs(g, w["m"], True, w["seed"])
+    plan = u.Plan(g, w["m"], True, bins, algo=u.ALGO_FFT)
+    L = u.ufss_lipschitz(plan, max_iters=200, rtol=1e-6, margin=0.01)
+    data = LN.make_dataset(plan, g, 6, LN.EVAL_SEED, 200, L, mu=w["mu"], offset=0,
+                           back_wall=w["back_wall"])
+    net = u.Net(plan, stages=16, channels=8, L=L, mu=w["mu"])
+    u.ufss_unrolled_load(net, path)
+    untrained = u.Net(plan, stages=16, channels=8, L=L, mu=w["mu"])
+    # plain FISTA's time per iteration on this plan
+    x = torch.zeros((g["ny"], g["nx"], g["nz"]), dtype=torch.complex64, device=dev)
+    u.ufss_fista(plan, data[0][0], u.lambda_from_mu(w["mu"]), L, 5, x)
+    x.zero_()
+    torch.cuda.synchronize()
+    import time
+    t0 = time.perf_counter()
+    u.ufss_fista(plan, data[0][0], u.lambda_from_mu(w["mu"]), L, 100, x)
+    torch.cuda.synchronize()
+    spi = (time.perf_counter() - t0) / 100
+    r = LN.evaluate(net, plan, data, L, w["mu"], fista_s_per_iter=spi)
+    ru = LN.evaluate(untrained, plan, data, L, w["mu"], factor=float("inf"))
+    assert r["iters_same_time"].min() >= 16
+    err, err_u, err_f = r["err"].mean(), ru["err_net"].mean(), r["err_fista_same_time"].mean()
+    assert err < 0.25 * err_u, (err, err_u)
+    assert err < 0.25 * err_f, (err, err_f)
+    assert err_u > 0.5
+    assert err < 0.1, err
+    net.close()
+    untrained.close()
+    plan.close()
