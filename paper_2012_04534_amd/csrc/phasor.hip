@@ -8,13 +8,14 @@
 //   adjoint  x[v, z] = sum_{p in W(v)} sum_m exp(+j 2 pi k_m(p) u(p - v, z)) R[p, m]
 //
 // with R = H r prepared by the adjoint pre pass.  Forward: one workgroup per
-// (position, group of 32 bins); lanes stride the (voxel, depth) terms of the
-// window with depth-contiguous, coalesced loads of x and of the delay table,
-// the 32 bins are wave-uniform scalars, and the per-lane sums are reduced
-// across the wavefront with shuffles and across waves in LDS.  Adjoint: one
-// workgroup per (voxel column, 256 depths); each lane owns one depth, so no
-// cross-lane reduction is needed, and the bins and operands of each position
-// are wave-uniform scalar loads.
+// (position, group of bins: the selection's size rounded up to a power of two,
+// at most 32); lanes stride the (voxel, depth) terms of the window with
+// depth-contiguous, coalesced loads of x and of the delay table, the bins are
+// wave-uniform scalars, and the per-lane sums are reduced across the wavefront
+// with shuffles and across waves in LDS.  Adjoint: each lane owns one depth of
+// one voxel column (64, 128 or 256 lanes per column), so no cross-lane
+// reduction is needed, and the bins and operands of each position are
+// wave-uniform scalar loads.
 #include "internal.h"
 
 namespace ufss {
@@ -27,35 +28,49 @@ __device__ __forceinline__ void phasor_p(uint32_t ku, float& c, float& s) {
     s = __builtin_amdgcn_sinf(ph);
 }
 
-static constexpr int kMB = 32;   // bins per forward workgroup
+// Bins per forward workgroup: the smallest power of two >= m, at most 32
+// (a plan with more bins runs several groups of 32), so a position with one
+// selected bin evaluates one phasor per term, not 32.
+static constexpr int kMBMax = 32;
+static int fwd_mb(int m) {
+    int mb = 1;
+    while (mb < m && mb < kMBMax) mb *= 2;
+    return mb;
+}
 
+template <int MB>
 __global__ __launch_bounds__(256) void fwd_phasor_kernel(
     const cf32* __restrict__ x, const uint32_t* __restrict__ ut, const float* __restrict__ amp,
     const int* __restrict__ bins, const float* __restrict__ hsel, const cf32* __restrict__ ymeas,
     cf32* __restrict__ y,
     double* __restrict__ part, int nx, int ny, int nz, int wx, int wy, int m, int ngroups) {
-    __shared__ float red[2 * kMB][4];
+    __shared__ float red[2 * MB][4];
     const int p = blockIdx.x / ngroups, grp = blockIdx.x - p * ngroups;
     const int px = p % nx, py = p / nx;
-    const int mb0 = grp * kMB;
-    uint32_t kb[kMB];
+    const int mb0 = grp * MB;
+    uint32_t kb[MB];
 #pragma unroll
-    for (int j = 0; j < kMB; ++j) kb[j] = (mb0 + j < m) ? (uint32_t)bins[(int64_t)p * m + mb0 + j] : 0u;
+    for (int j = 0; j < MB; ++j) kb[j] = (mb0 + j < m) ? (uint32_t)bins[(int64_t)p * m + mb0 + j] : 0u;
 
     const int vx_lo = max(px - wx, 0), vx_hi = min(px + wx, nx - 1);
     const int vy_lo = max(py - wy, 0), vy_hi = min(py + wy, ny - 1);
     const int nvx = vx_hi - vx_lo + 1;
     const int64_t total = (int64_t)nvx * (vy_hi - vy_lo + 1) * nz;
 
-    float acc_re[kMB], acc_im[kMB];
+    float acc_re[MB], acc_im[MB];
 #pragma unroll
-    for (int j = 0; j < kMB; ++j) acc_re[j] = acc_im[j] = 0.f;
+    for (int j = 0; j < MB; ++j) acc_re[j] = acc_im[j] = 0.f;
 
-    // walk t = w * nz + z with w the window column index; update (w, z) incrementally
+    // walk t = w * nz + z over the window's columns w = (cy, cx), updating
+    // (cx, cy, z) incrementally (no division per term)
     int64_t t = threadIdx.x;
-    int w = (int)(t / nz), z = (int)(t - (int64_t)w * nz);
+    int z = threadIdx.x, cx = 0, cy = 0;
+    while (z >= nz) {
+        z -= nz;
+        if (++cx == nvx) { cx = 0; ++cy; }
+    }
     for (; t < total; t += 256) {
-        const int vx = vx_lo + w % nvx, vy = vy_lo + w / nvx;
+        const int vx = vx_lo + cx, vy = vy_lo + cy;
         cf32 xv = x[((int64_t)vy * nx + vx) * nz + z];
         const int adx = px > vx ? px - vx : vx - px, ady = py > vy ? py - vy : vy - py;
         const int64_t o = ((int64_t)ady * (wx + 1) + adx) * nz + z;
@@ -66,7 +81,7 @@ __global__ __launch_bounds__(256) void fwd_phasor_kernel(
             xv.im *= gb;
         }
 #pragma unroll
-        for (int j = 0; j < kMB; ++j) {
+        for (int j = 0; j < MB; ++j) {
             float c, s;
             phasor_p(kb[j] * u, c, s);
             // (xr + j xi)(c - j s)
@@ -76,13 +91,13 @@ __global__ __launch_bounds__(256) void fwd_phasor_kernel(
         z += 256;
         while (z >= nz) {
             z -= nz;
-            ++w;
+            if (++cx == nvx) { cx = 0; ++cy; }
         }
     }
     // reduce over the block
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int j = 0; j < kMB; ++j) {
+    for (int j = 0; j < MB; ++j) {
         float a = acc_re[j], b = acc_im[j];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
@@ -96,7 +111,7 @@ __global__ __launch_bounds__(256) void fwd_phasor_kernel(
     }
     __syncthreads();
     double r2 = 0.0;
-    if (threadIdx.x < kMB) {
+    if (threadIdx.x < MB) {
         const int j = threadIdx.x, mi = mb0 + j;
         if (mi < m) {
             float re = (red[2 * j][0] + red[2 * j][1]) + (red[2 * j][2] + red[2 * j][3]);
@@ -113,7 +128,7 @@ __global__ __launch_bounds__(256) void fwd_phasor_kernel(
             r2 = (double)re * re + (double)im * im;
         }
     }
-    // partial |y|^2 of this block (threads >= kMB contribute 0); fixed order
+    // partial |y|^2 of this block (threads >= MB contribute 0); fixed order
     if (threadIdx.x < 64) {
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) r2 += __shfl_xor(r2, off, 64);
@@ -123,24 +138,50 @@ __global__ __launch_bounds__(256) void fwd_phasor_kernel(
 
 void launch_forward_phasor(const Plan& P, const cf32* x, cf32* y, const cf32* ymeas,
                            double* part, hipStream_t s) {
-    const int ngroups = (P.m + kMB - 1) / kMB;
+    const int mb = fwd_mb(P.m);
+    const int ngroups = (P.m + mb - 1) / mb;
     const int nblk = P.npos * ngroups;
     if (nblk > P.part_cap) fail(UFSS_ERR_UNSUPPORTED, "too many positions for the phasor path");
-    hipLaunchKernelGGL(fwd_phasor_kernel, dim3(nblk), dim3(256), 0, s, x, P.d_u, P.d_amp, P.d_bins,
-                       P.d_hsel, ymeas, y, part, P.g.nx, P.g.ny, P.g.nz, P.d.wx, P.d.wy, P.m,
-                       ngroups);
+#define UFSS_PF(MBV)                                                                              \
+    hipLaunchKernelGGL(fwd_phasor_kernel<MBV>, dim3(nblk), dim3(256), 0, s, x, P.d_u, P.d_amp,    \
+                       P.d_bins, P.d_hsel, ymeas, y, part, P.g.nx, P.g.ny, P.g.nz, P.d.wx, P.d.wy, \
+                       P.m, ngroups)
+    switch (mb) {
+        case 1: UFSS_PF(1); break;
+        case 2: UFSS_PF(2); break;
+        case 4: UFSS_PF(4); break;
+        case 8: UFSS_PF(8); break;
+        case 16: UFSS_PF(16); break;
+        default: UFSS_PF(32); break;
+    }
+#undef UFSS_PF
     UFSS_HIP(hipGetLastError());
 }
 
-int phasor_forward_blocks(const Plan& P) { return P.npos * ((P.m + kMB - 1) / kMB); }
+int phasor_forward_blocks(const Plan& P) { return P.npos * ((P.m + fwd_mb(P.m) - 1) / fwd_mb(P.m)); }
+
+// Adjoint lanes per voxel column: 64, 128 or 256 (the smallest that covers the
+// depths, else 256 with several depth chunks), so a workgroup of 256 threads
+// holds 256 / lanes whole columns and shallow grids do not leave most lanes
+// idle; every wave stays on one column, so its bins and operands are uniform
+// scalar loads.
+static int adj_lanes(int nz) { return nz <= 64 ? 64 : (nz <= 128 ? 128 : 256); }
 
 __global__ __launch_bounds__(256) void adj_phasor_kernel(
     const cf32* __restrict__ rop, const uint32_t* __restrict__ ut, const float* __restrict__ amp,
     const int* __restrict__ bins, cf32* __restrict__ out, int nx, int ny, int nz, int wx, int wy,
-    int m, int nzc) {
-    const int v = blockIdx.x / nzc, zc = blockIdx.x - v * nzc;
-    const int vx = v % nx, vy = v / nx;
-    const int z = zc * 256 + threadIdx.x;
+    int m, int nzc, int lanes, int64_t ncols) {
+    const int per = 256 / lanes;                          // columns per workgroup
+    // a wave never straddles two columns (lanes is a multiple of 64): the
+    // column index is wave-uniform, and reading it from the first lane lets
+    // the bins and operands below be scalar loads
+    const int64_t cidx = (int64_t)blockIdx.x * per +
+                         __builtin_amdgcn_readfirstlane((int)(threadIdx.x / lanes));
+    if (cidx >= ncols * nzc) return;                      // whole waves exit together
+    const int64_t v = cidx / nzc;
+    const int zc = (int)(cidx - v * nzc);
+    const int vx = (int)(v % nx), vy = (int)(v / nx);
+    const int z = zc * lanes + (int)(threadIdx.x % lanes);
     const int zl = z < nz ? z : nz - 1;      // clamp for loads; store is guarded
     const int px_lo = max(vx - wx, 0), px_hi = min(vx + wx, nx - 1);
     const int py_lo = max(vy - wy, 0), py_hi = min(vy + wy, ny - 1);
@@ -167,14 +208,18 @@ __global__ __launch_bounds__(256) void adj_phasor_kernel(
             acc_im += gb * in_im;
         }
     }
-    if (z < nz) out[(int64_t)v * nz + z] = cf32{acc_re, acc_im};
+    if (z < nz) out[v * nz + z] = cf32{acc_re, acc_im};
 }
 
 void launch_adjoint_phasor(const Plan& P, cf32* out, hipStream_t s) {
-    const int nzc = (P.g.nz + 255) / 256;
-    hipLaunchKernelGGL(adj_phasor_kernel, dim3(P.npos * nzc), dim3(256), 0, s,
+    const int lanes = adj_lanes(P.g.nz);
+    const int nzc = (P.g.nz + lanes - 1) / lanes;
+    const int64_t ncols = P.npos;
+    const int per = 256 / lanes;
+    const int64_t nblk = (ncols * nzc + per - 1) / per;
+    hipLaunchKernelGGL(adj_phasor_kernel, dim3((unsigned)nblk), dim3(256), 0, s,
                        static_cast<const cf32*>(P.d_rop), P.d_u, P.d_amp, P.d_bins, out, P.g.nx, P.g.ny,
-                       P.g.nz, P.d.wx, P.d.wy, P.m, nzc);
+                       P.g.nz, P.d.wx, P.d.wy, P.m, nzc, lanes, ncols);
     UFSS_HIP(hipGetLastError());
 }
 

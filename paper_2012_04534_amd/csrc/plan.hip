@@ -403,6 +403,17 @@ Plan* plan_create(const ufss_geom* g, int m, int per_position, const int32_t* bi
     } else {
         validate_bins(g, m, per_position, bins);
     }
+    if (g->algo == UFSS_ALGO_AUTO && per_position && !mix && g->dtype == UFSS_F32) {
+        // per-position subsets: the phasor path costs about one phasor per
+        // selected bin and term, the union-GEMM one MFMA slot per union bin
+        // (padded) at several times the rate; measured on the 50x50x50
+        // replica the phasor path wins while the union has at least ~5x the
+        // bins of one position (n_f = 1, 2, 5 of a 37-bin union), the GEMM above
+        std::vector<int> uu(bins, bins + nsel);
+        std::sort(uu.begin(), uu.end());
+        const int64_t nu = std::unique(uu.begin(), uu.end()) - uu.begin();
+        if (5 * (int64_t)m <= nu) algo = UFSS_ALGO_PHASOR;
+    }
     if (algo == UFSS_ALGO_PHASOR && g->dtype == UFSS_BF16)
         fail(UFSS_ERR_UNSUPPORTED, "the phasor path is FP32 only");
     if (algo == UFSS_ALGO_PHASOR && !per_position) algo = UFSS_ALGO_GEMM;

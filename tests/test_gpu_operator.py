@@ -338,7 +338,7 @@ def test_random_small_problems_against_dense_oracle(seed, dev):
     A = O.dense_A(g, bins)
     y_ref = (A @ x.reshape(-1).astype(np.complex128)).reshape(y.shape)
     x_ref = (A.conj().T @ y.reshape(-1).astype(np.complex128)).reshape(x.shape)
-    plan = u.Plan(g, m, per_pos, bins, dtype=u.F32 if dtype == "f32" else u.BF16)
+    plan = u.Plan(g, m, per_pos, bins, dtype=u.F32 if dtype == "f32" else u.BF16, algo=u.ALGO_GEMM)
     try:
         u.ufss_plan_set_tiling(plan, **t)
     except u.UfssError:
@@ -415,3 +415,63 @@ def test_beam_limits(dev):
         assert e.value.name == "INVALID_ARG"
     pb.close()
     pf.close()
+
+
+def test_auto_picks_phasor_for_sparse_per_position_subsets(dev):
+    """UFSS_ALGO_AUTO: FP32 per-position subsets whose union holds at least 5x
+    one position's bins run on the phasor path (one selected bin per A-scan of
+    the 50 x 50 x 50 replica), denser ones (64 of a 66-bin union) on the
+    union-GEMM; the AUTO plan computes the same operator as the explicit one."""
+    u = ufss()
+    g = W.sim_geometry()
+    g.update(nx=12, ny=10, nz=30)
+    bins, per = u.ufss_sample_bins(g, 1, u.SAMPLE_RND_F, 5001)
+    assert per
+    auto = u.Plan(g, 1, True, bins)
+    assert auto.info()["algo"] == u.ALGO_PHASOR
+    gemm = u.Plan(g, 1, True, bins, algo=u.ALGO_GEMM)
+    x = torch.from_numpy(W.cn((g["ny"], g["nx"], g["nz"]), 3).astype(np.complex64)).to(dev)
+    ya = torch.empty((g["ny"], g["nx"], 1), dtype=torch.complex64, device=dev)
+    yg = torch.empty_like(ya)
+    u.ufss_forward(auto, x, ya)
+    u.ufss_forward(gemm, x, yg)
+    assert (torch.linalg.norm(ya - yg) / torch.linalg.norm(yg)).item() < 1e-5
+    A = O.dense_A(g, bins)
+    y_ref = (A @ x.cpu().numpy().reshape(-1).astype(np.complex128)).reshape(ya.shape)
+    assert max(errs(ya.cpu().numpy(), y_ref)) < TOL32
+    auto.close()
+    gemm.close()
+    w = W.workload("cscan32")
+    b32, _ = u.ufss_select_freqs(w["geom"], w["m"], True, w["seed"])
+    p32 = u.Plan(w["geom"], w["m"], True, b32)
+    assert p32.info()["algo"] == u.ALGO_GEMM
+    p32.close()
+
+
+@pytest.mark.parametrize("nz,m", [(1, 1), (63, 2), (64, 3), (65, 5), (100, 17), (128, 8),
+                                  (129, 33), (300, 4)])
+def test_phasor_bin_groups_and_adjoint_lanes(nz, m, dev):
+    """The phasor path sizes its forward bin group to the selection (1, 2, 4,
+    ..., 32 bins, several groups above 32) and gives each adjoint voxel column
+    64, 128 or 256 lanes (several columns per workgroup, or several depth
+    chunks per column): depth counts around each boundary and bin counts
+    around each group size, against the dense FP64 oracle."""
+    u = ufss()
+    nt = 512 if nz > 128 else 256
+    g = W.geometry(5, 4, nz, nt, win_x=2, win_y=3)
+    bins, _ = u.ufss_select_freqs(g, m, True, 31 + nz + m)
+    x = W.cn((g["ny"], g["nx"], nz), 41 + m).astype(np.complex64)
+    y = W.cn((g["ny"], g["nx"], m), 51 + nz).astype(np.complex64)
+    A = O.dense_A(g, bins)
+    y_ref = (A @ x.reshape(-1).astype(np.complex128)).reshape(y.shape)
+    x_ref = (A.conj().T @ y.reshape(-1).astype(np.complex128)).reshape(x.shape)
+    plan = u.Plan(g, m, True, bins, algo=u.ALGO_PHASOR)
+    assert plan.info()["algo"] == u.ALGO_PHASOR
+    yo = torch.empty(y.shape, dtype=torch.complex64, device=dev)
+    xo = torch.empty(x.shape, dtype=torch.complex64, device=dev)
+    u.ufss_forward(plan, torch.from_numpy(x).to(dev), yo)
+    u.ufss_adjoint(plan, torch.from_numpy(y).to(dev), xo)
+    torch.cuda.synchronize()
+    assert max(errs(yo.cpu().numpy(), y_ref)) < TOL32
+    assert max(errs(xo.cpu().numpy(), x_ref)) < TOL32
+    plan.close()
