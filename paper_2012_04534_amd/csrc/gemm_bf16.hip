@@ -252,57 +252,84 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
                                        : nullptr;
             const int64_t tstep = (int64_t)nzc * a.mu * 64;
             auto tile_at = [&](int dx) { return tsrc + (dx < 0 ? -dx : dx) * tstep; };
-            // table path: tile dx + 1 waits in registers (Rn) while dx is consumed
-            // and dx + 2 is being loaded, so a load has two steps to arrive
+            // P_d depends on |d_x| only, so one staged tile serves d_x = +|d_x|
+            // and -|d_x| (twice the products per tile and per barrier).  Table
+            // path: tile |d_x| + 1 waits in registers (Rn) while |d_x| is
+            // consumed and |d_x| + 2 is being loaded, so a load has two steps
+            // to arrive.
+            const int adx_hi = max(dx_hi, -dx_lo);
+            const int adx_lo = (dx_lo <= 0 && dx_hi >= 0) ? 0 : min(dx_lo < 0 ? -dx_lo : dx_lo, dx_hi < 0 ? -dx_hi : dx_hi);
             TabRegs Rn;
             if (dx_lo <= dx_hi) {
                 if (a.tab) {
                     TabRegs R0;
-                    tab_load(R0, tile_at(dx_lo), nbins);
-                    if (dx_lo < dx_hi) tab_load(Rn, tile_at(dx_lo + 1), nbins);
+                    tab_load(R0, tile_at(adx_lo), nbins);
+                    if (adx_lo < adx_hi) tab_load(Rn, tile_at(adx_lo + 1), nbins);
                     tab_store(R0, ptile, ptile + NB * 16 * PROW, prow_count);
                 } else {
-                    gen(dx_lo, 0);
+                    gen(adx_lo, 0);
                 }
             }
             __syncthreads();
             int buf = 0;
-            for (int dx = dx_lo; dx <= dx_hi; ++dx) {
-                const bool more = dx < dx_hi;
+            for (int adx = adx_lo; adx <= adx_hi && dx_lo <= dx_hi; ++adx) {
+                const bool more = adx < adx_hi;
                 TabRegs R;
                 if (a.tab) {
-                    if (dx + 2 <= dx_hi) tab_load(R, tile_at(dx + 2), nbins);
+                    if (adx + 2 <= adx_hi) tab_load(R, tile_at(adx + 2), nbins);
                 } else if (more) {
-                    gen(dx + 1, buf ^ 1);
+                    gen(adx + 1, buf ^ 1);
                 }
                 const __bf16* pc = ptile + (size_t)buf * 2 * NB * 16 * PROW;
                 const __bf16* ps = pc + NB * 16 * PROW;
-                // A operands: x at (p - d) for this lane's position of each sub-tile
-                bf8 xr[NP], xi[NP];
-#pragma unroll
-                for (int s = 0; s < NP; ++s) {
-                    const int q = wave_x * NP + s;
-                    const int px = px0 + q * sw + i % sw, iy = wave_y * sh + i / sw;
-                    const int gx = px - dx;
-                    const int cell = (gx >= cx_lo && gx <= cx_hi) ? ((py0 + iy - dy) & (tpy - 1)) * pitch + (gx - cx_lo) : zero_cell;
-                    xr[s] = lds_bf8(halo + (size_t)cell * CELL + 8 * kq);
-                    xi[s] = lds_bf8(halo + (size_t)cell * CELL + ZCB + 8 * kq);
-                }
+                // every bin sub-tile runs (no data-dependent exit), so the
+                // 4 NP NB products issue in four independent passes; the
+                // sub-tiles past nb_act read stale LDS rows into accumulators
+                // that are never stored
+                bf8 c8[NB], s8[NB];
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
-                    if (nb >= nb_act) break;
-                    const bf8 c8 = lds_bf8(pc + (nb * 16 + i) * PROW + 8 * kq);
-                    const bf8 s8 = lds_bf8(ps + (nb * 16 + i) * PROW + 8 * kq);
-                    const bf8 ns8 = neg_bf8(s8);
+                    c8[nb] = lds_bf8(pc + (nb * 16 + i) * PROW + 8 * kq);
+                    s8[nb] = lds_bf8(ps + (nb * 16 + i) * PROW + 8 * kq);
+                }
+                auto apply = [&](const int dx) {
+                    // A operands: x at (p - d) for this lane's position of each sub-tile
+                    bf8 xr[NP], xi[NP];
 #pragma unroll
                     for (int s = 0; s < NP; ++s) {
-                        // (xr + j xi)(c - j s) = xr c + xi s + j (xi c - xr s)
-                        acc_re[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xr[s], c8, acc_re[s][nb], 0, 0, 0);
-                        acc_re[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xi[s], s8, acc_re[s][nb], 0, 0, 0);
-                        acc_im[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xi[s], c8, acc_im[s][nb], 0, 0, 0);
-                        acc_im[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xr[s], ns8, acc_im[s][nb], 0, 0, 0);
+                        const int q = wave_x * NP + s;
+                        const int px = px0 + q * sw + i % sw, iy = wave_y * sh + i / sw;
+                        const int gx = px - dx;
+                        const int cell = (gx >= cx_lo && gx <= cx_hi) ? ((py0 + iy - dy) & (tpy - 1)) * pitch + (gx - cx_lo) : zero_cell;
+                        xr[s] = lds_bf8(halo + (size_t)cell * CELL + 8 * kq);
+                        xi[s] = lds_bf8(halo + (size_t)cell * CELL + ZCB + 8 * kq);
                     }
-                }
+                    // (xr + j xi)(c - j s) = xr c + xi s + j (xi c - xr s)
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                        for (int s = 0; s < NP; ++s)
+                            acc_re[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xr[s], c8[nb], acc_re[s][nb], 0, 0, 0);
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                        for (int s = 0; s < NP; ++s)
+                            acc_im[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xi[s], c8[nb], acc_im[s][nb], 0, 0, 0);
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                        for (int s = 0; s < NP; ++s)
+                            acc_re[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xi[s], s8[nb], acc_re[s][nb], 0, 0, 0);
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) {
+                        const bf8 ns8 = neg_bf8(s8[nb]);
+#pragma unroll
+                        for (int s = 0; s < NP; ++s)
+                            acc_im[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xr[s], ns8, acc_im[s][nb], 0, 0, 0);
+                    }
+                };
+                if (adx <= dx_hi) apply(adx);                  // d_x = +|d_x|
+                if (adx > 0 && -adx >= dx_lo) apply(-adx);     // d_x = -|d_x|
                 if (more && a.tab) {
                     __bf16* pn = ptile + (size_t)(buf ^ 1) * 2 * NB * 16 * PROW;
                     tab_store(Rn, pn, pn + NB * 16 * PROW, prow_count);
@@ -460,54 +487,78 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
             const int64_t tstep = (int64_t)nkc * a.nz * 64;
             const int zrows = min(zspan, a.nz - zw0);
             auto tile_at = [&](int dx) { return tsrc + (dx < 0 ? -dx : dx) * tstep; };
-            TabRegs Rn;                      // as in the forward: two steps of prefetch
+            // as in the forward: one staged tile serves d_x = +|d_x| and -|d_x|,
+            // with two steps of prefetch
+            const int adx_hi = max(dx_hi, -dx_lo);
+            const int adx_lo = (dx_lo <= 0 && dx_hi >= 0) ? 0 : min(dx_lo < 0 ? -dx_lo : dx_lo, dx_hi < 0 ? -dx_hi : dx_hi);
+            TabRegs Rn;
             if (dx_lo <= dx_hi) {
                 if (a.tab) {
                     TabRegs R0;
-                    tab_load(R0, tile_at(dx_lo), zrows);
-                    if (dx_lo < dx_hi) tab_load(Rn, tile_at(dx_lo + 1), zrows);
+                    tab_load(R0, tile_at(adx_lo), zrows);
+                    if (adx_lo < adx_hi) tab_load(Rn, tile_at(adx_lo + 1), zrows);
                     tab_store(R0, ptile, ptile + zspan * PROW, zspan);
                 } else {
-                    gen(dx_lo, 0);
+                    gen(adx_lo, 0);
                 }
             }
             __syncthreads();
             int buf = 0;
-            for (int dx = dx_lo; dx <= dx_hi; ++dx) {
-                const bool more = dx < dx_hi;
+            for (int adx = adx_lo; adx <= adx_hi && dx_lo <= dx_hi; ++adx) {
+                const bool more = adx < adx_hi;
                 TabRegs R;
                 if (a.tab) {
-                    if (dx + 2 <= dx_hi) tab_load(R, tile_at(dx + 2), zrows);
+                    if (adx + 2 <= adx_hi) tab_load(R, tile_at(adx + 2), zrows);
                 } else if (more) {
-                    gen(dx + 1, buf ^ 1);
+                    gen(adx + 1, buf ^ 1);
                 }
                 const __bf16* pc = ptile + (size_t)buf * 2 * zspan * PROW;
                 const __bf16* ps = pc + zspan * PROW;
-                bf8 rr8[NV], ri8[NV];
-#pragma unroll
-                for (int s = 0; s < NV; ++s) {
-                    const int q = wave_x * NV + s;
-                    const int vx = vx0 + q * sw + i % sw, iy = wave_y * sh + i / sw;
-                    const int gx = vx + dx;
-                    const int cell = (gx >= cx_lo && gx <= cx_hi) ? ((vy0 + iy + dy) & (tvy - 1)) * pitch + (gx - cx_lo) : zero_cell;
-                    rr8[s] = lds_bf8(halo + (size_t)cell * CELL + 8 * kq);
-                    ri8[s] = lds_bf8(halo + (size_t)cell * CELL + ZCB + 8 * kq);
-                }
+                // all NZ depth sub-tiles in four independent passes (inactive
+                // ones are never stored)
+                bf8 c8[NZ], s8[NZ];
 #pragma unroll
                 for (int q = 0; q < NZ; ++q) {
-                    if (q >= nz_act) break;
-                    const bf8 c8 = lds_bf8(pc + (q * 16 + i) * PROW + 8 * kq);
-                    const bf8 s8 = lds_bf8(ps + (q * 16 + i) * PROW + 8 * kq);
-                    const bf8 ns8 = neg_bf8(s8);
+                    c8[q] = lds_bf8(pc + (q * 16 + i) * PROW + 8 * kq);
+                    s8[q] = lds_bf8(ps + (q * 16 + i) * PROW + 8 * kq);
+                }
+                auto apply = [&](const int dx) {
+                    bf8 rr8[NV], ri8[NV];
 #pragma unroll
                     for (int s = 0; s < NV; ++s) {
-                        // (rr + j ri)(c + j s) = rr c - ri s + j (rr s + ri c)
-                        acc_re[s][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rr8[s], c8, acc_re[s][q], 0, 0, 0);
-                        acc_re[s][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ri8[s], ns8, acc_re[s][q], 0, 0, 0);
-                        acc_im[s][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rr8[s], s8, acc_im[s][q], 0, 0, 0);
-                        acc_im[s][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ri8[s], c8, acc_im[s][q], 0, 0, 0);
+                        const int q = wave_x * NV + s;
+                        const int vx = vx0 + q * sw + i % sw, iy = wave_y * sh + i / sw;
+                        const int gx = vx + dx;
+                        const int cell = (gx >= cx_lo && gx <= cx_hi) ? ((vy0 + iy + dy) & (tvy - 1)) * pitch + (gx - cx_lo) : zero_cell;
+                        rr8[s] = lds_bf8(halo + (size_t)cell * CELL + 8 * kq);
+                        ri8[s] = lds_bf8(halo + (size_t)cell * CELL + ZCB + 8 * kq);
                     }
-                }
+                    // (rr + j ri)(c + j s) = rr c - ri s + j (rr s + ri c)
+#pragma unroll
+                    for (int q = 0; q < NZ; ++q)
+#pragma unroll
+                        for (int s = 0; s < NV; ++s)
+                            acc_re[s][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rr8[s], c8[q], acc_re[s][q], 0, 0, 0);
+#pragma unroll
+                    for (int q = 0; q < NZ; ++q)
+#pragma unroll
+                        for (int s = 0; s < NV; ++s)
+                            acc_im[s][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rr8[s], s8[q], acc_im[s][q], 0, 0, 0);
+#pragma unroll
+                    for (int q = 0; q < NZ; ++q)
+#pragma unroll
+                        for (int s = 0; s < NV; ++s)
+                            acc_im[s][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ri8[s], c8[q], acc_im[s][q], 0, 0, 0);
+#pragma unroll
+                    for (int q = 0; q < NZ; ++q) {
+                        const bf8 ns8 = neg_bf8(s8[q]);
+#pragma unroll
+                        for (int s = 0; s < NV; ++s)
+                            acc_re[s][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ri8[s], ns8, acc_re[s][q], 0, 0, 0);
+                    }
+                };
+                if (adx <= dx_hi) apply(adx);                  // d_x = +|d_x|
+                if (adx > 0 && -adx >= dx_lo) apply(-adx);     // d_x = -|d_x|
                 if (more && a.tab) {
                     __bf16* pn = ptile + (size_t)(buf ^ 1) * 2 * zspan * PROW;
                     tab_store(Rn, pn, pn + zspan * PROW, zspan);
