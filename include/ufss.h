@@ -96,10 +96,13 @@ typedef struct ufss_plan_info {
     int32_t union_size;   /* bins in the union of per-position subsets         */
     int64_t workspace_bytes;              /* device memory owned by the plan    */
     int32_t fwd_split, adj_split;         /* split-K factors of the GEMM path   */
-    int32_t fwd_waves, fwd_zsplit;       /* FP32 forward: waves per workgroup,
-                                            depth split (1 elsewhere)          */
+    int32_t fwd_waves, fwd_zsplit;       /* FP32 forward: waves per workgroup;
+                                            GEMM forward: depth split (1 for
+                                            phasor and transform plans)        */
     int32_t fwd_tile, adj_tile;          /* FP32 GEMMs: 16-position sub-tiles
-                                            per wave (0 elsewhere)             */
+                                            per wave; BF16 adjoint (adj_tile):
+                                            16-depth sub-tiles per wave (0
+                                            elsewhere)                         */
     int32_t fwd_rows, adj_rows;          /* BF16 GEMMs: rows of waves in a
                                             tile (0 elsewhere)                 */
     int32_t fwd_chunk, adj_chunk;        /* FP32 GEMMs: staged depth / bin
@@ -453,16 +456,18 @@ int ufss_autotune(ufss_plan_t plan, const char* cache_path, int32_t flags,
  *   fwd_split   parts of the forward GEMM's d_y range, 1..64
  *   adj_split   parts of the adjoint GEMM's d_y range, 1..64
  *   fwd_waves   FP32 forward: 16-bin sub-tiles (waves) per workgroup, 1..8
- *   fwd_zsplit  FP32 forward: parts of the depth range, 1..64
- *   fwd_tile, adj_tile    FP32: 16-position sub-tiles per wave, 2 or 4
+ *   fwd_zsplit  forward: parts of the depth range, 1..64 (FP32 and BF16)
+ *   fwd_tile, adj_tile    FP32: 16-position sub-tiles per wave, 2 or 4;
+ *               BF16 (adj_tile only): 16-depth sub-tiles per adjoint wave, 2
+ *               or 4 (2: half-height depth tiles, twice the workgroups)
  *   fwd_rows, adj_rows    BF16: rows of waves in a tile, 1 or 2 (2: half as
  *               wide and twice as tall; C-scans only)
  *   fwd_chunk, adj_chunk  FP32: depths (forward) or bins (adjoint) staged in
  *               LDS per step, 16 or 8 (8 halves the halo and admits more
  *               workgroups per CU; shrunk further if the window needs it)
  * Any valid setting computes the same operator; parts that receive no rows
- * contribute zeros.  BF16 plans accept only 0 or 1 for fwd_zsplit and ignore
- * the FP32-only fields; FP32 plans ignore the rows.  Reallocates the plan's
+ * contribute zeros.  BF16 plans ignore the FP32-only fields; FP32 plans
+ * ignore the rows.  Reallocates the plan's
  * split workspace (synchronises the device).  Errors: INVALID_ARG for values
  * out of range or NULL, UNSUPPORTED for phasor plans or a BF16 tile shape that
  * does not fit in LDS. */

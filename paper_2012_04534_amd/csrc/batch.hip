@@ -612,6 +612,7 @@ int autotune(Plan& P, const char* cache_path, int flags, hipStream_t s, int32_t*
         P.bf_adj_rows = (int)cache[key][9];
         P.fwd_zc = (int)cache[key][10];
         P.adj_kc = (int)cache[key][11];
+        if (cache[key].size() >= 13) P.bf_adj_nz = (int)cache[key][12];
         plan_set_splits(P, (int)cache[key][0], (int)cache[key][1], (int)cache[key][5]);
     } else {
         const int tpy = P.g.ny == 1 ? 1 : 4;
@@ -634,9 +635,8 @@ int autotune(Plan& P, const char* cache_path, int flags, hipStream_t s, int32_t*
         const std::vector<int> npc =
             (P.dtype == UFSS_F32 && !quick) ? std::vector<int>{2, 4} : std::vector<int>{2};
         std::vector<int> zcand{1};
-        if (P.dtype == UFSS_F32)
-            for (int z : {2, 4, 8})
-                if (P.g.nz >= 32 * z) zcand.push_back(z);
+        for (int z : {2, 4, 8})
+            if (P.g.nz >= 32 * z) zcand.push_back(z);
         if (quick && zcand.size() > 2) zcand = {1, zcand[2]};
         const std::vector<int> nwc = quick ? std::vector<int>{P.fwd_nw} : nw_candidates(P);
         for (int wr : rows)
@@ -667,17 +667,23 @@ int autotune(Plan& P, const char* cache_path, int flags, hipStream_t s, int32_t*
             }
         }
         P.fwd_zc = bzc;
+        // BF16 adjoint: 4 or 2 depth sub-tiles per wave (2: twice the workgroups)
+        const std::vector<int> nzc = P.dtype == UFSS_BF16 ? std::vector<int>{4, 2} : std::vector<int>{4};
+        int bnz = P.bf_adj_nz;
         for (int wr : rows)
             for (int np : npc)
-                for (int c : cand) {
-                    P.adj_np = np;
-                    P.bf_adj_rows = wr;
-                    plan_set_splits(P, bf, c, bz);
-                    double t = time_ms([&]() { op_adjoint(P, P.d_r, P.d_g, s); }, 3, s);
-                    if (t < best_a) { best_a = t; ba = c; bnpa = np; bar = wr; }
-                }
+                for (int nzs : nzc)
+                    for (int c : cand) {
+                        P.adj_np = np;
+                        P.bf_adj_rows = wr;
+                        P.bf_adj_nz = nzs;
+                        plan_set_splits(P, bf, c, bz);
+                        double t = time_ms([&]() { op_adjoint(P, P.d_r, P.d_g, s); }, 3, s);
+                        if (t < best_a) { best_a = t; ba = c; bnpa = np; bar = wr; bnz = nzs; }
+                    }
         P.adj_np = bnpa;
         P.bf_adj_rows = bar;
+        P.bf_adj_nz = bnz;
         // then the smaller bin chunk at that shape (FP32)
         int bkc = 16;
         if (P.dtype == UFSS_F32 && !quick) {
@@ -693,7 +699,8 @@ int autotune(Plan& P, const char* cache_path, int flags, hipStream_t s, int32_t*
         if (cache_path && (flags & 2)) {
             cache = read_cache(cache_path);
             cache[key] = {(double)bf, (double)ba, best_f, best_a, (double)bnw, (double)bz, (double)bnp,
-                          (double)bnpa, (double)bfr, (double)bar, (double)bzc, (double)bkc};
+                          (double)bnpa, (double)bfr, (double)bar, (double)bzc, (double)bkc,
+                          (double)P.bf_adj_nz};
             write_cache(cache_path, cache);
         }
     }

@@ -674,15 +674,16 @@ int ufss_plan_set_tiling(ufss_plan_t plan, const ufss_tiling* t) {
         !one_of(t->fwd_tile, 2, 4) || !one_of(t->adj_tile, 2, 4) || !in(t->fwd_rows, 2) ||
         !in(t->adj_rows, 2) || !one_of(t->fwd_chunk, 8, 16) || !one_of(t->adj_chunk, 8, 16))
         ufss::fail(UFSS_ERR_INVALID_ARG, "tiling value out of range");
-    if (P->dtype == UFSS_BF16 && t->fwd_zsplit > 1)
-        ufss::fail(UFSS_ERR_INVALID_ARG, "the BF16 forward GEMM does not split depth");
     if (P->dtype == UFSS_F32) {
         if (t->fwd_waves > 0) P->fwd_nw = t->fwd_waves;
         if (t->fwd_tile > 0) P->fwd_np = t->fwd_tile;
         if (t->adj_tile > 0) P->adj_np = t->adj_tile;
         if (t->fwd_chunk > 0) P->fwd_zc = t->fwd_chunk;
         if (t->adj_chunk > 0) P->adj_kc = t->adj_chunk;
-    } else if (t->fwd_rows > 0 || t->adj_rows > 0) {
+    } else {
+        if (t->adj_tile > 0) P->bf_adj_nz = t->adj_tile;
+    }
+    if (P->dtype == UFSS_BF16 && (t->fwd_rows > 0 || t->adj_rows > 0)) {
         const int fr = t->fwd_rows > 0 ? t->fwd_rows : P->bf_fwd_rows;
         const int ar = t->adj_rows > 0 ? t->adj_rows : P->bf_adj_rows;
         if (!ufss::bf16_rows_ok(*P, fr, ar))

@@ -165,6 +165,7 @@ struct FwdB {
     const int* kb;
     int nx, ny, nz, wx, wy, mu;
     int sw, ntx, nty, nbt, split;
+    int zsplit;            // depth-chunk split (partials [split * zsplit])
     int64_t npos;
     int nblk;              // blocks of this plan's grid
     const __bf16* tab;     // phasor tiles [wy+1][wx+1][nzc][mu][2][32] or null
@@ -187,7 +188,8 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
     const int ntile = a.ntx * a.nty;
     const int tile = b % ntile;
     const int bt = (b / ntile) % a.nbt;
-    const int sp = b / (ntile * a.nbt);
+    const int sp = b / (ntile * a.nbt);           // partial slot: d_y part + split * depth part
+    const int dsp = sp % a.split, zsp = sp / a.split;
     const int px0 = (tile % a.ntx) * tpx, py0 = (tile / a.ntx) * tpy;
     const int cx_lo = max(0, px0 - a.wx), cx_hi = min(a.nx - 1, px0 + tpx - 1 + a.wx);
     const int ncol = cx_hi - cx_lo + 1;
@@ -203,10 +205,14 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
     int dy_lo = max(-a.wy, py0 - (a.ny - 1));
     int dy_hi = min(a.wy, py0 + tpy - 1);
     const int chunk = (dy_hi - dy_lo + 1 + a.split - 1) / a.split;
-    dy_lo += sp * chunk;
+    dy_lo += dsp * chunk;
     dy_hi = min(dy_hi, dy_lo + chunk - 1);
     const int dx_lo = max(-a.wx, px0 - (a.nx - 1));
     const int dx_hi = min(a.wx, px0 + tpx - 1);
+    // this block's depth chunks (an empty range leaves zeros in its partial slot)
+    const int nzc_all = (a.nz + ZCB - 1) / ZCB;
+    const int zc_per = (nzc_all + a.zsplit - 1) / a.zsplit;
+    const int z_lo = zsp * zc_per * ZCB, z_hi = min(a.nz, (zsp + 1) * zc_per * ZCB);
 
     const int mb0 = bt * NB * 16;
     const int nbins = min(NB * 16, a.mu - mb0);          // valid bins of this tile
@@ -223,7 +229,7 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
         for (int q = 0; q < NB; ++q) acc_re[s][q] = acc_im[s][q] = f4{0.f, 0.f, 0.f, 0.f};
 
     const int prow_count = nb_act * 16;
-    for (int z0 = 0; z0 < a.nz; z0 += ZCB) {
+    for (int z0 = z_lo; z0 < z_hi; z0 += ZCB) {
         for (int dy = dy_lo; dy <= dy_hi; ++dy) {
             __syncthreads();
             // stage x rows (planar bf16) and the delay slab of |dy|
@@ -608,7 +614,7 @@ __global__ __launch_bounds__(256) void adj_gemm_bf16_kernel_grouped(const AdjB* 
 // Host side.
 // ---------------------------------------------------------------------------
 static constexpr int kBfNB = 4;     // forward: 4 x 16 bins per wave
-static constexpr int kBfNZ = 4;     // adjoint: 4 x 16 depths per wave
+static constexpr int kBfNZ = 4;     // adjoint: 4 x 16 depths per wave (default; 2 also built)
 static constexpr size_t kLdsMaxB = 64 * 1024;
 
 static int bf_sw(const Plan& P) { return P.g.ny == 1 ? 16 : 4; }
@@ -643,12 +649,12 @@ static size_t fwd_bf16_lds(const Plan& P, int np, int nb, int wr, bool tables) {
            (tables ? 0 : (size_t)(P.d.wx + 1) * ZCB * 4) + nb * 16 * 4;
 }
 
-static size_t adj_bf16_lds(const Plan& P, int nv, int wr, bool tables) {
+static size_t adj_bf16_lds(const Plan& P, int nv, int wr, bool tables, int nzs = kBfNZ) {
     int tvx, tvy;
     bf_tile(P, nv, wr, tvx, tvy);
     const int ncol = std::min(P.g.nx, tvx + 2 * P.d.wx);
-    return (size_t)(tvy * ncol + 1) * CELL * 2 + (size_t)2 * 2 * kBfNZ * 16 * PROW * 2 +
-           (tables ? 0 : (size_t)(P.d.wx + 1) * kBfNZ * 16 * 4) + ZCB * 4;
+    return (size_t)(tvy * ncol + 1) * CELL * 2 + (size_t)2 * 2 * nzs * 16 * PROW * 2 +
+           (tables ? 0 : (size_t)(P.d.wx + 1) * nzs * 16 * 4) + ZCB * 4;
 }
 
 // One-row tiles must fit with in-kernel phasor generation (the fallback).
@@ -714,15 +720,18 @@ static int fwdb_args(const Plan& P, FwdB& a, size_t& lds, int np, int nb, int wr
     a.nty = (a.ny + tpy - 1) / tpy;
     a.nbt = (a.mu + nb * 16 - 1) / (nb * 16);
     a.split = P.fwd_split;
+    a.zsplit = std::max(1, P.fwd_zsplit);
     a.npos = P.npos;
     a.tab = static_cast<const __bf16*>(P.d_ptab_f);
     lds = fwd_bf16_lds(P, np, nb, wr, a.tab != nullptr);
     if (lds > kLdsMaxB) fail(UFSS_ERR_UNSUPPORTED, "aperture window too wide for the BF16 GEMM path");
-    a.nblk = a.ntx * a.nty * a.nbt * a.split;
+    a.nblk = a.ntx * a.nty * a.nbt * a.split * a.zsplit;
     return a.nblk;
 }
 
-static int adjb_args(const Plan& P, cf32* out, AdjB& a, size_t& lds, int nv, int wr) {
+// nzs: 16-depth sub-tiles per wave (4, or 2 for twice the workgroups on
+// shallow grids / small windows).
+static int adjb_args(const Plan& P, cf32* out, AdjB& a, size_t& lds, int nv, int wr, int nzs) {
     a = AdjB{};
     a.r = static_cast<const cbf16*>(P.d_rop);
     a.out = out;
@@ -740,11 +749,11 @@ static int adjb_args(const Plan& P, cf32* out, AdjB& a, size_t& lds, int nv, int
     bf_tile(P, nv, wr, tvx, tvy);
     a.ntx = (a.nx + tvx - 1) / tvx;
     a.nty = (a.ny + tvy - 1) / tvy;
-    a.nzt = (a.nz + kBfNZ * 16 - 1) / (kBfNZ * 16);
+    a.nzt = (a.nz + nzs * 16 - 1) / (nzs * 16);
     a.split = P.adj_split;
     a.nvox = P.nvox;
     a.tab = static_cast<const __bf16*>(P.d_ptab_a);
-    lds = adj_bf16_lds(P, nv, wr, a.tab != nullptr);
+    lds = adj_bf16_lds(P, nv, wr, a.tab != nullptr, nzs);
     if (lds > kLdsMaxB) fail(UFSS_ERR_UNSUPPORTED, "aperture window too wide for the BF16 GEMM path");
     a.nblk = a.ntx * a.nty * a.nzt * a.split;
     return a.nblk;
@@ -777,15 +786,21 @@ void launch_forward_gemm_bf16(const Plan& P, hipStream_t s) {
 void launch_adjoint_gemm_bf16(const Plan& P, cf32* out, hipStream_t s, bool sum) {
     AdjB a;
     size_t lds;
-    const int nv = bf_np(P), wr = P.bf_adj_rows == 2 ? 2 : 1;
-    adjb_args(P, out, a, lds, nv, wr);
+    const int nv = bf_np(P), wr = P.bf_adj_rows == 2 ? 2 : 1, nzs = P.bf_adj_nz == 2 ? 2 : 4;
+    adjb_args(P, out, a, lds, nv, wr, nzs);
     const dim3 grid(a.nblk), block(256);
-#define UFSS_AB(NVV, WRV) hipLaunchKernelGGL((adj_gemm_bf16_kernel<NVV, kBfNZ, WRV>), grid, block, lds, s, a)
+#define UFSS_AB(NVV, NZV, WRV) hipLaunchKernelGGL((adj_gemm_bf16_kernel<NVV, NZV, WRV>), grid, block, lds, s, a)
+#define UFSS_ABZ(NVV, WRV)                                  \
+    do {                                                    \
+        if (nzs == 2) UFSS_AB(NVV, 2, WRV);                 \
+        else UFSS_AB(NVV, 4, WRV);                          \
+    } while (0)
     if (nv == 4) {
-        if (wr == 2) UFSS_AB(4, 2); else UFSS_AB(4, 1);
+        if (wr == 2) UFSS_ABZ(4, 2); else UFSS_ABZ(4, 1);
     } else {
-        if (wr == 2) UFSS_AB(2, 2); else UFSS_AB(2, 1);
+        if (wr == 2) UFSS_ABZ(2, 2); else UFSS_ABZ(2, 1);
     }
+#undef UFSS_ABZ
 #undef UFSS_AB
     UFSS_HIP(hipGetLastError());
     if (a.split > 1 && sum) launch_sum_parts(P.d_gpart, a.split, P.nvox, out, s);
@@ -881,7 +896,7 @@ size_t bf16_desc_size(GemmKind k) { return k == GemmKind::FwdBF16 ? sizeof(FwdB)
 int bf16_make_desc(GemmKind k, const Plan& P, const void* in, void* out, void* desc, size_t* lds) {
     (void)in;
     if (k == GemmKind::FwdBF16) return fwdb_args(P, *static_cast<FwdB*>(desc), *lds, 2, kBfNB, 1);
-    return adjb_args(P, static_cast<cf32*>(out), *static_cast<AdjB*>(desc), *lds, 2, 1);
+    return adjb_args(P, static_cast<cf32*>(out), *static_cast<AdjB*>(desc), *lds, 2, 1, kBfNZ);
 }
 
 void bf16_launch_grouped(GemmKind k, const void* descs, const int2* blk, int nblocks, size_t lds,

@@ -73,6 +73,7 @@ struct Plan {
                                    // (raw output holds fwd_split * fwd_zsplit partials)
     int fwd_np = 2, adj_np = 2;    // FP32 GEMMs: 16-position sub-tiles per wave (2 or 4)
     int bf_fwd_rows = 1, bf_adj_rows = 1;   // BF16 GEMMs: rows of waves in a tile (1 or 2)
+    int bf_adj_nz = 4;             // BF16 adjoint: 16-depth sub-tiles per wave (2 or 4)
     int fwd_zc = 16, adj_kc = 16;  // FP32 GEMMs: preferred staged depth / bin chunk (16 or 8)
     int adj_split = 1;             // split of the adjoint GEMM's d_y range
     cf32* d_gpart = nullptr;       // adjoint partials [adj_split][nvox] (adj_split > 1)

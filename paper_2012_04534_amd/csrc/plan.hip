@@ -537,7 +537,6 @@ Plan* plan_create(const ufss_geom* g, int m, int per_position, const int32_t* bi
 // Change the split-K factors of the GEMM path (reallocating their partials).
 void plan_set_splits(Plan& P, int fs, int as, int zs) {
     if (fs < 1 || as < 1 || zs < 1) fail(UFSS_ERR_INVALID_ARG, "split factors must be >= 1");
-    if (P.dtype == UFSS_BF16) zs = 1;                 // the BF16 forward splits d_y only
     const size_t mu = P.ubins_h.size();
     if (fs * zs != P.fwd_split * P.fwd_zsplit) {
         UFSS_HIP(hipDeviceSynchronize());
@@ -586,10 +585,11 @@ void plan_info(const Plan* P, ufss_plan_info* info) {
     info->adj_split = P->adj_split;
     const bool f32_gemm = P->algo == UFSS_ALGO_GEMM && P->dtype == UFSS_F32;
     info->fwd_waves = f32_gemm ? std::max(1, std::min(P->fwd_nw, ((int)P->ubins_h.size() + 15) / 16)) : 1;
-    info->fwd_zsplit = f32_gemm ? P->fwd_zsplit : 1;
+    info->fwd_zsplit = P->algo == UFSS_ALGO_GEMM ? P->fwd_zsplit : 1;
     info->phasor_tables = P->d_ptab_f != nullptr;
     info->fwd_tile = f32_gemm ? fwd_tile_np(*P) : 0;
     info->adj_tile = f32_gemm ? adj_tile_np(*P) : 0;
+    if (P->algo == UFSS_ALGO_GEMM && P->dtype == UFSS_BF16) info->adj_tile = P->bf_adj_nz;
     const bool bf_gemm = P->algo == UFSS_ALGO_GEMM && P->dtype == UFSS_BF16;
     info->fwd_rows = bf_gemm ? P->bf_fwd_rows : 0;
     info->adj_rows = bf_gemm ? P->bf_adj_rows : 0;

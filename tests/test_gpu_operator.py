@@ -157,7 +157,10 @@ def shipped_tiling(plan, g, dtype):
     e = json.load(open(SHIPPED)).get(key)
     if e is None or len(e) < 12:
         return None
-    fs, as_, _, _, nw, zs, npf, npa, rf, ra, zc, kc = [int(v) for v in e]
+    vals = [int(v) for v in e]
+    fs, as_, _, _, nw, zs, npf, npa, rf, ra, zc, kc = vals[:12]
+    if dtype == "bf16":          # BF16: adj_tile carries the adjoint's depth sub-tiles
+        npa = vals[12] if len(vals) > 12 else 4
     return dict(fwd_split=fs, adj_split=as_, fwd_waves=nw, fwd_zsplit=zs, fwd_tile=npf, adj_tile=npa,
                 fwd_rows=rf, adj_rows=ra, fwd_chunk=zc, adj_chunk=kc)
 
@@ -242,7 +245,9 @@ def test_manual_tiling_same_operator(dtype, dev):
                (9, 9, 8, 10, 4, 2, 0, 0, 16, 8), (64, 64, 3, 64, 2, 4, 0, 0, 8, 16)]
     if dtype == "bf16":
         rows = [(1, 1), (2, 2), (1, 2), (2, 1)]
-        tilings = [(t[0], t[1], 0, 1, 0, 0) + rows[n] + (0, 0) for n, t in enumerate(tilings)]
+        zsplits = [1, 2, 3, 64]          # depth parts (64: most of them empty)
+        nzs = [4, 2, 2, 4]               # adjoint depth sub-tiles per wave
+        tilings = [(t[0], t[1], 0, zsplits[n], 0, nzs[n]) + rows[n] + (0, 0) for n, t in enumerate(tilings)]
     xt = torch.from_numpy(x).to(dev)
     yt = torch.from_numpy(y).to(dev)
     for t in tilings:
@@ -253,7 +258,8 @@ def test_manual_tiling_same_operator(dtype, dev):
             assert (info["fwd_tile"], info["adj_tile"], info["fwd_zsplit"]) == (t[4], t[5], t[3])
             assert (info["fwd_chunk"], info["adj_chunk"]) == (t[8], t[9])
         else:
-            assert (info["fwd_rows"], info["adj_rows"]) == (t[6], t[7])
+            assert (info["fwd_rows"], info["adj_rows"], info["fwd_zsplit"], info["adj_tile"]) == \
+                (t[6], t[7], t[3], t[5])
         yo = torch.empty_like(yt)
         xo = torch.empty_like(xt)
         u.ufss_forward(plan, xt, yo)
@@ -320,8 +326,10 @@ def random_case(rng):
         t.update(fwd_waves=int(rng.integers(1, 9)), fwd_zsplit=int(rng.integers(1, 5)),
                  fwd_tile=int(rng.choice([2, 4])), adj_tile=int(rng.choice([2, 4])),
                  fwd_chunk=int(rng.choice([8, 16])), adj_chunk=int(rng.choice([8, 16])))
-    elif ny > 1:
-        t.update(fwd_rows=int(rng.integers(1, 3)), adj_rows=int(rng.integers(1, 3)))
+    else:
+        t.update(fwd_zsplit=int(rng.integers(1, 5)), adj_tile=int(rng.choice([2, 4])))
+        if ny > 1:
+            t.update(fwd_rows=int(rng.integers(1, 3)), adj_rows=int(rng.integers(1, 3)))
     return g, m, per_pos, dtype, t
 
 
