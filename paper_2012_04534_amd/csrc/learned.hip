@@ -39,14 +39,24 @@ struct Dims {
 
 static int nblk(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + kLT - 1) / kLT)); }
 
-__device__ __forceinline__ bool nb(const Dims& d, int64_t v, int e, int64_t& w) {
+// Grid coordinates of voxel v, computed once per voxel in 32-bit arithmetic
+// (a network's grid holds fewer than 2^31 voxels).
+struct VoxC {
+    int z, x, y;
+};
+__device__ __forceinline__ VoxC vox_coords(const Dims& d, int64_t v) {
+    const int vi = (int)v, t = vi / d.nz;
+    return VoxC{vi - t * d.nz, t % d.nx, t / d.nx};
+}
+
+// Neighbour w = v + e of voxel v (coordinates p) for offset index e; false
+// outside the grid.  With the offset loops unrolled, e is a constant.
+__device__ __forceinline__ bool nb(const Dims& d, const VoxC& p, int64_t v, int e, int64_t& w) {
     const int ez = e % 3 - 1, ex = (e / 3) % 3 - 1, ey = e / 9 - 1;
-    const int vz = (int)(v % d.nz);
-    const int64_t t = v / d.nz;
-    const int vx = (int)(t % d.nx), vy = (int)(t / d.nx);
-    const int y = vy + ey, x = vx + ex, z = vz + ez;
-    if (y < 0 || y >= d.ny || x < 0 || x >= d.nx || z < 0 || z >= d.nz) return false;
-    w = ((int64_t)y * d.nx + x) * d.nz + z;
+    if ((unsigned)(p.y + ey) >= (unsigned)d.ny || (unsigned)(p.x + ex) >= (unsigned)d.nx ||
+        (unsigned)(p.z + ez) >= (unsigned)d.nz)
+        return false;
+    w = v + ((int64_t)ey * d.nx + ex) * d.nz + ez;
     return true;
 }
 
@@ -91,9 +101,11 @@ __global__ __launch_bounds__(kLT) void k_conv1(Dims d, int ch, const cf32* __res
     for (int64_t v = (int64_t)blockIdx.x * kLT + threadIdx.x; v < d.n; v += (int64_t)gridDim.x * kLT) {
         float acc[kMaxCh];
         for (int o = 0; o < ch; ++o) acc[o] = w[ch * 54 + o];
+        const VoxC pc = vox_coords(d, v);
+#pragma unroll
         for (int e = 0; e < 27; ++e) {
             int64_t q;
-            if (!nb(d, v, e, q)) continue;
+            if (!nb(d, pc, v, e, q)) continue;
             const float ur = uf[2 * q] * ic, ui = uf[2 * q + 1] * ic;
             for (int o = 0; o < ch; ++o) acc[o] += w[o * 54 + e] * ur + w[o * 54 + 27 + e] * ui;
         }
@@ -113,9 +125,11 @@ __global__ __launch_bounds__(kLT) void k_conv2(Dims d, int ch, const float* __re
     __syncthreads();
     for (int64_t v = (int64_t)blockIdx.x * kLT + threadIdx.x; v < d.n; v += (int64_t)gridDim.x * kLT) {
         float ar = w[2 * ch * 27], ai = w[2 * ch * 27 + 1];
+        const VoxC pc = vox_coords(d, v);
+#pragma unroll
         for (int e = 0; e < 27; ++e) {
             int64_t q;
-            if (!nb(d, v, e, q)) continue;
+            if (!nb(d, pc, v, e, q)) continue;
             for (int c = 0; c < ch; ++c) {
                 const float hv = h[(int64_t)c * d.n + q];
                 ar += w[c * 27 + e] * hv;
@@ -159,9 +173,11 @@ __global__ __launch_bounds__(kLT) void k_conv2_bwd(Dims d, int ch, const cf32* _
     for (int64_t v = (int64_t)blockIdx.x * kLT + threadIdx.x; v < d.n; v += (int64_t)gridDim.x * kLT) {
         float acc[kMaxCh];
         for (int c = 0; c < ch; ++c) acc[c] = 0.f;
+        const VoxC pc = vox_coords(d, v);
+#pragma unroll
         for (int e = 0; e < 27; ++e) {
             int64_t q;
-            if (!nb(d, v, 26 - e, q)) continue;     // v - e
+            if (!nb(d, pc, v, 26 - e, q)) continue;     // v - e
             const cf32 g = dx[q];
             for (int c = 0; c < ch; ++c) acc[c] += w[c * 27 + e] * g.re + w[(ch + c) * 27 + e] * g.im;
         }
@@ -179,9 +195,11 @@ __global__ __launch_bounds__(kLT) void k_conv1_bwd(Dims d, int ch, const float* 
     __syncthreads();
     for (int64_t v = (int64_t)blockIdx.x * kLT + threadIdx.x; v < d.n; v += (int64_t)gridDim.x * kLT) {
         float ar = 0.f, ai = 0.f;
+        const VoxC pc = vox_coords(d, v);
+#pragma unroll
         for (int e = 0; e < 27; ++e) {
             int64_t q;
-            if (!nb(d, v, 26 - e, q)) continue;
+            if (!nb(d, pc, v, 26 - e, q)) continue;
             for (int o = 0; o < ch; ++o) {
                 const float gv = dh[(int64_t)o * d.n + q];
                 ar += w[o * 54 + e] * gv;
@@ -209,9 +227,11 @@ __global__ __launch_bounds__(kLT) void k_wgrad(Dims d, const float* __restrict__
     for (int64_t v = v0 + threadIdx.x; v < v1; v += kLT) {
         const float g = dout[o * ocs + v * ovs];
         if (g == 0.f) continue;
+        const VoxC pc = vox_coords(d, v);
+#pragma unroll
         for (int e = 0; e < 27; ++e) {
             int64_t q;
-            if (nb(d, v, e, q)) acc[e] += g * in[c * ics + q * ivs];
+            if (nb(d, pc, v, e, q)) acc[e] += g * in[c * ics + q * ivs];
         }
         acc[27] += g;
     }
@@ -392,6 +412,7 @@ static int stage_size(int ch) { return 2 + ch * 54 + ch + 2 * ch * 27 + 2; }
 Net* net_create(Plan* P, int S, int ch, double L, double mu, uint64_t seed) {
     if (!P) fail(UFSS_ERR_INVALID_ARG, "plan is NULL");
     if (S < 1 || S > 256 || ch < 1 || ch > kMaxCh) fail(UFSS_ERR_INVALID_ARG, "stages in [1,256], channels in [1,8]");
+    if (P->nvox >= (int64_t(1) << 31)) fail(UFSS_ERR_UNSUPPORTED, "the network needs fewer than 2^31 voxels");
     if (!(L > 0) || !(mu > 0)) fail(UFSS_ERR_INVALID_ARG, "L and mu must be positive");
     Net* N = new Net();
     try {
