@@ -175,6 +175,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--quick", action="store_true", help="n_f in {1, 10}, mu = 0.1 only")
     ap.add_argument("--algos", action="store_true", help="time both per-position algorithms")
+    ap.add_argument("--time-only", action="store_true",
+                    help="with --algos: the timings only, no reconstructions")
     ap.add_argument("--crb", action="store_true", help="the Cramer-Rao study only")
     ap.add_argument("--seed", type=int, default=5001)
     args = ap.parse_args(argv)
@@ -192,6 +194,8 @@ def main(argv=None):
         for nf in W.SIM_NF:
             print(json.dumps(dict(kind="algo_time", n_f=nf, **time_algos(g, nf, args.seed, dev))),
                   flush=True)
+        if args.time_only:
+            return
     for sname, xtrue in scenes.items():
         for mu in mus:
             for nf in nfs:
