@@ -410,6 +410,29 @@ int ufss_fista_batched(int32_t n, const ufss_plan_t* plans, const void* const* y
                        void* const* xs, const double* lambdas, const double* Ls,
                        int32_t iters, double* res_out, ufss_stream_t stream);
 
+/* Synthetic data on the device (training and evaluation scenes of the learned
+ * solver; the scenes follow the simulated point-scatterer specimens of Sec.
+ * VII).  Random numbers: SplitMix64 (Steele, Lea & Flood 2014) keyed `seed`,
+ * whose k-th output is mix64(seed + k 0x9E3779B97F4A7C15).
+ * ufss_synth_scene: x (DEVICE complex64 [ny][nx][nz]) = n_scat distinct point
+ *   scatterers at voxels with depth index < max_depth, real amplitudes
+ *   amp_lo + (amp_hi - amp_lo) u, plus (back_wall >= 0) amplitude 1 at every
+ *   voxel of depth index back_wall.  Draw: scatterer j takes voxel index
+ *   floor(next() N / 2^64) of the N = ny nx max_depth allowed ones (y, then x,
+ *   then depth; redrawn while it repeats an earlier index), then the n_scat
+ *   amplitudes with u = (next() >> 11) 2^-53.  n_scat <= 4096.
+ * ufss_synth_measure: y (DEVICE complex64 [ny][nx][m]) = A x + n with
+ *   n_i ~ CN(0, s^2), s^2 = ||A x||^2 / (ny nx m 10^(snr_db/10)) (||A x||^2 in
+ *   FP64 on the device, no host round trip); value i reads outputs 2i + 1 and
+ *   2i + 2: u1 = ((out >> 11) + 1) 2^-53, u2 = (out >> 11) 2^-53,
+ *   n_i = s sqrt(-log u1) (cos 2 pi u2 + j sin 2 pi u2) (FP64).  snr_db = +inf:
+ *   no noise.  Both are asynchronous on `stream`. */
+int ufss_synth_scene(const ufss_geom* g, int32_t n_scat, double amp_lo, double amp_hi,
+                     int32_t max_depth, int32_t back_wall, uint64_t seed, void* x,
+                     ufss_stream_t stream);
+int ufss_synth_measure(ufss_plan_t plan, const void* x, double snr_db, uint64_t seed, void* y,
+                       ufss_stream_t stream);
+
 /* Persistent batch (paper Alg. 1 on every scan of an uneven batch): the same
  * grouped launches as ufss_fista_batched, with the start state (gamma = x,
  * ||gamma||_1) and `iters` iterations captured ONCE into a hipGraph at

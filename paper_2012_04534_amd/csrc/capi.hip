@@ -31,6 +31,9 @@ int phasor_forward_blocks(const Plan& P);
 int fista_batched(int n, Plan* const* plans, const cf32* const* ys, cf32* const* xs,
                   const double* lambdas, const double* Ls, int iters, hipStream_t stream,
                   double* res_out);
+void synth_scene(const ufss_geom* g, int n, double lo, double hi, int max_depth, int back_wall,
+                 uint64_t seed, cf32* x, hipStream_t s);
+void synth_measure(Plan& P, const cf32* x, double snr_db, uint64_t seed, cf32* y, hipStream_t s);
 struct BatchRun;
 BatchRun* batch_create(int n, Plan* const* plans, const cf32* const* ys, cf32* const* xs,
                        const double* lambdas, const double* Ls, int iters, hipStream_t stream);
@@ -613,6 +616,23 @@ int ufss_fista_batched(int32_t n, const ufss_plan_t* plans, const void* const* y
     return ufss::fista_batched(n, ps.data(), reinterpret_cast<const ufss::cf32* const*>(ys),
                                reinterpret_cast<ufss::cf32* const*>(xs), lambdas, Ls, iters,
                                static_cast<hipStream_t>(stream), res_out);
+    UFSS_GUARD_END
+}
+
+int ufss_synth_scene(const ufss_geom* g, int32_t n_scat, double amp_lo, double amp_hi,
+                     int32_t max_depth, int32_t back_wall, uint64_t seed, void* x,
+                     ufss_stream_t stream) {
+    UFSS_GUARD_BEGIN
+    ufss::synth_scene(g, n_scat, amp_lo, amp_hi, max_depth, back_wall, seed,
+                      static_cast<ufss::cf32*>(x), static_cast<hipStream_t>(stream));
+    UFSS_GUARD_END
+}
+
+int ufss_synth_measure(ufss_plan_t plan, const void* x, double snr_db, uint64_t seed, void* y,
+                       ufss_stream_t stream) {
+    UFSS_GUARD_BEGIN
+    ufss::synth_measure(*as_plan(plan), static_cast<const ufss::cf32*>(x), snr_db, seed,
+                        static_cast<ufss::cf32*>(y), static_cast<hipStream_t>(stream));
     UFSS_GUARD_END
 }
 

@@ -5,12 +5,13 @@ network forward / backward, Adam, the residual norms of the fallback rule)
 runs in libufss through the binding or in torch device reductions.
 
 Data: scenes drawn like the 32 x 32 C-scan workload (seeded point scatterers
-plus the back wall), measurements y = A x + n at a drawn SNR, and as target
-the plain FP32 FISTA iterate after ``ref_iters`` (200) iterations on the same
-y -- the network learns to reach FISTA's answer in fewer stages.  Scene i of a
-set keyed by ``seed0`` draws its scatterer count and SNR from the generator
-keyed (seed0, i), its scene from seed0 * 100003 + i and its noise from
-seed0 * 7919 + i, so any slice of a set can be rebuilt on its own.
+plus the back wall), measurements y = A x + n at a drawn SNR, both generated
+on the device, and as target the plain FP32 FISTA iterate after ``ref_iters``
+(200) iterations on the same y -- the network learns to reach FISTA's answer
+in fewer stages.  Scene i of a set keyed by ``seed0`` draws its scatterer
+count and SNR from the generator keyed (seed0, i), its scene from the device
+stream seed0 * 100003 + i and its noise from seed0 * 7919 + i, so any slice of
+a set can be rebuilt on its own.
 
 Inference follows the fallback rule: if the network's residual ||A x_net - y||
 exceeds ``factor`` (1.1) times the residual of the FISTA answer, plain FISTA is
@@ -21,7 +22,6 @@ import time
 import numpy as np
 
 from . import ufss
-from . import workloads as W
 
 TRAIN_SEED = 1005
 EVAL_SEED = 2005
@@ -34,18 +34,20 @@ def scene_draw(seed0, i, n_scat=(5, 30), snr=(10.0, 20.0)):
 
 
 def measurements(plan, geom, seed0, i, back_wall=None, dev=None, n_scat=(5, 30), snr=(10.0, 20.0)):
-    """(y, x_true) device tensors of scene i of the set keyed seed0."""
+    """(y, x_true) device tensors of scene i of the set keyed seed0, generated
+    on the device (ufss_synth_scene, ufss_synth_measure: no host round trip);
+    scatterers lie above the back wall's depth minus 8."""
     import torch
     dev = dev or torch.device("cuda:0")
     k, snr_db = scene_draw(seed0, i, n_scat, snr)
+    shape_x = (geom["ny"], geom["nx"], geom["nz"])
     shape_y = (geom["ny"], geom["nx"], plan.m)
-    x = W.scene(geom, k, amp=(0.5, 1.0), seed=seed0 * 100003 + i, back_wall=back_wall)
-    xt = torch.from_numpy(x.astype(np.complex64)).to(dev)
-    y0 = torch.empty(shape_y, dtype=torch.complex64, device=dev)
-    ufss.ufss_forward(plan, xt, y0)
-    sig = W.noise_sigma(float((y0.abs() ** 2).sum().item()), y0.numel(), snr_db)
-    y = y0 + sig * torch.from_numpy(W.cn(shape_y, seed0 * 7919 + i).astype(np.complex64)).to(dev)
-    return y.contiguous(), xt
+    max_depth = geom["nz"] if back_wall is None else back_wall - 8
+    xt = torch.empty(shape_x, dtype=torch.complex64, device=dev)
+    ufss.ufss_synth_scene(geom, k, (0.5, 1.0), max_depth, back_wall, seed0 * 100003 + i, xt)
+    y = torch.empty(shape_y, dtype=torch.complex64, device=dev)
+    ufss.ufss_synth_measure(plan, xt, snr_db, seed0 * 7919 + i, y)
+    return y, xt
 
 
 def make_dataset(plan, geom, n, seed0, ref_iters, L, mu=0.1, offset=0, back_wall=None, dev=None,

@@ -31,6 +31,7 @@ EXPORTED = [
     "ufss_fista_backtracking",
     "ufss_shrink_update", "ufss_shrink_update_noalloc", "ufss_absmax", "ufss_time_kernel", "ufss_fista_batched",
     "ufss_batch_create", "ufss_batch_run", "ufss_batch_set_lambdas", "ufss_batch_destroy",
+    "ufss_synth_scene", "ufss_synth_measure",
     "ufss_autotune", "ufss_plan_set_tiling", "ufss_plan_kernel_timing", "ufss_plan_kernel_times", "ufss_plan_set_phasor_tables", "ufss_unrolled_create", "ufss_unrolled_destroy", "ufss_unrolled_params",
     "ufss_unrolled_forward", "ufss_unrolled_grad", "ufss_unrolled_train_step",
     "ufss_unrolled_save", "ufss_unrolled_load",
@@ -142,6 +143,8 @@ def lib():
             "ufss_fista_batched": ([I32, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
                                     ctypes.POINTER(D), ctypes.POINTER(D), I32, ctypes.POINTER(D), P],
                                    ctypes.c_int),
+            "ufss_synth_scene": ([ctypes.POINTER(Geom), I32, D, D, I32, I32, U64, P, P], ctypes.c_int),
+            "ufss_synth_measure": ([P, P, D, U64, P, P], ctypes.c_int),
             "ufss_batch_create": ([I32, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
                                    ctypes.POINTER(D), ctypes.POINTER(D), I32, P, ctypes.POINTER(P)],
                                   ctypes.c_int),
@@ -480,6 +483,23 @@ def ufss_fista_batched(plans, ys, xs, lambdas, Ls, iters, stream=None):
     res = (ctypes.c_double * n)()
     _check(lib().ufss_fista_batched(n, hp, yp, xp, lam, Lc, int(iters), res, _stream(stream)))
     return np.array(list(res))
+
+
+def ufss_synth_scene(g, n_scat, amp, max_depth, back_wall, seed, x, stream=None):
+    """Point-scatterer scene drawn on the device into x (see ufss.h)."""
+    _numel_check(x, g["nx"] * g["ny"] * g["nz"], "x")
+    geom = make_geom(g)
+    _check(lib().ufss_synth_scene(ctypes.byref(geom), int(n_scat), float(amp[0]), float(amp[1]),
+                                  int(max_depth), int(-1 if back_wall is None else back_wall),
+                                  ctypes.c_uint64(seed & (2 ** 64 - 1)), _ptr(x, "x"), _stream(stream)))
+
+
+def ufss_synth_measure(plan, x, snr_db, seed, y, stream=None):
+    """y = A x + complex Gaussian noise at snr_db, on the device (see ufss.h)."""
+    _numel_check(x, plan.nvox, "x")
+    _numel_check(y, plan.nmeas, "y")
+    _check(lib().ufss_synth_measure(plan.handle, _ptr(x, "x"), float(snr_db),
+                                    ctypes.c_uint64(seed & (2 ** 64 - 1)), _ptr(y, "y"), _stream(stream)))
 
 
 class Batch:

@@ -177,6 +177,59 @@ def scene(g, n_scat, amp=(1.0, 1.0), seed=0, back_wall=None, phase=0.0,
     return x
 
 
+# Counter-based generator of the device-side synthetic data (the library's
+# ufss_synth_scene / ufss_synth_measure draw the same numbers): SplitMix64
+# (Steele, Lea & Flood 2014), whose k-th output of the stream keyed s is
+# mix64(s + k gamma).
+_SM_MASK = (1 << 64) - 1
+_SM_GAMMA = 0x9E3779B97F4A7C15
+
+
+def splitmix64_outputs(seed, first, count):
+    """Outputs first .. first + count - 1 (1-based) of the stream keyed seed (uint64)."""
+    k = np.arange(first, first + count, dtype=np.uint64)
+    z = (np.uint64(seed & _SM_MASK) + k * np.uint64(_SM_GAMMA))
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def synth_scene(g, n_scat, amp, max_depth, back_wall, seed):
+    """The scene ufss_synth_scene draws on the device, [ny, nx, nz] complex128:
+    n_scat distinct voxels with depth index < max_depth (index j of scatterer j
+    = floor(out N / 2^64) over the N = ny nx max_depth allowed voxels, redrawn
+    on repeats), then the amplitudes lo + (hi - lo) (out >> 11) 2^-53, plus a
+    back wall of amplitude 1 at depth index back_wall (None: none)."""
+    nx, ny, nz = g["nx"], g["ny"], g["nz"]
+    nallow = ny * nx * max_depth
+    x = np.zeros((ny, nx, nz), dtype=np.complex128)
+    if back_wall is not None:
+        x[:, :, back_wall] = 1.0
+    k = 1
+    chosen = []
+    while len(chosen) < n_scat:
+        v = (int(splitmix64_outputs(seed, k, 1)[0]) * nallow) >> 64
+        k += 1
+        if v not in chosen:
+            chosen.append(v)
+    u = (splitmix64_outputs(seed, k, n_scat) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    for v, uj in zip(chosen, u):
+        iy, rem = divmod(v, nx * max_depth)
+        ix, iz = divmod(rem, max_depth)
+        x[iy, ix, iz] = np.float32(amp[0] + (amp[1] - amp[0]) * uj)
+    return x
+
+
+def synth_noise(count, seed):
+    """The CN(0, 1) values ufss_synth_measure scales and adds (complex128 [count]):
+    value i from outputs 2i + 1 and 2i + 2 by Box-Muller."""
+    o1 = splitmix64_outputs(seed, 1, 2 * count)
+    u1 = ((o1[0::2] >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
+    u2 = (o1[1::2] >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    r = np.sqrt(-2.0 * np.log(u1))
+    return r * (np.cos(2.0 * math.pi * u2) + 1j * np.sin(2.0 * math.pi * u2)) / math.sqrt(2.0)
+
+
 def rademacher(shape, seed):
     """Independent uniform signs in {-1, +1} (int8), for the mixing Sigma of the
     random sampling strategy."""
