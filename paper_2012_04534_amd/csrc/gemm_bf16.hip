@@ -166,6 +166,7 @@ struct FwdB {
     int nx, ny, nz, wx, wy, mu;
     int sw, ntx, nty, nbt, split;
     int zsplit;            // depth-chunk split (partials [split * zsplit])
+    int bt0, tile_bins;    // first bin tile of this launch, bins per (full) bin tile
     int64_t npos;
     int nblk;              // blocks of this plan's grid
     const __bf16* tab;     // phasor tiles [wy+1][wx+1][nzc][mu][2][32] or null
@@ -177,7 +178,8 @@ struct FwdB {
 template <int NP, int NB, int WR>
 __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nblk, unsigned char* smem) {
     static_assert(NB * 16 <= 64, "table tiles are copied in two passes of 256 x 16 bytes");
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int sw = a.sw, sh = 16 / sw;
     constexpr int WC = 4 / WR;                   // waves per tile row
     const int tpx = WC * NP * sw, tpy = WR * sh;
@@ -187,7 +189,7 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
     if (per_xcd * 8 == nblk) b = (b % 8) * per_xcd + b / 8;
     const int ntile = a.ntx * a.nty;
     const int tile = b % ntile;
-    const int bt = (b / ntile) % a.nbt;
+    const int bt = a.bt0 + (b / ntile) % a.nbt;
     const int sp = b / (ntile * a.nbt);           // partial slot: d_y part + split * depth part
     const int dsp = sp % a.split, zsp = sp / a.split;
     const int px0 = (tile % a.ntx) * tpx, py0 = (tile / a.ntx) * tpy;
@@ -209,12 +211,18 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
     dy_hi = min(dy_hi, dy_lo + chunk - 1);
     const int dx_lo = max(-a.wx, px0 - (a.nx - 1));
     const int dx_hi = min(a.wx, px0 + tpx - 1);
+    // offsets at which this wave's own positions see a voxel column inside
+    // the grid (wave-uniform; outside them its products would only read the
+    // zero cell, so it skips them and leaves the matrix cores to other waves)
+    const int wpx0 = px0 + wave_x * NP * sw, wpy0 = py0 + wave_y * sh;
+    const int wdx_lo = wpx0 - (a.nx - 1), wdx_hi = min(wpx0 + NP * sw, a.nx) - 1;
+    const int wdy_lo = wpy0 - (a.ny - 1), wdy_hi = min(wpy0 + sh, a.ny) - 1;
     // this block's depth chunks (an empty range leaves zeros in its partial slot)
     const int nzc_all = (a.nz + ZCB - 1) / ZCB;
     const int zc_per = (nzc_all + a.zsplit - 1) / a.zsplit;
     const int z_lo = zsp * zc_per * ZCB, z_hi = min(a.nz, (zsp + 1) * zc_per * ZCB);
 
-    const int mb0 = bt * NB * 16;
+    const int mb0 = bt * a.tile_bins;
     const int nbins = min(NB * 16, a.mu - mb0);          // valid bins of this tile
     const int nb_act = (nbins + 15) / 16;                // active bin sub-tiles
     const int i = lane & 15, kq = lane >> 4;
@@ -265,6 +273,7 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
             // to arrive.
             const int adx_hi = max(dx_hi, -dx_lo);
             const int adx_lo = (dx_lo <= 0 && dx_hi >= 0) ? 0 : min(dx_lo < 0 ? -dx_lo : dx_lo, dx_hi < 0 ? -dx_hi : dx_hi);
+            const bool wy_ok = dy >= wdy_lo && dy <= wdy_hi;
             TabRegs Rn;
             if (dx_lo <= dx_hi) {
                 if (a.tab) {
@@ -289,9 +298,10 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
                 const __bf16* pc = ptile + (size_t)buf * 2 * NB * 16 * PROW;
                 const __bf16* ps = pc + NB * 16 * PROW;
                 // every bin sub-tile runs (no data-dependent exit), so the
-                // 4 NP NB products issue in four independent passes; the
-                // sub-tiles past nb_act read stale LDS rows into accumulators
-                // that are never stored
+                // 4 NP NB products issue in four independent passes; a last
+                // bin tile with fewer sub-tiles is a launch of its own with a
+                // smaller NB (host), else (grouped launches) the sub-tiles past
+                // nb_act read stale LDS rows into accumulators never stored
                 bf8 c8[NB], s8[NB];
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
@@ -334,8 +344,9 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
                             acc_im[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xr[s], ns8, acc_im[s][nb], 0, 0, 0);
                     }
                 };
-                if (adx <= dx_hi) apply(adx);                  // d_x = +|d_x|
-                if (adx > 0 && -adx >= dx_lo) apply(-adx);     // d_x = -|d_x|
+                if (wy_ok && adx <= dx_hi && adx >= wdx_lo && adx <= wdx_hi) apply(adx);   // d_x = +|d_x|
+                if (wy_ok && adx > 0 && -adx >= dx_lo && -adx >= wdx_lo && -adx <= wdx_hi)
+                    apply(-adx);                                                          // d_x = -|d_x|
                 if (more && a.tab) {
                     __bf16* pn = ptile + (size_t)(buf ^ 1) * 2 * NB * 16 * PROW;
                     tab_store(Rn, pn, pn + NB * 16 * PROW, prow_count);
@@ -399,7 +410,8 @@ struct AdjB {
 
 template <int NV, int NZ, int WR>
 __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nblk, unsigned char* smem) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int sw = a.sw, sh = 16 / sw;
     constexpr int WC = 4 / WR;                   // waves per tile row
     const int tvx = WC * NV * sw, tvy = WR * sh;
@@ -432,6 +444,11 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
     dy_lo += sp * chunk;
     dy_hi = min(dy_hi, dy_lo + chunk - 1);
     const int dx_lo = max(-a.wx, -(vx0 + tvx - 1)), dx_hi = min(a.wx, a.nx - 1 - vx0);
+    // offsets at which this wave's own voxels see a position inside the grid
+    // (wave-uniform; the others are skipped, as in the forward)
+    const int wvx0 = vx0 + wave_x * NV * sw, wvy0 = vy0 + wave_y * sh;
+    const int wdx_lo = -(min(wvx0 + NV * sw, a.nx) - 1), wdx_hi = a.nx - 1 - wvx0;
+    const int wdy_lo = -(min(wvy0 + sh, a.ny) - 1), wdy_hi = a.ny - 1 - wvy0;
 
     const int i = lane & 15, kq = lane >> 4;
     const int nz_act = min(NZ, (a.nz - zw0 + 15) / 16);   // active depth sub-tiles
@@ -497,6 +514,7 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
             // with two steps of prefetch
             const int adx_hi = max(dx_hi, -dx_lo);
             const int adx_lo = (dx_lo <= 0 && dx_hi >= 0) ? 0 : min(dx_lo < 0 ? -dx_lo : dx_lo, dx_hi < 0 ? -dx_hi : dx_hi);
+            const bool wy_ok = dy >= wdy_lo && dy <= wdy_hi;
             TabRegs Rn;
             if (dx_lo <= dx_hi) {
                 if (a.tab) {
@@ -563,8 +581,9 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
                             acc_re[s][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ri8[s], ns8, acc_re[s][q], 0, 0, 0);
                     }
                 };
-                if (adx <= dx_hi) apply(adx);                  // d_x = +|d_x|
-                if (adx > 0 && -adx >= dx_lo) apply(-adx);     // d_x = -|d_x|
+                if (wy_ok && adx <= dx_hi && adx >= wdx_lo && adx <= wdx_hi) apply(adx);   // d_x = +|d_x|
+                if (wy_ok && adx > 0 && -adx >= dx_lo && -adx >= wdx_lo && -adx <= wdx_hi)
+                    apply(-adx);                                                          // d_x = -|d_x|
                 if (more && a.tab) {
                     __bf16* pn = ptile + (size_t)(buf ^ 1) * 2 * zspan * PROW;
                     tab_store(Rn, pn, pn + zspan * PROW, zspan);
@@ -719,6 +738,8 @@ static int fwdb_args(const Plan& P, FwdB& a, size_t& lds, int np, int nb, int wr
     a.ntx = (a.nx + tpx - 1) / tpx;
     a.nty = (a.ny + tpy - 1) / tpy;
     a.nbt = (a.mu + nb * 16 - 1) / (nb * 16);
+    a.bt0 = 0;
+    a.tile_bins = nb * 16;
     a.split = P.fwd_split;
     a.zsplit = std::max(1, P.fwd_zsplit);
     a.npos = P.npos;
@@ -764,19 +785,37 @@ void launch_forward_gemm_bf16(const Plan& P, hipStream_t s) {
     size_t lds;
     const int np = bf_np(P), nb = bf_nb(P, np), wr = P.bf_fwd_rows == 2 ? 2 : 1;
     fwdb_args(P, a, lds, np, nb, wr);
-    const dim3 grid(a.nblk), block(256);
-#define UFSS_FB(NPV, NBV, WRV) hipLaunchKernelGGL((fwd_gemm_bf16_kernel<NPV, NBV, WRV>), grid, block, lds, s, a)
-#define UFSS_FBN(NPV, WRV)                                                        \
+    // bin tiles with all nb sub-tiles, then (if shorter) the last tile as a
+    // launch of its own with exactly its active sub-tiles (no MFMA on padding)
+    const int mu = (int)P.ubins_h.size();
+    const int nb_last = (mu - (a.nbt - 1) * nb * 16 + 15) / 16;
+    const int ntile = a.ntx * a.nty, nsplit = a.split * a.zsplit;
+#define UFSS_FB(NPV, NBV, WRV) hipLaunchKernelGGL((fwd_gemm_bf16_kernel<NPV, NBV, WRV>), dim3(b.nblk), dim3(256), lds, s, b)
+#define UFSS_FBN(NBRT, NPV, WRV)                                                  \
     do {                                                                          \
-        if (nb == 4) UFSS_FB(NPV, 4, WRV);                                        \
-        else if (nb == 3) UFSS_FB(NPV, 3, WRV);                                   \
-        else if (nb == 2) UFSS_FB(NPV, 2, WRV);                                   \
+        if (NBRT == 4) UFSS_FB(NPV, 4, WRV);                                      \
+        else if (NBRT == 3) UFSS_FB(NPV, 3, WRV);                                 \
+        else if (NBRT == 2) UFSS_FB(NPV, 2, WRV);                                 \
         else UFSS_FB(NPV, 1, WRV);                                                \
     } while (0)
-    if (np == 4) {
-        if (wr == 2) UFSS_FBN(4, 2); else UFSS_FBN(4, 1);
+    auto launch = [&](const FwdB& b, int nbr) {
+        if (np == 4) {
+            if (wr == 2) UFSS_FBN(nbr, 4, 2); else UFSS_FBN(nbr, 4, 1);
+        } else {
+            if (wr == 2) UFSS_FBN(nbr, 2, 2); else UFSS_FBN(nbr, 2, 1);
+        }
+    };
+    if (nb_last == nb) {
+        launch(a, nb);
     } else {
-        if (wr == 2) UFSS_FBN(2, 2); else UFSS_FBN(2, 1);
+        FwdB full = a, last = a;
+        full.nbt = a.nbt - 1;
+        full.nblk = ntile * full.nbt * nsplit;
+        last.bt0 = a.nbt - 1;
+        last.nbt = 1;
+        last.nblk = ntile * nsplit;
+        if (full.nbt > 0) launch(full, nb);
+        launch(last, nb_last);
     }
 #undef UFSS_FBN
 #undef UFSS_FB
