@@ -62,13 +62,12 @@ __global__ __launch_bounds__(256) void fwd_phasor_kernel(
     for (int j = 0; j < MB; ++j) acc_re[j] = acc_im[j] = 0.f;
 
     // walk t = w * nz + z over the window's columns w = (cy, cx), updating
-    // (cx, cy, z) incrementally (no division per term)
+    // (cx, cy, z) incrementally: a step of 256 terms moves dcol columns and dz
+    // depths (divided once), plus one column when the depth wraps
+    const int dcol = 256 / nz, dz = 256 - dcol * nz;
     int64_t t = threadIdx.x;
-    int z = threadIdx.x, cx = 0, cy = 0;
-    while (z >= nz) {
-        z -= nz;
-        if (++cx == nvx) { cx = 0; ++cy; }
-    }
+    int z = threadIdx.x % nz, cx = threadIdx.x / nz, cy = 0;
+    while (cx >= nvx) { cx -= nvx; ++cy; }
     for (; t < total; t += 256) {
         const int vx = vx_lo + cx, vy = vy_lo + cy;
         cf32 xv = x[((int64_t)vy * nx + vx) * nz + z];
@@ -88,11 +87,10 @@ __global__ __launch_bounds__(256) void fwd_phasor_kernel(
             acc_re[j] += xv.re * c + xv.im * s;
             acc_im[j] += xv.im * c - xv.re * s;
         }
-        z += 256;
-        while (z >= nz) {
-            z -= nz;
-            if (++cx == nvx) { cx = 0; ++cy; }
-        }
+        z += dz;
+        cx += dcol;
+        if (z >= nz) { z -= nz; ++cx; }
+        while (cx >= nvx) { cx -= nvx; ++cy; }
     }
     // reduce over the block
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
