@@ -90,14 +90,9 @@ __global__ __launch_bounds__(kT) void g_post(const ScanDesc* __restrict__ d, con
         const int64_t sel = a.per_pos ? i : mi;
         const int j = a.map[sel];
         const float h = a.hsel[sel];
-        float re = 0.f, im = 0.f;
-        for (int s = 0; s < a.fsplit; ++s) {
-            cf32 v = a.yraw[((int64_t)s * a.npos + p) * a.mu + j];
-            re += v.re;
-            im += v.im;
-        }
-        re = re * h - a.y[i].re;
-        im = im * h - a.y[i].im;
+        const cf32 sum = sum_parts_ordered(a.yraw + p * a.mu + j, a.npos * a.mu, a.fsplit);
+        const float re = sum.re * h - a.y[i].re;
+        const float im = sum.im * h - a.y[i].im;
         a.r[i] = cf32{re, im};
         acc += (double)re * re + (double)im * im;
     }
@@ -144,13 +139,7 @@ __global__ __launch_bounds__(kT) void g_update(const ScanDesc* __restrict__ d, c
         cf32 gg;
         if (a.asplit > 1) {
             // the adjoint's split-K partials, summed in fixed order (its epilogue)
-            float re = 0.f, im = 0.f;
-            for (int q = 0; q < a.asplit; ++q) {
-                const cf32 v = a.gpart[(int64_t)q * a.nvox + i];
-                re += v.re;
-                im += v.im;
-            }
-            gg = cf32{re, im};
+            gg = sum_parts_ordered(a.gpart + i, a.nvox, a.asplit);
         } else {
             gg = a.g[i];
         }

@@ -34,6 +34,30 @@ __host__ __device__ inline cbf16 to_cbf16(float re, float im) {
     return cbf16{(__bf16)re, (__bf16)im};
 }
 
+// sum_{s < count} v[s * stride], added in order s = 0, 1, ... (the result
+// does not depend on the grouping), with eight loads in flight: the split-K
+// partials of the GEMMs are summed this way by every epilogue.
+__device__ __forceinline__ cf32 sum_parts_ordered(const cf32* __restrict__ v, int64_t stride, int count) {
+    float re = 0.f, im = 0.f;
+    int s = 0;
+    for (; s + 8 <= count; s += 8) {
+        cf32 q[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) q[u] = v[(int64_t)(s + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            re += q[u].re;
+            im += q[u].im;
+        }
+    }
+    for (; s < count; ++s) {
+        const cf32 q = v[(int64_t)s * stride];
+        re += q.re;
+        im += q.im;
+    }
+    return cf32{re, im};
+}
+
 // Host-side derived geometry, computed in FP64.
 struct Derived {
     int wx = 0, wy = 0;                 // effective aperture half-widths

@@ -62,14 +62,8 @@ __global__ __launch_bounds__(kThreads) void fwd_post_kernel(
         int64_t sel = per_pos ? i : mi;
         int j = map[sel];
         float h = hsel[sel];
-        float re = 0.f, im = 0.f;
-        for (int s = 0; s < split; ++s) {
-            cf32 v = yraw[((int64_t)s * npos + p) * mu + j];
-            re += v.re;
-            im += v.im;
-        }
-        re *= h;
-        im *= h;
+        const cf32 sum = sum_parts_ordered(yraw + p * mu + j, npos * mu, split);
+        float re = sum.re * h, im = sum.im * h;
         if (ymeas) {
             cf32 q = ymeas[i];
             re -= q.re;
@@ -172,15 +166,7 @@ __global__ __launch_bounds__(kThreads) void update_kernel(int64_t n, cf32* __res
          i += (int64_t)gridDim.x * kThreads) {
         cf32 gm = gamma[i], aa = a[i];
         cf32 gg = g[i];
-        if (nsplit > 1) {
-            float re = 0.f, im = 0.f;
-            for (int q = 0; q < nsplit; ++q) {
-                cf32 v = g[(int64_t)q * n + i];
-                re += v.re;
-                im += v.im;
-            }
-            gg = cf32{re, im};
-        }
+        if (nsplit > 1) gg = sum_parts_ordered(g + i, n, nsplit);
         // real: the reflectivity is real, the gradient step keeps Re (Re{H} model)
         float zr = gm.re - step * gg.re, zi = real ? 0.f : gm.im - step * gg.im;
         float mag = sqrtf(zr * zr + zi * zi);
@@ -233,14 +219,9 @@ __global__ __launch_bounds__(kThreads) void mix_post_kernel(
         __syncthreads();
         const cf32* xs = xih + (per_sign ? p * nt : 0);
         for (int j = threadIdx.x; j < nt; j += kThreads) {
-            float re = 0.f, im = 0.f;
-            for (int sp = 0; sp < split; ++sp) {
-                const cf32 q = yraw[((int64_t)sp * npos + p) * nt + j];
-                re += q.re;
-                im += q.im;
-            }
+            const cf32 sum = sum_parts_ordered(yraw + p * nt + j, npos * nt, split);
             const float h = hu[j];
-            v[j] = cf32{h * re, h * im};
+            v[j] = cf32{h * sum.re, h * sum.im};
             xr[j] = xs[j];
         }
         __syncthreads();
@@ -528,13 +509,7 @@ __global__ __launch_bounds__(kThreads) void sum_parts_kernel(const cf32* __restr
                                                              cf32* __restrict__ out) {
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kThreads) {
-        float re = 0.f, im = 0.f;
-        for (int s = 0; s < nsplit; ++s) {
-            cf32 v = part[(int64_t)s * n + i];
-            re += v.re;
-            im += v.im;
-        }
-        out[i] = cf32{re, im};
+        out[i] = sum_parts_ordered(part + i, n, nsplit);
     }
 }
 
