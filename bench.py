@@ -31,6 +31,13 @@ METRIC = "A+A^H GFLOP/s & FISTA time to 1e-2 rel error: FP32 plain vs BF16/learn
 PEAK_FP32_MFMA = 157.3e12
 PEAK_BF16_MFMA = 2.5e15
 PEAK_HBM = 8e12
+# VALU issue model of the phasor path: one wave64 instruction per SIMD every 4
+# cycles (256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane slots/s), and a
+# (term, bin) pair needs at least 9 instructions: the phase product, a convert,
+# a scale, sin, cos and 4 FMAs (the counters show the transcendentals taking no
+# more issue slots than the others)
+PHASOR_SLOTS_PER_TERM = 9
+PEAK_PHASOR_TERMS = 256 * 4 * 16 * 2.4e9 / PHASOR_SLOTS_PER_TERM
 
 # HBM bytes per launch of the dominant kernels, from two rocprofv3 counter runs
 # (FETCH_SIZE, then WRITE_SIZE, each scaled by what the same counter reads for a
@@ -38,7 +45,7 @@ PEAK_HBM = 8e12
 # are part of the traffic).  Each entry holds the SHA-256 prefix of the kernel
 # source it was measured on; a changed source or another tiling reports null.
 TRAFFIC = {
-    # 32 x 32 C-scan, FP32 union-GEMM, shipped tiling (profiles/cscan32_fp32_gemm_and_phasor.md)
+    # 32 x 32 C-scan, FP32 union-GEMM, shipped tiling (profiles/cscan32_fp32_gemm.md)
     "cscan32/gemm/forward/fs4-zs8-nw5-np2-zc8": {"bytes": 20.579e6, "sha": "07604cb76073e38b"},
     "cscan32/gemm/adjoint/as12-np2-kc16": {"bytes": 32.304e6, "sha": "07604cb76073e38b"},
     # transform-domain contraction (profiles/cscan32_fp32_transform.md, cscan64_fp32_transform.md):
@@ -67,9 +74,9 @@ def source_sha(rel):
 
 
 def tiling_key(info, direction):
-    if info["dtype"] == 1:          # BF16: d_y split and wave rows
-        return ("as%d-wr%d" % (info["adj_split"], info["adj_rows"]) if direction == "adjoint"
-                else "fs%d-wr%d" % (info["fwd_split"], info["fwd_rows"]))
+    if info["dtype"] == 1 and info["algo"] == 1:   # BF16 GEMM: d_y and depth splits, wave rows
+        return ("as%d-wr%d-nz%d" % (info["adj_split"], info["adj_rows"], info["adj_tile"]) if direction == "adjoint"
+                else "fs%d-zs%d-wr%d" % (info["fwd_split"], info["fwd_zsplit"], info["fwd_rows"]))
     if direction == "adjoint":
         return "as%d-np%d-kc%d" % (info["adj_split"], info["adj_tile"], info["adj_chunk"])
     return "fs%d-zs%d-nw%d-np%d-zc%d" % (info["fwd_split"], info["fwd_zsplit"], info["fwd_waves"],
@@ -93,8 +100,34 @@ def window_terms(g, bins, per_pos):
     return int(cy.sum()) * int(cx.sum()) * bins.shape[-1] * g["nz"]
 
 
-def cpu_baseline(w, bins, seconds=12.0):
-    """Time the FP64 oracle on a bounded sample of the same workload."""
+def operator_outputs(ufss, W, g, w, bins, dev, tcfg):
+    """A x and A^H y of every operator form at the full workload, for the
+    inputs the CPU leg samples (x = CN seed 5, y = CN seed 6), on the host."""
+    import torch
+    x = torch.from_numpy(W.cn((g["ny"], g["nx"], g["nz"]), 5).astype(np.complex64)).to(dev)
+    y = torch.from_numpy(W.cn((g["ny"], g["nx"], w["m"]), 6).astype(np.complex64)).to(dev)
+    forms = [("gemm_f32", ufss.F32, ufss.ALGO_GEMM), ("gemm_bf16", ufss.BF16, ufss.ALGO_GEMM),
+             ("transform_f32", ufss.F32, ufss.ALGO_FFT), ("transform_bf16", ufss.BF16, ufss.ALGO_FFT)]
+    if w["per_position"]:
+        forms.append(("phasor_f32", ufss.F32, ufss.ALGO_PHASOR))
+    out = {}
+    for name, dt, algo in forms:
+        p = ufss.Plan(g, w["m"], w["per_position"], bins, dtype=dt, algo=algo)
+        if algo == ufss.ALGO_GEMM:
+            autotune(ufss, p, tcfg)
+        yo = torch.empty_like(y)
+        xo = torch.empty_like(x)
+        ufss.ufss_forward(p, x, yo)
+        ufss.ufss_adjoint(p, y, xo)
+        out[name] = (yo.cpu().numpy(), xo.cpu().numpy())
+        p.close()
+    return out
+
+
+def cpu_baseline(w, bins, seconds=12.0, gpu_outputs=None):
+    """Time the FP64 oracle on a bounded sample of the same workload; the
+    sampled rows and columns also give each GPU operator form's error against
+    the oracle (max |gpu - oracle| / max |oracle| over the sample)."""
     from oracle import operator as O
     from paper_2012_04534_amd import workloads as W
     try:
@@ -109,21 +142,33 @@ def cpu_baseline(w, bins, seconds=12.0):
     wx = g["nx"] - 1 if g["win_x"] < 0 else g["win_x"]
     wy = g["ny"] - 1 if g["win_y"] < 0 else g["win_y"]
     cmac, n_fwd, n_adj = 0, 0, 0
+    gerr = {k: [0.0, 0.0, 0.0, 0.0] for k in (gpu_outputs or {})}   # fwd num, den, adj num, den
+    t_gpu_cmp = 0.0
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds:
+    while time.perf_counter() - t0 - t_gpu_cmp < seconds:
         py, px = int(rng.integers(g["ny"])), int(rng.integers(g["nx"]))
-        O.apply_A_at(g, bins, x, py, px)
+        row = O.apply_A_at(g, bins, x, py, px)
+        tc = time.perf_counter()
+        for k, (yg, _) in (gpu_outputs or {}).items():
+            gerr[k][0] = max(gerr[k][0], float(np.abs(yg[py, px] - row).max()))
+            gerr[k][1] = max(gerr[k][1], float(np.abs(row).max()))
+        t_gpu_cmp += time.perf_counter() - tc
         nvx = min(px + wx, g["nx"] - 1) - max(px - wx, 0) + 1
         nvy = min(py + wy, g["ny"] - 1) - max(py - wy, 0) + 1
         cmac += nvx * nvy * g["nz"] * w["m"]
         n_fwd += 1
         vy, vx = int(rng.integers(g["ny"])), int(rng.integers(g["nx"]))
-        O.apply_AH_at(g, bins, y, vy, vx)
+        col = O.apply_AH_at(g, bins, y, vy, vx)
+        tc = time.perf_counter()
+        for k, (_, xg) in (gpu_outputs or {}).items():
+            gerr[k][2] = max(gerr[k][2], float(np.abs(xg[vy, vx] - col).max()))
+            gerr[k][3] = max(gerr[k][3], float(np.abs(col).max()))
+        t_gpu_cmp += time.perf_counter() - tc
         npx = min(vx + wx, g["nx"] - 1) - max(vx - wx, 0) + 1
         npy = min(vy + wy, g["ny"] - 1) - max(vy - wy, 0) + 1
         cmac += npx * npy * g["nz"] * w["m"]
         n_adj += 1
-    dt = time.perf_counter() - t0
+    dt = time.perf_counter() - t0 - t_gpu_cmp
     if limit is not None:
         limit.unregister()
     host = {"affinity_cpus": len(os.sched_getaffinity(0))}
@@ -143,6 +188,8 @@ def cpu_baseline(w, bins, seconds=12.0):
         "sample": "%d rows of A x (one scan position each) and %d columns of A^H y (one voxel "
                   "column each) at the full 32x32 C-scan geometry, FP64 numpy direct sum, "
                   "1 BLAS thread, %.1f s" % (n_fwd, n_adj, dt),
+        "gpu_operator_error_vs_oracle": {
+            k: {"forward": v[0] / v[1], "adjoint": v[2] / v[3]} for k, v in gerr.items() if v[1] > 0},
     }
 
 
@@ -270,9 +317,11 @@ def cpu_structured(w, bins):
     return out
 
 
-def cpu_oracle_fista_bscan():
+def cpu_oracle_fista_bscan(gpu=None):
     """The plain oracle's FISTA (200 iterations, dense FP64 A, one core) on the
-    32-position B-scan workload, with L from its eigenvalues and the lambda rule."""
+    32-position B-scan workload, with L from its eigenvalues and the lambda rule;
+    with the GPU's run (its iterate, L and lambda) also the oracle's FISTA at the
+    GPU's L and lambda and the GPU iterate's error against it."""
     from threadpoolctl import threadpool_limits
     from oracle import operator as O
     from oracle import select as S
@@ -291,9 +340,15 @@ def cpu_oracle_fista_bscan():
         t0 = time.perf_counter()
         V.fista(lambda v: A @ v, lambda v: A.conj().T @ v, y, lam, L, w["iters"])
         dt = time.perf_counter() - t0
-    return {"iters": w["iters"], "solve_s": round(dt, 3), "setup_s": round(t_setup, 3), "cores": 1,
-            "sample": "the 32-position B-scan workload in full: dense FP64 A (%d x %d), numpy, "
-                      "one BLAS thread" % A.shape}
+        out = {"iters": w["iters"], "solve_s": round(dt, 3), "setup_s": round(t_setup, 3), "cores": 1,
+               "sample": "the 32-position B-scan workload in full: dense FP64 A (%d x %d), numpy, "
+                         "one BLAS thread" % A.shape}
+        if gpu is not None:
+            xg, Lg, lamg = gpu
+            a, _ = V.fista(lambda v: A @ v, lambda v: A.conj().T @ v, y, lamg, Lg, w["iters"])
+            out["gpu_fista_iterate_error_vs_oracle"] = float(np.linalg.norm(xg - a) / np.linalg.norm(a))
+            out["gpu_L_over_1.01_eigvalsh"] = float(Lg / (1.01 * L))
+    return out
 
 
 WEIGHTS = os.path.join(ROOT, "paper_2012_04534_amd", "weights", "unrolled_cscan32_s16c8.bin")
@@ -308,30 +363,63 @@ def autotune(ufss, plan, cfg):
     return ufss.ufss_autotune(plan, path, read, write)
 
 
-def fista_time(ufss, plan, y, lam, L, k, x):
+LEVELS = [0.3, 0.1, 0.03, 0.01]
+
+
+def level_iters(err, levels=LEVELS):
+    """First iteration (1-based) whose error is at or below each level (None: not reached)."""
+    out = []
+    for lev in levels:
+        hit = np.flatnonzero(np.asarray(err) <= lev)
+        out.append(int(hit[0]) + 1 if hit.size else None)
+    return out
+
+
+def timed_fista(ufss, plan, y, lam, L, k, x, a_ref=None, x0=None):
+    """Wall time of ONE FISTA run of k iterations (from zero, or from x0) with
+    its per-iteration FP64 statistics (and the error against a_ref), GPU
+    synchronised on both sides; returns (seconds, stats)."""
     import torch
-    x.zero_()
+    if x0 is None:
+        x.zero_()
+    else:
+        x.copy_(x0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ufss.ufss_fista(plan, y, lam, L, k, x)
+    st = ufss.ufss_fista(plan, y, lam, L, k, x, a_ref=a_ref)
     torch.cuda.synchronize()
-    return time.perf_counter() - t0
+    return time.perf_counter() - t0, st
 
 
-def time_to_accuracy(ufss, W, plan, g, w, bins, y, lam, L, t_l, dev, tcfg):
-    """Time to a relative error of 1e-2 (and coarser levels) against the plain
-    FP32 FISTA iterate at the workload's K: FP32 FISTA, BF16 FISTA and the
-    learned unrolled network (trained checkpoint, if present)."""
+def levels_wall_time(ufss, plan, y, lam, L, x, a_ref, iters):
+    """Wall time to each level: one timed run of exactly the iterations that
+    level needs (its statistics included), per level reached."""
+    out = []
+    for k in iters:
+        out.append(None if k is None else round(timed_fista(ufss, plan, y, lam, L, k, x, a_ref)[0], 5))
+    return out
+
+
+def time_to_accuracy(ufss, W, plan, g, w, bins, y, lam, L, t_l, dev, tcfg, timed_levels=None):
+    """Time to relative errors 0.3 ... 1e-2 against the plain FP32 FISTA
+    iterate at the workload's K (FISTA-K on the GEMM operator), for plain FP32
+    and BF16 FISTA on the GEMM and on the transform operator.  Every time is
+    the wall time of one run (statistics included) of the iterations the level
+    needs (``timed_levels``: indices of the levels timed, default all); the
+    ratios compare precisions on the same operator, at 1e-2."""
     import torch
     K = w["iters"]
+    timed_levels = range(len(LEVELS)) if timed_levels is None else timed_levels
     own = None
     if plan.info()["dtype"] != ufss.F32:      # the reference and the FP32 rows need an FP32 plan
         own = plan = ufss.Plan(g, w["m"], w["per_position"], bins, dtype=ufss.F32)
         autotune(ufss, plan, tcfg)
     a_ref = torch.zeros((g["ny"], g["nx"], g["nz"]), dtype=torch.complex64, device=dev)
     ufss.ufss_fista(plan, y, lam, L, K, a_ref)
-    out = {"reference": "plain FP32 FISTA iterate after %d iterations" % K,
-           "lipschitz_s": round(t_l, 4), "L": L, "lambda": lam, "levels": [0.3, 0.1, 0.03, 0.01]}
+    out = {"reference": "plain FP32 FISTA iterate after %d iterations (GEMM operator)" % K,
+           "timing": "wall time of one run (per-iteration statistics and error included) of the "
+                     "iterations each level needs",
+           "lipschitz_s": round(t_l, 4), "L": L, "lambda": lam, "levels": LEVELS}
     x = torch.zeros_like(a_ref)
     for tag, dt, algo in (("fp32", ufss.F32, None), ("fp32_transform", ufss.F32, ufss.ALGO_FFT),
                           ("bf16", ufss.BF16, ufss.ALGO_GEMM), ("bf16_transform", ufss.BF16, ufss.ALGO_FFT)):
@@ -340,75 +428,103 @@ def time_to_accuracy(ufss, W, plan, g, w, bins, y, lam, L, t_l, dev, tcfg):
             p = ufss.Plan(g, w["m"], w["per_position"], bins, dtype=dt, algo=algo)
             if algo == ufss.ALGO_GEMM:
                 autotune(ufss, p, tcfg)
-        x.zero_()                      # every row starts from zero, as the reference did
-        st = ufss.ufss_fista(p, y, lam, L, K, x, a_ref=a_ref)
-        per_it = fista_time(ufss, p, y, lam, L, 20, x) / 20
-        iters, times = [], []
-        for lev in out["levels"]:
-            hit = np.flatnonzero(st["err_ref"] <= lev)
-            k = int(hit[0]) + 1 if hit.size else None
-            iters.append(k)
-            times.append(round(k * per_it, 5) if k else None)
-        out[tag] = {"s_per_iter": round(per_it, 6), "iters_to_level": iters, "time_to_level_s": times,
+        timed_fista(ufss, p, y, lam, L, 3, x, a_ref)            # warm-up
+        t_all, st = timed_fista(ufss, p, y, lam, L, K, x, a_ref)
+        iters = level_iters(st["err_ref"])
+        it_t = [k if j in timed_levels else None for j, k in enumerate(iters)]
+        out[tag] = {"s_per_iter_full_run": round(t_all / K, 6), "iters_to_level": iters,
+                    "time_to_level_s": levels_wall_time(ufss, p, y, lam, L, x, a_ref, it_t),
                     "err_at_K": float(st["err_ref"][-1])}
         if p is not plan:
             p.close()
-    if os.path.exists(WEIGHTS):
-        from paper_2012_04534_amd import learned as LN
-        net = ufss.Net(plan, stages=16, channels=8, L=L, mu=w["mu"])
-        ufss.ufss_unrolled_load(net, WEIGHTS)
-        ev = LN.make_dataset(plan, g, 4, 2005, K, L, back_wall=w["back_wall"], dev=dev)
-        r = LN.evaluate(net, plan, ev, L)
-        fp32_s = out["fp32"]["s_per_iter"]
-        err_fista_same_time = []
-        for (yy, tgt, _), tn in zip(ev, r["time_s"]):
-            k_eq = max(1, int(tn / fp32_s))
-            st = ufss.ufss_fista(plan, yy, ufss.lambda_from_mu(w["mu"]), L, min(k_eq, K), x, a_ref=tgt)
-            err_fista_same_time.append(float(st["err_ref"][-1]))
-        # the network's output as the start of plain FP32 FISTA (the hand-off the
-        # fallback rule uses), against FISTA from zero on the same scenes
-        warm, cold = [], []
-        for yy, tgt, _ in ev:
-            for dst, start_net in ((warm, True), (cold, False)):
-                x.zero_()
-                if start_net:
-                    ufss.ufss_unrolled_forward(net, yy, x)
-                st = ufss.ufss_fista(plan, yy, ufss.lambda_from_mu(w["mu"]), L, K, x, a_ref=tgt)
-                row = []
-                for lev in out["levels"]:
-                    hit = np.flatnonzero(st["err_ref"] <= lev)
-                    row.append(int(hit[0]) + 1 if hit.size else None)
-                dst.append(row)
-
-        def mean_iters(rows, j):
-            v = [rw[j] for rw in rows]
-            return None if any(q is None for q in v) else float(np.mean(v))
-
-        t_net = float(r["time_s"].mean())
-        lv = len(out["levels"])
-        warm_it = [mean_iters(warm, j) for j in range(lv)]
-        out["learned"] = {"checkpoint": os.path.relpath(WEIGHTS, ROOT), "eval_scenes": len(ev),
-                          "err_mean": float(r["err"].mean()), "err_max": float(r["err"].max()),
-                          "fallbacks": int(r["fallback"].sum()),
-                          "time_s_mean": t_net,
-                          "fp32_fista_err_at_same_time": float(np.mean(err_fista_same_time)),
-                          "then_fista_iters_to_level": warm_it,
-                          "then_fista_time_to_level_s": [None if k is None else round(t_net + k * fp32_s, 5)
-                                                         for k in warm_it],
-                          "fista_from_zero_iters_to_level": [mean_iters(cold, j) for j in range(lv)]}
-        net.close()
-        # the same checkpoint with the transform-domain operator as its fixed layers
-        pt = ufss.Plan(g, w["m"], w["per_position"], bins, algo=ufss.ALGO_FFT)
-        nt_ = ufss.Net(pt, stages=16, channels=8, L=L, mu=w["mu"])
-        ufss.ufss_unrolled_load(nt_, WEIGHTS)
-        rt = LN.evaluate(nt_, pt, ev, L)
-        out["learned"]["transform_operator"] = {"time_s_mean": float(rt["time_s"].mean()),
-                                                "err_mean": float(rt["err"].mean()),
-                                                "err_max": float(rt["err"].max())}
-        nt_.close()
-        pt.close()
+    # like for like: BF16 against FP32 on the same operator, at the 1e-2 level
+    def ratio(a, b):
+        ta, tb = out[a]["time_to_level_s"][-1], out[b]["time_to_level_s"][-1]
+        return None if ta is None or tb is None else round(ta / tb, 2)
+    out["bf16_speedup_same_operator"] = {"gemm": ratio("fp32", "bf16"),
+                                         "transform": ratio("fp32_transform", "bf16_transform")}
+    out["transform_vs_gemm_fp32"] = ratio("fp32", "fp32_transform")
     if own is not None:
         own.close()
+    return out
+
+
+def measured_problem(ufss, W, w, bins, dev, tcfg):
+    """The workload's scene and noisy measurements y = A x + n (FP32 GEMM plan),
+    L by power iteration on the transform plan (the same operator, cheaper) and
+    lambda by the mu rule."""
+    import torch
+    g = w["geom"]
+    plan = ufss.Plan(g, w["m"], w["per_position"], bins, dtype=ufss.F32, algo=ufss.ALGO_GEMM)
+    autotune(ufss, plan, tcfg)
+    x_true = W.scene(g, w["n_scat"], amp=w["amp"], seed=w["seed"], back_wall=w["back_wall"])
+    xt = torch.from_numpy(x_true.astype(np.complex64)).to(dev)
+    y0 = torch.empty((g["ny"], g["nx"], w["m"]), dtype=torch.complex64, device=dev)
+    ufss.ufss_forward(plan, xt, y0)
+    sig = W.noise_sigma(float((y0.abs() ** 2).sum().item()), y0.numel(), w["snr_db"])
+    y = (y0 + sig * torch.from_numpy(W.cn(tuple(y0.shape), w["seed"] + 1).astype(np.complex64)).to(dev)).contiguous()
+    pt = ufss.Plan(g, w["m"], w["per_position"], bins, algo=ufss.ALGO_FFT)
+    t_l = time.perf_counter()
+    L = ufss.ufss_lipschitz(pt, max_iters=200, rtol=1e-6, margin=0.01, seed=4)
+    t_l = time.perf_counter() - t_l
+    pt.close()
+    x = torch.zeros_like(xt)
+    lam = ufss.ufss_fista(plan, y, ufss.lambda_from_mu(w["mu"]), L, 1, x)["lambda"]
+    return plan, y, L, lam, t_l
+
+
+def learned_block(ufss, W, g, w, bins, L_gemm, dev, tcfg, n_scenes=8):
+    """The learned unrolled solver against its judge (config of the learned
+    solver: FISTA-200 on the same operator), on held-out evaluation scenes,
+    with the residual fallback rule: per operator (transform, GEMM) the mean
+    network time, its error, the fallbacks, and plain FP32 FISTA's wall time to
+    the same error levels on the same scenes and operator."""
+    import torch
+    from paper_2012_04534_amd import learned as LN
+    if not os.path.exists(WEIGHTS):
+        return None
+    out = {"checkpoint": os.path.relpath(WEIGHTS, ROOT), "reference": "plain FP32 FISTA-200 on the same operator",
+           "eval_scenes": n_scenes, "eval_set": "held-out seeds 2005/0..%d" % (n_scenes - 1)}
+    for name, algo in (("transform", ufss.ALGO_FFT), ("gemm", ufss.ALGO_GEMM)):
+        plan = ufss.Plan(g, w["m"], w["per_position"], bins, algo=algo)
+        if algo == ufss.ALGO_GEMM:
+            autotune(ufss, plan, tcfg)
+        L = L_gemm
+        data = LN.make_dataset(plan, g, n_scenes, LN.EVAL_SEED, 200, L, mu=w["mu"], back_wall=w["back_wall"],
+                               dev=dev)
+        net = ufss.Net(plan, stages=16, channels=8, L=L, mu=w["mu"])
+        ufss.ufss_unrolled_load(net, WEIGHTS)
+        x = torch.zeros_like(data[0][1])
+        ufss.ufss_unrolled_forward(net, data[0][0], x)         # warm-up
+        r = LN.evaluate(net, plan, data, L, w["mu"])
+        f_iters, f_time = [], []
+        for yy, tgt, _ in data:
+            lam = -w["mu"]
+            timed_fista(ufss, plan, yy, lam, L, 3, x, tgt)
+            _, st = timed_fista(ufss, plan, yy, lam, L, 200, x, tgt)
+            it = level_iters(st["err_ref"])
+            f_iters.append(it)
+            f_time.append(levels_wall_time(ufss, plan, yy, lam, L, x, tgt, it))
+        mean_or_none = lambda v: None if any(q is None for q in v) else float(np.mean(v))
+        fista_t = [mean_or_none([row[j] for row in f_time]) for j in range(len(LEVELS))]
+        t_net = float(r["time_s"].mean())
+        err = float(r["err"].mean())
+        reached = [lev for lev in LEVELS if err <= lev]
+        row = {"net_time_s_mean": round(t_net, 5), "err_mean": err, "err_max": float(r["err"].max()),
+               "fallbacks": int(r["fallback"].sum()), "fallback_time_s": float(r["t_fallback"].sum()),
+               "fista_iters_to_level": [mean_or_none([row[j] for row in f_iters]) for j in range(len(LEVELS))],
+               "fista_time_to_level_s": fista_t,
+               "net_levels_reached": reached}
+        # plain FISTA time to the finest level the network reaches, over the network's time
+        if reached:
+            j = LEVELS.index(reached[-1])
+            row["speedup_at_finest_level_reached"] = (None if fista_t[j] is None else
+                                                      round(fista_t[j] / t_net, 2))
+        row["time_to_1e-2_s"] = round(t_net, 5) if err <= 1e-2 else None
+        out[name] = row
+        net.close()
+        del data
+        plan.close()
     return out
 
 
@@ -459,11 +575,16 @@ def transform_rates(ufss, g, m, per_pos, bins, x, y, xo, ev_time, cm):
                                         round(tab / (ca * 1e-3) / PEAK_HBM, 3)]}
 
 
-def batch_rate(ufss, W, dev, iters=5):
-    """Batched FISTA over the 64 uneven scans (FP32, autotuned splits)."""
+def batch_rate(ufss, W, dev, tcfg, iters=100):
+    """The 64 uneven scans (FP32, tilings from the autotuner cache or a quick
+    search) as one persistent batch: setup (plans, tilings, L), creation
+    (lambdas, descriptors, capture and instantiation of the K-iteration graph)
+    and the replay of K iterations are timed separately; beside them, the same
+    scans one after another with single-scan FISTA."""
     import torch
     specs = W.batch_workload()
     plans, ys, xs, Ls, cm = [], [], [], [], 0
+    path, read, write = tcfg
     t0 = time.perf_counter()
     for s in specs:
         g = s["geom"]
@@ -471,7 +592,7 @@ def batch_rate(ufss, W, dev, iters=5):
         m = min(s["m"], band)
         bins, _ = ufss.ufss_select_freqs(g, m, s["per_position"], s["seed"])
         p = ufss.Plan(g, m, s["per_position"], bins, algo=ufss.ALGO_GEMM)
-        ufss.ufss_autotune(p, None, use_cache=False, write_cache=False, quick=True)
+        ufss.ufss_autotune(p, path, use_cache=read, write_cache=write, quick=True)
         xt = torch.from_numpy(W.scene(g, s["n_scat"], amp=s["amp"], seed=s["seed"]).astype(np.complex64)).to(dev)
         y = torch.empty((g["ny"], g["nx"], m), dtype=torch.complex64, device=dev)
         ufss.ufss_forward(p, xt, y)
@@ -480,18 +601,44 @@ def batch_rate(ufss, W, dev, iters=5):
         ys.append(y)
         xs.append(torch.zeros((g["ny"], g["nx"], g["nz"]), dtype=torch.complex64, device=dev))
         cm += window_terms(g, bins, s["per_position"])
+    torch.cuda.synchronize()
     setup = time.perf_counter() - t0
-    ufss.ufss_fista_batched(plans, ys, xs, [-0.1] * len(plans), Ls, 1)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ufss.ufss_fista_batched(plans, ys, xs, [-0.1] * len(plans), Ls, iters)
+    b = ufss.Batch(plans, ys, xs, [-0.1] * len(plans), Ls, iters)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    t_create = time.perf_counter() - t0
+    b.run()                                            # first replay (warm)
+    reps = []
+    for _ in range(3):
+        for x in xs:
+            x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, lams = b.run()
+        torch.cuda.synchronize()
+        reps.append(time.perf_counter() - t0)
+    dt = float(np.median(reps))
+    b.close()
+    # the same scans one at a time (single-scan FISTA, 5 iterations each)
+    k1 = 5
+    t_seq = 0.0
+    for p, y, x, L, lam in zip(plans, ys, xs, Ls, lams):
+        x.zero_()
+        ufss.ufss_fista(p, y, lam, L, 1, x)
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ufss.ufss_fista(p, y, lam, L, k1, x)
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t0
     for p in plans:
         p.close()
-    return {"scans": len(specs), "iters": iters, "wall_s": round(dt, 4), "setup_s": round(setup, 2),
+    return {"scans": len(specs), "iters": iters, "setup_s": round(setup, 2),
+            "create_capture_instantiate_s": round(t_create, 3),
+            "replay_s": round(dt, 4), "replay_ms_per_iter": round(dt / iters * 1e3, 4),
             "cmac_per_apply": cm,
-            "a_plus_ah_tflops_incl_capture": round(16.0 * cm * iters / dt / 1e12, 2)}
+            "a_plus_ah_tflops_replay": round(16.0 * cm * iters / dt / 1e12, 2),
+            "sequential_single_scan_ms_per_iter": round(t_seq / k1 * 1e3, 4)}
 
 
 def gpu_clocks():
@@ -526,11 +673,12 @@ def bscan_fista(ufss, W, dev):
     x.zero_()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ufss.ufss_fista(plan, y, ufss.lambda_from_mu(w["mu"]), L, w["iters"], x)
+    st = ufss.ufss_fista(plan, y, ufss.lambda_from_mu(w["mu"]), L, w["iters"], x)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     plan.close()
-    return {"iters": w["iters"], "solve_s": round(dt, 4), "plan_and_L_s": round(setup, 3)}
+    return {"iters": w["iters"], "solve_s": round(dt, 4), "plan_and_L_s": round(setup, 3),
+            "_iterate": (x.cpu().numpy().reshape(-1), L, st["lambda"])}
 
 
 def main():
@@ -678,9 +826,11 @@ def main():
         roof = {"bound": "hbm", "achieved": round(tab / (k_ms * 1e-3) / 1e9, 1),
                 "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
     elif algo == ufss.ALGO_PHASOR:
-        # per term: one complex MAC (8 flops) on the VALU; peak is the FP32 vector rate
+        # per (term, bin): one complex MAC (8 algorithmic flops) on the VALU plus
+        # the phase it needs; peak from the issue model above
         roof = {"bound": "alu", "achieved": round(8.0 * cmac / (k_ms * 1e-3) / 1e12, 3),
-                "peak": 157.3, "unit": "TFLOP/s"}
+                "peak": round(PEAK_PHASOR_TERMS * 8.0 / 1e12, 2), "unit": "TFLOP/s",
+                "peak_basis": "VALU issue: %d lane slots per term" % PHASOR_SLOTS_PER_TERM}
     else:
         roof = {"bound": "mfma", "achieved": round(8.0 * cmac / (k_ms * 1e-3) / 1e12, 3),
                 "peak": (PEAK_BF16_MFMA if bf16 else PEAK_FP32_MFMA) / 1e12, "unit": "TFLOP/s"}
@@ -710,10 +860,21 @@ def main():
 
     if not args.quick:
         result["fista"] = time_to_accuracy(ufss, W, plan, g, w, bins, y, lam, L, t_l, dev, tcfg)
+        result["fista"]["learned"] = learned_block(ufss, W, g, w, bins, L, dev, tcfg)
         extras["cscan64"] = cscan64_rates(ufss, W, dev, ev_time, tcfg)
-        extras["batch64"] = batch_rate(ufss, W, dev)
+        # the precision study's own workload: BF16 against FP32 on the 64 x 64
+        # C-scan, time to the 1e-2 level only (its FP32 iterations take 26 ms)
+        w64 = W.workload("cscan64")
+        b64, _ = ufss.ufss_select_freqs(w64["geom"], w64["m"], w64["per_position"], w64["seed"])
+        p64, y64, L64, lam64, tl64 = measured_problem(ufss, W, w64, b64, dev, tcfg)
+        result["fista_cscan64"] = time_to_accuracy(ufss, W, p64, w64["geom"], w64, b64, y64, lam64, L64,
+                                                   tl64, dev, tcfg, timed_levels=[len(LEVELS) - 1])
+        p64.close()
+        del y64
+        extras["batch64"] = batch_rate(ufss, W, dev, tcfg)
         extras["bscan32_fista"] = bscan_fista(ufss, W, dev)
 
+    gpu_outputs = None if args.no_cpu else operator_outputs(ufss, W, g, w, bins, dev, tcfg)
     extras["gpu_clocks"] = gpu_clocks()
     result["extras"] = extras
     plan.close()
@@ -728,9 +889,11 @@ def main():
         result["extras"]["calib_copy_bytes_each_way"] = n * 4
 
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(w, bins)
+        result["cpu_baseline"] = cpu_baseline(w, bins, gpu_outputs=gpu_outputs)
         result["cpu_baseline"]["structured"] = cpu_structured(w, bins)
-        result["cpu_baseline"]["bscan32_oracle_fista"] = cpu_oracle_fista_bscan()
+        bs = extras.get("bscan32_fista", {}).get("_iterate")
+        result["cpu_baseline"]["bscan32_oracle_fista"] = cpu_oracle_fista_bscan(bs)
+    extras.get("bscan32_fista", {}).pop("_iterate", None)
     print(json.dumps(result), flush=True)
 
 
