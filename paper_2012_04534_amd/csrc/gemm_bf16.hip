@@ -302,11 +302,15 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
                 // bin tile with fewer sub-tiles is a launch of its own with a
                 // smaller NB (host), else (grouped launches) the sub-tiles past
                 // nb_act read stale LDS rows into accumulators never stored
-                bf8 c8[NB], s8[NB];
+                // -sin once for both signs of d_x, unless the registers it
+                // needs would cost a wave per SIMD (the widest tiles)
+                constexpr bool neg_once = NP * NB < 16;
+                bf8 c8[NB], s8[NB], ns8[NB];
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
                     c8[nb] = lds_bf8(pc + (nb * 16 + i) * PROW + 8 * kq);
                     s8[nb] = lds_bf8(ps + (nb * 16 + i) * PROW + 8 * kq);
+                    if constexpr (neg_once) ns8[nb] = neg_bf8(s8[nb]);
                 }
                 auto apply = [&](const int dx) {
                     // A operands: x at (p - d) for this lane's position of each sub-tile
@@ -337,12 +341,11 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
                         for (int s = 0; s < NP; ++s)
                             acc_re[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xi[s], s8[nb], acc_re[s][nb], 0, 0, 0);
 #pragma unroll
-                    for (int nb = 0; nb < NB; ++nb) {
-                        const bf8 ns8 = neg_bf8(s8[nb]);
+                    for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
                         for (int s = 0; s < NP; ++s)
-                            acc_im[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xr[s], ns8, acc_im[s][nb], 0, 0, 0);
-                    }
+                            acc_im[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                xr[s], neg_once ? ns8[nb] : neg_bf8(s8[nb]), acc_im[s][nb], 0, 0, 0);
                 };
                 if (wy_ok && adx <= dx_hi && adx >= wdx_lo && adx <= wdx_hi) apply(adx);   // d_x = +|d_x|
                 if (wy_ok && adx > 0 && -adx >= dx_lo && -adx >= wdx_lo && -adx <= wdx_hi)
@@ -540,11 +543,13 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
                 const __bf16* ps = pc + zspan * PROW;
                 // all NZ depth sub-tiles in four independent passes (inactive
                 // ones are never stored)
-                bf8 c8[NZ], s8[NZ];
+                constexpr bool neg_once = NV * NZ < 16;     // as in the forward
+                bf8 c8[NZ], s8[NZ], ns8[NZ];
 #pragma unroll
                 for (int q = 0; q < NZ; ++q) {
                     c8[q] = lds_bf8(pc + (q * 16 + i) * PROW + 8 * kq);
                     s8[q] = lds_bf8(ps + (q * 16 + i) * PROW + 8 * kq);
+                    if constexpr (neg_once) ns8[q] = neg_bf8(s8[q]);
                 }
                 auto apply = [&](const int dx) {
                     bf8 rr8[NV], ri8[NV];
@@ -574,12 +579,11 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
                         for (int s = 0; s < NV; ++s)
                             acc_im[s][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ri8[s], c8[q], acc_im[s][q], 0, 0, 0);
 #pragma unroll
-                    for (int q = 0; q < NZ; ++q) {
-                        const bf8 ns8 = neg_bf8(s8[q]);
+                    for (int q = 0; q < NZ; ++q)
 #pragma unroll
                         for (int s = 0; s < NV; ++s)
-                            acc_re[s][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ri8[s], ns8, acc_re[s][q], 0, 0, 0);
-                    }
+                            acc_re[s][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                ri8[s], neg_once ? ns8[q] : neg_bf8(s8[q]), acc_re[s][q], 0, 0, 0);
                 };
                 if (wy_ok && adx <= dx_hi && adx >= wdx_lo && adx <= wdx_hi) apply(adx);   // d_x = +|d_x|
                 if (wy_ok && adx > 0 && -adx >= dx_lo && -adx >= wdx_lo && -adx <= wdx_hi)
