@@ -14,7 +14,8 @@
 // wave-uniform scalars, and the per-lane sums are reduced across the wavefront
 // with shuffles and across waves in LDS.  Adjoint: each lane owns one depth of
 // one voxel column (64, 128 or 256 lanes per column), so no cross-lane
-// reduction is needed, and the bins and operands of each position are
+// reduction over depths is needed (the window's rows are split over the
+// workgroup's waves), and the bins and operands of each position are
 // wave-uniform scalar loads.
 #include "internal.h"
 
@@ -159,32 +160,35 @@ void launch_forward_phasor(const Plan& P, const cf32* x, cf32* y, const cf32* ym
 int phasor_forward_blocks(const Plan& P) { return P.npos * ((P.m + fwd_mb(P.m) - 1) / fwd_mb(P.m)); }
 
 // Adjoint lanes per voxel column: 64, 128 or 256 (the smallest that covers the
-// depths, else 256 with several depth chunks), so a workgroup of 256 threads
-// holds 256 / lanes whole columns and shallow grids do not leave most lanes
-// idle; every wave stays on one column, so its bins and operands are uniform
-// scalar loads.
+// depths, else 256 with several depth chunks).  A workgroup of 256 threads owns
+// one (column, depth chunk); its 256 / lanes groups of lanes split the window's
+// position rows between them and meet in LDS (fixed order), so a shallow grid
+// still launches four waves per column to hide the load latency of the
+// per-position operands.  Every wave stays on one column, so its bins and
+// operands are uniform scalar loads.
 static int adj_lanes(int nz) { return nz <= 64 ? 64 : (nz <= 128 ? 128 : 256); }
 
 __global__ __launch_bounds__(256) void adj_phasor_kernel(
     const cf32* __restrict__ rop, const uint32_t* __restrict__ ut, const float* __restrict__ amp,
     const int* __restrict__ bins, cf32* __restrict__ out, int nx, int ny, int nz, int wx, int wy,
-    int m, int nzc, int lanes, int64_t ncols) {
-    const int per = 256 / lanes;                          // columns per workgroup
-    // a wave never straddles two columns (lanes is a multiple of 64): the
-    // column index is wave-uniform, and reading it from the first lane lets
-    // the bins and operands below be scalar loads
-    const int64_t cidx = (int64_t)blockIdx.x * per +
-                         __builtin_amdgcn_readfirstlane((int)(threadIdx.x / lanes));
-    if (cidx >= ncols * nzc) return;                      // whole waves exit together
-    const int64_t v = cidx / nzc;
-    const int zc = (int)(cidx - v * nzc);
+    int m, int nzc, int lanes) {
+    __shared__ cf32 red[256];
+    const int nsplit = 256 / lanes;                       // row splits per column
+    const int64_t v = blockIdx.x / nzc;
+    const int zc = (int)(blockIdx.x - v * nzc);
     const int vx = (int)(v % nx), vy = (int)(v / nx);
-    const int z = zc * lanes + (int)(threadIdx.x % lanes);
+    // a wave never straddles two row splits (lanes is a multiple of 64): the
+    // split index is wave-uniform
+    const int sidx = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / lanes));
+    const int zl0 = (int)(threadIdx.x % lanes);
+    const int z = zc * lanes + zl0;
     const int zl = z < nz ? z : nz - 1;      // clamp for loads; store is guarded
     const int px_lo = max(vx - wx, 0), px_hi = min(vx + wx, nx - 1);
     const int py_lo = max(vy - wy, 0), py_hi = min(vy + wy, ny - 1);
+    const int nrow = py_hi - py_lo + 1, rows_per = (nrow + nsplit - 1) / nsplit;
+    const int r_lo = py_lo + sidx * rows_per, r_hi = min(py_hi, r_lo + rows_per - 1);
     float acc_re = 0.f, acc_im = 0.f;
-    for (int py = py_lo; py <= py_hi; ++py) {
+    for (int py = r_lo; py <= r_hi; ++py) {
         const int ady = py > vy ? py - vy : vy - py;
         for (int px = px_lo; px <= px_hi; ++px) {
             const int adx = px > vx ? px - vx : vx - px;
@@ -206,18 +210,27 @@ __global__ __launch_bounds__(256) void adj_phasor_kernel(
             acc_im += gb * in_im;
         }
     }
+    if (nsplit > 1) {
+        red[threadIdx.x] = cf32{acc_re, acc_im};
+        __syncthreads();
+        if (sidx != 0) return;
+        for (int q = 1; q < nsplit; ++q) {
+            const cf32 w = red[q * lanes + zl0];
+            acc_re += w.re;
+            acc_im += w.im;
+        }
+    }
     if (z < nz) out[v * nz + z] = cf32{acc_re, acc_im};
 }
 
 void launch_adjoint_phasor(const Plan& P, cf32* out, hipStream_t s) {
     const int lanes = adj_lanes(P.g.nz);
     const int nzc = (P.g.nz + lanes - 1) / lanes;
-    const int64_t ncols = P.npos;
-    const int per = 256 / lanes;
-    const int64_t nblk = (ncols * nzc + per - 1) / per;
+    const int64_t nblk = (int64_t)P.npos * nzc;
+    if (nblk > 0x7fffffff) fail(UFSS_ERR_UNSUPPORTED, "too many voxel columns for the phasor path");
     hipLaunchKernelGGL(adj_phasor_kernel, dim3((unsigned)nblk), dim3(256), 0, s,
                        static_cast<const cf32*>(P.d_rop), P.d_u, P.d_amp, P.d_bins, out, P.g.nx, P.g.ny,
-                       P.g.nz, P.d.wx, P.d.wy, P.m, nzc, lanes, ncols);
+                       P.g.nz, P.d.wx, P.d.wy, P.m, nzc, lanes);
     UFSS_HIP(hipGetLastError());
 }
 
