@@ -59,6 +59,14 @@ TRAFFIC = {
     "cscan32/transform-bf16/forward/fs1-zs1-nw1-np0-zc0": {"bytes": 80.372e6, "sha": "130f6e5e72ba81e0"},
     "cscan64/transform-bf16/adjoint/as1-np0-kc0": {"bytes": 473.496e6, "sha": "130f6e5e72ba81e0"},
     "cscan64/transform-bf16/forward/fs1-zs1-nw1-np0-zc0": {"bytes": 473.496e6, "sha": "130f6e5e72ba81e0"},
+    # BF16 GEMMs with phasor tables (profiles/cscan32_bf16_gemm.md, cscan64_bf16_gemm.md):
+    # mostly re-reads of the table tiles, one per workgroup and offset (the
+    # tables, 170 MB at 32 x 32, sit in the last-level cache); the 32 x 32
+    # forward is two launches (full bin tiles, then the short last one)
+    "cscan32/gemm-bf16/forward/fs12-zs8-wr1": {"bytes": 246.791e6, "sha": "cadb8dfe195b2976"},
+    "cscan32/gemm-bf16/adjoint/as12-wr1-nz2": {"bytes": 809.142e6, "sha": "cadb8dfe195b2976"},
+    "cscan64/gemm-bf16/forward/fs2-zs8-wr1": {"bytes": 483.769e6, "sha": "cadb8dfe195b2976"},
+    "cscan64/gemm-bf16/adjoint/as3-wr1-nz2": {"bytes": 676.594e6, "sha": "cadb8dfe195b2976"},
 }
 TRAFFIC_SRC = {"gemm": "paper_2012_04534_amd/csrc/gemm_f32.hip",
                "transform": "paper_2012_04534_amd/csrc/fft.hip",
@@ -643,8 +651,11 @@ def batch_rate(ufss, W, dev, tcfg, iters=100):
 
 def gpu_clocks():
     """Current GPU clocks (not locked on the box), read once with rocm-smi in a
-    child process; a failure is reported, never raised."""
+    child process; a failure is reported, never raised.  Skipped under a
+    profiler, whose preloaded library would also load into the child."""
     import subprocess
+    if any(k.startswith("ROCPROF") for k in os.environ):
+        return {"unavailable": "under rocprofv3"}
     try:
         r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True,
                            timeout=10)
