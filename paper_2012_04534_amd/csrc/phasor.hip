@@ -56,7 +56,7 @@ __global__ __launch_bounds__(256) void fwd_phasor_kernel(
     const int vx_lo = max(px - wx, 0), vx_hi = min(px + wx, nx - 1);
     const int vy_lo = max(py - wy, 0), vy_hi = min(py + wy, ny - 1);
     const int nvx = vx_hi - vx_lo + 1;
-    const int64_t total = (int64_t)nvx * (vy_hi - vy_lo + 1) * nz;
+    const int total = nvx * (vy_hi - vy_lo + 1) * nz;   // < 2^31 (host check)
 
     float acc_re[MB], acc_im[MB];
 #pragma unroll
@@ -64,16 +64,20 @@ __global__ __launch_bounds__(256) void fwd_phasor_kernel(
 
     // walk t = w * nz + z over the window's columns w = (cy, cx), updating
     // (cx, cy, z) incrementally: a step of 256 terms moves dcol columns and dz
-    // depths (divided once), plus one column when the depth wraps
+    // depths (divided once), plus one column when the depth wraps.  The offset
+    // of x moves by 256 per step plus (nx - nvx) nz per wrap to the next window
+    // row; the delay-table row of |d_y| changes only on such a wrap.
     const int dcol = 256 / nz, dz = 256 - dcol * nz;
-    int64_t t = threadIdx.x;
+    const int rowjump = (nx - nvx) * nz, ustride = (wx + 1) * nz;
     int z = threadIdx.x % nz, cx = threadIdx.x / nz, cy = 0;
     while (cx >= nvx) { cx -= nvx; ++cy; }
-    for (; t < total; t += 256) {
-        const int vx = vx_lo + cx, vy = vy_lo + cy;
-        cf32 xv = x[((int64_t)vy * nx + vx) * nz + z];
-        const int adx = px > vx ? px - vx : vx - px, ady = py > vy ? py - vy : vy - py;
-        const int64_t o = ((int64_t)ady * (wx + 1) + adx) * nz + z;
+    int xoff = ((vy_lo + cy) * nx + vx_lo + cx) * nz + z;
+    int urow = (py > vy_lo + cy ? py - vy_lo - cy : vy_lo + cy - py) * ustride;
+    const int pxr = px - vx_lo;                      // window column of the position
+    for (int t = threadIdx.x; t < total; t += 256) {
+        cf32 xv = x[xoff];
+        const int adx = pxr > cx ? pxr - cx : cx - pxr;
+        const int o = urow + adx * nz + z;
         const uint32_t u = ut[o];
         if (amp) {                       // Gaussian beam: g scales every bin's term
             const float gb = amp[o];
@@ -88,10 +92,19 @@ __global__ __launch_bounds__(256) void fwd_phasor_kernel(
             acc_re[j] += xv.re * c + xv.im * s;
             acc_im[j] += xv.im * c - xv.re * s;
         }
+        xoff += 256;
         z += dz;
         cx += dcol;
         if (z >= nz) { z -= nz; ++cx; }
-        while (cx >= nvx) { cx -= nvx; ++cy; }
+        if (cx >= nvx) {
+            do {
+                cx -= nvx;
+                ++cy;
+                xoff += rowjump;
+            } while (cx >= nvx);
+            const int vy = vy_lo + cy;
+            urow = (py > vy ? py - vy : vy - py) * ustride;
+        }
     }
     // reduce over the block
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -141,6 +154,10 @@ void launch_forward_phasor(const Plan& P, const cf32* x, cf32* y, const cf32* ym
     const int ngroups = (P.m + mb - 1) / mb;
     const int nblk = P.npos * ngroups;
     if (nblk > P.part_cap) fail(UFSS_ERR_UNSUPPORTED, "too many positions for the phasor path");
+    // the forward walks the volume and the delay table with 32-bit offsets
+    if ((int64_t)(P.npos + P.g.nx + 1) * P.g.nz + 256 > INT32_MAX ||
+        (int64_t)(P.d.wy + 1) * (P.d.wx + 1) * P.g.nz > INT32_MAX)
+        fail(UFSS_ERR_UNSUPPORTED, "volume too large for the phasor path");
 #define UFSS_PF(MBV)                                                                              \
     hipLaunchKernelGGL(fwd_phasor_kernel<MBV>, dim3(nblk), dim3(256), 0, s, x, P.d_u, P.d_amp,    \
                        P.d_bins, P.d_hsel, ymeas, y, part, P.g.nx, P.g.ny, P.g.nz, P.d.wx, P.d.wy, \
