@@ -27,6 +27,8 @@
 // grid); phasors are generated per lane in registers.  Accumulation is two
 // level (per d_y in MFMA registers, then into an outer FP32 sum) to keep the
 // FP32 error of ~1e5-term sums near 1e-6.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace ufss {
@@ -107,7 +109,8 @@ struct FwdArgs {
 template <int NP, int ZC, bool DIR = false>
 __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int nblk, unsigned char* smem) {
     constexpr int zc = ZC;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int sw = a.sw, sh = 16 / sw;
     const int tpx = sw * NP, tpy = sh;
     const int hc = tpx + 2 * a.wx;            // halo columns
@@ -139,97 +142,142 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
     const int dx_lo = max(-a.wx, px0 - (a.nx - 1));
     const int dx_hi = min(a.wx, px0 + tpx - 1);
 
-    const int mb = bt * 16 * a.nw + wave * 16 + (lane & 15);   // this lane's bin column
-    const bool wave_active = wave < a.nw && bt * 16 * a.nw + wave * 16 < a.mu;
-    const uint32_t kbin = (mb < a.mu) ? (uint32_t)a.kb[mb] : 0u;
+    const int bin0 = bt * 16 * a.nw + wave * 16;               // this wave's first bin
+    const bool wave_active = wave < a.nw && bin0 < a.mu;
     const int i = lane & 15, ix = i % sw, iy = i / sw;
     const int kq = lane >> 4;
+    // A wave left with at most 4 bins (the short last one of a union such as
+    // 66 = 4 x 16 + 2) runs v_mfma_f32_4x4x1_16b_f32 instead: 16 blocks of a
+    // 4 x 4 product with one depth each, the same rate per flop, a quarter of
+    // the 16 x 16 x 4 cycles.  Its A operand is the same (lane l: position
+    // l % 16, depth l / 16), its B operand takes bin l % 4 (block l / 4 =
+    // (position group, depth)), and the four depth blocks of a position group
+    // are summed across lanes at the end.
+    const bool tail = wave_active && a.mu - bin0 <= 4;
+    auto run = [&](auto tailc) {
+        constexpr bool TAIL = decltype(tailc)::value;
+        const int mb = bin0 + (TAIL ? (lane & 3) : (lane & 15));   // this lane's bin column
+        const uint32_t kbin = (mb < a.mu) ? (uint32_t)a.kb[mb] : 0u;
+        auto mfma = [](float av, float bv, f4 acc) {
+            if constexpr (TAIL) return __builtin_amdgcn_mfma_f32_4x4x1f32(av, bv, acc, 0, 0, 0);
+            else return __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+        };
 
-    f4 out_re[NP], out_im[NP];
+        f4 out_re[NP], out_im[NP];
 #pragma unroll
-    for (int s = 0; s < NP; ++s) out_re[s] = out_im[s] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int s = 0; s < NP; ++s) out_re[s] = out_im[s] = f4{0.f, 0.f, 0.f, 0.f};
 
-    for (int z0 = z_lo; z0 < z_hi; z0 += zc) {
-        for (int dy = dy_lo; dy <= dy_hi; ++dy) {
-            __syncthreads();
-            // stage x rows (py0 + r - dy), columns (px0 - wx + c), depths z0..z0+zc
-            // rows live in slot (grid row mod tpy): after the first d_y only the row
-            // entering the window is loaded
-            stage_halo<8>(halo, cs, dy == dy_lo ? tpy : 1, hc, hc, tpy - 1, zc, a.x, a.ny, a.nx, a.nz,
-                          py0 - dy, px0 - a.wx, z0, a.nz);
-            const int ady = dy < 0 ? -dy : dy;
-            for (int t = threadIdx.x; t < (a.wx + 1) * zc; t += blockDim.x) {
-                int adx = t / zc, zz = t - adx * zc;
-                int z = z0 + zz;
-                const int64_t o = ((int64_t)ady * (a.wx + 1) + adx) * a.nz + z;
-                ulds[t] = z < a.nz ? a.u[o] : 0u;
-                if (DIR) glds[t] = z < a.nz ? a.amp[o] : 0.f;
-            }
-            __syncthreads();
-            if (!wave_active) continue;
-            // Gauss's three-product form of (xr + j xi)(c - j s):
-            //   m1 = c (xr + xi), m2 = xr (-s - c), m3 = xi (c - s);
-            //   Re = m1 - m3 = xr c + xi s,  Im = m1 + m2 = xi c - xr s
-            f4 m1[NP], m2[NP], m3[NP];
-#pragma unroll
-            for (int s = 0; s < NP; ++s) m1[s] = m2[s] = m3[s] = f4{0.f, 0.f, 0.f, 0.f};
-            for (int dx = dx_lo; dx <= dx_hi; ++dx) {
-                const int adx = dx < 0 ? -dx : dx;
-                const uint32_t* urow = ulds + adx * zc;
-                const cf32* hrow = halo + ((((py0 + iy - dy) & (tpy - 1)) * hc) + ix + a.wx - dx) * cs;
-                // sub-tiles whose shifted columns all fall outside the grid add
-                // exact zeros: skip their MFMAs (wave-uniform test)
-                bool act[NP];
-#pragma unroll
-                for (int s = 0; s < NP; ++s) {
-                    const int c0 = px0 + s * sw - dx;
-                    act[s] = c0 + sw - 1 >= 0 && c0 <= a.nx - 1;
+        for (int z0 = z_lo; z0 < z_hi; z0 += zc) {
+            for (int dy = dy_lo; dy <= dy_hi; ++dy) {
+                __syncthreads();
+                // stage x rows (py0 + r - dy), columns (px0 - wx + c), depths z0..z0+zc
+                // rows live in slot (grid row mod tpy): after the first d_y only the row
+                // entering the window is loaded
+                stage_halo<8>(halo, cs, dy == dy_lo ? tpy : 1, hc, hc, tpy - 1, zc, a.x, a.ny, a.nx, a.nz,
+                              py0 - dy, px0 - a.wx, z0, a.nz);
+                const int ady = dy < 0 ? -dy : dy;
+                for (int t = threadIdx.x; t < (a.wx + 1) * zc; t += blockDim.x) {
+                    int adx = t / zc, zz = t - adx * zc;
+                    int z = z0 + zz;
+                    const int64_t o = ((int64_t)ady * (a.wx + 1) + adx) * a.nz + z;
+                    ulds[t] = z < a.nz ? a.u[o] : 0u;
+                    if (DIR) glds[t] = z < a.nz ? a.amp[o] : 0.f;
                 }
-                float cz[zc / 4], bmz[zc / 4], bpz[zc / 4];
+                __syncthreads();
+                if (!wave_active) continue;
+                // Gauss's three-product form of (xr + j xi)(c - j s):
+                //   m1 = c (xr + xi), m2 = xr (-s - c), m3 = xi (c - s);
+                //   Re = m1 - m3 = xr c + xi s,  Im = m1 + m2 = xi c - xr s
+                f4 m1[NP], m2[NP], m3[NP];
 #pragma unroll
-                for (int j = 0; j < zc / 4; ++j) {
-                    float c, sn;
-                    phasor(kbin * urow[4 * j + kq], c, sn);
-                    if (DIR) {
-                        const float gv = glds[adx * zc + 4 * j + kq];
-                        c *= gv;
-                        sn *= gv;
+                for (int s = 0; s < NP; ++s) m1[s] = m2[s] = m3[s] = f4{0.f, 0.f, 0.f, 0.f};
+                for (int dx = dx_lo; dx <= dx_hi; ++dx) {
+                    const int adx = dx < 0 ? -dx : dx;
+                    const uint32_t* urow = ulds + adx * zc;
+                    const cf32* hrow = halo + ((((py0 + iy - dy) & (tpy - 1)) * hc) + ix + a.wx - dx) * cs;
+                    // sub-tiles whose shifted columns all fall outside the grid add
+                    // exact zeros: skip their MFMAs (wave-uniform test)
+                    bool act[NP];
+#pragma unroll
+                    for (int s = 0; s < NP; ++s) {
+                        const int c0 = px0 + s * sw - dx;
+                        act[s] = c0 + sw - 1 >= 0 && c0 <= a.nx - 1;
                     }
-                    cz[j] = c;
-                    bmz[j] = -sn - c;
-                    bpz[j] = c - sn;
-                }
-#pragma unroll
-                for (int s = 0; s < NP; ++s) {
-                    if (!act[s]) continue;
+                    float cz[zc / 4], bmz[zc / 4], bpz[zc / 4];
 #pragma unroll
                     for (int j = 0; j < zc / 4; ++j) {
-                        cf32 xv = hrow[s * sw * cs + 4 * j + kq];
-                        m1[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.re + xv.im, cz[j], m1[s], 0, 0, 0);
-                        m2[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.re, bmz[j], m2[s], 0, 0, 0);
-                        m3[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.im, bpz[j], m3[s], 0, 0, 0);
+                        float c, sn;
+                        phasor(kbin * urow[4 * j + kq], c, sn);
+                        if (DIR) {
+                            const float gv = glds[adx * zc + 4 * j + kq];
+                            c *= gv;
+                            sn *= gv;
+                        }
+                        cz[j] = c;
+                        bmz[j] = -sn - c;
+                        bpz[j] = c - sn;
+                    }
+#pragma unroll
+                    for (int s = 0; s < NP; ++s) {
+                        if (!act[s]) continue;
+#pragma unroll
+                        for (int j = 0; j < zc / 4; ++j) {
+                            cf32 xv = hrow[s * sw * cs + 4 * j + kq];
+                            m1[s] = mfma(xv.re + xv.im, cz[j], m1[s]);
+                            m2[s] = mfma(xv.re, bmz[j], m2[s]);
+                            m3[s] = mfma(xv.im, bpz[j], m3[s]);
+                        }
                     }
                 }
+#pragma unroll
+                for (int s = 0; s < NP; ++s) {
+                    out_re[s] += m1[s] - m3[s];
+                    out_im[s] += m1[s] + m2[s];
+                }
             }
+        }
+        if (!wave_active) return;
+        cf32* yo = a.yraw + (int64_t)sp_all * a.npos * a.mu;
+        if constexpr (TAIL) {
+            // lane l holds rows r = 0..3 (positions 4 (l / 4 % 4) + r) of column
+            // l % 4 of block l / 4; the blocks of depths 0..3 (lanes l, l ^ 16,
+            // l ^ 32, l ^ 48) are summed in a fixed order
+#pragma unroll
+            for (int s = 0; s < NP; ++s)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    out_re[s][r] += __shfl_xor(out_re[s][r], 16, 64);
+                    out_im[s][r] += __shfl_xor(out_im[s][r], 16, 64);
+                    out_re[s][r] += __shfl_xor(out_re[s][r], 32, 64);
+                    out_im[s][r] += __shfl_xor(out_im[s][r], 32, 64);
+                }
+            if (lane >= 16 || mb >= a.mu) return;
 #pragma unroll
             for (int s = 0; s < NP; ++s) {
-                out_re[s] += m1[s] - m3[s];
-                out_im[s] += m1[s] + m2[s];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int irow = 4 * (lane >> 2) + r;
+                    const int px = px0 + s * sw + irow % sw, py = py0 + irow / sw;
+                    if (px < a.nx && py < a.ny)
+                        yo[((int64_t)py * a.nx + px) * a.mu + mb] = cf32{out_re[s][r], out_im[s][r]};
+                }
+            }
+        } else {
+            if (mb >= a.mu) return;
+#pragma unroll
+            for (int s = 0; s < NP; ++s) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    int irow = 4 * kq + r;
+                    int px = px0 + s * sw + irow % sw, py = py0 + irow / sw;
+                    if (px < a.nx && py < a.ny)
+                        yo[((int64_t)py * a.nx + px) * a.mu + mb] = cf32{out_re[s][r], out_im[s][r]};
+                }
             }
         }
-    }
-    if (!wave_active || mb >= a.mu) return;
-    cf32* yo = a.yraw + (int64_t)sp_all * a.npos * a.mu;
-#pragma unroll
-    for (int s = 0; s < NP; ++s) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            int irow = 4 * kq + r;
-            int px = px0 + s * sw + irow % sw, py = py0 + irow / sw;
-            if (px < a.nx && py < a.ny)
-                yo[((int64_t)py * a.nx + px) * a.mu + mb] = cf32{out_re[s][r], out_im[s][r]};
-        }
-    }
+    };
+    if (tail) run(std::true_type{});
+    else run(std::false_type{});
 }
 
 template <int NP, int ZC, bool DIR = false>
