@@ -46,8 +46,8 @@ PEAK_PHASOR_TERMS = 256 * 4 * 16 * 2.4e9 / PHASOR_SLOTS_PER_TERM
 # source it was measured on; a changed source or another tiling reports null.
 TRAFFIC = {
     # 32 x 32 C-scan, FP32 union-GEMM, shipped tiling (profiles/cscan32_fp32_gemm.md)
-    "cscan32/gemm/forward/fs4-zs8-nw5-np2-zc8": {"bytes": 20.579e6, "sha": "07604cb76073e38b"},
-    "cscan32/gemm/adjoint/as12-np2-kc16": {"bytes": 32.304e6, "sha": "07604cb76073e38b"},
+    "cscan32/gemm/forward/fs4-zs8-nw5-np2-zc16": {"bytes": 20.675e6, "sha": "ff8d8f30a900106b"},
+    "cscan32/gemm/adjoint/as12-np2-kc16": {"bytes": 32.304e6, "sha": "ff8d8f30a900106b"},
     # transform-domain contraction (profiles/cscan32_fp32_transform.md, cscan64_fp32_transform.md):
     # the table once plus the transform rows in and out
     "cscan32/transform/forward/fs1-zs1-nw1-np0-zc0": {"bytes": 149.649e6, "sha": "130f6e5e72ba81e0"},
@@ -59,14 +59,12 @@ TRAFFIC = {
     "cscan32/transform-bf16/forward/fs1-zs1-nw1-np0-zc0": {"bytes": 80.372e6, "sha": "130f6e5e72ba81e0"},
     "cscan64/transform-bf16/adjoint/as1-np0-kc0": {"bytes": 473.496e6, "sha": "130f6e5e72ba81e0"},
     "cscan64/transform-bf16/forward/fs1-zs1-nw1-np0-zc0": {"bytes": 473.496e6, "sha": "130f6e5e72ba81e0"},
-    # BF16 GEMMs with phasor tables (profiles/cscan32_bf16_gemm.md, cscan64_bf16_gemm.md):
+    # BF16 GEMMs with phasor tables (profiles/cscan32_bf16_gemm.md):
     # mostly re-reads of the table tiles, one per workgroup and offset (the
     # tables, 170 MB at 32 x 32, sit in the last-level cache); the 32 x 32
     # forward is two launches (full bin tiles, then the short last one)
-    "cscan32/gemm-bf16/forward/fs12-zs8-wr1": {"bytes": 246.791e6, "sha": "cadb8dfe195b2976"},
-    "cscan32/gemm-bf16/adjoint/as12-wr1-nz2": {"bytes": 809.142e6, "sha": "cadb8dfe195b2976"},
-    "cscan64/gemm-bf16/forward/fs2-zs8-wr1": {"bytes": 483.769e6, "sha": "cadb8dfe195b2976"},
-    "cscan64/gemm-bf16/adjoint/as3-wr1-nz2": {"bytes": 676.594e6, "sha": "cadb8dfe195b2976"},
+    "cscan32/gemm-bf16/forward/fs12-zs8-wr1": {"bytes": 282.074e6, "sha": "b75fd29285f69f3d"},
+    "cscan32/gemm-bf16/adjoint/as12-wr1-nz2": {"bytes": 808.820e6, "sha": "b75fd29285f69f3d"},
 }
 TRAFFIC_SRC = {"gemm": "paper_2012_04534_amd/csrc/gemm_f32.hip",
                "transform": "paper_2012_04534_amd/csrc/fft.hip",
