@@ -383,7 +383,13 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
             for (int s = 0; s < NP; ++s)
 #pragma unroll
                 for (int q = 0; q < NZ; ++q) m1[s][q] = m2[s][q] = m3[s][q] = f4{0.f, 0.f, 0.f, 0.f};
-            for (int dx = dx_lo; dx <= dx_hi; ++dx) {
+            // the offsets of [d0, d1] with the sub-tiles of MASK active: with two
+            // sub-tiles the range splits into (second only, both, first only),
+            // and a sub-tile whose shifted columns all leave the grid runs no
+            // MFMAs (compile-time masks keep the products branch-free)
+            auto dxloop = [&](auto maskc, const int d0, const int d1) {
+                constexpr int MASK = decltype(maskc)::value;
+            for (int dx = d0; dx <= d1; ++dx) {
                 const int adx = dx < 0 ? -dx : dx;
                 uint32_t uz[NZ];
                 float gz[NZ];
@@ -415,12 +421,23 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
                         const float bm = sn - c, bp = c + sn;
 #pragma unroll
                         for (int s = 0; s < NP; ++s) {
+                            if (!((MASK >> s) & 1)) continue;
                             m1[s][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(rs[s], c, m1[s][q], 0, 0, 0);
                             m2[s][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(rv[s].re, bm, m2[s][q], 0, 0, 0);
                             m3[s][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(rv[s].im, bp, m3[s][q], 0, 0, 0);
                         }
                     }
                 }
+            }
+            };
+            if constexpr (NP == 2) {
+                // column ranges of the two sub-tiles' shifted voxels inside the grid
+                const int a0 = -(vx0 + sw - 1), b1 = a.nx - 1 - vx0 - sw;
+                dxloop(std::integral_constant<int, 2>{}, dx_lo, min(min(a0 - 1, b1), dx_hi));
+                dxloop(std::integral_constant<int, 3>{}, max(dx_lo, a0), min(b1, dx_hi));
+                dxloop(std::integral_constant<int, 1>{}, max(max(a0, b1 + 1), dx_lo), dx_hi);
+            } else {
+                dxloop(std::integral_constant<int, (1 << NP) - 1>{}, dx_lo, dx_hi);
             }
 #pragma unroll
             for (int s = 0; s < NP; ++s)
