@@ -59,12 +59,14 @@ TRAFFIC = {
     "cscan32/transform-bf16/forward/fs1-zs1-nw1-np0-zc0": {"bytes": 80.372e6, "sha": "130f6e5e72ba81e0"},
     "cscan64/transform-bf16/adjoint/as1-np0-kc0": {"bytes": 473.496e6, "sha": "130f6e5e72ba81e0"},
     "cscan64/transform-bf16/forward/fs1-zs1-nw1-np0-zc0": {"bytes": 473.496e6, "sha": "130f6e5e72ba81e0"},
-    # BF16 GEMMs with phasor tables (profiles/cscan32_bf16_gemm.md):
+    # BF16 GEMMs with phasor tables (profiles/cscan32_bf16_gemm.md, cscan64_bf16_gemm.md):
     # mostly re-reads of the table tiles, one per workgroup and offset (the
     # tables, 170 MB at 32 x 32, sit in the last-level cache); the 32 x 32
     # forward is two launches (full bin tiles, then the short last one)
     "cscan32/gemm-bf16/forward/fs12-zs8-wr1": {"bytes": 282.074e6, "sha": "b75fd29285f69f3d"},
     "cscan32/gemm-bf16/adjoint/as12-wr1-nz2": {"bytes": 808.820e6, "sha": "b75fd29285f69f3d"},
+    "cscan64/gemm-bf16/forward/fs2-zs8-wr1": {"bytes": 510.794e6, "sha": "b75fd29285f69f3d"},
+    "cscan64/gemm-bf16/adjoint/as3-wr1-nz2": {"bytes": 675.016e6, "sha": "b75fd29285f69f3d"},
 }
 TRAFFIC_SRC = {"gemm": "paper_2012_04534_amd/csrc/gemm_f32.hip",
                "transform": "paper_2012_04534_amd/csrc/fft.hip",
