@@ -205,23 +205,67 @@ __global__ __launch_bounds__(256) void adj_phasor_kernel(
     const int nrow = py_hi - py_lo + 1, rows_per = (nrow + nsplit - 1) / nsplit;
     const int r_lo = py_lo + sidx * rows_per, r_hi = min(py_hi, r_lo + rows_per - 1);
     float acc_re = 0.f, acc_im = 0.f;
+    // one position's bins: (rr + j ri)(c + j s) summed over its selection
+    auto position = [&](const int64_t prow, const uint32_t u, float& in_re, float& in_im) {
+        for (int mi = 0; mi < m; ++mi) {
+            const uint32_t k = (uint32_t)bins[prow + mi];
+            const cf32 rv = rop[prow + mi];
+            float c, s;
+            phasor_p(k * u, c, s);
+            in_re += rv.re * c - rv.im * s;
+            in_im += rv.re * s + rv.im * c;
+        }
+    };
     for (int py = r_lo; py <= r_hi; ++py) {
         const int ady = py > vy ? py - vy : vy - py;
-        for (int px = px_lo; px <= px_hi; ++px) {
-            const int adx = px > vx ? px - vx : vx - px;
-            const int64_t o = ((int64_t)ady * (wx + 1) + adx) * nz + zl;
-            const uint32_t u = ut[o];
-            const int64_t prow = ((int64_t)py * nx + px) * m;
-            float in_re = 0.f, in_im = 0.f;
-            for (int mi = 0; mi < m; ++mi) {
-                const uint32_t k = (uint32_t)bins[prow + mi];
-                const cf32 rv = rop[prow + mi];
-                float c, s;
-                phasor_p(k * u, c, s);
-                // (rr + j ri)(c + j s)
-                in_re += rv.re * c - rv.im * s;
-                in_im += rv.re * s + rv.im * c;
+        const int64_t obase = (int64_t)ady * (wx + 1) * nz + zl;
+        const int64_t prow0 = (int64_t)py * nx * m;
+        int px = px_lo;
+        // four positions at a time: their delays and beams (vector loads) and,
+        // with one bin per position, their bins and operands (scalar loads)
+        // are all requested before the first is used
+        for (; px + 3 <= px_hi; px += 4) {
+            uint32_t u4[4];
+            float g4[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int adx = px + t > vx ? px + t - vx : vx - px - t;
+                const int64_t o = obase + (int64_t)adx * nz;
+                u4[t] = ut[o];
+                g4[t] = amp ? amp[o] : 1.f;
             }
+            if (m == 1) {
+                uint32_t k4[4];
+                cf32 r4[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    k4[t] = (uint32_t)bins[prow0 + px + t];
+                    r4[t] = rop[prow0 + px + t];
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    float c, s;
+                    phasor_p(k4[t] * u4[t], c, s);
+                    const float in_re = r4[t].re * c - r4[t].im * s;
+                    const float in_im = r4[t].re * s + r4[t].im * c;
+                    acc_re += g4[t] * in_re;
+                    acc_im += g4[t] * in_im;
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    float in_re = 0.f, in_im = 0.f;
+                    position(prow0 + (int64_t)(px + t) * m, u4[t], in_re, in_im);
+                    acc_re += g4[t] * in_re;
+                    acc_im += g4[t] * in_im;
+                }
+            }
+        }
+        for (; px <= px_hi; ++px) {
+            const int adx = px > vx ? px - vx : vx - px;
+            const int64_t o = obase + (int64_t)adx * nz;
+            float in_re = 0.f, in_im = 0.f;
+            position(prow0 + (int64_t)px * m, ut[o], in_re, in_im);
             const float gb = amp ? amp[o] : 1.f;
             acc_re += gb * in_re;
             acc_im += gb * in_im;
