@@ -207,6 +207,8 @@ __global__ __launch_bounds__(256) void adj_phasor_kernel(
     float acc_re = 0.f, acc_im = 0.f;
     // one position's bins: (rr + j ri)(c + j s) summed over its selection
     auto position = [&](const int64_t prow, const uint32_t u, float& in_re, float& in_im) {
+        // unrolled so that the scalar loads of two bins are requested together
+#pragma unroll 2
         for (int mi = 0; mi < m; ++mi) {
             const uint32_t k = (uint32_t)bins[prow + mi];
             const cf32 rv = rop[prow + mi];
