@@ -29,11 +29,17 @@ namespace ufss {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+typedef short s4v __attribute__((ext_vector_type(4)));
 
 static constexpr float kTwoM32b = 2.3283064365386963e-10f;
 static constexpr int ZCB = 32;             // reduction chunk = one MFMA K
 static constexpr int CELL = 2 * ZCB + 8;   // bf16 per halo cell (re, im, pad)
 static constexpr int PROW = ZCB + 8;       // bf16 per phasor-tile row
+// Adjoint with a short last bin chunk (at most ZX bins past the last full
+// one, e.g. 66 = 2 x 32 + 2): those bins ride along with the previous chunk in
+// the padding of its cells (re at 2 ZCB, im at 2 ZCB + ZX) and tile rows (at ZCB)
+static constexpr int ZX = 4;
 
 __device__ __forceinline__ void sincos_turns(uint32_t ku, float& c, float& s) {
     float ph = (float)(int32_t)ku * kTwoM32b;
@@ -51,22 +57,22 @@ __device__ __forceinline__ bf8 neg_bf8(bf8 v) {
     return __builtin_bit_cast(bf8, w);
 }
 
-// Stages rows x ncol cells of ZCB complex BF16 values into planar LDS cells
-// (ZCB real parts, then ZCB imaginary parts; row pitch `pitch` cells; grid row
-// gy = ybase + r in row slot gy & slot_mask, so a window of consecutive rows
-// that moves by one row only needs the entering row staged):
-//   cell (gy & slot_mask, c) <- src[(gy * nx + xbase + c) * ld + i0 + e], e < ZCB,
+// Stages rows x ncol cells of W complex BF16 values into planar LDS cells of
+// CELL bf16 (real parts at re0, imaginary parts at im0; row pitch `pitch` cells;
+// grid row gy = ybase + r in row slot gy & slot_mask, so a window of
+// consecutive rows that moves by one row only needs the entering row staged):
+//   cell (gy & slot_mask, c) <- src[(gy * nx + xbase + c) * ld + i0 + e], e < W,
 // zero for rows outside the grid or past `ilim` along the inner axis (columns
 // are inside the grid by construction).  Each thread keeps one e and walks the
 // cells with a fixed step, with UNR loads in flight before the LDS stores.
-template <int UNR>
+template <int UNR, int W = ZCB>
 __device__ __forceinline__ void stage_planar(__bf16* __restrict__ halo, int rows, int ncol, int pitch, int slot_mask,
                                              const cbf16* __restrict__ src, int ny, int nx, int64_t ld,
-                                             int ybase, int xbase, int i0, int ilim) {
-    const int e = threadIdx.x & (ZCB - 1);
-    const int step = blockDim.x / ZCB;
+                                             int ybase, int xbase, int i0, int ilim, int re0 = 0, int im0 = ZCB) {
+    const int e = threadIdx.x & (W - 1);
+    const int step = blockDim.x / W;
     const int total = rows * ncol;
-    int cell = threadIdx.x / ZCB;
+    int cell = threadIdx.x / W;
     int r = cell / ncol, c = cell - r * ncol;
     const bool eok = i0 + e < ilim;
     for (; cell < total; cell += UNR * step) {
@@ -86,8 +92,8 @@ __device__ __forceinline__ void stage_planar(__bf16* __restrict__ halo, int rows
 #pragma unroll
         for (int u = 0; u < UNR; ++u)
             if (cell + u * step < total) {
-                halo[(size_t)dst[u] * CELL + e] = v[u].re;
-                halo[(size_t)dst[u] * CELL + ZCB + e] = v[u].im;
+                halo[(size_t)dst[u] * CELL + re0 + e] = v[u].re;
+                halo[(size_t)dst[u] * CELL + im0 + e] = v[u].im;
             }
         r = rr;
         c = cc;
@@ -102,6 +108,7 @@ __device__ __forceinline__ void stage_planar(__bf16* __restrict__ halo, int rows
 // and written to LDS afterwards (tab_store).
 struct TabRegs {
     u4 v[2];
+    u2 x;                  // folded short chunk: the first ZX bins of the next table chunk
 };
 
 __device__ __forceinline__ void tab_load(TabRegs& R, const __bf16* __restrict__ src, int rows_valid) {
@@ -120,6 +127,29 @@ __device__ __forceinline__ void tab_store(const TabRegs& R, __bf16* pc, __bf16* 
         if (row < nrows)
             *reinterpret_cast<u4*>((part < 4 ? pc : ps) + row * PROW + (part & 3) * 8) = R.v[p];
     }
+}
+
+// The folded bins' part of a tile: per row the first ZX cos and ZX sin values
+// of the next table chunk (2 x 8 bytes, one per thread, threads 0..127),
+// stored in columns ZCB .. ZCB + ZX - 1 of the rows.
+__device__ __forceinline__ void tab_load_x(TabRegs& R, const __bf16* __restrict__ src, int rows_valid) {
+    const int t = threadIdx.x, row = t >> 1, part = t & 1;
+    R.x = u2{0u, 0u};
+    if (t < 128 && row < rows_valid) R.x = *reinterpret_cast<const u2*>(src + (size_t)row * 64 + part * ZCB);
+}
+
+__device__ __forceinline__ void tab_store_x(const TabRegs& R, __bf16* pc, __bf16* ps, int nrows) {
+    const int t = threadIdx.x, row = t >> 1, part = t & 1;
+    if (t < 128 && row < nrows) *reinterpret_cast<u2*>((part ? ps : pc) + row * PROW + ZCB) = R.x;
+}
+
+__device__ __forceinline__ s4v lds_s4(const __bf16* p) {
+    return __builtin_bit_cast(s4v, *reinterpret_cast<const u2*>(p));
+}
+
+__device__ __forceinline__ s4v neg_s4(s4v v) {
+    const u2 w = __builtin_bit_cast(u2, v);
+    return __builtin_bit_cast(s4v, u2{w.x ^ 0x80008000u, w.y ^ 0x80008000u});
 }
 
 // Cooperative phasor generation: `rows` x ZCB entries of cos / sin(2 pi k u)
@@ -274,6 +304,15 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
             const int adx_hi = max(dx_hi, -dx_lo);
             const int adx_lo = (dx_lo <= 0 && dx_hi >= 0) ? 0 : min(dx_lo < 0 ? -dx_lo : dx_lo, dx_hi < 0 ? -dx_hi : dx_hi);
             const bool wy_ok = dy >= wdy_lo && dy <= wdy_hi;
+            // this lane's halo column and byte address at d_x = 0 per sub-tile:
+            // at d_x the cell is column - d_x when that column is staged, else
+            // the zero cell (an add, a compare and a select per step)
+            int hcol[NP], hadr[NP];
+#pragma unroll
+            for (int s = 0; s < NP; ++s) {
+                hcol[s] = px0 + (wave_x * NP + s) * sw + i % sw - cx_lo;
+                hadr[s] = (((py0 + wave_y * sh + i / sw - dy) & (tpy - 1)) * pitch + hcol[s]) * (CELL * 2);
+            }
             TabRegs Ra, Rb;
             if (dx_lo <= dx_hi) {
                 if (a.tab) {
@@ -318,12 +357,10 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdB& a, int b, const int nb
                     bf8 xr[NP], xi[NP];
 #pragma unroll
                     for (int s = 0; s < NP; ++s) {
-                        const int q = wave_x * NP + s;
-                        const int px = px0 + q * sw + i % sw, iy = wave_y * sh + i / sw;
-                        const int gx = px - dx;
-                        const int cell = (gx >= cx_lo && gx <= cx_hi) ? ((py0 + iy - dy) & (tpy - 1)) * pitch + (gx - cx_lo) : zero_cell;
-                        xr[s] = lds_bf8(halo + (size_t)cell * CELL + 8 * kq);
-                        xi[s] = lds_bf8(halo + (size_t)cell * CELL + ZCB + 8 * kq);
+                        const int ab = (unsigned)(hcol[s] - dx) < (unsigned)ncol ? hadr[s] - dx * (CELL * 2) : zero_cell * (CELL * 2);
+                        const __bf16* hp = reinterpret_cast<const __bf16*>(reinterpret_cast<const unsigned char*>(halo) + ab);
+                        xr[s] = lds_bf8(hp + 8 * kq);
+                        xi[s] = lds_bf8(hp + ZCB + 8 * kq);
                     }
                     // (xr + j xi)(c - j s) = xr c + xi s + j (xi c - xr s)
 #pragma unroll
@@ -431,7 +468,9 @@ struct AdjB {
     const __bf16* tab;     // phasor tiles [wy+1][wx+1][nkc][nz][2][32] or null
 };
 
-template <int NV, int NZ, int WR>
+// EXT: the plan's last chunk holds at most ZX bins; they are folded into the
+// previous chunk (phasors from the tables only).
+template <int NV, int NZ, int WR, bool EXT = false>
 __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nblk, unsigned char* smem) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -456,7 +495,7 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
     const int pitch = ncol;
     __bf16* halo = reinterpret_cast<__bf16*>(smem);                  // [tvy*pitch + 1][CELL]
     const int zero_cell = tvy * pitch;
-    __bf16* ptile = halo + (size_t)(zero_cell + 1) * CELL;             // [2][2][zspan][PROW]
+    __bf16* ptile = halo + (size_t)(zero_cell + 1) * CELL;               // [2][2][zspan][PROW]
     // delay slab [wx+1][zspan] (phasor generation only: absent with tables), then bins [ZCB]
     uint32_t* ulds = reinterpret_cast<uint32_t*>(ptile + 2 * 2 * zspan * PROW);
     int* klds = reinterpret_cast<int*>(ulds + (a.tab ? 0 : (a.wx + 1) * zspan));
@@ -483,11 +522,18 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
 #pragma unroll
         for (int q = 0; q < NZ; ++q) acc_re[s][q] = acc_im[s][q] = f4{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = 0; k0 < a.mu; k0 += ZCB) {
+    const int nkm = EXT ? a.mu / ZCB : (a.mu + ZCB - 1) / ZCB;          // chunks run
+    for (int kc = 0; kc < nkm; ++kc) {
+        const int k0 = kc * ZCB;
+        const bool ext = EXT && kc == nkm - 1;            // this chunk carries the folded bins
         for (int dy = dy_lo; dy <= dy_hi; ++dy) {
             __syncthreads();
             stage_planar<8>(halo, dy == dy_lo ? tvy : 1, ncol, pitch, tvy - 1, a.r, a.ny, a.nx, a.mu,
                             dy == dy_lo ? vy0 + dy : vy0 + dy + tvy - 1, cx_lo, k0, a.mu);
+            if (ext)
+                stage_planar<4, ZX>(halo, dy == dy_lo ? tvy : 1, ncol, pitch, tvy - 1, a.r, a.ny, a.nx, a.mu,
+                                    dy == dy_lo ? vy0 + dy : vy0 + dy + tvy - 1, cx_lo, k0 + ZCB, a.mu,
+                                    2 * ZCB, 2 * ZCB + ZX);
             const int ady = dy < 0 ? -dy : dy;
             if (!a.tab)
                 for (int t = threadIdx.x; t < (a.wx + 1) * zspan; t += 256) {
@@ -533,18 +579,41 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
             const int64_t tstep = (int64_t)nkc * a.nz * 64;
             const int zrows = min(zspan, a.nz - zw0);
             auto tile_at = [&](int dx) { return tsrc + (dx < 0 ? -dx : dx) * tstep; };
+            // the folded bins: the same rows of the next table chunk
+            auto load = [&](TabRegs& R, int adx) {
+                tab_load(R, tile_at(adx), zrows);
+                if (ext) tab_load_x(R, tile_at(adx) + (int64_t)a.nz * 64, zrows);
+            };
+            auto store = [&](const TabRegs& R, __bf16* pn) {
+                tab_store(R, pn, pn + zspan * PROW, zspan);
+                if (ext) tab_store_x(R, pn, pn + zspan * PROW, zspan);
+            };
             // as in the forward: one staged tile serves d_x = +|d_x| and -|d_x|,
             // with two steps of prefetch
             const int adx_hi = max(dx_hi, -dx_lo);
             const int adx_lo = (dx_lo <= 0 && dx_hi >= 0) ? 0 : min(dx_lo < 0 ? -dx_lo : dx_lo, dx_hi < 0 ? -dx_hi : dx_hi);
             const bool wy_ok = dy >= wdy_lo && dy <= wdy_hi;
+            // as in the forward: halo column and byte address at d_x = 0 per
+            // sub-tile (the cell at d_x is column + d_x), for the lane's voxel
+            // i of the 16 x 16 products and voxel 4 kq + l % 4 of the folded ones
+            int hcol[NV], hadr[NV], xcol[EXT ? NV : 1], xadr[EXT ? NV : 1];
+#pragma unroll
+            for (int s = 0; s < NV; ++s) {
+                hcol[s] = vx0 + (wave_x * NV + s) * sw + i % sw - cx_lo;
+                hadr[s] = (((vy0 + wave_y * sh + i / sw + dy) & (tvy - 1)) * pitch + hcol[s]) * (CELL * 2);
+                if constexpr (EXT) {
+                    const int iv = 4 * kq + (lane & 3);
+                    xcol[s] = vx0 + (wave_x * NV + s) * sw + iv % sw - cx_lo;
+                    xadr[s] = (((vy0 + wave_y * sh + iv / sw + dy) & (tvy - 1)) * pitch + xcol[s]) * (CELL * 2);
+                }
+            }
             TabRegs Ra, Rb;
             if (dx_lo <= dx_hi) {
                 if (a.tab) {
                     TabRegs R0;
-                    tab_load(R0, tile_at(adx_lo), zrows);
-                    if (adx_lo < adx_hi) tab_load(Ra, tile_at(adx_lo + 1), zrows);
-                    tab_store(R0, ptile, ptile + zspan * PROW, zspan);
+                    load(R0, adx_lo);
+                    if (adx_lo < adx_hi) load(Ra, adx_lo + 1);
+                    store(R0, ptile);
                 } else {
                     gen(adx_lo, 0);
                 }
@@ -554,7 +623,7 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
             auto step = [&](const int adx, const int BUF, TabRegs& Rs, TabRegs& Rl) {
                 const bool more = adx < adx_hi;
                 if (a.tab) {
-                    if (adx + 2 <= adx_hi) tab_load(Rl, tile_at(adx + 2), zrows);
+                    if (adx + 2 <= adx_hi) load(Rl, adx + 2);
                 } else if (more) {
                     gen(adx + 1, BUF ^ 1);
                 }
@@ -574,12 +643,10 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
                     bf8 rr8[NV], ri8[NV];
 #pragma unroll
                     for (int s = 0; s < NV; ++s) {
-                        const int q = wave_x * NV + s;
-                        const int vx = vx0 + q * sw + i % sw, iy = wave_y * sh + i / sw;
-                        const int gx = vx + dx;
-                        const int cell = (gx >= cx_lo && gx <= cx_hi) ? ((vy0 + iy + dy) & (tvy - 1)) * pitch + (gx - cx_lo) : zero_cell;
-                        rr8[s] = lds_bf8(halo + (size_t)cell * CELL + 8 * kq);
-                        ri8[s] = lds_bf8(halo + (size_t)cell * CELL + ZCB + 8 * kq);
+                        const int ab = (unsigned)(hcol[s] + dx) < (unsigned)ncol ? hadr[s] + dx * (CELL * 2) : zero_cell * (CELL * 2);
+                        const __bf16* hp = reinterpret_cast<const __bf16*>(reinterpret_cast<const unsigned char*>(halo) + ab);
+                        rr8[s] = lds_bf8(hp + 8 * kq);
+                        ri8[s] = lds_bf8(hp + ZCB + 8 * kq);
                     }
                     // (rr + j ri)(c + j s) = rr c - ri s + j (rr s + ri c)
 #pragma unroll
@@ -603,14 +670,41 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
                         for (int s = 0; s < NV; ++s)
                             acc_re[s][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                                 ri8[s], neg_once ? ns8[q] : neg_bf8(s8[q]), acc_re[s][q], 0, 0, 0);
+                    if constexpr (EXT) {
+                        if (ext) {
+                            // the folded bins: v_mfma_f32_4x4x4_16b_bf16, 16 blocks of
+                            // 4 voxels x 4 depths with K = the ZX bins; block l / 4
+                            // takes voxels 4 (l / 16) .. + 3 and depths 4 (l / 4 % 4)
+                            // .. + 3, so lane l supplies voxel 4 kq + l % 4 (A) and depth
+                            // i (B) and the result lands in the 16 x 16 accumulator layout
+                            s4v rr4[NV], ri4[NV];
+#pragma unroll
+                            for (int s = 0; s < NV; ++s) {
+                                const int ab = (unsigned)(xcol[s] + dx) < (unsigned)ncol ? xadr[s] + dx * (CELL * 2) : zero_cell * (CELL * 2);
+                                const __bf16* hp = reinterpret_cast<const __bf16*>(reinterpret_cast<const unsigned char*>(halo) + ab);
+                                rr4[s] = lds_s4(hp + 2 * ZCB);
+                                ri4[s] = lds_s4(hp + 2 * ZCB + ZX);
+                            }
+#pragma unroll
+                            for (int q = 0; q < NZ; ++q) {
+                                const s4v c4 = lds_s4(pc + (q * 16 + i) * PROW + ZCB);
+                                const s4v s4 = lds_s4(ps + (q * 16 + i) * PROW + ZCB);
+                                const s4v n4 = neg_s4(s4);
+#pragma unroll
+                                for (int s = 0; s < NV; ++s) {
+                                    acc_re[s][q] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(rr4[s], c4, acc_re[s][q], 0, 0, 0);
+                                    acc_im[s][q] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(rr4[s], s4, acc_im[s][q], 0, 0, 0);
+                                    acc_im[s][q] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(ri4[s], c4, acc_im[s][q], 0, 0, 0);
+                                    acc_re[s][q] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(ri4[s], n4, acc_re[s][q], 0, 0, 0);
+                                }
+                            }
+                        }
+                    }
                 };
                 if (wy_ok && adx <= dx_hi && adx >= wdx_lo && adx <= wdx_hi) apply(adx);   // d_x = +|d_x|
                 if (wy_ok && adx > 0 && -adx >= dx_lo && -adx >= wdx_lo && -adx <= wdx_hi)
                     apply(-adx);                                                          // d_x = -|d_x|
-                if (more && a.tab) {
-                    __bf16* pn = ptile + (size_t)(BUF ^ 1) * 2 * zspan * PROW;
-                    tab_store(Rs, pn, pn + zspan * PROW, zspan);
-                }
+                if (more && a.tab) store(Rs, ptile + (size_t)(BUF ^ 1) * 2 * zspan * PROW);
                 __syncthreads();
             };
             if (dx_lo <= dx_hi)
@@ -640,10 +734,10 @@ __device__ __forceinline__ void adj_bf16_body(const AdjB& a, int b, const int nb
     }
 }
 
-template <int NV, int NZ, int WR>
+template <int NV, int NZ, int WR, bool EXT>
 __global__ __launch_bounds__(256) void adj_gemm_bf16_kernel(AdjB a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    adj_bf16_body<NV, NZ, WR>(a, blockIdx.x, gridDim.x, smem);
+    adj_bf16_body<NV, NZ, WR, EXT>(a, blockIdx.x, gridDim.x, smem);
 }
 
 // Grouped launch: block -> (plan index, block index inside that plan's grid).
@@ -701,6 +795,13 @@ static size_t adj_bf16_lds(const Plan& P, int nv, int wr, bool tables, int nzs =
     const int ncol = std::min(P.g.nx, tvx + 2 * P.d.wx);
     return (size_t)(tvy * ncol + 1) * CELL * 2 + (size_t)2 * 2 * nzs * 16 * PROW * 2 +
            (tables ? 0 : (size_t)(P.d.wx + 1) * nzs * 16 * 4) + ZCB * 4;
+}
+
+// The adjoint folds the last bin chunk into the previous one when it holds at
+// most ZX bins and the phasors come from the tables.
+static bool adj_bf16_ext(const Plan& P) {
+    const int mu = (int)P.ubins_h.size(), rem = mu % ZCB;
+    return P.d_ptab_a != nullptr && mu > ZCB && rem >= 1 && rem <= ZX;
 }
 
 // One-row tiles must fit with in-kernel phasor generation (the fallback).
@@ -854,8 +955,13 @@ void launch_adjoint_gemm_bf16(const Plan& P, cf32* out, hipStream_t s, bool sum)
     size_t lds;
     const int nv = bf_np(P), wr = P.bf_adj_rows == 2 ? 2 : 1, nzs = P.bf_adj_nz == 2 ? 2 : 4;
     adjb_args(P, out, a, lds, nv, wr, nzs);
+    const bool ext = adj_bf16_ext(P);
     const dim3 grid(a.nblk), block(256);
-#define UFSS_AB(NVV, NZV, WRV) hipLaunchKernelGGL((adj_gemm_bf16_kernel<NVV, NZV, WRV>), grid, block, lds, s, a)
+#define UFSS_AB(NVV, NZV, WRV)                                                                              \
+    do {                                                                                                    \
+        if (ext) hipLaunchKernelGGL((adj_gemm_bf16_kernel<NVV, NZV, WRV, true>), grid, block, lds, s, a);  \
+        else hipLaunchKernelGGL((adj_gemm_bf16_kernel<NVV, NZV, WRV, false>), grid, block, lds, s, a);     \
+    } while (0)
 #define UFSS_ABZ(NVV, WRV)                                  \
     do {                                                    \
         if (nzs == 2) UFSS_AB(NVV, 2, WRV);                 \

@@ -155,6 +155,30 @@ def test_bf16_fista_bscan(dev):
     plan.close()
 
 
+@pytest.mark.parametrize("m", [33, 36, 37, 68, 100])
+def test_bf16_adjoint_short_last_chunk(m, dev):
+    """Bin counts whose last 32-bin chunk holds 1, 4, 5, 4 and 4 bins: with the
+    phasor tables, up to 4 such bins are folded into the previous chunk's
+    offset steps (4 x 4 x 4 products), 5 take a chunk of their own; both match
+    the oracle, with the tables and with in-kernel phasor generation."""
+    u = ufss()
+    g = W.geometry(9, 5, 40, 1024, win_x=3, win_y=3)
+    bins, _ = u.ufss_select_freqs(g, m, False, 7 + m)
+    x = W.cn((g["ny"], g["nx"], g["nz"]), 500 + m)
+    y = W.cn((g["ny"], g["nx"], m), 600 + m)
+    A = O.dense_A(g, bins)
+    y_ref = (A @ x.reshape(-1)).reshape(y.shape)
+    x_ref = (A.conj().T @ y.reshape(-1)).reshape(x.shape)
+    plan = u.Plan(g, m, False, bins, dtype=u.BF16)
+    for enable in (True, False):
+        assert u.ufss_plan_set_phasor_tables(plan, enable) == enable
+        yo, xo = apply_both(u, plan, x, y, dev)
+        ey, ex = errs(yo, y_ref), errs(xo, x_ref)
+        assert max(ey) < TOL16 and max(ex) < TOL16, (enable, ey, ex)
+        assert ex[0] > 1e-5
+    plan.close()
+
+
 @pytest.mark.parametrize("ci", [2, 5, 6, 7])
 def test_bf16_tables_and_generation_agree(ci, dev):
     """The precomputed phasor tables (default) and in-kernel generation give
