@@ -63,10 +63,10 @@ TRAFFIC = {
     # mostly re-reads of the table tiles, one per workgroup and offset (the
     # tables, 170 MB at 32 x 32, sit in the last-level cache); the 32 x 32
     # forward is two launches (full bin tiles, then the short last one)
-    "cscan32/gemm-bf16/forward/fs12-zs8-wr1": {"bytes": 282.074e6, "sha": "b75fd29285f69f3d"},
-    "cscan32/gemm-bf16/adjoint/as12-wr1-nz2": {"bytes": 808.820e6, "sha": "b75fd29285f69f3d"},
-    "cscan64/gemm-bf16/forward/fs2-zs8-wr1": {"bytes": 510.794e6, "sha": "b75fd29285f69f3d"},
-    "cscan64/gemm-bf16/adjoint/as3-wr1-nz2": {"bytes": 675.016e6, "sha": "b75fd29285f69f3d"},
+    "cscan32/gemm-bf16/forward/fs12-zs8-wr1": {"bytes": 285.597e6, "sha": "6a80aa6837cf854b"},
+    "cscan32/gemm-bf16/adjoint/as12-wr1-nz2": {"bytes": 803.770e6, "sha": "6a80aa6837cf854b"},
+    "cscan64/gemm-bf16/forward/fs2-zs8-wr1": {"bytes": 508.500e6, "sha": "6a80aa6837cf854b"},
+    "cscan64/gemm-bf16/adjoint/as3-wr1-nz2": {"bytes": 680.896e6, "sha": "6a80aa6837cf854b"},
 }
 TRAFFIC_SRC = {"gemm": "paper_2012_04534_amd/csrc/gemm_f32.hip",
                "transform": "paper_2012_04534_amd/csrc/fft.hip",

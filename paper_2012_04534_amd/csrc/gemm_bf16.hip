@@ -11,6 +11,10 @@
 //
 // MFMA: v_mfma_f32_16x16x32_bf16.  Lane l holds A[i = l%16][k = 8(l/16) + e],
 // B[k = 8(l/16) + e][j = l%16] for e = 0..7, D[i = 4(l/16) + r][j = l%16].
+// The adjoint's folded short bin chunk uses v_mfma_f32_4x4x4_16b_bf16 (half
+// the cycles of the 16 x 16 x 32 form on gfx950, the 16 x 16 x 16 form costs
+// as much as the 16 x 16 x 32 one): block b = l/4 holds A_b[i = l%4][k = e],
+// B_b[k = e][j = l%4] for e = 0..3 and D_b[i = r][j = l%4].
 //
 // At BF16 rates a phasor costs far more VALU time than the MFMA work one wave
 // does with it, so the four waves of a workgroup share one phasor tile: it is
