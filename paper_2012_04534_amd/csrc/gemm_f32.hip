@@ -96,6 +96,7 @@ struct FwdArgs {
     int ntx, nty;          // lateral tiles
     int nbt;               // bin tiles of 16 * nw
     int nw;                // waves with a bin sub-tile (<= blockDim / 64)
+    int ft;                // bins past the last full tile (1..4) folded into it, else 0
     int zc;                // depth chunk (multiple of 4)
     int split;             // split of the d_y range
     int zsplit;            // split of the depth range (partials = split * zsplit)
@@ -106,7 +107,8 @@ struct FwdArgs {
 // ZC: the depth chunk a.zc as a compile-time constant (16, 8 or 4).
 // DIR: scale each phasor by the beam amplitude g(|d_x|, |d_y|, z) (staged in
 // LDS beside the delay table).
-template <int NP, int ZC, bool DIR = false>
+// FOLD: the plan folds a.ft tail bins into its last bin tile (below).
+template <int NP, int ZC, bool DIR = false, bool FOLD = false>
 __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int nblk, unsigned char* smem) {
     constexpr int zc = ZC;
     const int lane = threadIdx.x & 63;
@@ -154,18 +156,30 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
     // (position group, depth)), and the four depth blocks of a position group
     // are summed across lanes at the end.
     const bool tail = wave_active && a.mu - bin0 <= 4;
+    // Folded tail (four waves, a.ft bins past the last full bin tile, e.g. the
+    // 2 of 66 = 64 + 2): the last tile's waves share those bins' products on the
+    // same 4 x 4 x 1 form, wave w at the offsets d_x = w (mod 4), reusing the
+    // A operands of their own products; the four partial sums meet in LDS at
+    // the end.  Every wave keeps the same work per offset range, where a fifth
+    // wave for the tail shares a SIMD with another wave.
+    const bool fold = FOLD && bt == a.nbt - 1;
+    const int tb = FOLD ? a.nbt * 16 * a.nw + (lane & 3) : 0;   // this lane's folded bin
     auto run = [&](auto tailc) {
         constexpr bool TAIL = decltype(tailc)::value;
         const int mb = bin0 + (TAIL ? (lane & 3) : (lane & 15));   // this lane's bin column
         const uint32_t kbin = (mb < a.mu) ? (uint32_t)a.kb[mb] : 0u;
+        uint32_t kbt = 0u;
+        if constexpr (FOLD) kbt = (fold && tb < a.mu) ? (uint32_t)a.kb[tb] : 0u;
         auto mfma = [](float av, float bv, f4 acc) {
             if constexpr (TAIL) return __builtin_amdgcn_mfma_f32_4x4x1f32(av, bv, acc, 0, 0, 0);
             else return __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
         };
 
-        f4 out_re[NP], out_im[NP];
+        f4 out_re[NP], out_im[NP], t_re[FOLD ? NP : 1], t_im[FOLD ? NP : 1];
 #pragma unroll
         for (int s = 0; s < NP; ++s) out_re[s] = out_im[s] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < (FOLD ? NP : 1); ++s) t_re[s] = t_im[s] = f4{0.f, 0.f, 0.f, 0.f};
 
         for (int z0 = z_lo; z0 < z_hi; z0 += zc) {
             for (int dy = dy_lo; dy <= dy_hi; ++dy) {
@@ -228,11 +242,75 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
                             m3[s] = mfma(xv.im, bpz[j], m3[s]);
                         }
                     }
+                    if constexpr (FOLD && !TAIL) {
+                        if (fold && (dx & 3) == wave) {
+                            // (xr + j xi)(c - j s) for the folded bins, four real products
+#pragma unroll
+                            for (int j = 0; j < zc / 4; ++j) {
+                                float c, sn;
+                                phasor(kbt * urow[4 * j + kq], c, sn);
+                                if (DIR) {
+                                    const float gv = glds[adx * zc + 4 * j + kq];
+                                    c *= gv;
+                                    sn *= gv;
+                                }
+#pragma unroll
+                                for (int s = 0; s < NP; ++s) {
+                                    if (!act[s]) continue;
+                                    const cf32 xv = hrow[s * sw * cs + 4 * j + kq];
+                                    t_re[s] = __builtin_amdgcn_mfma_f32_4x4x1f32(xv.re, c, t_re[s], 0, 0, 0);
+                                    t_re[s] = __builtin_amdgcn_mfma_f32_4x4x1f32(xv.im, sn, t_re[s], 0, 0, 0);
+                                    t_im[s] = __builtin_amdgcn_mfma_f32_4x4x1f32(xv.im, c, t_im[s], 0, 0, 0);
+                                    t_im[s] = __builtin_amdgcn_mfma_f32_4x4x1f32(xv.re, -sn, t_im[s], 0, 0, 0);
+                                }
+                            }
+                        }
+                    }
                 }
 #pragma unroll
                 for (int s = 0; s < NP; ++s) {
                     out_re[s] += m1[s] - m3[s];
                     out_im[s] += m1[s] + m2[s];
+                }
+            }
+        }
+        if constexpr (FOLD && !TAIL) {
+            if (fold) {
+                cf32* yo = a.yraw + (int64_t)sp_all * a.npos * a.mu;
+                // the four waves' folded sums, added in wave order, then the four
+                // depth blocks of each position group as in the tail wave below
+                float* red = reinterpret_cast<float*>(smem);     // [4][NP][8][64]
+                __syncthreads();                                 // halo reads done
+                if (wave < 4) {
+#pragma unroll
+                    for (int s = 0; s < NP; ++s)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            red[((wave * NP + s) * 8 + r) * 64 + lane] = t_re[s][r];
+                            red[((wave * NP + s) * 8 + 4 + r) * 64 + lane] = t_im[s][r];
+                        }
+                }
+                __syncthreads();
+                if (wave == 0) {
+#pragma unroll
+                    for (int s = 0; s < NP; ++s)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            float vr = red[(s * 8 + r) * 64 + lane], vi = red[(s * 8 + 4 + r) * 64 + lane];
+#pragma unroll
+                            for (int w = 1; w < 4; ++w) {
+                                vr += red[((w * NP + s) * 8 + r) * 64 + lane];
+                                vi += red[((w * NP + s) * 8 + 4 + r) * 64 + lane];
+                            }
+                            vr += __shfl_xor(vr, 16, 64);
+                            vi += __shfl_xor(vi, 16, 64);
+                            vr += __shfl_xor(vr, 32, 64);
+                            vi += __shfl_xor(vi, 32, 64);
+                            const int irow = 4 * (lane >> 2) + r;
+                            const int px = px0 + s * sw + irow % sw, py = py0 + irow / sw;
+                            if (lane < 16 && tb < a.mu && px < a.nx && py < a.ny)
+                                yo[((int64_t)py * a.nx + px) * a.mu + tb] = cf32{vr, vi};
+                        }
                 }
             }
         }
@@ -280,10 +358,10 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
     else run(std::false_type{});
 }
 
-template <int NP, int ZC, bool DIR = false>
+template <int NP, int ZC, bool DIR = false, bool FOLD = false>
 __global__ __launch_bounds__(512) void fwd_gemm_f32_kernel(FwdArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    fwd_f32_body<NP, ZC, DIR>(a, blockIdx.x, gridDim.x, smem);
+    fwd_f32_body<NP, ZC, DIR, FOLD>(a, blockIdx.x, gridDim.x, smem);
 }
 
 // Grouped launch: block -> (plan index, block index inside that plan's grid).
@@ -500,7 +578,7 @@ static constexpr int kGroupNP = 2;   // grouped (batched) launches: one shape fo
 int fwd_tile_np(const Plan& P) { return P.fwd_np == 4 ? 4 : 2; }
 int adj_tile_np(const Plan& P) { return P.adj_np == 4 ? 4 : 2; }
 
-static int fwd_args(const Plan& P, const cf32* x, FwdArgs& a, size_t& lds, int np);
+static int fwd_args(const Plan& P, const cf32* x, FwdArgs& a, size_t& lds, int np, bool fold = true);
 static int adj_args(const Plan& P, cf32* out, AdjArgs& a, size_t& lds, int np);
 
 int fwd_chunk(const Plan& P) {
@@ -550,7 +628,9 @@ int adj_split(const Plan& P) {
 }
 
 // Descriptor of one plan's forward GEMM launch; returns the block count.
-static int fwd_args(const Plan& P, const cf32* x, FwdArgs& a, size_t& lds, int np) {
+// `fold`: allow the folded tail (single-plan launches; grouped launches keep
+// one kernel body for every plan).
+static int fwd_args(const Plan& P, const cf32* x, FwdArgs& a, size_t& lds, int np, bool fold) {
     a = FwdArgs{};
     a.x = x;
     a.yraw = P.d_yraw;
@@ -569,6 +649,10 @@ static int fwd_args(const Plan& P, const cf32* x, FwdArgs& a, size_t& lds, int n
     a.nty = (a.ny + tpy - 1) / tpy;
     a.nw = std::max(1, std::min(P.fwd_nw, (a.mu + 15) / 16));
     a.nbt = (a.mu + 16 * a.nw - 1) / (16 * a.nw);
+    // four waves and at most 4 bins past the last full tile: fold them into it
+    const int rem = a.mu % (16 * a.nw);
+    a.ft = (fold && a.nw == 4 && a.mu > 64 && rem >= 1 && rem <= 4) ? rem : 0;
+    if (a.ft) a.nbt = a.mu / 64;
     a.split = P.fwd_split;
     a.npos = P.npos;
     const int hc = tpx + 2 * a.wx;
@@ -580,6 +664,7 @@ static int fwd_args(const Plan& P, const cf32* x, FwdArgs& a, size_t& lds, int n
     while (zc > 4 && lds_of(zc) > kLdsMax) zc /= 2;   // powers of two: the staging needs zc | blockDim
     lds = lds_of(zc);
     if (lds > kLdsMax) fail(UFSS_ERR_UNSUPPORTED, "aperture window too wide for the GEMM path");
+    if (a.ft) lds = std::max(lds, (size_t)4 * np * 8 * 64 * sizeof(float));   // the folded sums
     a.zc = zc;
     a.zsplit = std::max(1, P.fwd_zsplit);
     a.nblk = a.ntx * a.nty * a.nbt * a.split * a.zsplit;
@@ -629,8 +714,16 @@ void launch_forward_gemm(const Plan& P, const cf32* x, hipStream_t s) {
     const int np = fwd_tile_np(P);
     fwd_args(P, x, a, lds, np);
     const dim3 grid(a.nblk), block(64 * a.nw);
-#define UFSS_FWD(NPV, ZCV) hipLaunchKernelGGL((fwd_gemm_f32_kernel<NPV, ZCV>), grid, block, lds, s, a)
-#define UFSS_FWDG(NPV, ZCV) hipLaunchKernelGGL((fwd_gemm_f32_kernel<NPV, ZCV, true>), grid, block, lds, s, a)
+#define UFSS_FWD(NPV, ZCV)                                                                                   \
+    do {                                                                                                     \
+        if (a.ft) hipLaunchKernelGGL((fwd_gemm_f32_kernel<NPV, ZCV, false, true>), grid, block, lds, s, a); \
+        else hipLaunchKernelGGL((fwd_gemm_f32_kernel<NPV, ZCV>), grid, block, lds, s, a);                   \
+    } while (0)
+#define UFSS_FWDG(NPV, ZCV)                                                                                 \
+    do {                                                                                                    \
+        if (a.ft) hipLaunchKernelGGL((fwd_gemm_f32_kernel<NPV, ZCV, true, true>), grid, block, lds, s, a); \
+        else hipLaunchKernelGGL((fwd_gemm_f32_kernel<NPV, ZCV, true>), grid, block, lds, s, a);            \
+    } while (0)
     if (a.amp) {
         if (np == 4) {
             if (a.zc == 16) UFSS_FWDG(4, 16); else if (a.zc == 8) UFSS_FWDG(4, 8); else UFSS_FWDG(4, 4);
@@ -690,7 +783,7 @@ int make_desc(GemmKind k, const Plan& P, const void* in, void* out, void* desc, 
     if (P.mix) fail(UFSS_ERR_UNSUPPORTED, "grouped launches do not take mixed plans");
     switch (k) {
         case GemmKind::FwdF32:
-            return fwd_args(P, static_cast<const cf32*>(in), *static_cast<FwdArgs*>(desc), *lds, kGroupNP);
+            return fwd_args(P, static_cast<const cf32*>(in), *static_cast<FwdArgs*>(desc), *lds, kGroupNP, false);
         case GemmKind::AdjF32:
             return adj_args(P, static_cast<cf32*>(out), *static_cast<AdjArgs*>(desc), *lds, kGroupNP);
         default: return bf16_make_desc(k, P, in, out, desc, lds);

@@ -362,6 +362,34 @@ def test_random_small_problems_against_dense_oracle(seed, dev):
     plan.close()
 
 
+@pytest.mark.parametrize("m,waves,tile,beam", [(65, 4, 2, False), (66, 4, 2, False), (68, 4, 4, False),
+                                               (66, 4, 2, True), (69, 4, 2, False), (66, 5, 2, False),
+                                               (130, 4, 4, False), (132, 4, 2, True)])
+def test_forward_folded_tail_bins(m, waves, tile, beam, dev):
+    """FP32 forward with 1-4 bins past the last full 64-bin tile: with four
+    waves those bins are folded into that tile (each wave takes the offsets
+    d_x = wave mod 4, the partial sums meet in LDS); 5 bins past it (69) take
+    a tile of their own, five waves (66) a tail wave.  Against the dense FP64
+    oracle, with and without the beam, over several depth and d_y splits."""
+    u = ufss()
+    g = W.geometry(9, 5, 40, 1024, win_x=3, win_y=2)
+    if beam:
+        g["theta"] = float(np.radians(30.0))
+    bins, _ = u.ufss_select_freqs(g, m, False, 41 + m)
+    x = W.cn((g["ny"], g["nx"], g["nz"]), 51 + m).astype(np.complex64)
+    A = O.dense_A(g, bins)
+    y_ref = (A @ x.reshape(-1).astype(np.complex128)).reshape(g["ny"], g["nx"], m)
+    plan = u.Plan(g, m, False, bins, algo=u.ALGO_GEMM)
+    for fs, zs in ((1, 1), (3, 2), (2, 3)):
+        u.ufss_plan_set_tiling(plan, fwd_split=fs, fwd_zsplit=zs, fwd_waves=waves, fwd_tile=tile, fwd_chunk=16)
+        assert plan.info()["fwd_waves"] == waves
+        yt = run_op(plan, x, (g["ny"], g["nx"], m), dev)
+        torch.cuda.synchronize()
+        ey = errs(yt.cpu().numpy(), y_ref)
+        assert max(ey) < TOL32, (m, waves, tile, beam, fs, zs, ey)
+    plan.close()
+
+
 @pytest.mark.parametrize("seed", range(16))
 def test_random_beam_problems_against_dense_oracle(seed, dev):
     """Gaussian beam (Sec. VI directivity): random small problems with a beam
