@@ -244,16 +244,21 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs& a, int b, const int 
                     }
                     if constexpr (FOLD && !TAIL) {
                         if (fold && (dx & 3) == wave) {
-                            // (xr + j xi)(c - j s) for the folded bins, four real products
+                            // (xr + j xi)(c - j s) for the folded bins, four real products;
+                            // the wave's 4 bins x zc depths are one phasor per lane (bin
+                            // l % 4, depth l / 4), handed to the lanes that take them
+                            const int dz = min(lane >> 2, zc - 1);
+                            float c0, s0;
+                            phasor(kbt * urow[dz], c0, s0);
+                            if (DIR) {
+                                const float gv = glds[adx * zc + dz];
+                                c0 *= gv;
+                                s0 *= gv;
+                            }
 #pragma unroll
                             for (int j = 0; j < zc / 4; ++j) {
-                                float c, sn;
-                                phasor(kbt * urow[4 * j + kq], c, sn);
-                                if (DIR) {
-                                    const float gv = glds[adx * zc + 4 * j + kq];
-                                    c *= gv;
-                                    sn *= gv;
-                                }
+                                const int src = 4 * (4 * j + kq) + (lane & 3);
+                                const float c = __shfl(c0, src, 64), sn = __shfl(s0, src, 64);
 #pragma unroll
                                 for (int s = 0; s < NP; ++s) {
                                     if (!act[s]) continue;
