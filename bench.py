@@ -50,15 +50,15 @@ TRAFFIC = {
     "cscan32/gemm/adjoint/as12-np2-kc16": {"bytes": 44.452e6, "sha": "c19d8c372f3712fe"},
     # transform-domain contraction (profiles/cscan32_fp32_transform.md, cscan64_fp32_transform.md):
     # the table once plus the transform rows in and out
-    "cscan32/transform/forward/fs1-zs1-nw1-np0-zc0": {"bytes": 149.649e6, "sha": "130f6e5e72ba81e0"},
-    "cscan32/transform/adjoint/as1-np0-kc0": {"bytes": 149.147e6, "sha": "130f6e5e72ba81e0"},
-    "cscan64/transform/forward/fs1-zs1-nw1-np0-zc0": {"bytes": 914.111e6, "sha": "130f6e5e72ba81e0"},
-    "cscan64/transform/adjoint/as1-np0-kc0": {"bytes": 914.115e6, "sha": "130f6e5e72ba81e0"},
+    "cscan32/transform/forward/fs1-zs1-nw1-np0-zc0": {"bytes": 149.644e6, "sha": "b7d94652b869eec0"},
+    "cscan32/transform/adjoint/as1-np0-kc0": {"bytes": 149.143e6, "sha": "b7d94652b869eec0"},
+    "cscan64/transform/forward/fs1-zs1-nw1-np0-zc0": {"bytes": 914.074e6, "sha": "b7d94652b869eec0"},
+    "cscan64/transform/adjoint/as1-np0-kc0": {"bytes": 914.088e6, "sha": "b7d94652b869eec0"},
     # the same with the BF16 table (profiles/cscan32_bf16_transform.md, cscan64_bf16_transform.md)
-    "cscan32/transform-bf16/adjoint/as1-np0-kc0": {"bytes": 79.961e6, "sha": "130f6e5e72ba81e0"},
-    "cscan32/transform-bf16/forward/fs1-zs1-nw1-np0-zc0": {"bytes": 80.372e6, "sha": "130f6e5e72ba81e0"},
-    "cscan64/transform-bf16/adjoint/as1-np0-kc0": {"bytes": 473.496e6, "sha": "130f6e5e72ba81e0"},
-    "cscan64/transform-bf16/forward/fs1-zs1-nw1-np0-zc0": {"bytes": 473.496e6, "sha": "130f6e5e72ba81e0"},
+    "cscan32/transform-bf16/adjoint/as1-np0-kc0": {"bytes": 79.976e6, "sha": "b7d94652b869eec0"},
+    "cscan32/transform-bf16/forward/fs1-zs1-nw1-np0-zc0": {"bytes": 80.399e6, "sha": "b7d94652b869eec0"},
+    "cscan64/transform-bf16/adjoint/as1-np0-kc0": {"bytes": 473.501e6, "sha": "b7d94652b869eec0"},
+    "cscan64/transform-bf16/forward/fs1-zs1-nw1-np0-zc0": {"bytes": 473.507e6, "sha": "b7d94652b869eec0"},
     # BF16 GEMMs with phasor tables (profiles/cscan32_bf16_gemm.md, cscan64_bf16_gemm.md):
     # mostly re-reads of the table tiles, one per workgroup and offset (the
     # tables, 170 MB at 32 x 32, sit in the last-level cache); the 32 x 32

@@ -265,6 +265,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
                                                       const cf32* __restrict__ in,
                                                       cf32* __restrict__ out, int ly, int lx,
                                                       int nox, int C, int R) {
+    // rows ahead: BF16 entries are half the bytes, so two more rows (as many
+    // as fit the 64 registers of eight waves per SIMD) keep more bytes in flight
+    constexpr int PF = sizeof(TT) == sizeof(cf32) ? kPF : kPF + 2;
     extern __shared__ __align__(16) unsigned char smem[];
     cf32* vs = reinterpret_cast<cf32*>(smem);                 // [4][R] input rows
     float* red = reinterpret_cast<float*>(vs + 4 * R);        // [G][4][C][2] partials
@@ -279,9 +282,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     const int rper = (R + G - 1) / G;
     const int r0 = grp * rper, r1 = min(R, r0 + rper);
     const bool active = grp < G;
-    TT cur[kPF];
+    TT cur[PF];
 #pragma unroll
-    for (int t = 0; t < kPF; ++t)
+    for (int t = 0; t < PF; ++t)
         cur[t] = (active && lane_c < C && r0 + t < r1) ? tb[(int64_t)(r0 + t) * C + lane_c] : TT{};
     for (int t = threadIdx.x; t < nq * R; t += blockDim.x) {
         const int q = t / R, r = t - q * R;
@@ -291,15 +294,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     for (int c = lane_c; c < C && active; c += W) {
         const TT* col = tb + c;
         float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int rb = r0; rb < r1; rb += kPF) {
-            TT nxt[kPF];
+        for (int rb = r0; rb < r1; rb += PF) {
+            TT nxt[PF];
 #pragma unroll
-            for (int t = 0; t < kPF; ++t) {
-                const int r = rb + kPF + t;
+            for (int t = 0; t < PF; ++t) {
+                const int r = rb + PF + t;
                 nxt[t] = r < r1 ? col[(int64_t)r * C] : TT{};
             }
 #pragma unroll
-            for (int t = 0; t < kPF; ++t) {
+            for (int t = 0; t < PF; ++t) {
                 if (rb + t >= r1) break;
                 const cf32 kv = entry(cur[t]);
                 const float ki = CONJ ? -kv.im : kv.im;
@@ -314,7 +317,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
                 }
             }
 #pragma unroll
-            for (int t = 0; t < kPF; ++t) cur[t] = nxt[t];
+            for (int t = 0; t < PF; ++t) cur[t] = nxt[t];
         }
         if (G == 1) {
             for (int q = 0; q < nq; ++q)
@@ -328,7 +331,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         // first block of this thread's next column (C > NT only)
         const int cn = c + W;
 #pragma unroll
-        for (int t = 0; t < kPF; ++t)
+        for (int t = 0; t < PF; ++t)
             cur[t] = (cn < C && r0 + t < r1) ? tb[(int64_t)(r0 + t) * C + cn] : TT{};
     }
     if (G == 1) return;
