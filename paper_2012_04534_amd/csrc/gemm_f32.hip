@@ -442,6 +442,7 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
 
     for (int k0 = 0; k0 < a.mu; k0 += kc) {
         const int kcur = min(kc, (a.mu - k0 + 3) & ~3);   // last chunk: valid bins, rounded to 4
+        const bool pair = a.mu - k0 <= 2;                 // at most 2 bins left: two offsets per product
         for (int dy = dy_lo; dy <= dy_hi; ++dy) {
             __syncthreads();
             stage_halo<8>(halo, cs, dy == dy_lo ? tpy : 1, hc, hc, tpy - 1, kc, a.r, a.ny, a.nx, a.mu,
@@ -513,7 +514,44 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
                 }
             }
             };
-            if constexpr (NP == 2) {
+            if (pair) {
+                // a last chunk of at most 2 bins: the K = 4 of one product takes
+                // those bins at two offsets, lane groups kq = 0, 1 at d_x and
+                // kq = 2, 3 at d_x + 1 (zero past dx_hi), so the chunk runs half
+                // the offset steps and no product lane carries a padding bin
+                // (every sub-tile, out-of-grid cells are staged as zeros)
+                const uint32_t k = (uint32_t)klds[kq & 1];
+                for (int dx = dx_lo; dx <= dx_hi; dx += 2) {
+                    const bool ok = dx + (kq >> 1) <= dx_hi;
+                    const int dl = ok ? dx + (kq >> 1) : dx;
+                    const int adl = dl < 0 ? -dl : dl;
+                    const cf32* hrow = halo + ((((vy0 + iy + dy) & (tpy - 1)) * hc) + ix + a.wx + dl) * cs + (kq & 1);
+                    cf32 rv[NP];
+                    float rs[NP];
+#pragma unroll
+                    for (int s = 0; s < NP; ++s) {
+                        rv[s] = ok ? hrow[s * sw * cs] : cf32{0.f, 0.f};
+                        rs[s] = rv[s].re + rv[s].im;
+                    }
+#pragma unroll
+                    for (int q = 0; q < NZ; ++q) {
+                        float c, sn;
+                        phasor(k * ulds[adl * zspan + wave * NZ * 16 + q * 16 + i], c, sn);
+                        if (DIR) {
+                            const float gv = glds[adl * zspan + wave * NZ * 16 + q * 16 + i];
+                            c *= gv;
+                            sn *= gv;
+                        }
+                        const float bm = sn - c, bp = c + sn;
+#pragma unroll
+                        for (int s = 0; s < NP; ++s) {
+                            m1[s][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(rs[s], c, m1[s][q], 0, 0, 0);
+                            m2[s][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(rv[s].re, bm, m2[s][q], 0, 0, 0);
+                            m3[s][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(rv[s].im, bp, m3[s][q], 0, 0, 0);
+                        }
+                    }
+                }
+            } else if constexpr (NP == 2) {
                 // column ranges of the two sub-tiles' shifted voxels inside the grid
                 const int a0 = -(vx0 + sw - 1), b1 = a.nx - 1 - vx0 - sw;
                 dxloop(std::integral_constant<int, 2>{}, dx_lo, min(min(a0 - 1, b1), dx_hi));
