@@ -196,6 +196,7 @@ struct Batch {
     std::vector<int> gemm_idx;                         // scans on the grouped GEMM path
     void* d_desc = nullptr;                            // ScanDesc[n]
     std::map<int, std::pair<void*, size_t>> gdesc;     // GemmKind -> (device descs, lds)
+    std::map<int, int> gthreads;                       // GemmKind -> threads per workgroup
     std::map<int, int> gcount;                         // GemmKind -> total blocks
     std::map<int, int2*> gblk;                         // GemmKind -> block table
     int2 *blk_post = nullptr, *blk_pre = nullptr, *blk_vox = nullptr, *blk_upd = nullptr,
@@ -398,22 +399,26 @@ BatchRun* batch_create(int n, Plan* const* plans, const cf32* const* ys, cf32* c
             std::vector<unsigned char> bytes;
             std::vector<int2> blk;
             size_t lds_max = 0;
+            int threads_max = 64;
             int idx = 0;
             for (int i = 0; i < n; ++i) {
                 Plan& P = *plans[i];
                 if ((P.dtype == UFSS_BF16) != want_bf16) continue;
                 std::vector<unsigned char> one(dsz);
                 size_t lds = 0;
+                int threads = 256;
                 int nb = make_desc(K, P, fwd ? (const void*)P.d_gamma : nullptr,
                                    fwd ? nullptr : (P.adj_split > 1 ? (void*)P.d_gpart : (void*)P.d_g),
-                                   one.data(), &lds);
+                                   one.data(), &lds, &threads);
                 bytes.insert(bytes.end(), one.begin(), one.end());
                 lds_max = std::max(lds_max, lds);
+                threads_max = std::max(threads_max, threads);
                 for (int b = 0; b < nb; ++b) blk.push_back(int2{idx, b});
                 ++idx;
             }
             if (idx == 0) continue;
             B.gdesc[kind] = {upload_vec(B, bytes), lds_max};
+            B.gthreads[kind] = threads_max;
             B.gblk[kind] = upload_vec(B, blk);
             B.gcount[kind] = (int)blk.size();
         }
@@ -436,13 +441,13 @@ BatchRun* batch_create(int n, Plan* const* plans, const cf32* const* ys, cf32* c
                 for (int kind : {0, 2})
                     if (B.gcount.count(kind))
                         launch_grouped((GemmKind)kind, B.gdesc[kind].first, B.gblk[kind], B.gcount[kind],
-                                       B.gdesc[kind].second, cs);
+                                       B.gdesc[kind].second, B.gthreads[kind], cs);
                 hipLaunchKernelGGL(g_post, dim3(B.n_post), dim3(kT), 0, cs, D, B.blk_post);
                 hipLaunchKernelGGL(g_pre, dim3(B.n_pre), dim3(128), 0, cs, D, B.blk_pre);
                 for (int kind : {1, 3})
                     if (B.gcount.count(kind))
                         launch_grouped((GemmKind)kind, B.gdesc[kind].first, B.gblk[kind], B.gcount[kind],
-                                       B.gdesc[kind].second, cs);
+                                       B.gdesc[kind].second, B.gthreads[kind], cs);
                 hipLaunchKernelGGL(g_update, dim3(B.n_upd), dim3(kT), 0, cs, D, B.blk_upd, beta);
                 hipLaunchKernelGGL(g_finish, dim3(n), dim3(kT), 0, cs, D, k);
             }

@@ -821,24 +821,33 @@ size_t desc_size(GemmKind k) {
     }
 }
 
-int make_desc(GemmKind k, const Plan& P, const void* in, void* out, void* desc, size_t* lds) {
+int make_desc(GemmKind k, const Plan& P, const void* in, void* out, void* desc, size_t* lds, int* threads) {
     if (P.d_amp) fail(UFSS_ERR_UNSUPPORTED, "grouped launches do not take a Gaussian beam");
     if (P.mix) fail(UFSS_ERR_UNSUPPORTED, "grouped launches do not take mixed plans");
     switch (k) {
-        case GemmKind::FwdF32:
-            return fwd_args(P, static_cast<const cf32*>(in), *static_cast<FwdArgs*>(desc), *lds, kGroupNP, false);
+        case GemmKind::FwdF32: {
+            FwdArgs& a = *static_cast<FwdArgs*>(desc);
+            const int nb = fwd_args(P, static_cast<const cf32*>(in), a, *lds, kGroupNP, false);
+            *threads = 64 * a.nw;                   // the waves with a bin sub-tile
+            return nb;
+        }
         case GemmKind::AdjF32:
+            *threads = 256;
             return adj_args(P, static_cast<cf32*>(out), *static_cast<AdjArgs*>(desc), *lds, kGroupNP);
-        default: return bf16_make_desc(k, P, in, out, desc, lds);
+        default:
+            *threads = 256;
+            return bf16_make_desc(k, P, in, out, desc, lds);
     }
 }
 
-void launch_grouped(GemmKind k, const void* descs, const int2* blk, int nblocks, size_t lds,
+void launch_grouped(GemmKind k, const void* descs, const int2* blk, int nblocks, size_t lds, int threads,
                     hipStream_t s) {
     if (nblocks <= 0) return;
     switch (k) {
         case GemmKind::FwdF32:
-            hipLaunchKernelGGL(fwd_gemm_f32_kernel_grouped<kGroupNP>, dim3(nblocks), dim3(512), lds, s,
+            if (threads < 64 || threads > 512 || threads % 64)
+                fail(UFSS_ERR_INVALID_ARG, "grouped forward: workgroup size must be 64 to 512 in steps of 64");
+            hipLaunchKernelGGL(fwd_gemm_f32_kernel_grouped<kGroupNP>, dim3(nblocks), dim3(threads), lds, s,
                                static_cast<const FwdArgs*>(descs), blk);
             break;
         case GemmKind::AdjF32:

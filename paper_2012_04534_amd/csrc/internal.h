@@ -185,10 +185,11 @@ int adj_chunk(const Plan& P);
 // blk[b] = {plan index, block index inside that plan's own grid}.
 enum class GemmKind { FwdF32 = 0, AdjF32 = 1, FwdBF16 = 2, AdjBF16 = 3 };
 size_t desc_size(GemmKind k);
-// Fills `desc` for plan P (in: forward input; out: adjoint output) and the LDS
-// bytes it needs; returns the plan's block count.
-int make_desc(GemmKind k, const Plan& P, const void* in, void* out, void* desc, size_t* lds);
-void launch_grouped(GemmKind k, const void* descs, const int2* blk, int nblocks, size_t lds,
+// Fills `desc` for plan P (in: forward input; out: adjoint output), the LDS
+// bytes and the threads per workgroup it needs; returns the plan's block count.
+int make_desc(GemmKind k, const Plan& P, const void* in, void* out, void* desc, size_t* lds, int* threads);
+// One grid over many plans' blocks; `threads`: the most any of them needs.
+void launch_grouped(GemmKind k, const void* descs, const int2* blk, int nblocks, size_t lds, int threads,
                     hipStream_t s);
 size_t bf16_desc_size(GemmKind k);
 int bf16_make_desc(GemmKind k, const Plan& P, const void* in, void* out, void* desc, size_t* lds);
