@@ -46,18 +46,18 @@ PEAK_PHASOR_TERMS = 256 * 4 * 16 * 2.4e9 / PHASOR_SLOTS_PER_TERM
 # source it was measured on; a changed source or another tiling reports null.
 TRAFFIC = {
     # 32 x 32 C-scan, FP32 union-GEMM, shipped tiling (profiles/cscan32_fp32_gemm.md)
-    "cscan32/gemm/forward/fs12-zs8-nw4-np2-zc16": {"bytes": 55.405e6, "sha": "99c3c06916365a6f"},
-    "cscan32/gemm/adjoint/as12-np2-kc16": {"bytes": 59.360e6, "sha": "99c3c06916365a6f"},
+    "cscan32/gemm/forward/fs12-zs8-nw4-np2-zc16": {"bytes": 55.415e6, "sha": "2077fd0bb15202fe"},
+    "cscan32/gemm/adjoint/as12-np2-kc16-nw8": {"bytes": 82.292e6, "sha": "2077fd0bb15202fe"},
     # transform-domain contraction (profiles/cscan32_fp32_transform.md, cscan64_fp32_transform.md):
     # the table once plus the transform rows in and out
     "cscan32/transform/forward/fs1-zs1-nw1-np0-zc0": {"bytes": 149.644e6, "sha": "b7d94652b869eec0"},
-    "cscan32/transform/adjoint/as1-np0-kc0": {"bytes": 149.143e6, "sha": "b7d94652b869eec0"},
+    "cscan32/transform/adjoint/as1-np0-kc0-nw0": {"bytes": 149.143e6, "sha": "b7d94652b869eec0"},
     "cscan64/transform/forward/fs1-zs1-nw1-np0-zc0": {"bytes": 914.074e6, "sha": "b7d94652b869eec0"},
-    "cscan64/transform/adjoint/as1-np0-kc0": {"bytes": 914.088e6, "sha": "b7d94652b869eec0"},
+    "cscan64/transform/adjoint/as1-np0-kc0-nw0": {"bytes": 914.088e6, "sha": "b7d94652b869eec0"},
     # the same with the BF16 table (profiles/cscan32_bf16_transform.md, cscan64_bf16_transform.md)
-    "cscan32/transform-bf16/adjoint/as1-np0-kc0": {"bytes": 79.976e6, "sha": "b7d94652b869eec0"},
+    "cscan32/transform-bf16/adjoint/as1-np0-kc0-nw0": {"bytes": 79.976e6, "sha": "b7d94652b869eec0"},
     "cscan32/transform-bf16/forward/fs1-zs1-nw1-np0-zc0": {"bytes": 80.399e6, "sha": "b7d94652b869eec0"},
-    "cscan64/transform-bf16/adjoint/as1-np0-kc0": {"bytes": 473.501e6, "sha": "b7d94652b869eec0"},
+    "cscan64/transform-bf16/adjoint/as1-np0-kc0-nw0": {"bytes": 473.501e6, "sha": "b7d94652b869eec0"},
     "cscan64/transform-bf16/forward/fs1-zs1-nw1-np0-zc0": {"bytes": 473.507e6, "sha": "b7d94652b869eec0"},
     # BF16 GEMMs with phasor tables (profiles/cscan32_bf16_gemm.md, cscan64_bf16_gemm.md):
     # mostly re-reads of the table tiles, one per workgroup and offset (the
@@ -86,7 +86,7 @@ def tiling_key(info, direction):
         return ("as%d-wr%d-nz%d" % (info["adj_split"], info["adj_rows"], info["adj_tile"]) if direction == "adjoint"
                 else "fs%d-zs%d-wr%d" % (info["fwd_split"], info["fwd_zsplit"], info["fwd_rows"]))
     if direction == "adjoint":
-        return "as%d-np%d-kc%d" % (info["adj_split"], info["adj_tile"], info["adj_chunk"])
+        return "as%d-np%d-kc%d-nw%d" % (info["adj_split"], info["adj_tile"], info["adj_chunk"], info["adj_waves"])
     return "fs%d-zs%d-nw%d-np%d-zc%d" % (info["fwd_split"], info["fwd_zsplit"], info["fwd_waves"],
                                          info["fwd_tile"], info["fwd_chunk"])
 

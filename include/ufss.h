@@ -108,6 +108,8 @@ typedef struct ufss_plan_info {
     int32_t fwd_chunk, adj_chunk;        /* FP32 GEMMs: staged depth / bin
                                             chunk (0 elsewhere)                */
     int32_t phasor_tables;               /* 1: BF16 phasor tables in use       */
+    int32_t adj_waves;                   /* FP32 GEMM adjoint: waves per
+                                            workgroup (0 elsewhere)            */
 } ufss_plan_info;
 
 /* Per-iteration FISTA statistics, FP64, written to HOST arrays of length
@@ -488,6 +490,11 @@ int ufss_autotune(ufss_plan_t plan, const char* cache_path, int32_t flags,
  *   fwd_chunk, adj_chunk  FP32: depths (forward) or bins (adjoint) staged in
  *               LDS per step, 16 or 8 (8 halves the halo and admits more
  *               workgroups per CU; shrunk further if the window needs it)
+ *   adj_waves   FP32 adjoint with 2 sub-tiles per wave: waves (16 depths
+ *               each) per workgroup, 4 or 8 (8: one staged halo serves 128
+ *               depths, so more waves fit a CU's LDS; the bin chunk shrinks
+ *               if the twice longer delay rows need it); with 4 sub-tiles
+ *               per wave the adjoint runs 4 waves whatever this says
  * Any valid setting computes the same operator; parts that receive no rows
  * contribute zeros.  BF16 plans ignore the FP32-only fields; FP32 plans
  * ignore the rows.  Reallocates the plan's
@@ -500,6 +507,7 @@ typedef struct ufss_tiling {
     int32_t fwd_tile, adj_tile;
     int32_t fwd_rows, adj_rows;
     int32_t fwd_chunk, adj_chunk;
+    int32_t adj_waves;
 } ufss_tiling;
 int ufss_plan_set_tiling(ufss_plan_t plan, const ufss_tiling* tiling);
 

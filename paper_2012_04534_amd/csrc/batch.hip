@@ -607,6 +607,7 @@ int autotune(Plan& P, const char* cache_path, int flags, hipStream_t s, int32_t*
         P.fwd_zc = (int)cache[key][10];
         P.adj_kc = (int)cache[key][11];
         if (cache[key].size() >= 13) P.bf_adj_nz = (int)cache[key][12];
+        if (cache[key].size() >= 14) P.adj_nw = (int)cache[key][13];
         plan_set_splits(P, (int)cache[key][0], (int)cache[key][1], (int)cache[key][5]);
     } else {
         const int tpy = P.g.ny == 1 ? 1 : 4;
@@ -663,21 +664,29 @@ int autotune(Plan& P, const char* cache_path, int flags, hipStream_t s, int32_t*
         P.fwd_zc = bzc;
         // BF16 adjoint: 4 or 2 depth sub-tiles per wave (2: twice the workgroups)
         const std::vector<int> nzc = P.dtype == UFSS_BF16 ? std::vector<int>{4, 2} : std::vector<int>{4};
-        int bnz = P.bf_adj_nz;
+        // FP32 adjoint with 2 sub-tiles per wave: 4 or 8 waves per workgroup
+        const std::vector<int> awc =
+            (P.dtype == UFSS_F32 && !quick) ? std::vector<int>{4, 8} : std::vector<int>{P.adj_nw};
+        int bnz = P.bf_adj_nz, baw = P.adj_nw;
         for (int wr : rows)
             for (int np : npc)
                 for (int nzs : nzc)
-                    for (int c : cand) {
-                        P.adj_np = np;
-                        P.bf_adj_rows = wr;
-                        P.bf_adj_nz = nzs;
-                        plan_set_splits(P, bf, c, bz);
-                        double t = time_ms([&]() { op_adjoint(P, P.d_r, P.d_g, s); }, 3, s);
-                        if (t < best_a) { best_a = t; ba = c; bnpa = np; bar = wr; bnz = nzs; }
+                    for (int aw : awc) {
+                        if (aw == 8 && np != 2) continue;
+                        for (int c : cand) {
+                            P.adj_np = np;
+                            P.bf_adj_rows = wr;
+                            P.bf_adj_nz = nzs;
+                            P.adj_nw = aw;
+                            plan_set_splits(P, bf, c, bz);
+                            double t = time_ms([&]() { op_adjoint(P, P.d_r, P.d_g, s); }, 3, s);
+                            if (t < best_a) { best_a = t; ba = c; bnpa = np; bar = wr; bnz = nzs; baw = aw; }
+                        }
                     }
         P.adj_np = bnpa;
         P.bf_adj_rows = bar;
         P.bf_adj_nz = bnz;
+        P.adj_nw = baw;
         // then the smaller bin chunk at that shape (FP32)
         int bkc = 16;
         if (P.dtype == UFSS_F32 && !quick) {
@@ -694,7 +703,7 @@ int autotune(Plan& P, const char* cache_path, int flags, hipStream_t s, int32_t*
             cache = read_cache(cache_path);
             cache[key] = {(double)bf, (double)ba, best_f, best_a, (double)bnw, (double)bz, (double)bnp,
                           (double)bnpa, (double)bfr, (double)bar, (double)bzc, (double)bkc,
-                          (double)P.bf_adj_nz};
+                          (double)P.bf_adj_nz, (double)P.adj_nw};
             write_cache(cache_path, cache);
         }
     }

@@ -692,7 +692,8 @@ int ufss_plan_set_tiling(ufss_plan_t plan, const ufss_tiling* t) {
     auto one_of = [](int v, int a, int b) { return v == 0 || v == a || v == b; };
     if (!in(t->fwd_split, 64) || !in(t->adj_split, 64) || !in(t->fwd_waves, 8) || !in(t->fwd_zsplit, 64) ||
         !one_of(t->fwd_tile, 2, 4) || !one_of(t->adj_tile, 2, 4) || !in(t->fwd_rows, 2) ||
-        !in(t->adj_rows, 2) || !one_of(t->fwd_chunk, 8, 16) || !one_of(t->adj_chunk, 8, 16))
+        !in(t->adj_rows, 2) || !one_of(t->fwd_chunk, 8, 16) || !one_of(t->adj_chunk, 8, 16) ||
+        !one_of(t->adj_waves, 4, 8))
         ufss::fail(UFSS_ERR_INVALID_ARG, "tiling value out of range");
     if (P->dtype == UFSS_F32) {
         if (t->fwd_waves > 0) P->fwd_nw = t->fwd_waves;
@@ -700,6 +701,7 @@ int ufss_plan_set_tiling(ufss_plan_t plan, const ufss_tiling* t) {
         if (t->adj_tile > 0) P->adj_np = t->adj_tile;
         if (t->fwd_chunk > 0) P->fwd_zc = t->fwd_chunk;
         if (t->adj_chunk > 0) P->adj_kc = t->adj_chunk;
+        if (t->adj_waves > 0) P->adj_nw = t->adj_waves;
     } else {
         if (t->adj_tile > 0) P->bf_adj_nz = t->adj_tile;
     }

@@ -399,7 +399,10 @@ struct AdjArgs {
 
 // KC: the bin chunk a.kc as a compile-time constant (16, 8 or 4).
 // DIR: scale each phasor by the beam amplitude (staged in LDS after the bins).
-template <int NP, int NZ, int KC, bool DIR = false>
+// NW: waves per workgroup, each on its own 16 x NZ depths; the staged halo
+// (positions x bins) is the same for every depth, so 8 waves share one halo
+// over 128 depths where 4 waves cover 64.
+template <int NP, int NZ, int KC, bool DIR = false, int NW = 4>
 __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int nblk, unsigned char* smem) {
     constexpr int kc = KC;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -407,7 +410,7 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
     const int tpx = sw * NP, tpy = sh;
     const int hc = tpx + 2 * a.wx;
     const int cs = kc + 1;
-    const int zspan = 64 * NZ;                       // depths per workgroup
+    const int zspan = 16 * NW * NZ;                  // depths per workgroup
     cf32* halo = reinterpret_cast<cf32*>(smem);
     uint32_t* ulds = reinterpret_cast<uint32_t*>(halo + (size_t)tpy * hc * cs);
     int* klds = reinterpret_cast<int*>(ulds + (size_t)(a.wx + 1) * zspan);
@@ -448,14 +451,14 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
             stage_halo<8>(halo, cs, dy == dy_lo ? tpy : 1, hc, hc, tpy - 1, kc, a.r, a.ny, a.nx, a.mu,
                           dy == dy_lo ? vy0 + dy : vy0 + dy + tpy - 1, vx0 - a.wx, k0, a.mu);
             const int ady = dy < 0 ? -dy : dy;
-            for (int t = threadIdx.x; t < (a.wx + 1) * zspan; t += 256) {
+            for (int t = threadIdx.x; t < (a.wx + 1) * zspan; t += 64 * NW) {
                 int adx = t / zspan, zz = t - adx * zspan;
                 int z = zw0 + zz;
                 const int64_t o = ((int64_t)ady * (a.wx + 1) + adx) * a.nz + z;
                 ulds[t] = z < a.nz ? a.u[o] : 0u;
                 if (DIR) glds[t] = z < a.nz ? a.amp[o] : 0.f;
             }
-            for (int t = threadIdx.x; t < kc; t += 256)
+            for (int t = threadIdx.x; t < kc; t += 64 * NW)
                 klds[t] = (k0 + t < a.mu) ? a.kb[k0 + t] : 0;
             __syncthreads();
             if (!wave_active) continue;
@@ -470,9 +473,12 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
             // the offsets of [d0, d1] with the sub-tiles of MASK active: with two
             // sub-tiles the range splits into (second only, both, first only),
             // and a sub-tile whose shifted columns all leave the grid runs no
-            // MFMAs (compile-time masks keep the products branch-free)
-            auto dxloop = [&](auto maskc, const int d0, const int d1) {
+            // MFMAs (compile-time masks keep the products branch-free); FULL: a
+            // whole chunk of kc bins, so the offset step is one basic block whose
+            // LDS reads and products the compiler can interleave
+            auto dxloop = [&](auto maskc, auto fullc, const int d0, const int d1) {
                 constexpr int MASK = decltype(maskc)::value;
+                constexpr bool FULL = decltype(fullc)::value;
             for (int dx = d0; dx <= d1; ++dx) {
                 const int adx = dx < 0 ? -dx : dx;
                 uint32_t uz[NZ];
@@ -485,7 +491,7 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
                 const cf32* hrow = halo + ((((vy0 + iy + dy) & (tpy - 1)) * hc) + ix + a.wx + dx) * cs;
 #pragma unroll
                 for (int kk = 0; kk < kc; kk += 4) {
-                    if (kk >= kcur) break;
+                    if (!FULL && kk >= kcur) break;
                     const uint32_t k = (uint32_t)klds[kk + kq];
                     cf32 rv[NP];
                     float rs[NP];
@@ -554,11 +560,15 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
             } else if constexpr (NP == 2) {
                 // column ranges of the two sub-tiles' shifted voxels inside the grid
                 const int a0 = -(vx0 + sw - 1), b1 = a.nx - 1 - vx0 - sw;
-                dxloop(std::integral_constant<int, 2>{}, dx_lo, min(min(a0 - 1, b1), dx_hi));
-                dxloop(std::integral_constant<int, 3>{}, max(dx_lo, a0), min(b1, dx_hi));
-                dxloop(std::integral_constant<int, 1>{}, max(max(a0, b1 + 1), dx_lo), dx_hi);
+                auto segs = [&](auto fullc) {
+                    dxloop(std::integral_constant<int, 2>{}, fullc, dx_lo, min(min(a0 - 1, b1), dx_hi));
+                    dxloop(std::integral_constant<int, 3>{}, fullc, max(dx_lo, a0), min(b1, dx_hi));
+                    dxloop(std::integral_constant<int, 1>{}, fullc, max(max(a0, b1 + 1), dx_lo), dx_hi);
+                };
+                if (kcur == kc) segs(std::true_type{});   // every chunk but a short last one
+                else segs(std::false_type{});
             } else {
-                dxloop(std::integral_constant<int, (1 << NP) - 1>{}, dx_lo, dx_hi);
+                dxloop(std::integral_constant<int, (1 << NP) - 1>{}, std::false_type{}, dx_lo, dx_hi);
             }
 #pragma unroll
             for (int s = 0; s < NP; ++s)
@@ -593,12 +603,14 @@ __global__ __launch_bounds__(256) void adj_gemm_f32_kernel(AdjArgs a) {
 
 // Two sub-tiles per wave: registers capped for 6 waves per SIMD, which pays
 // when a small LDS chunk admits that many workgroups per CU (measured on the
-// 32 x 32 and 64 x 64 C-scans).
-template <int NZ, int KC, bool DIR = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8)))
+// 32 x 32 and 64 x 64 C-scans).  NW = 8: one halo for 128 depths, so the
+// LDS of 8 waves is the halo plus twice the delay rows instead of twice both
+// (on the 32 x 32 C-scan 3 workgroups per CU: 6 waves per SIMD, not 3).
+template <int NZ, int KC, bool DIR = false, int NW = 4>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(6, 8)))
 void adj_gemm_f32_kernel_np2(AdjArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    adj_f32_body<2, NZ, KC, DIR>(a, blockIdx.x, gridDim.x, smem);
+    adj_f32_body<2, NZ, KC, DIR, NW>(a, blockIdx.x, gridDim.x, smem);
 }
 
 // Grouped launch: block -> (plan index, block index inside that plan's grid).
@@ -620,9 +632,10 @@ static constexpr int kGroupNP = 2;   // grouped (batched) launches: one shape fo
 
 int fwd_tile_np(const Plan& P) { return P.fwd_np == 4 ? 4 : 2; }
 int adj_tile_np(const Plan& P) { return P.adj_np == 4 ? 4 : 2; }
+int adj_waves(const Plan& P) { return adj_tile_np(P) == 2 && P.adj_nw == 8 ? 8 : 4; }
 
 static int fwd_args(const Plan& P, const cf32* x, FwdArgs& a, size_t& lds, int np, bool fold = true);
-static int adj_args(const Plan& P, cf32* out, AdjArgs& a, size_t& lds, int np);
+static int adj_args(const Plan& P, cf32* out, AdjArgs& a, size_t& lds, int np, int nw = 4);
 
 int fwd_chunk(const Plan& P) {
     FwdArgs a;
@@ -634,7 +647,7 @@ int fwd_chunk(const Plan& P) {
 int adj_chunk(const Plan& P) {
     AdjArgs a;
     size_t lds;
-    adj_args(P, nullptr, a, lds, adj_tile_np(P));
+    adj_args(P, nullptr, a, lds, adj_tile_np(P), adj_waves(P));
     return a.kc;
 }
 static constexpr int kAdjNZ = 1;
@@ -714,7 +727,8 @@ static int fwd_args(const Plan& P, const cf32* x, FwdArgs& a, size_t& lds, int n
     return a.nblk;
 }
 
-static int adj_args(const Plan& P, cf32* out, AdjArgs& a, size_t& lds, int np) {
+// nw: waves per workgroup (4, or 8 with two sub-tiles per wave), 16 depths each.
+static int adj_args(const Plan& P, cf32* out, AdjArgs& a, size_t& lds, int np, int nw) {
     a = AdjArgs{};
     a.r = static_cast<const cf32*>(P.d_rop);
     a.out = out;
@@ -731,7 +745,7 @@ static int adj_args(const Plan& P, cf32* out, AdjArgs& a, size_t& lds, int np) {
     const int tpx = a.sw * np, tpy = 16 / a.sw;
     a.ntx = (a.nx + tpx - 1) / tpx;
     a.nty = (a.ny + tpy - 1) / tpy;
-    const int zspan = 64 * kAdjNZ;
+    const int zspan = 16 * nw * kAdjNZ;
     a.nzt = (a.nz + zspan - 1) / zspan;
     const int hc = tpx + 2 * a.wx;
     int kc = P.adj_kc == 8 ? 8 : 16;
@@ -787,12 +801,21 @@ void launch_adjoint_gemm(const Plan& P, cf32* out, hipStream_t s, bool sum) {
     AdjArgs a;
     size_t lds;
     const int np = adj_tile_np(P);
-    adj_args(P, out, a, lds, np);
-    const dim3 grid(a.nblk), block(256);
+    const int nw = adj_waves(P);
+    adj_args(P, out, a, lds, np, nw);
+    const dim3 grid(a.nblk), block(64 * nw);
 #define UFSS_ADJ(NPV, KCV) hipLaunchKernelGGL((adj_gemm_f32_kernel<NPV, kAdjNZ, KCV>), grid, block, lds, s, a)
-#define UFSS_ADJ2(KCV) hipLaunchKernelGGL((adj_gemm_f32_kernel_np2<kAdjNZ, KCV>), grid, block, lds, s, a)
+#define UFSS_ADJ2(KCV)                                                                                       \
+    do {                                                                                                     \
+        if (nw == 8) hipLaunchKernelGGL((adj_gemm_f32_kernel_np2<kAdjNZ, KCV, false, 8>), grid, block, lds, s, a); \
+        else hipLaunchKernelGGL((adj_gemm_f32_kernel_np2<kAdjNZ, KCV>), grid, block, lds, s, a);              \
+    } while (0)
 #define UFSS_ADJG(NPV, KCV) hipLaunchKernelGGL((adj_gemm_f32_kernel<NPV, kAdjNZ, KCV, true>), grid, block, lds, s, a)
-#define UFSS_ADJ2G(KCV) hipLaunchKernelGGL((adj_gemm_f32_kernel_np2<kAdjNZ, KCV, true>), grid, block, lds, s, a)
+#define UFSS_ADJ2G(KCV)                                                                                      \
+    do {                                                                                                     \
+        if (nw == 8) hipLaunchKernelGGL((adj_gemm_f32_kernel_np2<kAdjNZ, KCV, true, 8>), grid, block, lds, s, a); \
+        else hipLaunchKernelGGL((adj_gemm_f32_kernel_np2<kAdjNZ, KCV, true>), grid, block, lds, s, a);        \
+    } while (0)
     if (a.amp) {
         if (np == 4) {
             if (a.kc == 16) UFSS_ADJG(4, 16); else if (a.kc == 8) UFSS_ADJG(4, 8); else UFSS_ADJG(4, 4);

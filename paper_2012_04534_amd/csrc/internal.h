@@ -99,6 +99,7 @@ struct Plan {
     int bf_fwd_rows = 1, bf_adj_rows = 1;   // BF16 GEMMs: rows of waves in a tile (1 or 2)
     int bf_adj_nz = 4;             // BF16 adjoint: 16-depth sub-tiles per wave (2 or 4)
     int fwd_zc = 16, adj_kc = 16;  // FP32 GEMMs: preferred staged depth / bin chunk (16 or 8)
+    int adj_nw = 4;                // FP32 adjoint with 2 sub-tiles: waves per workgroup (4 or 8)
     int adj_split = 1;             // split of the adjoint GEMM's d_y range
     cf32* d_gpart = nullptr;       // adjoint partials [adj_split][nvox] (adj_split > 1)
     std::vector<int> bins_h;       // [m] or [npos*m]
@@ -177,6 +178,8 @@ void plan_set_splits(Plan& P, int fs, int as, int zs);
 // Lateral tile shape of the FP32 GEMMs (sub-tiles per wave, 2 or 4).
 int fwd_tile_np(const Plan& P);
 int adj_tile_np(const Plan& P);
+// Waves per FP32 adjoint workgroup the GEMM actually uses (8 only with 2 sub-tiles).
+int adj_waves(const Plan& P);
 // The staged chunk the FP32 GEMMs actually use (the preference, halved until LDS fits).
 int fwd_chunk(const Plan& P);
 int adj_chunk(const Plan& P);

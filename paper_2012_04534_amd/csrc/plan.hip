@@ -595,6 +595,7 @@ void plan_info(const Plan* P, ufss_plan_info* info) {
     info->adj_rows = bf_gemm ? P->bf_adj_rows : 0;
     info->fwd_chunk = f32_gemm ? fwd_chunk(*P) : 0;
     info->adj_chunk = f32_gemm ? adj_chunk(*P) : 0;
+    info->adj_waves = f32_gemm ? adj_waves(*P) : 0;
 }
 
 }  // namespace ufss

@@ -72,7 +72,7 @@ class PlanInfo(ctypes.Structure):
         ("fwd_tile", ctypes.c_int32), ("adj_tile", ctypes.c_int32),
         ("fwd_rows", ctypes.c_int32), ("adj_rows", ctypes.c_int32),
         ("fwd_chunk", ctypes.c_int32), ("adj_chunk", ctypes.c_int32),
-        ("phasor_tables", ctypes.c_int32),
+        ("phasor_tables", ctypes.c_int32), ("adj_waves", ctypes.c_int32),
     ]
 
 
@@ -80,7 +80,7 @@ class Tiling(ctypes.Structure):
     """GEMM tiling (ufss_tiling); 0 keeps the plan's current value."""
     _fields_ = [(f, ctypes.c_int32) for f in (
         "fwd_split", "adj_split", "fwd_waves", "fwd_zsplit", "fwd_tile", "adj_tile",
-        "fwd_rows", "adj_rows", "fwd_chunk", "adj_chunk")]
+        "fwd_rows", "adj_rows", "fwd_chunk", "adj_chunk", "adj_waves")]
 
 
 class FistaStats(ctypes.Structure):

@@ -161,8 +161,9 @@ def shipped_tiling(plan, g, dtype):
     fs, as_, _, _, nw, zs, npf, npa, rf, ra, zc, kc = vals[:12]
     if dtype == "bf16":          # BF16: adj_tile carries the adjoint's depth sub-tiles
         npa = vals[12] if len(vals) > 12 else 4
+    aw = vals[13] if len(vals) > 13 else 4
     return dict(fwd_split=fs, adj_split=as_, fwd_waves=nw, fwd_zsplit=zs, fwd_tile=npf, adj_tile=npa,
-                fwd_rows=rf, adj_rows=ra, fwd_chunk=zc, adj_chunk=kc)
+                fwd_rows=rf, adj_rows=ra, fwd_chunk=zc, adj_chunk=kc, adj_waves=aw)
 
 
 @pytest.mark.parametrize("name,dtype", WORKLOADS)
@@ -240,14 +241,16 @@ def test_manual_tiling_same_operator(dtype, dev):
     tol = TOL32 if dtype == "f32" else 1e-2
     plan = u.Plan(g, 20, True, bins, dtype=u.F32 if dtype == "f32" else u.BF16)
     # (fwd_split, adj_split, fwd_waves, fwd_zsplit, fwd_tile, adj_tile, fwd_rows,
-    #  adj_rows, fwd_chunk, adj_chunk)
-    tilings = [(1, 1, 1, 1, 2, 2, 0, 0, 16, 16), (3, 2, 2, 3, 4, 4, 0, 0, 8, 8),
-               (9, 9, 8, 10, 4, 2, 0, 0, 16, 8), (64, 64, 3, 64, 2, 4, 0, 0, 8, 16)]
+    #  adj_rows, fwd_chunk, adj_chunk, adj_waves)
+    tilings = [(1, 1, 1, 1, 2, 2, 0, 0, 16, 16, 8), (3, 2, 2, 3, 4, 4, 0, 0, 8, 8, 8),
+               (9, 9, 8, 10, 4, 2, 0, 0, 16, 8, 4), (64, 64, 3, 64, 2, 4, 0, 0, 8, 16, 4),
+               (2, 5, 4, 1, 2, 2, 0, 0, 16, 8, 8)]
     if dtype == "bf16":
         rows = [(1, 1), (2, 2), (1, 2), (2, 1)]
         zsplits = [1, 2, 3, 64]          # depth parts (64: most of them empty)
         nzs = [4, 2, 2, 4]               # adjoint depth sub-tiles per wave
-        tilings = [(t[0], t[1], 0, zsplits[n], 0, nzs[n]) + rows[n] + (0, 0) for n, t in enumerate(tilings)]
+        tilings = [(t[0], t[1], 0, zsplits[n], 0, nzs[n]) + rows[n] + (0, 0, 0)
+                   for n, t in enumerate(tilings[:4])]
     xt = torch.from_numpy(x).to(dev)
     yt = torch.from_numpy(y).to(dev)
     for t in tilings:
@@ -257,6 +260,8 @@ def test_manual_tiling_same_operator(dtype, dev):
         if dtype == "f32":
             assert (info["fwd_tile"], info["adj_tile"], info["fwd_zsplit"]) == (t[4], t[5], t[3])
             assert (info["fwd_chunk"], info["adj_chunk"]) == (t[8], t[9])
+            # 8 waves per adjoint workgroup with 2 sub-tiles per wave only
+            assert info["adj_waves"] == (t[10] if t[5] == 2 else 4)
         else:
             assert (info["fwd_rows"], info["adj_rows"], info["fwd_zsplit"], info["adj_tile"]) == \
                 (t[6], t[7], t[3], t[5])
@@ -269,7 +274,8 @@ def test_manual_tiling_same_operator(dtype, dev):
         assert max(ey) < tol and max(ex) < tol, (t, ey, ex)
     for bad in [(-1, 0, 0, 0, 0, 0), (65, 0, 0, 0, 0, 0), (0, 0, 9, 0, 0, 0), (0, 0, 0, 65, 0, 0),
                 (0, 0, 0, 0, 3, 0), (0, 0, 0, 0, 0, 8), (0, 0, 0, 0, 0, 0, 3, 0), (0, 0, 0, 0, 0, 0, 0, -1),
-                (0, 0, 0, 0, 0, 0, 0, 0, 4, 0), (0, 0, 0, 0, 0, 0, 0, 0, 0, 12)]:
+                (0, 0, 0, 0, 0, 0, 0, 0, 4, 0), (0, 0, 0, 0, 0, 0, 0, 0, 0, 12),
+                (0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 6)]:
         with pytest.raises(u.UfssError):
             u.ufss_plan_set_tiling(plan, *bad)
     plan.close()
@@ -325,7 +331,8 @@ def random_case(rng):
     if dtype == "f32":
         t.update(fwd_waves=int(rng.integers(1, 9)), fwd_zsplit=int(rng.integers(1, 5)),
                  fwd_tile=int(rng.choice([2, 4])), adj_tile=int(rng.choice([2, 4])),
-                 fwd_chunk=int(rng.choice([8, 16])), adj_chunk=int(rng.choice([8, 16])))
+                 fwd_chunk=int(rng.choice([8, 16])), adj_chunk=int(rng.choice([8, 16])),
+                 adj_waves=int(rng.choice([4, 8])))
     else:
         t.update(fwd_zsplit=int(rng.integers(1, 5)), adj_tile=int(rng.choice([2, 4])))
         if ny > 1:
@@ -387,6 +394,40 @@ def test_forward_folded_tail_bins(m, waves, tile, beam, dev):
         torch.cuda.synchronize()
         ey = errs(yt.cpu().numpy(), y_ref)
         assert max(ey) < TOL32, (m, waves, tile, beam, fs, zs, ey)
+    plan.close()
+
+
+@pytest.mark.parametrize("nz,m,beam", [(200, 20, False), (130, 18, True), (16, 34, False), (129, 64, False)])
+def test_adjoint_eight_waves_per_workgroup(nz, m, beam, dev):
+    """FP32 adjoint with 8 waves per workgroup (one staged halo for 128
+    depths): two depth workgroups with a ragged last one (200, 130, 129),
+    fewer depths than one wave group covers (16), a short last bin chunk (20),
+    the paired last 2 bins (18, 34) and whole chunks only (64), with and
+    without the beam, over two d_y splits.  Against the dense FP64 oracle, and
+    bit for bit against 4 waves per workgroup (each voxel takes the same
+    products in the same order)."""
+    u = ufss()
+    g = W.geometry(6, 5, nz, 1024, win_x=3, win_y=2)
+    if beam:
+        g["theta"] = float(np.radians(30.0))
+    bins, _ = u.ufss_select_freqs(g, m, False, 61 + m)
+    y = W.cn((g["ny"], g["nx"], m), 71 + nz).astype(np.complex64)
+    A = O.dense_A(g, bins)
+    x_ref = (A.conj().T @ y.reshape(-1).astype(np.complex128)).reshape(g["ny"], g["nx"], nz)
+    plan = u.Plan(g, m, False, bins, algo=u.ALGO_GEMM)
+    yt = torch.from_numpy(y).to(dev)
+    for split in (1, 3):
+        out = {}
+        for aw in (4, 8):
+            u.ufss_plan_set_tiling(plan, adj_split=split, adj_tile=2, adj_chunk=16, adj_waves=aw)
+            assert plan.info()["adj_waves"] == aw
+            xo = torch.empty((g["ny"], g["nx"], nz), dtype=torch.complex64, device=dev)
+            u.ufss_adjoint(plan, yt, xo)
+            torch.cuda.synchronize()
+            out[aw] = xo.cpu().numpy()
+            ex = errs(out[aw], x_ref)
+            assert max(ex) < TOL32, (nz, m, beam, split, aw, ex)
+        assert np.array_equal(out[4].view(np.int32), out[8].view(np.int32)), (nz, m, beam, split)
     plan.close()
 
 

@@ -30,10 +30,11 @@ def shape_key(name, dtype):
 def test_shipped_cache_entry(name, dtype):
     cache = json.load(open(SHIPPED))
     e = cache[shape_key(name, dtype)]
-    assert len(e) == 13
-    fs, as_, tf, ta, nw, zs, npf, npa, rf, ra, zc, kc, bnz = e
+    assert len(e) == 14
+    fs, as_, tf, ta, nw, zs, npf, npa, rf, ra, zc, kc, bnz, aw = e
     assert 1 <= fs <= 64 and 1 <= as_ <= 64 and tf > 0 and ta > 0
     assert 1 <= nw <= 8 and 1 <= zs <= 64 and npf in (2, 4) and npa in (2, 4)
     assert rf in (1, 2) and ra in (1, 2) and zc in (8, 16) and kc in (8, 16)
     assert bnz in (2, 4)                    # BF16 adjoint depth sub-tiles (4 on FP32 entries)
+    assert aw in (4, 8) and (aw == 4 or npa == 2)   # FP32 adjoint waves (8 with 2 sub-tiles only)
     assert fs * zs <= 96                    # the autotuner's bound on forward partials
