@@ -475,7 +475,10 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
             // and a sub-tile whose shifted columns all leave the grid runs no
             // MFMAs (compile-time masks keep the products branch-free); FULL: a
             // whole chunk of kc bins, so the offset step is one basic block whose
-            // LDS reads and products the compiler can interleave
+            // LDS reads and products the compiler can interleave (8-wave
+            // workgroups only: with 4 waves the second copy of the offset loops
+            // costs registers and measured 3% slower on the 64 x 64 C-scan and
+            // in grouped launches)
             auto dxloop = [&](auto maskc, auto fullc, const int d0, const int d1) {
                 constexpr int MASK = decltype(maskc)::value;
                 constexpr bool FULL = decltype(fullc)::value;
@@ -565,8 +568,12 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
                     dxloop(std::integral_constant<int, 3>{}, fullc, max(dx_lo, a0), min(b1, dx_hi));
                     dxloop(std::integral_constant<int, 1>{}, fullc, max(max(a0, b1 + 1), dx_lo), dx_hi);
                 };
-                if (kcur == kc) segs(std::true_type{});   // every chunk but a short last one
-                else segs(std::false_type{});
+                if constexpr (NW == 8) {
+                    if (kcur == kc) segs(std::true_type{});   // every chunk but a short last one
+                    else segs(std::false_type{});
+                } else {
+                    segs(std::false_type{});
+                }
             } else {
                 dxloop(std::integral_constant<int, (1 << NP) - 1>{}, std::false_type{}, dx_lo, dx_hi);
             }
