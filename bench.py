@@ -46,8 +46,8 @@ PEAK_PHASOR_TERMS = 256 * 4 * 16 * 2.4e9 / PHASOR_SLOTS_PER_TERM
 # source it was measured on; a changed source or another tiling reports null.
 TRAFFIC = {
     # 32 x 32 C-scan, FP32 union-GEMM, shipped tiling (profiles/cscan32_fp32_gemm.md)
-    "cscan32/gemm/forward/fs12-zs8-nw4-np2-zc16": {"bytes": 55.411e6, "sha": "8f43cf5e16d9bdb3"},
-    "cscan32/gemm/adjoint/as12-np2-kc16-nw8": {"bytes": 82.239e6, "sha": "8f43cf5e16d9bdb3"},
+    "cscan32/gemm/forward/fs12-zs8-nw4-np2-zc16": {"bytes": 55.414e6, "sha": "50773752df10ba5f"},
+    "cscan32/gemm/adjoint/as12-np2-kc16-nw8": {"bytes": 81.190e6, "sha": "50773752df10ba5f"},
     # transform-domain contraction (profiles/cscan32_fp32_transform.md, cscan64_fp32_transform.md):
     # the table once plus the transform rows in and out
     "cscan32/transform/forward/fs1-zs1-nw1-np0-zc0": {"bytes": 149.644e6, "sha": "b7d94652b869eec0"},

@@ -391,6 +391,7 @@ struct AdjArgs {
     int nx, ny, nz, wx, wy, mu;
     int sw, ntx, nty, nzt; // lateral tiles, depth tiles (of 64 * NZ)
     int kc;                // bin chunk (multiple of 4)
+    int kcons;             // 1: the union's bins are consecutive integers (phasor rotation)
     int split;             // split of the d_y range; split > 1 writes partials
     cf32* part;            // [split][ny][nx][nz] when split > 1
     int64_t nvox;
@@ -479,9 +480,10 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
             // workgroups only: with 4 waves the second copy of the offset loops
             // costs registers and measured 3% slower on the 64 x 64 C-scan and
             // in grouped launches)
-            auto dxloop = [&](auto maskc, auto fullc, const int d0, const int d1) {
+            auto dxloop = [&](auto maskc, auto fullc, auto consc, const int d0, const int d1) {
                 constexpr int MASK = decltype(maskc)::value;
                 constexpr bool FULL = decltype(fullc)::value;
+                constexpr bool CONS = decltype(consc)::value;
             for (int dx = d0; dx <= d1; ++dx) {
                 const int adx = dx < 0 ? -dx : dx;
                 uint32_t uz[NZ];
@@ -492,6 +494,20 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
                     gz[q] = DIR ? glds[adx * zspan + wave * NZ * 16 + q * 16 + i] : 1.f;
                 }
                 const cf32* hrow = halo + ((((vy0 + iy + dy) & (tpy - 1)) * hc) + ix + a.wx + dx) * cs;
+                // CONS (consecutive bins, whole chunk): lane group kq takes bins
+                // k0 + kq + 4 j, so its phasor steps by exp(-j 2 pi 4 u) from one
+                // bin step to the next: one rotation (4 FMAs) instead of a cos/sin
+                // pair, whose issue does not hide under the products; the chain
+                // restarts from cos/sin at every offset (3 rotations at most)
+                float pc[NZ], ps[NZ], rc[NZ], rsn[NZ];
+                if constexpr (CONS) {
+                    const uint32_t k0l = (uint32_t)klds[kq];
+#pragma unroll
+                    for (int q = 0; q < NZ; ++q) {
+                        phasor(k0l * uz[q], pc[q], ps[q]);
+                        phasor(uz[q] << 2, rc[q], rsn[q]);
+                    }
+                }
 #pragma unroll
                 for (int kk = 0; kk < kc; kk += 4) {
                     if (!FULL && kk >= kcur) break;
@@ -506,7 +522,16 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
 #pragma unroll
                     for (int q = 0; q < NZ; ++q) {
                         float c, sn;
-                        phasor(k * uz[q], c, sn);
+                        if constexpr (CONS) {
+                            c = pc[q];
+                            sn = ps[q];
+                            if (kk + 4 < kc) {
+                                pc[q] = c * rc[q] - sn * rsn[q];
+                                ps[q] = sn * rc[q] + c * rsn[q];
+                            }
+                        } else {
+                            phasor(k * uz[q], c, sn);
+                        }
                         if (DIR) {
                             c *= gz[q];
                             sn *= gz[q];
@@ -563,19 +588,23 @@ __device__ __forceinline__ void adj_f32_body(const AdjArgs& a, int b, const int 
             } else if constexpr (NP == 2) {
                 // column ranges of the two sub-tiles' shifted voxels inside the grid
                 const int a0 = -(vx0 + sw - 1), b1 = a.nx - 1 - vx0 - sw;
-                auto segs = [&](auto fullc) {
-                    dxloop(std::integral_constant<int, 2>{}, fullc, dx_lo, min(min(a0 - 1, b1), dx_hi));
-                    dxloop(std::integral_constant<int, 3>{}, fullc, max(dx_lo, a0), min(b1, dx_hi));
-                    dxloop(std::integral_constant<int, 1>{}, fullc, max(max(a0, b1 + 1), dx_lo), dx_hi);
+                auto segs = [&](auto fullc, auto consc) {
+                    dxloop(std::integral_constant<int, 2>{}, fullc, consc, dx_lo, min(min(a0 - 1, b1), dx_hi));
+                    dxloop(std::integral_constant<int, 3>{}, fullc, consc, max(dx_lo, a0), min(b1, dx_hi));
+                    dxloop(std::integral_constant<int, 1>{}, fullc, consc, max(max(a0, b1 + 1), dx_lo), dx_hi);
                 };
                 if constexpr (NW == 8) {
-                    if (kcur == kc) segs(std::true_type{});   // every chunk but a short last one
-                    else segs(std::false_type{});
+                    if (kcur == kc) {                         // every chunk but a short last one
+                        if (a.kcons) segs(std::true_type{}, std::true_type{});
+                        else segs(std::true_type{}, std::false_type{});
+                    } else {
+                        segs(std::false_type{}, std::false_type{});
+                    }
                 } else {
-                    segs(std::false_type{});
+                    segs(std::false_type{}, std::false_type{});
                 }
             } else {
-                dxloop(std::integral_constant<int, (1 << NP) - 1>{}, std::false_type{}, dx_lo, dx_hi);
+                dxloop(std::integral_constant<int, (1 << NP) - 1>{}, std::false_type{}, std::false_type{}, dx_lo, dx_hi);
             }
 #pragma unroll
             for (int s = 0; s < NP; ++s)
@@ -764,6 +793,9 @@ static int adj_args(const Plan& P, cf32* out, AdjArgs& a, size_t& lds, int np, i
     while (kc > 4 && lds_of(kc) > kLdsMax) kc /= 2;   // powers of two (staging)
     if (lds_of(kc) > kLdsMax) fail(UFSS_ERR_UNSUPPORTED, "aperture window too wide for the GEMM path");
     a.kc = kc;
+    a.kcons = 1;                              // a band without gaps (the C-scan unions)
+    for (size_t t = 1; t < P.ubins_h.size(); ++t)
+        if (P.ubins_h[t] != P.ubins_h[t - 1] + 1) a.kcons = 0;
     lds = lds_of(kc);
     a.split = P.adj_split;
     a.part = P.d_gpart;

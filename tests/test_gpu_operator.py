@@ -397,20 +397,31 @@ def test_forward_folded_tail_bins(m, waves, tile, beam, dev):
     plan.close()
 
 
-@pytest.mark.parametrize("nz,m,beam", [(200, 20, False), (130, 18, True), (16, 34, False), (129, 64, False)])
-def test_adjoint_eight_waves_per_workgroup(nz, m, beam, dev):
+@pytest.mark.parametrize("nz,m,beam,gaps", [(200, 20, False, False), (130, 18, True, False), (16, 34, False, False),
+                                            (129, 64, False, False), (129, 64, False, True), (200, 36, True, True)])
+def test_adjoint_eight_waves_per_workgroup(nz, m, beam, gaps, dev):
     """FP32 adjoint with 8 waves per workgroup (one staged halo for 128
     depths): two depth workgroups with a ragged last one (200, 130, 129),
-    fewer depths than one wave group covers (16), a short last bin chunk (20),
-    the paired last 2 bins (18, 34) and whole chunks only (64), with and
-    without the beam, over two d_y splits.  Against the dense FP64 oracle, and
-    bit for bit against 4 waves per workgroup (each voxel takes the same
-    products in the same order)."""
+    fewer depths than one wave group covers (16), a short last bin chunk (20,
+    36), the paired last 2 bins (18, 34) and whole chunks only (64), with and
+    without the beam, over two d_y splits; bins in one band without gaps (the
+    8-wave kernel then rotates each lane's phasor from one bin step to the
+    next) or every other bin of the band (cos/sin at every step).  Against the
+    dense FP64 oracle, and against 4 waves per workgroup (the same products:
+    bit for bit with gaps, within the rotations' rounding without)."""
     u = ufss()
     g = W.geometry(6, 5, nz, 1024, win_x=3, win_y=2)
     if beam:
         g["theta"] = float(np.radians(30.0))
-    bins, _ = u.ufss_select_freqs(g, m, False, 61 + m)
+    drawn, _ = u.ufss_select_freqs(g, m, False, 61 + m)
+    probe = u.Plan(g, m, False, drawn, algo=u.ALGO_GEMM)
+    lo, hi = probe.info()["band_lo"], probe.info()["band_hi"]
+    probe.close()
+    assert hi - lo + 1 >= 2 * m
+    if gaps:                                   # every other bin of the band
+        bins = (lo + 2 * np.arange(m)).astype(drawn.dtype)
+    else:                                      # m consecutive bins mid-band
+        bins = (lo + (hi - lo + 1 - m) // 2 + np.arange(m)).astype(drawn.dtype)
     y = W.cn((g["ny"], g["nx"], m), 71 + nz).astype(np.complex64)
     A = O.dense_A(g, bins)
     x_ref = (A.conj().T @ y.reshape(-1).astype(np.complex128)).reshape(g["ny"], g["nx"], nz)
@@ -426,8 +437,12 @@ def test_adjoint_eight_waves_per_workgroup(nz, m, beam, dev):
             torch.cuda.synchronize()
             out[aw] = xo.cpu().numpy()
             ex = errs(out[aw], x_ref)
-            assert max(ex) < TOL32, (nz, m, beam, split, aw, ex)
-        assert np.array_equal(out[4].view(np.int32), out[8].view(np.int32)), (nz, m, beam, split)
+            assert max(ex) < TOL32, (nz, m, beam, gaps, split, aw, ex)
+        if gaps:
+            assert np.array_equal(out[4].view(np.int32), out[8].view(np.int32)), (nz, m, beam, split)
+        else:
+            d = np.abs(out[8] - out[4]).max() / np.abs(out[4]).max()
+            assert d < 2e-6, (nz, m, beam, split, d)
     plan.close()
 
 
